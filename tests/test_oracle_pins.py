@@ -1,0 +1,505 @@
+"""Pins of the FP64 oracle against what the mathematics fixes (CPU only).
+
+Every check here compares the oracle with something other than itself: closed
+forms, library routines (scipy.ndimage, scipy.interpolate, scipy.integrate,
+numpy statistics), brute force, or invariants.  Each is chosen so that a
+plausible slip in the oracle (a dropped term, a wrong sign or index, a
+transposed operand) fails at least one of them.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, interpolate, ndimage
+
+import oracle
+from synth import Params, gaussian_kernel, make_frame
+
+
+# ----------------------------------------------------------------------------
+# exact disk / pixel overlap
+# ----------------------------------------------------------------------------
+def _quad_overlap(x0, x1, y0, y1, cx, cy, r):
+    """Area by 1-D quadrature of the clipped chord length (scipy.integrate)."""
+    def h(x):
+        u = x - cx
+        if abs(u) >= r:
+            return 0.0
+        s = math.sqrt(r * r - u * u)
+        lo, hi = max(y0, cy - s), min(y1, cy + s)
+        return max(0.0, hi - lo)
+    a, b = max(x0, cx - r), min(x1, cx + r)
+    if a >= b:
+        return 0.0
+    pts = [p for p in (cx - math.sqrt(max(r * r - (y - cy) ** 2, 0.0)) for y in (y0, y1))] + \
+          [p for p in (cx + math.sqrt(max(r * r - (y - cy) ** 2, 0.0)) for y in (y0, y1))]
+    pts = sorted(p for p in pts if a < p < b)
+    val, _ = integrate.quad(h, a, b, points=pts or None, epsabs=1e-13, epsrel=1e-12, limit=200)
+    return val
+
+
+@pytest.mark.parametrize("r", [0.3, 0.5, 1.0, 2.7, 3.0, 6.0, 9.0, 15.0, 18.0])
+@pytest.mark.parametrize("c", [(0.0, 0.0), (0.5, 0.5), (0.37, -0.21), (10.123, 5.777)])
+def test_overlap_sums_to_pi_r2(r, c):
+    cx, cy = c
+    tot = 0.0
+    R = int(math.ceil(r)) + 2
+    for py in range(int(math.floor(cy)) - R, int(math.floor(cy)) + R + 1):
+        for px in range(int(math.floor(cx)) - R, int(math.floor(cx)) + R + 1):
+            tot += oracle.overlap(px - .5, px + .5, py - .5, py + .5, cx, cy, r)
+    assert abs(tot - math.pi * r * r) <= 1e-12 * max(1.0, math.pi * r * r)
+
+
+def test_overlap_special_cases():
+    # small disk centred in a pixel
+    for r in (0.1, 0.25, 0.5):
+        assert abs(oracle.overlap(-.5, .5, -.5, .5, 0.0, 0.0, r) - math.pi * r * r) < 1e-15
+    # pixel entirely inside the disk
+    assert oracle.overlap(2.5, 3.5, 0.5, 1.5, 0.0, 0.0, 5.0) == pytest.approx(1.0, abs=1e-14)
+    # entirely outside
+    assert oracle.overlap(5.5, 6.5, 5.5, 6.5, 0.0, 0.0, 5.0) == 0.0
+    # a pixel quadrant of a centred disk with r >= sqrt(2)/2 covers the pixel
+    assert oracle.overlap(-.5, .5, -.5, .5, 0, 0, 0.75) == pytest.approx(1.0, abs=1e-14)
+    # r = 0 -> nothing
+    assert oracle.overlap(-.5, .5, -.5, .5, 0, 0, 0.0) == 0.0
+
+
+def test_overlap_symmetries_and_quadrature():
+    rng = np.random.default_rng(7)
+    for _ in range(300):
+        r = rng.uniform(0.2, 20.0)
+        cx, cy = rng.uniform(-1, 1, 2)
+        px, py = rng.integers(-int(r) - 2, int(r) + 3, 2)
+        w = oracle.overlap(px - .5, px + .5, py - .5, py + .5, cx, cy, r)
+        # x <-> y swap
+        w2 = oracle.overlap(py - .5, py + .5, px - .5, px + .5, cy, cx, r)
+        # reflection x -> -x
+        w3 = oracle.overlap(-px - .5, -px + .5, py - .5, py + .5, -cx, cy, r)
+        assert abs(w - w2) < 1e-12 and abs(w - w3) < 1e-12
+        assert -1e-12 <= w <= 1.0 + 1e-12   # f64 cancellation ~ eps * r^2
+        q = _quad_overlap(px - .5, px + .5, py - .5, py + .5, cx, cy, r)
+        assert abs(w - q) < 1e-9, (r, cx, cy, px, py, w, q)
+
+
+# ----------------------------------------------------------------------------
+# aperture sums
+# ----------------------------------------------------------------------------
+def test_aperture_constant_image():
+    H = W = 80
+    c = 7.25
+    M = np.full((H, W), c)
+    R = np.full((H, W), 2.0)
+    xs = np.array([40.0, 33.3, 41.71])
+    ys = np.array([40.0, 45.6, 38.02])
+    radii = [3.0, 6.0, 9.0]
+    out = oracle.aperture(M, R, xs, ys, radii, 13.0, 18.0)
+    for k, r in enumerate(radii):
+        np.testing.assert_allclose(out["area"][:, k], math.pi * r * r, rtol=1e-12)
+        np.testing.assert_allclose(out["flux"][:, k], 0.0, atol=1e-9)
+    np.testing.assert_allclose(out["bkg"], c, rtol=1e-13)
+    assert not np.any(out["flags"])
+
+
+def test_aperture_recovers_injected_flux():
+    H = W = 96
+    s = 3.0 / (2 * math.sqrt(2 * math.log(2)))
+    F0 = 12345.0
+    x0, y0 = 47.3, 49.8
+    from scipy.special import erf
+    px = np.arange(W)
+    py = np.arange(H)
+    gx = 0.5 * (erf((px + .5 - x0) / (s * math.sqrt(2))) - erf((px - .5 - x0) / (s * math.sqrt(2))))
+    gy = 0.5 * (erf((py + .5 - y0) / (s * math.sqrt(2))) - erf((py - .5 - y0) / (s * math.sqrt(2))))
+    M = F0 * np.outer(gy, gx)
+    out = oracle.aperture(M, None, [x0], [y0], [20.0], 30.0, 40.0, want_err=False)
+    assert out["bkg"][0] == pytest.approx(0.0, abs=1e-12)
+    assert out["flux"][0, 0] == pytest.approx(F0, rel=1e-9)
+
+
+def test_aperture_truncation_flag_and_error():
+    M = np.ones((40, 40))
+    R = np.full((40, 40), 3.0)
+    out = oracle.aperture(M, R, [2.0, 20.0], [20.0, 20.0], [0.4], 5.0, 10.0)
+    assert out["flags"][0] & oracle.FLAG_APER_TRUNC
+    assert not out["flags"][1] & oracle.FLAG_APER_TRUNC
+    # a disk inside one pixel: error = R * w with w = pi r^2
+    w = math.pi * 0.16
+    assert out["fluxerr"][1, 0] == pytest.approx(3.0 * w, rel=1e-12)
+    # Poisson term: sqrt(w^2 (R^2 + M/gain))
+    out2 = oracle.aperture(M * 4.0, R, [20.0], [20.0], [0.4], 5.0, 10.0, gain=2.0)
+    assert out2["fluxerr"][0, 0] == pytest.approx(w * math.sqrt(9.0 + 2.0), rel=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# matched filter
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [1, 3, 5, 9, 15])
+def test_filter_delta_kernel_is_identity(k):
+    rng = np.random.default_rng(k)
+    M = rng.normal(size=(23, 31)).astype(np.float32).astype(np.float64)
+    K = np.zeros((k, k))
+    K[k // 2, k // 2] = 2.5   # any scale: the kernel is normalised to unit sum
+    F = oracle.filter_image(M, K)
+    assert np.array_equal(F, M)
+
+
+def test_filter_constant_and_scipy_reflect():
+    rng = np.random.default_rng(3)
+    M = np.full((17, 29), 3.5)
+    K = gaussian_kernel(9, 3.5).astype(np.float64)
+    np.testing.assert_allclose(oracle.filter_image(M, K), 3.5, rtol=1e-14)
+    # random image and an asymmetric kernel against scipy.ndimage.correlate
+    # (mode 'reflect' is the half-sample mirror)
+    M = rng.normal(size=(37, 23))
+    K = rng.uniform(0.1, 1.0, size=(5, 7))
+    ref = ndimage.correlate(M, K / K.sum(), mode="reflect")
+    np.testing.assert_allclose(oracle.filter_image(M, K), ref, rtol=1e-12, atol=1e-12)
+    # kernel larger than the frame: repeated reflection
+    M = rng.normal(size=(3, 4))
+    K = rng.uniform(0.1, 1.0, size=(9, 9))
+    ref = ndimage.correlate(M, K / K.sum(), mode="reflect")
+    np.testing.assert_allclose(oracle.filter_image(M, K), ref, rtol=1e-12, atol=1e-12)
+    # zero-sum kernel is applied as given
+    K = np.array([[0, 0, 0], [-1, 0, 1], [0, 0, 0]], float)
+    ref = ndimage.correlate(M, K, mode="reflect")
+    np.testing.assert_allclose(oracle.filter_image(M, K), ref, atol=1e-14)
+
+
+# ----------------------------------------------------------------------------
+# spline interpolation of the mesh grid
+# ----------------------------------------------------------------------------
+def _knots(n, m):
+    return np.array([0.5 * (k * m + min(k * m + m, n) - 1) for k in range(-(-n // m))])
+
+
+@pytest.mark.parametrize("nx,ny", [(5, 4), (1, 6), (2, 3), (7, 1), (2, 2), (3, 3)])
+def test_spline_matches_scipy_natural(nx, ny):
+    rng = np.random.default_rng(nx * 10 + ny)
+    mw, mh = 16, 12
+    W, H = nx * mw - 5, ny * mh - 3          # ragged last meshes
+    nx_, ny_ = -(-W // mw), -(-H // mh)
+    assert (nx_, ny_) == (nx, ny)
+    G = rng.normal(size=(ny, nx)) * 10 + 100
+    cx, cy = _knots(W, mw), _knots(H, mh)
+
+    def natural(t, f):
+        if len(t) == 1:
+            return lambda x: np.full_like(np.asarray(x, float), f[0])
+        if len(t) == 2:
+            return lambda x: f[0] + (f[1] - f[0]) / (t[1] - t[0]) * (np.asarray(x) - t[0])
+        cs = interpolate.CubicSpline(t, f, bc_type="natural")
+        d0, d1 = cs(t[0], 1), cs(t[-1], 1)
+
+        def ev(x):
+            x = np.asarray(x, float)
+            out = cs(np.clip(x, t[0], t[-1]))
+            out = np.where(x < t[0], f[0] + d0 * (x - t[0]), out)
+            out = np.where(x > t[-1], f[-1] + d1 * (x - t[-1]), out)
+            return out
+        return ev
+
+    ys = np.arange(H)
+    xs = np.arange(W)
+    V = np.stack([natural(cy, G[:, i])(ys) for i in range(nx)], axis=1)   # (H, nx)
+    ref = np.stack([natural(cx, V[y])(xs) for y in range(H)])
+    got = oracle.grid_map(G, W, H, mw, mh)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-10)
+
+
+def test_spline_reproduces_planes():
+    mw = mh = 10
+    W, H = 57, 43
+    cx, cy = _knots(W, mw), _knots(H, mh)
+    G = 3.0 + 0.25 * cx[None, :] - 0.5 * cy[:, None]
+    got = oracle.grid_map(G, W, H, mw, mh)
+    x = np.arange(W)[None, :]
+    y = np.arange(H)[:, None]
+    np.testing.assert_allclose(got, 3.0 + 0.25 * x - 0.5 * y, atol=1e-11)
+
+
+# ----------------------------------------------------------------------------
+# mesh statistics
+# ----------------------------------------------------------------------------
+def test_mesh_constant_sky():
+    img = np.full((100, 130), 812.5)
+    st = oracle.mesh_stats(img, 32, 32)
+    assert np.all(st["back"] == 812.5) and np.all(st["rms"] == 0.0)
+    p = Params(mesh_w=32, mesh_h=32, mesh_filter=3)
+    bk = oracle.background(img, p)
+    assert np.all(bk.B == 812.5) and np.all(bk.R == 0.0)
+
+
+def test_mesh_no_clip_case_equals_numpy():
+    # a uniform spread never reaches 3 sigma from its median: no pixel is
+    # clipped, sigma is unchanged, so back = mean and rms = std (numpy)
+    rng = np.random.default_rng(11)
+    v = rng.uniform(0, 1, 4096)
+    st = oracle.mesh_one(v)
+    assert st["iters"] == 1
+    assert st["back"] == pytest.approx(np.mean(v), rel=1e-14)
+    assert st["rms"] == pytest.approx(np.std(v), rel=1e-13)
+    assert st["med"] == pytest.approx(np.median(v), rel=0, abs=0)
+
+
+def test_mesh_outlier_removed_and_mode_rule():
+    rng = np.random.default_rng(12)
+    core = rng.uniform(-1, 1, 999)
+    v = np.concatenate([core, [1e4]])
+    st = oracle.mesh_one(v)
+    # the outlier inflates sigma0 far beyond 20%: mode = 2.5 med - 1.5 mean of the rest
+    assert st["sigma0"] == pytest.approx(np.std(v), rel=1e-13)
+    assert st["rms"] == pytest.approx(np.std(core), rel=1e-12)
+    assert st["back"] == pytest.approx(2.5 * np.median(core) - 1.5 * np.mean(core), rel=1e-12, abs=1e-12)
+    # a small symmetric contamination keeps sigma within 20%: clipped mean
+    v2 = np.concatenate([rng.normal(0, 1, 20000), [4.5, -4.6]])
+    st2 = oracle.mesh_one(v2)
+    assert abs(st2["rms"] - st2["sigma0"]) < 0.2 * st2["sigma0"]
+    assert st2["back"] == pytest.approx(st2["mean"], rel=0, abs=0)
+
+
+def _brute_mesh(v, clip=3.0, crowd=0.2, a=2.5, b=1.5, max_iter=100):
+    """Independent re-statement with numpy primitives (median, std, masks)."""
+    S = np.asarray(v, float)
+    s0 = np.std(S) if S.min() != S.max() else 0.0
+    if s0 == 0:
+        return S[0], 0.0
+    for _ in range(max_iter):
+        med = np.median(S)
+        sd = np.std(S) if S.min() != S.max() else 0.0
+        keep = S[np.abs(S - med) <= clip * sd]
+        if keep.size == S.size or keep.size == 0:
+            break
+        S = keep
+    med, mean = np.median(S), np.mean(S)
+    sd = np.std(S) if S.min() != S.max() else 0.0
+    back = mean if abs(sd - s0) < crowd * s0 else a * med - b * mean
+    return back, sd
+
+
+def test_mesh_against_numpy_restatement():
+    rng = np.random.default_rng(5)
+    for trial in range(40):
+        n = int(rng.integers(1, 3000))
+        v = rng.normal(1000, 30, n)
+        if trial % 3 == 0:
+            v[: n // 10] += rng.uniform(100, 5e4, n // 10)   # a star in the mesh
+        if trial % 5 == 0:
+            v = np.round(v)                                  # integer data with ties
+        b, s = _brute_mesh(v)
+        st = oracle.mesh_one(v)
+        assert st["back"] == pytest.approx(b, rel=1e-12, abs=1e-9)
+        assert st["rms"] == pytest.approx(s, rel=1e-12, abs=1e-12)
+
+
+def test_mesh_gaussian_sky_statistics():
+    rng = np.random.default_rng(2)
+    c, sn = 1000.0, 10.0
+    img = c + rng.normal(0, sn, size=(256, 256))
+    st = oracle.mesh_stats(img, 64, 64)
+    n = 64 * 64
+    assert np.all(np.abs(st["back"] - c) < 5 * sn / math.sqrt(n) * 3)
+    assert np.all(np.abs(st["rms"] / sn - 1) < 0.05)
+
+
+def test_background_linear_ramp_is_exact():
+    # symmetric distribution in every mesh (actual-centre knots) and a spline
+    # that reproduces lines: B equals the plane (filter off)
+    W, H = 200, 150
+    x = np.arange(W)[None, :]
+    y = np.arange(H)[:, None]
+    img = 500.0 + 0.3 * x + 0.1 * y + 0.0 * x * y
+    p = Params(mesh_w=32, mesh_h=32, mesh_filter=1)
+    bk = oracle.background(img, p)
+    np.testing.assert_allclose(bk.B, img, rtol=0, atol=1e-9)
+
+
+def test_median_filter_against_scipy():
+    rng = np.random.default_rng(4)
+    G = rng.normal(size=(9, 12))
+    got = oracle.median_filter(G, 3)
+    # interior: plain 3x3 median (scipy.ndimage.median_filter)
+    ref = ndimage.median_filter(G, size=3, mode="nearest")
+    np.testing.assert_allclose(got[1:-1, 1:-1], ref[1:-1, 1:-1], rtol=0, atol=0)
+    # corner: mean of the two middle values of the 2x2 window
+    w = np.sort(G[:2, :2].ravel())
+    assert got[0, 0] == pytest.approx(0.5 * (w[1] + w[2]), abs=0)
+    assert np.array_equal(oracle.median_filter(G, 1), G)
+
+
+# ----------------------------------------------------------------------------
+# connected components
+# ----------------------------------------------------------------------------
+def _canon_scipy(mask, conn):
+    st = ndimage.generate_binary_structure(2, 1 if conn == 4 else 2)
+    lab, n = ndimage.label(mask, structure=st)
+    # renumber by first raster pixel
+    order = {}
+    flat = lab.ravel()
+    out = np.zeros_like(flat)
+    nxt = 0
+    for i, l in enumerate(flat):
+        if l and l not in order:
+            nxt += 1
+            order[l] = nxt
+    for l, k in order.items():
+        out[flat == l] = k
+    return out.reshape(mask.shape), n
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_ccl_all_4x4_masks(conn):
+    st = ndimage.generate_binary_structure(2, 1 if conn == 4 else 2)
+    for bits in range(1 << 16):
+        m = np.array([(bits >> i) & 1 for i in range(16)], bool).reshape(4, 4)
+        seg, n = oracle.label_mask(m, conn)
+        lab, n2 = ndimage.label(m, structure=st)
+        assert n == n2
+        # same partition, numbered by first raster pixel
+        if n:
+            firsts = [np.flatnonzero(lab.ravel() == k)[0] for k in range(1, n2 + 1)]
+            order = np.argsort(firsts)
+            for newk, oldk in enumerate(order, start=1):
+                assert np.array_equal(seg == newk, lab == oldk + 1)
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_ccl_random_and_adversarial(conn):
+    rng = np.random.default_rng(conn)
+    shapes = []
+    for d in (0.05, 0.3, 0.5, 0.6, 0.95):
+        shapes.append(rng.random((64, 64)) < d)
+    # spiral
+    sp = np.zeros((41, 41), bool)
+    x = y = 20
+    dx, dy, step = 1, 0, 1
+    while 0 <= x < 41 and 0 <= y < 41:
+        for _ in range(2):
+            for _ in range(step):
+                if 0 <= x < 41 and 0 <= y < 41:
+                    sp[y, x] = True
+                x += dx * 1
+                y += dy * 1
+            dx, dy = -dy, dx
+        step += 2
+    shapes.append(sp)
+    comb = np.zeros((30, 70), bool)
+    comb[0, :] = True
+    comb[:, ::2] = True
+    shapes.append(comb)
+    snake = np.zeros((70, 130), bool)
+    for r in range(0, 70, 2):
+        snake[r, :] = True
+        snake[r + 1 if r + 1 < 70 else r, (129 if (r // 2) % 2 == 0 else 0)] = True
+    shapes.append(snake)
+    shapes.append(np.ones((33, 65), bool))
+    checker = (np.add.outer(np.arange(20), np.arange(21)) % 2).astype(bool)
+    shapes.append(checker)
+    for m in shapes:
+        seg, n = oracle.label_mask(m, conn)
+        ref, n2 = _canon_scipy(m, conn)
+        assert n == n2
+        assert np.array_equal(seg, ref)
+
+
+def test_minarea_and_seg_convention():
+    m = np.zeros((10, 10), bool)
+    m[1, 1] = True                      # single pixel: dropped
+    m[5:7, 5:8] = True                  # 6 pixels: kept
+    F = m.astype(float)
+    seg, n = oracle.threshold_label(F, np.zeros_like(F), 0.0, 5, 8)
+    assert n == 1
+    assert seg[1, 1] == -1 and np.all(seg[5:7, 5:8] == 1) and seg[0, 0] == 0
+    # strict threshold: F == t R is not detected
+    F = np.full((4, 4), 3.0)
+    R = np.full((4, 4), 2.0)
+    _, n = oracle.threshold_label(F, R, 1.5, 1, 8)
+    assert n == 0
+    _, n = oracle.threshold_label(F + 1e-12, R, 1.5, 1, 8)
+    assert n == 1
+
+
+# ----------------------------------------------------------------------------
+# moments
+# ----------------------------------------------------------------------------
+def _measure(M, conn=8, I=None, sat=np.inf):
+    seg, n = oracle.threshold_label(np.where(M != 0, 1.0, 0.0), np.zeros_like(M), 0.0, 1, conn)
+    return oracle.measure(M if I is None else I, M, seg, n, sat), seg
+
+
+def test_moments_closed_forms():
+    M = np.zeros((12, 14))
+    M[3, 9] = 5.0
+    cat, _ = _measure(M)
+    assert cat["x"][0] == 9.0 and cat["y"][0] == 3.0
+    assert cat["x2"][0] == 0 and cat["y2"][0] == 0 and cat["xy"][0] == 0
+    assert cat["flux"][0] == 5.0 and cat["npix"][0] == 1 and cat["pmin"][0] == 3 * 14 + 9
+    M = np.zeros((12, 14))
+    M[4:7, 2:5] = 2.0
+    cat, _ = _measure(M)
+    assert cat["x"][0] == pytest.approx(3.0) and cat["y"][0] == pytest.approx(5.0)
+    assert cat["x2"][0] == pytest.approx(2.0 / 3.0) and cat["y2"][0] == pytest.approx(2.0 / 3.0)
+    assert cat["xy"][0] == pytest.approx(0.0, abs=1e-15)
+    assert (cat["xmin"][0], cat["xmax"][0], cat["ymin"][0], cat["ymax"][0]) == (2, 4, 4, 6)
+    M = np.zeros((5, 5))
+    M[2, 1:3] = 1.0
+    cat, _ = _measure(M)
+    assert cat["x2"][0] == pytest.approx(0.25) and cat["y2"][0] == 0.0
+
+
+def test_moments_symmetry_translation_and_nonpos():
+    rng = np.random.default_rng(9)
+    blob = rng.uniform(1, 5, (7, 7))
+    blob = blob + blob[::-1, :]                  # mirror symmetric in y
+    blob = blob + blob[:, ::-1]                  # and in x
+    M = np.zeros((30, 30))
+    M[10:17, 12:19] = blob
+    cat, _ = _measure(M)
+    assert cat["xy"][0] == pytest.approx(0.0, abs=1e-12)
+    assert cat["x"][0] == pytest.approx(15.0) and cat["y"][0] == pytest.approx(13.0)
+    M2 = np.zeros((30, 30))
+    M2[13:20, 5:12] = blob
+    cat2, _ = _measure(M2)
+    assert cat2["x"][0] - cat["x"][0] == pytest.approx(-7.0)
+    assert cat2["y"][0] - cat["y"][0] == pytest.approx(3.0)
+    for k in ("x2", "y2", "xy"):
+        assert cat2[k][0] == pytest.approx(cat[k][0], rel=1e-12, abs=1e-12)
+    # sum M <= 0: unit weights and NONPOS
+    M = np.zeros((9, 9))
+    M[2:5, 2:5] = -1.0
+    M[3, 3] = 0.5
+    seg, n = oracle.threshold_label(np.where(M != 0, 1.0, 0.0), np.zeros_like(M), 0.0, 1, 8)
+    cat = oracle.measure(M, M, seg, n)
+    assert cat["flags"][0] & oracle.FLAG_NONPOS
+    assert cat["x"][0] == pytest.approx(3.0) and cat["x2"][0] == pytest.approx(2.0 / 3.0)
+
+
+def test_flags_edge_and_saturation():
+    M = np.zeros((10, 10))
+    M[0:2, 4:6] = 1.0
+    M[6:8, 6:8] = 2.0
+    I = M.copy()
+    I[7, 7] = 70000.0
+    cat, _ = _measure(M, I=I, sat=65535.0)
+    assert cat["flags"][0] & oracle.FLAG_EDGE and not cat["flags"][0] & oracle.FLAG_SATURATED
+    assert cat["flags"][1] & oracle.FLAG_SATURATED and not cat["flags"][1] & oracle.FLAG_EDGE
+    assert cat["peak"][1] == 2.0
+
+
+# ----------------------------------------------------------------------------
+# whole chain: statistical sanity on injected stars
+# ----------------------------------------------------------------------------
+def test_chain_finds_injected_stars():
+    fr = make_frame("c1", seed=3, W=256, H=256, nstars=12)
+    p = fr.params
+    res = oracle.run(fr.image, p)
+    t = fr.truth
+    bright = t["flux"] > 2e4
+    found = 0
+    for x0, y0 in zip(t["x"][bright], t["y"][bright]):
+        d = np.hypot(res.cat["x"] - x0, res.cat["y"] - y0)
+        if d.size and d.min() < 1.0:
+            found += 1
+    assert found == bright.sum()
+    # large-aperture fluxes of bright isolated stars approach the injected flux
+    assert np.all(np.isfinite(res.phot["flux"]))
