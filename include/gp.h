@@ -1,0 +1,252 @@
+/*
+ * gp.h -- C ABI of the MI355X (gfx950) photometry hot path.
+ *
+ * Three calls carry the method, in the order the paper's GPU Implementation
+ * section applies its stages to a frame:
+ *
+ *   gp_background  mesh background: per-mesh kappa-sigma clipped mode and rms
+ *                  (the SExtractor method the paper cites), a median filter over
+ *                  the mesh grid and a natural bicubic spline that turns the grid
+ *                  into the per-pixel background B and noise map R (the paper's
+ *                  background subsection: a local background estimate plus a
+ *                  per-pixel noise map used as the significance normaliser).
+ *   gp_detect      matched-filter detection (source detection subsection): the
+ *                  background-subtracted frame M = I - B is correlated with a
+ *                  unit-sum kernel using reflected borders, pixels with F > t R
+ *                  are grouped into 8- (or 4-) connected components, components
+ *                  smaller than minarea are dropped, and the survivors are
+ *                  measured (flux, peak, first-moment centroid, second moments).
+ *   gp_aperture    circular aperture photometry (adaptive aperture photometry
+ *                  subsection): exact pixel/disk overlap sums for each radius,
+ *                  an annulus background, and the propagated noise.
+ *
+ * All three work on a batch of nframes >= 1 frames of any sizes at once; the
+ * plain per-frame use is nframes = 1.
+ *
+ * Memory.  Every pointer inside gp_frame, gp_catalog, gp_phot and the
+ * background and workspace buffers is caller-owned DEVICE memory on the
+ * context's device; the library allocates nothing on these paths.  Host
+ * pointers appear only in the parameter structs (filter kernel, radii), which
+ * are read during the call and may be freed when it returns.
+ *
+ * Asynchrony.  The calls only enqueue kernels on the given stream (NULL = the
+ * default stream) and can be captured into a HIP graph.  Argument errors are
+ * returned synchronously.  Data-dependent conditions (more objects than the
+ * catalogue holds, more components than the workspace holds) are written to
+ * device status words that the caller reads after synchronising.
+ *
+ * Errors.  A non-GP_OK return leaves a message for gp_last_error() (per host
+ * thread).  Nothing is enqueued when a call returns an error.
+ *
+ * Threads.  A context may be used from several host threads as long as each
+ * (workspace, stream) pair is used by one thread at a time.
+ */
+#ifndef GP_H
+#define GP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gp_status {
+    GP_OK = 0,
+    GP_ERR_INVALID_ARG = 1,   /* bad argument (returned synchronously)             */
+    GP_ERR_UNSUPPORTED = 2,   /* valid but outside what the kernels implement      */
+    GP_ERR_WORKSPACE = 3,     /* workspace too small (sync) or component overflow  */
+    GP_ERR_CAPACITY = 4,      /* more objects than catalogue rows (device status)  */
+    GP_ERR_HIP = 5            /* a HIP runtime call failed                         */
+} gp_status;
+
+typedef enum gp_dtype { GP_U16 = 1, GP_F32 = 2 } gp_dtype;
+
+/* Arithmetic of the per-pixel work.  GP_PREC_F32: FP32 per-pixel work with
+ * compensated (two-sum) accumulation; FP64 only for the spline solve and the
+ * final moment normalisation.  GP_PREC_F64: the same kernels in FP64 end to end
+ * (a reference variant of the GPU path, several times slower). */
+typedef enum gp_precision { GP_PREC_F32 = 0, GP_PREC_F64 = 1 } gp_precision;
+
+/* One frame: row-major pixels, x = column in [0, width), y = row in
+ * [0, height), element (x, y) at data[y * pitch + x] (pitch in elements,
+ * >= width).  Values must be finite. */
+typedef struct gp_frame {
+    const void* data;      /* device pointer */
+    int32_t width, height;
+    int64_t pitch;
+    int32_t dtype;         /* gp_dtype */
+} gp_frame;
+
+/* Background parameters.  Meshes are mesh_w x mesh_h pixels tiling the frame
+ * from (0, 0); the last mesh column/row may be narrower.  Per mesh: sigma0 =
+ * std of all pixels; repeat up to max_iter times {med = median, sigma = std,
+ * keep pixels with |v - med| <= clip_sigma * sigma} until nothing is removed;
+ * back = clipped mean if |sigma - sigma0| < crowd_tol * sigma0, otherwise
+ * mode_a * median - mode_b * mean; rms = clipped sigma.  The grids are then
+ * median filtered over filter_size x filter_size meshes (odd, 1 = off,
+ * truncated at the grid edges) and interpolated by natural cubic splines
+ * through the mesh centres, first along y then along x, continued linearly
+ * past the outer mesh centres.
+ * Limits: 16 <= mesh_w, mesh_h; mesh_w * mesh_h <= 16384; filter_size <= 7. */
+#define GP_BKG_GRID_GIVEN 1u   /* skip the mesh statistics and the filter: the
+                                  caller has written the back/rms grids */
+typedef struct gp_bkg_params {
+    int32_t mesh_w, mesh_h;
+    int32_t filter_size;
+    float clip_sigma;      /* 3    */
+    float crowd_tol;       /* 0.2  */
+    float mode_a, mode_b;  /* 2.5, 1.5 */
+    int32_t max_iter;      /* 100  */
+    uint32_t flags;        /* GP_BKG_* */
+} gp_bkg_params;
+
+/* Layout of one frame's block inside the background buffer (all offsets in
+ * bytes from the buffer start, 256-byte aligned).  Grids are double
+ * [ny][nx] row-major; coef holds the interpolation as bicubic pieces, double
+ * [2][ny+1][nx+1][16] (B then R; piece (jy, ix) covers the rows between mesh
+ * centres jy-1 and jy and the columns between centres ix-1 and ix, with the
+ * outer pieces extending to the frame edges; coefficient [p*4+q] multiplies
+ * (x - X_ix)^p (y - Y_jy)^q where X_ix is the centre max(ix-1, 0) and Y_jy
+ * likewise). */
+typedef struct gp_bkg_layout {
+    int32_t nx, ny;
+    int64_t back_raw, rms_raw;   /* per-mesh statistics before the filter */
+    int64_t back, rms;           /* filtered grids (what the spline uses)  */
+    int64_t coef;
+    int64_t iters;               /* int32 [ny][nx]: clipping passes per mesh */
+    int64_t bytes;               /* size of this frame's block */
+} gp_bkg_layout;
+
+/* Detection parameters.  kernel: HOST pointer to kh x kw floats, row-major,
+ * both odd and <= 15; it is normalised to unit sum by the library (used as
+ * given when its sum is zero) and applied as a correlation with half-sample
+ * reflected borders.  A rank-one kernel (e.g. a circular Gaussian) is applied
+ * as two 1-D passes.  Pixels with F > thresh * R form the mask. */
+typedef struct gp_det_params {
+    const float* kernel;
+    int32_t kw, kh;
+    float thresh;
+    int32_t minarea;       /* >= 1 */
+    int32_t connectivity;  /* 8 or 4 */
+    float sat_level;       /* raw value flagged SATURATED (+inf: never) */
+    int32_t precision;     /* gp_precision */
+} gp_det_params;
+
+/* Aperture parameters.  radii: HOST pointer to nr (1..8) positive radii in
+ * pixels; the annulus is [r_in, r_out] with 0 <= r_in < r_out <= 64.
+ * gain > 0 adds the Poisson term max(M, 0) / gain to the pixel variance. */
+typedef struct gp_ap_params {
+    const float* radii;
+    int32_t nr;
+    float r_in, r_out;
+    float gain;
+    int32_t want_err;
+    int32_t precision;     /* gp_precision */
+} gp_ap_params;
+
+/* Object flags */
+#define GP_FLAG_SATURATED 1u   /* a raw pixel of the object >= sat_level       */
+#define GP_FLAG_EDGE 2u        /* the bounding box touches the frame border    */
+#define GP_FLAG_NONPOS 4u      /* sum of M <= 0: moments use unit weights       */
+#define GP_FLAG_APER_TRUNC 8u  /* an aperture or the annulus leaves the frame   */
+
+/* Catalogue, structure of arrays.  Frame f's rows are [f*capacity,
+ * (f+1)*capacity) of every column; row k holds label k+1.  Labels number the
+ * kept components in raster order of their first pixel.  n_obj[f] is the
+ * number of components found (it may exceed capacity: then status[f] =
+ * GP_ERR_CAPACITY and the first `capacity` labels are stored).  Coordinates
+ * are 0-based pixel centres; pmin = y * width + x of the first pixel. */
+typedef struct gp_catalog {
+    int32_t capacity;
+    int32_t* n_obj;        /* [nframes] */
+    int32_t* status;       /* [nframes] */
+    int32_t *npix, *xmin, *xmax, *ymin, *ymax;
+    int64_t* pmin;
+    double *flux, *x, *y, *x2, *y2, *xy;
+    float* peak;
+    uint32_t* flags;
+} gp_catalog;
+
+/* Photometry, rows as in the catalogue: flux/area/fluxerr [row][nr],
+ * bkg [row].  fluxerr may be NULL when want_err = 0. */
+typedef struct gp_phot {
+    double* flux;
+    double* area;
+    double* bkg;
+    double* fluxerr;
+} gp_phot;
+
+typedef struct gp_ctx gp_ctx;
+
+/* Create a context on HIP device `device`.  tune_cache: path of the JSON file
+ * holding autotuned launch shapes (NULL: built-in defaults). */
+gp_status gp_ctx_create(int device, const char* tune_cache, gp_ctx** out);
+void gp_ctx_destroy(gp_ctx* ctx);
+
+/* Message of the last error on this host thread ("" if none). */
+const char* gp_last_error(void);
+
+/* Library version string. */
+const char* gp_version(void);
+
+/* Size and per-frame layout of the background buffer for a batch.  layouts may
+ * be NULL; otherwise it receives nframes entries. */
+gp_status gp_background_layout(const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
+                               gp_bkg_layout* layouts, size_t* bytes);
+
+/* Per-pixel background B and noise map R of frame `index` of the batch, from
+ * a background buffer filled by gp_background: device double [height][width]
+ * maps (row pitch = width; either may be NULL).  Evaluated exactly as the
+ * detection and aperture kernels evaluate them in the given precision
+ * (gp_precision).  A diagnostic output (like a background check image); the
+ * hot path never materialises these maps. */
+gp_status gp_background_map(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                            const gp_bkg_params* bp, const void* bkg, int32_t index,
+                            int32_t precision, double* back_map, double* rms_map, void* stream);
+
+/* Workspace bytes for running gp_background, gp_detect and gp_aperture on this
+ * batch with catalogues of cat_capacity rows per frame and room for
+ * comp_capacity connected-component pieces in total (0: a default of
+ * max(65536, pixels / 64)).  One workspace serves all three calls. */
+gp_status gp_workspace_size(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                            const gp_bkg_params* bp, const gp_det_params* dp,
+                            const gp_ap_params* ap, int32_t cat_capacity, int64_t comp_capacity,
+                            size_t* bytes);
+
+/* Mesh statistics, grid filter and spline pieces into `bkg` (device buffer of
+ * gp_background_layout bytes).  With GP_BKG_GRID_GIVEN only the spline pieces
+ * are built from the back/rms grids already in the buffer. */
+gp_status gp_background(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                        const gp_bkg_params* bp, void* bkg, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* Detection into the catalogue.  seg: NULL, or a HOST array of nframes
+ * pointers, each NULL or a device int32 [height][width] map (row pitch =
+ * width) that receives per pixel the label (>= 1), -1 for pixels above
+ * threshold in a dropped component, 0 below threshold.  comp_status (device int32[2], may be
+ * NULL) receives {GP_OK or GP_ERR_WORKSPACE, pieces needed}. */
+gp_status gp_detect(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                    const gp_bkg_params* bp, const void* bkg, const gp_det_params* dp,
+                    gp_catalog* cat, int32_t* const* seg, int32_t* comp_status, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* Aperture photometry of every catalogued object; also ORs GP_FLAG_APER_TRUNC
+ * into cat->flags. */
+gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                      const gp_bkg_params* bp, const void* bkg, const gp_catalog* cat,
+                      const gp_ap_params* ap, gp_phot* out, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* Per-kernel timing with HIP events recorded on the launch stream.  When
+ * enabled, every kernel launch is bracketed by events; gp_profile_read
+ * synchronises and returns the summed milliseconds and launch count for the
+ * kernel named `name` since the last reset. */
+gp_status gp_profile_enable(gp_ctx* ctx, int on);
+gp_status gp_profile_read(gp_ctx* ctx, const char* name, double* total_ms, int64_t* count);
+gp_status gp_profile_reset(gp_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GP_H */

@@ -1,0 +1,76 @@
+// k_args.h -- kernel argument blocks and launcher entry points shared by the
+// kernel translation units and the host runtime.
+#pragma once
+#include "k_common.h"
+
+namespace gpk {
+
+struct BkgArgs {
+    float clip, crowd, mode_a, mode_b;
+    int32_t max_iter;
+    int32_t fsize;
+};
+
+// matched-filter and detection arguments, stored in the workspace
+struct DetArgs {
+    int32_t kw, kh, separable, conn;
+    float thresh, sat;
+    int32_t minarea, want_seg;
+    float kx[kMaxK], ky[kMaxK];       // normalised 1-D factors (rank-one kernels)
+    float kd[kMaxK * kMaxK];          // normalised dense kernel
+    double kxd[kMaxK], kyd[kMaxK];    // the same in FP64 (reference variant)
+    double kdd[kMaxK * kMaxK];
+};
+
+// what the host hands to the argument-writing kernel (the dense kernel is
+// normalised on the device)
+struct DetArgsIn {
+    int32_t kw, kh, separable, conn;
+    float thresh, sat;
+    int32_t minarea, want_seg;
+    float kraw[kMaxK * kMaxK];
+    float kx[kMaxK], ky[kMaxK];
+    double kxd[kMaxK], kyd[kMaxK];
+};
+
+struct ApArgs {
+    int32_t nr, want_err, capacity, nframes;
+    float radii[kMaxRadii];
+    float r_in, r_out, gain, rmax;
+};
+
+struct ApCat {
+    const int32_t* n_obj;
+    const double *x, *y;
+    uint32_t* flags;
+    double *flux, *area, *bkg, *fluxerr;
+};
+
+struct CatOut {
+    int32_t capacity;
+    int32_t *n_obj, *status;
+    int32_t *npix, *xmin, *xmax, *ymin, *ymax;
+    int64_t* pmin;
+    double *flux, *x, *y, *x2, *y2, *xy;
+    float* peak;
+    uint32_t* flags;
+};
+
+void launch_mesh_stats(const FrameDesc* desc, int nframes, int total_meshes, int max_area, BkgArgs a,
+                       hipStream_t s);
+void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, int fsize, hipStream_t s);
+void launch_spline(const FrameDesc* desc, int nframes, int total_ycols, int total_xk, int total_pieces,
+                   hipStream_t s);
+void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, hipStream_t s);
+void launch_merge(const DetWork& wk, int conn, int minarea, int persist_blocks, hipStream_t s);
+void launch_catalog(const DetWork& wk, const CatOut& cat, int minarea, int persist_blocks, int32_t* comp_status,
+                    hipStream_t s);
+void launch_seg(const DetWork& wk, int f, int64_t npx, hipStream_t s);
+void launch_aperture(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int total_rows, int blocks,
+                     bool f64, hipStream_t s);
+void launch_bkg_map(const FrameDesc& d, double* bmap, double* rmap, bool f64, hipStream_t s);
+void launch_write_desc(const DescChunk& c, FrameDesc* table, hipStream_t s);
+void launch_write_detargs(const DetArgsIn& in, DetArgs* out, hipStream_t s);
+
+}  // namespace gpk

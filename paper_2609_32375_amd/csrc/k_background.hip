@@ -1,0 +1,594 @@
+// k_background.hip -- mesh background for gfx950.
+//
+//  k_mesh_stats   one workgroup per mesh.  The mesh's pixels stay in VGPRs for
+//                 the whole kappa-sigma loop.  Each clipping pass tests every
+//                 surviving pixel against |v - med| <= kappa*sigma, accumulates
+//                 the shifted sums of the new set (compensated) and bins it into
+//                 an LDS histogram over the clip window; the exact median is the
+//                 order statistic found through the histogram's prefix sums and
+//                 a gather of the (few) pixels in the target bin.  All float
+//                 reductions run in a fixed order, so a mesh gives bit-identical
+//                 results wherever it is scheduled.
+//  k_grid_filter  f x f median over the mesh grid (truncated at the edges).
+//  k_spline_*     natural cubic splines through the mesh centres, solved in
+//                 FP64 (Thomas), turned into bicubic pieces per mesh cell.
+//
+// The statistics follow the SExtractor method the paper cites for local
+// background estimation; the paper's background subsection fixes the output
+// role: a per-pixel background and a per-pixel noise map (here the clipped
+// rms, interpolated like the background).
+#include "k_args.h"
+#include "k_rowpoly.h"
+
+namespace gpk {
+
+constexpr int kBins = 2048;
+constexpr int kList = 1024;
+constexpr int kMeshThreads = 256;
+
+struct MeshShared {
+    uint32_t hist[kBins];
+    float list[kList];
+    F2 pf[4][2];
+    int32_t pi[4];
+    float pmin[4], pmax[4];
+    uint32_t wsum[4];
+    int32_t sel_bin[2];
+    uint32_t sel_cum[2];
+    uint32_t cnt, kmin, kmax;
+    float out[2];
+    int32_t ucnt[4];
+};
+
+__device__ __forceinline__ int bin_of(float v, float lo, float scale) {
+    float t = (v - lo) * scale;
+    t = fminf(fmaxf(t, 0.0f), (float)(kBins - 1));
+    return (int)t;
+}
+
+// exclusive scan of one uint32 per thread over the 256-thread block
+__device__ uint32_t block_exscan(uint32_t x, MeshShared& sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) sh.wsum[w] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int i = 0; i < w; ++i) off += sh.wsum[i];
+    __syncthreads();
+    return off + incl - x;
+}
+
+__device__ int block_sum_i(int x, MeshShared& sh) {
+    x = wave_sum_i(x);
+    if ((threadIdx.x & 63) == 0) sh.ucnt[threadIdx.x >> 6] = x;
+    __syncthreads();
+    int s = sh.ucnt[0] + sh.ucnt[1] + sh.ucnt[2] + sh.ucnt[3];
+    __syncthreads();
+    return s;
+}
+
+// deterministic block reduction of two compensated sums, a count and min/max
+__device__ void block_stats(F2& a, F2& b, int& n, float& mn, float& mx, MeshShared& sh) {
+    const int w = threadIdx.x >> 6;
+    a = wave_sum_f2(a);
+    b = wave_sum_f2(b);
+    n = wave_sum_i(n);
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) {
+        sh.pf[w][0] = a;
+        sh.pf[w][1] = b;
+        sh.pi[w] = n;
+        sh.pmin[w] = mn;
+        sh.pmax[w] = mx;
+    }
+    __syncthreads();
+    a = sh.pf[0][0];
+    b = sh.pf[0][1];
+    n = sh.pi[0];
+    mn = sh.pmin[0];
+    mx = sh.pmax[0];
+    for (int i = 1; i < 4; ++i) {
+        a = f2_add(a, sh.pf[i][0]);
+        b = f2_add(b, sh.pf[i][1]);
+        n += sh.pi[i];
+        mn = fminf(mn, sh.pmin[i]);
+        mx = fmaxf(mx, sh.pmax[i]);
+    }
+    __syncthreads();
+}
+
+// Values of ranks r1 <= r2 (0-based, r2 - r1 <= 1) among the alive pixels.
+// The histogram window [lo, hi] only steers the binning: bins are clamped, so
+// every alive pixel is counted and the selection is exact for any window.
+template <int PPT>
+__device__ void select_pair(const float (&v)[PPT], uint64_t alive, float lo, float hi, int r1, int r2,
+                            float& o1, float& o2, MeshShared& sh) {
+    const int tid = threadIdx.x;
+    for (int b = tid; b < kBins; b += kMeshThreads) sh.hist[b] = 0u;
+    if (tid == 0) {
+        sh.cnt = 0u;
+        sh.kmin = 0xffffffffu;
+        sh.kmax = 0u;
+    }
+    __syncthreads();
+    const float scale = (hi > lo) ? (float)kBins / (hi - lo) : 0.0f;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k)
+        if ((alive >> k) & 1ull) atomicAdd(&sh.hist[bin_of(v[k], lo, scale)], 1u);
+    __syncthreads();
+    constexpr int per = kBins / kMeshThreads;  // 8 bins per thread
+    uint32_t c[per];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int q = 0; q < per; ++q) {
+        c[q] = sh.hist[tid * per + q];
+        tot += c[q];
+    }
+    uint32_t pre = block_exscan(tot, sh);
+    const int rr[2] = {r1, r2};
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        uint32_t r = (uint32_t)rr[t];
+        if (pre <= r && r < pre + tot) {
+            uint32_t cum = pre;
+            for (int q = 0; q < per; ++q) {
+                if (r < cum + c[q]) {
+                    sh.sel_bin[t] = tid * per + q;
+                    sh.sel_cum[t] = cum;
+                    break;
+                }
+                cum += c[q];
+            }
+        }
+    }
+    __syncthreads();
+    const int b1 = sh.sel_bin[0], b2 = sh.sel_bin[1];
+    const uint32_t cb = sh.sel_cum[0];
+    // gather the pixels of bins [b1, b2] (bins strictly between are empty)
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if ((alive >> k) & 1ull) {
+            int b = bin_of(v[k], lo, scale);
+            if (b >= b1 && b <= b2) {
+                uint32_t s = atomicAdd(&sh.cnt, 1u);
+                if (s < (uint32_t)kList) sh.list[s] = v[k];
+                uint32_t key = f2ord(v[k]);
+                atomicMin(&sh.kmin, key);
+                atomicMax(&sh.kmax, key);
+            }
+        }
+    }
+    __syncthreads();
+    const int m = (int)sh.cnt;
+    const int k1 = r1 - (int)cb, k2 = r2 - (int)cb;
+    const uint32_t kmin = sh.kmin, kmax = sh.kmax;
+    if (kmin == kmax) {
+        o1 = o2 = ord2f(kmin);
+        __syncthreads();
+        return;
+    }
+    if (m <= kList) {
+        for (int e = tid; e < m; e += kMeshThreads) {
+            float x = sh.list[e];
+            int less = 0, eq = 0;
+            for (int j2 = 0; j2 < m; ++j2) {
+                float y = sh.list[j2];
+                less += (y < x);
+                eq += (y == x);
+            }
+            if (less <= k1 && k1 < less + eq) sh.out[0] = x;
+            if (less <= k2 && k2 < less + eq) sh.out[1] = x;
+        }
+        __syncthreads();
+        o1 = sh.out[0];
+        o2 = sh.out[1];
+        __syncthreads();
+        return;
+    }
+    // Many pixels in the target bins (heavy ties in float data): bisection on
+    // the order-preserving keys of the subset, 32 counting passes at most.
+    const int kk[2] = {k1, k2};
+    float res[2];
+    for (int t = 0; t < 2; ++t) {
+        uint32_t a = kmin, z = kmax;
+        while (a < z) {
+            uint32_t mid = a + ((z - a) >> 1);
+            int cnt = 0;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                if ((alive >> k) & 1ull) {
+                    int b = bin_of(v[k], lo, scale);
+                    cnt += (b >= b1 && b <= b2 && f2ord(v[k]) <= mid);
+                }
+            }
+            cnt = block_sum_i(cnt, sh);
+            if (cnt > kk[t]) z = mid;
+            else a = mid + 1;
+        }
+        res[t] = ord2f(a);
+    }
+    o1 = res[0];
+    o2 = res[1];
+}
+
+template <int PPT>
+__global__ __launch_bounds__(kMeshThreads) void k_mesh_stats(const FrameDesc* __restrict__ desc,
+                                                             int nframes, BkgArgs a) {
+    __shared__ MeshShared sh;
+    const int tid = threadIdx.x;
+    const int gm = blockIdx.x;
+    const int f = frame_of(nframes, gm, [&](int i) { return desc[i].mesh_base; });
+    const FrameDesc d = desc[f];
+    const int lm = gm - d.mesh_base;
+    const int mi = lm % d.nx, mj = lm / d.nx;
+    const int x0 = mi * d.mw, y0 = mj * d.mh;
+    const int w = min(d.mw, d.W - x0), h = min(d.mh, d.H - y0);
+    const int n = w * h;
+
+    float v[PPT];
+    uint64_t alive = 0ull;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        int p = k * kMeshThreads + tid;
+        v[k] = 0.0f;
+        if (p < n) {
+            int yy = p / w;
+            int xx = p - yy * w;
+            v[k] = load_px(d, x0 + xx, y0 + yy);
+            alive |= 1ull << k;
+        }
+    }
+    // pass 0: sigma0 of all pixels (sums shifted by the first pixel)
+    const float c0 = load_px(d, x0, y0);
+    F2 s1{0.f, 0.f}, s2{0.f, 0.f};
+    float mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if ((alive >> k) & 1ull) {
+            float dd = v[k] - c0;
+            f2_acc(s1, dd);
+            f2_acc(s2, dd * dd);
+            mn = fminf(mn, v[k]);
+            mx = fmaxf(mx, v[k]);
+        }
+    }
+    int cnt = 0;
+    block_stats(s1, s2, cnt, mn, mx, sh);
+    const int out_idx = mj * d.nx + mi;
+    if (mn == mx) {
+        if (tid == 0) {
+            d.back_raw[out_idx] = (double)mn;
+            d.rms_raw[out_idx] = 0.0;
+            d.iters[out_idx] = 0;
+        }
+        return;
+    }
+    const double nd0 = (double)n;
+    double m1 = f2_d(s1) / nd0;
+    double var = f2_d(s2) / nd0 - m1 * m1;
+    const double sig0 = sqrt(var > 0.0 ? var : 0.0);
+    double mean = (double)c0 + m1;
+    double sig = sig0;
+    int ncur = n;
+
+    // median of all pixels: it lies within one sigma of the mean
+    auto median_of = [&](uint64_t al, int nn, float lo, float hi, float& mh, float& ml) {
+        int r2 = nn / 2;
+        int r1 = (nn & 1) ? r2 : r2 - 1;
+        float o1, o2;
+        select_pair<PPT>(v, al, lo, hi, r1, r2, o1, o2, sh);
+        if (r1 == r2) {
+            mh = o1;
+            ml = 0.0f;
+        } else {
+            // (o1 + o2) / 2 as an unevaluated pair: exact
+            float s, e;
+            two_sum(o1, o2, s, e);
+            mh = 0.5f * s;
+            ml = 0.5f * e;
+        }
+    };
+    float med_h, med_l;
+    median_of(alive, ncur, (float)(mean - sig0), (float)(mean + sig0), med_h, med_l);
+
+    int iters = 0;
+    for (int it = 0; it < a.max_iter; ++it) {
+        const float thr = (float)((double)a.clip * sig);
+        // clip pass: new set, its shifted sums and its histogram window
+        uint64_t nal = 0ull;
+        F2 t1{0.f, 0.f}, t2{0.f, 0.f};
+        float lmn = INFINITY, lmx = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if ((alive >> k) & 1ull) {
+                float dd = v[k] - med_h;
+                float dv = dd - med_l;
+                if (fabsf(dv) <= thr) {
+                    nal |= 1ull << k;
+                    f2_acc(t1, dd);
+                    f2_acc(t2, dd * dd);
+                    lmn = fminf(lmn, v[k]);
+                    lmx = fmaxf(lmx, v[k]);
+                }
+            }
+        }
+        int nn = 0;
+        // per-thread count
+        nn = __popcll(nal);
+        block_stats(t1, t2, nn, lmn, lmx, sh);
+        ++iters;
+        if (nn == ncur || nn == 0) break;
+        alive = nal;
+        ncur = nn;
+        const double nd = (double)nn;
+        double q1 = f2_d(t1) / nd;
+        double vv = f2_d(t2) / nd - q1 * q1;
+        mean = (double)med_h + q1;
+        sig = (lmn == lmx) ? 0.0 : sqrt(vv > 0.0 ? vv : 0.0);
+        const float wlo = (float)((double)med_h - (double)thr);
+        const float whi = (float)((double)med_h + (double)thr);
+        median_of(alive, ncur, wlo, whi, med_h, med_l);
+    }
+    if (tid == 0) {
+        const double med = (double)med_h + (double)med_l;
+        const double dsig = fabs(sig - sig0);
+        const double back = (dsig < (double)a.crowd * sig0) ? mean
+                                                             : ((double)a.mode_a * med - (double)a.mode_b * mean);
+        d.back_raw[out_idx] = back;
+        d.rms_raw[out_idx] = sig;
+        d.iters[out_idx] = iters;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// f x f median over the mesh grid, back and rms separately
+__device__ double median_small(double* w, int n) {
+    for (int i = 1; i < n; ++i) {
+        double x = w[i];
+        int j = i - 1;
+        while (j >= 0 && w[j] > x) {
+            w[j + 1] = w[j];
+            --j;
+        }
+        w[j + 1] = x;
+    }
+    return (n & 1) ? w[n / 2] : 0.5 * (w[n / 2 - 1] + w[n / 2]);
+}
+
+__global__ void k_grid_filter(const FrameDesc* __restrict__ desc, int nframes, int total, int fsize) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int f = frame_of(nframes, g, [&](int i) { return desc[i].mesh_base; });
+    const FrameDesc& d = desc[f];
+    const int lm = g - d.mesh_base;
+    const int i = lm % d.nx, j = lm / d.nx;
+    const int hh = fsize / 2;
+    double w[49];
+    for (int q = 0; q < 2; ++q) {
+        const double* src = q ? d.rms_raw : d.back_raw;
+        double* dst = q ? d.rms : d.back;
+        int n = 0;
+        for (int b = j - hh; b <= j + hh; ++b)
+            for (int c = i - hh; c <= i + hh; ++c)
+                if (b >= 0 && b < d.ny && c >= 0 && c < d.nx) w[n++] = src[b * d.nx + c];
+        dst[lm] = median_small(w, n);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// natural spline second derivatives through (t_k, f_k), k < n, by Thomas
+// elimination; f and m are strided views, work holds 2n doubles
+__device__ void natural_second(int n, const double* t, const double* f, int fs, double* m, int ms,
+                               double* work) {
+    for (int k = 0; k < n; ++k) m[k * ms] = 0.0;
+    if (n < 3) return;
+    double* c = work;
+    double* r = work + n;
+    for (int k = 1; k <= n - 2; ++k) {
+        double h0 = t[k] - t[k - 1], h1 = t[k + 1] - t[k];
+        double rhs = 6.0 * ((f[(k + 1) * fs] - f[k * fs]) / h1 - (f[k * fs] - f[(k - 1) * fs]) / h0);
+        double b = 2.0 * (h0 + h1);
+        if (k == 1) {
+            c[k] = h1 / b;
+            r[k] = rhs / b;
+        } else {
+            double den = b - h0 * c[k - 1];
+            c[k] = h1 / den;
+            r[k] = (rhs - h0 * r[k - 1]) / den;
+        }
+    }
+    m[(n - 2) * ms] = r[n - 2];
+    for (int k = n - 3; k >= 1; --k) m[k * ms] = r[k] - c[k] * m[(k + 1) * ms];
+}
+
+// cubic of one spline piece in local coordinate s = t - ref:
+// piece 0 (t < t_0) and piece n (t >= t_{n-1}) are the end tangents,
+// piece j in [1, n-1] spans [t_{j-1}, t_j)
+__device__ void piece_poly(int n, const double* t, const double* f, int fs, const double* m, int ms,
+                           int piece, double out[4]) {
+    out[0] = out[1] = out[2] = out[3] = 0.0;
+    if (n == 1) {
+        out[0] = f[0];
+        return;
+    }
+    if (piece == 0) {
+        double h = t[1] - t[0];
+        out[0] = f[0];
+        out[1] = (f[fs] - f[0]) / h - h * (2.0 * m[0] + m[ms]) / 6.0;
+        return;
+    }
+    if (piece == n) {
+        double h = t[n - 1] - t[n - 2];
+        out[0] = f[(n - 1) * fs];
+        out[1] = (f[(n - 1) * fs] - f[(n - 2) * fs]) / h + h * (m[(n - 2) * ms] + 2.0 * m[(n - 1) * ms]) / 6.0;
+        return;
+    }
+    int j = piece - 1;
+    double h = t[j + 1] - t[j];
+    double mj = m[j * ms], mj1 = m[(j + 1) * ms];
+    out[0] = f[j * fs];
+    out[1] = (f[(j + 1) * fs] - f[j * fs]) / h - h * (2.0 * mj + mj1) / 6.0;
+    out[2] = 0.5 * mj;
+    out[3] = (mj1 - mj) / (6.0 * h);
+}
+
+// y-splines: one thread per (frame, quantity, mesh column); knots are
+// recomputed here from the mesh geometry (at most 4096 per axis)
+__global__ void k_spline_y(const FrameDesc* __restrict__ desc, int nframes, int total) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    // flattened over frames with 2 * nx entries each; base = 2 * sum(nx)
+    int f = 0;
+    {
+        int acc = 0;
+        for (; f < nframes; ++f) {
+            int c = 2 * desc[f].nx;
+            if (g < acc + c) break;
+            acc += c;
+        }
+        g -= acc;
+    }
+    const FrameDesc& d = desc[f];
+    const int q = g / d.nx, i = g % d.nx;
+    const int ny = d.ny, nx = d.nx;
+    const double* grid = q ? d.rms : d.back;
+    double* scr = d.scratch + (size_t)(q * nx + i) * (size_t)(4 * ny);
+    double* tk = scr;            // knots
+    double* mm = scr + ny;       // second derivatives
+    double* wk = scr + 2 * ny;   // 2 ny work
+    for (int k = 0; k < ny; ++k) tk[k] = knot_at(k, d.H, d.mh);
+    natural_second(ny, tk, grid + i, nx, mm, 1, wk);
+    for (int jy = 0; jy <= ny; ++jy) {
+        double c[4];
+        piece_poly(ny, tk, grid + i, nx, mm, 1, jy, c);
+        double* o = d.ycoef + (((size_t)q * (ny + 1) + jy) * nx + i) * 4;
+        o[0] = c[0];
+        o[1] = c[1];
+        o[2] = c[2];
+        o[3] = c[3];
+    }
+}
+
+// x-basis: coefficients of every x piece as a linear function of the knot
+// values (cardinal natural splines), lx[ix][p][k]
+__global__ void k_spline_xbasis(const FrameDesc* __restrict__ desc, int nframes, int total) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int f = 0;
+    {
+        int acc = 0;
+        for (; f < nframes; ++f) {
+            int c = desc[f].nx;
+            if (g < acc + c) break;
+            acc += c;
+        }
+        g -= acc;
+    }
+    const FrameDesc& d = desc[f];
+    const int nx = d.nx, ny = d.ny, k = g;
+    double* scr = d.scratch + (size_t)(2 * nx) * (size_t)(4 * ny) + (size_t)k * (size_t)(5 * nx);
+    double* tk = scr;
+    double* e = scr + nx;
+    double* mm = scr + 2 * nx;
+    double* wk = scr + 3 * nx;
+    for (int j = 0; j < nx; ++j) {
+        tk[j] = knot_at(j, d.W, d.mw);
+        e[j] = (j == k) ? 1.0 : 0.0;
+    }
+    natural_second(nx, tk, e, 1, mm, 1, wk);
+    for (int ix = 0; ix <= nx; ++ix) {
+        double c[4];
+        piece_poly(nx, tk, e, 1, mm, 1, ix, c);
+        for (int p = 0; p < 4; ++p) d.lx[((size_t)ix * 4 + p) * nx + k] = c[p];
+    }
+}
+
+// bicubic pieces: coef[q][jy][ix][p*4+r] = sum_k lx[ix][p][k] ycoef[q][jy][k][r]
+__global__ void k_spline_pieces(const FrameDesc* __restrict__ desc, int nframes, int total) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int f = 0;
+    {
+        int acc = 0;
+        for (; f < nframes; ++f) {
+            int c = 2 * (desc[f].nx + 1) * (desc[f].ny + 1);
+            if (g < acc + c) break;
+            acc += c;
+        }
+        g -= acc;
+    }
+    const FrameDesc& d = desc[f];
+    const int nx = d.nx, ny = d.ny;
+    const int ix = g % (nx + 1);
+    const int jy = (g / (nx + 1)) % (ny + 1);
+    const int q = g / ((nx + 1) * (ny + 1));
+    double acc[16];
+    for (int z = 0; z < 16; ++z) acc[z] = 0.0;
+    const double* Y = d.ycoef + (((size_t)q * (ny + 1) + jy) * nx) * 4;
+    for (int k = 0; k < nx; ++k) {
+        const double* yk = Y + (size_t)k * 4;
+        for (int p = 0; p < 4; ++p) {
+            double l = d.lx[((size_t)ix * 4 + p) * nx + k];
+            if (l == 0.0) continue;
+            for (int r = 0; r < 4; ++r) acc[p * 4 + r] += l * yk[r];
+        }
+    }
+    double* o = d.coef + (((size_t)q * (ny + 1) + jy) * (nx + 1) + ix) * 16;
+    for (int z = 0; z < 16; ++z) o[z] = acc[z];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+void launch_mesh_stats(const FrameDesc* desc, int nframes, int total_meshes, int max_area, BkgArgs a,
+                       hipStream_t s) {
+    if (max_area <= 16 * kMeshThreads)
+        k_mesh_stats<16><<<total_meshes, kMeshThreads, 0, s>>>(desc, nframes, a);
+    else if (max_area <= 32 * kMeshThreads)
+        k_mesh_stats<32><<<total_meshes, kMeshThreads, 0, s>>>(desc, nframes, a);
+    else
+        k_mesh_stats<64><<<total_meshes, kMeshThreads, 0, s>>>(desc, nframes, a);
+}
+
+void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, int fsize, hipStream_t s) {
+    k_grid_filter<<<(total_meshes + 255) / 256, 256, 0, s>>>(desc, nframes, total_meshes, fsize);
+}
+
+void launch_spline(const FrameDesc* desc, int nframes, int total_ycols, int total_xk, int total_pieces,
+                   hipStream_t s) {
+    k_spline_y<<<(total_ycols + 63) / 64, 64, 0, s>>>(desc, nframes, total_ycols);
+    k_spline_xbasis<<<(total_xk + 63) / 64, 64, 0, s>>>(desc, nframes, total_xk);
+    k_spline_pieces<<<(total_pieces + 255) / 256, 256, 0, s>>>(desc, nframes, total_pieces);
+}
+
+// ---------------------------------------------------------------------------
+// full-resolution background and noise maps of one frame (diagnostic output;
+// the same per-row cubic and per-pixel evaluation as the detection kernel)
+template <typename Real>
+__global__ __launch_bounds__(256) void k_bkg_map(FrameDesc d, double* bmap, double* rmap) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= d.W) return;
+    for (int y = blockIdx.y; y < d.H; y += gridDim.y) {
+    const int jy = piece_of(y, d.H, d.mh);
+    const double u = (double)y - piece_ref(jy, d.H, d.mh);
+    const int ix = piece_of(x, d.W, d.mw);
+    const RowT<Real> t = make_row<Real>(d.coef, d.nx, d.ny, ix, jy, u);
+    const Real s = (Real)((double)x - piece_ref(ix, d.W, d.mw));
+    const size_t o = (size_t)y * d.W + x;
+    if (bmap) bmap[o] = eval_B(t, s);
+    if (rmap) rmap[o] = (double)eval_R(t, s);
+    }
+}
+
+void launch_bkg_map(const FrameDesc& d, double* bmap, double* rmap, bool f64, hipStream_t s) {
+    dim3 grid((d.W + 255) / 256, d.H < 32768 ? d.H : 32768);
+    if (f64) k_bkg_map<double><<<grid, 256, 0, s>>>(d, bmap, rmap);
+    else k_bkg_map<float><<<grid, 256, 0, s>>>(d, bmap, rmap);
+}
+
+}  // namespace gpk

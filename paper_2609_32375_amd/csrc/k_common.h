@@ -1,0 +1,211 @@
+// k_common.h -- device-side descriptors and helpers shared by the gfx950 kernels.
+//
+// Frames of a batch are described by FrameDesc records that live in the
+// workspace; every stage kernel works on a flattened index space (meshes,
+// tiles, objects) over all frames and finds its frame by a binary search over
+// per-frame prefix offsets.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpk {
+
+constexpr int kTile = 64;          // detection tile edge; equals the wavefront width
+constexpr int kMaxK = 15;          // largest filter edge
+constexpr int kMaxR = kMaxK / 2;   // largest filter half-width
+constexpr int kNixMax = 8;         // spline x-pieces a tile region can touch (mesh >= 16)
+constexpr int kRegion = kTile + 2 * kMaxR;  // 78: tile plus filter halo
+constexpr int kLocalRecs = 160;    // components per tile accumulated in LDS
+constexpr int kMaxRadii = 8;
+constexpr int kDescChunk = 8;      // descriptors written per init launch
+
+enum : int { kDtypeU16 = 1, kDtypeF32 = 2 };
+enum : uint32_t { kFlagSat = 1u, kFlagEdge = 2u, kFlagNonpos = 4u, kFlagTrunc = 8u };
+
+struct FrameDesc {
+    const void* data;
+    int64_t pitch;
+    int32_t W, H, dtype, pad0;
+    int32_t mw, mh, nx, ny;
+    double* back_raw;     // [ny][nx]
+    double* rms_raw;
+    double* back;         // filtered
+    double* rms;
+    double* coef;         // [2][ny+1][nx+1][16]
+    int32_t* iters;       // [ny][nx]
+    double* ycoef;        // workspace: [2][ny+1][nx][4]
+    double* lx;           // workspace: [nx+1][4][nx]
+    double* scratch;      // workspace: Thomas sweeps, [2 * nx + nx][2 * max(nx, ny)]
+    int32_t mesh_base;    // first flattened mesh of this frame
+    int32_t tile_base;    // first flattened detection tile
+    int32_t ntx, nty;     // detection tiles per row / column
+    uint32_t* bitmap;     // first-pixel bitmap of this frame (1024-bit blocks)
+    int32_t bm_block_base, nblocks;
+    int32_t cat_base;     // first catalogue row of this frame
+    int32_t pad1;
+    int32_t* seg;         // nullable segmentation map (int32 [H][W])
+};
+
+struct DescChunk {
+    int32_t first, count;
+    FrameDesc d[kDescChunk];
+};
+
+// Per-component partial record (one per connected piece inside one tile;
+// after merging, the root record holds the whole component).  Sums are taken
+// about the reference (x0, y0) = origin of the tile that produced the piece:
+//   s[0..5]  = sum M, M dx, M dy, M dx^2, M dy^2, M dx dy
+//   s[6..11] = the same with unit weights (n, dx, dy, ...)
+struct CompRec {
+    double s[12];
+    int32_t xmin, xmax, ymin, ymax;  // frame coordinates
+    uint32_t pmin;                   // raster index of the first pixel in the frame
+    uint32_t peak;                   // order-preserving bits of max M
+    uint32_t flags;
+    int32_t frame;
+    int32_t x0, y0;
+    int32_t pad[2];
+};
+
+struct TileInfo {
+    int32_t base;   // first record id (-1 when the tile holds no component)
+    int32_t ncomp;
+};
+
+// Workspace pointers used by the detection kernels.
+struct DetWork {
+    FrameDesc* desc;
+    int32_t nframes;
+    int32_t total_tiles;
+    uint32_t* counters;    // [0] records used, [1] overflow flag
+    TileInfo* tiles;       // [total_tiles]
+    int16_t* edges;        // [total_tiles][4][64]: top, bottom, left, right
+    CompRec* recs;         // [rec_cap]
+    int32_t* parent;       // [rec_cap]
+    int32_t* root;         // [rec_cap]
+    int32_t* label;        // [rec_cap]
+    uint32_t* blockcnt;    // [total_blocks + 1] bitmap popcounts -> exclusive prefix
+    uint32_t* chunksum;    // scan helper
+    uint32_t* bitmap;      // all frames' first-pixel bitmaps
+    int32_t rec_cap;
+    int32_t total_blocks;
+};
+
+// ---------------------------------------------------------------------------
+// order-preserving float bits (monotone uint32 image of IEEE float)
+__device__ __forceinline__ uint32_t f2ord(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(uint32_t u) {
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// ---------------------------------------------------------------------------
+// compensated FP32 arithmetic (Knuth two-sum)
+struct F2 {
+    float hi, lo;
+};
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ F2 f2_add(F2 a, F2 b) {
+    float s, e;
+    two_sum(a.hi, b.hi, s, e);
+    e += a.lo + b.lo;
+    float h = s + e;
+    return F2{h, e - (h - s)};
+}
+// running compensated sum of single values
+__device__ __forceinline__ void f2_acc(F2& a, float v) {
+    float s, e;
+    two_sum(a.hi, v, s, e);
+    a.hi = s;
+    a.lo += e;
+}
+__device__ __forceinline__ double f2_d(F2 a) { return (double)a.hi + (double)a.lo; }
+
+// deterministic wavefront reductions (fixed butterfly order)
+__device__ __forceinline__ F2 wave_sum_f2(F2 v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        F2 w{__shfl_xor(v.hi, o), __shfl_xor(v.lo, o)};
+        // order the operands by lane so both partners compute the same value
+        v = ((threadIdx.x & o) == 0) ? f2_add(v, w) : f2_add(w, v);
+    }
+    return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        double w = __shfl_xor(v, o);
+        v = ((threadIdx.x & o) == 0) ? v + w : w + v;
+    }
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// frame lookup by flattened index: the last frame whose base <= idx
+template <typename Get>
+__device__ __forceinline__ int frame_of(int nframes, int idx, Get base) {
+    int lo = 0, hi = nframes - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (base(mid) <= idx) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// half-sample symmetric reflection into [0, n)
+__device__ __forceinline__ int reflect_idx(int i, int n) {
+    if (i >= 0 && i < n) return i;
+    int p = 2 * n;
+    int r = i % p;
+    if (r < 0) r += p;
+    return (r < n) ? r : (p - 1 - r);
+}
+
+__device__ __forceinline__ float load_px(const FrameDesc& d, int x, int y) {
+    int64_t off = (int64_t)y * d.pitch + x;
+    if (d.dtype == kDtypeU16) return (float)((const uint16_t*)d.data)[off];
+    return ((const float*)d.data)[off];
+}
+
+// mesh centre ("knot") along an axis and the spline piece holding a pixel:
+// piece k spans [c_{k-1}, c_k); piece 0 and piece n extend to the frame edges
+__device__ __forceinline__ double knot_at(int k, int n, int m) {
+    int a = k * m;
+    int b = min(a + m, n);
+    return 0.5 * (double)(a + b - 1);
+}
+__device__ __forceinline__ int piece_of(int p, int n, int m) {
+    int k0 = p / m;
+    int a = k0 * m;
+    int b = min(a + m, n);
+    // c_{k0} = (a + b - 1) / 2 ; p >= c_{k0}  <=>  2p >= a + b - 1
+    return k0 + ((2 * p >= a + b - 1) ? 1 : 0);
+}
+__device__ __forceinline__ double piece_ref(int piece, int n, int m) {
+    return knot_at(piece > 0 ? piece - 1 : 0, n, m);
+}
+
+}  // namespace gpk

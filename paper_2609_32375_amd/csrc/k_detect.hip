@@ -1,0 +1,846 @@
+// k_detect.hip -- matched-filter detection, connected components and moments.
+//
+//  k_detect_tiles  one workgroup (4 wavefronts) per 64x64 tile.  Builds
+//                  M = I - B over the tile plus the filter halo in LDS
+//                  (reflected borders), correlates it with the unit-sum kernel
+//                  (two 1-D passes for a rank-one kernel), thresholds F > t R,
+//                  labels the tile's components with a lock-free union-find in
+//                  LDS (roots = smallest raster index), numbers them in raster
+//                  order and accumulates per-piece moments: each lane owns one
+//                  column and sums column runs with compensated FP32, flushing a
+//                  run into the piece's record when it ends.  Border labels are
+//                  kept for the merge.
+//  k_merge_edges   unions pieces that touch across tile borders (8- or
+//                  4-neighbourhood) in a global union-find.
+//  k_merge_records adds every non-root piece into its root record.
+//  k_mark_kept     sets the first-pixel bit of every component with
+//                  npix >= minarea in a per-frame bitmap.
+//  k_scan_*        prefix sums of the bitmap's popcounts -> label = rank of
+//                  the first pixel in raster order.
+//  k_write_catalog moment normalisation (FP64) and catalogue rows.
+//  k_seg_finalize  optional per-pixel label map.
+//
+// The paper's detection is a matched filter normalised by the noise map with a
+// threshold in sigma and first-moment positions; grouping pixels into
+// connected components, minarea and the second moments are the SExtractor
+// conventions this path adds.
+#include "k_args.h"
+#include "k_rowpoly.h"
+
+#include <algorithm>
+
+namespace gpk {
+
+struct LocalRec {
+    double s[12];
+    int32_t xmin, xmax, ymin, ymax;
+    uint32_t peak, flags;
+    int32_t rootpix, pad;
+};
+
+template <typename Real>
+struct DetShared {
+    union U1 {
+        RowT<Real> tab[kRegion * kNixMax];
+        Real hs[kRegion * kTile];
+        LocalRec rec[kLocalRecs];
+    } u1;
+    union U2 {
+        Real ms[kRegion * (kRegion + 1)];
+        struct {
+            int32_t lab[kTile * kTile];
+            int16_t comp[kTile * kTile];
+        } l;
+    } u2;
+    int32_t colx[kRegion], rowy[kRegion], colp[kRegion];
+    Real cols[kRegion];
+    uint32_t wsum[4];
+    int32_t misc[4];
+};
+
+__device__ __forceinline__ int lds_find(int* L, int x) {
+    volatile int* V = L;
+    while (true) {
+        int q = V[x];
+        if (q == x) return x;
+        x = q;
+    }
+}
+__device__ __forceinline__ void lds_union(int* L, int a, int b) {
+    while (true) {
+        a = lds_find(L, a);
+        b = lds_find(L, b);
+        if (a < b) {
+            int old = atomicMin(&L[b], a);
+            if (old == b) return;
+            b = old;
+        } else if (b < a) {
+            int old = atomicMin(&L[a], b);
+            if (old == a) return;
+            a = old;
+        } else {
+            return;
+        }
+    }
+}
+__device__ __forceinline__ int g_find(int* P, int x) {
+    volatile int* V = P;
+    while (true) {
+        int q = V[x];
+        if (q == x) return x;
+        x = q;
+    }
+}
+__device__ __forceinline__ void g_union(int* P, int a, int b) {
+    while (true) {
+        a = g_find(P, a);
+        b = g_find(P, b);
+        if (a < b) {
+            int old = atomicMin(&P[b], a);
+            if (old == b) return;
+            b = old;
+        } else if (b < a) {
+            int old = atomicMin(&P[a], b);
+            if (old == a) return;
+            a = old;
+        } else {
+            return;
+        }
+    }
+}
+
+template <typename Real>
+struct RunAcc;
+template <>
+struct RunAcc<float> {
+    F2 S, T, U;
+    __device__ void reset() { S = T = U = F2{0.f, 0.f}; }
+    __device__ void add(float m, float dy) {
+        f2_acc(S, m);
+        f2_acc(T, dy * m);
+        f2_acc(U, dy * dy * m);
+    }
+    __device__ double s() const { return f2_d(S); }
+    __device__ double t() const { return f2_d(T); }
+    __device__ double u() const { return f2_d(U); }
+};
+template <>
+struct RunAcc<double> {
+    double S, T, U;
+    __device__ void reset() { S = T = U = 0.0; }
+    __device__ void add(double m, double dy) {
+        S += m;
+        T += dy * m;
+        U += dy * dy * m;
+    }
+    __device__ double s() const { return S; }
+    __device__ double t() const { return T; }
+    __device__ double u() const { return U; }
+};
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs* __restrict__ pa) {
+    __shared__ DetShared<Real> sh;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int gt = blockIdx.x;
+    const int f = frame_of(wk.nframes, gt, [&](int i) { return wk.desc[i].tile_base; });
+    const FrameDesc d = wk.desc[f];
+    const int lt = gt - d.tile_base;
+    const int tx = lt % d.ntx, ty = lt / d.ntx;
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int tw = min(kTile, d.W - x0), th = min(kTile, d.H - y0);
+    const int kw = pa->kw, kh = pa->kh;
+    const int rx = kw >> 1, ry = kh >> 1;
+    const int RW = tw + 2 * rx, RH = th + 2 * ry;
+    const int xs_lo = max(0, x0 - rx), xs_hi = min(d.W - 1, x0 + tw - 1 + rx);
+    const int ixlo = piece_of(xs_lo, d.W, d.mw);
+    const int nix = piece_of(xs_hi, d.W, d.mw) - ixlo + 1;
+    constexpr int MS = kRegion + 1;
+
+    // region column / row geometry
+    if (tid < RW) {
+        int xs = reflect_idx(x0 - rx + tid, d.W);
+        int ix = piece_of(xs, d.W, d.mw);
+        sh.colx[tid] = xs;
+        sh.colp[tid] = ix - ixlo;
+        sh.cols[tid] = (Real)((double)xs - piece_ref(ix, d.W, d.mw));
+    }
+    if (tid >= 128 && tid - 128 < RH) sh.rowy[tid - 128] = reflect_idx(y0 - ry + (tid - 128), d.H);
+    __syncthreads();
+    // 1. per region row and x piece: the row's cubic (FP64 -> working precision)
+    for (int e = tid; e < RH * nix; e += 256) {
+        int r = e / nix, pi = e - r * nix;
+        int ys = sh.rowy[r];
+        int jy = piece_of(ys, d.H, d.mh);
+        double u = (double)ys - piece_ref(jy, d.H, d.mh);
+        sh.u1.tab[r * kNixMax + pi] = make_row<Real>(d.coef, d.nx, d.ny, ixlo + pi, jy, u);
+    }
+    __syncthreads();
+    // 2. M = I - B over tile + halo
+    for (int r = wv; r < RH; r += 4) {
+        const int ys = sh.rowy[r];
+        const RowT<Real>* trow = &sh.u1.tab[r * kNixMax];
+        for (int c = lane; c < RW; c += 64) {
+            Real v = (Real)load_px(d, sh.colx[c], ys);
+            sh.u2.ms[r * MS + c] = eval_M(trow[sh.colp[c]], sh.cols[c], v);
+        }
+    }
+    __syncthreads();
+    // 3. the 16 pixels this lane owns: column `lane`, rows 16*wv .. 16*wv+15
+    const bool colok = lane < tw;
+    Real Mo[16], To[16];
+    float Io[16];
+    const bool has_sat = pa->sat < INFINITY;
+    {
+        const Real th_s = (Real)pa->thresh;
+        const RowT<Real>* tb = sh.u1.tab;
+        const int cc = lane + rx;
+        const int cp = colok ? sh.colp[cc] : 0;
+        const Real cs = colok ? sh.cols[cc] : (Real)0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int ly = 16 * wv + k;
+            Mo[k] = 0;
+            To[k] = 0;
+            Io[k] = 0.f;
+            if (colok && ly < th) {
+                Mo[k] = sh.u2.ms[(ly + ry) * MS + cc];
+                To[k] = th_s * eval_R(tb[(ly + ry) * kNixMax + cp], cs);
+                if (has_sat) Io[k] = load_px(d, x0 + lane, y0 + ly);
+            }
+        }
+    }
+    __syncthreads();
+    // 4. matched filter
+    Real Fo[16];
+    const bool dbl = sizeof(Real) == 8;
+    if (pa->separable) {
+        for (int r = wv; r < RH; r += 4) {
+            if (colok) {
+                Real acc = 0;
+                const Real* mr = &sh.u2.ms[r * MS + lane];
+                for (int b = 0; b < kw; ++b) acc += (dbl ? (Real)pa->kxd[b] : (Real)pa->kx[b]) * mr[b];
+                sh.u1.hs[r * kTile + lane] = acc;
+            }
+        }
+        __syncthreads();
+        Real win[16 + 2 * kMaxR];
+        const int nwin = 16 + 2 * ry;
+        for (int q = 0; q < nwin; ++q) {
+            int r = 16 * wv + q;
+            win[q] = (colok && r < RH) ? sh.u1.hs[r * kTile + lane] : (Real)0;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            Real acc = 0;
+            for (int aa = 0; aa < kh; ++aa) acc += (dbl ? (Real)pa->kyd[aa] : (Real)pa->ky[aa]) * win[k + aa];
+            Fo[k] = acc;
+        }
+    } else {
+#pragma unroll 1
+        for (int k = 0; k < 16; ++k) {
+            const int ly = 16 * wv + k;
+            Real acc = 0;
+            if (colok && ly < th) {
+                for (int aa = 0; aa < kh; ++aa) {
+                    const Real* mr = &sh.u2.ms[(ly + aa) * MS + lane];
+                    for (int b = 0; b < kw; ++b)
+                        acc += (dbl ? (Real)pa->kdd[aa * kw + b] : (Real)pa->kd[aa * kw + b]) * mr[b];
+                }
+            }
+            Fo[k] = acc;
+        }
+    }
+    uint32_t mbits = 0u;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int ly = 16 * wv + k;
+        if (colok && ly < th && Fo[k] > To[k]) mbits |= 1u << k;
+    }
+    const int any = __syncthreads_or(mbits != 0u);
+    int32_t* seg = d.seg;
+    if (!any) {
+        if (tid == 0) wk.tiles[gt] = TileInfo{-1, 0};
+        if (seg && colok) {
+            for (int k = 0; k < 16; ++k) {
+                int ly = 16 * wv + k;
+                if (ly < th) seg[(int64_t)(y0 + ly) * d.W + x0 + lane] = -1;
+            }
+        }
+        return;
+    }
+    // 5. connected components inside the tile (LDS union-find)
+    int32_t* lab = sh.u2.l.lab;
+    int16_t* comp = sh.u2.l.comp;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int p = (16 * wv + k) * kTile + lane;
+        lab[p] = ((mbits >> k) & 1u) ? p : -1;
+    }
+    __syncthreads();
+    const bool conn8 = pa->conn == 8;
+#pragma unroll 1
+    for (int k = 0; k < 16; ++k) {
+        if (!((mbits >> k) & 1u)) continue;
+        const int ly = 16 * wv + k;
+        const int p = ly * kTile + lane;
+        if (lane > 0 && lab[p - 1] >= 0) lds_union(lab, p, p - 1);
+        if (ly > 0) {
+            if (lab[p - kTile] >= 0) lds_union(lab, p, p - kTile);
+            if (conn8) {
+                if (lane > 0 && lab[p - kTile - 1] >= 0) lds_union(lab, p, p - kTile - 1);
+                if (lane + 1 < tw && lab[p - kTile + 1] >= 0) lds_union(lab, p, p - kTile + 1);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if ((mbits >> k) & 1u) {
+            const int p = (16 * wv + k) * kTile + lane;
+            lab[p] = lds_find(lab, p);
+        }
+    }
+    __syncthreads();
+    // number roots in raster order: thread t scans raster pixels [16t, 16t+16)
+    uint32_t nroot = 0;
+    for (int q = 0; q < 16; ++q) {
+        int p = tid * 16 + q;
+        nroot += (lab[p] == p);
+    }
+    uint32_t incl = nroot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) sh.wsum[wv] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int i = 0; i < wv; ++i) off += sh.wsum[i];
+    const int ncomp = (int)(sh.wsum[0] + sh.wsum[1] + sh.wsum[2] + sh.wsum[3]);
+    {
+        int idx = (int)(off + incl - nroot);
+        for (int q = 0; q < 16; ++q) {
+            int p = tid * 16 + q;
+            if (lab[p] == p) comp[p] = (int16_t)(idx++);
+        }
+    }
+    __syncthreads();
+    int co[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int p = (16 * wv + k) * kTile + lane;
+        co[k] = ((mbits >> k) & 1u) ? (int)comp[lab[p]] : -1;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) comp[(16 * wv + k) * kTile + lane] = (int16_t)co[k];
+    // 6. records for the tile's pieces
+    if (tid == 0) {
+        int base = (int)atomicAdd(&wk.counters[0], (uint32_t)ncomp);
+        if ((int64_t)base + ncomp > (int64_t)wk.rec_cap) {
+            atomicOr(&wk.counters[1], 1u);
+            base = -2;
+        }
+        sh.misc[0] = base;
+    }
+    __syncthreads();
+    const int base = sh.misc[0];
+    if (base < 0) {
+        if (tid == 0) wk.tiles[gt] = TileInfo{-2, 0};
+        return;
+    }
+    const int nloc = min(ncomp, kLocalRecs);
+    for (int c = tid; c < ncomp; c += 256) {
+        wk.parent[base + c] = base + c;
+        if (c < kLocalRecs) {
+            LocalRec& R = sh.u1.rec[c];
+            for (int z = 0; z < 12; ++z) R.s[z] = 0.0;
+            R.xmin = R.ymin = 0x7fffffff;
+            R.xmax = R.ymax = -1;
+            R.peak = 0u;
+            R.flags = 0u;
+        } else {
+            CompRec& R = wk.recs[base + c];
+            for (int z = 0; z < 12; ++z) R.s[z] = 0.0;
+            R.xmin = R.ymin = 0x7fffffff;
+            R.xmax = R.ymax = -1;
+            R.peak = 0u;
+            R.flags = 0u;
+            R.frame = f;
+            R.x0 = x0;
+            R.y0 = y0;
+        }
+    }
+    __syncthreads();
+    // first pixel of every piece = its root
+    for (int q = 0; q < 16; ++q) {
+        int p = tid * 16 + q;
+        if (lab[p] == p) {
+            int c = comp[p];
+            uint32_t pm = (uint32_t)((y0 + p / kTile) * d.W + x0 + (p % kTile));
+            if (c < kLocalRecs) sh.u1.rec[c].rootpix = (int32_t)pm;
+            else wk.recs[base + c].pmin = pm;
+        }
+    }
+    // 7. moments: column runs, compensated, flushed into the piece records
+    {
+        const float sat = pa->sat;
+        const int gx = x0 + lane;
+        RunAcc<Real> run;
+        run.reset();
+        int cur = -1, rcnt = 0, rdy = 0, rdy2 = 0, ry0 = 0, ry1 = 0;
+        float rpk = -INFINITY;
+        uint32_t rfl = 0u;
+        auto flush = [&]() {
+            const bool loc = cur < kLocalRecs;
+            const double dxd = (double)lane;
+            const double S = run.s(), T = run.t(), U = run.u();
+            const double n = (double)rcnt, sy = (double)rdy, syy = (double)rdy2;
+            const double add[12] = {S, dxd * S, T, dxd * dxd * S, U, dxd * T,
+                                    n, dxd * n, sy, dxd * dxd * n, syy, dxd * sy};
+            if (loc) {
+                double* s = sh.u1.rec[cur].s;
+#pragma unroll
+                for (int z = 0; z < 12; ++z) atomicAdd(&s[z], add[z]);
+            } else {
+                double* s = wk.recs[base + cur].s;
+#pragma unroll
+                for (int z = 0; z < 12; ++z) unsafeAtomicAdd(&s[z], add[z]);
+            }
+            if (loc) {
+                LocalRec& R = sh.u1.rec[cur];
+                atomicMin(&R.xmin, gx);
+                atomicMax(&R.xmax, gx);
+                atomicMin(&R.ymin, y0 + ry0);
+                atomicMax(&R.ymax, y0 + ry1);
+                atomicMax(&R.peak, f2ord(rpk));
+                if (rfl) atomicOr(&R.flags, rfl);
+            } else {
+                CompRec& R = wk.recs[base + cur];
+                atomicMin(&R.xmin, gx);
+                atomicMax(&R.xmax, gx);
+                atomicMin(&R.ymin, y0 + ry0);
+                atomicMax(&R.ymax, y0 + ry1);
+                atomicMax(&R.peak, f2ord(rpk));
+                if (rfl) atomicOr(&R.flags, rfl);
+            }
+            run.reset();
+            cur = -1;
+            rcnt = rdy = rdy2 = 0;
+            rpk = -INFINITY;
+            rfl = 0u;
+        };
+#pragma unroll 1
+        for (int k = 0; k < 16; ++k) {
+            const bool m = (mbits >> k) & 1u;
+            const int c = co[k];
+            if (cur >= 0 && (!m || c != cur)) flush();
+            if (m) {
+                const int ly = 16 * wv + k;
+                if (cur < 0) {
+                    cur = c;
+                    ry0 = ly;
+                }
+                ry1 = ly;
+                run.add(Mo[k], (Real)ly);
+                rcnt += 1;
+                rdy += ly;
+                rdy2 += ly * ly;
+                const float mf = (float)Mo[k];
+                rpk = fmaxf(rpk, mf);
+                if (Io[k] >= sat) rfl |= kFlagSat;
+            }
+        }
+        if (cur >= 0) flush();
+    }
+    __syncthreads();
+    // 8. publish the LDS records
+    for (int c = tid; c < nloc; c += 256) {
+        const LocalRec& L = sh.u1.rec[c];
+        CompRec& R = wk.recs[base + c];
+        for (int z = 0; z < 12; ++z) R.s[z] = L.s[z];
+        R.xmin = L.xmin;
+        R.xmax = L.xmax;
+        R.ymin = L.ymin;
+        R.ymax = L.ymax;
+        R.pmin = (uint32_t)L.rootpix;
+        R.peak = L.peak;
+        R.flags = L.flags;
+        R.frame = f;
+        R.x0 = x0;
+        R.y0 = y0;
+    }
+    // 9. border labels for the merge
+    int16_t* E = wk.edges + (size_t)gt * 4 * kTile;
+    if (tid < 64) {
+        E[0 * kTile + tid] = (tid < tw) ? comp[0 * kTile + tid] : (int16_t)-1;
+        E[1 * kTile + tid] = (tid < tw) ? comp[(th - 1) * kTile + tid] : (int16_t)-1;
+    } else if (tid < 128) {
+        const int r = tid - 64;
+        E[2 * kTile + r] = (r < th) ? comp[r * kTile + 0] : (int16_t)-1;
+        E[3 * kTile + r] = (r < th) ? comp[r * kTile + tw - 1] : (int16_t)-1;
+    }
+    if (seg && colok) {
+        for (int k = 0; k < 16; ++k) {
+            int ly = 16 * wv + k;
+            if (ly < th) seg[(int64_t)(y0 + ly) * d.W + x0 + lane] = co[k];
+        }
+    }
+    if (tid == 0) wk.tiles[gt] = TileInfo{base, ncomp};
+}
+
+// ---------------------------------------------------------------------------
+// unions across tile borders: one wavefront per tile (its right and bottom
+// borders, plus the two lower diagonal corners for 8-connectivity)
+__global__ __launch_bounds__(256) void k_merge_edges(DetWork wk, int conn) {
+    if (wk.counters[1] != 0u) return;  // record overflow: the call reports it, nothing to merge
+    const int lane = threadIdx.x & 63;
+    const int gt = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (gt >= wk.total_tiles) return;
+    const TileInfo A = wk.tiles[gt];
+    if (A.ncomp <= 0) return;
+    const int f = frame_of(wk.nframes, gt, [&](int i) { return wk.desc[i].tile_base; });
+    const FrameDesc& d = wk.desc[f];
+    const int lt = gt - d.tile_base;
+    const int tx = lt % d.ntx, ty = lt / d.ntx;
+    const int tw = min(kTile, d.W - tx * kTile), th = min(kTile, d.H - ty * kTile);
+    const int16_t* EA = wk.edges + (size_t)gt * 4 * kTile;
+    const int dj0 = (conn == 8) ? -1 : 0, dj1 = (conn == 8) ? 1 : 0;
+    if (tx + 1 < d.ntx) {
+        const TileInfo B = wk.tiles[gt + 1];
+        if (B.ncomp > 0 && lane < th) {
+            const int16_t* EB = wk.edges + (size_t)(gt + 1) * 4 * kTile;
+            const int a = EA[3 * kTile + lane];
+            if (a >= 0)
+                for (int dj = dj0; dj <= dj1; ++dj) {
+                    const int j = lane + dj;
+                    if (j < 0 || j >= th) continue;
+                    const int b = EB[2 * kTile + j];
+                    if (b >= 0) g_union(wk.parent, A.base + a, B.base + b);
+                }
+        }
+    }
+    if (ty + 1 < d.nty) {
+        const int gc = gt + d.ntx;
+        const TileInfo C = wk.tiles[gc];
+        if (C.ncomp > 0 && lane < tw) {
+            const int16_t* EC = wk.edges + (size_t)gc * 4 * kTile;
+            const int a = EA[1 * kTile + lane];
+            if (a >= 0)
+                for (int dj = dj0; dj <= dj1; ++dj) {
+                    const int j = lane + dj;
+                    if (j < 0 || j >= tw) continue;
+                    const int b = EC[0 * kTile + j];
+                    if (b >= 0) g_union(wk.parent, A.base + a, C.base + b);
+                }
+        }
+        if (conn == 8) {
+            // down-right corner: (x0+63, y0+63) with (x0+64, y0+64)
+            if (lane == 0 && tx + 1 < d.ntx) {
+                const TileInfo D = wk.tiles[gc + 1];
+                const int a = EA[1 * kTile + tw - 1];
+                if (D.ncomp > 0 && a >= 0) {
+                    const int b = wk.edges[(size_t)(gc + 1) * 4 * kTile + 0];
+                    if (b >= 0) g_union(wk.parent, A.base + a, D.base + b);
+                }
+            }
+            // down-left corner: (x0, y0+63) with (x0-1, y0+64)
+            if (lane == 1 && tx > 0) {
+                const TileInfo D = wk.tiles[gc - 1];
+                const int a = EA[1 * kTile + 0];
+                if (D.ncomp > 0 && a >= 0) {
+                    const int b = wk.edges[(size_t)(gc - 1) * 4 * kTile + kTile - 1];
+                    if (b >= 0) g_union(wk.parent, A.base + a, D.base + b);
+                }
+            }
+        }
+    }
+}
+
+// every piece finds its root; non-roots add their sums into the root record
+__global__ __launch_bounds__(256) void k_merge_records(DetWork wk) {
+    if (wk.counters[1] != 0u) return;
+    const int total = min((int)wk.counters[0], wk.rec_cap);
+    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
+        const int r = g_find(wk.parent, id);
+        wk.root[id] = r;
+        if (r == id) continue;
+        const CompRec& S = wk.recs[id];
+        CompRec& R = wk.recs[r];
+        const double ox = (double)(S.x0 - R.x0), oy = (double)(S.y0 - R.y0);
+        for (int h = 0; h < 2; ++h) {
+            const double* s = S.s + 6 * h;
+            double* t = R.s + 6 * h;
+            unsafeAtomicAdd(&t[0], s[0]);
+            unsafeAtomicAdd(&t[1], s[1] + ox * s[0]);
+            unsafeAtomicAdd(&t[2], s[2] + oy * s[0]);
+            unsafeAtomicAdd(&t[3], s[3] + 2.0 * ox * s[1] + ox * ox * s[0]);
+            unsafeAtomicAdd(&t[4], s[4] + 2.0 * oy * s[2] + oy * oy * s[0]);
+            unsafeAtomicAdd(&t[5], s[5] + ox * s[2] + oy * s[1] + ox * oy * s[0]);
+        }
+        atomicMin(&R.xmin, S.xmin);
+        atomicMax(&R.xmax, S.xmax);
+        atomicMin(&R.ymin, S.ymin);
+        atomicMax(&R.ymax, S.ymax);
+        atomicMin(&R.pmin, S.pmin);
+        atomicMax(&R.peak, S.peak);
+        if (S.flags) atomicOr(&R.flags, S.flags);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mark_kept(DetWork wk, int minarea) {
+    if (wk.counters[1] != 0u) return;
+    const int total = min((int)wk.counters[0], wk.rec_cap);
+    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
+        if (wk.root[id] != id) continue;
+        const CompRec& R = wk.recs[id];
+        if (R.s[6] < (double)minarea) continue;
+        const FrameDesc& d = wk.desc[R.frame];
+        atomicOr(&d.bitmap[R.pmin >> 5], 1u << (R.pmin & 31u));
+    }
+}
+
+// popcount of each 1024-bit block
+__global__ __launch_bounds__(256) void k_block_popc(const uint32_t* __restrict__ bm, uint32_t* cnt, int nblocks) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblocks) return;
+    const uint4* p = (const uint4*)(bm + (size_t)b * 32);
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        uint4 q = p[i];
+        c += __popc(q.x) + __popc(q.y) + __popc(q.z) + __popc(q.w);
+    }
+    cnt[b] = c;
+}
+
+// exclusive scan in chunks of 2048 (8 per thread) with chunk totals
+__global__ __launch_bounds__(256) void k_scan_chunks(uint32_t* a, uint32_t* chunksum, int n) {
+    __shared__ uint32_t ws[4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int base = blockIdx.x * 2048 + tid * 8;
+    uint32_t v[8], t = 0;
+    for (int i = 0; i < 8; ++i) {
+        v[i] = (base + i < n) ? a[base + i] : 0u;
+        t += v[i];
+    }
+    uint32_t incl = t;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) ws[wv] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int i = 0; i < wv; ++i) off += ws[i];
+    uint32_t run = off + incl - t;
+    for (int i = 0; i < 8; ++i) {
+        if (base + i < n) a[base + i] = run;
+        run += v[i];
+    }
+    if (tid == 255) chunksum[blockIdx.x] = off + incl;
+}
+
+// exclusive scan of the chunk totals (one workgroup, up to 1024 * 8 chunks);
+// writes the grand total to a[n]
+__global__ __launch_bounds__(1024) void k_scan_tops(uint32_t* chunksum, int nchunks, uint32_t* a, int n) {
+    __shared__ uint32_t ws[16];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int base = tid * 8;
+    uint32_t v[8], t = 0;
+    for (int i = 0; i < 8; ++i) {
+        v[i] = (base + i < nchunks) ? chunksum[base + i] : 0u;
+        t += v[i];
+    }
+    uint32_t incl = t;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) ws[wv] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int i = 0; i < wv; ++i) off += ws[i];
+    uint32_t run = off + incl - t;
+    for (int i = 0; i < 8; ++i) {
+        if (base + i < nchunks) chunksum[base + i] = run;
+        run += v[i];
+    }
+    if (tid == 1023) a[n] = off + incl;
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(uint32_t* a, const uint32_t* chunksum, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] += chunksum[i / 2048];
+}
+
+__global__ __launch_bounds__(256) void k_write_catalog(DetWork wk, CatOut cat, int minarea) {
+    if (wk.counters[1] != 0u) return;
+    const int total = min((int)wk.counters[0], wk.rec_cap);
+    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
+        if (wk.root[id] != id) continue;
+        const CompRec& R = wk.recs[id];
+        if (R.s[6] < (double)minarea) {
+            wk.label[id] = -1;
+            continue;
+        }
+        const FrameDesc& d = wk.desc[R.frame];
+        const uint32_t pm = R.pmin;
+        const int blk = (int)(pm >> 10);
+        const uint32_t* bw = d.bitmap + (size_t)blk * 32;
+        uint32_t rank = wk.blockcnt[d.bm_block_base + blk] - wk.blockcnt[d.bm_block_base];
+        const int wi = (int)((pm >> 5) & 31u);
+        for (int i = 0; i < wi; ++i) rank += __popc(bw[i]);
+        rank += __popc(bw[wi] & ((1u << (pm & 31u)) - 1u));
+        wk.label[id] = (int)rank + 1;
+        if ((int)rank >= cat.capacity) continue;
+        const size_t row = (size_t)d.cat_base + rank;
+        const bool nonpos = !(R.s[0] > 0.0);
+        const double* w = nonpos ? R.s + 6 : R.s;
+        const double W0 = w[0];
+        const double mx = w[1] / W0, my = w[2] / W0;
+        cat.npix[row] = (int32_t)R.s[6];
+        cat.xmin[row] = R.xmin;
+        cat.xmax[row] = R.xmax;
+        cat.ymin[row] = R.ymin;
+        cat.ymax[row] = R.ymax;
+        cat.pmin[row] = (int64_t)pm;
+        cat.flux[row] = R.s[0];
+        cat.x[row] = (double)R.x0 + mx;
+        cat.y[row] = (double)R.y0 + my;
+        cat.x2[row] = w[3] / W0 - mx * mx;
+        cat.y2[row] = w[4] / W0 - my * my;
+        cat.xy[row] = w[5] / W0 - mx * my;
+        cat.peak[row] = ord2f(R.peak);
+        uint32_t fl = R.flags;
+        if (nonpos) fl |= kFlagNonpos;
+        if (R.xmin == 0 || R.ymin == 0 || R.xmax == d.W - 1 || R.ymax == d.H - 1) fl |= kFlagEdge;
+        cat.flags[row] = fl;
+    }
+}
+
+__global__ void k_frame_status(DetWork wk, CatOut cat, int32_t* comp_status) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < wk.nframes) {
+        const FrameDesc& d = wk.desc[f];
+        const int n = (int)(wk.blockcnt[d.bm_block_base + d.nblocks] - wk.blockcnt[d.bm_block_base]);
+        cat.n_obj[f] = n;
+        cat.status[f] = (wk.counters[1] != 0u) ? 3 : ((n > cat.capacity) ? 4 : 0);
+    }
+    if (f == 0 && comp_status) {
+        comp_status[0] = (wk.counters[1] != 0u) ? 3 : 0;
+        comp_status[1] = (int32_t)wk.counters[0];
+    }
+}
+
+// per-pixel labels: piece index -> root -> label (-1 dropped, 0 background)
+__global__ __launch_bounds__(256) void k_seg_finalize(DetWork wk, int f) {
+    if (wk.counters[1] != 0u) return;
+    const FrameDesc& d = wk.desc[f];
+    int32_t* seg = d.seg;
+    const int64_t npx = (int64_t)d.W * d.H;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npx;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int v = seg[p];
+        if (v < 0) {
+            seg[p] = 0;
+            continue;
+        }
+        const int y = (int)(p / d.W), x = (int)(p - (int64_t)y * d.W);
+        const int gt = d.tile_base + (y / kTile) * d.ntx + x / kTile;
+        const TileInfo T = wk.tiles[gt];
+        if (T.base < 0) {
+            seg[p] = 0;
+            continue;
+        }
+        const int id = T.base + v;
+        seg[p] = wk.label[wk.root[id]];
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
+    if (n == 0) return;
+    int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
+    k_fill_u32<<<blocks, 256, 0, s>>>(p, n, v);
+}
+
+void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, hipStream_t s) {
+    if (f64) k_detect_tiles<double><<<wk.total_tiles, 256, 0, s>>>(wk, args);
+    else k_detect_tiles<float><<<wk.total_tiles, 256, 0, s>>>(wk, args);
+}
+
+void launch_merge(const DetWork& wk, int conn, int minarea, int persist_blocks, hipStream_t s) {
+    k_merge_edges<<<(wk.total_tiles + 3) / 4, 256, 0, s>>>(wk, conn);
+    k_merge_records<<<persist_blocks, 256, 0, s>>>(wk);
+    k_mark_kept<<<persist_blocks, 256, 0, s>>>(wk, minarea);
+    const int nb = wk.total_blocks;
+    k_block_popc<<<(nb + 255) / 256, 256, 0, s>>>(wk.bitmap, wk.blockcnt, nb);
+    const int nchunks = (nb + 2047) / 2048;
+    k_scan_chunks<<<nchunks, 256, 0, s>>>(wk.blockcnt, wk.chunksum, nb);
+    k_scan_tops<<<1, 1024, 0, s>>>(wk.chunksum, nchunks, wk.blockcnt, nb);
+    k_scan_add<<<(nb + 255) / 256, 256, 0, s>>>(wk.blockcnt, wk.chunksum, nb);
+}
+
+void launch_catalog(const DetWork& wk, const CatOut& cat, int minarea, int persist_blocks,
+                    int32_t* comp_status, hipStream_t s) {
+    k_write_catalog<<<persist_blocks, 256, 0, s>>>(wk, cat, minarea);
+    k_frame_status<<<(wk.nframes + 63) / 64, 64, 0, s>>>(wk, cat, comp_status);
+}
+
+void launch_seg(const DetWork& wk, int f, int64_t npx, hipStream_t s) {
+    int blocks = (int)std::min<int64_t>((npx + 255) / 256, 16384);
+    k_seg_finalize<<<blocks, 256, 0, s>>>(wk, f);
+}
+
+// descriptor and argument upload (kernel arguments -> workspace)
+__global__ void k_write_desc(DescChunk c, FrameDesc* table) {
+    const int i = threadIdx.x;
+    if (i < c.count) table[c.first + i] = c.d[i];
+}
+
+// the dense kernel is normalised here (sum in FP64, fixed order)
+__global__ void k_write_detargs(DetArgsIn in, DetArgs* out) {
+    if (threadIdx.x != 0) return;
+    out->kw = in.kw;
+    out->kh = in.kh;
+    out->separable = in.separable;
+    out->conn = in.conn;
+    out->thresh = in.thresh;
+    out->sat = in.sat;
+    out->minarea = in.minarea;
+    out->want_seg = in.want_seg;
+    double sum = 0.0;
+    const int n = in.kw * in.kh;
+    for (int i = 0; i < n; ++i) sum += (double)in.kraw[i];
+    const double norm = (sum != 0.0) ? sum : 1.0;
+    for (int i = 0; i < kMaxK * kMaxK; ++i) {
+        const double v = (i < n) ? (double)in.kraw[i] / norm : 0.0;
+        out->kdd[i] = v;
+        out->kd[i] = (float)v;
+    }
+    for (int i = 0; i < kMaxK; ++i) {
+        out->kx[i] = in.kx[i];
+        out->ky[i] = in.ky[i];
+        out->kxd[i] = in.kxd[i];
+        out->kyd[i] = in.kyd[i];
+    }
+}
+
+void launch_write_desc(const DescChunk& c, FrameDesc* table, hipStream_t s) {
+    k_write_desc<<<1, 64, 0, s>>>(c, table);
+}
+
+void launch_write_detargs(const DetArgsIn& in, DetArgs* out, hipStream_t s) {
+    k_write_detargs<<<1, 64, 0, s>>>(in, out);
+}
+
+}  // namespace gpk

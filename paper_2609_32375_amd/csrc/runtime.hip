@@ -1,0 +1,700 @@
+// runtime.hip -- host side of the C ABI declared in include/gp.h.
+//
+// Responsibilities: argument validation (synchronous errors), the layout of
+// the background buffer and of the workspace for a batch of frames, frame
+// descriptors (written into the workspace by small kernels so that the whole
+// call sequence can be captured into a HIP graph), kernel launches on the
+// caller's stream, and optional per-kernel timing with HIP events.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gp.h"
+#include "k_args.h"
+
+using namespace gpk;
+
+// ---------------------------------------------------------------------------
+// errors
+static thread_local std::string g_err;
+
+static gp_status fail(gp_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(GP_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char* gp_last_error(void) { return g_err.c_str(); }
+extern "C" const char* gp_version(void) { return "gpphot 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// context
+struct ProfPair {
+    std::string name;
+    hipEvent_t a, b;
+};
+
+struct gp_ctx {
+    int device = 0;
+    int cus = 256;
+    bool profiling = false;
+    std::mutex mu;
+    std::vector<ProfPair> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<double, int64_t>> totals;
+    std::string tune_path;
+};
+
+namespace {
+struct ProfScope {
+    gp_ctx* c;
+    hipStream_t s;
+    const char* name;
+    hipEvent_t a = nullptr;
+    ProfScope(gp_ctx* c_, hipStream_t s_, const char* n) : c(c_), s(s_), name(n) {
+        if (!c->profiling) return;
+        std::lock_guard<std::mutex> g(c->mu);
+        a = take();
+        (void)hipEventRecord(a, s);
+    }
+    hipEvent_t take() {
+        if (c->pool.empty()) {
+            hipEvent_t e;
+            (void)hipEventCreate(&e);
+            return e;
+        }
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    ~ProfScope() {
+        if (!c->profiling || !a) return;
+        std::lock_guard<std::mutex> g(c->mu);
+        hipEvent_t b = take();
+        (void)hipEventRecord(b, s);
+        c->pending.push_back(ProfPair{name, a, b});
+    }
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct FramePlan {
+    int nx, ny, ntx, nty;
+    int64_t meshes, tiles, nblocks;
+    size_t bkg_off;  // frame block offset in the background buffer
+    size_t back_raw, rms_raw, back, rms, coef, iters, bkg_bytes;  // relative to block
+    size_t spl_off;  // workspace offset of this frame's spline scratch
+    size_t ycoef_n, lx_n, scr_n;  // doubles
+};
+
+struct Plan {
+    std::vector<FramePlan> fr;
+    int64_t total_meshes = 0, total_tiles = 0, total_blocks = 0, total_ycols = 0, total_xk = 0,
+            total_pieces = 0, total_px = 0;
+    int max_area = 0;
+    size_t bkg_bytes = 0;
+    // workspace sections
+    size_t o_desc = 0, o_detargs = 0, o_counters = 0, o_tiles = 0, o_edges = 0, o_recs = 0, o_parent = 0,
+           o_root = 0, o_label = 0, o_bitmap = 0, o_blockcnt = 0, o_chunks = 0, o_spline = 0, ws_bytes = 0;
+    int64_t rec_cap = 0;
+};
+
+gp_status check_frames(const gp_frame* frames, int32_t nframes) {
+    if (!frames) return fail(GP_ERR_INVALID_ARG, "frames is NULL");
+    if (nframes < 1) return fail(GP_ERR_INVALID_ARG, "nframes must be >= 1 (got %d)", nframes);
+    for (int f = 0; f < nframes; ++f) {
+        const gp_frame& F = frames[f];
+        if (!F.data) return fail(GP_ERR_INVALID_ARG, "frame %d: data is NULL", f);
+        if (F.width < 1 || F.height < 1)
+            return fail(GP_ERR_INVALID_ARG, "frame %d: bad size %dx%d", f, F.width, F.height);
+        if (F.pitch < F.width) return fail(GP_ERR_INVALID_ARG, "frame %d: pitch < width", f);
+        if (F.dtype != GP_U16 && F.dtype != GP_F32)
+            return fail(GP_ERR_INVALID_ARG, "frame %d: unknown dtype %d", f, F.dtype);
+        if ((int64_t)F.width * F.height >= (int64_t)1 << 31)
+            return fail(GP_ERR_UNSUPPORTED, "frame %d: more than 2^31 pixels", f);
+    }
+    return GP_OK;
+}
+
+gp_status check_bkg(const gp_bkg_params* bp) {
+    if (!bp) return fail(GP_ERR_INVALID_ARG, "background parameters are NULL");
+    if (bp->mesh_w < 16 || bp->mesh_h < 16)
+        return fail(GP_ERR_UNSUPPORTED, "mesh %dx%d: meshes must be at least 16 pixels", bp->mesh_w, bp->mesh_h);
+    if ((int64_t)bp->mesh_w * bp->mesh_h > 16384)
+        return fail(GP_ERR_UNSUPPORTED, "mesh %dx%d: at most 16384 pixels per mesh", bp->mesh_w, bp->mesh_h);
+    if (bp->filter_size < 1 || bp->filter_size > 7 || !(bp->filter_size & 1))
+        return fail(GP_ERR_INVALID_ARG, "filter_size must be odd in [1, 7] (got %d)", bp->filter_size);
+    if (!(bp->clip_sigma > 0.f) || !std::isfinite(bp->clip_sigma))
+        return fail(GP_ERR_INVALID_ARG, "clip_sigma must be positive");
+    if (!std::isfinite(bp->crowd_tol) || !std::isfinite(bp->mode_a) || !std::isfinite(bp->mode_b))
+        return fail(GP_ERR_INVALID_ARG, "non-finite background parameter");
+    if (bp->max_iter < 0) return fail(GP_ERR_INVALID_ARG, "max_iter must be >= 0");
+    return GP_OK;
+}
+
+gp_status check_det(const gp_det_params* dp) {
+    if (!dp) return fail(GP_ERR_INVALID_ARG, "detection parameters are NULL");
+    if (!dp->kernel) return fail(GP_ERR_INVALID_ARG, "filter kernel is NULL");
+    if (dp->kw < 1 || dp->kh < 1 || dp->kw > kMaxK || dp->kh > kMaxK || !(dp->kw & 1) || !(dp->kh & 1))
+        return fail(GP_ERR_INVALID_ARG, "kernel must be odd and at most 15 per side (got %dx%d)", dp->kw, dp->kh);
+    for (int i = 0; i < dp->kw * dp->kh; ++i)
+        if (!std::isfinite(dp->kernel[i])) return fail(GP_ERR_INVALID_ARG, "kernel has a non-finite tap");
+    if (!std::isfinite(dp->thresh)) return fail(GP_ERR_INVALID_ARG, "thresh must be finite");
+    if (dp->minarea < 1) return fail(GP_ERR_INVALID_ARG, "minarea must be >= 1");
+    if (dp->connectivity != 4 && dp->connectivity != 8)
+        return fail(GP_ERR_INVALID_ARG, "connectivity must be 4 or 8");
+    if (std::isnan(dp->sat_level)) return fail(GP_ERR_INVALID_ARG, "sat_level is NaN");
+    if (dp->precision != GP_PREC_F32 && dp->precision != GP_PREC_F64)
+        return fail(GP_ERR_INVALID_ARG, "unknown precision %d", dp->precision);
+    return GP_OK;
+}
+
+gp_status check_ap(const gp_ap_params* ap) {
+    if (!ap) return fail(GP_ERR_INVALID_ARG, "aperture parameters are NULL");
+    if (ap->nr < 1 || ap->nr > kMaxRadii) return fail(GP_ERR_INVALID_ARG, "nr must be in [1, 8]");
+    if (!ap->radii) return fail(GP_ERR_INVALID_ARG, "radii is NULL");
+    for (int i = 0; i < ap->nr; ++i)
+        if (!(ap->radii[i] > 0.f) || ap->radii[i] > 64.f)
+            return fail(GP_ERR_INVALID_ARG, "radius %d must be in (0, 64]", i);
+    if (!(ap->r_in >= 0.f) || !(ap->r_out > ap->r_in) || ap->r_out > 64.f)
+        return fail(GP_ERR_INVALID_ARG, "annulus must satisfy 0 <= r_in < r_out <= 64");
+    if (!std::isfinite(ap->gain)) return fail(GP_ERR_INVALID_ARG, "gain must be finite");
+    if (ap->precision != GP_PREC_F32 && ap->precision != GP_PREC_F64)
+        return fail(GP_ERR_INVALID_ARG, "unknown precision %d", ap->precision);
+    return GP_OK;
+}
+
+// background layout (independent of the workspace)
+void plan_bkg(const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp, Plan& P) {
+    P.fr.resize(nframes);
+    size_t off = 0;
+    for (int f = 0; f < nframes; ++f) {
+        FramePlan& F = P.fr[f];
+        const int W = frames[f].width, H = frames[f].height;
+        F.nx = (int)ceil_div(W, bp->mesh_w);
+        F.ny = (int)ceil_div(H, bp->mesh_h);
+        F.meshes = (int64_t)F.nx * F.ny;
+        size_t g = align256(sizeof(double) * F.meshes);
+        F.back_raw = 0;
+        F.rms_raw = g;
+        F.back = 2 * g;
+        F.rms = 3 * g;
+        F.coef = 4 * g;
+        size_t cb = align256(sizeof(double) * 2 * (F.nx + 1) * (F.ny + 1) * 16);
+        F.iters = F.coef + cb;
+        F.bkg_bytes = F.iters + align256(sizeof(int32_t) * F.meshes);
+        F.bkg_off = off;
+        off += F.bkg_bytes;
+        P.total_meshes += F.meshes;
+        P.total_ycols += 2 * F.nx;
+        P.total_xk += F.nx;
+        P.total_pieces += 2 * (int64_t)(F.nx + 1) * (F.ny + 1);
+        const int mw = std::min(bp->mesh_w, W), mh = std::min(bp->mesh_h, H);
+        P.max_area = std::max(P.max_area, mw * mh);
+        F.ntx = (int)ceil_div(W, kTile);
+        F.nty = (int)ceil_div(H, kTile);
+        F.tiles = (int64_t)F.ntx * F.nty;
+        F.nblocks = ceil_div((int64_t)W * H, 1024);
+        P.total_tiles += F.tiles;
+        P.total_blocks += F.nblocks;
+        P.total_px += (int64_t)W * H;
+        F.ycoef_n = (size_t)2 * (F.ny + 1) * F.nx * 4;
+        F.lx_n = (size_t)(F.nx + 1) * 4 * F.nx;
+        F.scr_n = (size_t)8 * F.nx * F.ny + (size_t)5 * F.nx * F.nx;
+    }
+    P.bkg_bytes = off;
+}
+
+// Workspace: fixed sections first (their offsets depend only on the batch),
+// then the component-record arrays, whose capacity is whatever fits.
+void plan_fixed(int32_t nframes, Plan& P) {
+    size_t o = 0;
+    auto sec = [&](size_t bytes) {
+        size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    P.o_desc = sec(sizeof(FrameDesc) * nframes);
+    P.o_detargs = sec(sizeof(DetArgs));
+    P.o_counters = sec(64 * sizeof(uint32_t));
+    P.o_tiles = sec(sizeof(TileInfo) * P.total_tiles);
+    P.o_edges = sec(sizeof(int16_t) * 4 * kTile * P.total_tiles);
+    P.o_bitmap = sec(128 * (size_t)P.total_blocks);
+    P.o_blockcnt = sec(sizeof(uint32_t) * (P.total_blocks + 1));
+    P.o_chunks = sec(sizeof(uint32_t) * (ceil_div(P.total_blocks, 2048) + 1));
+    P.o_spline = o;
+    for (int f = 0; f < nframes; ++f) {
+        FramePlan& F = P.fr[f];
+        F.spl_off = o;
+        o += align256(sizeof(double) * (F.ycoef_n + F.lx_n + F.scr_n));
+    }
+    P.o_recs = o;
+}
+
+size_t rec_bytes(int64_t cap) {
+    return align256(sizeof(CompRec) * cap) + 3 * align256(sizeof(int32_t) * cap);
+}
+
+void plan_recs(int64_t cap, Plan& P) {
+    P.rec_cap = cap;
+    P.o_parent = P.o_recs + align256(sizeof(CompRec) * cap);
+    P.o_root = P.o_parent + align256(sizeof(int32_t) * cap);
+    P.o_label = P.o_root + align256(sizeof(int32_t) * cap);
+    P.ws_bytes = P.o_recs + rec_bytes(cap);
+}
+
+int64_t default_rec_cap(const Plan& P) { return std::max<int64_t>(65536, P.total_px / 64); }
+
+// largest record capacity a workspace of ws_bytes holds (0 if none)
+int64_t cap_for(const Plan& P, size_t ws_bytes) {
+    if (ws_bytes < P.o_recs + rec_bytes(1)) return 0;
+    int64_t lo = 1, hi = ((int64_t)1 << 31) - 1;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo + 1) / 2;
+        if (P.o_recs + rec_bytes(mid) <= ws_bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+gp_status upload_desc(const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp, const Plan& P,
+                      const void* bkg, void* ws, int32_t cat_capacity, int32_t* const* seg, hipStream_t s) {
+    char* W = (char*)ws;
+    char* B = (char*)bkg;
+    FrameDesc* table = (FrameDesc*)(W + P.o_desc);
+    int64_t mesh_base = 0, tile_base = 0, blk_base = 0;
+    DescChunk ch{};
+    for (int f = 0; f < nframes; ++f) {
+        const FramePlan& F = P.fr[f];
+        FrameDesc d{};
+        d.data = frames[f].data;
+        d.pitch = frames[f].pitch;
+        d.W = frames[f].width;
+        d.H = frames[f].height;
+        d.dtype = frames[f].dtype;
+        d.mw = bp->mesh_w;
+        d.mh = bp->mesh_h;
+        d.nx = F.nx;
+        d.ny = F.ny;
+        char* fb = B + F.bkg_off;
+        d.back_raw = (double*)(fb + F.back_raw);
+        d.rms_raw = (double*)(fb + F.rms_raw);
+        d.back = (double*)(fb + F.back);
+        d.rms = (double*)(fb + F.rms);
+        d.coef = (double*)(fb + F.coef);
+        d.iters = (int32_t*)(fb + F.iters);
+        double* sp = (double*)(W + F.spl_off);
+        d.ycoef = sp;
+        d.lx = sp + F.ycoef_n;
+        d.scratch = sp + F.ycoef_n + F.lx_n;
+        d.mesh_base = (int32_t)mesh_base;
+        d.tile_base = (int32_t)tile_base;
+        d.ntx = F.ntx;
+        d.nty = F.nty;
+        d.bitmap = (uint32_t*)(W + P.o_bitmap) + blk_base * 32;
+        d.bm_block_base = (int32_t)blk_base;
+        d.nblocks = (int32_t)F.nblocks;
+        d.cat_base = f * cat_capacity;
+        d.seg = seg ? seg[f] : nullptr;
+        mesh_base += F.meshes;
+        tile_base += F.tiles;
+        blk_base += F.nblocks;
+        if (ch.count == 0) ch.first = f;
+        ch.d[ch.count++] = d;
+        if (ch.count == kDescChunk || f == nframes - 1) {
+            launch_write_desc(ch, table, s);
+            HIP_TRY(hipGetLastError());
+            ch = DescChunk{};
+        }
+    }
+    return GP_OK;
+}
+
+// rank-one test of the filter kernel; on success fills normalised factors
+bool separable_factors(const gp_det_params* dp, double* kx, double* ky) {
+    const int kw = dp->kw, kh = dp->kh;
+    const float* K = dp->kernel;
+    int am = 0, bm = 0;
+    double vmax = 0.0;
+    for (int a = 0; a < kh; ++a)
+        for (int b = 0; b < kw; ++b)
+            if (std::fabs((double)K[a * kw + b]) > vmax) {
+                vmax = std::fabs((double)K[a * kw + b]);
+                am = a;
+                bm = b;
+            }
+    if (vmax == 0.0) return false;
+    std::vector<double> u(kh), v(kw);
+    for (int a = 0; a < kh; ++a) u[a] = K[a * kw + bm];
+    for (int b = 0; b < kw; ++b) v[b] = (double)K[am * kw + b] / (double)K[am * kw + bm];
+    for (int a = 0; a < kh; ++a)
+        for (int b = 0; b < kw; ++b)
+            if (std::fabs((double)K[a * kw + b] - u[a] * v[b]) > 1e-6 * vmax) return false;
+    double su = 0.0, sv = 0.0;
+    for (double x : u) su += x;
+    for (double x : v) sv += x;
+    if (su == 0.0 || sv == 0.0) return false;
+    for (int a = 0; a < kh; ++a) ky[a] = u[a] / su;
+    for (int b = 0; b < kw; ++b) kx[b] = v[b] / sv;
+    return true;
+}
+
+gp_status check_ws(const Plan& P, void* ws, size_t ws_bytes) {
+    if (!ws) return fail(GP_ERR_INVALID_ARG, "workspace is NULL");
+    if (ws_bytes < P.ws_bytes)
+        return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, P.ws_bytes);
+    return GP_OK;
+}
+
+}  // namespace
+
+extern "C" gp_status gp_ctx_create(int device, const char* tune_cache, gp_ctx** out) {
+    if (!out) return fail(GP_ERR_INVALID_ARG, "out is NULL");
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(GP_ERR_INVALID_ARG, "device %d of %d", device, n);
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(GP_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+    gp_ctx* c = new gp_ctx;
+    c->device = device;
+    c->cus = prop.multiProcessorCount;
+    if (tune_cache) c->tune_path = tune_cache;
+    *out = c;
+    return GP_OK;
+}
+
+extern "C" void gp_ctx_destroy(gp_ctx* c) {
+    if (!c) return;
+    for (auto& p : c->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+extern "C" gp_status gp_background_layout(const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
+                                          gp_bkg_layout* layouts, size_t* bytes) {
+    gp_status st;
+    if ((st = check_frames(frames, nframes)) != GP_OK) return st;
+    if ((st = check_bkg(bp)) != GP_OK) return st;
+    Plan P;
+    plan_bkg(frames, nframes, bp, P);
+    if (layouts)
+        for (int f = 0; f < nframes; ++f) {
+            const FramePlan& F = P.fr[f];
+            gp_bkg_layout& L = layouts[f];
+            L.nx = F.nx;
+            L.ny = F.ny;
+            L.back_raw = (int64_t)(F.bkg_off + F.back_raw);
+            L.rms_raw = (int64_t)(F.bkg_off + F.rms_raw);
+            L.back = (int64_t)(F.bkg_off + F.back);
+            L.rms = (int64_t)(F.bkg_off + F.rms);
+            L.coef = (int64_t)(F.bkg_off + F.coef);
+            L.iters = (int64_t)(F.bkg_off + F.iters);
+            L.bytes = (int64_t)F.bkg_bytes;
+        }
+    if (bytes) *bytes = P.bkg_bytes;
+    return GP_OK;
+}
+
+extern "C" gp_status gp_workspace_size(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                                       const gp_bkg_params* bp, const gp_det_params* dp, const gp_ap_params* ap,
+                                       int32_t cat_capacity, int64_t comp_capacity, size_t* bytes) {
+    if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
+    if (!bytes) return fail(GP_ERR_INVALID_ARG, "bytes is NULL");
+    gp_status st;
+    if ((st = check_frames(frames, nframes)) != GP_OK) return st;
+    if ((st = check_bkg(bp)) != GP_OK) return st;
+    if (dp && (st = check_det(dp)) != GP_OK) return st;
+    if (ap && (st = check_ap(ap)) != GP_OK) return st;
+    if (cat_capacity < 0) return fail(GP_ERR_INVALID_ARG, "cat_capacity < 0");
+    if (comp_capacity < 0 || comp_capacity >= ((int64_t)1 << 31))
+        return fail(GP_ERR_INVALID_ARG, "comp_capacity out of range");
+    Plan P;
+    plan_bkg(frames, nframes, bp, P);
+    plan_fixed(nframes, P);
+    plan_recs(comp_capacity > 0 ? comp_capacity : default_rec_cap(P), P);
+    *bytes = P.ws_bytes;
+    return GP_OK;
+}
+
+extern "C" gp_status gp_background(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
+                                   void* bkg, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
+    gp_status st;
+    if ((st = check_frames(frames, nframes)) != GP_OK) return st;
+    if ((st = check_bkg(bp)) != GP_OK) return st;
+    if (!bkg) return fail(GP_ERR_INVALID_ARG, "background buffer is NULL");
+    Plan P;
+    plan_bkg(frames, nframes, bp, P);
+    plan_fixed(nframes, P);
+    P.ws_bytes = P.o_recs;  // the record arrays are not used here
+    if ((st = check_ws(P, ws, ws_bytes)) != GP_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((st = upload_desc(frames, nframes, bp, P, bkg, ws, 0, nullptr, s)) != GP_OK) return st;
+    const FrameDesc* desc = (const FrameDesc*)((char*)ws + P.o_desc);
+    if (!(bp->flags & GP_BKG_GRID_GIVEN)) {
+        BkgArgs a{bp->clip_sigma, bp->crowd_tol, bp->mode_a, bp->mode_b, bp->max_iter, bp->filter_size};
+        {
+            ProfScope ps(ctx, s, "mesh_stats");
+            launch_mesh_stats(desc, nframes, (int)P.total_meshes, P.max_area, a, s);
+        }
+        HIP_TRY(hipGetLastError());
+        {
+            ProfScope ps(ctx, s, "grid_filter");
+            launch_grid_filter(desc, nframes, (int)P.total_meshes, bp->filter_size, s);
+        }
+        HIP_TRY(hipGetLastError());
+    }
+    {
+        ProfScope ps(ctx, s, "spline");
+        launch_spline(desc, nframes, (int)P.total_ycols, (int)P.total_xk, (int)P.total_pieces, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return GP_OK;
+}
+
+extern "C" gp_status gp_background_map(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                                       const gp_bkg_params* bp, const void* bkg, int32_t index, int32_t precision,
+                                       double* back_map, double* rms_map, void* stream) {
+    if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
+    gp_status st;
+    if ((st = check_frames(frames, nframes)) != GP_OK) return st;
+    if ((st = check_bkg(bp)) != GP_OK) return st;
+    if (!bkg) return fail(GP_ERR_INVALID_ARG, "background buffer is NULL");
+    if (index < 0 || index >= nframes) return fail(GP_ERR_INVALID_ARG, "frame index %d of %d", index, nframes);
+    if (precision != GP_PREC_F32 && precision != GP_PREC_F64)
+        return fail(GP_ERR_INVALID_ARG, "unknown precision %d", precision);
+    if (!back_map && !rms_map) return GP_OK;
+    Plan P;
+    plan_bkg(frames, nframes, bp, P);
+    const FramePlan& F = P.fr[index];
+    FrameDesc d{};
+    d.data = frames[index].data;
+    d.pitch = frames[index].pitch;
+    d.W = frames[index].width;
+    d.H = frames[index].height;
+    d.dtype = frames[index].dtype;
+    d.mw = bp->mesh_w;
+    d.mh = bp->mesh_h;
+    d.nx = F.nx;
+    d.ny = F.ny;
+    d.coef = (double*)((char*)bkg + F.bkg_off + F.coef);
+    HIP_TRY(hipSetDevice(ctx->device));
+    launch_bkg_map(d, back_map, rms_map, precision == GP_PREC_F64, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return GP_OK;
+}
+
+static gp_status check_cat(const gp_catalog* cat, bool need_moments) {
+    if (!cat) return fail(GP_ERR_INVALID_ARG, "catalogue is NULL");
+    if (cat->capacity < 0) return fail(GP_ERR_INVALID_ARG, "catalogue capacity < 0");
+    if (!cat->n_obj || !cat->status) return fail(GP_ERR_INVALID_ARG, "catalogue n_obj/status is NULL");
+    if (!cat->x || !cat->y || !cat->flags) return fail(GP_ERR_INVALID_ARG, "catalogue x/y/flags is NULL");
+    if (need_moments && (!cat->npix || !cat->xmin || !cat->xmax || !cat->ymin || !cat->ymax || !cat->pmin ||
+                         !cat->flux || !cat->x2 || !cat->y2 || !cat->xy || !cat->peak))
+        return fail(GP_ERR_INVALID_ARG, "a catalogue column is NULL");
+    return GP_OK;
+}
+
+extern "C" gp_status gp_detect(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
+                               const void* bkg, const gp_det_params* dp, gp_catalog* cat, int32_t* const* seg,
+                               int32_t* comp_status, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
+    gp_status st;
+    if ((st = check_frames(frames, nframes)) != GP_OK) return st;
+    if ((st = check_bkg(bp)) != GP_OK) return st;
+    if ((st = check_det(dp)) != GP_OK) return st;
+    if ((st = check_cat(cat, true)) != GP_OK) return st;
+    if (!bkg) return fail(GP_ERR_INVALID_ARG, "background buffer is NULL");
+    Plan P;
+    plan_bkg(frames, nframes, bp, P);
+    plan_fixed(nframes, P);
+    plan_recs(1, P);
+    if ((st = check_ws(P, ws, ws_bytes)) != GP_OK) return st;
+    plan_recs(cap_for(P, ws_bytes), P);
+    if (P.total_tiles >= ((int64_t)1 << 31)) return fail(GP_ERR_UNSUPPORTED, "too many tiles in one batch");
+    if (ceil_div(P.total_blocks, 2048) > 8192) return fail(GP_ERR_UNSUPPORTED, "batch too large for one call");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((st = upload_desc(frames, nframes, bp, P, bkg, ws, cat->capacity, seg, s)) != GP_OK) return st;
+    char* W = (char*)ws;
+    // filter arguments
+    DetArgsIn in{};
+    in.kw = dp->kw;
+    in.kh = dp->kh;
+    in.conn = dp->connectivity;
+    in.thresh = dp->thresh;
+    in.sat = dp->sat_level;
+    in.minarea = dp->minarea;
+    in.want_seg = seg ? 1 : 0;
+    for (int i = 0; i < dp->kw * dp->kh; ++i) in.kraw[i] = dp->kernel[i];
+    double kx[kMaxK] = {0}, ky[kMaxK] = {0};
+    in.separable = separable_factors(dp, kx, ky) ? 1 : 0;
+    for (int i = 0; i < kMaxK; ++i) {
+        in.kx[i] = (float)kx[i];
+        in.ky[i] = (float)ky[i];
+        in.kxd[i] = kx[i];
+        in.kyd[i] = ky[i];
+    }
+    DetArgs* dargs = (DetArgs*)(W + P.o_detargs);
+    launch_write_detargs(in, dargs, s);
+    HIP_TRY(hipGetLastError());
+    DetWork wk{};
+    wk.desc = (FrameDesc*)(W + P.o_desc);
+    wk.nframes = nframes;
+    wk.total_tiles = (int32_t)P.total_tiles;
+    wk.counters = (uint32_t*)(W + P.o_counters);
+    wk.tiles = (TileInfo*)(W + P.o_tiles);
+    wk.edges = (int16_t*)(W + P.o_edges);
+    wk.recs = (CompRec*)(W + P.o_recs);
+    wk.parent = (int32_t*)(W + P.o_parent);
+    wk.root = (int32_t*)(W + P.o_root);
+    wk.label = (int32_t*)(W + P.o_label);
+    wk.blockcnt = (uint32_t*)(W + P.o_blockcnt);
+    wk.chunksum = (uint32_t*)(W + P.o_chunks);
+    wk.bitmap = (uint32_t*)(W + P.o_bitmap);
+    wk.rec_cap = (int32_t)P.rec_cap;
+    wk.total_blocks = (int32_t)P.total_blocks;
+    {
+        ProfScope ps(ctx, s, "clear");
+        launch_fill_u32(wk.counters, 64, 0u, s);
+        launch_fill_u32(wk.bitmap, (size_t)P.total_blocks * 32, 0u, s);
+    }
+    const bool f64 = dp->precision == GP_PREC_F64;
+    {
+        ProfScope ps(ctx, s, "detect_tiles");
+        launch_detect_tiles(wk, dargs, f64, s);
+    }
+    HIP_TRY(hipGetLastError());
+    const int persist = ctx->cus * 4;
+    {
+        ProfScope ps(ctx, s, "merge");
+        launch_merge(wk, dp->connectivity, dp->minarea, persist, s);
+    }
+    HIP_TRY(hipGetLastError());
+    CatOut co{cat->capacity, cat->n_obj, cat->status, cat->npix, cat->xmin, cat->xmax, cat->ymin, cat->ymax,
+              cat->pmin, cat->flux, cat->x, cat->y, cat->x2, cat->y2, cat->xy, cat->peak, cat->flags};
+    {
+        ProfScope ps(ctx, s, "catalog");
+        launch_catalog(wk, co, dp->minarea, persist, comp_status, s);
+    }
+    HIP_TRY(hipGetLastError());
+    if (seg) {
+        ProfScope ps(ctx, s, "seg");
+        for (int f = 0; f < nframes; ++f)
+            if (seg[f]) launch_seg(wk, f, (int64_t)frames[f].width * frames[f].height, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return GP_OK;
+}
+
+extern "C" gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
+                                 const void* bkg, const gp_catalog* cat, const gp_ap_params* ap, gp_phot* out,
+                                 void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
+    gp_status st;
+    if ((st = check_frames(frames, nframes)) != GP_OK) return st;
+    if ((st = check_bkg(bp)) != GP_OK) return st;
+    if ((st = check_ap(ap)) != GP_OK) return st;
+    if ((st = check_cat(cat, false)) != GP_OK) return st;
+    if (!out || !out->flux || !out->area || !out->bkg) return fail(GP_ERR_INVALID_ARG, "photometry output is NULL");
+    if (ap->want_err && !out->fluxerr) return fail(GP_ERR_INVALID_ARG, "fluxerr is NULL with want_err");
+    if (!bkg) return fail(GP_ERR_INVALID_ARG, "background buffer is NULL");
+    Plan P;
+    plan_bkg(frames, nframes, bp, P);
+    plan_fixed(nframes, P);
+    P.ws_bytes = P.o_recs;
+    if ((st = check_ws(P, ws, ws_bytes)) != GP_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    // only the descriptor table is needed; it sits at the start of the workspace
+    if ((st = upload_desc(frames, nframes, bp, P, bkg, ws, cat->capacity, nullptr, s)) != GP_OK) return st;
+    ApArgs a{};
+    a.nr = ap->nr;
+    a.want_err = ap->want_err ? 1 : 0;
+    a.capacity = cat->capacity;
+    a.nframes = nframes;
+    float rmax = ap->r_out;
+    for (int i = 0; i < ap->nr; ++i) {
+        a.radii[i] = ap->radii[i];
+        rmax = std::max(rmax, ap->radii[i]);
+    }
+    a.r_in = ap->r_in;
+    a.r_out = ap->r_out;
+    a.gain = ap->gain;
+    a.rmax = rmax;
+    ApCat c{cat->n_obj, cat->x, cat->y, cat->flags, out->flux, out->area, out->bkg, out->fluxerr};
+    const int total_rows = nframes * cat->capacity;
+    const int blocks = std::max(1, std::min(ctx->cus * 8, (total_rows + 3) / 4));
+    {
+        ProfScope ps(ctx, s, "aperture");
+        launch_aperture((const FrameDesc*)((char*)ws + P.o_desc), a, c, total_rows, blocks,
+                        ap->precision == GP_PREC_F64, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return GP_OK;
+}
+
+extern "C" gp_status gp_profile_enable(gp_ctx* ctx, int on) {
+    if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
+    ctx->profiling = on != 0;
+    return GP_OK;
+}
+
+static gp_status drain(gp_ctx* ctx) {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    for (auto& p : ctx->pending) {
+        HIP_TRY(hipEventSynchronize(p.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p.a, p.b));
+        auto& t = ctx->totals[p.name];
+        t.first += ms;
+        t.second += 1;
+        ctx->pool.push_back(p.a);
+        ctx->pool.push_back(p.b);
+    }
+    ctx->pending.clear();
+    return GP_OK;
+}
+
+extern "C" gp_status gp_profile_read(gp_ctx* ctx, const char* name, double* total_ms, int64_t* count) {
+    if (!ctx || !name) return fail(GP_ERR_INVALID_ARG, "NULL argument");
+    gp_status st = drain(ctx);
+    if (st != GP_OK) return st;
+    auto it = ctx->totals.find(name);
+    if (total_ms) *total_ms = it == ctx->totals.end() ? 0.0 : it->second.first;
+    if (count) *count = it == ctx->totals.end() ? 0 : it->second.second;
+    return GP_OK;
+}
+
+extern "C" gp_status gp_profile_reset(gp_ctx* ctx) {
+    if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
+    gp_status st = drain(ctx);
+    ctx->totals.clear();
+    return st;
+}

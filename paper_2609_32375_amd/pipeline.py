@@ -1,0 +1,243 @@
+"""Device buffers and call sequencing around the C ABI (torch for memory/streams).
+
+`Photometry` owns, for a fixed batch geometry, the background buffer, the
+workspace, the catalogue and photometry columns (all torch tensors on the
+GPU) and enqueues gp_background -> gp_detect -> gp_aperture on a stream.
+Nothing here computes any part of the method; it sizes, allocates, fills the
+gp_* structs and copies results back.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class PhotParams:
+    mesh_w: int = 64
+    mesh_h: int = 64
+    mesh_filter: int = 3
+    clip_sigma: float = 3.0
+    crowd_tol: float = 0.2
+    mode_a: float = 2.5
+    mode_b: float = 1.5
+    max_iter: int = 100
+    thresh: float = 1.5
+    minarea: int = 5
+    conn: int = 8
+    radii: Sequence[float] = (3.0, 6.0)
+    r_in: float = 10.0
+    r_out: float = 15.0
+    sat_level: float = math.inf
+    gain: float = 0.0
+    want_err: bool = True
+
+    @classmethod
+    def of(cls, obj) -> "PhotParams":
+        """Copy the fields from any object that has them (e.g. a workload spec)."""
+        kw = {k: getattr(obj, k) for k in cls.__dataclass_fields__ if hasattr(obj, k)}
+        return cls(**kw)
+
+
+CAT_INT = ("npix", "xmin", "xmax", "ymin", "ymax")
+CAT_F64 = ("flux", "x", "y", "x2", "y2", "xy")
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.uint16:
+        return L.GP_U16
+    if t.dtype == torch.float32:
+        return L.GP_F32
+    raise TypeError(f"frames must be uint16 or float32 (got {t.dtype})")
+
+
+def make_frame(t: torch.Tensor) -> L.gp_frame:
+    if not t.is_cuda:
+        raise ValueError("frames must be device tensors")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("frames must be 2-D with unit column stride")
+    return L.gp_frame(t.data_ptr(), t.shape[1], t.shape[0], t.stride(0), _dtype_code(t))
+
+
+class Photometry:
+    """One batch geometry: shapes, dtypes and parameters fixed at construction."""
+
+    def __init__(self, frames: Sequence[torch.Tensor], params, kernel: np.ndarray, capacity: int,
+                 comp_capacity: int = 0, precision: int = L.GP_PREC_F32, device: int = 0,
+                 seg: bool = False, ctx=None):
+        self.p = PhotParams.of(params)
+        self.device = torch.device("cuda", device)
+        self.ctx = ctx if ctx is not None else L.gp_ctx_create(device)
+        self._own_ctx = ctx is None
+        self.frames_t = list(frames)
+        self.frames = [make_frame(t) for t in self.frames_t]
+        self.n = len(self.frames)
+        self.capacity = int(capacity)
+        self.kernel = np.ascontiguousarray(kernel, dtype=np.float32)
+        self.radii = np.ascontiguousarray(list(self.p.radii), dtype=np.float32)
+        p = self.p
+        self.bp = L.gp_bkg_params(p.mesh_w, p.mesh_h, p.mesh_filter, p.clip_sigma, p.crowd_tol, p.mode_a,
+                                  p.mode_b, p.max_iter, 0)
+        kh, kw = self.kernel.shape
+        self.dp = L.gp_det_params(self.kernel.ctypes.data_as(C.POINTER(C.c_float)), kw, kh, p.thresh,
+                                  p.minarea, p.conn, p.sat_level, precision)
+        self.ap = L.gp_ap_params(self.radii.ctypes.data_as(C.POINTER(C.c_float)), len(self.radii), p.r_in,
+                                 p.r_out, p.gain, 1 if p.want_err else 0, precision)
+        self.layouts, bkg_bytes = L.gp_background_layout(self.frames, self.bp)
+        self.ws_bytes = L.gp_workspace_size(self.ctx, self.frames, self.bp, self.dp, self.ap, self.capacity,
+                                            comp_capacity)
+        dev = self.device
+        self.bkg = torch.zeros(max(bkg_bytes, 256), dtype=torch.uint8, device=dev)
+        self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=dev)
+        rows = max(self.n * self.capacity, 1)
+        nr = len(self.radii)
+        self.cat = {k: torch.zeros(rows, dtype=torch.int32, device=dev) for k in CAT_INT}
+        self.cat.update({k: torch.zeros(rows, dtype=torch.float64, device=dev) for k in CAT_F64})
+        self.cat["pmin"] = torch.zeros(rows, dtype=torch.int64, device=dev)
+        self.cat["peak"] = torch.zeros(rows, dtype=torch.float32, device=dev)
+        self.cat["flags"] = torch.zeros(rows, dtype=torch.int32, device=dev)
+        self.n_obj = torch.zeros(self.n, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(self.n, dtype=torch.int32, device=dev)
+        self.comp_status = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.phot = {"flux": torch.zeros(rows, nr, dtype=torch.float64, device=dev),
+                     "area": torch.zeros(rows, nr, dtype=torch.float64, device=dev),
+                     "fluxerr": torch.zeros(rows, nr, dtype=torch.float64, device=dev),
+                     "bkg": torch.zeros(rows, dtype=torch.float64, device=dev)}
+        c = self.cat
+        self.gcat = L.gp_catalog(self.capacity, self.n_obj.data_ptr(), self.status.data_ptr(),
+                                 *[c[k].data_ptr() for k in CAT_INT], c["pmin"].data_ptr(),
+                                 *[c[k].data_ptr() for k in CAT_F64], c["peak"].data_ptr(),
+                                 c["flags"].data_ptr())
+        ph = self.phot
+        self.gphot = L.gp_phot(ph["flux"].data_ptr(), ph["area"].data_ptr(), ph["bkg"].data_ptr(),
+                               ph["fluxerr"].data_ptr())
+        self.seg = None
+        if seg:
+            self.seg = [torch.zeros(t.shape[0], t.shape[1], dtype=torch.int32, device=dev) for t in self.frames_t]
+
+    def close(self):
+        if self._own_ctx and self.ctx:
+            L.gp_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def rebind(self, frames: Sequence[torch.Tensor]):
+        """Point the batch at other frames of the same shapes and dtypes."""
+        if len(frames) != self.n:
+            raise ValueError("rebind needs the same number of frames")
+        new = [make_frame(t) for t in frames]
+        for a, b in zip(new, self.frames):
+            if (a.width, a.height, a.dtype) != (b.width, b.height, b.dtype):
+                raise ValueError("rebind needs the same shapes and dtypes")
+        self.frames_t = list(frames)
+        self.frames = new
+
+    def stream_ptr(self, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return C.c_void_p(s.cuda_stream)
+
+    def background(self, stream=None, grid_given: bool = False):
+        bp = L.gp_bkg_params.from_buffer_copy(self.bp)
+        if grid_given:
+            bp.flags |= L.GP_BKG_GRID_GIVEN
+        L.gp_background(self.ctx, self.frames, bp, C.c_void_p(self.bkg.data_ptr()),
+                        C.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.stream_ptr(stream))
+
+    def detect(self, stream=None):
+        seg = [s.data_ptr() for s in self.seg] if self.seg is not None else None
+        L.gp_detect(self.ctx, self.frames, self.bp, C.c_void_p(self.bkg.data_ptr()), self.dp, self.gcat, seg,
+                    C.c_void_p(self.comp_status.data_ptr()), C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                    self.stream_ptr(stream))
+
+    def aperture(self, stream=None):
+        L.gp_aperture(self.ctx, self.frames, self.bp, C.c_void_p(self.bkg.data_ptr()), self.gcat, self.ap,
+                      self.gphot, C.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.stream_ptr(stream))
+
+    def run(self, stream=None):
+        self.background(stream)
+        self.detect(stream)
+        self.aperture(stream)
+
+    # ------------------------------------------------------------------
+    # host-side inspection (tests, bench)
+    def grids(self, f: int):
+        lay = self.layouts[f]
+        ny, nx = lay.ny, lay.nx
+        raw = self.bkg
+
+        def view(off, n, dt):
+            return raw[off: off + n * np.dtype(dt).itemsize].view(
+                {np.float64: torch.float64, np.int32: torch.int32}[dt]).cpu().numpy()
+        out = {k: view(getattr(lay, k), nx * ny, np.float64).reshape(ny, nx)
+               for k in ("back_raw", "rms_raw", "back", "rms")}
+        out["iters"] = view(lay.iters, nx * ny, np.int32).reshape(ny, nx)
+        out["coef"] = view(lay.coef, 2 * (ny + 1) * (nx + 1) * 16, np.float64).reshape(2, ny + 1, nx + 1, 16)
+        return out
+
+    def maps(self, f: int, precision: int = L.GP_PREC_F32):
+        """Per-pixel background and noise maps of frame f (float64, synchronises)."""
+        t = self.frames_t[f]
+        H, W = t.shape
+        B = torch.empty(H, W, dtype=torch.float64, device=self.device)
+        R = torch.empty(H, W, dtype=torch.float64, device=self.device)
+        L.gp_background_map(self.ctx, self.frames, self.bp, C.c_void_p(self.bkg.data_ptr()), f, precision,
+                            C.c_void_p(B.data_ptr()), C.c_void_p(R.data_ptr()), self.stream_ptr())
+        torch.cuda.synchronize(self.device)
+        return B.cpu().numpy(), R.cpu().numpy()
+
+    def set_grids(self, f: int, back: np.ndarray, rms: np.ndarray):
+        """Write the background/rms grids of frame f (used with grid_given)."""
+        lay = self.layouts[f]
+        for off, g in ((lay.back, back), (lay.rms, rms)):
+            a = torch.from_numpy(np.ascontiguousarray(g, dtype=np.float64).ravel())
+            self.bkg[off: off + a.numel() * 8].copy_(a.view(torch.uint8))
+
+    def set_catalog(self, f: int, x: np.ndarray, y: np.ndarray, flags: Optional[np.ndarray] = None):
+        """Write object centres of frame f (used to run the aperture stage alone)."""
+        n = len(x)
+        if n > self.capacity:
+            raise ValueError("more objects than capacity")
+        base = f * self.capacity
+        self.cat["x"][base: base + n] = torch.as_tensor(np.asarray(x, np.float64), device=self.device)
+        self.cat["y"][base: base + n] = torch.as_tensor(np.asarray(y, np.float64), device=self.device)
+        fl = np.zeros(n, np.int32) if flags is None else np.asarray(flags, np.int32)
+        self.cat["flags"][base: base + n] = torch.as_tensor(fl, device=self.device)
+        self.n_obj[f] = n
+        self.status[f] = 0
+
+    def results(self, f: int = 0):
+        """Catalogue and photometry of frame f as numpy arrays (synchronises)."""
+        torch.cuda.synchronize(self.device)
+        n = int(self.n_obj[f].item())
+        st = int(self.status[f].item())
+        k = min(n, self.capacity)
+        base = f * self.capacity
+        cat = {name: t[base: base + k].cpu().numpy() for name, t in self.cat.items()}
+        cat["flags"] = cat["flags"].astype(np.uint32)
+        phot = {name: t[base: base + k].cpu().numpy() for name, t in self.phot.items()}
+        return dict(n_obj=n, status=st, cat=cat, phot=phot,
+                    comp_status=self.comp_status.cpu().numpy().tolist(),
+                    seg=self.seg[f].cpu().numpy() if self.seg is not None else None)
+
+
+def run_plain(frame: torch.Tensor, params, kernel: np.ndarray, capacity: int, **kw):
+    """One frame through background -> detect -> aperture; returns the results."""
+    ph = Photometry([frame], params, kernel, capacity, **kw)
+    ph.run()
+    out = ph.results(0)
+    out["grids"] = ph.grids(0)
+    ph.close()
+    return out

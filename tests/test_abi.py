@@ -1,0 +1,80 @@
+"""The C ABI library loads and exports every declared entry point (CPU only)."""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+from tests._util import ROOT, header_functions
+
+
+def test_header_declares_the_three_calls():
+    fns = header_functions()
+    for f in ("gp_background", "gp_detect", "gp_aperture", "gp_ctx_create", "gp_workspace_size",
+              "gp_last_error", "gp_background_layout", "gp_background_map"):
+        assert f in fns
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2609_32375_amd import _lib as L
+    lib = L.load()
+    for f in header_functions():
+        assert hasattr(lib, f), f
+    assert set(L.EXPORTS) == set(header_functions())
+    assert L.gp_version().startswith("gpphot")
+
+
+def _frame(w, h, dtype=2):
+    from paper_2609_32375_amd import _lib as L
+    return L.gp_frame(1, w, h, w, dtype)   # non-null dummy pointer: never dereferenced here
+
+
+def test_layout_and_validation_errors_are_synchronous():
+    from paper_2609_32375_amd import _lib as L
+    bp = L.gp_bkg_params(64, 64, 3, 3.0, 0.2, 2.5, 1.5, 100, 0)
+    lay, size = L.gp_background_layout([_frame(300, 200)], bp)
+    assert (lay[0].nx, lay[0].ny) == (5, 4)
+    assert size >= lay[0].bytes > 0
+    assert all(getattr(lay[0], k) % 256 == 0 for k in ("back_raw", "rms_raw", "back", "rms", "coef", "iters"))
+    # batch: blocks are consecutive
+    lay2, size2 = L.gp_background_layout([_frame(300, 200), _frame(17, 5, 1)], bp)
+    assert lay2[1].back_raw >= lay2[0].bytes and (lay2[1].nx, lay2[1].ny) == (1, 1)
+    bad = [
+        (L.gp_bkg_params(8, 64, 3, 3.0, 0.2, 2.5, 1.5, 100, 0), L.GP_ERR_UNSUPPORTED),
+        (L.gp_bkg_params(256, 256, 3, 3.0, 0.2, 2.5, 1.5, 100, 0), L.GP_ERR_UNSUPPORTED),
+        (L.gp_bkg_params(64, 64, 2, 3.0, 0.2, 2.5, 1.5, 100, 0), L.GP_ERR_INVALID_ARG),
+        (L.gp_bkg_params(64, 64, 3, -1.0, 0.2, 2.5, 1.5, 100, 0), L.GP_ERR_INVALID_ARG),
+        (L.gp_bkg_params(64, 64, 3, 3.0, 0.2, 2.5, 1.5, -1, 0), L.GP_ERR_INVALID_ARG),
+    ]
+    for b, code in bad:
+        with pytest.raises(L.GpError) as e:
+            L.gp_background_layout([_frame(300, 200)], b)
+        assert e.value.status == code
+        assert L.load().gp_last_error().decode()
+    with pytest.raises(L.GpError) as e:
+        L.gp_background_layout([L.gp_frame(0, 10, 10, 10, 2)], bp)
+    assert e.value.status == L.GP_ERR_INVALID_ARG
+    with pytest.raises(L.GpError):
+        L.gp_background_layout([L.gp_frame(1, 10, 10, 5, 2)], bp)     # pitch < width
+    with pytest.raises(L.GpError):
+        L.gp_background_layout([L.gp_frame(1, 10, 10, 10, 7)], bp)    # dtype
+
+
+def test_null_context_is_rejected():
+    from paper_2609_32375_amd import _lib as L
+    lib = L.load()
+    bp = L.gp_bkg_params(64, 64, 3, 3.0, 0.2, 2.5, 1.5, 100, 0)
+    fr = (L.gp_frame * 1)(_frame(100, 100))
+    size = C.c_size_t()
+    assert lib.gp_workspace_size(None, fr, 1, C.byref(bp), None, None, 10, 0, C.byref(size)) == L.GP_ERR_INVALID_ARG
+    assert lib.gp_background(None, fr, 1, C.byref(bp), None, None, 0, None) == L.GP_ERR_INVALID_ARG
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2609_32375_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, fn
+                assert "gp_oracle" not in txt, fn

@@ -1,0 +1,418 @@
+"""GPU path vs the FP64 oracle, through the C ABI (needs an MI355X).
+
+Stage-isolated checks feed each GPU stage the oracle's upstream output, so a
+difference is attributable to that stage; decisions whose margins fall below
+FP32 rounding (mesh clip / estimator tests, threshold tests) are excluded and
+counted, everything else must match to the stated tolerances, labels bit for
+bit.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import Params, gaussian_kernel, make_frame
+from tests._util import (AMBIG_T, TOL_BKG_REL, cmp_catalog, cmp_phot, f32_params, mesh_ambiguous,
+                         phot_condition, thresh_ambiguous)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2609_32375_amd import pipeline
+    return pipeline
+
+
+def _dev(img):
+    return torch.from_numpy(np.ascontiguousarray(img)).cuda()
+
+
+def _params(name="c1", **kw):
+    from synth import config_params
+    p = config_params(name)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return f32_params(p)
+
+
+# ----------------------------------------------------------------------------
+# mesh statistics and the background interpolation
+# ----------------------------------------------------------------------------
+MESH_CASES = [
+    ("c1", 300, 200, "f32", 64, 64, 0),
+    ("c1", 257, 131, "u16", 64, 64, 1),
+    ("c2", 390, 270, "f32", 128, 128, 2),
+    ("c1", 200, 150, "f32", 17, 23, 3),
+    ("c1", 40, 30, "f32", 64, 64, 4),        # frame smaller than one mesh
+]
+
+
+@pytest.mark.parametrize("case", MESH_CASES, ids=lambda c: f"{c[0]}-{c[1]}x{c[2]}-{c[3]}-m{c[4]}x{c[5]}")
+def test_mesh_statistics_match_oracle(P, case):
+    name, W, H, dt, mw, mh, seed = case
+    _say("mesh case", case)
+    fr = make_frame(name, seed=100 + seed, W=W, H=H, dtype=dt)
+    p = _params(name, mesh_w=mw, mesh_h=mh)
+    img = fr.image
+    ph = P.Photometry([_dev(img)], p, p.kernel(), capacity=64)
+    ph.background()
+    g = ph.grids(0)
+    st = oracle.mesh_stats(img.astype(np.float64), mw, mh, p.clip_sigma, p.crowd_tol, p.mode_a, p.mode_b, p.max_iter)
+    amb = mesh_ambiguous(st)
+    ok = ~amb
+    _say("meshes", st["back"].size, "ambiguous", int(amb.sum()))
+    assert amb.sum() <= max(1, st["back"].size // 20)
+    rel_b = np.abs(g["back_raw"] - st["back"]) / np.abs(st["back"])
+    rel_r = np.abs(g["rms_raw"] - st["rms"]) / np.maximum(np.abs(st["rms"]), 1e-30)
+    _say("max rel back", rel_b[ok].max(), "rms", rel_r[ok].max())
+    assert np.all(rel_b[ok] <= TOL_BKG_REL) and np.all(rel_r[ok] <= TOL_BKG_REL)
+    # identical clipping decisions: same number of passes
+    np.testing.assert_array_equal(g["iters"][ok], st["iters"][ok].astype(np.int32))
+    # the grid filter is exact given the same raw grid
+    np.testing.assert_array_equal(g["back"], oracle.median_filter(g["back_raw"], p.mesh_filter))
+    np.testing.assert_array_equal(g["rms"], oracle.median_filter(g["rms_raw"], p.mesh_filter))
+    ph.close()
+
+
+@pytest.mark.parametrize("shape", [(300, 200, 64, 64), (130, 77, 32, 16), (50, 20, 64, 64), (1000, 40, 128, 16)])
+def test_background_maps_match_oracle_spline(P, shape):
+    W, H, mw, mh = shape
+    _say("map case", shape)
+    rng = np.random.default_rng(W + H)
+    nx, ny = -(-W // mw), -(-H // mh)
+    back = 1000 + 30 * rng.standard_normal((ny, nx))
+    rms = 20 + 3 * rng.random((ny, nx))
+    img = np.zeros((H, W), np.float32)
+    p = _params("c1", mesh_w=mw, mesh_h=mh)
+    ph = P.Photometry([_dev(img)], p, p.kernel(), capacity=16)
+    ph.set_grids(0, back, rms)
+    ph.background(grid_given=True)
+    B, R = ph.maps(0)
+    Bo = oracle.grid_map(back, W, H, mw, mh)
+    Ro = oracle.grid_map(rms, W, H, mw, mh)
+    eb = np.abs(B - Bo).max()
+    er = (np.abs(R - Ro) / np.abs(Ro)).max()
+    _say("max |dB|", eb, "max rel dR", er)
+    assert eb <= 1e-5                      # ADU, far inside 1e-5 relative
+    assert er <= TOL_BKG_REL
+    B64, R64 = ph.maps(0, precision=1)
+    assert np.abs(B64 - Bo).max() <= 1e-9 and (np.abs(R64 - Ro) / Ro).max() <= 1e-12
+    ph.close()
+
+
+def test_constant_sky_gives_constant_background(P):
+    img = np.full((150, 220), 812.5, np.float32)
+    p = _params("c1", mesh_w=32, mesh_h=32)
+    ph = P.Photometry([_dev(img)], p, p.kernel(), capacity=16)
+    ph.background()
+    ph.detect()
+    B, R = ph.maps(0)
+    assert np.all(B == 812.5) and np.all(R == 0.0)
+    r = ph.results(0)
+    assert r["n_obj"] == 0 and r["status"] == 0
+    ph.close()
+
+
+# ----------------------------------------------------------------------------
+# labelling: a given mask through constant sky, zero rms and a delta kernel
+# ----------------------------------------------------------------------------
+def _mask_cases():
+    rng = np.random.default_rng(0)
+    cases = []
+    for d in (0.02, 0.3, 0.55, 0.9):
+        cases.append((f"rand{d}", rng.random((150, 200)) < d))
+    full = np.ones((130, 129), bool)
+    cases.append(("full", full))
+    cases.append(("empty", np.zeros((70, 70), bool)))
+    checker = (np.add.outer(np.arange(100), np.arange(140)) % 2).astype(bool)
+    cases.append(("checker", checker))
+    snake = np.zeros((140, 200), bool)
+    for r in range(0, 140, 2):
+        snake[r, :] = True
+        if r + 1 < 140:
+            snake[r + 1, 199 if (r // 2) % 2 == 0 else 0] = True
+    cases.append(("snake", snake))
+    # diagonal chains across tile corners
+    diag = np.zeros((200, 200), bool)
+    for i in range(200):
+        diag[i, i] = True
+        diag[i, 199 - i] = True
+    cases.append(("diag", diag))
+    tiny = rng.random((3, 5)) < 0.5
+    cases.append(("tiny", tiny))
+    one = np.ones((1, 1), bool)
+    cases.append(("one", one))
+    return cases
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+@pytest.mark.parametrize("case", _mask_cases(), ids=lambda c: c[0])
+def test_labels_bit_exact_for_given_mask(P, case, conn):
+    name, mask = case
+    _say("mask case", name, conn)
+    H, W = mask.shape
+    c, A = 500.0, 100.0
+    rng = np.random.default_rng(H * W)
+    amp = A + 50.0 * rng.random(mask.shape)
+    img = (c + np.where(mask, amp, 0.0)).astype(np.float32)
+    minarea = 3
+    p = _params("c1", mesh_w=16, mesh_h=16, conn=conn, minarea=minarea, thresh=1.5)
+    K = np.zeros((3, 3), np.float32)
+    K[1, 1] = 1.0
+    nx, ny = -(-W // 16), -(-H // 16)
+    ph = P.Photometry([_dev(img)], p, K, capacity=max(8, W * H), seg=True)
+    ph.set_grids(0, np.full((ny, nx), c), np.zeros((ny, nx)))
+    ph.background(grid_given=True)
+    ph.detect()
+    r = ph.results(0)
+    seg_o, n_o = oracle.label_mask(mask, conn, minarea)
+    assert r["status"] == 0 and r["comp_status"][0] == 0
+    assert r["n_obj"] == n_o
+    np.testing.assert_array_equal(r["seg"], seg_o)
+    M = img.astype(np.float64) - c
+    ocat = oracle.measure(img, M, seg_o, n_o)
+    cmp_catalog(r["cat"], ocat, M, seg_o, tag=name)
+    ph.close()
+
+
+# ----------------------------------------------------------------------------
+# detection and photometry on star fields, stage-isolated
+# ----------------------------------------------------------------------------
+FIELD_CASES = [
+    ("c1", 320, 256, "f32", 11),
+    ("c1", 333, 211, "u16", 12),
+    ("c2", 400, 300, "f32", 13),
+]
+
+
+def _field(case):
+    name, W, H, dt, seed = case
+    nst = max(10, int(W * H / 4e3))
+    fr = make_frame(name, seed=seed, W=W, H=H, dtype=dt, nstars=nst)
+    p = f32_params(fr.params)
+    p.mesh_w = p.mesh_h = 64
+    return fr, p
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("case", FIELD_CASES, ids=lambda c: f"{c[0]}-{c[1]}x{c[2]}-{c[3]}")
+def test_detection_stage_isolated(P, case, prec):
+    _say("detect case", case, prec)
+    fr, p = _field(case)
+    img = fr.image
+    I = img.astype(np.float64)
+    H, W = img.shape
+    ob = oracle.background(I, p, maps=True)
+    M = I - ob.B
+    K = p.kernel()
+    F = oracle.filter_image(M, K)
+    ph = P.Photometry([_dev(img)], p, K, capacity=4096, seg=True, precision=prec)
+    ph.set_grids(0, ob.back, ob.rms)
+    ph.background(grid_given=True)
+    ph.detect()
+    ph.aperture()
+    r = ph.results(0)
+    assert r["status"] == 0 and r["comp_status"][0] == 0
+    seg_g = r["seg"]
+    mask_g = seg_g != 0
+    mask_o = F > p.thresh * ob.R
+    amb = thresh_ambiguous(F, ob.R, p.thresh)
+    diff = mask_g != mask_o
+    _say("mask pixels", int(mask_o.sum()), "differ", int(diff.sum()), "ambiguous", int(amb.sum()))
+    assert np.all(amb[diff])
+    # labels bit-exact for the GPU's own mask
+    seg_chk, n_chk = oracle.threshold_label(mask_g.astype(np.float64), np.zeros_like(I), 0.0, p.minarea, p.conn)
+    np.testing.assert_array_equal(seg_g, seg_chk)
+    assert r["n_obj"] == n_chk
+    # moments: oracle measurements of the same labels
+    ocat = oracle.measure(I, M, seg_g, n_chk, p.sat_level)
+    err = cmp_catalog(r["cat"], ocat, M, seg_g, tag=str(case))
+    _say("catalogue errors", err)
+    # apertures at the GPU's centres on the oracle's M and R
+    xs, ys = r["cat"]["x"], r["cat"]["y"]
+    oph = oracle.aperture(M, ob.R, xs, ys, list(p.radii), p.r_in, p.r_out, p.gain, p.want_err)
+    cond, cond_ann = phot_condition(M, xs, ys, p)
+    err = cmp_phot(r["phot"], oph, cond, cond_ann, tag=str(case))
+    _say("photometry errors", err)
+    trunc = (r["cat"]["flags"] & 8) != 0
+    np.testing.assert_array_equal(trunc, (oph["flags"] & 8) != 0)
+    ph.close()
+
+
+@pytest.mark.parametrize("case", FIELD_CASES[:2], ids=lambda c: f"{c[0]}-{c[1]}x{c[2]}-{c[3]}")
+def test_aperture_stage_isolated_exact_centres(P, case):
+    _say("aperture case", case)
+    fr, p = _field(case)
+    img = fr.image
+    I = img.astype(np.float64)
+    H, W = img.shape
+    ob = oracle.background(I, p, maps=True)
+    M = I - ob.B
+    rng = np.random.default_rng(5)
+    n = 300
+    xs = rng.uniform(-3, W + 3, n)
+    ys = rng.uniform(-3, H + 3, n)
+    ph = P.Photometry([_dev(img)], p, p.kernel(), capacity=n)
+    ph.set_grids(0, ob.back, ob.rms)
+    ph.background(grid_given=True)
+    ph.set_catalog(0, xs, ys)
+    ph.aperture()
+    r = ph.results(0)
+    oph = oracle.aperture(M, ob.R, xs, ys, list(p.radii), p.r_in, p.r_out, p.gain, p.want_err)
+    cond, cond_ann = phot_condition(M, xs, ys, p)
+    err = cmp_phot(r["phot"], oph, cond, cond_ann, tag=str(case))
+    _say("photometry errors", err)
+    np.testing.assert_array_equal((r["cat"]["flags"] & 8) != 0, (oph["flags"] & 8) != 0)
+    ph.close()
+
+
+def test_aperture_constant_image_closed_form(P):
+    c = 7.25
+    W = H = 120
+    img = np.full((H, W), c, np.float32)
+    p = _params("c2")
+    nx, ny = -(-W // p.mesh_w), -(-H // p.mesh_h)
+    ph = P.Photometry([_dev(img)], p, p.kernel(), capacity=64)
+    ph.set_grids(0, np.zeros((ny, nx)), np.ones((ny, nx)))
+    ph.background(grid_given=True)
+    rng = np.random.default_rng(1)
+    xs = 60 + rng.uniform(-2, 2, 40)
+    ys = 60 + rng.uniform(-2, 2, 40)
+    ph.set_catalog(0, xs, ys)
+    ph.aperture()
+    r = ph.results(0)
+    for k, rad in enumerate(p.radii):
+        np.testing.assert_allclose(r["phot"]["area"][:, k], math.pi * rad * rad, rtol=2e-7)
+        np.testing.assert_allclose(r["phot"]["flux"][:, k], 0.0, atol=1e-6 * c * math.pi * rad * rad)
+    np.testing.assert_allclose(r["phot"]["bkg"], c, rtol=1e-7)
+    ph.close()
+
+
+# ----------------------------------------------------------------------------
+# whole chain, batches and failure paths
+# ----------------------------------------------------------------------------
+def test_end_to_end_against_oracle(P):
+    fr = make_frame("c1", seed=21, W=384, H=320, nstars=40)
+    p = f32_params(fr.params)
+    img = fr.image
+    I = img.astype(np.float64)
+    res = oracle.run(I, p)
+    ph = P.Photometry([_dev(img)], p, p.kernel(), capacity=2048, seg=True)
+    ph.run()
+    r = ph.results(0)
+    g = ph.grids(0)
+    amb = mesh_ambiguous(res.bkg.stats)
+    _say("ambiguous meshes", int(amb.sum()))
+    rel = np.abs(g["back_raw"] - res.bkg.stats["back"]) / np.abs(res.bkg.stats["back"])
+    assert np.all(rel[~amb] <= TOL_BKG_REL)
+    if amb.any():
+        pytest.skip("an ambiguous mesh decision: the stage-isolated tests cover the rest")
+    ocat = res.cat
+    gcat = r["cat"]
+    amb_px = thresh_ambiguous(res.F, res.bkg.R, p.thresh)
+    same = np.array_equal(r["seg"] != 0, res.seg != 0)
+    _say("objects", r["n_obj"], len(ocat["npix"]), "masks equal", same, "ambiguous px", int(amb_px.sum()))
+    if same:
+        np.testing.assert_array_equal(r["seg"], res.seg)
+        err = cmp_catalog(gcat, ocat, res.M, res.seg, tag="e2e")
+        cond, cond_ann = phot_condition(res.M, ocat["x"], ocat["y"], p)
+        cmp_phot(r["phot"], res.phot, cond, cond_ann, tag="e2e")
+        _say("e2e errors", err)
+    else:
+        assert np.all(amb_px[(r["seg"] != 0) != (res.seg != 0)])
+
+
+def test_batch_matches_single_frames(P):
+    frs = [make_frame("c1", seed=31, W=300, H=260, nstars=30),
+           make_frame("c1", seed=32, W=130, H=90, nstars=8, dtype="u16"),
+           make_frame("c1", seed=33, W=450, H=128, nstars=25)]
+    p = f32_params(frs[0].params)
+    K = p.kernel()
+    devs = [_dev(f.image) for f in frs]
+    batch = P.Photometry(devs, p, K, capacity=1024, seg=True)
+    batch.run()
+    for i, d in enumerate(devs):
+        one = P.Photometry([d], p, K, capacity=1024, seg=True)
+        one.run()
+        a, b = batch.results(i), one.results(0)
+        assert a["n_obj"] == b["n_obj"] > 0
+        np.testing.assert_array_equal(a["seg"], b["seg"])
+        for k in a["cat"]:
+            if a["cat"][k].dtype.kind in "iu":
+                np.testing.assert_array_equal(a["cat"][k], b["cat"][k], err_msg=k)
+            else:
+                np.testing.assert_allclose(a["cat"][k], b["cat"][k], rtol=1e-12, atol=1e-12, err_msg=k)
+        for k in a["phot"]:
+            np.testing.assert_array_equal(a["phot"][k], b["phot"][k], err_msg=k)
+        ga, gb = batch.grids(i), one.grids(0)
+        for k in ("back_raw", "rms_raw", "back", "rms", "coef"):
+            np.testing.assert_array_equal(ga[k], gb[k])
+        one.close()
+    batch.close()
+
+
+def test_capacity_overflow_keeps_first_labels(P):
+    fr = make_frame("c1", seed=41, W=320, H=320, nstars=60)
+    p = f32_params(fr.params)
+    dev = _dev(fr.image)
+    full = P.Photometry([dev], p, p.kernel(), capacity=4096)
+    full.run()
+    a = full.results(0)
+    n = a["n_obj"]
+    assert n > 6
+    small = P.Photometry([dev], p, p.kernel(), capacity=5)
+    small.run()
+    b = small.results(0)
+    assert b["status"] == 4 and b["n_obj"] == n
+    for k in ("pmin", "npix", "x", "y"):
+        np.testing.assert_array_equal(b["cat"][k], a["cat"][k][:5])
+    full.close()
+    small.close()
+
+
+def test_component_overflow_reports_required_size(P):
+    mask = (np.add.outer(np.arange(128), np.arange(128)) % 2).astype(bool)
+    img = np.where(mask, 600.0, 500.0).astype(np.float32)
+    p = _params("c1", mesh_w=16, mesh_h=16, conn=4, minarea=1)
+    K = np.ones((1, 1), np.float32)
+    ph = P.Photometry([_dev(img)], p, K, capacity=16, comp_capacity=100)
+    ph.set_grids(0, np.full((8, 8), 500.0), np.zeros((8, 8)))
+    ph.background(grid_given=True)
+    ph.detect()
+    r = ph.results(0)
+    assert r["comp_status"][0] == 3 and r["comp_status"][1] == 128 * 128 // 2
+    assert r["status"] == 3
+    ph.close()
+
+
+def test_invalid_arguments_fail_synchronously(P):
+    from paper_2609_32375_amd import _lib as L
+    img = _dev(np.zeros((64, 64), np.float32))
+    p = _params("c1")
+    ph = P.Photometry([img], p, p.kernel(), capacity=8)
+    bad_k = np.ones((4, 4), np.float32)
+    with pytest.raises(L.GpError) as e:
+        P.Photometry([img], p, bad_k, capacity=8)
+    assert e.value.status == L.GP_ERR_INVALID_ARG
+    q = _params("c1", minarea=0)
+    with pytest.raises(L.GpError):
+        P.Photometry([img], q, p.kernel(), capacity=8)
+    q = _params("c1", conn=6)
+    with pytest.raises(L.GpError):
+        P.Photometry([img], q, p.kernel(), capacity=8)
+    # undersized workspace
+    with pytest.raises(L.GpError) as e:
+        L.gp_detect(ph.ctx, ph.frames, ph.bp, ph.bkg.data_ptr(), ph.dp, ph.gcat, None, None,
+                    ph.ws.data_ptr(), 1024, ph.stream_ptr())
+    assert e.value.status == L.GP_ERR_WORKSPACE
+    ph.close()
