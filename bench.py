@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the photometry hot path on one MI355X.
+
+A step is one pass of the whole path -- gp_background, gp_detect, gp_aperture
+-- over one synthetic frame already resident in HBM.  The default workload is
+the 6144 x 6144 float32 field (20,000 Moffat stars, mesh 128, 9x9 Gaussian
+filter, threshold 1.5 sigma, minarea 5, 8-connected, apertures 3/6/9 px,
+annulus 13-18 px).  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--forms]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "extracted MP/s + p50/p99 frame latency, batched/served vs plain, 1 MI355X"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-crop", type=int, default=3072, help="side of the CPU-baseline crop")
+    ap.add_argument("--forms", action="store_true", help="also time the graph-captured form")
+    ap.add_argument("--profile-steps", type=int, default=5)
+    return ap.parse_args()
+
+
+def kernel_bytes(name, W, H, bpp, n_obj, rmax):
+    """Algorithmic bytes one launch of a kernel must move."""
+    if name in ("mesh_stats", "detect_tiles"):
+        return W * H * bpp
+    if name == "aperture":
+        return n_obj * math.pi * rmax * rmax * bpp
+    return None
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU form is a design note",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2609_32375_amd import _lib as L
+    from paper_2609_32375_amd.pipeline import Photometry
+    from synth import make_frame
+
+    t0 = time.time()
+    fr = make_frame(a.workload)
+    img = fr.image
+    H, W = img.shape
+    p = fr.params
+    log(f"frame {a.workload} {W}x{H} {img.dtype} generated in {time.time() - t0:.1f}s")
+    dev = torch.from_numpy(img).cuda()
+    K = p.kernel()
+    cap = 65536 if a.workload != "c3" else 262144
+    ph = Photometry([dev], p, K, capacity=cap)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ph.run()
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    r = ph.results(0)
+    n_obj = r["n_obj"]
+    log(f"objects {n_obj} status {r['status']}")
+    # timed region
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    lat = []
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(a.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        step()
+        e1.record(stream)
+        lat.append((e0, e1))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    ms = total_ms / a.steps
+    lat_ms = np.array([x.elapsed_time(y) for x, y in lat])
+    mp = W * H / 1e6
+    value = mp / (ms / 1e3)
+    log(f"plain: {ms:.3f} ms/step, {value:.1f} MP/s")
+
+    # per-kernel durations (events around each launch, same stream)
+    L.gp_profile_reset(ph.ctx)
+    L.gp_profile_enable(ph.ctx, True)
+    for _ in range(a.profile_steps):
+        step()
+    torch.cuda.synchronize()
+    L.gp_profile_enable(ph.ctx, False)
+    kern = {}
+    for name in ("mesh_stats", "grid_filter", "spline", "clear", "detect_tiles", "merge", "catalog", "aperture"):
+        tot, cnt = L.gp_profile_read(ph.ctx, name)
+        if cnt:
+            kern[name] = tot / cnt
+    log("kernel ms:", {k: round(v, 4) for k, v in kern.items()})
+    bpp = img.dtype.itemsize
+    rmax = max(p.r_out, max(p.radii))
+    dom = max((k for k in kern if kernel_bytes(k, W, H, bpp, n_obj, rmax)), key=lambda k: kern[k])
+    alg = kernel_bytes(dom, W, H, bpp, n_obj, rmax)
+    achieved = alg / (kern[dom] * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{dom}_{a.workload}.json")
+    if os.path.exists(tfile):
+        try:
+            traffic = json.load(open(tfile)).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel_ms": round(kern[dom], 4), "algorithmic_bytes": int(alg)}
+    # whole-step algorithmic bytes (both frame passes + aperture footprints)
+    step_bytes = 2 * W * H * bpp + n_obj * math.pi * rmax * rmax * bpp
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "MP/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {W}x{H} {img.dtype} star field, plain per-frame calls",
+                   "objects": n_obj, "mesh": p.mesh_w, "kernel": p.kernel_size, "radii": list(p.radii)},
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 4)},
+        "step_hbm_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernels_ms": {k: round(v, 4) for k, v in kern.items()},
+        "roofline": roof,
+    }
+    if a.forms:
+        # the same three calls captured once into a HIP graph and replayed
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            step()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            step()
+        for _ in range(a.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        gms = e0.elapsed_time(e1) / a.steps
+        out["forms"] = {"plain": {"mp_s": round(value, 1), "ms": round(ms, 4)},
+                        "graph": {"mp_s": round(mp / (gms / 1e3), 1), "ms": round(gms, 4)}}
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(fr, a.cpu_crop)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(fr, side):
+    """The FP64 oracle on a bounded crop of the same frame, one host thread."""
+    import oracle
+    from synth import crop
+    H, W = fr.image.shape
+    s = min(side, W, H)
+    c = crop(fr, (W - s) // 2, (H - s) // 2, s, s)
+    I = c.image.astype(np.float64)
+    t0 = time.time()
+    oracle.run(I, fr.params)
+    dt = time.time() - t0
+    return {"value": round(s * s / 1e6 / dt, 4), "unit": "MP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{s}x{s} central crop of the same frame, full chain, FP64, one thread, {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -617,8 +617,9 @@ double or_overlap(double x0, double x1, double y0, double y1, double cx, double 
  *   flux_k  = raw_k - bkg * area_k
  *   err_k   = sqrt(sum_p w_p(r_k)^2 (R_p^2 + max(M_p, 0) / gain))  (gain <= 0:
  *             no Poisson term)
- * Pixels outside the frame contribute nothing; an object whose apertures or
- * annulus reach outside the frame gets APER_TRUNC.  Outputs are [n][nr].
+ * Pixels outside the frame contribute nothing.  An object whose largest circle
+ * (aperture or annulus) crosses the frame boundary [-1/2, W-1/2] x [-1/2, H-1/2]
+ * gets APER_TRUNC.  Outputs are [n][nr].
  */
 int or_aperture(const double* M, const double* R, long W, long H, const double* xc,
                 const double* yc, long n, const double* radii, int nr, double r_in,
@@ -649,10 +650,8 @@ int or_aperture(const double* M, const double* R, long W, long H, const double* 
                     wk[k] = or_overlap(x0, x1, y0, y1, cx, cy, radii[k]);
                     if (wk[k] > wmax) wmax = wk[k];
                 }
-                if (!inside) {
-                    if (wmax > 0.0) fl |= OR_FLAG_APER_TRUNC;
-                    continue;
-                }
+                (void)wmax;
+                if (!inside) continue;
                 double m = M[py * W + px];
                 for (int k = 0; k < nr; ++k) {
                     A[k] += wk[k];
@@ -666,6 +665,8 @@ int or_aperture(const double* M, const double* R, long W, long H, const double* 
                 Aa += wo - wi;
                 Sa += (wo - wi) * m;
             }
+        if (cx - rmax < -0.5 || cx + rmax > (double)W - 0.5 || cy - rmax < -0.5 || cy + rmax > (double)H - 0.5)
+            fl |= OR_FLAG_APER_TRUNC;
         double b = (Aa > 0.0) ? Sa / Aa : 0.0;
         bkg[o] = b;
         for (int k = 0; k < nr; ++k) {

@@ -55,7 +55,8 @@ __device__ __forceinline__ Real quad_area(Real a0, Real a1, Real b0, Real b1, Re
     if (a0 * a0 + b0 * b0 >= r2) return (Real)0;
     if (a1 * a1 + b1 * b1 <= r2) return (a1 - a0) * (b1 - b0);
     const Real uhi = sqrt(fmax(r2 - b0 * b0, (Real)0));   // arc height == b0
-    const Real ulo = sqrt(fmax(r2 - b1 * b1, (Real)0));   // arc height == b1
+    // abscissa where the arc height is b1; when b1 >= r the arc stays below b1
+    const Real ulo = (b1 * b1 < r2) ? sqrt(r2 - b1 * b1) : (Real)-1;
     const Real p = fmin(fmax(ulo, a0), a1);
     const Real q = fmin(uhi, a1);
     Real area = (p - a0) * (b1 - b0);
@@ -170,10 +171,8 @@ __global__ __launch_bounds__(256) void k_aperture(const FrameDesc* __restrict__ 
         }
         aA.zero();
         aS.zero();
-        bool trunc = false;
         const Real rin = (Real)a.r_in, rout = (Real)a.r_out;
         const Real rin2 = rin * rin, rout2 = rout * rout;
-        const Real rmax2 = rmax * rmax;
         const Real inv_gain = (a.gain > 0.f) ? (Real)1 / (Real)a.gain : (Real)0;
         for (int band = 0; band < side; band += kApBand) {
             const int nb = min(kApBand, side - band);
@@ -192,11 +191,7 @@ __global__ __launch_bounds__(256) void k_aperture(const FrameDesc* __restrict__ 
                 const int px = bx0 + c, py = by0 + band + rr;
                 const Real dx = (Real)(px - cxi) - fx, dy = (Real)(py - cyi) - fy;
                 const bool inside = px >= 0 && px < d.W && py >= 0 && py < d.H;
-                if (!inside) {
-                    const Real ax = fmax(fabs(dx) - (Real)0.5, (Real)0), ay = fmax(fabs(dy) - (Real)0.5, (Real)0);
-                    if (ax * ax + ay * ay < rmax2) trunc = true;
-                    continue;
-                }
+                if (!inside) continue;
                 const RowT<Real>& T = sh.tab[wv][rr * kApNix + sh.colp[wv][c]];
                 const Real s = sh.cols[wv][c];
                 const Real v = (Real)load_px(d, px, py);
@@ -228,7 +223,10 @@ __global__ __launch_bounds__(256) void k_aperture(const FrameDesc* __restrict__ 
         }
         const double Aa = aA.reduce(), Sa = aS.reduce();
         const double b = (Aa > 0.0) ? Sa / Aa : 0.0;
-        const bool any_trunc = __any(trunc);
+        // the largest circle crosses the frame boundary
+        const double rm = (double)a.rmax;
+        const bool any_trunc = xc - rm < -0.5 || xc + rm > (double)d.W - 0.5 || yc - rm < -0.5 ||
+                               yc + rm > (double)d.H - 0.5;
 #pragma unroll
         for (int q = 0; q < kMaxRadii; ++q) {
             if (q >= nr) break;

@@ -59,8 +59,7 @@ struct CatOut {
 void launch_mesh_stats(const FrameDesc* desc, int nframes, int total_meshes, int max_area, BkgArgs a,
                        hipStream_t s);
 void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, int fsize, hipStream_t s);
-void launch_spline(const FrameDesc* desc, int nframes, int total_ycols, int total_xk, int total_pieces,
-                   hipStream_t s);
+void launch_spline(const FrameDesc* desc, int nframes, int total_ycols, int total_xrows, hipStream_t s);
 void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, hipStream_t s);
 void launch_merge(const DetWork& wk, int conn, int minarea, int persist_blocks, hipStream_t s);

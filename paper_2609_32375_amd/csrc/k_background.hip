@@ -475,49 +475,19 @@ __global__ void k_spline_y(const FrameDesc* __restrict__ desc, int nframes, int 
     }
 }
 
-// x-basis: coefficients of every x piece as a linear function of the knot
-// values (cardinal natural splines), lx[ix][p][k]
-__global__ void k_spline_xbasis(const FrameDesc* __restrict__ desc, int nframes, int total) {
+// x-splines: the tensor spline's row cubic on y piece jy is a cubic in u whose
+// four coefficients are linear in the column values, so the x spline of each
+// coefficient vector (one natural spline per (quantity, jy, power of u)) gives
+// the bicubic pieces directly: coef[q][jy][ix][p*4+r] = x-piece p coefficient
+// of the spline through (ycoef[q][jy][k][r])_k.  Exact on constant grids.
+__global__ void k_spline_x(const FrameDesc* __restrict__ desc, int nframes, int total) {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total) return;
     int f = 0;
     {
         int acc = 0;
         for (; f < nframes; ++f) {
-            int c = desc[f].nx;
-            if (g < acc + c) break;
-            acc += c;
-        }
-        g -= acc;
-    }
-    const FrameDesc& d = desc[f];
-    const int nx = d.nx, ny = d.ny, k = g;
-    double* scr = d.scratch + (size_t)(2 * nx) * (size_t)(4 * ny) + (size_t)k * (size_t)(5 * nx);
-    double* tk = scr;
-    double* e = scr + nx;
-    double* mm = scr + 2 * nx;
-    double* wk = scr + 3 * nx;
-    for (int j = 0; j < nx; ++j) {
-        tk[j] = knot_at(j, d.W, d.mw);
-        e[j] = (j == k) ? 1.0 : 0.0;
-    }
-    natural_second(nx, tk, e, 1, mm, 1, wk);
-    for (int ix = 0; ix <= nx; ++ix) {
-        double c[4];
-        piece_poly(nx, tk, e, 1, mm, 1, ix, c);
-        for (int p = 0; p < 4; ++p) d.lx[((size_t)ix * 4 + p) * nx + k] = c[p];
-    }
-}
-
-// bicubic pieces: coef[q][jy][ix][p*4+r] = sum_k lx[ix][p][k] ycoef[q][jy][k][r]
-__global__ void k_spline_pieces(const FrameDesc* __restrict__ desc, int nframes, int total) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    int f = 0;
-    {
-        int acc = 0;
-        for (; f < nframes; ++f) {
-            int c = 2 * (desc[f].nx + 1) * (desc[f].ny + 1);
+            int c = 2 * (desc[f].ny + 1) * 4;
             if (g < acc + c) break;
             acc += c;
         }
@@ -525,22 +495,22 @@ __global__ void k_spline_pieces(const FrameDesc* __restrict__ desc, int nframes,
     }
     const FrameDesc& d = desc[f];
     const int nx = d.nx, ny = d.ny;
-    const int ix = g % (nx + 1);
-    const int jy = (g / (nx + 1)) % (ny + 1);
-    const int q = g / ((nx + 1) * (ny + 1));
-    double acc[16];
-    for (int z = 0; z < 16; ++z) acc[z] = 0.0;
-    const double* Y = d.ycoef + (((size_t)q * (ny + 1) + jy) * nx) * 4;
-    for (int k = 0; k < nx; ++k) {
-        const double* yk = Y + (size_t)k * 4;
-        for (int p = 0; p < 4; ++p) {
-            double l = d.lx[((size_t)ix * 4 + p) * nx + k];
-            if (l == 0.0) continue;
-            for (int r = 0; r < 4; ++r) acc[p * 4 + r] += l * yk[r];
-        }
+    const int r = g & 3;
+    const int jy = (g >> 2) % (ny + 1);
+    const int q = (g >> 2) / (ny + 1);
+    double* scr = d.scratch + (size_t)(2 * nx) * (size_t)(4 * ny) + (size_t)g * (size_t)(4 * nx);
+    double* tk = scr;
+    double* mm = scr + nx;
+    double* wk = scr + 2 * nx;
+    for (int j = 0; j < nx; ++j) tk[j] = knot_at(j, d.W, d.mw);
+    const double* vals = d.ycoef + (((size_t)q * (ny + 1) + jy) * nx) * 4 + r;  // stride 4
+    natural_second(nx, tk, vals, 4, mm, 1, wk);
+    for (int ix = 0; ix <= nx; ++ix) {
+        double c[4];
+        piece_poly(nx, tk, vals, 4, mm, 1, ix, c);
+        double* o = d.coef + (((size_t)q * (ny + 1) + jy) * (nx + 1) + ix) * 16;
+        for (int p = 0; p < 4; ++p) o[p * 4 + r] = c[p];
     }
-    double* o = d.coef + (((size_t)q * (ny + 1) + jy) * (nx + 1) + ix) * 16;
-    for (int z = 0; z < 16; ++z) o[z] = acc[z];
 }
 
 // ---------------------------------------------------------------------------
@@ -559,11 +529,9 @@ void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, in
     k_grid_filter<<<(total_meshes + 255) / 256, 256, 0, s>>>(desc, nframes, total_meshes, fsize);
 }
 
-void launch_spline(const FrameDesc* desc, int nframes, int total_ycols, int total_xk, int total_pieces,
-                   hipStream_t s) {
+void launch_spline(const FrameDesc* desc, int nframes, int total_ycols, int total_xrows, hipStream_t s) {
     k_spline_y<<<(total_ycols + 63) / 64, 64, 0, s>>>(desc, nframes, total_ycols);
-    k_spline_xbasis<<<(total_xk + 63) / 64, 64, 0, s>>>(desc, nframes, total_xk);
-    k_spline_pieces<<<(total_pieces + 255) / 256, 256, 0, s>>>(desc, nframes, total_pieces);
+    k_spline_x<<<(total_xrows + 63) / 64, 64, 0, s>>>(desc, nframes, total_xrows);
 }
 
 // ---------------------------------------------------------------------------

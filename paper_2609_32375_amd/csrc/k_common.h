@@ -35,8 +35,7 @@ struct FrameDesc {
     double* coef;         // [2][ny+1][nx+1][16]
     int32_t* iters;       // [ny][nx]
     double* ycoef;        // workspace: [2][ny+1][nx][4]
-    double* lx;           // workspace: [nx+1][4][nx]
-    double* scratch;      // workspace: Thomas sweeps, [2 * nx + nx][2 * max(nx, ny)]
+    double* scratch;      // workspace: Thomas sweeps of the y and x splines
     int32_t mesh_base;    // first flattened mesh of this frame
     int32_t tile_base;    // first flattened detection tile
     int32_t ntx, nty;     // detection tiles per row / column

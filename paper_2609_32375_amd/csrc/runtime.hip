@@ -104,13 +104,13 @@ struct FramePlan {
     size_t bkg_off;  // frame block offset in the background buffer
     size_t back_raw, rms_raw, back, rms, coef, iters, bkg_bytes;  // relative to block
     size_t spl_off;  // workspace offset of this frame's spline scratch
-    size_t ycoef_n, lx_n, scr_n;  // doubles
+    size_t ycoef_n, scr_n;  // doubles
 };
 
 struct Plan {
     std::vector<FramePlan> fr;
-    int64_t total_meshes = 0, total_tiles = 0, total_blocks = 0, total_ycols = 0, total_xk = 0,
-            total_pieces = 0, total_px = 0;
+    int64_t total_meshes = 0, total_tiles = 0, total_blocks = 0, total_ycols = 0, total_xrows = 0,
+            total_px = 0;
     int max_area = 0;
     size_t bkg_bytes = 0;
     // workspace sections
@@ -207,8 +207,7 @@ void plan_bkg(const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp, 
         off += F.bkg_bytes;
         P.total_meshes += F.meshes;
         P.total_ycols += 2 * F.nx;
-        P.total_xk += F.nx;
-        P.total_pieces += 2 * (int64_t)(F.nx + 1) * (F.ny + 1);
+        P.total_xrows += 2 * (int64_t)(F.ny + 1) * 4;
         const int mw = std::min(bp->mesh_w, W), mh = std::min(bp->mesh_h, H);
         P.max_area = std::max(P.max_area, mw * mh);
         F.ntx = (int)ceil_div(W, kTile);
@@ -219,8 +218,8 @@ void plan_bkg(const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp, 
         P.total_blocks += F.nblocks;
         P.total_px += (int64_t)W * H;
         F.ycoef_n = (size_t)2 * (F.ny + 1) * F.nx * 4;
-        F.lx_n = (size_t)(F.nx + 1) * 4 * F.nx;
-        F.scr_n = (size_t)8 * F.nx * F.ny + (size_t)5 * F.nx * F.nx;
+        // Thomas sweeps: 4 ny per y-spline (2 nx of them), 4 nx per x-spline (8 (ny+1))
+        F.scr_n = (size_t)8 * F.nx * F.ny + (size_t)32 * F.nx * (F.ny + 1);
     }
     P.bkg_bytes = off;
 }
@@ -246,7 +245,7 @@ void plan_fixed(int32_t nframes, Plan& P) {
     for (int f = 0; f < nframes; ++f) {
         FramePlan& F = P.fr[f];
         F.spl_off = o;
-        o += align256(sizeof(double) * (F.ycoef_n + F.lx_n + F.scr_n));
+        o += align256(sizeof(double) * (F.ycoef_n + F.scr_n));
     }
     P.o_recs = o;
 }
@@ -305,8 +304,7 @@ gp_status upload_desc(const gp_frame* frames, int32_t nframes, const gp_bkg_para
         d.iters = (int32_t*)(fb + F.iters);
         double* sp = (double*)(W + F.spl_off);
         d.ycoef = sp;
-        d.lx = sp + F.ycoef_n;
-        d.scratch = sp + F.ycoef_n + F.lx_n;
+        d.scratch = sp + F.ycoef_n;
         d.mesh_base = (int32_t)mesh_base;
         d.tile_base = (int32_t)tile_base;
         d.ntx = F.ntx;
@@ -472,7 +470,7 @@ extern "C" gp_status gp_background(gp_ctx* ctx, const gp_frame* frames, int32_t 
     }
     {
         ProfScope ps(ctx, s, "spline");
-        launch_spline(desc, nframes, (int)P.total_ycols, (int)P.total_xk, (int)P.total_pieces, s);
+        launch_spline(desc, nframes, (int)P.total_ycols, (int)P.total_xrows, s);
     }
     HIP_TRY(hipGetLastError());
     return GP_OK;
