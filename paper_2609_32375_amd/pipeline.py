@@ -94,22 +94,23 @@ class Photometry:
         self.ws_bytes = L.gp_workspace_size(self.ctx, self.frames, self.bp, self.dp, self.ap, self.capacity,
                                             comp_capacity)
         dev = self.device
-        self.bkg = torch.zeros(max(bkg_bytes, 256), dtype=torch.uint8, device=dev)
-        self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=dev)
+        # the library writes everything it later reads: no clearing needed
+        self.bkg = torch.empty(max(bkg_bytes, 256), dtype=torch.uint8, device=dev)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
         rows = max(self.n * self.capacity, 1)
         nr = len(self.radii)
-        self.cat = {k: torch.zeros(rows, dtype=torch.int32, device=dev) for k in CAT_INT}
-        self.cat.update({k: torch.zeros(rows, dtype=torch.float64, device=dev) for k in CAT_F64})
-        self.cat["pmin"] = torch.zeros(rows, dtype=torch.int64, device=dev)
-        self.cat["peak"] = torch.zeros(rows, dtype=torch.float32, device=dev)
-        self.cat["flags"] = torch.zeros(rows, dtype=torch.int32, device=dev)
+        self.cat = {k: torch.empty(rows, dtype=torch.int32, device=dev) for k in CAT_INT}
+        self.cat.update({k: torch.empty(rows, dtype=torch.float64, device=dev) for k in CAT_F64})
+        self.cat["pmin"] = torch.empty(rows, dtype=torch.int64, device=dev)
+        self.cat["peak"] = torch.empty(rows, dtype=torch.float32, device=dev)
+        self.cat["flags"] = torch.empty(rows, dtype=torch.int32, device=dev)
         self.n_obj = torch.zeros(self.n, dtype=torch.int32, device=dev)
         self.status = torch.zeros(self.n, dtype=torch.int32, device=dev)
         self.comp_status = torch.zeros(2, dtype=torch.int32, device=dev)
-        self.phot = {"flux": torch.zeros(rows, nr, dtype=torch.float64, device=dev),
-                     "area": torch.zeros(rows, nr, dtype=torch.float64, device=dev),
-                     "fluxerr": torch.zeros(rows, nr, dtype=torch.float64, device=dev),
-                     "bkg": torch.zeros(rows, dtype=torch.float64, device=dev)}
+        self.phot = {"flux": torch.empty(rows, nr, dtype=torch.float64, device=dev),
+                     "area": torch.empty(rows, nr, dtype=torch.float64, device=dev),
+                     "fluxerr": torch.empty(rows, nr, dtype=torch.float64, device=dev),
+                     "bkg": torch.empty(rows, dtype=torch.float64, device=dev)}
         c = self.cat
         self.gcat = L.gp_catalog(self.capacity, self.n_obj.data_ptr(), self.status.data_ptr(),
                                  *[c[k].data_ptr() for k in CAT_INT], c["pmin"].data_ptr(),

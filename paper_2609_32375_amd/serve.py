@@ -1,0 +1,196 @@
+"""Serving: continuous batching of frames over the C ABI.
+
+Requests (frames of any size, u16 or f32, on the host or already in HBM)
+arrive over time.  The loop admits waiting requests in arrival order while a
+slot is free and their HBM footprint fits the budget, launches every request
+admitted at one poll as one batch (one gp_background / gp_detect /
+gp_aperture sequence over all of them) on the next stream of a small pool, and
+keeps going: batches from consecutive polls run concurrently on the device
+while earlier ones finish.  A finished batch releases its slots and footprint
+and hands each request its catalogue and photometry.
+
+Everything per pixel runs in the HIP library; this module schedules.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Any, List, Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .pipeline import Photometry
+
+
+@dataclass
+class Request:
+    rid: int
+    frame: Any                      # numpy array (host) or torch tensor (device)
+    arrival: float = 0.0            # seconds on the server clock
+    footprint: int = 0
+    t_admit: Optional[float] = None
+    t_done: Optional[float] = None
+    result: Optional[dict] = None
+
+    @property
+    def latency(self):
+        return None if self.t_done is None else self.t_done - self.arrival
+
+
+@dataclass
+class _Epoch:
+    reqs: List[Request]
+    ph: Photometry
+    stream: torch.cuda.Stream
+    done: torch.cuda.Event
+    dev_frames: list = field(default_factory=list)
+
+
+class Server:
+    """Continuous-batching server for one GPU.
+
+    hbm_budget: bytes of HBM the in-flight requests may hold (frames, background
+    buffers, workspace, catalogue); None = 90% of the free memory at start.
+    slots: most requests in flight.  streams: concurrent batches.
+    """
+
+    def __init__(self, params, kernel, capacity: int = 65536, hbm_budget: Optional[int] = None,
+                 slots: int = 8, streams: int = 2, device: int = 0, max_batch: Optional[int] = None):
+        self.params = params
+        self.kernel = np.ascontiguousarray(kernel, dtype=np.float32)
+        self.capacity = capacity
+        self.device = torch.device("cuda", device)
+        self.ctx = L.gp_ctx_create(device)
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            hbm_budget = int(0.9 * free)
+        self.budget = int(hbm_budget)
+        self.slots = slots
+        self.max_batch = max_batch or slots
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
+        self._next_stream = 0
+        self.waiting: deque = deque()
+        self.inflight: List[_Epoch] = []
+        self.resident = 0
+        self.t0 = time.perf_counter()
+        self.finished: List[Request] = []
+        self._ws_cache = {}
+
+    # ------------------------------------------------------------------
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def footprint(self, frame) -> int:
+        """HBM bytes a request holds while in flight (its frame, its share of
+        the background buffer and workspace, its catalogue rows)."""
+        H, W = frame.shape
+        bpp = 2 if frame.dtype in (np.uint16, torch.uint16) else 4
+        fr = L.gp_frame(1, W, H, W, L.GP_U16 if bpp == 2 else L.GP_F32)
+        p = self.params
+        bp = L.gp_bkg_params(p.mesh_w, p.mesh_h, p.mesh_filter, p.clip_sigma, p.crowd_tol, p.mode_a, p.mode_b,
+                             p.max_iter, 0)
+        key = (W, H, bpp)
+        if key not in self._ws_cache:
+            _, bkg = L.gp_background_layout([fr], bp)
+            ws = L.gp_workspace_size(self.ctx, [fr], bp, None, None, self.capacity, 0)
+            self._ws_cache[key] = bkg + ws
+        nr = len(p.radii)
+        cat = self.capacity * (5 * 4 + 8 + 6 * 8 + 4 + 4 + 3 * nr * 8 + 8)
+        own = W * H * bpp if not (isinstance(frame, torch.Tensor) and frame.is_cuda) else 0
+        return own + self._ws_cache[key] + cat
+
+    def submit(self, req: Request):
+        req.footprint = self.footprint(req.frame)
+        if req.footprint > self.budget:
+            raise ValueError(f"request {req.rid} needs {req.footprint} bytes, above the budget {self.budget}")
+        self.waiting.append(req)
+
+    # ------------------------------------------------------------------
+    def _retire(self):
+        keep = []
+        for ep in self.inflight:
+            if ep.done.query():
+                t = self.now()
+                for i, r in enumerate(ep.reqs):
+                    r.result = ep.ph.results(i)
+                    r.t_done = t
+                    self.resident -= r.footprint
+                    self.finished.append(r)
+                ep.ph.close()
+            else:
+                keep.append(ep)
+        self.inflight = keep
+
+    def _admit(self):
+        batch = []
+        n_inflight = sum(len(e.reqs) for e in self.inflight)
+        while self.waiting and len(batch) < self.max_batch:
+            r = self.waiting[0]
+            if r.arrival > self.now():
+                break
+            if n_inflight + len(batch) >= self.slots or self.resident + r.footprint > self.budget:
+                break
+            self.waiting.popleft()
+            r.t_admit = self.now()
+            self.resident += r.footprint
+            batch.append(r)
+        if not batch:
+            return False
+        stream = self.streams[self._next_stream % len(self.streams)]
+        self._next_stream += 1
+        with torch.cuda.stream(stream):
+            devs = []
+            for r in batch:
+                f = r.frame
+                if isinstance(f, torch.Tensor) and f.is_cuda:
+                    devs.append(f)
+                else:
+                    t = torch.as_tensor(f)
+                    devs.append(t.to(self.device, non_blocking=True))
+            ph = Photometry(devs, self.params, self.kernel, self.capacity, ctx=self.ctx)
+            ph.run(stream)
+            done = torch.cuda.Event()
+            done.record(stream)
+        self.inflight.append(_Epoch(batch, ph, stream, done, devs))
+        return True
+
+    def poll(self):
+        self._retire()
+        while self._admit():
+            pass
+
+    def drain(self, poll_sleep: float = 2e-4):
+        while self.waiting or self.inflight:
+            self.poll()
+            if self.inflight or self.waiting:
+                time.sleep(poll_sleep)
+
+    def run(self, requests: List[Request], poll_sleep: float = 2e-4):
+        """Serve requests whose `arrival` times are relative to now; returns
+        them finished, with latencies."""
+        self.t0 = time.perf_counter()
+        for r in sorted(requests, key=lambda r: r.arrival):
+            self.submit(r)
+        self.drain(poll_sleep)
+        return requests
+
+    def close(self):
+        for ep in self.inflight:
+            ep.done.synchronize()
+            ep.ph.close()
+        self.inflight = []
+        if self.ctx:
+            L.gp_ctx_destroy(self.ctx)
+            self.ctx = None
+
+
+def latency_stats(reqs: List[Request]):
+    lat = np.array([r.latency for r in reqs if r.latency is not None])
+    if lat.size == 0:
+        return {}
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3)}

@@ -1,0 +1,64 @@
+"""Serving: continuous batching returns, for every request, the result it gets
+alone; admission respects the HBM budget and the slot count (needs a GPU)."""
+import numpy as np
+import pytest
+
+from synth import make_frame
+from tests._util import f32_params
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _solo(P, img, p, K, cap):
+    ph = P.Photometry([torch.from_numpy(img).cuda()], p, K, cap)
+    ph.run()
+    r = ph.results(0)
+    ph.close()
+    return r
+
+
+def test_results_alone_equal_results_in_the_mix():
+    from paper_2609_32375_amd import pipeline as P
+    from paper_2609_32375_amd.serve import Request, Server, latency_stats
+    frs = [make_frame("c1", seed=60 + i, W=w, H=h, nstars=n, dtype=dt)
+           for i, (w, h, n, dt) in enumerate([(300, 260, 30, "f32"), (512, 128, 20, "u16"), (200, 200, 12, "f32"),
+                                               (640, 300, 40, "u16"), (256, 256, 25, "f32"), (96, 400, 10, "f32")])]
+    p = f32_params(frs[0].params)
+    K = p.kernel()
+    cap = 2048
+    solo = [_solo(P, f.image, p, K, cap) for f in frs]
+    # a tight budget forces deferral; half the frames come from the host
+    srv = Server(p, K, capacity=cap, slots=3, streams=2)
+    fps = [srv.footprint(f.image) for f in frs]
+    srv.budget = int(max(fps) * 2.5)
+    reqs = []
+    for i, f in enumerate(frs):
+        frame = f.image if i % 2 else torch.from_numpy(f.image).cuda()
+        reqs.append(Request(i, frame, arrival=0.002 * i))
+    peak = [0]
+    orig = srv._admit
+
+    def admit():
+        ok = orig()
+        peak[0] = max(peak[0], srv.resident)
+        assert sum(len(e.reqs) for e in srv.inflight) <= srv.slots
+        return ok
+    srv._admit = admit
+    srv.run(reqs)
+    assert peak[0] <= srv.budget
+    for r, s in zip(reqs, solo):
+        a = r.result
+        assert a["n_obj"] == s["n_obj"] and a["status"] == s["status"] == 0
+        for k in ("pmin", "npix", "xmin", "xmax", "ymin", "ymax", "flags"):
+            np.testing.assert_array_equal(a["cat"][k], s["cat"][k], err_msg=k)
+        for k in ("flux", "x", "y", "x2", "y2", "xy"):
+            np.testing.assert_allclose(a["cat"][k], s["cat"][k], rtol=1e-12, atol=1e-12, err_msg=k)
+        for k in a["phot"]:
+            np.testing.assert_array_equal(a["phot"][k], s["phot"][k], err_msg=k)
+        assert r.latency is not None and r.latency >= 0
+    st = latency_stats(reqs)
+    assert st["p99_ms"] >= st["p50_ms"] > 0
+    with pytest.raises(ValueError):
+        srv.submit(Request(99, np.zeros((4096, 4096), np.float32)))
+    srv.close()
