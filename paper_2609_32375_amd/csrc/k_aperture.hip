@@ -131,12 +131,12 @@ struct ApShared {
     Real cols[kApWaves][kApBox];
 };
 
-template <typename Real>
+template <typename Real, int NR>
 __global__ __launch_bounds__(256) void k_aperture(const FrameDesc* __restrict__ desc, ApArgs a, ApCat cat,
                                                   int total_rows) {
     __shared__ ApShared<Real> sh;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int nr = a.nr;
+    constexpr int nr = NR;
     const Real rmax = (Real)a.rmax;
     const int R = (int)ceilf(a.rmax) + 1;
     const int side = 2 * R + 2;
@@ -162,9 +162,9 @@ __global__ __launch_bounds__(256) void k_aperture(const FrameDesc* __restrict__ 
                 sh.cols[wv][c] = (Real)((double)px - piece_ref(ix, d.W, d.mw));
             }
         }
-        Acc<Real> sA[kMaxRadii], sS[kMaxRadii], sV[kMaxRadii], aA, aS;
+        Acc<Real> sA[NR], sS[NR], sV[NR], aA, aS;
 #pragma unroll
-        for (int q = 0; q < kMaxRadii; ++q) {
+        for (int q = 0; q < NR; ++q) {
             sA[q].zero();
             sS[q].zero();
             sV[q].zero();
@@ -186,37 +186,54 @@ __global__ __launch_bounds__(256) void k_aperture(const FrameDesc* __restrict__ 
                 sh.tab[wv][rr * kApNix + pi] = make_row<Real>(d.coef, d.nx, d.ny, ixlo + pi, jy, u);
             }
             wave_sync();
-            for (int e = lane; e < nb * side; e += 64) {
-                const int rr = e / side, c = e - rr * side;
-                const int px = bx0 + c, py = by0 + band + rr;
-                const Real dx = (Real)(px - cxi) - fx, dy = (Real)(py - cyi) - fy;
-                const bool inside = px >= 0 && px < d.W && py >= 0 && py < d.H;
-                if (!inside) continue;
-                const RowT<Real>& T = sh.tab[wv][rr * kApNix + sh.colp[wv][c]];
-                const Real s = sh.cols[wv][c];
-                const Real v = (Real)load_px(d, px, py);
-                const Real m = eval_M(T, s, v);
-                Real var = 0;
-                if (a.want_err) {
-                    const Real rr_ = eval_R(T, s);
-                    var = rr_ * rr_ + ((m > (Real)0) ? m * inv_gain : (Real)0);
-                }
-                const Real wo = pixel_area<Real>(dx, dy, rout, rout2);
-                const Real wi = (rin > (Real)0) ? pixel_area<Real>(dx, dy, rin, rin2) : (Real)0;
-                const Real wa = wo - wi;
-                if (wa != (Real)0) {
-                    aA.add(wa);
-                    aS.add(wa * m);
+            // pixels of the band, 8 per lane at a time with their loads in flight
+            const int npx = nb * side;
+            for (int e0 = 0; e0 < npx; e0 += 8 * 64) {
+                float vv[8];
+                int pxs[8], pys[8];
+                bool use[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int e = e0 + j * 64 + lane;
+                    const int rr = e / side, c = e - rr * side;
+                    pxs[j] = bx0 + c;
+                    pys[j] = by0 + band + rr;
+                    const Real dx = (Real)(pxs[j] - cxi) - fx, dy = (Real)(pys[j] - cyi) - fy;
+                    const Real ax = fmax(fabs(dx) - (Real)0.5, (Real)0), ay = fmax(fabs(dy) - (Real)0.5, (Real)0);
+                    use[j] = e < npx && pxs[j] >= 0 && pxs[j] < d.W && pys[j] >= 0 && pys[j] < d.H &&
+                             ax * ax + ay * ay < rmax * rmax;
+                    vv[j] = use[j] ? load_px(d, pxs[j], pys[j]) : 0.0f;
                 }
 #pragma unroll
-                for (int q = 0; q < kMaxRadii; ++q) {
-                    if (q >= nr) break;
-                    const Real rq = (Real)a.radii[q];
-                    const Real w = pixel_area<Real>(dx, dy, rq, rq * rq);
-                    if (w != (Real)0) {
-                        sA[q].add(w);
-                        sS[q].add(w * m);
-                        if (a.want_err) sV[q].add(w * w * var);
+                for (int j = 0; j < 8; ++j) {
+                    if (!use[j]) continue;
+                    const int e = e0 + j * 64 + lane;
+                    const int rr = e / side, c = e - rr * side;
+                    const Real dx = (Real)(pxs[j] - cxi) - fx, dy = (Real)(pys[j] - cyi) - fy;
+                    const RowT<Real>& T = sh.tab[wv][rr * kApNix + sh.colp[wv][c]];
+                    const Real s = sh.cols[wv][c];
+                    const Real m = eval_M(T, s, (Real)vv[j]);
+                    Real var = 0;
+                    if (a.want_err) {
+                        const Real rr_ = eval_R(T, s);
+                        var = rr_ * rr_ + ((m > (Real)0) ? m * inv_gain : (Real)0);
+                    }
+                    const Real wo = pixel_area<Real>(dx, dy, rout, rout2);
+                    const Real wi = (rin > (Real)0) ? pixel_area<Real>(dx, dy, rin, rin2) : (Real)0;
+                    const Real wa = wo - wi;
+                    if (wa != (Real)0) {
+                        aA.add(wa);
+                        aS.add(wa * m);
+                    }
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) {
+                        const Real rq = (Real)a.radii[q];
+                        const Real w = pixel_area<Real>(dx, dy, rq, rq * rq);
+                        if (w != (Real)0) {
+                            sA[q].add(w);
+                            sS[q].add(w * m);
+                            if (a.want_err) sV[q].add(w * w * var);
+                        }
                     }
                 }
             }
@@ -228,8 +245,7 @@ __global__ __launch_bounds__(256) void k_aperture(const FrameDesc* __restrict__ 
         const bool any_trunc = xc - rm < -0.5 || xc + rm > (double)d.W - 0.5 || yc - rm < -0.5 ||
                                yc + rm > (double)d.H - 0.5;
 #pragma unroll
-        for (int q = 0; q < kMaxRadii; ++q) {
-            if (q >= nr) break;
+        for (int q = 0; q < NR; ++q) {
             const double A = sA[q].reduce(), S = sS[q].reduce();
             const double V = a.want_err ? sV[q].reduce() : 0.0;
             if (lane == 0) {
@@ -245,11 +261,26 @@ __global__ __launch_bounds__(256) void k_aperture(const FrameDesc* __restrict__ 
     }
 }
 
+template <typename Real>
+static void launch_ap_t(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int total_rows, int blocks,
+                        hipStream_t s) {
+    switch (a.nr) {
+        case 1: k_aperture<Real, 1><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
+        case 2: k_aperture<Real, 2><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
+        case 3: k_aperture<Real, 3><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
+        case 4: k_aperture<Real, 4><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
+        case 5: k_aperture<Real, 5><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
+        case 6: k_aperture<Real, 6><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
+        case 7: k_aperture<Real, 7><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
+        default: k_aperture<Real, 8><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
+    }
+}
+
 void launch_aperture(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int total_rows, int blocks,
                      bool f64, hipStream_t s) {
     if (total_rows <= 0) return;
-    if (f64) k_aperture<double><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows);
-    else k_aperture<float><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows);
+    if (f64) launch_ap_t<double>(desc, a, cat, total_rows, blocks, s);
+    else launch_ap_t<float>(desc, a, cat, total_rows, blocks, s);
 }
 
 }  // namespace gpk

@@ -56,12 +56,12 @@ struct CatOut {
     uint32_t* flags;
 };
 
-void launch_mesh_stats(const FrameDesc* desc, int nframes, int total_meshes, int max_area, BkgArgs a,
+void launch_mesh_stats(const FrameDesc* desc, int nframes, int total_meshes, int max_area, BkgArgs a, int cfg,
                        hipStream_t s);
 void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, int fsize, hipStream_t s);
 void launch_spline(const FrameDesc* desc, int nframes, int total_ycols, int total_xrows, hipStream_t s);
 void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
-void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, hipStream_t s);
+void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, int rad, hipStream_t s);
 void launch_merge(const DetWork& wk, int conn, int minarea, int persist_blocks, hipStream_t s);
 void launch_catalog(const DetWork& wk, const CatOut& cat, int minarea, int persist_blocks, int32_t* comp_status,
                     hipStream_t s);

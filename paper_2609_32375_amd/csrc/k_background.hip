@@ -22,22 +22,22 @@
 
 namespace gpk {
 
-constexpr int kBins = 2048;
+constexpr int kBins = 4096;
 constexpr int kList = 1024;
-constexpr int kMeshThreads = 256;
+constexpr int kMaxWaves = 16;     // up to 1024 threads per mesh
 
 struct MeshShared {
     uint32_t hist[kBins];
     float list[kList];
-    F2 pf[4][2];
-    int32_t pi[4];
-    float pmin[4], pmax[4];
-    uint32_t wsum[4];
+    F2 pf[kMaxWaves][2];
+    int32_t pi[kMaxWaves];
+    float pmin[kMaxWaves], pmax[kMaxWaves];
+    uint32_t wsum[kMaxWaves];
     int32_t sel_bin[2];
     uint32_t sel_cum[2];
     uint32_t cnt, kmin, kmax;
     float out[2];
-    int32_t ucnt[4];
+    int32_t ucnt[kMaxWaves];
 };
 
 __device__ __forceinline__ int bin_of(float v, float lo, float scale) {
@@ -46,7 +46,8 @@ __device__ __forceinline__ int bin_of(float v, float lo, float scale) {
     return (int)t;
 }
 
-// exclusive scan of one uint32 per thread over the 256-thread block
+// exclusive scan of one uint32 per thread over the block
+template <int NT>
 __device__ uint32_t block_exscan(uint32_t x, MeshShared& sh) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t incl = x;
@@ -63,17 +64,23 @@ __device__ uint32_t block_exscan(uint32_t x, MeshShared& sh) {
     return off + incl - x;
 }
 
+template <int NT>
 __device__ int block_sum_i(int x, MeshShared& sh) {
+    constexpr int NW = NT / 64;
     x = wave_sum_i(x);
     if ((threadIdx.x & 63) == 0) sh.ucnt[threadIdx.x >> 6] = x;
     __syncthreads();
-    int s = sh.ucnt[0] + sh.ucnt[1] + sh.ucnt[2] + sh.ucnt[3];
+    int s = 0;
+    for (int i = 0; i < NW; ++i) s += sh.ucnt[i];
     __syncthreads();
     return s;
 }
 
 // deterministic block reduction of two compensated sums, a count and min/max
+// (wavefront butterflies, then the wavefront partials in wavefront order)
+template <int NT>
 __device__ void block_stats(F2& a, F2& b, int& n, float& mn, float& mx, MeshShared& sh) {
+    constexpr int NW = NT / 64;
     const int w = threadIdx.x >> 6;
     a = wave_sum_f2(a);
     b = wave_sum_f2(b);
@@ -93,7 +100,7 @@ __device__ void block_stats(F2& a, F2& b, int& n, float& mn, float& mx, MeshShar
     n = sh.pi[0];
     mn = sh.pmin[0];
     mx = sh.pmax[0];
-    for (int i = 1; i < 4; ++i) {
+    for (int i = 1; i < NW; ++i) {
         a = f2_add(a, sh.pf[i][0]);
         b = f2_add(b, sh.pf[i][1]);
         n += sh.pi[i];
@@ -106,11 +113,11 @@ __device__ void block_stats(F2& a, F2& b, int& n, float& mn, float& mx, MeshShar
 // Values of ranks r1 <= r2 (0-based, r2 - r1 <= 1) among the alive pixels.
 // The histogram window [lo, hi] only steers the binning: bins are clamped, so
 // every alive pixel is counted and the selection is exact for any window.
-template <int PPT>
-__device__ void select_pair(const float (&v)[PPT], uint64_t alive, float lo, float hi, int r1, int r2,
+template <int NT, int PPT>
+__device__ void select_pair(const float (&v)[PPT], uint32_t alive, float lo, float hi, int r1, int r2,
                             float& o1, float& o2, MeshShared& sh) {
     const int tid = threadIdx.x;
-    for (int b = tid; b < kBins; b += kMeshThreads) sh.hist[b] = 0u;
+    for (int b = tid; b < kBins; b += NT) sh.hist[b] = 0u;
     if (tid == 0) {
         sh.cnt = 0u;
         sh.kmin = 0xffffffffu;
@@ -120,9 +127,9 @@ __device__ void select_pair(const float (&v)[PPT], uint64_t alive, float lo, flo
     const float scale = (hi > lo) ? (float)kBins / (hi - lo) : 0.0f;
 #pragma unroll
     for (int k = 0; k < PPT; ++k)
-        if ((alive >> k) & 1ull) atomicAdd(&sh.hist[bin_of(v[k], lo, scale)], 1u);
+        if ((alive >> k) & 1u) atomicAdd(&sh.hist[bin_of(v[k], lo, scale)], 1u);
     __syncthreads();
-    constexpr int per = kBins / kMeshThreads;  // 8 bins per thread
+    constexpr int per = kBins / NT;
     uint32_t c[per];
     uint32_t tot = 0;
 #pragma unroll
@@ -130,7 +137,7 @@ __device__ void select_pair(const float (&v)[PPT], uint64_t alive, float lo, flo
         c[q] = sh.hist[tid * per + q];
         tot += c[q];
     }
-    uint32_t pre = block_exscan(tot, sh);
+    uint32_t pre = block_exscan<NT>(tot, sh);
     const int rr[2] = {r1, r2};
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
@@ -153,7 +160,7 @@ __device__ void select_pair(const float (&v)[PPT], uint64_t alive, float lo, flo
     // gather the pixels of bins [b1, b2] (bins strictly between are empty)
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        if ((alive >> k) & 1ull) {
+        if ((alive >> k) & 1u) {
             int b = bin_of(v[k], lo, scale);
             if (b >= b1 && b <= b2) {
                 uint32_t s = atomicAdd(&sh.cnt, 1u);
@@ -174,7 +181,7 @@ __device__ void select_pair(const float (&v)[PPT], uint64_t alive, float lo, flo
         return;
     }
     if (m <= kList) {
-        for (int e = tid; e < m; e += kMeshThreads) {
+        for (int e = tid; e < m; e += NT) {
             float x = sh.list[e];
             int less = 0, eq = 0;
             for (int j2 = 0; j2 < m; ++j2) {
@@ -202,12 +209,12 @@ __device__ void select_pair(const float (&v)[PPT], uint64_t alive, float lo, flo
             int cnt = 0;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                if ((alive >> k) & 1ull) {
+                if ((alive >> k) & 1u) {
                     int b = bin_of(v[k], lo, scale);
                     cnt += (b >= b1 && b <= b2 && f2ord(v[k]) <= mid);
                 }
             }
-            cnt = block_sum_i(cnt, sh);
+            cnt = block_sum_i<NT>(cnt, sh);
             if (cnt > kk[t]) z = mid;
             else a = mid + 1;
         }
@@ -217,9 +224,8 @@ __device__ void select_pair(const float (&v)[PPT], uint64_t alive, float lo, flo
     o2 = res[1];
 }
 
-template <int PPT>
-__global__ __launch_bounds__(kMeshThreads) void k_mesh_stats(const FrameDesc* __restrict__ desc,
-                                                             int nframes, BkgArgs a) {
+template <int NT, int PPT>
+__global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__ desc, int nframes, BkgArgs a) {
     __shared__ MeshShared sh;
     const int tid = threadIdx.x;
     const int gm = blockIdx.x;
@@ -232,16 +238,16 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_stats(const FrameDesc* __
     const int n = w * h;
 
     float v[PPT];
-    uint64_t alive = 0ull;
+    uint32_t alive = 0u;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        int p = k * kMeshThreads + tid;
+        int p = k * NT + tid;
         v[k] = 0.0f;
         if (p < n) {
             int yy = p / w;
             int xx = p - yy * w;
             v[k] = load_px(d, x0 + xx, y0 + yy);
-            alive |= 1ull << k;
+            alive |= 1u << k;
         }
     }
     // pass 0: sigma0 of all pixels (sums shifted by the first pixel)
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_stats(const FrameDesc* __
     float mn = INFINITY, mx = -INFINITY;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        if ((alive >> k) & 1ull) {
+        if ((alive >> k) & 1u) {
             float dd = v[k] - c0;
             f2_acc(s1, dd);
             f2_acc(s2, dd * dd);
@@ -259,7 +265,7 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_stats(const FrameDesc* __
         }
     }
     int cnt = 0;
-    block_stats(s1, s2, cnt, mn, mx, sh);
+    block_stats<NT>(s1, s2, cnt, mn, mx, sh);
     const int out_idx = mj * d.nx + mi;
     if (mn == mx) {
         if (tid == 0) {
@@ -277,12 +283,11 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_stats(const FrameDesc* __
     double sig = sig0;
     int ncur = n;
 
-    // median of all pixels: it lies within one sigma of the mean
-    auto median_of = [&](uint64_t al, int nn, float lo, float hi, float& mh, float& ml) {
+    auto median_of = [&](uint32_t al, int nn, float lo, float hi, float& mh, float& ml) {
         int r2 = nn / 2;
         int r1 = (nn & 1) ? r2 : r2 - 1;
         float o1, o2;
-        select_pair<PPT>(v, al, lo, hi, r1, r2, o1, o2, sh);
+        select_pair<NT, PPT>(v, al, lo, hi, r1, r2, o1, o2, sh);
         if (r1 == r2) {
             mh = o1;
             ml = 0.0f;
@@ -294,23 +299,24 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_stats(const FrameDesc* __
             ml = 0.5f * e;
         }
     };
+    // the median of all pixels lies within one sigma of their mean
     float med_h, med_l;
     median_of(alive, ncur, (float)(mean - sig0), (float)(mean + sig0), med_h, med_l);
 
     int iters = 0;
     for (int it = 0; it < a.max_iter; ++it) {
         const float thr = (float)((double)a.clip * sig);
-        // clip pass: new set, its shifted sums and its histogram window
-        uint64_t nal = 0ull;
+        // clip pass: the new set and its shifted, compensated sums
+        uint32_t nal = 0u;
         F2 t1{0.f, 0.f}, t2{0.f, 0.f};
         float lmn = INFINITY, lmx = -INFINITY;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            if ((alive >> k) & 1ull) {
+            if ((alive >> k) & 1u) {
                 float dd = v[k] - med_h;
                 float dv = dd - med_l;
                 if (fabsf(dv) <= thr) {
-                    nal |= 1ull << k;
+                    nal |= 1u << k;
                     f2_acc(t1, dd);
                     f2_acc(t2, dd * dd);
                     lmn = fminf(lmn, v[k]);
@@ -318,10 +324,8 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_stats(const FrameDesc* __
                 }
             }
         }
-        int nn = 0;
-        // per-thread count
-        nn = __popcll(nal);
-        block_stats(t1, t2, nn, lmn, lmx, sh);
+        int nn = __popc(nal);
+        block_stats<NT>(t1, t2, nn, lmn, lmx, sh);
         ++iters;
         if (nn == ncur || nn == 0) break;
         alive = nal;
@@ -515,14 +519,19 @@ __global__ void k_spline_x(const FrameDesc* __restrict__ desc, int nframes, int 
 
 // ---------------------------------------------------------------------------
 // launchers
-void launch_mesh_stats(const FrameDesc* desc, int nframes, int total_meshes, int max_area, BkgArgs a,
+// cfg: 0 = automatic, 1 = 256 x 16, 2 = 512 x 16, 3 = 512 x 32, 4 = 1024 x 16
+// (threads x pixels per thread; the product must cover the largest mesh)
+void launch_mesh_stats(const FrameDesc* desc, int nframes, int total_meshes, int max_area, BkgArgs a, int cfg,
                        hipStream_t s) {
-    if (max_area <= 16 * kMeshThreads)
-        k_mesh_stats<16><<<total_meshes, kMeshThreads, 0, s>>>(desc, nframes, a);
-    else if (max_area <= 32 * kMeshThreads)
-        k_mesh_stats<32><<<total_meshes, kMeshThreads, 0, s>>>(desc, nframes, a);
-    else
-        k_mesh_stats<64><<<total_meshes, kMeshThreads, 0, s>>>(desc, nframes, a);
+    if (cfg == 0) cfg = (max_area <= 4096) ? 1 : (max_area <= 8192) ? 2 : 3;
+    if (cfg == 1 && max_area > 4096) cfg = 3;
+    if (cfg == 2 && max_area > 8192) cfg = 3;
+    switch (cfg) {
+        case 1: k_mesh_stats<256, 16><<<total_meshes, 256, 0, s>>>(desc, nframes, a); break;
+        case 2: k_mesh_stats<512, 16><<<total_meshes, 512, 0, s>>>(desc, nframes, a); break;
+        case 4: k_mesh_stats<1024, 16><<<total_meshes, 1024, 0, s>>>(desc, nframes, a); break;
+        default: k_mesh_stats<512, 32><<<total_meshes, 512, 0, s>>>(desc, nframes, a); break;
+    }
 }
 
 void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, int fsize, hipStream_t s) {

@@ -38,32 +38,38 @@ struct LocalRec {
     int32_t rootpix, pad;
 };
 
+// LDS regions are reused phase by phase:
+//   u1: row cubics (build M, R) -> horizontal pass -> labels + piece ids
+//   u2: M over tile + halo      -> piece records (M is then held in VGPRs)
 template <typename Real>
 struct DetShared {
     union U1 {
         RowT<Real> tab[kRegion * kNixMax];
         Real hs[kRegion * kTile];
-        LocalRec rec[kLocalRecs];
-    } u1;
-    union U2 {
-        Real ms[kRegion * (kRegion + 1)];
         struct {
             int32_t lab[kTile * kTile];
             int16_t comp[kTile * kTile];
         } l;
+    } u1;
+    union U2 {
+        Real ms[kRegion * (kRegion + 1)];
+        LocalRec rec[kLocalRecs];
     } u2;
-    int32_t colx[kRegion], rowy[kRegion], colp[kRegion];
-    Real cols[kRegion];
-    uint32_t wsum[4];
+    uint64_t rowmask[kTile];
+    int32_t rowoff[kTile + 1];
     int32_t misc[4];
 };
 
+// find with path halving: every link points to a smaller index, so writing a
+// grandparent over a parent only shortens the chain
 __device__ __forceinline__ int lds_find(int* L, int x) {
     volatile int* V = L;
     while (true) {
-        int q = V[x];
+        const int q = V[x];
         if (q == x) return x;
-        x = q;
+        const int g = V[q];
+        if (g != q) V[x] = g;
+        x = g;
     }
 }
 __device__ __forceinline__ void lds_union(int* L, int a, int b) {
@@ -138,9 +144,15 @@ struct RunAcc<double> {
     __device__ double u() const { return U; }
 };
 
-template <typename Real>
+// RAD >= 0: square rank-one kernel of radius RAD applied as two 1-D passes
+// (taps in registers, fully unrolled); RAD < 0: any kernel, applied densely.
+template <typename Real, int RAD>
 __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs* __restrict__ pa) {
     __shared__ DetShared<Real> sh;
+    constexpr bool kSep = RAD >= 0;
+    constexpr int kR = kSep ? RAD : 0;
+    constexpr bool kDbl = sizeof(Real) == 8;
+    constexpr int MS = kRegion + 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int gt = blockIdx.x;
     const int f = frame_of(wk.nframes, gt, [&](int i) { return wk.desc[i].tile_base; });
@@ -149,103 +161,110 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     const int tx = lt % d.ntx, ty = lt / d.ntx;
     const int x0 = tx * kTile, y0 = ty * kTile;
     const int tw = min(kTile, d.W - x0), th = min(kTile, d.H - y0);
-    const int kw = pa->kw, kh = pa->kh;
+    const int kw = kSep ? 2 * kR + 1 : pa->kw;
+    const int kh = kSep ? 2 * kR + 1 : pa->kh;
     const int rx = kw >> 1, ry = kh >> 1;
     const int RW = tw + 2 * rx, RH = th + 2 * ry;
     const int xs_lo = max(0, x0 - rx), xs_hi = min(d.W - 1, x0 + tw - 1 + rx);
     const int ixlo = piece_of(xs_lo, d.W, d.mw);
     const int nix = piece_of(xs_hi, d.W, d.mw) - ixlo + 1;
-    constexpr int MS = kRegion + 1;
 
-    // region column / row geometry
-    if (tid < RW) {
-        int xs = reflect_idx(x0 - rx + tid, d.W);
-        int ix = piece_of(xs, d.W, d.mw);
-        sh.colx[tid] = xs;
-        sh.colp[tid] = ix - ixlo;
-        sh.cols[tid] = (Real)((double)xs - piece_ref(ix, d.W, d.mw));
-    }
-    if (tid >= 128 && tid - 128 < RH) sh.rowy[tid - 128] = reflect_idx(y0 - ry + (tid - 128), d.H);
-    __syncthreads();
     // 1. per region row and x piece: the row's cubic (FP64 -> working precision)
     for (int e = tid; e < RH * nix; e += 256) {
-        int r = e / nix, pi = e - r * nix;
-        int ys = sh.rowy[r];
-        int jy = piece_of(ys, d.H, d.mh);
-        double u = (double)ys - piece_ref(jy, d.H, d.mh);
+        const int r = e / nix, pi = e - r * nix;
+        const int ys = reflect_idx(y0 - ry + r, d.H);
+        const int jy = piece_of(ys, d.H, d.mh);
+        const double u = (double)ys - piece_ref(jy, d.H, d.mh);
         sh.u1.tab[r * kNixMax + pi] = make_row<Real>(d.coef, d.nx, d.ny, ixlo + pi, jy, u);
     }
     __syncthreads();
-    // 2. M = I - B over tile + halo
-    for (int r = wv; r < RH; r += 4) {
-        const int ys = sh.rowy[r];
-        const RowT<Real>* trow = &sh.u1.tab[r * kNixMax];
-        for (int c = lane; c < RW; c += 64) {
-            Real v = (Real)load_px(d, sh.colx[c], ys);
-            sh.u2.ms[r * MS + c] = eval_M(trow[sh.colp[c]], sh.cols[c], v);
-        }
-    }
-    __syncthreads();
-    // 3. the 16 pixels this lane owns: column `lane`, rows 16*wv .. 16*wv+15
-    const bool colok = lane < tw;
-    Real Mo[16], To[16];
-    float Io[16];
-    const bool has_sat = pa->sat < INFINITY;
-    {
-        const Real th_s = (Real)pa->thresh;
-        const RowT<Real>* tb = sh.u1.tab;
-        const int cc = lane + rx;
-        const int cp = colok ? sh.colp[cc] : 0;
-        const Real cs = colok ? sh.cols[cc] : (Real)0;
+    // 2. M = I - B over tile + halo; lanes own region columns lane and lane + 64
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int ly = 16 * wv + k;
-            Mo[k] = 0;
-            To[k] = 0;
-            Io[k] = 0.f;
-            if (colok && ly < th) {
-                Mo[k] = sh.u2.ms[(ly + ry) * MS + cc];
-                To[k] = th_s * eval_R(tb[(ly + ry) * kNixMax + cp], cs);
-                if (has_sat) Io[k] = load_px(d, x0 + lane, y0 + ly);
+    for (int half = 0; half < 2; ++half) {
+        const int c = lane + 64 * half;
+        if (c < RW) {
+            const int xs = reflect_idx(x0 - rx + c, d.W);
+            const int ix = piece_of(xs, d.W, d.mw);
+            const int pc = ix - ixlo;
+            const Real sx = (Real)((double)xs - piece_ref(ix, d.W, d.mw));
+            // issue all of this column's loads before using any of them
+            constexpr int NR = (kRegion + 3) / 4;
+            float vals[NR];
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                const int r = wv + 4 * i;
+                vals[i] = (r < RH) ? load_px(d, xs, reflect_idx(y0 - ry + r, d.H)) : 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                const int r = wv + 4 * i;
+                if (r < RH) sh.u2.ms[r * MS + c] = eval_M(sh.u1.tab[r * kNixMax + pc], sx, (Real)vals[i]);
             }
         }
     }
+    // thresholds t R of the 16 pixels this lane owns: column `lane`, rows 16 wv ..
+    const bool colok = lane < tw;
+    Real To[16];
+    {
+        const Real ts = (Real)pa->thresh;
+        const int gx = colok ? x0 + lane : x0;
+        const int ix = piece_of(gx, d.W, d.mw);
+        const int pc = ix - ixlo;
+        const Real sx = (Real)((double)gx - piece_ref(ix, d.W, d.mw));
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int ly = 16 * wv + k;
+            To[k] = (colok && ly < th) ? ts * eval_R(sh.u1.tab[(ly + ry) * kNixMax + pc], sx) : (Real)0;
+        }
+    }
     __syncthreads();
-    // 4. matched filter
-    Real Fo[16];
-    const bool dbl = sizeof(Real) == 8;
-    if (pa->separable) {
-        for (int r = wv; r < RH; r += 4) {
-            if (colok) {
-                Real acc = 0;
+    // 3. matched filter; own M values move to VGPRs
+    Real Mo[16], Fo[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int ly = 16 * wv + k;
+        Mo[k] = (colok && ly < th) ? sh.u2.ms[(ly + ry) * MS + lane + rx] : (Real)0;
+    }
+    if constexpr (kSep) {
+        Real kx[2 * kR + 1], ky[2 * kR + 1];
+#pragma unroll
+        for (int b = 0; b <= 2 * kR; ++b) {
+            kx[b] = kDbl ? (Real)pa->kxd[b] : (Real)pa->kx[b];
+            ky[b] = kDbl ? (Real)pa->kyd[b] : (Real)pa->ky[b];
+        }
+        if (colok) {
+            for (int r = wv; r < RH; r += 4) {
                 const Real* mr = &sh.u2.ms[r * MS + lane];
-                for (int b = 0; b < kw; ++b) acc += (dbl ? (Real)pa->kxd[b] : (Real)pa->kx[b]) * mr[b];
+                Real acc = 0;
+#pragma unroll
+                for (int b = 0; b <= 2 * kR; ++b) acc = fma(kx[b], mr[b], acc);
                 sh.u1.hs[r * kTile + lane] = acc;
             }
         }
         __syncthreads();
-        Real win[16 + 2 * kMaxR];
-        const int nwin = 16 + 2 * ry;
-        for (int q = 0; q < nwin; ++q) {
-            int r = 16 * wv + q;
+        Real win[16 + 2 * kR];
+#pragma unroll
+        for (int q = 0; q < 16 + 2 * kR; ++q) {
+            const int r = 16 * wv + q;
             win[q] = (colok && r < RH) ? sh.u1.hs[r * kTile + lane] : (Real)0;
         }
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             Real acc = 0;
-            for (int aa = 0; aa < kh; ++aa) acc += (dbl ? (Real)pa->kyd[aa] : (Real)pa->ky[aa]) * win[k + aa];
+#pragma unroll
+            for (int a = 0; a <= 2 * kR; ++a) acc = fma(ky[a], win[k + a], acc);
             Fo[k] = acc;
         }
     } else {
-#pragma unroll 1
+#pragma unroll
         for (int k = 0; k < 16; ++k) {
             const int ly = 16 * wv + k;
             Real acc = 0;
             if (colok && ly < th) {
-                for (int aa = 0; aa < kh; ++aa) {
-                    const Real* mr = &sh.u2.ms[(ly + aa) * MS + lane];
+                for (int a = 0; a < kh; ++a) {
+                    const Real* mr = &sh.u2.ms[(ly + a) * MS + lane];
                     for (int b = 0; b < kw; ++b)
-                        acc += (dbl ? (Real)pa->kdd[aa * kw + b] : (Real)pa->kd[aa * kw + b]) * mr[b];
+                        acc = fma(kDbl ? (Real)pa->kdd[a * kw + b] : (Real)pa->kd[a * kw + b], mr[b], acc);
                 }
             }
             Fo[k] = acc;
@@ -263,34 +282,59 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
         if (tid == 0) wk.tiles[gt] = TileInfo{-1, 0};
         if (seg && colok) {
             for (int k = 0; k < 16; ++k) {
-                int ly = 16 * wv + k;
+                const int ly = 16 * wv + k;
                 if (ly < th) seg[(int64_t)(y0 + ly) * d.W + x0 + lane] = -1;
             }
         }
         return;
     }
-    // 5. connected components inside the tile (LDS union-find)
-    int32_t* lab = sh.u2.l.lab;
-    int16_t* comp = sh.u2.l.comp;
+    // 4. connected components inside the tile.  A tile row is one wavefront
+    //    (lane = column), so each row's mask is one ballot.  Pixels start
+    //    labelled with the first pixel of their horizontal run; runs of
+    //    adjacent rows are then united once per touching pair, in an LDS
+    //    union-find whose roots are the smallest raster index of each
+    //    component.
+    int32_t* lab = sh.u1.l.lab;
+    int16_t* comp = sh.u1.l.comp;
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));   // lanes < lane
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        const int p = (16 * wv + k) * kTile + lane;
-        lab[p] = ((mbits >> k) & 1u) ? p : -1;
+        const uint64_t m = __ballot((mbits >> k) & 1u);
+        if (lane == 0) sh.rowmask[16 * wv + k] = m;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int ly = 16 * wv + k;
+        const int p = ly * kTile + lane;
+        int v = -1;
+        if ((mbits >> k) & 1u) {
+            const uint64_t zb = ~sh.rowmask[ly] & below;
+            const int s0 = zb ? 64 - __clzll(zb) : 0;
+            v = ly * kTile + s0;
+        }
+        lab[p] = v;
     }
     __syncthreads();
     const bool conn8 = pa->conn == 8;
 #pragma unroll 1
     for (int k = 0; k < 16; ++k) {
-        if (!((mbits >> k) & 1u)) continue;
         const int ly = 16 * wv + k;
+        if (!((mbits >> k) & 1u) || ly == 0) continue;
+        const uint64_t m = sh.rowmask[ly], mu = sh.rowmask[ly - 1];
         const int p = ly * kTile + lane;
-        if (lane > 0 && lab[p - 1] >= 0) lds_union(lab, p, p - 1);
-        if (ly > 0) {
-            if (lab[p - kTile] >= 0) lds_union(lab, p, p - kTile);
-            if (conn8) {
-                if (lane > 0 && lab[p - kTile - 1] >= 0) lds_union(lab, p, p - kTile - 1);
-                if (lane + 1 < tw && lab[p - kTile + 1] >= 0) lds_union(lab, p, p - kTile + 1);
-            }
+        const uint64_t zb = ~m & below;
+        const int a0 = zb ? 64 - __clzll(zb) : 0;                     // run start
+        const uint64_t za = (lane == 63) ? 0ull : (~m & ((~0ull) << (lane + 1)));
+        const int a1 = za ? __ffsll((long long)za) - 2 : 63;            // run end
+        const bool up = (mu >> lane) & 1ull;
+        const bool upl = lane > 0 && ((mu >> (lane - 1)) & 1ull);
+        const bool upr = lane < 63 && ((mu >> (lane + 1)) & 1ull);
+        // one union per pair of touching runs: at the first column of their overlap
+        if (up && (lane == a0 || !upl)) lds_union(lab, p, p - kTile);
+        if (conn8) {
+            if (lane == a0 && upl) lds_union(lab, p, p - kTile - 1);
+            if (lane == a1 && upr && !up) lds_union(lab, p, p - kTile + 1);
         }
     }
     __syncthreads();
@@ -302,29 +346,26 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
         }
     }
     __syncthreads();
-    // number roots in raster order: thread t scans raster pixels [16t, 16t+16)
-    uint32_t nroot = 0;
-    for (int q = 0; q < 16; ++q) {
-        int p = tid * 16 + q;
-        nroot += (lab[p] == p);
-    }
-    uint32_t incl = nroot;
+    // roots in raster order: per-row ballots, then a prefix over the 64 rows
+    uint64_t rb[16];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
+    for (int k = 0; k < 16; ++k) {
+        const int p = (16 * wv + k) * kTile + lane;
+        rb[k] = __ballot(((mbits >> k) & 1u) && lab[p] == p);
+        if (lane == 0) sh.rowoff[16 * wv + k + 1] = __popcll(rb[k]);
     }
-    if (lane == 63) sh.wsum[wv] = incl;
     __syncthreads();
-    uint32_t off = 0;
-    for (int i = 0; i < wv; ++i) off += sh.wsum[i];
-    const int ncomp = (int)(sh.wsum[0] + sh.wsum[1] + sh.wsum[2] + sh.wsum[3]);
-    {
-        int idx = (int)(off + incl - nroot);
-        for (int q = 0; q < 16; ++q) {
-            int p = tid * 16 + q;
-            if (lab[p] == p) comp[p] = (int16_t)(idx++);
-        }
+    if (tid == 0) {
+        sh.rowoff[0] = 0;
+        for (int y = 1; y <= kTile; ++y) sh.rowoff[y] += sh.rowoff[y - 1];
+    }
+    __syncthreads();
+    const int ncomp = sh.rowoff[kTile];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int ly = 16 * wv + k;
+        const int p = ly * kTile + lane;
+        if ((rb[k] >> lane) & 1ull) comp[p] = (int16_t)(sh.rowoff[ly] + __popcll(rb[k] & below));
     }
     __syncthreads();
     int co[16];
@@ -336,7 +377,8 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 16; ++k) comp[(16 * wv + k) * kTile + lane] = (int16_t)co[k];
-    // 6. records for the tile's pieces
+    // 5. records for the tile's pieces (LDS for the first kLocalRecs, in u2,
+    //    now free: M lives in VGPRs)
     if (tid == 0) {
         int base = (int)atomicAdd(&wk.counters[0], (uint32_t)ncomp);
         if ((int64_t)base + ncomp > (int64_t)wk.rec_cap) {
@@ -355,7 +397,7 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     for (int c = tid; c < ncomp; c += 256) {
         wk.parent[base + c] = base + c;
         if (c < kLocalRecs) {
-            LocalRec& R = sh.u1.rec[c];
+            LocalRec& R = sh.u2.rec[c];
             for (int z = 0; z < 12; ++z) R.s[z] = 0.0;
             R.xmin = R.ymin = 0x7fffffff;
             R.xmax = R.ymax = -1;
@@ -373,20 +415,38 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
             R.y0 = y0;
         }
     }
+    // border labels for the merge, and the per-pixel piece ids
+    int16_t* E = wk.edges + (size_t)gt * 4 * kTile;
+    if (tid < 64) {
+        E[0 * kTile + tid] = (tid < tw) ? comp[0 * kTile + tid] : (int16_t)-1;
+        E[1 * kTile + tid] = (tid < tw) ? comp[(th - 1) * kTile + tid] : (int16_t)-1;
+    } else if (tid < 128) {
+        const int r = tid - 64;
+        E[2 * kTile + r] = (r < th) ? comp[r * kTile + 0] : (int16_t)-1;
+        E[3 * kTile + r] = (r < th) ? comp[r * kTile + tw - 1] : (int16_t)-1;
+    }
+    if (seg && colok) {
+        for (int k = 0; k < 16; ++k) {
+            const int ly = 16 * wv + k;
+            if (ly < th) seg[(int64_t)(y0 + ly) * d.W + x0 + lane] = co[k];
+        }
+    }
     __syncthreads();
     // first pixel of every piece = its root
-    for (int q = 0; q < 16; ++q) {
-        int p = tid * 16 + q;
-        if (lab[p] == p) {
-            int c = comp[p];
-            uint32_t pm = (uint32_t)((y0 + p / kTile) * d.W + x0 + (p % kTile));
-            if (c < kLocalRecs) sh.u1.rec[c].rootpix = (int32_t)pm;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if ((rb[k] >> lane) & 1ull) {
+            const int ly = 16 * wv + k;
+            const int c = co[k];
+            const uint32_t pm = (uint32_t)((y0 + ly) * d.W + x0 + lane);
+            if (c < kLocalRecs) sh.u2.rec[c].rootpix = (int32_t)pm;
             else wk.recs[base + c].pmin = pm;
         }
     }
-    // 7. moments: column runs, compensated, flushed into the piece records
+    // 6. moments: column runs, compensated, flushed into the piece records
     {
         const float sat = pa->sat;
+        const bool has_sat = sat < INFINITY;
         const int gx = x0 + lane;
         RunAcc<Real> run;
         run.reset();
@@ -401,16 +461,9 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
             const double add[12] = {S, dxd * S, T, dxd * dxd * S, U, dxd * T,
                                     n, dxd * n, sy, dxd * dxd * n, syy, dxd * sy};
             if (loc) {
-                double* s = sh.u1.rec[cur].s;
+                LocalRec& R = sh.u2.rec[cur];
 #pragma unroll
-                for (int z = 0; z < 12; ++z) atomicAdd(&s[z], add[z]);
-            } else {
-                double* s = wk.recs[base + cur].s;
-#pragma unroll
-                for (int z = 0; z < 12; ++z) unsafeAtomicAdd(&s[z], add[z]);
-            }
-            if (loc) {
-                LocalRec& R = sh.u1.rec[cur];
+                for (int z = 0; z < 12; ++z) atomicAdd(&R.s[z], add[z]);
                 atomicMin(&R.xmin, gx);
                 atomicMax(&R.xmax, gx);
                 atomicMin(&R.ymin, y0 + ry0);
@@ -419,6 +472,8 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
                 if (rfl) atomicOr(&R.flags, rfl);
             } else {
                 CompRec& R = wk.recs[base + cur];
+#pragma unroll
+                for (int z = 0; z < 12; ++z) unsafeAtomicAdd(&R.s[z], add[z]);
                 atomicMin(&R.xmin, gx);
                 atomicMax(&R.xmax, gx);
                 atomicMin(&R.ymin, y0 + ry0);
@@ -448,45 +503,28 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
                 rcnt += 1;
                 rdy += ly;
                 rdy2 += ly * ly;
-                const float mf = (float)Mo[k];
-                rpk = fmaxf(rpk, mf);
-                if (Io[k] >= sat) rfl |= kFlagSat;
+                rpk = fmaxf(rpk, (float)Mo[k]);
+                if (has_sat && load_px(d, gx, y0 + ly) >= sat) rfl |= kFlagSat;
             }
         }
         if (cur >= 0) flush();
     }
     __syncthreads();
-    // 8. publish the LDS records
+    // 7. publish the LDS records
     for (int c = tid; c < nloc; c += 256) {
-        const LocalRec& L = sh.u1.rec[c];
+        const LocalRec& Lr = sh.u2.rec[c];
         CompRec& R = wk.recs[base + c];
-        for (int z = 0; z < 12; ++z) R.s[z] = L.s[z];
-        R.xmin = L.xmin;
-        R.xmax = L.xmax;
-        R.ymin = L.ymin;
-        R.ymax = L.ymax;
-        R.pmin = (uint32_t)L.rootpix;
-        R.peak = L.peak;
-        R.flags = L.flags;
+        for (int z = 0; z < 12; ++z) R.s[z] = Lr.s[z];
+        R.xmin = Lr.xmin;
+        R.xmax = Lr.xmax;
+        R.ymin = Lr.ymin;
+        R.ymax = Lr.ymax;
+        R.pmin = (uint32_t)Lr.rootpix;
+        R.peak = Lr.peak;
+        R.flags = Lr.flags;
         R.frame = f;
         R.x0 = x0;
         R.y0 = y0;
-    }
-    // 9. border labels for the merge
-    int16_t* E = wk.edges + (size_t)gt * 4 * kTile;
-    if (tid < 64) {
-        E[0 * kTile + tid] = (tid < tw) ? comp[0 * kTile + tid] : (int16_t)-1;
-        E[1 * kTile + tid] = (tid < tw) ? comp[(th - 1) * kTile + tid] : (int16_t)-1;
-    } else if (tid < 128) {
-        const int r = tid - 64;
-        E[2 * kTile + r] = (r < th) ? comp[r * kTile + 0] : (int16_t)-1;
-        E[3 * kTile + r] = (r < th) ? comp[r * kTile + tw - 1] : (int16_t)-1;
-    }
-    if (seg && colok) {
-        for (int k = 0; k < 16; ++k) {
-            int ly = 16 * wv + k;
-            if (ly < th) seg[(int64_t)(y0 + ly) * d.W + x0 + lane] = co[k];
-        }
     }
     if (tid == 0) wk.tiles[gt] = TileInfo{base, ncomp};
 }
@@ -773,9 +811,26 @@ void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
     k_fill_u32<<<blocks, 256, 0, s>>>(p, n, v);
 }
 
-void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, hipStream_t s) {
-    if (f64) k_detect_tiles<double><<<wk.total_tiles, 256, 0, s>>>(wk, args);
-    else k_detect_tiles<float><<<wk.total_tiles, 256, 0, s>>>(wk, args);
+template <typename Real>
+static void launch_detect_t(const DetWork& wk, const DetArgs* args, int rad, hipStream_t s) {
+    const int g = wk.total_tiles;
+    switch (rad) {
+        case 0: k_detect_tiles<Real, 0><<<g, 256, 0, s>>>(wk, args); break;
+        case 1: k_detect_tiles<Real, 1><<<g, 256, 0, s>>>(wk, args); break;
+        case 2: k_detect_tiles<Real, 2><<<g, 256, 0, s>>>(wk, args); break;
+        case 3: k_detect_tiles<Real, 3><<<g, 256, 0, s>>>(wk, args); break;
+        case 4: k_detect_tiles<Real, 4><<<g, 256, 0, s>>>(wk, args); break;
+        case 5: k_detect_tiles<Real, 5><<<g, 256, 0, s>>>(wk, args); break;
+        case 6: k_detect_tiles<Real, 6><<<g, 256, 0, s>>>(wk, args); break;
+        case 7: k_detect_tiles<Real, 7><<<g, 256, 0, s>>>(wk, args); break;
+        default: k_detect_tiles<Real, -1><<<g, 256, 0, s>>>(wk, args); break;
+    }
+}
+
+// rad: radius of a square rank-one kernel (two 1-D passes), -1 for the dense path
+void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, int rad, hipStream_t s) {
+    if (f64) launch_detect_t<double>(wk, args, rad, s);
+    else launch_detect_t<float>(wk, args, rad, s);
 }
 
 void launch_merge(const DetWork& wk, int conn, int minarea, int persist_blocks, hipStream_t s) {

@@ -61,6 +61,7 @@ struct gp_ctx {
     std::vector<hipEvent_t> pool;
     std::map<std::string, std::pair<double, int64_t>> totals;
     std::string tune_path;
+    int mesh_cfg = 0;  // launch shape of the mesh-statistics kernel (0 = automatic)
 };
 
 namespace {
@@ -459,7 +460,7 @@ extern "C" gp_status gp_background(gp_ctx* ctx, const gp_frame* frames, int32_t 
         BkgArgs a{bp->clip_sigma, bp->crowd_tol, bp->mode_a, bp->mode_b, bp->max_iter, bp->filter_size};
         {
             ProfScope ps(ctx, s, "mesh_stats");
-            launch_mesh_stats(desc, nframes, (int)P.total_meshes, P.max_area, a, s);
+            launch_mesh_stats(desc, nframes, (int)P.total_meshes, P.max_area, a, ctx->mesh_cfg, s);
         }
         HIP_TRY(hipGetLastError());
         {
@@ -586,7 +587,8 @@ extern "C" gp_status gp_detect(gp_ctx* ctx, const gp_frame* frames, int32_t nfra
     const bool f64 = dp->precision == GP_PREC_F64;
     {
         ProfScope ps(ctx, s, "detect_tiles");
-        launch_detect_tiles(wk, dargs, f64, s);
+        const int rad = (in.separable && dp->kw == dp->kh) ? dp->kw / 2 : -1;
+        launch_detect_tiles(wk, dargs, f64, rad, s);
     }
     HIP_TRY(hipGetLastError());
     const int persist = ctx->cus * 4;
