@@ -7,7 +7,7 @@ the 6144 x 6144 float32 field (20,000 Moffat stars, mesh 128, 9x9 Gaussian
 filter, threshold 1.5 sigma, minarea 5, 8-connected, apertures 3/6/9 px,
 annulus 13-18 px).  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--forms]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-forms]
 """
 from __future__ import annotations
 
@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-crop", type=int, default=3072, help="side of the CPU-baseline crop")
-    ap.add_argument("--forms", action="store_true", help="also time the graph-captured form")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and served forms")
+    ap.add_argument("--stream-seconds", type=float, default=10.0, help="length of the Poisson arrival stream")
     ap.add_argument("--profile-steps", type=int, default=5)
     return ap.parse_args()
 
@@ -150,33 +151,136 @@ def main():
         "kernels_ms": {k: round(v, 4) for k, v in kern.items()},
         "roofline": roof,
     }
-    if a.forms:
-        # the same three calls captured once into a HIP graph and replayed
-        g = torch.cuda.CUDAGraph()
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            step()
-        torch.cuda.current_stream().wait_stream(s)
-        torch.cuda.synchronize()
-        with torch.cuda.graph(g):
-            step()
-        for _ in range(a.warmup):
-            g.replay()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(a.steps):
-            g.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        gms = e0.elapsed_time(e1) / a.steps
+    if not a.no_forms:
+        gms = graph_time(torch, step, a.steps, a.warmup)
         out["forms"] = {"plain": {"mp_s": round(value, 1), "ms": round(ms, 4)},
                         "graph": {"mp_s": round(mp / (gms / 1e3), 1), "ms": round(gms, 4)}}
+        ph.close()
+        del ph, dev
+        torch.cuda.empty_cache()
+        out["forms"]["batched"] = form_batched(torch, a)
+        torch.cuda.empty_cache()
+        out["forms"]["served"] = form_served(torch, a)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(fr, a.cpu_crop)
     print(json.dumps(out), flush=True)
+
+
+def graph_time(torch, step, steps, warmup):
+    """ms per replay of the step captured once into a HIP graph."""
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        step()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def form_batched(torch, a):
+    """The 64-frame uneven uint16 batch: one graph replay of the three calls over
+    all frames vs. the same frames through per-frame calls (sync after each)."""
+    from paper_2609_32375_amd.pipeline import Photometry
+    from synth import batch_shapes, config_params, render_gpu
+    t0 = time.time()
+    shapes = batch_shapes()
+    frames = [render_gpu(w, h, n, seed) for (w, h, n, seed) in shapes]
+    torch.cuda.synchronize()
+    log(f"batch: {len(frames)} frames rendered in {time.time() - t0:.1f}s")
+    p = config_params("c1")
+    K = p.kernel()
+    mp = sum(f.shape[0] * f.shape[1] for f in frames) / 1e6
+    batch = Photometry(frames, p, K, capacity=65536)
+    bms = graph_time(torch, batch.run, max(3, a.steps // 4), 2)
+    nobj = [batch.results(i)["n_obj"] for i in range(len(frames))]
+    batch.close()
+    del batch
+    torch.cuda.empty_cache()
+    singles = [Photometry([f], p, K, capacity=65536) for f in frames]
+    for s in singles:
+        s.run()
+    torch.cuda.synchronize()
+    reps = max(2, a.steps // 8)
+    t = time.perf_counter()
+    for _ in range(reps):
+        for s in singles:
+            s.run()
+            torch.cuda.synchronize()
+    pms = (time.perf_counter() - t) * 1e3 / reps
+    for s in singles:
+        s.close()
+    del singles
+    log(f"batched: {bms:.2f} ms ({mp / bms * 1e3:.0f} MP/s); plain per-frame: {pms:.2f} ms ({mp / pms * 1e3:.0f} MP/s)")
+    return {"workload": "64 uint16 frames: 24 x 2048^2, 24 x 4096^2, 16 x 9600x6400; c1 parameters",
+            "mp": round(mp, 2), "objects": int(sum(nobj)), "ms": round(bms, 3), "mp_s": round(mp / bms * 1e3, 1),
+            "plain_ms": round(pms, 3), "plain_mp_s": round(mp / pms * 1e3, 1),
+            "speedup_vs_plain": round(pms / bms, 3)}
+
+
+def form_served(torch, a):
+    """Mixed 4.2 / 37.7 / 151.3 MP uint16 requests, device-resident, each with
+    its shape's parameters: (i) all queued at once (saturating) vs the same
+    requests through per-frame calls; (ii) Poisson arrivals at 4 /s: p50/p99."""
+    from paper_2609_32375_amd.pipeline import Photometry
+    from paper_2609_32375_amd.serve import Request, Server, latency_stats
+    from synth import arrival_stream, config_params, render_gpu
+    shp = {"c1": (2048, 2048, 300), "c2": (6144, 6144, 20000), "c3": (12300, 12300, 134000)}
+    pools, params, kernels = {}, {}, {}
+    for kname, (w, h, n) in shp.items():
+        pools[kname] = [render_gpu(w, h, n, 3000 + 10 * list(shp).index(kname) + j) for j in range(3)]
+        params[kname] = config_params(kname)
+        kernels[kname] = params[kname].kernel()
+    torch.cuda.synchronize()
+    cap = 262144
+    times, kinds = arrival_stream(rate=4.0, duration=a.stream_seconds)
+    reqs_of = lambda arr: [Request(i, pools[k][i % 3], arrival=t, params=params[k], kernel=kernels[k])
+                           for i, (t, k) in enumerate(zip(arr, kinds))]
+    mp = sum(pools[k][0].shape[0] * pools[k][0].shape[1] for k in kinds) / 1e6
+    srv = Server(params["c1"], kernels["c1"], capacity=cap, slots=8, streams=2)
+    srv.run(reqs_of(np.zeros(len(kinds))))           # warm-up (allocator, code objects)
+    t = time.perf_counter()
+    done = srv.run(reqs_of(np.zeros(len(kinds))))
+    sat_s = time.perf_counter() - t
+    sat_lat = latency_stats(done)
+    # plain: the same requests one at a time
+    plain = {k: Photometry([pools[k][0]], params[k], kernels[k], capacity=cap) for k in shp}
+    for k in shp:
+        plain[k].run()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i, k in enumerate(kinds):
+        plain[k].rebind([pools[k][i % 3]])
+        plain[k].run()
+        torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t
+    for k in shp:
+        plain[k].close()
+    # open loop at the arrival rate
+    done = srv.run(reqs_of(times))
+    open_lat = latency_stats(done)
+    srv.close()
+    log(f"served: saturating {mp / sat_s:.0f} MP/s vs plain {mp / plain_s:.0f} MP/s; open-loop {open_lat}")
+    return {"workload": f"{len(kinds)} requests, shapes uniform over 2048^2 / 6144^2 / 12300^2 uint16, "
+                        f"device-resident, Poisson 4/s over {a.stream_seconds:.0f} s",
+            "mp": round(mp, 1), "saturating_mp_s": round(mp / sat_s, 1), "plain_mp_s": round(mp / plain_s, 1),
+            "speedup_vs_plain": round(plain_s / sat_s, 3),
+            "saturating_p50_ms": round(sat_lat.get("p50_ms", 0), 2),
+            "saturating_p99_ms": round(sat_lat.get("p99_ms", 0), 2),
+            "p50_ms": round(open_lat.get("p50_ms", 0), 2), "p99_ms": round(open_lat.get("p99_ms", 0), 2),
+            "slots": 8, "streams": 2}
 
 
 def cpu_baseline(fr, side):

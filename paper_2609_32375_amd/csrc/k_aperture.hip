@@ -1,15 +1,14 @@
 // k_aperture.hip -- circular aperture photometry with exact pixel/disk overlap.
 //
-// One wavefront per catalogued object.  The object's box (every pixel the
-// outer circle can touch) is walked in row bands of 16: the band's background
-// and noise-map cubics are built in LDS (FP64 -> working precision), then each
-// lane takes pixels of the band, forms M = I - B, and for every circle (the
-// aperture radii, r_in and r_out) the exact area of the circle inside the
-// pixel.  Pixels wholly inside or outside a circle take 1 or 0 directly; the
-// rest use a cancellation-free formula: clipped rectangle + trapezoid under the
-// chord + circular segment (theta - sin theta by series for small angles).
-// Sums are compensated per lane and reduced across the wavefront in a fixed
-// order, so an object's result does not depend on what else runs.
+// One wavefront per catalogued object.  The rows of the object's box are taken
+// in bands of 16: the band's background and noise-map cubics are built in LDS
+// (FP64 -> working precision), the pixels the outer circle can touch are
+// numbered run by run and spread over the lanes, and each lane forms M = I - B
+// for its pixels and classifies them against every circle (the aperture radii,
+// r_in and r_out).  Pixels wholly inside or outside a circle take weight 1 or
+// 0; the rest get the exact area of the circle inside the pixel from a
+// cancellation-free formula: clipped rectangle + trapezoid under the chord +
+// circular segment (theta - sin theta by series for small angles).
 //
 // The paper measures fluxes in circular apertures of several radii with the
 // variance propagated through the same weights and float64 accumulation; the
@@ -20,7 +19,6 @@
 namespace gpk {
 
 constexpr int kApBand = 16;    // rows per band
-constexpr int kApNix = 12;     // x pieces a box can touch (box <= 132 px, mesh >= 16)
 constexpr int kApBox = 2 * 66; // widest box (r <= 64)
 constexpr int kApWaves = 4;
 
@@ -107,39 +105,92 @@ __device__ __forceinline__ Real pixel_area(Real dx, Real dy, Real r, Real r2) {
     return a;
 }
 
-template <typename Real>
-struct Acc;
-template <>
-struct Acc<float> {
-    F2 v;
-    __device__ void zero() { v = F2{0.f, 0.f}; }
-    __device__ void add(float x) { f2_acc(v, x); }
-    __device__ double reduce() { return f2_d(wave_sum_f2(v)); }
-};
-template <>
-struct Acc<double> {
-    double v;
-    __device__ void zero() { v = 0.0; }
-    __device__ void add(double x) { v += x; }
-    __device__ double reduce() { return wave_sum_d(v); }
-};
+constexpr int kApList = 128;   // queued (pixel, circle) cuts per wavefront
+constexpr int kApUnroll = 4;   // pixels per lane in flight
 
 template <typename Real>
-struct ApShared {
-    RowT<Real> tab[kApWaves][kApBand * kApNix];
-    int32_t colp[kApWaves][kApBox];
-    Real cols[kApWaves][kApBox];
+struct ApEntry {
+    Real dx, dy, m, var;
+    int32_t j;
 };
 
-template <typename Real, int NR>
+// Per-wavefront LDS layout (dynamic shared memory; the host sizes it from the
+// number of spline pieces a box can touch).  Bin sums are per lane, bin-major,
+// so a lane's read-modify-write of its bin never conflicts with another lane.
+template <typename Real, int NC>
+struct ApLayout {
+    int o_s, o_a, o_v, o_colp, o_cols, o_rxl, o_roff, o_tab, o_list, o_rad, bytes;
+    __host__ __device__ ApLayout(int band, int nixmax) {
+        int o = 0;
+        auto take = [&](int n, int al) {
+            o = (o + al - 1) / al * al;
+            const int r = o;
+            o += n;
+            return r;
+        };
+        o_s = take(NC * 64 * 8, 16);
+        o_a = take(NC * 64 * (int)sizeof(Real), 16);
+        o_v = take(NC * 64 * (int)sizeof(Real), 16);
+        o_colp = take(kApBox * 4, 16);
+        o_cols = take(kApBox * (int)sizeof(Real), 16);
+        o_rxl = take(band * 4, 16);
+        o_roff = take((band + 1) * 4, 16);
+        o_tab = take(band * nixmax * (int)sizeof(RowT<Real>), 16);
+        o_list = take(kApList * (int)sizeof(ApEntry<Real>), 16);
+        o_rad = take(NC * (int)sizeof(Real), 16);
+        bytes = (o + 15) / 16 * 16;
+    }
+};
+
+// Circles: the aperture radii, r_in and r_out, sorted by radius on the host
+// (a.crad / a.crole).  Circles are nested, so a pixel lies wholly inside every
+// circle from some index kin on, wholly outside those before kout, and only
+// the circles in [kout, kin) cut it (usually none or one).  A wholly-inside
+// pixel adds (M, 1, var) to bin kin; the circle sums are prefix sums over the
+// bins.  A cut pixel is queued and, in a compacted lane-parallel pass, adds
+// its exact weight w as (w M, w, w^2 var) to bin j and subtracts it from bin
+// j + 1, so that only circle j sees it.
+//
+// Only the pixels the outer circle can touch are visited: each row of the box
+// contributes the run of columns within half a pixel plus the chord of the
+// outer circle, and the runs of a band of rows are numbered consecutively and
+// spread over the lanes.  Sums are kept per lane (FP64 for the flux) and
+// reduced in a fixed order, so an object's result does not depend on what else
+// runs.
+template <typename Real, int NC>
 __global__ __launch_bounds__(256) void k_aperture(const FrameDesc* __restrict__ desc, ApArgs a, ApCat cat,
-                                                  int total_rows) {
-    __shared__ ApShared<Real> sh;
+                                                  int total_rows, int band, int nixmax) {
+    extern __shared__ __align__(16) unsigned char ap_dyn[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    constexpr int nr = NR;
-    const Real rmax = (Real)a.rmax;
+    const ApLayout<Real, NC> L(band, nixmax);
+    unsigned char* base = ap_dyn + (size_t)wv * L.bytes;
+    double* binS = (double*)(base + L.o_s);
+    Real* binA = (Real*)(base + L.o_a);
+    Real* binV = (Real*)(base + L.o_v);
+    int32_t* colp = (int32_t*)(base + L.o_colp);
+    Real* cols = (Real*)(base + L.o_cols);
+    int32_t* rxl = (int32_t*)(base + L.o_rxl);
+    int32_t* roff = (int32_t*)(base + L.o_roff);
+    RowT<Real>* tab = (RowT<Real>*)(base + L.o_tab);
+    ApEntry<Real>* list = (ApEntry<Real>*)(base + L.o_list);
+    Real* rad = (Real*)(base + L.o_rad);
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+
+    Real cr[NC], cr2[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        cr[j] = (Real)a.crad[j];
+        cr2[j] = cr[j] * cr[j];
+    }
+    const Real rmax = cr[NC - 1], rmax2 = cr2[NC - 1];
     const int R = (int)ceilf(a.rmax) + 1;
     const int side = 2 * R + 2;
+    const Real inv_gain = (a.gain > 0.f) ? (Real)1 / (Real)a.gain : (Real)0;
+    // radius by circle index for the cut-pixel pass (a lane-varying index)
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+        if (lane == j) rad[j] = cr[j];
+
     for (int row = blockIdx.x * kApWaves + wv; row < total_rows; row += gridDim.x * kApWaves) {
         const int f = row / a.capacity, k = row - f * a.capacity;
         const int nobj = min(cat.n_obj[f], a.capacity);
@@ -149,138 +200,280 @@ __global__ __launch_bounds__(256) void k_aperture(const FrameDesc* __restrict__ 
         const int cxi = (int)floor(xc), cyi = (int)floor(yc);
         const Real fx = (Real)(xc - (double)cxi), fy = (Real)(yc - (double)cyi);
         const int bx0 = cxi - R, by0 = cyi - R;
-        // columns of the box inside the frame and their spline pieces
         const int cx_lo = max(bx0, 0), cx_hi = min(bx0 + side - 1, d.W - 1);
         const int ixlo = (cx_lo <= cx_hi) ? piece_of(cx_lo, d.W, d.mw) : 0;
-        const int nix = (cx_lo <= cx_hi) ? piece_of(cx_hi, d.W, d.mw) - ixlo + 1 : 0;
+        const int nix = (cx_lo <= cx_hi) ? min(piece_of(cx_hi, d.W, d.mw) - ixlo + 1, nixmax) : 0;
         wave_sync();
         for (int c = lane; c < side; c += 64) {
             const int px = bx0 + c;
             if (px >= 0 && px < d.W) {
                 const int ix = piece_of(px, d.W, d.mw);
-                sh.colp[wv][c] = ix - ixlo;
-                sh.cols[wv][c] = (Real)((double)px - piece_ref(ix, d.W, d.mw));
+                colp[c] = min(ix - ixlo, nixmax - 1);
+                cols[c] = (Real)((double)px - piece_ref(ix, d.W, d.mw));
             }
         }
-        Acc<Real> sA[NR], sS[NR], sV[NR], aA, aS;
 #pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            sA[q].zero();
-            sS[q].zero();
-            sV[q].zero();
+        for (int j = 0; j < NC; ++j) {
+            binS[j * 64 + lane] = 0.0;
+            binA[j * 64 + lane] = (Real)0;
+            binV[j * 64 + lane] = (Real)0;
         }
-        aA.zero();
-        aS.zero();
-        const Real rin = (Real)a.r_in, rout = (Real)a.r_out;
-        const Real rin2 = rin * rin, rout2 = rout * rout;
-        const Real inv_gain = (a.gain > 0.f) ? (Real)1 / (Real)a.gain : (Real)0;
-        for (int band = 0; band < side; band += kApBand) {
-            const int nb = min(kApBand, side - band);
+        int listn = 0;
+        // exact weights of the queued cut pixels
+        auto flush = [&]() __attribute__((always_inline)) {
             wave_sync();
+            for (int e = lane; e < listn; e += 64) {
+                const ApEntry<Real> E = list[e];
+                const Real rj = rad[E.j];
+                const Real w = pixel_area<Real>(E.dx, E.dy, rj, rj * rj);
+                const double ws = (double)w * (double)E.m;
+                const Real wa = w, wvv = w * w * E.var;
+                const int i0 = E.j * 64 + lane;
+                binS[i0] += ws;
+                binA[i0] += wa;
+                binV[i0] += wvv;
+                if (E.j + 1 < NC) {
+                    binS[i0 + 64] -= ws;
+                    binA[i0 + 64] -= wa;
+                    binV[i0 + 64] -= wvv;
+                }
+            }
+            listn = 0;
+            wave_sync();
+        };
+        const int ry0 = max(by0, 0), ry1 = min(by0 + side - 1, d.H - 1);
+        for (int band0 = ry0; band0 <= ry1; band0 += band) {
+            const int nb = min(band, ry1 - band0 + 1);
+            wave_sync();
+            // the band's row runs: columns within half a pixel of the outer
+            // circle's chord (one pixel of margin each side), clipped to the box
+            int cnt = 0, xl = 0;
+            if (lane < nb) {
+                const int py = band0 + lane;
+                const Real dy = (Real)(py - cyi) - fy;
+                const Real nyd = fmax(fabs(dy) - (Real)0.5, (Real)0);
+                if (nyd < rmax) {
+                    const double hw = 0.5 + sqrt(fmax((double)rmax2 - (double)nyd * (double)nyd, 0.0));
+                    xl = max(cx_lo, (int)floor(xc - hw) - 1);
+                    const int xr = min(cx_hi, (int)ceil(xc + hw) + 1);
+                    cnt = max(xr - xl + 1, 0);
+                }
+            }
+            int incl = cnt;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            const int total = __shfl(incl, nb - 1);
+            if (lane < nb) {
+                rxl[lane] = xl;
+                roff[lane] = incl - cnt;
+            }
+            if (lane == 0) roff[nb] = total;
             for (int e = lane; e < nb * nix; e += 64) {
                 const int rr = e / nix, pi = e - rr * nix;
-                const int py = by0 + band + rr;
-                if (py < 0 || py >= d.H) continue;
+                const int py = band0 + rr;
                 const int jy = piece_of(py, d.H, d.mh);
                 const double u = (double)py - piece_ref(jy, d.H, d.mh);
-                sh.tab[wv][rr * kApNix + pi] = make_row<Real>(d.coef, d.nx, d.ny, ixlo + pi, jy, u);
+                tab[rr * nixmax + pi] = make_row<Real>(d.coef, d.nx, d.ny, ixlo + pi, jy, u);
             }
             wave_sync();
-            // pixels of the band, 8 per lane at a time with their loads in flight
-            const int npx = nb * side;
-            for (int e0 = 0; e0 < npx; e0 += 8 * 64) {
-                float vv[8];
-                int pxs[8], pys[8];
-                bool use[8];
+            int rr = 0;
+            for (int b0 = 0; b0 < total; b0 += 64 * kApUnroll) {
+                int pxs[kApUnroll], rrs[kApUnroll];
+                float iv[kApUnroll];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int e = e0 + j * 64 + lane;
-                    const int rr = e / side, c = e - rr * side;
-                    pxs[j] = bx0 + c;
-                    pys[j] = by0 + band + rr;
-                    const Real dx = (Real)(pxs[j] - cxi) - fx, dy = (Real)(pys[j] - cyi) - fy;
-                    const Real ax = fmax(fabs(dx) - (Real)0.5, (Real)0), ay = fmax(fabs(dy) - (Real)0.5, (Real)0);
-                    use[j] = e < npx && pxs[j] >= 0 && pxs[j] < d.W && pys[j] >= 0 && pys[j] < d.H &&
-                             ax * ax + ay * ay < rmax * rmax;
-                    vv[j] = use[j] ? load_px(d, pxs[j], pys[j]) : 0.0f;
+                for (int u = 0; u < kApUnroll; ++u) {
+                    const int idx = b0 + u * 64 + lane;
+                    rrs[u] = -1;
+                    pxs[u] = 0;
+                    iv[u] = 0.0f;
+                    if (idx < total) {
+                        while (idx >= roff[rr + 1]) ++rr;
+                        rrs[u] = rr;
+                        pxs[u] = rxl[rr] + (idx - roff[rr]);
+                        iv[u] = load_px(d, pxs[u], band0 + rr);
+                    }
                 }
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    if (!use[j]) continue;
-                    const int e = e0 + j * 64 + lane;
-                    const int rr = e / side, c = e - rr * side;
-                    const Real dx = (Real)(pxs[j] - cxi) - fx, dy = (Real)(pys[j] - cyi) - fy;
-                    const RowT<Real>& T = sh.tab[wv][rr * kApNix + sh.colp[wv][c]];
-                    const Real s = sh.cols[wv][c];
-                    const Real m = eval_M(T, s, (Real)vv[j]);
-                    Real var = 0;
-                    if (a.want_err) {
-                        const Real rr_ = eval_R(T, s);
-                        var = rr_ * rr_ + ((m > (Real)0) ? m * inv_gain : (Real)0);
-                    }
-                    const Real wo = pixel_area<Real>(dx, dy, rout, rout2);
-                    const Real wi = (rin > (Real)0) ? pixel_area<Real>(dx, dy, rin, rin2) : (Real)0;
-                    const Real wa = wo - wi;
-                    if (wa != (Real)0) {
-                        aA.add(wa);
-                        aS.add(wa * m);
-                    }
+                for (int u = 0; u < kApUnroll; ++u) {
+                    const int r_ = rrs[u];
+                    const int px = pxs[u], py = band0 + (r_ < 0 ? 0 : r_);
+                    const Real dx = (Real)(px - cxi) - fx;
+                    const Real dy = (Real)(py - cyi) - fy;
+                    const Real ax = fabs(dx), ay = fabs(dy);
+                    const Real nxd = fmax(ax - (Real)0.5, (Real)0), nyd = fmax(ay - (Real)0.5, (Real)0);
+                    const Real fxd = ax + (Real)0.5, fyd = ay + (Real)0.5;
+                    const Real dmin2 = nxd * nxd + nyd * nyd, dmax2 = fxd * fxd + fyd * fyd;
+                    const bool use = r_ >= 0 && dmin2 < rmax2;
+                    int kin = NC, kout = NC;
+                    Real m = 0, var = 0;
+                    if (use) {
+                        const int c = px - bx0;
+                        const RowT<Real> T = tab[r_ * nixmax + colp[c]];
+                        const Real sx = cols[c];
+                        m = eval_M(T, sx, (Real)iv[u]);
+                        if (a.want_err) {
+                            const Real rv = eval_R(T, sx);
+                            var = rv * rv + ((m > (Real)0) ? m * inv_gain : (Real)0);
+                        }
+                        kin = 0;
+                        kout = 0;
 #pragma unroll
-                    for (int q = 0; q < NR; ++q) {
-                        const Real rq = (Real)a.radii[q];
-                        const Real w = pixel_area<Real>(dx, dy, rq, rq * rq);
-                        if (w != (Real)0) {
-                            sA[q].add(w);
-                            sS[q].add(w * m);
-                            if (a.want_err) sV[q].add(w * w * var);
+                        for (int j = 0; j < NC; ++j) {
+                            kin += (cr2[j] < dmax2) ? 1 : 0;
+                            kout += (cr2[j] <= dmin2) ? 1 : 0;
+                        }
+                        if (kin < NC) {
+                            const int i0 = kin * 64 + lane;
+                            binS[i0] += (double)m;
+                            binA[i0] += (Real)1;
+                            binV[i0] += var;
                         }
                     }
+                    // circles that cut the pixel: queue (pixel, circle) pairs
+                    const int ncut = kin - kout;
+                    int mx = ncut;
+#pragma unroll
+                    for (int o = 32; o >= 1; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
+                    for (int q = 0; q < mx; ++q) {
+                        const bool has = q < ncut;
+                        const uint64_t bm = __ballot(has);
+                        const int pos = listn + __popcll(bm & below);
+                        if (has) list[pos] = ApEntry<Real>{dx, dy, m, var, kout + q};
+                        listn += __popcll(bm);
+                        if (listn > kApList - 64) flush();
+                    }
                 }
             }
         }
-        const double Aa = aA.reduce(), Sa = aS.reduce();
-        const double b = (Aa > 0.0) ? Sa / Aa : 0.0;
-        // the largest circle crosses the frame boundary
-        const double rm = (double)a.rmax;
-        const bool any_trunc = xc - rm < -0.5 || xc + rm > (double)d.W - 0.5 || yc - rm < -0.5 ||
-                               yc + rm > (double)d.H - 0.5;
+        flush();
+        // circle sums: prefix over the bins in each lane (in place), then each
+        // of the 3 NC totals summed over the lanes in a fixed order
+        {
+            double ps = 0.0, pa = 0.0, pv = 0.0;
 #pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            const double A = sA[q].reduce(), S = sS[q].reduce();
-            const double V = a.want_err ? sV[q].reduce() : 0.0;
-            if (lane == 0) {
-                cat.area[(size_t)row * nr + q] = A;
-                cat.flux[(size_t)row * nr + q] = S - b * A;
-                if (a.want_err && cat.fluxerr) cat.fluxerr[(size_t)row * nr + q] = sqrt(V);
+            for (int j = 0; j < NC; ++j) {
+                const int i0 = j * 64 + lane;
+                ps += binS[i0];
+                pa += (double)binA[i0];
+                pv += (double)binV[i0];
+                binS[i0] = ps;
+                binA[i0] = (Real)pa;
+                binV[i0] = (Real)pv;
             }
         }
+        wave_sync();
+        constexpr int Q = 3 * NC;
+        constexpr int Q2 = (Q <= 16) ? 16 : 32;
+        constexpr int G = 64 / Q2;          // lanes per total
+        constexpr int SPAN = 64 / G;        // lane slots each of them sums
+        double part = 0.0;
+        {
+            const int q = lane / G, g = lane - q * G;
+            if (q < Q) {
+                const int j = (q < NC) ? q : (q < 2 * NC ? q - NC : q - 2 * NC);
+                const int s0 = j * 64 + g * SPAN;
+                if (q < NC) {
+                    for (int t = 0; t < SPAN; ++t) part += binS[s0 + t];
+                } else {
+                    const Real* src = (q < 2 * NC) ? binA : binV;
+                    for (int t = 0; t < SPAN; ++t) part += (double)src[s0 + t];
+                }
+            }
+#pragma unroll
+            for (int o = G / 2; o >= 1; o >>= 1) {
+                const double w = __shfl_xor(part, o);
+                part = ((lane & o) == 0) ? part + w : w + part;
+            }
+        }
+        double S[NC], A[NC], V[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            S[j] = __shfl(part, j * G);
+            A[j] = __shfl(part, (NC + j) * G);
+            V[j] = a.want_err ? __shfl(part, (2 * NC + j) * G) : 0.0;
+        }
+        double Sin = 0, Ain = 0, Sout = 0, Aout = 0;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            const int role = a.crole[j];
+            if (role == kMaxRadii) {
+                Sin = S[j];
+                Ain = A[j];
+            } else if (role == kMaxRadii + 1) {
+                Sout = S[j];
+                Aout = A[j];
+            }
+        }
+        const double Aa = Aout - Ain, Sa = Sout - Sin;
+        const double bk = (Aa > 0.0) ? Sa / Aa : 0.0;
         if (lane == 0) {
-            cat.bkg[row] = b;
-            if (any_trunc) cat.flags[row] |= kFlagTrunc;
+            const int nr = a.nr;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                const int q = a.crole[j];
+                if (q < nr) {
+                    cat.area[(size_t)row * nr + q] = A[j];
+                    cat.flux[(size_t)row * nr + q] = S[j] - bk * A[j];
+                    if (a.want_err && cat.fluxerr) cat.fluxerr[(size_t)row * nr + q] = sqrt(fmax(V[j], 0.0));
+                }
+            }
+            cat.bkg[row] = bk;
+            const double rm = (double)a.rmax;
+            if (xc - rm < -0.5 || xc + rm > (double)d.W - 0.5 || yc - rm < -0.5 || yc + rm > (double)d.H - 0.5)
+                cat.flags[row] |= kFlagTrunc;
         }
     }
+}
+
+template <typename Real, int NC>
+static void launch_ap_nc(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int total_rows, int blocks,
+                         int band, int nixmax, hipStream_t s) {
+    const ApLayout<Real, NC> L(band, nixmax);
+    const size_t lds = (size_t)L.bytes * kApWaves;
+    static bool attr = false;
+    if (lds > 64 * 1024 && !attr) {
+        // large radii on small meshes in FP64: allow the whole LDS
+        (void)hipFuncSetAttribute((const void*)k_aperture<Real, NC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        attr = true;
+    }
+    k_aperture<Real, NC><<<blocks, 64 * kApWaves, lds, s>>>(desc, a, cat, total_rows, band, nixmax);
 }
 
 template <typename Real>
 static void launch_ap_t(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int total_rows, int blocks,
-                        hipStream_t s) {
-    switch (a.nr) {
-        case 1: k_aperture<Real, 1><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
-        case 2: k_aperture<Real, 2><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
-        case 3: k_aperture<Real, 3><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
-        case 4: k_aperture<Real, 4><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
-        case 5: k_aperture<Real, 5><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
-        case 6: k_aperture<Real, 6><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
-        case 7: k_aperture<Real, 7><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
-        default: k_aperture<Real, 8><<<blocks, 256, 0, s>>>(desc, a, cat, total_rows); break;
+                        int band, int nixmax, hipStream_t s) {
+    switch (a.nr + 2) {
+        case 3: launch_ap_nc<Real, 3>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
+        case 4: launch_ap_nc<Real, 4>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
+        case 5: launch_ap_nc<Real, 5>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
+        case 6: launch_ap_nc<Real, 6>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
+        case 7: launch_ap_nc<Real, 7>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
+        case 8: launch_ap_nc<Real, 8>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
+        case 9: launch_ap_nc<Real, 9>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
+        default: launch_ap_nc<Real, 10>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
     }
 }
 
+// Pieces a box of `side` columns can touch: knots are one mesh apart except
+// the last, which is at least half a mesh from its neighbour, so at most
+// (side - 1) / mesh + 2 knots fall inside and the box spans one more piece.
+static int ap_nixmax(int side, int mesh, int nmesh) {
+    return std::max(1, std::min(nmesh + 1, (side - 1) / std::max(mesh, 1) + 3));
+}
+
 void launch_aperture(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int total_rows, int blocks,
-                     bool f64, hipStream_t s) {
+                     int mesh_w, int max_nx, bool f64, hipStream_t s) {
     if (total_rows <= 0) return;
-    if (f64) launch_ap_t<double>(desc, a, cat, total_rows, blocks, s);
-    else launch_ap_t<float>(desc, a, cat, total_rows, blocks, s);
+    const int R = (int)ceilf(a.rmax) + 1;
+    const int side = 2 * R + 2;
+    const int nixmax = ap_nixmax(side, mesh_w, max_nx);
+    const int band = kApBand;
+    if (f64) launch_ap_t<double>(desc, a, cat, total_rows, blocks, band, nixmax, s);
+    else launch_ap_t<float>(desc, a, cat, total_rows, blocks, band, nixmax, s);
 }
 
 }  // namespace gpk

@@ -33,10 +33,14 @@ struct DetArgsIn {
     double kxd[kMaxK], kyd[kMaxK];
 };
 
+// circles sorted by radius: crole[j] = aperture index (< nr), kMaxRadii for
+// r_in, kMaxRadii + 1 for r_out
 struct ApArgs {
     int32_t nr, want_err, capacity, nframes;
     float radii[kMaxRadii];
     float r_in, r_out, gain, rmax;
+    float crad[kMaxRadii + 2];
+    int32_t crole[kMaxRadii + 2];
 };
 
 struct ApCat {
@@ -67,7 +71,7 @@ void launch_catalog(const DetWork& wk, const CatOut& cat, int minarea, int persi
                     hipStream_t s);
 void launch_seg(const DetWork& wk, int f, int64_t npx, hipStream_t s);
 void launch_aperture(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int total_rows, int blocks,
-                     bool f64, hipStream_t s);
+                     int mesh_w, int max_nx, bool f64, hipStream_t s);
 void launch_bkg_map(const FrameDesc& d, double* bmap, double* rmap, bool f64, hipStream_t s);
 void launch_write_desc(const DescChunk& c, FrameDesc* table, hipStream_t s);
 void launch_write_detargs(const DetArgsIn& in, DetArgs* out, hipStream_t s);

@@ -29,7 +29,7 @@ constexpr int kMaxWaves = 16;     // up to 1024 threads per mesh
 struct MeshShared {
     uint32_t hist[kBins];
     float list[kList];
-    F2 pf[kMaxWaves][2];
+    double pd[kMaxWaves][2];
     int32_t pi[kMaxWaves];
     float pmin[kMaxWaves], pmax[kMaxWaves];
     uint32_t wsum[kMaxWaves];
@@ -76,33 +76,33 @@ __device__ int block_sum_i(int x, MeshShared& sh) {
     return s;
 }
 
-// deterministic block reduction of two compensated sums, a count and min/max
+// deterministic block reduction of two FP64 sums, a count and min/max
 // (wavefront butterflies, then the wavefront partials in wavefront order)
 template <int NT>
-__device__ void block_stats(F2& a, F2& b, int& n, float& mn, float& mx, MeshShared& sh) {
+__device__ void block_stats(double& a, double& b, int& n, float& mn, float& mx, MeshShared& sh) {
     constexpr int NW = NT / 64;
     const int w = threadIdx.x >> 6;
-    a = wave_sum_f2(a);
-    b = wave_sum_f2(b);
+    a = wave_sum_d(a);
+    b = wave_sum_d(b);
     n = wave_sum_i(n);
     mn = wave_min(mn);
     mx = wave_max(mx);
     if ((threadIdx.x & 63) == 0) {
-        sh.pf[w][0] = a;
-        sh.pf[w][1] = b;
+        sh.pd[w][0] = a;
+        sh.pd[w][1] = b;
         sh.pi[w] = n;
         sh.pmin[w] = mn;
         sh.pmax[w] = mx;
     }
     __syncthreads();
-    a = sh.pf[0][0];
-    b = sh.pf[0][1];
+    a = sh.pd[0][0];
+    b = sh.pd[0][1];
     n = sh.pi[0];
     mn = sh.pmin[0];
     mx = sh.pmax[0];
     for (int i = 1; i < NW; ++i) {
-        a = f2_add(a, sh.pf[i][0]);
-        b = f2_add(b, sh.pf[i][1]);
+        a += sh.pd[i][0];
+        b += sh.pd[i][1];
         n += sh.pi[i];
         mn = fminf(mn, sh.pmin[i]);
         mx = fmaxf(mx, sh.pmax[i]);
@@ -110,25 +110,29 @@ __device__ void block_stats(F2& a, F2& b, int& n, float& mn, float& mx, MeshShar
     __syncthreads();
 }
 
-// Values of ranks r1 <= r2 (0-based, r2 - r1 <= 1) among the alive pixels.
-// The histogram window [lo, hi] only steers the binning: bins are clamped, so
-// every alive pixel is counted and the selection is exact for any window.
-template <int NT, int PPT>
-__device__ void select_pair(const float (&v)[PPT], uint32_t alive, float lo, float hi, int r1, int r2,
-                            float& o1, float& o2, MeshShared& sh) {
-    const int tid = threadIdx.x;
-    for (int b = tid; b < kBins; b += NT) sh.hist[b] = 0u;
-    if (tid == 0) {
+__device__ __forceinline__ float bin_scale(float lo, float hi) { return (hi > lo) ? (float)kBins / (hi - lo) : 0.0f; }
+
+// zero the histogram and the gather state of select_pair
+template <int NT>
+__device__ void hist_clear(MeshShared& sh) {
+    for (int b = threadIdx.x; b < kBins; b += NT) sh.hist[b] = 0u;
+    if (threadIdx.x == 0) {
         sh.cnt = 0u;
         sh.kmin = 0xffffffffu;
         sh.kmax = 0u;
     }
     __syncthreads();
-    const float scale = (hi > lo) ? (float)kBins / (hi - lo) : 0.0f;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k)
-        if ((alive >> k) & 1u) atomicAdd(&sh.hist[bin_of(v[k], lo, scale)], 1u);
-    __syncthreads();
+}
+
+// Values of ranks r1 <= r2 (0-based, r2 - r1 <= 1) among the alive pixels,
+// given their histogram over bins of [lo, lo + kBins / scale] (filled by the
+// caller after hist_clear).  The window only steers the binning: bins are
+// clamped, so every alive pixel is counted and the selection is exact for any
+// window.
+template <int NT, int PPT>
+__device__ void select_pair(const float (&v)[PPT], uint32_t alive, float lo, float scale, int r1, int r2,
+                            float& o1, float& o2, MeshShared& sh) {
+    const int tid = threadIdx.x;
     constexpr int per = kBins / NT;
     uint32_t c[per];
     uint32_t tot = 0;
@@ -250,16 +254,16 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
             alive |= 1u << k;
         }
     }
-    // pass 0: sigma0 of all pixels (sums shifted by the first pixel)
-    const float c0 = load_px(d, x0, y0);
-    F2 s1{0.f, 0.f}, s2{0.f, 0.f};
+    // pass 0: sigma0 of all pixels (FP64 sums shifted by the first pixel)
+    const double c0 = (double)load_px(d, x0, y0);
+    double s1 = 0.0, s2 = 0.0;
     float mn = INFINITY, mx = -INFINITY;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         if ((alive >> k) & 1u) {
-            float dd = v[k] - c0;
-            f2_acc(s1, dd);
-            f2_acc(s2, dd * dd);
+            const double dd = (double)v[k] - c0;
+            s1 += dd;
+            s2 = fma(dd, dd, s2);
             mn = fminf(mn, v[k]);
             mx = fmaxf(mx, v[k]);
         }
@@ -276,51 +280,72 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
         return;
     }
     const double nd0 = (double)n;
-    double m1 = f2_d(s1) / nd0;
-    double var = f2_d(s2) / nd0 - m1 * m1;
+    double m1 = s1 / nd0;
+    double var = s2 / nd0 - m1 * m1;
     const double sig0 = sqrt(var > 0.0 ? var : 0.0);
-    double mean = (double)c0 + m1;
+    double mean = c0 + m1;
     double sig = sig0;
     int ncur = n;
 
-    auto median_of = [&](uint32_t al, int nn, float lo, float hi, float& mh, float& ml) {
+    // median (exact, as an unevaluated pair when the count is even) of the
+    // alive pixels from their histogram over [lo, ...)
+    float med_h, med_l;
+    auto median_of = [&](uint32_t al, int nn, float lo, float scale) {
         int r2 = nn / 2;
         int r1 = (nn & 1) ? r2 : r2 - 1;
         float o1, o2;
-        select_pair<NT, PPT>(v, al, lo, hi, r1, r2, o1, o2, sh);
+        select_pair<NT, PPT>(v, al, lo, scale, r1, r2, o1, o2, sh);
         if (r1 == r2) {
-            mh = o1;
-            ml = 0.0f;
+            med_h = o1;
+            med_l = 0.0f;
         } else {
             // (o1 + o2) / 2 as an unevaluated pair: exact
             float s, e;
             two_sum(o1, o2, s, e);
-            mh = 0.5f * s;
-            ml = 0.5f * e;
+            med_h = 0.5f * s;
+            med_l = 0.5f * e;
         }
     };
     // the median of all pixels lies within one sigma of their mean
-    float med_h, med_l;
-    median_of(alive, ncur, (float)(mean - sig0), (float)(mean + sig0), med_h, med_l);
+    {
+        const float lo = (float)(mean - sig0), hi = (float)(mean + sig0);
+        const float scale = bin_scale(lo, hi);
+        hist_clear<NT>(sh);
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+            if ((alive >> k) & 1u) atomicAdd(&sh.hist[bin_of(v[k], lo, scale)], 1u);
+        __syncthreads();
+        median_of(alive, ncur, lo, scale);
+    }
 
     int iters = 0;
     for (int it = 0; it < a.max_iter; ++it) {
         const float thr = (float)((double)a.clip * sig);
-        // clip pass: the new set and its shifted, compensated sums
+        // the survivors lie within thr of the median: bin them over that
+        // window in the same pass, for the next median
+        const float wlo = (float)((double)med_h - (double)thr);
+        const float whi = (float)((double)med_h + (double)thr);
+        const float scale = bin_scale(wlo, whi);
+        hist_clear<NT>(sh);
+        // clip pass: the new set, its FP64 sums shifted by the median, and
+        // the histogram of the new set
         uint32_t nal = 0u;
-        F2 t1{0.f, 0.f}, t2{0.f, 0.f};
+        double t1 = 0.0, t2 = 0.0;
+        const double mh = (double)med_h;
         float lmn = INFINITY, lmx = -INFINITY;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             if ((alive >> k) & 1u) {
-                float dd = v[k] - med_h;
-                float dv = dd - med_l;
+                const float dd = v[k] - med_h;
+                const float dv = dd - med_l;
                 if (fabsf(dv) <= thr) {
                     nal |= 1u << k;
-                    f2_acc(t1, dd);
-                    f2_acc(t2, dd * dd);
+                    const double e = (double)v[k] - mh;
+                    t1 += e;
+                    t2 = fma(e, e, t2);
                     lmn = fminf(lmn, v[k]);
                     lmx = fmaxf(lmx, v[k]);
+                    atomicAdd(&sh.hist[bin_of(v[k], wlo, scale)], 1u);
                 }
             }
         }
@@ -331,13 +356,11 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
         alive = nal;
         ncur = nn;
         const double nd = (double)nn;
-        double q1 = f2_d(t1) / nd;
-        double vv = f2_d(t2) / nd - q1 * q1;
-        mean = (double)med_h + q1;
+        const double q1 = t1 / nd;
+        const double vv = t2 / nd - q1 * q1;
+        mean = mh + q1;
         sig = (lmn == lmx) ? 0.0 : sqrt(vv > 0.0 ? vv : 0.0);
-        const float wlo = (float)((double)med_h - (double)thr);
-        const float whi = (float)((double)med_h + (double)thr);
-        median_of(alive, ncur, wlo, whi, med_h, med_l);
+        median_of(alive, ncur, wlo, scale);
     }
     if (tid == 0) {
         const double med = (double)med_h + (double)med_l;

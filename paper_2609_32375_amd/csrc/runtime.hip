@@ -61,7 +61,7 @@ struct gp_ctx {
     std::vector<hipEvent_t> pool;
     std::map<std::string, std::pair<double, int64_t>> totals;
     std::string tune_path;
-    int mesh_cfg = 0;  // launch shape of the mesh-statistics kernel (0 = automatic)
+    int mesh_cfg = 0;     // launch shape of the mesh-statistics kernel (0 = automatic)
 };
 
 namespace {
@@ -648,12 +648,26 @@ extern "C" gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nf
     a.r_out = ap->r_out;
     a.gain = ap->gain;
     a.rmax = rmax;
+    {
+        // circles in increasing radius (ties keep apertures first)
+        std::vector<std::pair<float, int>> c;
+        for (int i = 0; i < ap->nr; ++i) c.push_back({ap->radii[i], i});
+        c.push_back({ap->r_in, kMaxRadii});
+        c.push_back({ap->r_out, kMaxRadii + 1});
+        std::stable_sort(c.begin(), c.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+        for (size_t j = 0; j < c.size(); ++j) {
+            a.crad[j] = c[j].first;
+            a.crole[j] = c[j].second;
+        }
+    }
     ApCat c{cat->n_obj, cat->x, cat->y, cat->flags, out->flux, out->area, out->bkg, out->fluxerr};
     const int total_rows = nframes * cat->capacity;
     const int blocks = std::max(1, std::min(ctx->cus * 8, (total_rows + 3) / 4));
     {
         ProfScope ps(ctx, s, "aperture");
-        launch_aperture((const FrameDesc*)((char*)ws + P.o_desc), a, c, total_rows, blocks,
+        int max_nx = 1;
+        for (int i = 0; i < nframes; ++i) max_nx = std::max(max_nx, (frames[i].width + bp->mesh_w - 1) / bp->mesh_w);
+        launch_aperture((const FrameDesc*)((char*)ws + P.o_desc), a, c, total_rows, blocks, bp->mesh_w, max_nx,
                         ap->precision == GP_PREC_F64, s);
     }
     HIP_TRY(hipGetLastError());

@@ -219,9 +219,11 @@ class Photometry:
         self.n_obj[f] = n
         self.status[f] = 0
 
-    def results(self, f: int = 0):
-        """Catalogue and photometry of frame f as numpy arrays (synchronises)."""
-        torch.cuda.synchronize(self.device)
+    def results(self, f: int = 0, sync: bool = True):
+        """Catalogue and photometry of frame f as numpy arrays.  sync=False when
+        the caller already knows the work is done (e.g. an event completed)."""
+        if sync:
+            torch.cuda.synchronize(self.device)
         n = int(self.n_obj[f].item())
         st = int(self.status[f].item())
         k = min(n, self.capacity)

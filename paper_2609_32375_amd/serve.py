@@ -31,6 +31,8 @@ class Request:
     rid: int
     frame: Any                      # numpy array (host) or torch tensor (device)
     arrival: float = 0.0            # seconds on the server clock
+    params: Any = None              # per-request parameters (None: the server's)
+    kernel: Any = None              # per-request filter kernel (None: the server's)
     footprint: int = 0
     t_admit: Optional[float] = None
     t_done: Optional[float] = None
@@ -48,6 +50,7 @@ class _Epoch:
     stream: torch.cuda.Stream
     done: torch.cuda.Event
     dev_frames: list = field(default_factory=list)
+    key: Any = None
 
 
 class Server:
@@ -79,21 +82,24 @@ class Server:
         self.t0 = time.perf_counter()
         self.finished: List[Request] = []
         self._ws_cache = {}
+        # batch objects (buffers sized for a set of shapes) kept for reuse:
+        # key -> list of idle Photometry
+        self._idle = {}
 
     # ------------------------------------------------------------------
     def now(self) -> float:
         return time.perf_counter() - self.t0
 
-    def footprint(self, frame) -> int:
+    def footprint(self, frame, params=None) -> int:
         """HBM bytes a request holds while in flight (its frame, its share of
         the background buffer and workspace, its catalogue rows)."""
         H, W = frame.shape
         bpp = 2 if frame.dtype in (np.uint16, torch.uint16) else 4
         fr = L.gp_frame(1, W, H, W, L.GP_U16 if bpp == 2 else L.GP_F32)
-        p = self.params
+        p = params if params is not None else self.params
         bp = L.gp_bkg_params(p.mesh_w, p.mesh_h, p.mesh_filter, p.clip_sigma, p.crowd_tol, p.mode_a, p.mode_b,
                              p.max_iter, 0)
-        key = (W, H, bpp)
+        key = (W, H, bpp, p.mesh_w, p.mesh_h)
         if key not in self._ws_cache:
             _, bkg = L.gp_background_layout([fr], bp)
             ws = L.gp_workspace_size(self.ctx, [fr], bp, None, None, self.capacity, 0)
@@ -104,7 +110,7 @@ class Server:
         return own + self._ws_cache[key] + cat
 
     def submit(self, req: Request):
-        req.footprint = self.footprint(req.frame)
+        req.footprint = self.footprint(req.frame, req.params)
         if req.footprint > self.budget:
             raise ValueError(f"request {req.rid} needs {req.footprint} bytes, above the budget {self.budget}")
         self.waiting.append(req)
@@ -116,28 +122,41 @@ class Server:
             if ep.done.query():
                 t = self.now()
                 for i, r in enumerate(ep.reqs):
-                    r.result = ep.ph.results(i)
+                    r.result = ep.ph.results(i, sync=False)
                     r.t_done = t
                     self.resident -= r.footprint
                     self.finished.append(r)
-                ep.ph.close()
+                self._idle.setdefault(ep.key, []).append(ep.ph)
             else:
                 keep.append(ep)
         self.inflight = keep
 
+    def _key(self, r):
+        return (id(r.params) if r.params is not None else None, id(r.kernel) if r.kernel is not None else None)
+
     def _admit(self):
+        """Start one batch: the oldest arrived request plus every other arrived
+        request with the same parameters, while slots and footprint allow."""
         batch = []
         n_inflight = sum(len(e.reqs) for e in self.inflight)
-        while self.waiting and len(batch) < self.max_batch:
-            r = self.waiting[0]
-            if r.arrival > self.now():
-                break
-            if n_inflight + len(batch) >= self.slots or self.resident + r.footprint > self.budget:
-                break
-            self.waiting.popleft()
-            r.t_admit = self.now()
-            self.resident += r.footprint
-            batch.append(r)
+        now = self.now()
+        key = None
+        keep = deque()
+        while self.waiting:
+            r = self.waiting.popleft()
+            fits = (len(batch) < self.max_batch and r.arrival <= now and n_inflight + len(batch) < self.slots
+                    and self.resident + r.footprint <= self.budget)
+            if fits and (key is None or self._key(r) == key):
+                key = self._key(r)
+                r.t_admit = now
+                self.resident += r.footprint
+                batch.append(r)
+            else:
+                keep.append(r)
+                if r.arrival > now or not batch and not fits:
+                    break      # FIFO: nothing behind an unadmittable head starts first
+        keep.extend(self.waiting)
+        self.waiting = keep
         if not batch:
             return False
         stream = self.streams[self._next_stream % len(self.streams)]
@@ -151,11 +170,19 @@ class Server:
                 else:
                     t = torch.as_tensor(f)
                     devs.append(t.to(self.device, non_blocking=True))
-            ph = Photometry(devs, self.params, self.kernel, self.capacity, ctx=self.ctx)
+            params = batch[0].params if batch[0].params is not None else self.params
+            kernel = batch[0].kernel if batch[0].kernel is not None else self.kernel
+            bkey = (key, tuple((tuple(t.shape), t.dtype) for t in devs))
+            idle = self._idle.get(bkey)
+            if idle:
+                ph = idle.pop()
+                ph.rebind(devs)
+            else:
+                ph = Photometry(devs, params, kernel, self.capacity, ctx=self.ctx)
             ph.run(stream)
             done = torch.cuda.Event()
             done.record(stream)
-        self.inflight.append(_Epoch(batch, ph, stream, done, devs))
+        self.inflight.append(_Epoch(batch, ph, stream, done, devs, bkey))
         return True
 
     def poll(self):
@@ -183,6 +210,10 @@ class Server:
             ep.done.synchronize()
             ep.ph.close()
         self.inflight = []
+        for lst in self._idle.values():
+            for ph in lst:
+                ph.close()
+        self._idle = {}
         if self.ctx:
             L.gp_ctx_destroy(self.ctx)
             self.ctx = None

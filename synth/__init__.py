@@ -346,3 +346,65 @@ def arrival_stream(rate: float = 4.0, duration: float = 60.0, seed: int = 5):
         times.append(t)
         kinds.append(["c1", "c2", "c3"][int(rng.integers(0, 3))])
     return np.array(times), kinds
+
+
+# ----------------------------------------------------------------------------
+# Device-side rendering for the large batch / stream workloads (seconds in
+# numpy become milliseconds on the GPU).  Same scene recipe as the c1 frames:
+# sky 1000 + 0.05 x, erf-integrated Gaussian stars (FWHM 3), power-law fluxes,
+# Poisson counts (gain 1) plus N(0, 10^2) read noise; uint16 by rounding and
+# clipping.  Positions and fluxes come from numpy PCG64 (seeded); the noise
+# from a seeded torch generator on the device.
+# ----------------------------------------------------------------------------
+def render_gpu(W: int, H: int, nstars: int, seed: int, fwhm: float = 3.0, dtype: str = "u16",
+               device: str = "cuda"):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xs = rng.uniform(0, W, nstars)
+    ys = rng.uniform(0, H, nstars)
+    fl = _powerlaw_fluxes(rng, nstars)
+    dev = torch.device(device)
+    x = torch.arange(W, device=dev, dtype=torch.float32)
+    img = (1000.0 + 0.05 * x)[None, :].repeat(H, 1)
+    s = fwhm / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    hw = int(math.ceil(6.0 * fwhm))
+    k = torch.arange(-hw, hw + 1, device=dev, dtype=torch.float64)
+    inv = 1.0 / (s * math.sqrt(2.0))
+    flat = img.view(-1)
+    for c0 in range(0, nstars, 4096):
+        x0 = torch.as_tensor(xs[c0:c0 + 4096], device=dev)
+        y0 = torch.as_tensor(ys[c0:c0 + 4096], device=dev)
+        f0 = torch.as_tensor(fl[c0:c0 + 4096], device=dev)
+        px = torch.round(x0)[:, None] + k[None, :]
+        py = torch.round(y0)[:, None] + k[None, :]
+        gx = 0.5 * (torch.erf((px + 0.5 - x0[:, None]) * inv) - torch.erf((px - 0.5 - x0[:, None]) * inv))
+        gy = 0.5 * (torch.erf((py + 0.5 - y0[:, None]) * inv) - torch.erf((py - 0.5 - y0[:, None]) * inv))
+        st = f0[:, None, None] * gy[:, :, None] * gx[:, None, :]
+        X = px[:, None, :].expand_as(st)
+        Y = py[:, :, None].expand_as(st)
+        ok = (X >= 0) & (X < W) & (Y >= 0) & (Y < H)
+        idx = (Y[ok] * W + X[ok]).long()
+        flat.index_add_(0, idx, st[ok].float())
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(seed))
+    out = torch.poisson(img.clamp_min(0), generator=g)
+    out += 10.0 * torch.randn(img.shape, device=dev, generator=g)
+    if dtype == "u16":
+        return torch.round(out).clamp(0, 65535).to(torch.int32).to(torch.uint16)
+    return out.float()
+
+
+def batch_shapes(count_scale: float = 1.0, seed0: int = 1000):
+    """(W, H, nstars, seed) of the 64-frame uneven batch: 24 x 2048^2,
+    24 x 4096^2, 16 x 9600x6400, log-uniform 300..40,000 stars each."""
+    shapes = [(2048, 2048)] * 24 + [(4096, 4096)] * 24 + [(9600, 6400)] * 16
+    if count_scale != 1.0:
+        keep = max(1, int(round(len(shapes) * count_scale)))
+        idx = np.linspace(0, len(shapes) - 1, keep).round().astype(int)
+        shapes = [shapes[i] for i in idx]
+    out = []
+    for i, (w, h) in enumerate(shapes):
+        r = np.random.Generator(np.random.PCG64(seed0 + i))
+        n = int(round(300.0 * (40000.0 / 300.0) ** r.random()))
+        out.append((w, h, n, seed0 + i))
+    return out
