@@ -8,6 +8,13 @@ filter, threshold 1.5 sigma, minarea 5, 8-connected, apertures 3/6/9 px,
 annulus 13-18 px).  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-forms]
+
+Two helper modes feed the roofline's `traffic` figure from rocprofv3 counters:
+  python bench.py --copy-calibration MIB    one elementwise copy (torch.neg) of
+                                            MIB MiB, the reference kernel whose
+                                            known bytes scale FETCH_SIZE/WRITE_SIZE
+  python bench.py --traffic KERNEL FETCH.csv WRITE.csv CAL_FETCH.csv CAL_WRITE.csv
+                                            writes profiles/traffic_<KERNEL>_<workload>.json
 """
 from __future__ import annotations
 
@@ -38,11 +45,74 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-crop", type=int, default=3072, help="side of the CPU-baseline crop")
+    ap.add_argument("--cpu-crop", type=int, default=6144, help="side of the CPU-baseline crop")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and served forms")
     ap.add_argument("--stream-seconds", type=float, default=10.0, help="length of the Poisson arrival stream")
     ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
+    ap.add_argument("--traffic", nargs=5, metavar=("KERNEL", "FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"))
     return ap.parse_args()
+
+
+CAL_KERNEL = "neg"   # name fragment of the calibration copy kernel
+# the source file of each timed kernel: a traffic figure is only reported while
+# the file is unchanged since its counters were taken
+KERNEL_SOURCE = {"mesh_stats": "k_background.hip", "detect_tiles": "k_detect.hip", "aperture": "k_aperture.hip"}
+
+
+def source_sha1(kern):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2609_32375_amd", "csrc", KERNEL_SOURCE[kern])
+    return hashlib.sha1(open(path, "rb").read()).hexdigest()
+
+
+def copy_calibration(mib):
+    """Run one float32 elementwise copy of `mib` MiB (after a warm-up launch)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_bytes_each_way": n * 4}), flush=True)
+
+
+def counter_mean(path, fragment, counter):
+    """Mean of a counter (summed over its instances) per dispatch of the kernels
+    whose name contains `fragment`, from a rocprofv3 counter_collection.csv."""
+    import csv
+    per = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if fragment in r["Kernel_Name"] and r["Counter_Name"] == counter:
+                per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    if not per:
+        raise SystemExit(f"no {counter} rows for kernels named *{fragment}* in {path}")
+    return sum(per.values()) / len(per), len(per)
+
+
+def write_traffic(a):
+    kern, fetch, write, cfetch, cwrite = a.traffic
+    frag = {"mesh_stats": "k_mesh_stats", "detect_tiles": "k_detect_tiles", "aperture": "k_aperture"}[kern]
+    cal_bytes = None
+    # the calibration copy moves the same bytes each way: its last dispatch is
+    # the timed one (the first is a warm-up of identical size)
+    fk, nf = counter_mean(fetch, frag, "FETCH_SIZE")
+    wk, nw = counter_mean(write, frag, "WRITE_SIZE")
+    cfk, _ = counter_mean(cfetch, CAL_KERNEL, "FETCH_SIZE")
+    cwk, _ = counter_mean(cwrite, CAL_KERNEL, "WRITE_SIZE")
+    cal_bytes = a.copy_calibration * (1 << 20) if a.copy_calibration else 1 << 30
+    sf, sw = cal_bytes / (cfk * 1024), cal_bytes / (cwk * 1024)
+    out = {"kernel": kern, "workload": a.workload, "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
+           "dispatches": [nf, nw], "calibration_bytes": cal_bytes, "calibration_fetch_kib": cfk,
+           "calibration_write_kib": cwk, "fetch_scale": sf, "write_scale": sw,
+           "bytes_per_launch": int(fk * 1024 * sf + wk * 1024 * sw), "source_sha1": source_sha1(kern)}
+    path = os.path.join(ROOT, "profiles", f"traffic_{kern}_{a.workload}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out), flush=True)
 
 
 def kernel_bytes(name, W, H, bpp, n_obj, rmax):
@@ -56,6 +126,12 @@ def kernel_bytes(name, W, H, bpp, n_obj, rmax):
 
 def main():
     a = parse()
+    if a.traffic:
+        write_traffic(a)
+        return
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU form is a design note",
               file=sys.stderr)
@@ -131,7 +207,9 @@ def main():
     tfile = os.path.join(ROOT, "profiles", f"traffic_{dom}_{a.workload}.json")
     if os.path.exists(tfile):
         try:
-            traffic = json.load(open(tfile)).get("bytes_per_launch")
+            tj = json.load(open(tfile))
+            if tj.get("source_sha1") == source_sha1(dom):
+                traffic = tj.get("bytes_per_launch")
         except Exception:
             traffic = None
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -264,7 +342,7 @@ def form_served(torch, a):
     for i, k in enumerate(kinds):
         plain[k].rebind([pools[k][i % 3]])
         plain[k].run()
-        torch.cuda.synchronize()
+        plain[k].results(0)          # the catalogue comes back, as it does for a served request
     plain_s = time.perf_counter() - t
     for k in shp:
         plain[k].close()

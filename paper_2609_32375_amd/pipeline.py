@@ -16,6 +16,9 @@ from typing import List, Optional, Sequence
 import numpy as np
 import torch
 
+_NP_DTYPE = {torch.float64: np.float64, torch.float32: np.float32, torch.int32: np.int32,
+             torch.int64: np.int64, torch.uint8: np.uint8, torch.int16: np.int16}
+
 from . import _lib as L
 
 
@@ -221,18 +224,30 @@ class Photometry:
 
     def results(self, f: int = 0, sync: bool = True):
         """Catalogue and photometry of frame f as numpy arrays.  sync=False when
-        the caller already knows the work is done (e.g. an event completed)."""
+        the caller already knows the work is done (e.g. an event completed).
+        The frame's rows of every column are packed on the device and brought
+        over in one copy."""
         if sync:
             torch.cuda.synchronize(self.device)
-        n = int(self.n_obj[f].item())
-        st = int(self.status[f].item())
+        hdr = torch.stack([self.n_obj[f], self.status[f]]).cpu().numpy()
+        n, st = int(hdr[0]), int(hdr[1])
         k = min(n, self.capacity)
         base = f * self.capacity
-        cat = {name: t[base: base + k].cpu().numpy() for name, t in self.cat.items()}
-        cat["flags"] = cat["flags"].astype(np.uint32)
-        phot = {name: t[base: base + k].cpu().numpy() for name, t in self.phot.items()}
-        return dict(n_obj=n, status=st, cat=cat, phot=phot,
-                    comp_status=self.comp_status.cpu().numpy().tolist(),
+        cols = [("cat", name, t) for name, t in self.cat.items()] + \
+               [("phot", name, t) for name, t in self.phot.items()]
+        parts = [t[base: base + k].reshape(-1).view(torch.uint8) for _, _, t in cols]
+        parts.append(self.comp_status.reshape(-1).view(torch.uint8))
+        flat = torch.cat(parts).cpu().numpy()
+        out = {"cat": {}, "phot": {}}
+        off = 0
+        for (grp, name, t), pt in zip(cols, parts):
+            nb = pt.numel()
+            shape = (k,) + tuple(t.shape[1:])
+            out[grp][name] = flat[off: off + nb].view(_NP_DTYPE[t.dtype]).reshape(shape).copy()
+            off += nb
+        comp = flat[off:].view(_NP_DTYPE[self.comp_status.dtype]).tolist()
+        out["cat"]["flags"] = out["cat"]["flags"].astype(np.uint32)
+        return dict(n_obj=n, status=st, cat=out["cat"], phot=out["phot"], comp_status=comp,
                     seg=self.seg[f].cpu().numpy() if self.seg is not None else None)
 
 

@@ -58,7 +58,8 @@ class Server:
 
     hbm_budget: bytes of HBM the in-flight requests may hold (frames, background
     buffers, workspace, catalogue); None = 90% of the free memory at start.
-    slots: most requests in flight.  streams: concurrent batches.
+    slots: most requests in flight.  streams: concurrent batches.  max_batch:
+    most requests per batch (default: slots / streams).
     """
 
     def __init__(self, params, kernel, capacity: int = 65536, hbm_budget: Optional[int] = None,
@@ -73,7 +74,9 @@ class Server:
             hbm_budget = int(0.9 * free)
         self.budget = int(hbm_budget)
         self.slots = slots
-        self.max_batch = max_batch or slots
+        # a batch takes at most its stream's share of the slots, so the next
+        # batch can start on the other stream while one is being retired
+        self.max_batch = max_batch or max(1, slots // max(1, streams))
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self._next_stream = 0
         self.waiting: deque = deque()
