@@ -23,20 +23,21 @@
 namespace gpk {
 
 constexpr int kBins = 4096;
-constexpr int kList = 1024;
 constexpr int kMaxWaves = 16;     // up to 1024 threads per mesh
+
+constexpr int kBuf = 4096;        // sorted window of ranks around the median
+constexpr int kHalf = 512;        // half-width of that window, in ranks
 
 struct MeshShared {
     uint32_t hist[kBins];
-    float list[kList];
+    float buf[kBuf];
     double pd[kMaxWaves][2];
-    int32_t pi[kMaxWaves];
+    int32_t pi[kMaxWaves][2];
     float pmin[kMaxWaves], pmax[kMaxWaves];
     uint32_t wsum[kMaxWaves];
     int32_t sel_bin[2];
     uint32_t sel_cum[2];
     uint32_t cnt, kmin, kmax;
-    float out[2];
     int32_t ucnt[kMaxWaves];
 };
 
@@ -45,6 +46,8 @@ __device__ __forceinline__ int bin_of(float v, float lo, float scale) {
     t = fminf(fmaxf(t, 0.0f), (float)(kBins - 1));
     return (int)t;
 }
+
+__device__ __forceinline__ float bin_scale(float lo, float hi) { return (hi > lo) ? (float)kBins / (hi - lo) : 0.0f; }
 
 // exclusive scan of one uint32 per thread over the block
 template <int NT>
@@ -76,63 +79,120 @@ __device__ int block_sum_i(int x, MeshShared& sh) {
     return s;
 }
 
-// deterministic block reduction of two FP64 sums, a count and min/max
+// deterministic block reduction of two FP64 sums, two counts and min/max
 // (wavefront butterflies, then the wavefront partials in wavefront order)
 template <int NT>
-__device__ void block_stats(double& a, double& b, int& n, float& mn, float& mx, MeshShared& sh) {
+__device__ void block_stats(double& a, double& b, int& n, int& n2, float& mn, float& mx, MeshShared& sh) {
     constexpr int NW = NT / 64;
     const int w = threadIdx.x >> 6;
     a = wave_sum_d(a);
     b = wave_sum_d(b);
     n = wave_sum_i(n);
+    n2 = wave_sum_i(n2);
     mn = wave_min(mn);
     mx = wave_max(mx);
     if ((threadIdx.x & 63) == 0) {
         sh.pd[w][0] = a;
         sh.pd[w][1] = b;
-        sh.pi[w] = n;
+        sh.pi[w][0] = n;
+        sh.pi[w][1] = n2;
         sh.pmin[w] = mn;
         sh.pmax[w] = mx;
     }
     __syncthreads();
     a = sh.pd[0][0];
     b = sh.pd[0][1];
-    n = sh.pi[0];
+    n = sh.pi[0][0];
+    n2 = sh.pi[0][1];
     mn = sh.pmin[0];
     mx = sh.pmax[0];
     for (int i = 1; i < NW; ++i) {
         a += sh.pd[i][0];
         b += sh.pd[i][1];
-        n += sh.pi[i];
+        n += sh.pi[i][0];
+        n2 += sh.pi[i][1];
         mn = fminf(mn, sh.pmin[i]);
         mx = fmaxf(mx, sh.pmax[i]);
     }
     __syncthreads();
 }
 
-__device__ __forceinline__ float bin_scale(float lo, float hi) { return (hi > lo) ? (float)kBins / (hi - lo) : 0.0f; }
-
-// zero the histogram and the gather state of select_pair
-template <int NT>
-__device__ void hist_clear(MeshShared& sh) {
-    for (int b = threadIdx.x; b < kBins; b += NT) sh.hist[b] = 0u;
-    if (threadIdx.x == 0) {
-        sh.cnt = 0u;
-        sh.kmin = 0xffffffffu;
-        sh.kmax = 0u;
+// ascending bitonic sorting network over a thread's registers
+template <int PPT>
+__device__ __forceinline__ void sort_regs(float (&v)[PPT]) {
+#pragma unroll
+    for (int k = 2; k <= PPT; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const float a = v[i], b = v[l];
+                    const bool up = (i & k) == 0;
+                    v[i] = up ? fminf(a, b) : fmaxf(a, b);
+                    v[l] = up ? fmaxf(a, b) : fminf(a, b);
+                }
+            }
+        }
     }
-    __syncthreads();
 }
 
-// Values of ranks r1 <= r2 (0-based, r2 - r1 <= 1) among the alive pixels,
-// given their histogram over bins of [lo, lo + kBins / scale] (filled by the
-// caller after hist_clear).  The window only steers the binning: bins are
-// clamped, so every alive pixel is counted and the selection is exact for any
-// window.
-template <int NT, int PPT>
-__device__ void select_pair(const float (&v)[PPT], uint32_t alive, float lo, float scale, int r1, int r2,
-                            float& o1, float& o2, MeshShared& sh) {
+// ascending bitonic sort of buf[0, P) in LDS (P a power of two)
+template <int NT>
+__device__ void sort_buf(float* buf, int P) {
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < P / 2; t += NT) {
+                const int i = 2 * t - (t & (j - 1));
+                const int l = i + j;
+                const float a = buf[i], b = buf[l];
+                const bool up = (i & k) == 0;
+                if ((a > b) == up) {
+                    buf[i] = b;
+                    buf[l] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// The pixels of a mesh as per-thread sorted runs in LDS: thread t holds
+// T[k * NT + t] for k in [lo, hi), ascending.
+template <int NT>
+struct Runs {
+    const float* T;
+    int lo, hi;
+    template <typename F>
+    __device__ __forceinline__ void each(F&& f) const {
+        for (int k = lo; k < hi; ++k) f(T[k * NT + threadIdx.x]);
+    }
+    // number of this thread's values <= x (binary search in the run)
+    __device__ __forceinline__ int count_le(float x) const {
+        int a = lo, b = hi;
+        while (a < b) {
+            const int m = (a + b) >> 1;
+            if (T[m * NT + threadIdx.x] <= x) a = m + 1;
+            else b = m;
+        }
+        return a - lo;
+    }
+};
+
+// Fill sh.buf with the values of ranks [ra, rb] (0-based, within the alive
+// set) and their bin-mates, sorted; returns the rank of buf[0] (>= 0) and the
+// count in m, or -1 when the gathered bins exceed the buffer.  The histogram
+// window [wlo, whi] only steers the binning (bins are clamped).
+template <int NT>
+__device__ int build_window(const Runs<NT>& run, float wlo, float whi, int ra, int rb, int& m, MeshShared& sh) {
     const int tid = threadIdx.x;
+    for (int b = tid; b < kBins; b += NT) sh.hist[b] = 0u;
+    if (tid == 0) sh.cnt = 0u;
+    __syncthreads();
+    const float scale = bin_scale(wlo, whi);
+    run.each([&](float x) { atomicAdd(&sh.hist[bin_of(x, wlo, scale)], 1u); });
+    __syncthreads();
     constexpr int per = kBins / NT;
     uint32_t c[per];
     uint32_t tot = 0;
@@ -141,11 +201,11 @@ __device__ void select_pair(const float (&v)[PPT], uint32_t alive, float lo, flo
         c[q] = sh.hist[tid * per + q];
         tot += c[q];
     }
-    uint32_t pre = block_exscan<NT>(tot, sh);
-    const int rr[2] = {r1, r2};
+    const uint32_t pre = block_exscan<NT>(tot, sh);
+    const int rr[2] = {ra, rb};
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-        uint32_t r = (uint32_t)rr[t];
+        const uint32_t r = (uint32_t)rr[t];
         if (pre <= r && r < pre + tot) {
             uint32_t cum = pre;
             for (int q = 0; q < per; ++q) {
@@ -160,65 +220,37 @@ __device__ void select_pair(const float (&v)[PPT], uint32_t alive, float lo, flo
     }
     __syncthreads();
     const int b1 = sh.sel_bin[0], b2 = sh.sel_bin[1];
-    const uint32_t cb = sh.sel_cum[0];
-    // gather the pixels of bins [b1, b2] (bins strictly between are empty)
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        if ((alive >> k) & 1u) {
-            int b = bin_of(v[k], lo, scale);
-            if (b >= b1 && b <= b2) {
-                uint32_t s = atomicAdd(&sh.cnt, 1u);
-                if (s < (uint32_t)kList) sh.list[s] = v[k];
-                uint32_t key = f2ord(v[k]);
-                atomicMin(&sh.kmin, key);
-                atomicMax(&sh.kmax, key);
-            }
+    const int base = (int)sh.sel_cum[0];
+    run.each([&](float x) {
+        const int b = bin_of(x, wlo, scale);
+        if (b >= b1 && b <= b2) {
+            const uint32_t s = atomicAdd(&sh.cnt, 1u);
+            if (s < (uint32_t)kBuf) sh.buf[s] = x;
         }
-    }
+    });
     __syncthreads();
-    const int m = (int)sh.cnt;
-    const int k1 = r1 - (int)cb, k2 = r2 - (int)cb;
-    const uint32_t kmin = sh.kmin, kmax = sh.kmax;
-    if (kmin == kmax) {
-        o1 = o2 = ord2f(kmin);
-        __syncthreads();
-        return;
-    }
-    if (m <= kList) {
-        for (int e = tid; e < m; e += NT) {
-            float x = sh.list[e];
-            int less = 0, eq = 0;
-            for (int j2 = 0; j2 < m; ++j2) {
-                float y = sh.list[j2];
-                less += (y < x);
-                eq += (y == x);
-            }
-            if (less <= k1 && k1 < less + eq) sh.out[0] = x;
-            if (less <= k2 && k2 < less + eq) sh.out[1] = x;
-        }
-        __syncthreads();
-        o1 = sh.out[0];
-        o2 = sh.out[1];
-        __syncthreads();
-        return;
-    }
-    // Many pixels in the target bins (heavy ties in float data): bisection on
-    // the order-preserving keys of the subset, 32 counting passes at most.
-    const int kk[2] = {k1, k2};
+    m = (int)sh.cnt;
+    if (m > kBuf) return -1;
+    int P = 2;
+    while (P < m) P <<= 1;
+    for (int i = m + tid; i < P; i += NT) sh.buf[i] = INFINITY;
+    __syncthreads();
+    sort_buf<NT>(sh.buf, P);
+    return base;
+}
+
+// Values of ranks r1 <= r2 of the alive set by bisection on the
+// order-preserving keys (count_le per run); for windows the buffer cannot hold.
+template <int NT>
+__device__ void bisect_pair(const Runs<NT>& run, float lmn, float lmx, int r1, int r2, float& o1, float& o2,
+                            MeshShared& sh) {
+    const int kk[2] = {r1, r2};
     float res[2];
     for (int t = 0; t < 2; ++t) {
-        uint32_t a = kmin, z = kmax;
+        uint32_t a = f2ord(lmn), z = f2ord(lmx);
         while (a < z) {
-            uint32_t mid = a + ((z - a) >> 1);
-            int cnt = 0;
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                if ((alive >> k) & 1u) {
-                    int b = bin_of(v[k], lo, scale);
-                    cnt += (b >= b1 && b <= b2 && f2ord(v[k]) <= mid);
-                }
-            }
-            cnt = block_sum_i<NT>(cnt, sh);
+            const uint32_t mid = a + ((z - a) >> 1);
+            const int cnt = block_sum_i<NT>(run.count_le(ord2f(mid)), sh);
             if (cnt > kk[t]) z = mid;
             else a = mid + 1;
         }
@@ -228,9 +260,16 @@ __device__ void select_pair(const float (&v)[PPT], uint32_t alive, float lo, flo
     o2 = res[1];
 }
 
+// One workgroup per mesh.  Pass 0 gives sigma0 of all pixels; the pixels are
+// then sorted per thread and kept in LDS as runs.  The clipped set is a value
+// interval, so a clipping pass only moves each run's ends inward, taking the
+// dropped values off the thread's FP64 sums.  The median comes from a sorted
+// window of ranks around it (built through a histogram of the runs), which
+// stays valid while the ranks removed below keep the median inside it.
 template <int NT, int PPT>
 __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__ desc, int nframes, BkgArgs a) {
     __shared__ MeshShared sh;
+    __shared__ float T[NT * PPT];
     const int tid = threadIdx.x;
     const int gm = blockIdx.x;
     const int f = frame_of(nframes, gm, [&](int i) { return desc[i].mesh_base; });
@@ -242,16 +281,16 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
     const int n = w * h;
 
     float v[PPT];
-    uint32_t alive = 0u;
+    int cnt_t = 0;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        int p = k * NT + tid;
-        v[k] = 0.0f;
+        const int p = k * NT + tid;
+        v[k] = INFINITY;
         if (p < n) {
-            int yy = p / w;
-            int xx = p - yy * w;
+            const int yy = p / w;
+            const int xx = p - yy * w;
             v[k] = load_px(d, x0 + xx, y0 + yy);
-            alive |= 1u << k;
+            ++cnt_t;
         }
     }
     // pass 0: sigma0 of all pixels (FP64 sums shifted by the first pixel)
@@ -260,7 +299,7 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
     float mn = INFINITY, mx = -INFINITY;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        if ((alive >> k) & 1u) {
+        if (k < cnt_t) {
             const double dd = (double)v[k] - c0;
             s1 += dd;
             s2 = fma(dd, dd, s2);
@@ -268,8 +307,8 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
             mx = fmaxf(mx, v[k]);
         }
     }
-    int cnt = 0;
-    block_stats<NT>(s1, s2, cnt, mn, mx, sh);
+    int cnt = 0, unused = 0;
+    block_stats<NT>(s1, s2, cnt, unused, mn, mx, sh);
     const int out_idx = mj * d.nx + mi;
     if (mn == mx) {
         if (tid == 0) {
@@ -280,21 +319,51 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
         return;
     }
     const double nd0 = (double)n;
-    double m1 = s1 / nd0;
-    double var = s2 / nd0 - m1 * m1;
-    const double sig0 = sqrt(var > 0.0 ? var : 0.0);
+    const double m1 = s1 / nd0;
+    const double var0 = s2 / nd0 - m1 * m1;
+    const double sig0 = sqrt(var0 > 0.0 ? var0 : 0.0);
     double mean = c0 + m1;
     double sig = sig0;
-    int ncur = n;
 
-    // median (exact, as an unevaluated pair when the count is even) of the
-    // alive pixels from their histogram over [lo, ...)
+    // the thread's run, sorted, in LDS; its FP64 sums shifted by a float
+    // near the mean (so every shifted value is exact)
+    sort_regs<PPT>(v);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) T[k * NT + tid] = v[k];
+    const double cs = (double)(float)mean;
+    double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if (k < cnt_t) {
+            const double e = (double)v[k] - cs;
+            t1 += e;
+            t2 = fma(e, e, t2);
+        }
+    }
+    Runs<NT> run{T, 0, cnt_t};
+    float vlo = (cnt_t > 0) ? T[tid] : INFINITY;
+    float vhi = (cnt_t > 0) ? T[(cnt_t - 1) * NT + tid] : -INFINITY;
+
+    int ncur = n;
+    int R0 = -1, bm = 0;      // rank of buf[0] in the alive set (-1: no window)
     float med_h, med_l;
-    auto median_of = [&](uint32_t al, int nn, float lo, float scale) {
-        int r2 = nn / 2;
-        int r1 = (nn & 1) ? r2 : r2 - 1;
+    float lmn = mn, lmx = mx;
+    // exact median (an unevaluated pair when the count is even) of the alive
+    // set, from the window, rebuilding it when the median has left it
+    auto median = [&](float wlo, float whi) __attribute__((always_inline)) {
+        const int r2 = ncur / 2;
+        const int r1 = (ncur & 1) ? r2 : r2 - 1;
         float o1, o2;
-        select_pair<NT, PPT>(v, al, lo, scale, r1, r2, o1, o2, sh);
+        if (R0 < 0 || r1 - R0 < 0 || r2 - R0 >= bm) {
+            R0 = build_window<NT>(run, wlo, whi, max(r1 - kHalf, 0), min(r2 + kHalf, ncur - 1), bm, sh);
+            if (R0 < 0) R0 = build_window<NT>(run, wlo, whi, r1, r2, bm, sh);
+        }
+        if (R0 >= 0) {
+            o1 = sh.buf[r1 - R0];
+            o2 = sh.buf[r2 - R0];
+        } else {
+            bisect_pair<NT>(run, lmn, lmx, r1, r2, o1, o2, sh);
+        }
         if (r1 == r2) {
             med_h = o1;
             med_l = 0.0f;
@@ -307,60 +376,45 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
         }
     };
     // the median of all pixels lies within one sigma of their mean
-    {
-        const float lo = (float)(mean - sig0), hi = (float)(mean + sig0);
-        const float scale = bin_scale(lo, hi);
-        hist_clear<NT>(sh);
-#pragma unroll
-        for (int k = 0; k < PPT; ++k)
-            if ((alive >> k) & 1u) atomicAdd(&sh.hist[bin_of(v[k], lo, scale)], 1u);
-        __syncthreads();
-        median_of(alive, ncur, lo, scale);
-    }
+    median((float)(mean - sig0), (float)(mean + sig0));
 
     int iters = 0;
     for (int it = 0; it < a.max_iter; ++it) {
         const float thr = (float)((double)a.clip * sig);
-        // the survivors lie within thr of the median: bin them over that
-        // window in the same pass, for the next median
-        const float wlo = (float)((double)med_h - (double)thr);
-        const float whi = (float)((double)med_h + (double)thr);
-        const float scale = bin_scale(wlo, whi);
-        hist_clear<NT>(sh);
-        // clip pass: the new set, its FP64 sums shifted by the median, and
-        // the histogram of the new set
-        uint32_t nal = 0u;
-        double t1 = 0.0, t2 = 0.0;
-        const double mh = (double)med_h;
-        float lmn = INFINITY, lmx = -INFINITY;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            if ((alive >> k) & 1u) {
-                const float dd = v[k] - med_h;
-                const float dv = dd - med_l;
-                if (fabsf(dv) <= thr) {
-                    nal |= 1u << k;
-                    const double e = (double)v[k] - mh;
-                    t1 += e;
-                    t2 = fma(e, e, t2);
-                    lmn = fminf(lmn, v[k]);
-                    lmx = fmaxf(lmx, v[k]);
-                    atomicAdd(&sh.hist[bin_of(v[k], wlo, scale)], 1u);
-                }
-            }
+        auto keep = [&](float x) { return fabsf((x - med_h) - med_l) <= thr; };
+        // clipping pass: move the run's ends inward
+        int rem = 0;
+        while (run.lo < run.hi && !keep(vlo)) {
+            const double e = (double)vlo - cs;
+            t1 -= e;
+            t2 = fma(-e, e, t2);
+            ++run.lo;
+            ++rem;
+            if (run.lo < run.hi) vlo = T[run.lo * NT + tid];
         }
-        int nn = __popc(nal);
-        block_stats<NT>(t1, t2, nn, lmn, lmx, sh);
+        while (run.lo < run.hi && !keep(vhi)) {
+            const double e = (double)vhi - cs;
+            t1 -= e;
+            t2 = fma(-e, e, t2);
+            --run.hi;
+            if (run.lo < run.hi) vhi = T[(run.hi - 1) * NT + tid];
+        }
+        double q1s = t1, q2s = t2;
+        int nn = run.hi - run.lo, nrem = rem;
+        float tmn = (run.lo < run.hi) ? vlo : INFINITY, tmx = (run.lo < run.hi) ? vhi : -INFINITY;
+        block_stats<NT>(q1s, q2s, nn, nrem, tmn, tmx, sh);
         ++iters;
         if (nn == ncur || nn == 0) break;
-        alive = nal;
         ncur = nn;
+        if (R0 >= 0) R0 -= nrem;
+        lmn = tmn;
+        lmx = tmx;
         const double nd = (double)nn;
-        const double q1 = t1 / nd;
-        const double vv = t2 / nd - q1 * q1;
-        mean = mh + q1;
+        const double q1 = q1s / nd;
+        const double vv = q2s / nd - q1 * q1;
+        mean = cs + q1;
         sig = (lmn == lmx) ? 0.0 : sqrt(vv > 0.0 ? vv : 0.0);
-        median_of(alive, ncur, wlo, scale);
+        median(lmn, lmx);
     }
     if (tid == 0) {
         const double med = (double)med_h + (double)med_l;
@@ -372,6 +426,7 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
         d.iters[out_idx] = iters;
     }
 }
+
 
 // ---------------------------------------------------------------------------
 // f x f median over the mesh grid, back and rms separately

@@ -57,6 +57,51 @@ MESH_CASES = [
 ]
 
 
+def _structured_meshes(m, seed):
+    """A frame of 3 x 2 meshes of m x m float32 pixels, each with a value
+    distribution that stresses one part of the clipping loop: heavy ties
+    (2 integer levels), a bright source over a third of the mesh (the median
+    moves far between passes), tiny values of both signs, a two-level mesh,
+    a bimodal mixture and a Gaussian sky with a few saturated pixels."""
+    rng = np.random.default_rng(seed)
+    n = m * m
+    ties = 1000.0 + rng.integers(0, 2, n)
+    ties[rng.choice(n, n // 50, replace=False)] = 60000.0
+    src = 500.0 + 5.0 * rng.standard_normal(n)
+    src[: n // 3] += 800.0 + 200.0 * rng.standard_normal(n // 3)
+    tiny = 1e-3 * rng.standard_normal(n)
+    two = np.where(rng.random(n) < 0.7, 3.0, 7.0)
+    bim = np.concatenate([100.0 + rng.standard_normal(n - n // 4), 140.0 + rng.standard_normal(n // 4)])
+    rng.shuffle(bim)
+    sat = 2000.0 + 30.0 * rng.standard_normal(n)
+    sat[rng.choice(n, 40, replace=False)] = 65535.0
+    blocks = [x.reshape(m, m) for x in (ties, src, tiny, two, bim, sat)]
+    img = np.block([[blocks[0], blocks[1], blocks[2]], [blocks[3], blocks[4], blocks[5]]])
+    return np.ascontiguousarray(img.astype(np.float32))
+
+
+@pytest.mark.parametrize("m", [64, 128])
+def test_mesh_statistics_structured(P, m):
+    """Tie-heavy, drifting, tiny, two-level and bimodal meshes (4096 and 16384
+    pixels: both launch shapes of the statistics kernel)."""
+    _say("structured meshes", m)
+    img = _structured_meshes(m, 7 + m)
+    p = _params("c1", mesh_w=m, mesh_h=m, mesh_filter=1)
+    ph = P.Photometry([_dev(img)], p, p.kernel(), capacity=64)
+    ph.background()
+    g = ph.grids(0)
+    st = oracle.mesh_stats(img.astype(np.float64), m, m, p.clip_sigma, p.crowd_tol, p.mode_a, p.mode_b, p.max_iter)
+    ok = ~mesh_ambiguous(st)
+    _say("ambiguous", int((~ok).sum()), "iters", st["iters"].ravel().tolist())
+    assert ok.sum() >= 5
+    rel_b = np.abs(g["back_raw"] - st["back"]) / np.maximum(np.abs(st["back"]), 1e-30)
+    rel_r = np.abs(g["rms_raw"] - st["rms"]) / np.maximum(np.abs(st["rms"]), 1e-30)
+    _say("max rel back", rel_b[ok].max(), "rms", rel_r[ok].max())
+    assert np.all(rel_b[ok] <= TOL_BKG_REL) and np.all((rel_r[ok] <= TOL_BKG_REL) | (st["rms"][ok] == 0))
+    np.testing.assert_array_equal(g["iters"][ok], st["iters"][ok].astype(np.int32))
+    ph.close()
+
+
 @pytest.mark.parametrize("case", MESH_CASES, ids=lambda c: f"{c[0]}-{c[1]}x{c[2]}-{c[3]}-m{c[4]}x{c[5]}")
 def test_mesh_statistics_match_oracle(P, case):
     name, W, H, dt, mw, mh, seed = case
