@@ -22,13 +22,6 @@ constexpr int kApBand = 16;    // rows per band
 constexpr int kApBox = 2 * 66; // widest box (r <= 64)
 constexpr int kApWaves = 4;
 
-// make one wavefront's LDS writes visible to its other lanes
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 // theta - sin(theta) without cancellation for small angles: theta^3/6 times
 // the nested series 1 - t^2/20 (1 - t^2/42 (1 - t^2/72 (...))), denominators
 // (2k)(2k+1); enough terms for the working precision at theta < 1/2

@@ -25,11 +25,14 @@ namespace gpk {
 constexpr int kBins = 4096;
 constexpr int kMaxWaves = 16;     // up to 1024 threads per mesh
 
-constexpr int kBuf = 4096;        // sorted window of ranks around the median
+constexpr int kBuf = 4096;        // sorted window of ranks around the median (== kBins)
 constexpr int kHalf = 512;        // half-width of that window, in ranks
 
 struct MeshShared {
-    uint32_t hist[kBins];
+    union {
+        uint32_t hist[kBins];
+        float buf2[kBuf];     // second buffer of the window sort
+    };
     float buf[kBuf];
     double pd[kMaxWaves][2];
     int32_t pi[kMaxWaves][2];
@@ -138,24 +141,98 @@ __device__ __forceinline__ void sort_regs(float (&v)[PPT]) {
     }
 }
 
-// ascending bitonic sort of buf[0, P) in LDS (P a power of two)
-template <int NT>
-__device__ void sort_buf(float* buf, int P) {
-    for (int k = 2; k <= P; k <<= 1) {
+// Ascending bitonic sort of the SEG = 64 E values a wavefront holds, E per
+// lane (lane l holds positions l E .. l E + E - 1): partners closer than E sit
+// in the same lane, the others are exchanged with a lane shuffle.
+template <int E>
+__device__ __forceinline__ void wave_sort(float (&x)[E], int lane) {
+#pragma unroll
+    for (int k = 2; k <= 64 * E; k <<= 1) {
+#pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < P / 2; t += NT) {
-                const int i = 2 * t - (t & (j - 1));
-                const int l = i + j;
-                const float a = buf[i], b = buf[l];
-                const bool up = (i & k) == 0;
-                if ((a > b) == up) {
-                    buf[i] = b;
-                    buf[l] = a;
+            if (j < E) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int g = e ^ j;
+                    if (g > e) {
+                        const bool up = ((lane * E + e) & k) == 0;
+                        const float a = x[e], b = x[g];
+                        x[e] = up ? fminf(a, b) : fmaxf(a, b);
+                        x[g] = up ? fmaxf(a, b) : fminf(a, b);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const float o = __shfl_xor(x[e], j / E);
+                    const int i = lane * E + e;
+                    const bool up = (i & k) == 0, lower = (i & j) == 0;
+                    x[e] = (lower == up) ? fminf(x[e], o) : fmaxf(x[e], o);
                 }
             }
-            __syncthreads();
         }
     }
+}
+
+template <int E>
+__device__ __forceinline__ void wave_sort_segment(float* buf, int w, int lane) {
+    float x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = buf[w * 64 * E + lane * E + e];
+    wave_sort<E>(x, lane);
+#pragma unroll
+    for (int e = 0; e < E; ++e) buf[w * 64 * E + lane * E + e] = x[e];
+}
+
+// Ascending sort of a[0, P) (P a power of two, 64 <= P <= 64 * 16 * waves)
+// using b[0, P) as scratch: each wavefront sorts a segment of SEG values in
+// registers, then segments are merged pairwise, every value finding its place
+// by a binary search in the partner segment (ties: the left segment first).
+// Returns the buffer that holds the result.
+template <int NT>
+__device__ float* sort_window(float* a, float* b, int P) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nseg = min(NW, P / 64);
+    const int SEG = P / nseg;
+    __syncthreads();
+    if (w < nseg) {
+        switch (SEG / 64) {
+            case 1: wave_sort_segment<1>(a, w, lane); break;
+            case 2: wave_sort_segment<2>(a, w, lane); break;
+            case 4: wave_sort_segment<4>(a, w, lane); break;
+            case 8: wave_sort_segment<8>(a, w, lane); break;
+            default: wave_sort_segment<16>(a, w, lane); break;
+        }
+    }
+    __syncthreads();
+    for (int len = SEG; len < P; len <<= 1) {
+        for (int g = threadIdx.x; g < P; g += NT) {
+            const int r = g / len, p = g - r * len;
+            const float x = a[g];
+            const float* q = a + (r ^ 1) * len;
+            int lo = 0, hi = len;
+            if ((r & 1) == 0) {
+                while (lo < hi) {      // partner values < x
+                    const int m = (lo + hi) >> 1;
+                    if (q[m] < x) lo = m + 1;
+                    else hi = m;
+                }
+            } else {
+                while (lo < hi) {      // partner values <= x
+                    const int m = (lo + hi) >> 1;
+                    if (q[m] <= x) lo = m + 1;
+                    else hi = m;
+                }
+            }
+            b[(r & ~1) * len + p + lo] = x;
+        }
+        __syncthreads();
+        float* t = a;
+        a = b;
+        b = t;
+    }
+    return a;
 }
 
 // The pixels of a mesh as per-thread sorted runs in LDS: thread t holds
@@ -180,18 +257,20 @@ struct Runs {
     }
 };
 
-// Fill sh.buf with the values of ranks [ra, rb] (0-based, within the alive
-// set) and their bin-mates, sorted; returns the rank of buf[0] (>= 0) and the
-// count in m, or -1 when the gathered bins exceed the buffer.  The histogram
-// window [wlo, whi] only steers the binning (bins are clamped).
-template <int NT>
-__device__ int build_window(const Runs<NT>& run, float wlo, float whi, int ra, int rb, int& m, MeshShared& sh) {
+// Sort the values of ranks [ra, rb] (0-based, within the alive set) and their
+// bin-mates into a window; returns the rank of its first value (-1 when the
+// gathered bins exceed the buffer), its count in m and its storage in win.
+// each(f) calls f on every alive value of the thread.  The histogram window
+// [wlo, whi] only steers the binning (bins are clamped).
+template <int NT, typename Each>
+__device__ int build_window(Each&& each, float wlo, float whi, int ra, int rb, int& m, const float*& win,
+                            MeshShared& sh) {
     const int tid = threadIdx.x;
     for (int b = tid; b < kBins; b += NT) sh.hist[b] = 0u;
     if (tid == 0) sh.cnt = 0u;
     __syncthreads();
     const float scale = bin_scale(wlo, whi);
-    run.each([&](float x) { atomicAdd(&sh.hist[bin_of(x, wlo, scale)], 1u); });
+    each([&](float x) { atomicAdd(&sh.hist[bin_of(x, wlo, scale)], 1u); });
     __syncthreads();
     constexpr int per = kBins / NT;
     uint32_t c[per];
@@ -221,7 +300,7 @@ __device__ int build_window(const Runs<NT>& run, float wlo, float whi, int ra, i
     __syncthreads();
     const int b1 = sh.sel_bin[0], b2 = sh.sel_bin[1];
     const int base = (int)sh.sel_cum[0];
-    run.each([&](float x) {
+    each([&](float x) {
         const int b = bin_of(x, wlo, scale);
         if (b >= b1 && b <= b2) {
             const uint32_t s = atomicAdd(&sh.cnt, 1u);
@@ -231,11 +310,10 @@ __device__ int build_window(const Runs<NT>& run, float wlo, float whi, int ra, i
     __syncthreads();
     m = (int)sh.cnt;
     if (m > kBuf) return -1;
-    int P = 2;
+    int P = 64;
     while (P < m) P <<= 1;
     for (int i = m + tid; i < P; i += NT) sh.buf[i] = INFINITY;
-    __syncthreads();
-    sort_buf<NT>(sh.buf, P);
+    win = sort_window<NT>(sh.buf, sh.buf2, P);
     return base;
 }
 
@@ -345,22 +423,31 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
     float vhi = (cnt_t > 0) ? T[(cnt_t - 1) * NT + tid] : -INFINITY;
 
     int ncur = n;
-    int R0 = -1, bm = 0;      // rank of buf[0] in the alive set (-1: no window)
+    int R0 = -1, bm = 0;      // rank of win[0] in the alive set (-1: no window)
+    const float* win = sh.buf;
     float med_h, med_l;
     float lmn = mn, lmx = mx;
+    // every alive value of the thread: from its registers before the first
+    // clipping pass, from its run in LDS afterwards
+    auto each_reg = [&](auto&& f) __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+            if (k < cnt_t) f(v[k]);
+    };
+    auto each_run = [&](auto&& f) __attribute__((always_inline)) { run.each(f); };
     // exact median (an unevaluated pair when the count is even) of the alive
     // set, from the window, rebuilding it when the median has left it
-    auto median = [&](float wlo, float whi) __attribute__((always_inline)) {
+    auto median = [&](float wlo, float whi, auto&& each) __attribute__((always_inline)) {
         const int r2 = ncur / 2;
         const int r1 = (ncur & 1) ? r2 : r2 - 1;
         float o1, o2;
         if (R0 < 0 || r1 - R0 < 0 || r2 - R0 >= bm) {
-            R0 = build_window<NT>(run, wlo, whi, max(r1 - kHalf, 0), min(r2 + kHalf, ncur - 1), bm, sh);
-            if (R0 < 0) R0 = build_window<NT>(run, wlo, whi, r1, r2, bm, sh);
+            R0 = build_window<NT>(each, wlo, whi, max(r1 - kHalf, 0), min(r2 + kHalf, ncur - 1), bm, win, sh);
+            if (R0 < 0) R0 = build_window<NT>(each, wlo, whi, r1, r2, bm, win, sh);
         }
         if (R0 >= 0) {
-            o1 = sh.buf[r1 - R0];
-            o2 = sh.buf[r2 - R0];
+            o1 = win[r1 - R0];
+            o2 = win[r2 - R0];
         } else {
             bisect_pair<NT>(run, lmn, lmx, r1, r2, o1, o2, sh);
         }
@@ -376,7 +463,7 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
         }
     };
     // the median of all pixels lies within one sigma of their mean
-    median((float)(mean - sig0), (float)(mean + sig0));
+    median((float)(mean - sig0), (float)(mean + sig0), each_reg);
 
     int iters = 0;
     for (int it = 0; it < a.max_iter; ++it) {
@@ -414,7 +501,7 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
         const double vv = q2s / nd - q1 * q1;
         mean = cs + q1;
         sig = (lmn == lmx) ? 0.0 : sqrt(vv > 0.0 ? vv : 0.0);
-        median(lmn, lmx);
+        median(lmn, lmx, each_run);
     }
     if (tid == 0) {
         const double med = (double)med_h + (double)med_l;

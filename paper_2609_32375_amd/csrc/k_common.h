@@ -125,6 +125,13 @@ __device__ __forceinline__ void f2_acc(F2& a, float v) {
     a.hi = s;
     a.lo += e;
 }
+// make one wavefront's LDS writes visible to its other lanes
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 __device__ __forceinline__ double f2_d(F2 a) { return (double)a.hi + (double)a.lo; }
 
 // deterministic wavefront reductions (fixed butterfly order)
