@@ -469,9 +469,12 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
     for (int it = 0; it < a.max_iter; ++it) {
         const float thr = (float)((double)a.clip * sig);
         auto keep = [&](float x) { return fabsf((x - med_h) - med_l) <= thr; };
-        // clipping pass: move the run's ends inward
+        auto below = [&](float x) { return ((x - med_h) - med_l) < -thr; };
+        // clipping pass: move the run's ends inward.  Only values clipped for
+        // lying below the window shift the ranks of the survivors; a run
+        // lying wholly above it is emptied from the top.
         int rem = 0;
-        while (run.lo < run.hi && !keep(vlo)) {
+        while (run.lo < run.hi && below(vlo)) {
             const double e = (double)vlo - cs;
             t1 -= e;
             t2 = fma(-e, e, t2);
@@ -517,63 +520,79 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
 
 // ---------------------------------------------------------------------------
 // f x f median over the mesh grid, back and rms separately
-__device__ double median_small(double* w, int n) {
+// median of w[0], w[S], ..., w[(n-1) S] (insertion sort in place)
+__device__ double median_small(double* w, int n, int S) {
     for (int i = 1; i < n; ++i) {
-        double x = w[i];
+        const double x = w[i * S];
         int j = i - 1;
-        while (j >= 0 && w[j] > x) {
-            w[j + 1] = w[j];
+        while (j >= 0 && w[j * S] > x) {
+            w[(j + 1) * S] = w[j * S];
             --j;
         }
-        w[j + 1] = x;
+        w[(j + 1) * S] = x;
     }
-    return (n & 1) ? w[n / 2] : 0.5 * (w[n / 2 - 1] + w[n / 2]);
+    return (n & 1) ? w[(n / 2) * S] : 0.5 * (w[(n / 2 - 1) * S] + w[(n / 2) * S]);
 }
 
-__global__ void k_grid_filter(const FrameDesc* __restrict__ desc, int nframes, int total, int fsize) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
+// one thread per mesh; each thread's window sits in its own LDS column
+constexpr int kGridThreads = 64;
+__global__ __launch_bounds__(kGridThreads) void k_grid_filter(const FrameDesc* __restrict__ desc, int nframes,
+                                                              int total, int fsize) {
+    __shared__ double w[49 * kGridThreads];
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total) return;
     const int f = frame_of(nframes, g, [&](int i) { return desc[i].mesh_base; });
     const FrameDesc& d = desc[f];
     const int lm = g - d.mesh_base;
     const int i = lm % d.nx, j = lm / d.nx;
     const int hh = fsize / 2;
-    double w[49];
+    double* wt = w + threadIdx.x;
     for (int q = 0; q < 2; ++q) {
         const double* src = q ? d.rms_raw : d.back_raw;
         double* dst = q ? d.rms : d.back;
         int n = 0;
         for (int b = j - hh; b <= j + hh; ++b)
             for (int c = i - hh; c <= i + hh; ++c)
-                if (b >= 0 && b < d.ny && c >= 0 && c < d.nx) w[n++] = src[b * d.nx + c];
-        dst[lm] = median_small(w, n);
+                if (b >= 0 && b < d.ny && c >= 0 && c < d.nx) wt[(n++) * kGridThreads] = src[b * d.nx + c];
+        dst[lm] = median_small(wt, n, kGridThreads);
     }
 }
 
 // ---------------------------------------------------------------------------
 // natural spline second derivatives through (t_k, f_k), k < n, by Thomas
 // elimination; f and m are strided views, work holds 2n doubles
-__device__ void natural_second(int n, const double* t, const double* f, int fs, double* m, int ms,
-                               double* work) {
+__device__ void natural_second(int n, const double* t, const double* __restrict__ f, int fs,
+                               double* __restrict__ m, int ms, double* __restrict__ work) {
     for (int k = 0; k < n; ++k) m[k * ms] = 0.0;
     if (n < 3) return;
     double* c = work;
     double* r = work + n;
+    // forward sweep: the carried c[k-1], r[k-1] stay in registers
+    double cp = 0.0, rp = 0.0;
     for (int k = 1; k <= n - 2; ++k) {
-        double h0 = t[k] - t[k - 1], h1 = t[k + 1] - t[k];
-        double rhs = 6.0 * ((f[(k + 1) * fs] - f[k * fs]) / h1 - (f[k * fs] - f[(k - 1) * fs]) / h0);
-        double b = 2.0 * (h0 + h1);
+        const double h0 = t[k] - t[k - 1], h1 = t[k + 1] - t[k];
+        const double rhs = 6.0 * ((f[(k + 1) * fs] - f[k * fs]) / h1 - (f[k * fs] - f[(k - 1) * fs]) / h0);
+        const double b = 2.0 * (h0 + h1);
+        double ck, rk;
         if (k == 1) {
-            c[k] = h1 / b;
-            r[k] = rhs / b;
+            ck = h1 / b;
+            rk = rhs / b;
         } else {
-            double den = b - h0 * c[k - 1];
-            c[k] = h1 / den;
-            r[k] = (rhs - h0 * r[k - 1]) / den;
+            const double den = b - h0 * cp;
+            ck = h1 / den;
+            rk = (rhs - h0 * rp) / den;
         }
+        c[k] = ck;
+        r[k] = rk;
+        cp = ck;
+        rp = rk;
     }
-    m[(n - 2) * ms] = r[n - 2];
-    for (int k = n - 3; k >= 1; --k) m[k * ms] = r[k] - c[k] * m[(k + 1) * ms];
+    double mk = r[n - 2];
+    m[(n - 2) * ms] = mk;
+    for (int k = n - 3; k >= 1; --k) {
+        mk = r[k] - c[k] * mk;
+        m[k * ms] = mk;
+    }
 }
 
 // cubic of one spline piece in local coordinate s = t - ref:
@@ -700,7 +719,8 @@ void launch_mesh_stats(const FrameDesc* desc, int nframes, int total_meshes, int
 }
 
 void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, int fsize, hipStream_t s) {
-    k_grid_filter<<<(total_meshes + 255) / 256, 256, 0, s>>>(desc, nframes, total_meshes, fsize);
+    k_grid_filter<<<(total_meshes + kGridThreads - 1) / kGridThreads, kGridThreads, 0, s>>>(desc, nframes,
+                                                                                         total_meshes, fsize);
 }
 
 void launch_spline(const FrameDesc* desc, int nframes, int total_ycols, int total_xrows, hipStream_t s) {

@@ -864,29 +864,32 @@ __global__ void k_write_desc(DescChunk c, FrameDesc* table) {
 
 // the dense kernel is normalised here (sum in FP64, fixed order)
 __global__ void k_write_detargs(DetArgsIn in, DetArgs* out) {
-    if (threadIdx.x != 0) return;
-    out->kw = in.kw;
-    out->kh = in.kh;
-    out->separable = in.separable;
-    out->conn = in.conn;
-    out->thresh = in.thresh;
-    out->sat = in.sat;
-    out->minarea = in.minarea;
-    out->want_seg = in.want_seg;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        out->kw = in.kw;
+        out->kh = in.kh;
+        out->separable = in.separable;
+        out->conn = in.conn;
+        out->thresh = in.thresh;
+        out->sat = in.sat;
+        out->minarea = in.minarea;
+        out->want_seg = in.want_seg;
+    }
+    // every lane forms the same sum in the same order
     double sum = 0.0;
     const int n = in.kw * in.kh;
     for (int i = 0; i < n; ++i) sum += (double)in.kraw[i];
     const double norm = (sum != 0.0) ? sum : 1.0;
-    for (int i = 0; i < kMaxK * kMaxK; ++i) {
+    for (int i = t; i < kMaxK * kMaxK; i += blockDim.x) {
         const double v = (i < n) ? (double)in.kraw[i] / norm : 0.0;
         out->kdd[i] = v;
         out->kd[i] = (float)v;
     }
-    for (int i = 0; i < kMaxK; ++i) {
-        out->kx[i] = in.kx[i];
-        out->ky[i] = in.ky[i];
-        out->kxd[i] = in.kxd[i];
-        out->kyd[i] = in.kyd[i];
+    if (t < kMaxK) {
+        out->kx[t] = in.kx[t];
+        out->ky[t] = in.ky[t];
+        out->kxd[t] = in.kxd[t];
+        out->kyd[t] = in.kyd[t];
     }
 }
 
@@ -895,7 +898,7 @@ void launch_write_desc(const DescChunk& c, FrameDesc* table, hipStream_t s) {
 }
 
 void launch_write_detargs(const DetArgsIn& in, DetArgs* out, hipStream_t s) {
-    k_write_detargs<<<1, 64, 0, s>>>(in, out);
+    k_write_detargs<<<1, 256, 0, s>>>(in, out);
 }
 
 }  // namespace gpk
