@@ -88,7 +88,8 @@ typedef struct gp_frame {
  * truncated at the grid edges) and interpolated by natural cubic splines
  * through the mesh centres, first along y then along x, continued linearly
  * past the outer mesh centres.
- * Limits: 16 <= mesh_w, mesh_h; mesh_w * mesh_h <= 16384; filter_size <= 7. */
+ * Limits: 16 <= mesh_w, mesh_h; mesh_w * mesh_h <= 16384; filter_size <= 7;
+ * at most 4096 meshes along either axis of a frame (GP_ERR_UNSUPPORTED). */
 #define GP_BKG_GRID_GIVEN 1u   /* skip the mesh statistics and the filter: the
                                   caller has written the back/rms grids */
 typedef struct gp_bkg_params {

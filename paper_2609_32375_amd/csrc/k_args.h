@@ -5,6 +5,9 @@
 
 namespace gpk {
 
+// mesh centres per axis the spline kernels hold in LDS
+constexpr int kSplineMaxKnots = 4096;
+
 struct BkgArgs {
     float clip, crowd, mode_a, mode_b;
     int32_t max_iter;
@@ -63,7 +66,7 @@ struct CatOut {
 void launch_mesh_stats(const FrameDesc* desc, int nframes, int total_meshes, int max_area, BkgArgs a, int cfg,
                        hipStream_t s);
 void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, int fsize, hipStream_t s);
-void launch_spline(const FrameDesc* desc, int nframes, int total_ycols, int total_xrows, hipStream_t s);
+void launch_spline(const FrameDesc* desc, int nframes, int max_nx, int max_ny, hipStream_t s);
 void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, int rad, hipStream_t s);
 void launch_merge(const DetWork& wk, int conn, int minarea, int persist_blocks, hipStream_t s);

@@ -559,38 +559,46 @@ __global__ __launch_bounds__(kGridThreads) void k_grid_filter(const FrameDesc* _
 }
 
 // ---------------------------------------------------------------------------
-// natural spline second derivatives through (t_k, f_k), k < n, by Thomas
-// elimination; f and m are strided views, work holds 2n doubles
-__device__ void natural_second(int n, const double* t, const double* __restrict__ f, int fs,
-                               double* __restrict__ m, int ms, double* __restrict__ work) {
-    for (int k = 0; k < n; ++k) m[k * ms] = 0.0;
-    if (n < 3) return;
-    double* c = work;
-    double* r = work + n;
-    // forward sweep: the carried c[k-1], r[k-1] stay in registers
-    double cp = 0.0, rp = 0.0;
+// Natural spline second derivatives through (t_k, f_k), k < n, by Thomas
+// elimination.  The elimination factors depend on the knots only, so a block
+// computes them once into LDS (spline_factor) and every column then runs a
+// single dependent chain (spline_solve), its right-hand sides loaded ahead.
+__device__ void spline_factor(int n, const double* t, double* c, double* den) {
+    double cp = 0.0;
     for (int k = 1; k <= n - 2; ++k) {
         const double h0 = t[k] - t[k - 1], h1 = t[k + 1] - t[k];
-        const double rhs = 6.0 * ((f[(k + 1) * fs] - f[k * fs]) / h1 - (f[k * fs] - f[(k - 1) * fs]) / h0);
         const double b = 2.0 * (h0 + h1);
-        double ck, rk;
-        if (k == 1) {
-            ck = h1 / b;
-            rk = rhs / b;
-        } else {
-            const double den = b - h0 * cp;
-            ck = h1 / den;
-            rk = (rhs - h0 * rp) / den;
-        }
-        c[k] = ck;
-        r[k] = rk;
-        cp = ck;
-        rp = rk;
+        const double dk = (k == 1) ? b : b - h0 * cp;
+        den[k] = dk;
+        cp = h1 / dk;
+        c[k] = cp;
     }
-    double mk = r[n - 2];
+}
+
+// f at stride fs; r (work) and m (result) at stride ms
+__device__ void spline_solve(int n, const double* t, const double* c, const double* den,
+                             const double* __restrict__ f, int fs, double* __restrict__ r,
+                             double* __restrict__ m, int ms) {
+    m[0] = 0.0;
+    if (n > 1) m[(n - 1) * ms] = 0.0;
+    if (n < 3) return;
+    double rp = 0.0;
+    double f0 = f[0], f1 = f[fs];
+#pragma unroll 4
+    for (int k = 1; k <= n - 2; ++k) {
+        const double f2 = f[(k + 1) * fs];
+        const double h0 = t[k] - t[k - 1], h1 = t[k + 1] - t[k];
+        const double rhs = 6.0 * ((f2 - f1) / h1 - (f1 - f0) / h0);
+        rp = (k == 1) ? rhs / den[k] : (rhs - h0 * rp) / den[k];
+        r[k * ms] = rp;
+        f0 = f1;
+        f1 = f2;
+    }
+    double mk = rp;
     m[(n - 2) * ms] = mk;
+#pragma unroll 4
     for (int k = n - 3; k >= 1; --k) {
-        mk = r[k] - c[k] * mk;
+        mk = r[k * ms] - c[k] * mk;
         m[k * ms] = mk;
     }
 }
@@ -626,35 +634,30 @@ __device__ void piece_poly(int n, const double* t, const double* f, int fs, cons
     out[3] = (mj1 - mj) / (6.0 * h);
 }
 
-// y-splines: one thread per (frame, quantity, mesh column); knots are
-// recomputed here from the mesh geometry (at most 4096 per axis)
-__global__ void k_spline_y(const FrameDesc* __restrict__ desc, int nframes, int total) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    // flattened over frames with 2 * nx entries each; base = 2 * sum(nx)
-    int f = 0;
-    {
-        int acc = 0;
-        for (; f < nframes; ++f) {
-            int c = 2 * desc[f].nx;
-            if (g < acc + c) break;
-            acc += c;
-        }
-        g -= acc;
-    }
-    const FrameDesc& d = desc[f];
-    const int q = g / d.nx, i = g % d.nx;
+constexpr int kSplThreads = 256;
+
+// y-splines: blockIdx.y = frame; one thread per (quantity, mesh column)
+__global__ __launch_bounds__(kSplThreads) void k_spline_y(const FrameDesc* __restrict__ desc) {
+    __shared__ double tk[kSplineMaxKnots], cf[kSplineMaxKnots], dn[kSplineMaxKnots];
+    const FrameDesc& d = desc[blockIdx.y];
     const int ny = d.ny, nx = d.nx;
-    const double* grid = q ? d.rms : d.back;
-    double* scr = d.scratch + (size_t)(q * nx + i) * (size_t)(4 * ny);
-    double* tk = scr;            // knots
-    double* mm = scr + ny;       // second derivatives
-    double* wk = scr + 2 * ny;   // 2 ny work
-    for (int k = 0; k < ny; ++k) tk[k] = knot_at(k, d.H, d.mh);
-    natural_second(ny, tk, grid + i, nx, mm, 1, wk);
+    if (blockIdx.x * kSplThreads >= 2 * nx) return;
+    for (int k = threadIdx.x; k < ny; k += kSplThreads) tk[k] = knot_at(k, d.H, d.mh);
+    __syncthreads();
+    if (threadIdx.x == 0) spline_factor(ny, tk, cf, dn);
+    __syncthreads();
+    const int g = blockIdx.x * kSplThreads + threadIdx.x;
+    if (g >= 2 * nx) return;
+    const int q = g / nx, i = g - q * nx;
+    const double* col = (q ? d.rms : d.back) + i;
+    // scratch [k][g]: work then second derivatives, 2 nx columns each
+    double* r = d.scratch + g;
+    double* mm = d.scratch + (size_t)2 * nx * ny + g;
+    spline_solve(ny, tk, cf, dn, col, nx, r, mm, 2 * nx);
+#pragma unroll 4
     for (int jy = 0; jy <= ny; ++jy) {
         double c[4];
-        piece_poly(ny, tk, grid + i, nx, mm, 1, jy, c);
+        piece_poly(ny, tk, col, nx, mm, 2 * nx, jy, c);
         double* o = d.ycoef + (((size_t)q * (ny + 1) + jy) * nx + i) * 4;
         o[0] = c[0];
         o[1] = c[1];
@@ -668,34 +671,31 @@ __global__ void k_spline_y(const FrameDesc* __restrict__ desc, int nframes, int 
 // coefficient vector (one natural spline per (quantity, jy, power of u)) gives
 // the bicubic pieces directly: coef[q][jy][ix][p*4+r] = x-piece p coefficient
 // of the spline through (ycoef[q][jy][k][r])_k.  Exact on constant grids.
-__global__ void k_spline_x(const FrameDesc* __restrict__ desc, int nframes, int total) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    int f = 0;
-    {
-        int acc = 0;
-        for (; f < nframes; ++f) {
-            int c = 2 * (desc[f].ny + 1) * 4;
-            if (g < acc + c) break;
-            acc += c;
-        }
-        g -= acc;
-    }
-    const FrameDesc& d = desc[f];
+// blockIdx.y = frame; one thread per (quantity, jy, power).
+__global__ __launch_bounds__(kSplThreads) void k_spline_x(const FrameDesc* __restrict__ desc) {
+    __shared__ double tk[kSplineMaxKnots], cf[kSplineMaxKnots], dn[kSplineMaxKnots];
+    const FrameDesc& d = desc[blockIdx.y];
     const int nx = d.nx, ny = d.ny;
+    const int G = 8 * (ny + 1);
+    if (blockIdx.x * kSplThreads >= G) return;
+    for (int k = threadIdx.x; k < nx; k += kSplThreads) tk[k] = knot_at(k, d.W, d.mw);
+    __syncthreads();
+    if (threadIdx.x == 0) spline_factor(nx, tk, cf, dn);
+    __syncthreads();
+    const int g = blockIdx.x * kSplThreads + threadIdx.x;
+    if (g >= G) return;
     const int r = g & 3;
     const int jy = (g >> 2) % (ny + 1);
     const int q = (g >> 2) / (ny + 1);
-    double* scr = d.scratch + (size_t)(2 * nx) * (size_t)(4 * ny) + (size_t)g * (size_t)(4 * nx);
-    double* tk = scr;
-    double* mm = scr + nx;
-    double* wk = scr + 2 * nx;
-    for (int j = 0; j < nx; ++j) tk[j] = knot_at(j, d.W, d.mw);
+    double* base = d.scratch + (size_t)8 * nx * ny;   // after the y-spline scratch
+    double* w = base + g;                               // [k][g], G columns
+    double* mm = base + (size_t)G * nx + g;
     const double* vals = d.ycoef + (((size_t)q * (ny + 1) + jy) * nx) * 4 + r;  // stride 4
-    natural_second(nx, tk, vals, 4, mm, 1, wk);
+    spline_solve(nx, tk, cf, dn, vals, 4, w, mm, G);
+#pragma unroll 4
     for (int ix = 0; ix <= nx; ++ix) {
         double c[4];
-        piece_poly(nx, tk, vals, 4, mm, 1, ix, c);
+        piece_poly(nx, tk, vals, 4, mm, G, ix, c);
         double* o = d.coef + (((size_t)q * (ny + 1) + jy) * (nx + 1) + ix) * 16;
         for (int p = 0; p < 4; ++p) o[p * 4 + r] = c[p];
     }
@@ -723,9 +723,9 @@ void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, in
                                                                                          total_meshes, fsize);
 }
 
-void launch_spline(const FrameDesc* desc, int nframes, int total_ycols, int total_xrows, hipStream_t s) {
-    k_spline_y<<<(total_ycols + 63) / 64, 64, 0, s>>>(desc, nframes, total_ycols);
-    k_spline_x<<<(total_xrows + 63) / 64, 64, 0, s>>>(desc, nframes, total_xrows);
+void launch_spline(const FrameDesc* desc, int nframes, int max_nx, int max_ny, hipStream_t s) {
+    k_spline_y<<<dim3((2 * max_nx + kSplThreads - 1) / kSplThreads, nframes), kSplThreads, 0, s>>>(desc);
+    k_spline_x<<<dim3((8 * (max_ny + 1) + kSplThreads - 1) / kSplThreads, nframes), kSplThreads, 0, s>>>(desc);
 }
 
 // ---------------------------------------------------------------------------

@@ -113,6 +113,7 @@ struct Plan {
     int64_t total_meshes = 0, total_tiles = 0, total_blocks = 0, total_ycols = 0, total_xrows = 0,
             total_px = 0;
     int max_area = 0;
+    int max_nx = 0, max_ny = 0;
     size_t bkg_bytes = 0;
     // workspace sections
     size_t o_desc = 0, o_detargs = 0, o_counters = 0, o_tiles = 0, o_edges = 0, o_recs = 0, o_parent = 0,
@@ -137,7 +138,7 @@ gp_status check_frames(const gp_frame* frames, int32_t nframes) {
     return GP_OK;
 }
 
-gp_status check_bkg(const gp_bkg_params* bp) {
+gp_status check_bkg(const gp_bkg_params* bp, const gp_frame* frames, int32_t nframes) {
     if (!bp) return fail(GP_ERR_INVALID_ARG, "background parameters are NULL");
     if (bp->mesh_w < 16 || bp->mesh_h < 16)
         return fail(GP_ERR_UNSUPPORTED, "mesh %dx%d: meshes must be at least 16 pixels", bp->mesh_w, bp->mesh_h);
@@ -150,6 +151,13 @@ gp_status check_bkg(const gp_bkg_params* bp) {
     if (!std::isfinite(bp->crowd_tol) || !std::isfinite(bp->mode_a) || !std::isfinite(bp->mode_b))
         return fail(GP_ERR_INVALID_ARG, "non-finite background parameter");
     if (bp->max_iter < 0) return fail(GP_ERR_INVALID_ARG, "max_iter must be >= 0");
+    for (int f = 0; f < nframes; ++f) {
+        const int64_t nx = ceil_div((int64_t)frames[f].width, bp->mesh_w);
+        const int64_t ny = ceil_div((int64_t)frames[f].height, bp->mesh_h);
+        if (nx > kSplineMaxKnots || ny > kSplineMaxKnots)
+            return fail(GP_ERR_UNSUPPORTED, "frame %d: %lldx%lld meshes, at most %d per axis", f, (long long)nx,
+                        (long long)ny, kSplineMaxKnots);
+    }
     return GP_OK;
 }
 
@@ -209,6 +217,8 @@ void plan_bkg(const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp, 
         P.total_meshes += F.meshes;
         P.total_ycols += 2 * F.nx;
         P.total_xrows += 2 * (int64_t)(F.ny + 1) * 4;
+        P.max_nx = std::max(P.max_nx, F.nx);
+        P.max_ny = std::max(P.max_ny, F.ny);
         const int mw = std::min(bp->mesh_w, W), mh = std::min(bp->mesh_h, H);
         P.max_area = std::max(P.max_area, mw * mh);
         F.ntx = (int)ceil_div(W, kTile);
@@ -398,7 +408,7 @@ extern "C" gp_status gp_background_layout(const gp_frame* frames, int32_t nframe
                                           gp_bkg_layout* layouts, size_t* bytes) {
     gp_status st;
     if ((st = check_frames(frames, nframes)) != GP_OK) return st;
-    if ((st = check_bkg(bp)) != GP_OK) return st;
+    if ((st = check_bkg(bp, frames, nframes)) != GP_OK) return st;
     Plan P;
     plan_bkg(frames, nframes, bp, P);
     if (layouts)
@@ -426,7 +436,7 @@ extern "C" gp_status gp_workspace_size(gp_ctx* ctx, const gp_frame* frames, int3
     if (!bytes) return fail(GP_ERR_INVALID_ARG, "bytes is NULL");
     gp_status st;
     if ((st = check_frames(frames, nframes)) != GP_OK) return st;
-    if ((st = check_bkg(bp)) != GP_OK) return st;
+    if ((st = check_bkg(bp, frames, nframes)) != GP_OK) return st;
     if (dp && (st = check_det(dp)) != GP_OK) return st;
     if (ap && (st = check_ap(ap)) != GP_OK) return st;
     if (cat_capacity < 0) return fail(GP_ERR_INVALID_ARG, "cat_capacity < 0");
@@ -445,7 +455,7 @@ extern "C" gp_status gp_background(gp_ctx* ctx, const gp_frame* frames, int32_t 
     if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
     gp_status st;
     if ((st = check_frames(frames, nframes)) != GP_OK) return st;
-    if ((st = check_bkg(bp)) != GP_OK) return st;
+    if ((st = check_bkg(bp, frames, nframes)) != GP_OK) return st;
     if (!bkg) return fail(GP_ERR_INVALID_ARG, "background buffer is NULL");
     Plan P;
     plan_bkg(frames, nframes, bp, P);
@@ -471,7 +481,7 @@ extern "C" gp_status gp_background(gp_ctx* ctx, const gp_frame* frames, int32_t 
     }
     {
         ProfScope ps(ctx, s, "spline");
-        launch_spline(desc, nframes, (int)P.total_ycols, (int)P.total_xrows, s);
+        launch_spline(desc, nframes, P.max_nx, P.max_ny, s);
     }
     HIP_TRY(hipGetLastError());
     return GP_OK;
@@ -483,7 +493,7 @@ extern "C" gp_status gp_background_map(gp_ctx* ctx, const gp_frame* frames, int3
     if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
     gp_status st;
     if ((st = check_frames(frames, nframes)) != GP_OK) return st;
-    if ((st = check_bkg(bp)) != GP_OK) return st;
+    if ((st = check_bkg(bp, frames, nframes)) != GP_OK) return st;
     if (!bkg) return fail(GP_ERR_INVALID_ARG, "background buffer is NULL");
     if (index < 0 || index >= nframes) return fail(GP_ERR_INVALID_ARG, "frame index %d of %d", index, nframes);
     if (precision != GP_PREC_F32 && precision != GP_PREC_F64)
@@ -526,7 +536,7 @@ extern "C" gp_status gp_detect(gp_ctx* ctx, const gp_frame* frames, int32_t nfra
     if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
     gp_status st;
     if ((st = check_frames(frames, nframes)) != GP_OK) return st;
-    if ((st = check_bkg(bp)) != GP_OK) return st;
+    if ((st = check_bkg(bp, frames, nframes)) != GP_OK) return st;
     if ((st = check_det(dp)) != GP_OK) return st;
     if ((st = check_cat(cat, true)) != GP_OK) return st;
     if (!bkg) return fail(GP_ERR_INVALID_ARG, "background buffer is NULL");
@@ -619,7 +629,7 @@ extern "C" gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nf
     if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
     gp_status st;
     if ((st = check_frames(frames, nframes)) != GP_OK) return st;
-    if ((st = check_bkg(bp)) != GP_OK) return st;
+    if ((st = check_bkg(bp, frames, nframes)) != GP_OK) return st;
     if ((st = check_ap(ap)) != GP_OK) return st;
     if ((st = check_cat(cat, false)) != GP_OK) return st;
     if (!out || !out->flux || !out->area || !out->bkg) return fail(GP_ERR_INVALID_ARG, "photometry output is NULL");
