@@ -58,6 +58,8 @@ struct DetShared {
     uint64_t rowmask[kTile];
     int32_t rowoff[kTile + 1];
     int32_t misc[4];
+    int32_t colp[kRegion];      // x piece of each region column (relative to the first)
+    Real colsx[kRegion];        // its local coordinate in that piece
 };
 
 // find with path halving: every link points to a smaller index, so writing a
@@ -169,7 +171,19 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     const int ixlo = piece_of(xs_lo, d.W, d.mw);
     const int nix = piece_of(xs_hi, d.W, d.mw) - ixlo + 1;
 
-    // 1. per region row and x piece: the row's cubic (FP64 -> working precision)
+    // 1. the region's pixels (tile + halo, reflected at the frame border),
+    //    flattened over the block so the loads coalesce and are all in flight
+    //    while the row cubics and the column pieces are built
+    constexpr int REG = kSep ? kTile + 2 * kR : kRegion;   // region row stride
+    constexpr int NL = (REG * REG + 255) / 256;
+    float pv[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int e = tid + 256 * i;
+        const int r = e / REG, c = e - r * REG;
+        pv[i] = (r < RH && c < RW) ? load_px(d, reflect_idx(x0 - rx + c, d.W), reflect_idx(y0 - ry + r, d.H))
+                                   : 0.0f;
+    }
     for (int e = tid; e < RH * nix; e += 256) {
         const int r = e / nix, pi = e - r * nix;
         const int ys = reflect_idx(y0 - ry + r, d.H);
@@ -177,30 +191,20 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
         const double u = (double)ys - piece_ref(jy, d.H, d.mh);
         sh.u1.tab[r * kNixMax + pi] = make_row<Real>(d.coef, d.nx, d.ny, ixlo + pi, jy, u);
     }
+    for (int c = tid; c < RW; c += 256) {
+        const int xs = reflect_idx(x0 - rx + c, d.W);
+        const int ix = piece_of(xs, d.W, d.mw);
+        sh.colp[c] = ix - ixlo;
+        sh.colsx[c] = (Real)((double)xs - piece_ref(ix, d.W, d.mw));
+    }
     __syncthreads();
-    // 2. M = I - B over tile + halo; lanes own region columns lane and lane + 64
+    // 2. M = I - B over the region
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        const int c = lane + 64 * half;
-        if (c < RW) {
-            const int xs = reflect_idx(x0 - rx + c, d.W);
-            const int ix = piece_of(xs, d.W, d.mw);
-            const int pc = ix - ixlo;
-            const Real sx = (Real)((double)xs - piece_ref(ix, d.W, d.mw));
-            // issue all of this column's loads before using any of them
-            constexpr int NR = (kRegion + 3) / 4;
-            float vals[NR];
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                const int r = wv + 4 * i;
-                vals[i] = (r < RH) ? load_px(d, xs, reflect_idx(y0 - ry + r, d.H)) : 0.0f;
-            }
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                const int r = wv + 4 * i;
-                if (r < RH) sh.u2.ms[r * MS + c] = eval_M(sh.u1.tab[r * kNixMax + pc], sx, (Real)vals[i]);
-            }
-        }
+    for (int i = 0; i < NL; ++i) {
+        const int e = tid + 256 * i;
+        const int r = e / REG, c = e - r * REG;
+        if (r < RH && c < RW)
+            sh.u2.ms[r * MS + c] = eval_M(sh.u1.tab[r * kNixMax + sh.colp[c]], sh.colsx[c], (Real)pv[i]);
     }
     // thresholds t R of the 16 pixels this lane owns: column `lane`, rows 16 wv ..
     const bool colok = lane < tw;
@@ -355,9 +359,17 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
         if (lane == 0) sh.rowoff[16 * wv + k + 1] = __popcll(rb[k]);
     }
     __syncthreads();
-    if (tid == 0) {
-        sh.rowoff[0] = 0;
-        for (int y = 1; y <= kTile; ++y) sh.rowoff[y] += sh.rowoff[y - 1];
+    if (wv == 0) {
+        // rows' root counts -> exclusive offsets (one wavefront, lane = row)
+        const int cnt = sh.rowoff[lane + 1];
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        sh.rowoff[lane + 1] = incl;
+        if (lane == 0) sh.rowoff[0] = 0;
     }
     __syncthreads();
     const int ncomp = sh.rowoff[kTile];
