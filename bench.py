@@ -229,12 +229,16 @@ def main():
         "kernels_ms": {k: round(v, 4) for k, v in kern.items()},
         "roofline": roof,
     }
+    out["copy_ceiling_gbs"] = round(copy_ceiling(torch), 1)
     if not a.no_forms:
         gms = graph_time(torch, step, a.steps, a.warmup)
         out["forms"] = {"plain": {"mp_s": round(value, 1), "ms": round(ms, 4)},
                         "graph": {"mp_s": round(mp / (gms / 1e3), 1), "ms": round(gms, 4)}}
         ph.close()
-        del ph, dev
+        del ph
+        torch.cuda.empty_cache()
+        out["forms"]["f64_variant"] = f64_variant(torch, dev, p, K, cap, a)
+        del dev
         torch.cuda.empty_cache()
         out["forms"]["batched"] = form_batched(torch, a)
         torch.cuda.empty_cache()
@@ -242,6 +246,49 @@ def main():
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(fr, a.cpu_crop)
     print(json.dumps(out), flush=True)
+
+
+def copy_ceiling(torch, mib=1024, reps=10):
+    """Read + write GB/s of a plain elementwise copy (torch.neg) of `mib` MiB:
+    the practical HBM ceiling next to the 8 TB/s peak."""
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.neg(x, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    return gbs
+
+
+def f64_variant(torch, dev, p, K, cap, a):
+    """The same step with the detection and aperture kernels in FP64."""
+    from paper_2609_32375_amd import _lib as L
+    from paper_2609_32375_amd.pipeline import Photometry
+    ph = Photometry([dev], p, K, capacity=cap, precision=L.GP_PREC_F64)
+    for _ in range(2):
+        ph.run()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = max(3, a.steps // 4)
+    e0.record()
+    for _ in range(reps):
+        ph.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ph.close()
+    H, W = dev.shape
+    log(f"f64 variant: {ms:.3f} ms/step")
+    return {"ms": round(ms, 4), "mp_s": round(W * H / 1e6 / (ms / 1e3), 1)}
 
 
 def graph_time(torch, step, steps, warmup):
@@ -281,13 +328,16 @@ def form_batched(torch, a):
     p = config_params("c1")
     K = p.kernel()
     mp = sum(f.shape[0] * f.shape[1] for f in frames) / 1e6
-    batch = Photometry(frames, p, K, capacity=65536)
+    tune_path = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"gpphot_tune_{os.getpid()}.json")
+    batch = Photometry(frames, p, K, capacity=65536, autotune=True, tune_cache=tune_path)
+    tuned = json.load(open(tune_path)) if os.path.exists(tune_path) else {}
+    log(f"autotuned launch shapes: {tuned}")
     bms = graph_time(torch, batch.run, max(3, a.steps // 4), 2)
     nobj = [batch.results(i)["n_obj"] for i in range(len(frames))]
     batch.close()
     del batch
     torch.cuda.empty_cache()
-    singles = [Photometry([f], p, K, capacity=65536) for f in frames]
+    singles = [Photometry([f], p, K, capacity=65536, tune_cache=tune_path) for f in frames]
     for s in singles:
         s.run()
     torch.cuda.synchronize()
@@ -305,7 +355,7 @@ def form_batched(torch, a):
     return {"workload": "64 uint16 frames: 24 x 2048^2, 24 x 4096^2, 16 x 9600x6400; c1 parameters",
             "mp": round(mp, 2), "objects": int(sum(nobj)), "ms": round(bms, 3), "mp_s": round(mp / bms * 1e3, 1),
             "plain_ms": round(pms, 3), "plain_mp_s": round(mp / pms * 1e3, 1),
-            "speedup_vs_plain": round(pms / bms, 3)}
+            "speedup_vs_plain": round(pms / bms, 3), "autotuned": tuned}
 
 
 def form_served(torch, a):
@@ -350,6 +400,26 @@ def form_served(torch, a):
     done = srv.run(reqs_of(times))
     open_lat = latency_stats(done)
     srv.close()
+    # a 4 GB HBM budget, which binds: admission holds requests back
+    srv4 = Server(params["c1"], kernels["c1"], capacity=cap, slots=8, streams=2, hbm_budget=4 << 30)
+    srv4.run(reqs_of(np.zeros(len(kinds))))
+    t = time.perf_counter()
+    done = srv4.run(reqs_of(np.zeros(len(kinds))))
+    b4_s = time.perf_counter() - t
+    b4_lat = latency_stats(done)
+    srv4.close()
+    # host-sourced: the frames come from host memory (H2D inside the request)
+    host = {k: [pools[k][j].cpu().numpy() for j in range(3)] for k in shp}
+    hreqs = lambda arr: [Request(i, host[k][i % 3], arrival=t, params=params[k], kernel=kernels[k])
+                         for i, (t, k) in enumerate(zip(arr, kinds))]
+    srvh = Server(params["c1"], kernels["c1"], capacity=cap, slots=8, streams=2)
+    srvh.run(hreqs(np.zeros(len(kinds))))
+    t = time.perf_counter()
+    done = srvh.run(hreqs(np.zeros(len(kinds))))
+    host_s = time.perf_counter() - t
+    host_lat = latency_stats(done)
+    srvh.close()
+    log(f"served with a 4 GB budget: {mp / b4_s:.0f} MP/s; host-sourced: {mp / host_s:.0f} MP/s")
     log(f"served: saturating {mp / sat_s:.0f} MP/s vs plain {mp / plain_s:.0f} MP/s; open-loop {open_lat}")
     return {"workload": f"{len(kinds)} requests, shapes uniform over 2048^2 / 6144^2 / 12300^2 uint16, "
                         f"device-resident, Poisson 4/s over {a.stream_seconds:.0f} s",
@@ -358,6 +428,11 @@ def form_served(torch, a):
             "saturating_p50_ms": round(sat_lat.get("p50_ms", 0), 2),
             "saturating_p99_ms": round(sat_lat.get("p99_ms", 0), 2),
             "p50_ms": round(open_lat.get("p50_ms", 0), 2), "p99_ms": round(open_lat.get("p99_ms", 0), 2),
+            "budget_4gb": {"saturating_mp_s": round(mp / b4_s, 1), "p50_ms": round(b4_lat.get("p50_ms", 0), 2),
+                           "p99_ms": round(b4_lat.get("p99_ms", 0), 2)},
+            "host_sourced": {"saturating_mp_s": round(mp / host_s, 1),
+                             "p50_ms": round(host_lat.get("p50_ms", 0), 2),
+                             "p99_ms": round(host_lat.get("p99_ms", 0), 2)},
             "slots": 8, "streams": 2}
 
 

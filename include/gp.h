@@ -181,8 +181,19 @@ typedef struct gp_phot {
 typedef struct gp_ctx gp_ctx;
 
 /* Create a context on HIP device `device`.  tune_cache: path of the JSON file
- * holding autotuned launch shapes (NULL: built-in defaults). */
+ * holding autotuned launch shapes (NULL: built-in defaults); read here when it
+ * exists, rewritten whenever tuning adds a choice. */
 gp_status gp_ctx_create(int device, const char* tune_cache, gp_ctx** out);
+
+/* Autotuning switch (default off).  While on, a gp_background or gp_aperture
+ * call whose shape class (mesh area; radii count, r_max, mesh width and
+ * precision) has no choice yet times every candidate launch shape of its
+ * kernel (mesh statistics: threads x pixels per thread; apertures: workgroups
+ * per CU), each twice, synchronously on the call's stream, and keeps the
+ * fastest for the context and the cache.  Outputs are those of an ordinary
+ * call.  Skipped while the stream is being captured into a graph.  Not a hot
+ * path entry: tune once, then switch it off. */
+gp_status gp_ctx_set_tuning(gp_ctx* ctx, int32_t on);
 void gp_ctx_destroy(gp_ctx* ctx);
 
 /* Message of the last error on this host thread ("" if none). */

@@ -66,7 +66,7 @@ class gp_phot(C.Structure):
 EXPORTS = ("gp_ctx_create", "gp_ctx_destroy", "gp_last_error", "gp_version", "gp_background_layout",
            "gp_workspace_size", "gp_background", "gp_background_map", "gp_detect", "gp_aperture",
            "gp_profile_enable",
-           "gp_profile_read", "gp_profile_reset")
+           "gp_profile_read", "gp_profile_reset", "gp_ctx_set_tuning")
 
 _lib = None
 
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
                               C.POINTER(gp_catalog), C.POINTER(gp_ap_params), C.POINTER(gp_phot), vp,
                               C.c_size_t, vp]
     L.gp_profile_enable.argtypes = [vp, C.c_int]
+    L.gp_ctx_set_tuning.argtypes = [vp, i32]
     L.gp_profile_read.argtypes = [vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)]
     L.gp_profile_reset.argtypes = [vp]
     for f in ("gp_ctx_create", "gp_background_layout", "gp_workspace_size", "gp_background",
@@ -181,6 +182,10 @@ def gp_aperture(ctx, frames, bp, bkg_ptr, cat, ap, phot, ws_ptr, ws_bytes, strea
     arr = (gp_frame * n)(*frames)
     check(load().gp_aperture(ctx, arr, n, C.byref(bp), bkg_ptr, C.byref(cat), C.byref(ap), C.byref(phot),
                              ws_ptr, ws_bytes, stream))
+
+
+def gp_ctx_set_tuning(ctx, on: bool):
+    check(load().gp_ctx_set_tuning(ctx, 1 if on else 0))
 
 
 def gp_profile_enable(ctx, on: bool):

@@ -62,6 +62,8 @@ struct gp_ctx {
     std::map<std::string, std::pair<double, int64_t>> totals;
     std::string tune_path;
     int mesh_cfg = 0;     // launch shape of the mesh-statistics kernel (0 = automatic)
+    bool tuning = false;  // time the candidates of a shape class not yet in `tuned`
+    std::map<std::string, int> tuned;   // shape class -> chosen launch shape
 };
 
 namespace {
@@ -377,6 +379,93 @@ gp_status check_ws(const Plan& P, void* ws, size_t ws_bytes) {
 
 }  // namespace
 
+namespace {
+// The tune cache is a flat JSON object {"<shape class>": <choice>, ...}.
+void tune_load(gp_ctx* c) {
+    FILE* fh = std::fopen(c->tune_path.c_str(), "r");
+    if (!fh) return;
+    std::string txt;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, fh)) > 0) txt.append(buf, n);
+    std::fclose(fh);
+    size_t i = 0;
+    while ((i = txt.find('"', i)) != std::string::npos) {
+        const size_t j = txt.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const std::string key = txt.substr(i + 1, j - i - 1);
+        size_t k = txt.find(':', j);
+        if (k == std::string::npos) break;
+        c->tuned[key] = (int)std::strtol(txt.c_str() + k + 1, nullptr, 10);
+        i = txt.find_first_of(",}", k);
+        if (i == std::string::npos) break;
+    }
+}
+
+void tune_save(gp_ctx* c) {
+    if (c->tune_path.empty()) return;
+    const std::string tmp = c->tune_path + ".tmp";
+    FILE* fh = std::fopen(tmp.c_str(), "w");
+    if (!fh) return;
+    std::fputs("{", fh);
+    bool first = true;
+    for (const auto& kv : c->tuned) {
+        std::fprintf(fh, "%s\n \"%s\": %d", first ? "" : ",", kv.first.c_str(), kv.second);
+        first = false;
+    }
+    std::fputs("\n}\n", fh);
+    std::fclose(fh);
+    std::rename(tmp.c_str(), c->tune_path.c_str());
+}
+
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+// The choice for a shape class: the cached one, else (tuning on, not under
+// graph capture) the fastest candidate, each timed on the call's stream after
+// a warm-up launch, else `fallback`.
+template <typename Launch>
+int choose(gp_ctx* c, const std::string& key, const std::vector<int>& cands, int fallback, hipStream_t s,
+           Launch&& launch) {
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end()) return it->second;
+    if (!c->tuning || cands.size() < 2 || capturing(s)) return fallback;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fallback;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fallback;
+    }
+    int best = fallback;
+    float best_ms = 1e30f;
+    for (int cand : cands) {
+        launch(cand);
+        (void)hipEventRecord(e0, s);
+        launch(cand);
+        (void)hipEventRecord(e1, s);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+            ms < best_ms) {
+            best_ms = ms;
+            best = cand;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->tuned[key] = best;
+    tune_save(c);
+    return best;
+}
+}  // namespace
+
+extern "C" gp_status gp_ctx_set_tuning(gp_ctx* ctx, int32_t on) {
+    if (!ctx) return fail(GP_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->tuning = on != 0;
+    return GP_OK;
+}
+
 extern "C" gp_status gp_ctx_create(int device, const char* tune_cache, gp_ctx** out) {
     if (!out) return fail(GP_ERR_INVALID_ARG, "out is NULL");
     int n = 0;
@@ -389,7 +478,10 @@ extern "C" gp_status gp_ctx_create(int device, const char* tune_cache, gp_ctx** 
     gp_ctx* c = new gp_ctx;
     c->device = device;
     c->cus = prop.multiProcessorCount;
-    if (tune_cache) c->tune_path = tune_cache;
+    if (tune_cache) {
+        c->tune_path = tune_cache;
+        tune_load(c);
+    }
     *out = c;
     return GP_OK;
 }
@@ -470,7 +562,18 @@ extern "C" gp_status gp_background(gp_ctx* ctx, const gp_frame* frames, int32_t 
         BkgArgs a{bp->clip_sigma, bp->crowd_tol, bp->mode_a, bp->mode_b, bp->max_iter, bp->filter_size};
         {
             ProfScope ps(ctx, s, "mesh_stats");
-            launch_mesh_stats(desc, nframes, (int)P.total_meshes, P.max_area, a, ctx->mesh_cfg, s);
+            std::vector<int> cands;
+            if (P.max_area <= 4096) cands.push_back(1);
+            if (P.max_area <= 8192) cands.push_back(2);
+            cands.push_back(3);
+            cands.push_back(4);
+            const int cfg = ctx->mesh_cfg ? ctx->mesh_cfg
+                                          : choose(ctx, "mesh_stats:" + std::to_string(P.max_area), cands, 0, s,
+                                                   [&](int k) {
+                                                       launch_mesh_stats(desc, nframes, (int)P.total_meshes,
+                                                                         P.max_area, a, k, s);
+                                                   });
+            launch_mesh_stats(desc, nframes, (int)P.total_meshes, P.max_area, a, cfg, s);
         }
         HIP_TRY(hipGetLastError());
         {
@@ -672,13 +775,20 @@ extern "C" gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nf
     }
     ApCat c{cat->n_obj, cat->x, cat->y, cat->flags, out->flux, out->area, out->bkg, out->fluxerr};
     const int total_rows = nframes * cat->capacity;
-    const int blocks = std::max(1, std::min(ctx->cus * 8, (total_rows + 3) / 4));
     {
         ProfScope ps(ctx, s, "aperture");
         int max_nx = 1;
         for (int i = 0; i < nframes; ++i) max_nx = std::max(max_nx, (frames[i].width + bp->mesh_w - 1) / bp->mesh_w);
-        launch_aperture((const FrameDesc*)((char*)ws + P.o_desc), a, c, total_rows, blocks, bp->mesh_w, max_nx,
-                        ap->precision == GP_PREC_F64, s);
+        const bool f64 = ap->precision == GP_PREC_F64;
+        auto run = [&](int per_cu) {
+            const int blocks = std::max(1, std::min(ctx->cus * per_cu, (total_rows + 3) / 4));
+            launch_aperture((const FrameDesc*)((char*)ws + P.o_desc), a, c, total_rows, blocks, bp->mesh_w, max_nx,
+                            f64, s);
+        };
+        // workgroups per CU of the persistent grid
+        const std::string key = "aperture:" + std::to_string(ap->nr) + ":" + std::to_string((int)std::ceil(rmax)) +
+                                ":" + std::to_string(bp->mesh_w) + (f64 ? ":f64" : ":f32");
+        run(choose(ctx, key, {2, 4, 8, 16}, 8, s, run));
     }
     HIP_TRY(hipGetLastError());
     return GP_OK;

@@ -70,14 +70,18 @@ def make_frame(t: torch.Tensor) -> L.gp_frame:
 
 
 class Photometry:
-    """One batch geometry: shapes, dtypes and parameters fixed at construction."""
+    """One batch geometry: shapes, dtypes and parameters fixed at construction.
+
+    autotune: time the candidate launch shapes of this batch's shape classes
+    once, here (one synchronous run), and use the fastest from then on;
+    tune_cache: JSON file that keeps those choices across contexts."""
 
     def __init__(self, frames: Sequence[torch.Tensor], params, kernel: np.ndarray, capacity: int,
                  comp_capacity: int = 0, precision: int = L.GP_PREC_F32, device: int = 0,
-                 seg: bool = False, ctx=None):
+                 seg: bool = False, ctx=None, autotune: bool = False, tune_cache: Optional[str] = None):
         self.p = PhotParams.of(params)
         self.device = torch.device("cuda", device)
-        self.ctx = ctx if ctx is not None else L.gp_ctx_create(device)
+        self.ctx = ctx if ctx is not None else L.gp_ctx_create(device, tune_cache)
         self._own_ctx = ctx is None
         self.frames_t = list(frames)
         self.frames = [make_frame(t) for t in self.frames_t]
@@ -125,6 +129,13 @@ class Photometry:
         self.seg = None
         if seg:
             self.seg = [torch.zeros(t.shape[0], t.shape[1], dtype=torch.int32, device=dev) for t in self.frames_t]
+        if autotune:
+            L.gp_ctx_set_tuning(self.ctx, True)
+            try:
+                self.run()
+                torch.cuda.synchronize(self.device)
+            finally:
+                L.gp_ctx_set_tuning(self.ctx, False)
 
     def close(self):
         if self._own_ctx and self.ctx:

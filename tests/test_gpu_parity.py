@@ -472,3 +472,32 @@ def test_invalid_arguments_fail_synchronously(P):
                     ph.ws.data_ptr(), 1024, ph.stream_ptr())
     assert e.value.status == L.GP_ERR_WORKSPACE
     ph.close()
+
+
+def test_autotuning_keeps_results_and_writes_the_cache(P, tmp_path):
+    import json
+    fr = make_frame("c1", seed=41, W=512, H=384, nstars=40)
+    p = f32_params(fr.params)
+    d = _dev(fr.image)
+    ref = P.Photometry([d], p, p.kernel(), capacity=1024)
+    ref.run()
+    a = ref.results(0)
+    path = str(tmp_path / "tune.json")
+    tuned = P.Photometry([d], p, p.kernel(), capacity=1024, autotune=True, tune_cache=path)
+    tuned.run()
+    b = tuned.results(0)
+    cache = json.load(open(path))
+    _say("tuned", cache)
+    assert any(k.startswith("mesh_stats:") for k in cache) and any(k.startswith("aperture:") for k in cache)
+    assert a["n_obj"] == b["n_obj"] > 0
+    for k in ("npix", "xmin", "xmax", "ymin", "ymax", "pmin"):
+        np.testing.assert_array_equal(a["cat"][k], b["cat"][k])
+    for k in ("flux", "area", "bkg", "fluxerr"):
+        np.testing.assert_allclose(a["phot"][k], b["phot"][k], rtol=1e-12, atol=1e-9)
+    # a new context reads the choices back
+    again = P.Photometry([d], p, p.kernel(), capacity=1024, tune_cache=path)
+    again.run()
+    c = again.results(0)
+    np.testing.assert_array_equal(b["cat"]["pmin"], c["cat"]["pmin"])
+    for o in (ref, tuned, again):
+        o.close()
