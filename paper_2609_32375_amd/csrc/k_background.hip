@@ -190,7 +190,7 @@ __device__ __forceinline__ void wave_sort_segment(float* buf, int w, int lane) {
 // by a binary search in the partner segment (ties: the left segment first).
 // Returns the buffer that holds the result.
 template <int NT>
-__device__ float* sort_window(float* a, float* b, int P) {
+__device__ __forceinline__ float* sort_window(float* a, float* b, int P) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nseg = min(NW, P / 64);
@@ -206,26 +206,38 @@ __device__ float* sort_window(float* a, float* b, int P) {
         }
     }
     __syncthreads();
+    // merge rounds (merge path): thread t writes outputs [t E, t E + E) of the
+    // merged pair; it finds how many of them come from the left segment by a
+    // binary search along that output diagonal (ties: the left segment
+    // first), then merges its E outputs sequentially
+    const int E = max(1, P / NT);
     for (int len = SEG; len < P; len <<= 1) {
-        for (int g = threadIdx.x; g < P; g += NT) {
-            const int r = g / len, p = g - r * len;
-            const float x = a[g];
-            const float* q = a + (r ^ 1) * len;
-            int lo = 0, hi = len;
-            if ((r & 1) == 0) {
-                while (lo < hi) {      // partner values < x
-                    const int m = (lo + hi) >> 1;
-                    if (q[m] < x) lo = m + 1;
-                    else hi = m;
-                }
-            } else {
-                while (lo < hi) {      // partner values <= x
-                    const int m = (lo + hi) >> 1;
-                    if (q[m] <= x) lo = m + 1;
-                    else hi = m;
+        const int o0 = threadIdx.x * E;
+        if (o0 < P) {
+            const int pair = o0 / (2 * len);
+            const float* A = a + pair * 2 * len;
+            const float* B = A + len;
+            const int dg = o0 - pair * 2 * len;
+            int lo = max(0, dg - len), hi = min(dg, len);
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (A[mid] <= B[dg - mid - 1]) lo = mid + 1;
+                else hi = mid;
+            }
+            int i = lo, j = dg - lo;
+            float va = (i < len) ? A[i] : INFINITY, vb = (j < len) ? B[j] : INFINITY;
+            float* out = b + pair * 2 * len + dg;
+            for (int e = 0; e < E; ++e) {
+                const bool ta = (j >= len) || (i < len && va <= vb);
+                out[e] = ta ? va : vb;
+                if (ta) {
+                    ++i;
+                    va = (i < len) ? A[i] : INFINITY;
+                } else {
+                    ++j;
+                    vb = (j < len) ? B[j] : INFINITY;
                 }
             }
-            b[(r & ~1) * len + p + lo] = x;
         }
         __syncthreads();
         float* t = a;
@@ -263,7 +275,7 @@ struct Runs {
 // each(f) calls f on every alive value of the thread.  The histogram window
 // [wlo, whi] only steers the binning (bins are clamped).
 template <int NT, typename Each>
-__device__ int build_window(Each&& each, float wlo, float whi, int ra, int rb, int& m, const float*& win,
+__device__ __forceinline__ int build_window(Each&& each, float wlo, float whi, int ra, int rb, int& m, const float*& win,
                             MeshShared& sh) {
     const int tid = threadIdx.x;
     for (int b = tid; b < kBins; b += NT) sh.hist[b] = 0u;
@@ -322,20 +334,18 @@ __device__ int build_window(Each&& each, float wlo, float whi, int ra, int rb, i
 template <int NT>
 __device__ void bisect_pair(const Runs<NT>& run, float lmn, float lmx, int r1, int r2, float& o1, float& o2,
                             MeshShared& sh) {
-    const int kk[2] = {r1, r2};
-    float res[2];
-    for (int t = 0; t < 2; ++t) {
+    auto kth = [&](int k) {
         uint32_t a = f2ord(lmn), z = f2ord(lmx);
         while (a < z) {
             const uint32_t mid = a + ((z - a) >> 1);
             const int cnt = block_sum_i<NT>(run.count_le(ord2f(mid)), sh);
-            if (cnt > kk[t]) z = mid;
+            if (cnt > k) z = mid;
             else a = mid + 1;
         }
-        res[t] = ord2f(a);
-    }
-    o1 = res[0];
-    o2 = res[1];
+        return ord2f(a);
+    };
+    o1 = kth(r1);
+    o2 = (r2 == r1) ? o1 : kth(r2);
 }
 
 // One workgroup per mesh.  Pass 0 gives sigma0 of all pixels; the pixels are
@@ -360,15 +370,23 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
 
     float v[PPT];
     int cnt_t = 0;
+    {
+        // pixel k * NT + tid of the mesh, stepped by NT without divisions
+        const int dy = NT / w, dx = NT - dy * w;
+        int yy = tid / w, xx = tid - yy * w;
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int p = k * NT + tid;
-        v[k] = INFINITY;
-        if (p < n) {
-            const int yy = p / w;
-            const int xx = p - yy * w;
-            v[k] = load_px(d, x0 + xx, y0 + yy);
-            ++cnt_t;
+        for (int k = 0; k < PPT; ++k) {
+            v[k] = INFINITY;
+            if (k * NT + tid < n) {
+                v[k] = load_px(d, x0 + xx, y0 + yy);
+                ++cnt_t;
+            }
+            xx += dx;
+            yy += dy;
+            if (xx >= w) {
+                xx -= w;
+                ++yy;
+            }
         }
     }
     // pass 0: sigma0 of all pixels (FP64 sums shifted by the first pixel)

@@ -190,10 +190,15 @@ __device__ __forceinline__ int reflect_idx(int i, int n) {
     return (r < n) ? r : (p - 1 - r);
 }
 
+// frames live in global memory: address them as such (global_load rather
+// than the generic flat path)
+typedef __attribute__((address_space(1))) const float gfloat_t;
+typedef __attribute__((address_space(1))) const uint16_t gu16_t;
+
 __device__ __forceinline__ float load_px(const FrameDesc& d, int x, int y) {
     int64_t off = (int64_t)y * d.pitch + x;
-    if (d.dtype == kDtypeU16) return (float)((const uint16_t*)d.data)[off];
-    return ((const float*)d.data)[off];
+    if (d.dtype == kDtypeU16) return (float)((gu16_t*)d.data)[off];
+    return ((gfloat_t*)d.data)[off];
 }
 
 // mesh centre ("knot") along an axis and the spline piece holding a pixel:
