@@ -321,11 +321,21 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     }
     __syncthreads();
     const bool conn8 = pa->conn == 8;
+    // Union pairs (pixel, pixel above) for every pair of touching runs, one
+    // at the first column of their overlap.  Each wavefront lists its rows'
+    // pairs in its own share of the (now free) M region, then the whole
+    // block applies them concurrently; a full list falls back to uniting at
+    // once.  Pixel indices are < 4096: a pair packs into 24 bits.
+    constexpr int PCAP = (int)(sizeof(typename DetShared<Real>::U2) / sizeof(uint32_t)) / 4;
+    uint32_t* plist = reinterpret_cast<uint32_t*>(&sh.u2) + wv * PCAP;
+    int npair = 0;
 #pragma unroll 1
     for (int k = 0; k < 16; ++k) {
         const int ly = 16 * wv + k;
-        if (!((mbits >> k) & 1u) || ly == 0) continue;
+        if (ly == 0) continue;
         const uint64_t m = sh.rowmask[ly], mu = sh.rowmask[ly - 1];
+        if (conn8 ? (m & (mu | (mu << 1) | (mu >> 1))) == 0ull : (m & mu) == 0ull) continue;
+        const bool on = (m >> lane) & 1ull;
         const int p = ly * kTile + lane;
         const uint64_t zb = ~m & below;
         const int a0 = zb ? 64 - __clzll(zb) : 0;                     // run start
@@ -334,20 +344,55 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
         const bool up = (mu >> lane) & 1ull;
         const bool upl = lane > 0 && ((mu >> (lane - 1)) & 1ull);
         const bool upr = lane < 63 && ((mu >> (lane + 1)) & 1ull);
-        // one union per pair of touching runs: at the first column of their overlap
-        if (up && (lane == a0 || !upl)) lds_union(lab, p, p - kTile);
-        if (conn8) {
-            if (lane == a0 && upl) lds_union(lab, p, p - kTile - 1);
-            if (lane == a1 && upr && !up) lds_union(lab, p, p - kTile + 1);
+        const bool c0 = on && up && (lane == a0 || !upl);
+        const bool c1 = on && conn8 && lane == a0 && upl;
+        const bool c2 = on && conn8 && lane == a1 && upr && !up;
+        const int qq[3] = {p - kTile, p - kTile - 1, p - kTile + 1};
+        const bool cc[3] = {c0, c1, c2};
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const uint64_t bm = __ballot(cc[t]);
+            if (bm == 0ull) continue;
+            const int pos = npair + __popcll(bm & below);
+            if (cc[t]) {
+                if (pos < PCAP) plist[pos] = ((uint32_t)p << 12) | (uint32_t)qq[t];
+                else lds_union(lab, p, qq[t]);
+            }
+            npair += __popcll(bm);
+        }
+    }
+    if (lane == 0) sh.misc[wv] = min(npair, PCAP);
+    __syncthreads();
+    {
+        const int n0 = sh.misc[0], n1 = sh.misc[1], n2 = sh.misc[2], n3 = sh.misc[3];
+        const int tot = n0 + n1 + n2 + n3;
+        for (int i = tid; i < tot; i += 256) {
+            int w = 0, o = i;
+            if (o >= n0) {
+                o -= n0;
+                w = 1;
+                if (o >= n1) {
+                    o -= n1;
+                    w = 2;
+                    if (o >= n2) {
+                        o -= n2;
+                        w = 3;
+                    }
+                }
+            }
+            const uint32_t e = reinterpret_cast<const uint32_t*>(&sh.u2)[w * PCAP + o];
+            lds_union(lab, (int)(e >> 12), (int)(e & 4095u));
         }
     }
     __syncthreads();
+    // each pixel's root stays in a register: writing it back into the forest
+    // could be overwritten by another thread's path halving with a non-root
+    // ancestor (path halving never writes a root's own entry)
+    int rt[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        if ((mbits >> k) & 1u) {
-            const int p = (16 * wv + k) * kTile + lane;
-            lab[p] = lds_find(lab, p);
-        }
+        rt[k] = -1;
+        if ((mbits >> k) & 1u) rt[k] = lds_find(lab, (16 * wv + k) * kTile + lane);
     }
     __syncthreads();
     // roots in raster order: per-row ballots, then a prefix over the 64 rows
@@ -355,7 +400,7 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int p = (16 * wv + k) * kTile + lane;
-        rb[k] = __ballot(((mbits >> k) & 1u) && lab[p] == p);
+        rb[k] = __ballot(((mbits >> k) & 1u) && rt[k] == p);
         if (lane == 0) sh.rowoff[16 * wv + k + 1] = __popcll(rb[k]);
     }
     __syncthreads();
@@ -382,10 +427,7 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     __syncthreads();
     int co[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int p = (16 * wv + k) * kTile + lane;
-        co[k] = ((mbits >> k) & 1u) ? (int)comp[lab[p]] : -1;
-    }
+    for (int k = 0; k < 16; ++k) co[k] = ((mbits >> k) & 1u) ? (int)comp[rt[k]] : -1;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 16; ++k) comp[(16 * wv + k) * kTile + lane] = (int16_t)co[k];
