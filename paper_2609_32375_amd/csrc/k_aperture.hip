@@ -100,6 +100,8 @@ __device__ __forceinline__ Real pixel_area(Real dx, Real dy, Real r, Real r2) {
 
 constexpr int kApList = 128;   // queued (pixel, circle) cuts per wavefront
 constexpr int kApUnroll = 4;   // pixels per lane in flight
+constexpr int kApMaxFrames = kMaxFramesPerCall;   // object-count prefix over the frames, in LDS
+constexpr int kApPrefixBytes = (int)((sizeof(int32_t) * (kApMaxFrames + 1) + 15) / 16 * 16);
 
 template <typename Real>
 struct ApEntry {
@@ -151,12 +153,13 @@ struct ApLayout {
 // reduced in a fixed order, so an object's result does not depend on what else
 // runs.
 template <typename Real, int NC>
-__global__ __launch_bounds__(256) void k_aperture(const FrameDesc* __restrict__ desc, ApArgs a, ApCat cat,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 3 : 1))) void k_aperture(const FrameDesc* __restrict__ desc, ApArgs a, ApCat cat,
                                                   int total_rows, int band, int nixmax) {
     extern __shared__ __align__(16) unsigned char ap_dyn[];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const ApLayout<Real, NC> L(band, nixmax);
-    unsigned char* base = ap_dyn + (size_t)wv * L.bytes;
+    int32_t* fpre = reinterpret_cast<int32_t*>(ap_dyn);     // kApPrefixBytes
+    unsigned char* base = ap_dyn + kApPrefixBytes + (size_t)wv * L.bytes;
     double* binS = (double*)(base + L.o_s);
     Real* binA = (Real*)(base + L.o_a);
     Real* binV = (Real*)(base + L.o_v);
@@ -184,10 +187,47 @@ __global__ __launch_bounds__(256) void k_aperture(const FrameDesc* __restrict__ 
     for (int j = 0; j < NC; ++j)
         if (lane == j) rad[j] = cr[j];
 
-    for (int row = blockIdx.x * kApWaves + wv; row < total_rows; row += gridDim.x * kApWaves) {
-        const int f = row / a.capacity, k = row - f * a.capacity;
-        const int nobj = min(cat.n_obj[f], a.capacity);
-        if (k >= nobj) continue;
+    // The catalogued objects of all frames, numbered consecutively (frame by
+    // frame, rows < n_obj only), are split into 8 contiguous ranges, one per
+    // XCD: neighbouring objects, whose boxes overlap, share that XCD's L2.
+    const int nf = a.nframes;
+    if (wv == 0) {
+        // prefix of min(n_obj, capacity) over the frames (one wavefront)
+        constexpr int PER = kApMaxFrames / 64;
+        int t = 0;
+        for (int q = 0; q < PER; ++q) {
+            const int fr = lane * PER + q;
+            if (fr < nf) t += min(cat.n_obj[fr], a.capacity);
+        }
+        int incl = t;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        int run = incl - t;
+        for (int q = 0; q < PER; ++q) {
+            const int fr = lane * PER + q;
+            fpre[fr] = run;
+            if (fr < nf) run += min(cat.n_obj[fr], a.capacity);
+        }
+        if (lane == 63) fpre[kApMaxFrames] = incl;
+    }
+    __syncthreads();
+    const int total = fpre[kApMaxFrames];
+    const int chunk = (total + kXcds - 1) / kXcds;
+    const int xcd = blockIdx.x % kXcds, per_xcd = gridDim.x / kXcds;
+    const int o_end = min(total, (xcd + 1) * chunk);
+    for (int o = xcd * chunk + (blockIdx.x / kXcds) * nw + wv; o < o_end; o += per_xcd * nw) {
+        // frame of object o: last frame whose prefix is <= o
+        int lo = 0, hi = nf - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (fpre[mid] <= o) lo = mid;
+            else hi = mid - 1;
+        }
+        const int f = lo, k = o - fpre[f];
+        const int row = f * a.capacity + k;
         const FrameDesc& d = desc[f];
         const double xc = cat.x[row], yc = cat.y[row];
         const int cxi = (int)floor(xc), cyi = (int)floor(yc);
@@ -425,15 +465,14 @@ template <typename Real, int NC>
 static void launch_ap_nc(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int total_rows, int blocks,
                          int band, int nixmax, hipStream_t s) {
     const ApLayout<Real, NC> L(band, nixmax);
-    const size_t lds = (size_t)L.bytes * kApWaves;
-    static bool attr = false;
-    if (lds > 64 * 1024 && !attr) {
-        // large radii on small meshes in FP64: allow the whole LDS
-        (void)hipFuncSetAttribute((const void*)k_aperture<Real, NC>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-        attr = true;
-    }
-    k_aperture<Real, NC><<<blocks, 64 * kApWaves, lds, s>>>(desc, a, cat, total_rows, band, nixmax);
+    // waves per workgroup: as many (up to kApWaves) as keep the workgroup's
+    // LDS within 64 KB; the grid keeps the same number of wavefronts
+    int nw = kApWaves;
+    while (nw > 1 && (size_t)kApPrefixBytes + (size_t)L.bytes * nw > 64 * 1024) nw >>= 1;
+    const size_t lds = (size_t)kApPrefixBytes + (size_t)L.bytes * nw;
+    const int wg = blocks * (kApWaves / nw);
+    const int g = kXcds * std::max(1, (wg + kXcds - 1) / kXcds);
+    k_aperture<Real, NC><<<g, 64 * nw, lds, s>>>(desc, a, cat, total_rows, band, nixmax);
 }
 
 template <typename Real>

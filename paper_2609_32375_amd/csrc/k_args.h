@@ -7,6 +7,8 @@ namespace gpk {
 
 // mesh centres per axis the spline kernels hold in LDS
 constexpr int kSplineMaxKnots = 4096;
+// frames per call (the aperture kernel keeps their object-count prefix in LDS)
+constexpr int kMaxFramesPerCall = 1024;
 
 struct BkgArgs {
     float clip, crowd, mode_a, mode_b;

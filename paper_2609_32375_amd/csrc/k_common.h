@@ -125,6 +125,13 @@ __device__ __forceinline__ void f2_acc(F2& a, float v) {
     a.hi = s;
     a.lo += e;
 }
+// Workgroups are handed to the 8 XCDs (each with its own L2) in turn.  With a
+// grid of 8 * chunk workgroups, item (blockIdx mod 8) * chunk + blockIdx / 8
+// gives each XCD a contiguous run of items, so neighbours that share data
+// (tile halos, overlapping apertures) meet in the same L2.  Items >= n: none.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_item(int block, int chunk) { return (block % kXcds) * chunk + block / kXcds; }
+
 // make one wavefront's LDS writes visible to its other lanes
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");

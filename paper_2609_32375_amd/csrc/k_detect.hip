@@ -156,7 +156,8 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     constexpr bool kDbl = sizeof(Real) == 8;
     constexpr int MS = kRegion + 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int gt = blockIdx.x;
+    const int gt = xcd_item(blockIdx.x, (wk.total_tiles + kXcds - 1) / kXcds);
+    if (gt >= wk.total_tiles) return;
     const int f = frame_of(wk.nframes, gt, [&](int i) { return wk.desc[i].tile_base; });
     const FrameDesc d = wk.desc[f];
     const int lt = gt - d.tile_base;
@@ -867,7 +868,8 @@ void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
 
 template <typename Real>
 static void launch_detect_t(const DetWork& wk, const DetArgs* args, int rad, hipStream_t s) {
-    const int g = wk.total_tiles;
+    // 8 * ceil(tiles / 8) workgroups: a contiguous band of tiles per XCD
+    const int g = kXcds * ((wk.total_tiles + kXcds - 1) / kXcds);
     switch (rad) {
         case 0: k_detect_tiles<Real, 0><<<g, 256, 0, s>>>(wk, args); break;
         case 1: k_detect_tiles<Real, 1><<<g, 256, 0, s>>>(wk, args); break;

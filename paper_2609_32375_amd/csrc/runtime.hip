@@ -126,6 +126,8 @@ struct Plan {
 gp_status check_frames(const gp_frame* frames, int32_t nframes) {
     if (!frames) return fail(GP_ERR_INVALID_ARG, "frames is NULL");
     if (nframes < 1) return fail(GP_ERR_INVALID_ARG, "nframes must be >= 1 (got %d)", nframes);
+    if (nframes > kMaxFramesPerCall)
+        return fail(GP_ERR_UNSUPPORTED, "at most %d frames per call (got %d)", kMaxFramesPerCall, nframes);
     for (int f = 0; f < nframes; ++f) {
         const gp_frame& F = frames[f];
         if (!F.data) return fail(GP_ERR_INVALID_ARG, "frame %d: data is NULL", f);

@@ -58,6 +58,10 @@ def test_layout_and_validation_errors_are_synchronous():
         L.gp_background_layout([L.gp_frame(1, 10, 10, 5, 2)], bp)     # pitch < width
     with pytest.raises(L.GpError):
         L.gp_background_layout([L.gp_frame(1, 10, 10, 10, 7)], bp)    # dtype
+    # at most 1024 frames per call
+    with pytest.raises(L.GpError) as e:
+        L.gp_background_layout([_frame(32, 32)] * 1025, bp)
+    assert e.value.status == L.GP_ERR_UNSUPPORTED
     # more than 4096 meshes along an axis (the spline kernels' LDS knot table)
     b16 = L.gp_bkg_params(16, 16, 3, 3.0, 0.2, 2.5, 1.5, 100, 0)
     lay, _ = L.gp_background_layout([_frame(16 * 4096, 32)], b16)
