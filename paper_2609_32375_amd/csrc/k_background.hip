@@ -109,6 +109,8 @@ __device__ void block_stats(double& a, double& b, int& n, int& n2, float& mn, fl
     n2 = sh.pi[0][1];
     mn = sh.pmin[0];
     mx = sh.pmax[0];
+    // all partials loaded at once up to 8 wavefronts; 16 would spill
+#pragma unroll(NW > 8 ? 4 : 8)
     for (int i = 1; i < NW; ++i) {
         a += sh.pd[i][0];
         b += sh.pd[i][1];
@@ -197,13 +199,14 @@ __device__ __forceinline__ float* sort_window(float* a, float* b, int P) {
     const int SEG = P / nseg;
     __syncthreads();
     if (w < nseg) {
-        switch (SEG / 64) {
-            case 1: wave_sort_segment<1>(a, w, lane); break;
-            case 2: wave_sort_segment<2>(a, w, lane); break;
-            case 4: wave_sort_segment<4>(a, w, lane); break;
-            case 8: wave_sort_segment<8>(a, w, lane); break;
-            default: wave_sort_segment<16>(a, w, lane); break;
-        }
+        // values per lane: SEG / 64 <= kBuf / NT (only those shapes exist)
+        constexpr int EMAX = kBuf / NT;
+        const int E = SEG / 64;
+        if (E == 1) wave_sort_segment<1>(a, w, lane);
+        else if (E == 2) wave_sort_segment<2>(a, w, lane);
+        else if (E == 4 || EMAX < 8) wave_sort_segment<(EMAX < 4 ? EMAX : 4)>(a, w, lane);
+        else if (E == 8 || EMAX < 16) wave_sort_segment<(EMAX < 8 ? EMAX : 8)>(a, w, lane);
+        else wave_sort_segment<(EMAX < 16 ? EMAX : 16)>(a, w, lane);
     }
     __syncthreads();
     // merge rounds (merge path): thread t writes outputs [t E, t E + E) of the
