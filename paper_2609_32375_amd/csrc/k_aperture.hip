@@ -99,7 +99,7 @@ __device__ __forceinline__ Real pixel_area(Real dx, Real dy, Real r, Real r2) {
 }
 
 constexpr int kApList = 128;   // queued (pixel, circle) cuts per wavefront
-constexpr int kApUnroll = 4;   // pixels per lane in flight
+constexpr int kApUnroll = 2;   // pixels per lane in flight
 constexpr int kApMaxFrames = kMaxFramesPerCall;   // object-count prefix over the frames, in LDS
 constexpr int kApPrefixBytes = (int)((sizeof(int32_t) * (kApMaxFrames + 1) + 15) / 16 * 16);
 
@@ -312,7 +312,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real
                 tab[rr * nixmax + pi] = make_row<Real>(d.coef, d.nx, d.ny, ixlo + pi, jy, u);
             }
             wave_sync();
-            int rr = 0;
+            // the band's row offsets in registers: a pixel's row is the number
+            // of rows that end at or before it (compares, no dependent loads)
+            int ro[kApBand + 1];
+#pragma unroll
+            for (int q = 0; q <= kApBand; ++q) ro[q] = (q <= nb) ? roff[q] : 0x7fffffff;
             for (int b0 = 0; b0 < total; b0 += 64 * kApUnroll) {
                 int pxs[kApUnroll], rrs[kApUnroll];
                 float iv[kApUnroll];
@@ -323,10 +327,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real
                     pxs[u] = 0;
                     iv[u] = 0.0f;
                     if (idx < total) {
-                        while (idx >= roff[rr + 1]) ++rr;
-                        rrs[u] = rr;
-                        pxs[u] = rxl[rr] + (idx - roff[rr]);
-                        iv[u] = load_px(d, pxs[u], band0 + rr);
+                        int r = 0, start = 0;
+#pragma unroll
+                        for (int q = 1; q <= kApBand; ++q) {
+                            const bool past = ro[q] <= idx;
+                            r += past ? 1 : 0;
+                            start = past ? ro[q] : start;
+                        }
+                        rrs[u] = r;
+                        pxs[u] = rxl[r] + (idx - start);
+                        iv[u] = load_px(d, pxs[u], band0 + r);
                     }
                 }
 #pragma unroll
@@ -367,12 +377,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real
                     }
                     // circles that cut the pixel: queue (pixel, circle) pairs
                     const int ncut = kin - kout;
-                    int mx = ncut;
-#pragma unroll
-                    for (int o = 32; o >= 1; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
-                    for (int q = 0; q < mx; ++q) {
+                    for (int q = 0;; ++q) {
                         const bool has = q < ncut;
                         const uint64_t bm = __ballot(has);
+                        if (bm == 0ull) break;
                         const int pos = listn + __popcll(bm & below);
                         if (has) list[pos] = ApEntry<Real>{dx, dy, m, var, kout + q};
                         listn += __popcll(bm);
