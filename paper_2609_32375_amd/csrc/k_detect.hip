@@ -31,8 +31,12 @@
 
 namespace gpk {
 
+// A piece's sums while its tile is labelled: the M-weighted sums in FP64 and
+// the pixel-count sums (n, x n, y-sums, ...) as exact 32-bit integers (a tile
+// holds 4096 pixels with offsets below 64, so every count sum is < 2^24).
 struct LocalRec {
-    double s[12];
+    double s[6];
+    int32_t c[6];
     int32_t xmin, xmax, ymin, ymax;
     uint32_t peak, flags;
     int32_t rootpix, pad;
@@ -302,19 +306,23 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     int32_t* lab = sh.u1.l.lab;
     int16_t* comp = sh.u1.l.comp;
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));   // lanes < lane
+    // the wavefront's own row masks stay in registers; the row above its
+    // first row is read from LDS
+    uint64_t rm[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        const uint64_t m = __ballot((mbits >> k) & 1u);
-        if (lane == 0) sh.rowmask[16 * wv + k] = m;
+        rm[k] = __ballot((mbits >> k) & 1u);
+        if (lane == 0) sh.rowmask[16 * wv + k] = rm[k];
     }
-    __syncthreads();
+    // (the horizontal pass that shared lab's LDS was finished by every
+    // wavefront before the barrier above)
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int ly = 16 * wv + k;
         const int p = ly * kTile + lane;
         int v = -1;
         if ((mbits >> k) & 1u) {
-            const uint64_t zb = ~sh.rowmask[ly] & below;
+            const uint64_t zb = ~rm[k] & below;
             const int s0 = zb ? 64 - __clzll(zb) : 0;
             v = ly * kTile + s0;
         }
@@ -330,11 +338,11 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     constexpr int PCAP = (int)(sizeof(typename DetShared<Real>::U2) / sizeof(uint32_t)) / 4;
     uint32_t* plist = reinterpret_cast<uint32_t*>(&sh.u2) + wv * PCAP;
     int npair = 0;
-#pragma unroll 1
+    const uint64_t mtop = (wv > 0) ? sh.rowmask[16 * wv - 1] : 0ull;
+#pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int ly = 16 * wv + k;
-        if (ly == 0) continue;
-        const uint64_t m = sh.rowmask[ly], mu = sh.rowmask[ly - 1];
+        const uint64_t m = rm[k], mu = (k > 0) ? rm[k - 1] : mtop;
         if (conn8 ? (m & (mu | (mu << 1) | (mu >> 1))) == 0ull : (m & mu) == 0ull) continue;
         const bool on = (m >> lane) & 1ull;
         const int p = ly * kTile + lane;
@@ -386,23 +394,36 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
         }
     }
     __syncthreads();
-    // each pixel's root stays in a register: writing it back into the forest
-    // could be overwritten by another thread's path halving with a non-root
-    // ancestor (path halving never writes a root's own entry)
+    // Roots of the lane's 16 pixels.  The forest no longer changes, so the
+    // 16 chains are walked side by side (one LDS round trip per step for all
+    // of them) and nothing is written back: each root stays in a register.
     int rt[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        rt[k] = -1;
-        if ((mbits >> k) & 1u) rt[k] = lds_find(lab, (16 * wv + k) * kTile + lane);
+    for (int k = 0; k < 16; ++k) rt[k] = ((mbits >> k) & 1u) ? lab[(16 * wv + k) * kTile + lane] : -1;
+    for (;;) {
+        bool more = false;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int q = rt[k];
+            const int g = lab[q & (kTile * kTile - 1)];
+            if (q >= 0 && g != q) {
+                rt[k] = g;
+                more = true;
+            }
+        }
+        if (__ballot(more) == 0ull) break;
     }
-    __syncthreads();
-    // roots in raster order: per-row ballots, then a prefix over the 64 rows
+    // roots in raster order: per-row ballots (kept in rowmask, whose union
+    // masks are no longer read), then a prefix over the 64 rows
     uint64_t rb[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int p = (16 * wv + k) * kTile + lane;
         rb[k] = __ballot(((mbits >> k) & 1u) && rt[k] == p);
-        if (lane == 0) sh.rowoff[16 * wv + k + 1] = __popcll(rb[k]);
+        if (lane == 0) {
+            sh.rowmask[16 * wv + k] = rb[k];
+            sh.rowoff[16 * wv + k + 1] = __popcll(rb[k]);
+        }
     }
     __syncthreads();
     if (wv == 0) {
@@ -419,19 +440,17 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     }
     __syncthreads();
     const int ncomp = sh.rowoff[kTile];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int ly = 16 * wv + k;
-        const int p = ly * kTile + lane;
-        if ((rb[k] >> lane) & 1ull) comp[p] = (int16_t)(sh.rowoff[ly] + __popcll(rb[k] & below));
-    }
-    __syncthreads();
+    // piece id of a pixel = rank of its root among the tile's roots
     int co[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) co[k] = ((mbits >> k) & 1u) ? (int)comp[rt[k]] : -1;
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 16; ++k) comp[(16 * wv + k) * kTile + lane] = (int16_t)co[k];
+    for (int k = 0; k < 16; ++k) {
+        const int r = rt[k] & (kTile * kTile - 1);
+        const int ry_ = r >> 6, rx_ = r & 63;
+        const uint64_t lowr = (rx_ == 0) ? 0ull : ((~0ull) >> (64 - rx_));
+        const int c = sh.rowoff[ry_] + __popcll(sh.rowmask[ry_] & lowr);
+        co[k] = ((mbits >> k) & 1u) ? c : -1;
+        comp[(16 * wv + k) * kTile + lane] = (int16_t)co[k];
+    }
     // 5. records for the tile's pieces (LDS for the first kLocalRecs, in u2,
     //    now free: M lives in VGPRs)
     if (tid == 0) {
@@ -453,7 +472,10 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
         wk.parent[base + c] = base + c;
         if (c < kLocalRecs) {
             LocalRec& R = sh.u2.rec[c];
-            for (int z = 0; z < 12; ++z) R.s[z] = 0.0;
+            for (int z = 0; z < 6; ++z) {
+                R.s[z] = 0.0;
+                R.c[z] = 0;
+            }
             R.xmin = R.ymin = 0x7fffffff;
             R.xmax = R.ymax = -1;
             R.peak = 0u;
@@ -512,13 +534,15 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
             const bool loc = cur < kLocalRecs;
             const double dxd = (double)lane;
             const double S = run.s(), T = run.t(), U = run.u();
-            const double n = (double)rcnt, sy = (double)rdy, syy = (double)rdy2;
-            const double add[12] = {S, dxd * S, T, dxd * dxd * S, U, dxd * T,
-                                    n, dxd * n, sy, dxd * dxd * n, syy, dxd * sy};
+            const double add[6] = {S, dxd * S, T, dxd * dxd * S, U, dxd * T};
+            const int addc[6] = {rcnt, lane * rcnt, rdy, lane * lane * rcnt, rdy2, lane * rdy};
             if (loc) {
                 LocalRec& R = sh.u2.rec[cur];
 #pragma unroll
-                for (int z = 0; z < 12; ++z) atomicAdd(&R.s[z], add[z]);
+                for (int z = 0; z < 6; ++z) {
+                    atomicAdd(&R.s[z], add[z]);
+                    atomicAdd(&R.c[z], addc[z]);
+                }
                 atomicMin(&R.xmin, gx);
                 atomicMax(&R.xmax, gx);
                 atomicMin(&R.ymin, y0 + ry0);
@@ -528,7 +552,10 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
             } else {
                 CompRec& R = wk.recs[base + cur];
 #pragma unroll
-                for (int z = 0; z < 12; ++z) unsafeAtomicAdd(&R.s[z], add[z]);
+                for (int z = 0; z < 6; ++z) {
+                    unsafeAtomicAdd(&R.s[z], add[z]);
+                    unsafeAtomicAdd(&R.s[6 + z], (double)addc[z]);
+                }
                 atomicMin(&R.xmin, gx);
                 atomicMax(&R.xmax, gx);
                 atomicMin(&R.ymin, y0 + ry0);
@@ -569,7 +596,10 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     for (int c = tid; c < nloc; c += 256) {
         const LocalRec& Lr = sh.u2.rec[c];
         CompRec& R = wk.recs[base + c];
-        for (int z = 0; z < 12; ++z) R.s[z] = Lr.s[z];
+        for (int z = 0; z < 6; ++z) {
+            R.s[z] = Lr.s[z];
+            R.s[6 + z] = (double)Lr.c[z];
+        }
         R.xmin = Lr.xmin;
         R.xmax = Lr.xmax;
         R.ymin = Lr.ymin;
