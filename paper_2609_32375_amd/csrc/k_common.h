@@ -201,6 +201,8 @@ __device__ __forceinline__ int reflect_idx(int i, int n) {
 // than the generic flat path)
 typedef __attribute__((address_space(1))) const float gfloat_t;
 typedef __attribute__((address_space(1))) const uint16_t gu16_t;
+typedef __attribute__((address_space(1))) const double gdouble_t;
+typedef __attribute__((address_space(1))) int32_t gi32_t;
 
 __device__ __forceinline__ float load_px(const FrameDesc& d, int x, int y) {
     int64_t off = (int64_t)y * d.pitch + x;

@@ -67,14 +67,21 @@ struct DetShared {
 };
 
 // find with path halving: every link points to a smaller index, so writing a
-// grandparent over a parent only shortens the chain
+// grandparent over a parent only shortens the chain.  Links are read and
+// written as relaxed workgroup-scope atomics (never cached in registers
+// across the loop; the compiler keeps them as LDS instructions).
+__device__ __forceinline__ int lds_ld(int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_st(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 __device__ __forceinline__ int lds_find(int* L, int x) {
-    volatile int* V = L;
     while (true) {
-        const int q = V[x];
+        const int q = lds_ld(&L[x]);
         if (q == x) return x;
-        const int g = V[q];
-        if (g != q) V[x] = g;
+        const int g = lds_ld(&L[q]);
+        if (g != q) lds_st(&L[x], g);
         x = g;
     }
 }
@@ -182,12 +189,46 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     constexpr int REG = kSep ? kTile + 2 * kR : kRegion;   // region row stride
     constexpr int NL = (REG * REG + 255) / 256;
     float pv[NL];
+    // a region inside the frame (no reflection) is addressed from its first
+    // pixel with 32-bit offsets; tiles at the frame border take the general path
+    const bool inner = x0 >= rx && y0 >= ry && x0 + tw + rx <= d.W && y0 + th + ry <= d.H &&
+                       d.pitch < (int64_t)(1 << 24);
+    if (inner) {
+        const int64_t o0 = (int64_t)(y0 - ry) * d.pitch + (x0 - rx);
+        const int pitch = (int)d.pitch;
+        if (d.dtype == kDtypeU16) {
+            gu16_t* b = (gu16_t*)d.data + o0;
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-        const int e = tid + 256 * i;
-        const int r = e / REG, c = e - r * REG;
-        pv[i] = (r < RH && c < RW) ? load_px(d, reflect_idx(x0 - rx + c, d.W), reflect_idx(y0 - ry + r, d.H))
-                                   : 0.0f;
+            for (int i = 0; i < NL; ++i) {
+                const int e = tid + 256 * i;
+                const int r = e / REG, c = e - r * REG;
+                const bool ok = r < RH && c < RW;
+                // every lane loads (offset 0 = the region's first pixel when
+                // outside it), so the loads issue back to back
+                const float v = (float)b[ok ? __umul24(r, pitch) + c : 0u];
+                pv[i] = ok ? v : 0.0f;
+            }
+        } else {
+            gfloat_t* b = (gfloat_t*)d.data + o0;
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const int e = tid + 256 * i;
+                const int r = e / REG, c = e - r * REG;
+                const bool ok = r < RH && c < RW;
+                // every lane loads (offset 0 = the region's first pixel when
+                // outside it), so the loads issue back to back
+                const float v = b[ok ? __umul24(r, pitch) + c : 0u];
+                pv[i] = ok ? v : 0.0f;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e / REG, c = e - r * REG;
+            pv[i] = (r < RH && c < RW) ? load_px(d, reflect_idx(x0 - rx + c, d.W), reflect_idx(y0 - ry + r, d.H))
+                                       : 0.0f;
+        }
     }
     for (int e = tid; e < RH * nix; e += 256) {
         const int r = e / nix, pi = e - r * nix;
@@ -286,7 +327,7 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
         if (colok && ly < th && Fo[k] > To[k]) mbits |= 1u << k;
     }
     const int any = __syncthreads_or(mbits != 0u);
-    int32_t* seg = d.seg;
+    gi32_t* seg = (gi32_t*)d.seg;
     if (!any) {
         if (tid == 0) wk.tiles[gt] = TileInfo{-1, 0};
         if (seg && colok) {
@@ -862,7 +903,7 @@ __global__ void k_frame_status(DetWork wk, CatOut cat, int32_t* comp_status) {
 __global__ __launch_bounds__(256) void k_seg_finalize(DetWork wk, int f) {
     if (wk.counters[1] != 0u) return;
     const FrameDesc& d = wk.desc[f];
-    int32_t* seg = d.seg;
+    gi32_t* seg = (gi32_t*)d.seg;
     const int64_t npx = (int64_t)d.W * d.H;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npx;
          p += (int64_t)gridDim.x * blockDim.x) {

@@ -26,7 +26,7 @@ struct RowT<double> {
 
 __device__ __forceinline__ void piece_row(const double* __restrict__ coef, int nx, int ny, int q, int ix,
                                           int jy, double u, double a[4]) {
-    const double* P = coef + (((size_t)q * (ny + 1) + jy) * (nx + 1) + ix) * 16;
+    gdouble_t* P = (gdouble_t*)coef + (((size_t)q * (ny + 1) + jy) * (nx + 1) + ix) * 16;
 #pragma unroll
     for (int p = 0; p < 4; ++p) a[p] = ((P[p * 4 + 3] * u + P[p * 4 + 2]) * u + P[p * 4 + 1]) * u + P[p * 4];
 }
