@@ -25,36 +25,43 @@ namespace gpk {
 constexpr int kBins = 4096;
 constexpr int kMaxWaves = 16;     // up to 1024 threads per mesh
 
-constexpr int kBuf = 4096;        // sorted window of ranks around the median (== kBins)
+constexpr int kBuf = 4096;        // sorted window of ranks around the median
 constexpr int kHalf = 512;        // half-width of that window, in ranks
+constexpr int kRankSmall = 16;    // first-level bins up to this size are ordered by rank counting
+constexpr int kRankMax = 256;     // second-level bins beyond this size go to the merge sort
 
+template <int NB>
 struct MeshShared {
+    static constexpr int kNB = NB;
     union {
-        uint32_t hist[kBins];
+        uint32_t hist[NB];
         float buf2[kBuf];     // second buffer of the window sort
     };
     float buf[kBuf];
-    double pd[kMaxWaves][2];
-    int32_t pi[kMaxWaves][2];
-    float pmin[kMaxWaves], pmax[kMaxWaves];
+    double pd[2][kMaxWaves][2];                // block_stats partials, double-buffered
+    int32_t pi[2][kMaxWaves][2];
+    float pmin[2][kMaxWaves], pmax[2][kMaxWaves];
     uint32_t wsum[kMaxWaves];
+    uint32_t maxnb, wmin, wmax;
     int32_t sel_bin[2];
     uint32_t sel_cum[2];
     uint32_t cnt, kmin, kmax;
     int32_t ucnt[kMaxWaves];
 };
 
+template <int NB>
 __device__ __forceinline__ int bin_of(float v, float lo, float scale) {
     float t = (v - lo) * scale;
-    t = fminf(fmaxf(t, 0.0f), (float)(kBins - 1));
+    t = fminf(fmaxf(t, 0.0f), (float)(NB - 1));
     return (int)t;
 }
 
-__device__ __forceinline__ float bin_scale(float lo, float hi) { return (hi > lo) ? (float)kBins / (hi - lo) : 0.0f; }
+template <int NB>
+__device__ __forceinline__ float bin_scale(float lo, float hi) { return (hi > lo) ? (float)NB / (hi - lo) : 0.0f; }
 
 // exclusive scan of one uint32 per thread over the block
-template <int NT>
-__device__ uint32_t block_exscan(uint32_t x, MeshShared& sh) {
+template <int NT, typename SH>
+__device__ __forceinline__ uint32_t block_exscan(uint32_t x, SH& sh) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t incl = x;
 #pragma unroll
@@ -70,8 +77,8 @@ __device__ uint32_t block_exscan(uint32_t x, MeshShared& sh) {
     return off + incl - x;
 }
 
-template <int NT>
-__device__ int block_sum_i(int x, MeshShared& sh) {
+template <int NT, typename SH>
+__device__ int block_sum_i(int x, SH& sh) {
     constexpr int NW = NT / 64;
     x = wave_sum_i(x);
     if ((threadIdx.x & 63) == 0) sh.ucnt[threadIdx.x >> 6] = x;
@@ -83,11 +90,17 @@ __device__ int block_sum_i(int x, MeshShared& sh) {
 }
 
 // deterministic block reduction of two FP64 sums, two counts and min/max
-// (wavefront butterflies, then the wavefront partials in wavefront order)
-template <int NT>
-__device__ void block_stats(double& a, double& b, int& n, int& n2, float& mn, float& mx, MeshShared& sh) {
+// (wavefront butterflies, then the wavefront partials in wavefront order).
+// The partials alternate between two LDS sets (par flips on every call), so
+// one barrier per call suffices: a set is written again only two calls later,
+// after every thread has passed the barrier of the call in between.
+template <int NT, typename SH>
+__device__ __forceinline__ void block_stats(double& a, double& b, int& n, int& n2, float& mn, float& mx, int& par,
+                                            SH& sh) {
     constexpr int NW = NT / 64;
     const int w = threadIdx.x >> 6;
+    const int P = par;
+    par ^= 1;
     a = wave_sum_d(a);
     b = wave_sum_d(b);
     n = wave_sum_i(n);
@@ -95,31 +108,30 @@ __device__ void block_stats(double& a, double& b, int& n, int& n2, float& mn, fl
     mn = wave_min(mn);
     mx = wave_max(mx);
     if ((threadIdx.x & 63) == 0) {
-        sh.pd[w][0] = a;
-        sh.pd[w][1] = b;
-        sh.pi[w][0] = n;
-        sh.pi[w][1] = n2;
-        sh.pmin[w] = mn;
-        sh.pmax[w] = mx;
+        sh.pd[P][w][0] = a;
+        sh.pd[P][w][1] = b;
+        sh.pi[P][w][0] = n;
+        sh.pi[P][w][1] = n2;
+        sh.pmin[P][w] = mn;
+        sh.pmax[P][w] = mx;
     }
     __syncthreads();
-    a = sh.pd[0][0];
-    b = sh.pd[0][1];
-    n = sh.pi[0][0];
-    n2 = sh.pi[0][1];
-    mn = sh.pmin[0];
-    mx = sh.pmax[0];
+    a = sh.pd[P][0][0];
+    b = sh.pd[P][0][1];
+    n = sh.pi[P][0][0];
+    n2 = sh.pi[P][0][1];
+    mn = sh.pmin[P][0];
+    mx = sh.pmax[P][0];
     // all partials loaded at once up to 8 wavefronts; 16 would spill
 #pragma unroll(NW > 8 ? 4 : 8)
     for (int i = 1; i < NW; ++i) {
-        a += sh.pd[i][0];
-        b += sh.pd[i][1];
-        n += sh.pi[i][0];
-        n2 += sh.pi[i][1];
-        mn = fminf(mn, sh.pmin[i]);
-        mx = fmaxf(mx, sh.pmax[i]);
+        a += sh.pd[P][i][0];
+        b += sh.pd[P][i][1];
+        n += sh.pi[P][i][0];
+        n2 += sh.pi[P][i][1];
+        mn = fminf(mn, sh.pmin[P][i]);
+        mx = fmaxf(mx, sh.pmax[P][i]);
     }
-    __syncthreads();
 }
 
 // ascending bitonic sorting network over a thread's registers
@@ -272,27 +284,58 @@ struct Runs {
     }
 };
 
-// Sort the values of ranks [ra, rb] (0-based, within the alive set) and their
-// bin-mates into a window; returns the rank of its first value (-1 when the
-// gathered bins exceed the buffer), its count in m and its storage in win.
-// each(f) calls f on every alive value of the thread.  The histogram window
-// [wlo, whi] only steers the binning (bins are clamped).
-template <int NT, typename Each>
-__device__ __forceinline__ int build_window(Each&& each, float wlo, float whi, int ra, int rb, int& m, const float*& win,
-                            MeshShared& sh) {
+// Bin b of a histogram is stored at slot hist_slot(b): the low bits are
+// XORed with a function of the thread b / per that owns the bin in the scan,
+// so that the threads of a wavefront reading their own bins side by side hit
+// 64 different LDS banks.
+template <int NT, int NB>
+__device__ __forceinline__ int hist_slot(int b) {
+    constexpr int per = NB / NT;   // a power of two <= 64
+    constexpr int G = (64 / per) > 0 ? 64 / per : 1;
+    return b ^ (((b / per) / G) & (per - 1));
+}
+
+// bins narrower than 0.99 units hold one integer value each (edge bins also
+// collect the clamped values outside the range)
+template <int NB>
+__device__ __forceinline__ bool single_value_bin(bool int_vals, float scale, int b) {
+    return int_vals && scale >= 1.01f && b != 0 && b != NB - 1;
+}
+
+struct Placed {
+    int b1, b2;       // first and last bin of the selected ranks
+    uint32_t base;    // values in bins below b1
+    int m;            // values in bins b1 .. b2
+    uint32_t maxnb;   // largest of those bins that may hold different values
+};
+
+// Histogram of the values each(f) visits over [lo, lo + NB / scale), the bins
+// holding ranks ra and rb, and the first slot of every bin in [b1, b2]
+// relative to b1 (left in the histogram for the caller's placement).
+// first: also resets the window's value range (read by the caller between a
+// first-level and a second-level call, so only the first one may reset it).
+template <int NT, typename SH, typename Each>
+__device__ __forceinline__ Placed place_bins(Each&& each, float lo, float scale, bool int_vals, int ra, int rb,
+                                             bool first, SH& sh) {
+    constexpr int NB = SH::kNB;
+    constexpr int per = NB / NT;
     const int tid = threadIdx.x;
-    for (int b = tid; b < kBins; b += NT) sh.hist[b] = 0u;
-    if (tid == 0) sh.cnt = 0u;
+    for (int b = tid; b < NB; b += NT) sh.hist[b] = 0u;
+    if (tid == 0) {
+        sh.maxnb = 0u;
+        if (first) {
+            sh.wmin = 0xffffffffu;
+            sh.wmax = 0u;
+        }
+    }
     __syncthreads();
-    const float scale = bin_scale(wlo, whi);
-    each([&](float x) { atomicAdd(&sh.hist[bin_of(x, wlo, scale)], 1u); });
+    each([&](float x) { atomicAdd(&sh.hist[hist_slot<NT, NB>(bin_of<NB>(x, lo, scale))], 1u); });
     __syncthreads();
-    constexpr int per = kBins / NT;
     uint32_t c[per];
     uint32_t tot = 0;
 #pragma unroll
     for (int q = 0; q < per; ++q) {
-        c[q] = sh.hist[tid * per + q];
+        c[q] = sh.hist[hist_slot<NT, NB>(tid * per + q)];
         tot += c[q];
     }
     const uint32_t pre = block_exscan<NT>(tot, sh);
@@ -313,30 +356,150 @@ __device__ __forceinline__ int build_window(Each&& each, float wlo, float whi, i
         }
     }
     __syncthreads();
-    const int b1 = sh.sel_bin[0], b2 = sh.sel_bin[1];
-    const int base = (int)sh.sel_cum[0];
-    each([&](float x) {
-        const int b = bin_of(x, wlo, scale);
-        if (b >= b1 && b <= b2) {
-            const uint32_t s = atomicAdd(&sh.cnt, 1u);
-            if (s < (uint32_t)kBuf) sh.buf[s] = x;
+    Placed P;
+    P.b1 = sh.sel_bin[0];
+    P.b2 = sh.sel_bin[1];
+    P.base = sh.sel_cum[0];
+    {
+        uint32_t cum = pre, big = 0u;
+#pragma unroll
+        for (int q = 0; q < per; ++q) {
+            const int b = tid * per + q;
+            if (b >= P.b1 && b <= P.b2) {
+                sh.hist[hist_slot<NT, NB>(b)] = cum - P.base;
+                if (!single_value_bin<NB>(int_vals, scale, b)) big = max(big, c[q]);
+            }
+            if (b == P.b2) sh.cnt = cum + c[q] - P.base;
+            cum += c[q];
         }
-    });
+        if (big > 1u) atomicMax(&sh.maxnb, big);
+    }
     __syncthreads();
-    m = (int)sh.cnt;
+    P.m = (int)sh.cnt;
+    P.maxnb = sh.maxnb;
+    return P;
+}
+
+// Copies src[0, m), grouped by bin (bin slices ending at the histogram's
+// entries), to dst in ascending order: each value's place is its slice start
+// plus the smaller values of its slice (and the equal ones before it).
+template <int NT, typename SH>
+__device__ __forceinline__ void rank_place(const float* src, float* dst, int m, float lo, float scale, bool int_vals,
+                                           const Placed& P, SH& sh) {
+    constexpr int NB = SH::kNB;
+    for (int j = threadIdx.x; j < m; j += NT) {
+        const float x = src[j];
+        const int b = bin_of<NB>(x, lo, scale);
+        int r = j;   // a bin of equal values keeps its order
+        if (!single_value_bin<NB>(int_vals, scale, b)) {
+            const int s0 = (b == P.b1) ? 0 : (int)sh.hist[hist_slot<NT, NB>(b - 1)];
+            const int e = (int)sh.hist[hist_slot<NT, NB>(b)];
+            r = s0;
+            for (int i = s0; i < e; i += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int ii = i + u;
+                    const float y = src[min(ii, e - 1)];
+                    r += (ii < e && (y < x || (y == x && ii < j))) ? 1 : 0;
+                }
+            }
+        }
+        dst[r] = x;
+    }
+}
+
+// Sort the values of ranks [ra, rb] (0-based, within the alive set) and their
+// bin-mates into a window; returns the rank of its first value (-1 when the
+// gathered bins exceed the buffer), its count in m and its storage in win.
+// each(f) calls f on every alive value of the thread; each2(f1, f2) calls f1
+// on all of them, then f2(f1's result, value) where that result is >= 0.  The
+// histogram window [wlo, whi] only steers the binning (bins are clamped).
+// The window is gathered grouped by bin (each bin's slice found from the
+// histogram's prefix sums).  Small bins are then ordered directly by rank
+// counting; otherwise a second histogram over the window's own value range
+// spreads it over fine bins, it is regrouped by those and ordered by rank
+// counting.  A window over half the buffer, or a fine bin of more than
+// kRankMax different values, goes through the merge sort instead.
+// int_vals: the values are integers.
+template <int NT, typename Each, typename Each2, typename SH>
+__device__ __forceinline__ int build_window(Each&& each, Each2&& each2, float wlo, float whi, int ra, int rb,
+                                            bool int_vals, int& m, const float*& win, SH& sh) {
+    constexpr int NB = SH::kNB;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const float scale = bin_scale<NB>(wlo, whi);
+    const Placed P1 = place_bins<NT>(each, wlo, scale, int_vals, ra, rb, true, sh);
+    m = P1.m;
     if (m > kBuf) return -1;
-    int P = 64;
-    while (P < m) P <<= 1;
-    for (int i = m + tid; i < P; i += NT) sh.buf[i] = INFINITY;
-    win = sort_window<NT>(sh.buf, sh.buf2, P);
-    return base;
+    // gather: all slots are claimed before any value is stored
+    float gmn = INFINITY, gmx = -INFINITY;
+    each2(
+        [&](float x) {
+            const int b = bin_of<NB>(x, wlo, scale);
+            return (b >= P1.b1 && b <= P1.b2) ? (int)atomicAdd(&sh.hist[hist_slot<NT, NB>(b)], 1u) : -1;
+        },
+        [&](int slot, float x) {
+            sh.buf[slot] = x;
+            gmn = fminf(gmn, x);
+            gmx = fmaxf(gmx, x);
+        });
+    gmn = wave_min(gmn);
+    gmx = wave_max(gmx);
+    if (lane == 0 && gmn <= gmx) {
+        atomicMin(&sh.wmin, f2ord(gmn));
+        atomicMax(&sh.wmax, f2ord(gmx));
+    }
+    __syncthreads();
+    float* out = sh.buf + kBuf / 2;
+    if (m <= kBuf / 2 && P1.maxnb <= (uint32_t)kRankSmall) {
+        rank_place<NT>(sh.buf, out, m, wlo, scale, int_vals, P1, sh);
+        __syncthreads();
+        win = out;
+        return (int)P1.base;
+    }
+    if (m <= kBuf / 2) {
+        const float lo2 = ord2f(sh.wmin), hi2 = ord2f(sh.wmax);
+        const float scale2 = bin_scale<NB>(lo2, hi2);
+        if (!(scale2 > 0.0f)) {
+            win = sh.buf;   // one value only
+            return (int)P1.base;
+        }
+        auto each_buf = [&](auto&& f) __attribute__((always_inline)) {
+            for (int j = tid; j < m; j += NT) f(sh.buf[j]);
+        };
+        const Placed P2 = place_bins<NT>(each_buf, lo2, scale2, int_vals, 0, m - 1, false, sh);
+        if (P2.maxnb <= (uint32_t)kRankMax) {
+            constexpr int MAXJ = (kBuf / 2 + NT - 1) / NT;
+            int sl[MAXJ];
+            float xv[MAXJ];
+#pragma unroll
+            for (int i = 0; i < MAXJ; ++i) {
+                const int j = tid + i * NT;
+                xv[i] = (j < m) ? sh.buf[j] : 0.0f;
+                sl[i] = (j < m) ? (int)atomicAdd(&sh.hist[hist_slot<NT, NB>(bin_of<NB>(xv[i], lo2, scale2))], 1u)
+                                : -1;
+            }
+#pragma unroll
+            for (int i = 0; i < MAXJ; ++i)
+                if (sl[i] >= 0) out[sl[i]] = xv[i];
+            __syncthreads();
+            rank_place<NT>(out, sh.buf, m, lo2, scale2, int_vals, P2, sh);
+            __syncthreads();
+            win = sh.buf;
+            return (int)P1.base;
+        }
+    }
+    int Pn = 64;
+    while (Pn < m) Pn <<= 1;
+    for (int i = m + tid; i < Pn; i += NT) sh.buf[i] = INFINITY;
+    win = sort_window<NT>(sh.buf, sh.buf2, Pn);
+    return (int)P1.base;
 }
 
 // Values of ranks r1 <= r2 of the alive set by bisection on the
 // order-preserving keys (count_le per run); for windows the buffer cannot hold.
-template <int NT>
+template <int NT, typename SH>
 __device__ void bisect_pair(const Runs<NT>& run, float lmn, float lmx, int r1, int r2, float& o1, float& o2,
-                            MeshShared& sh) {
+                            SH& sh) {
     auto kth = [&](int k) {
         uint32_t a = f2ord(lmn), z = f2ord(lmx);
         while (a < z) {
@@ -359,7 +522,7 @@ __device__ void bisect_pair(const Runs<NT>& run, float lmn, float lmx, int r1, i
 // stays valid while the ranks removed below keep the median inside it.
 template <int NT, int PPT>
 __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__ desc, int nframes, BkgArgs a) {
-    __shared__ MeshShared sh;
+    __shared__ MeshShared<kBins> sh;
     __shared__ float T[NT * PPT];
     const int tid = threadIdx.x;
     const int gm = blockIdx.x;
@@ -370,6 +533,7 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
     const int x0 = mi * d.mw, y0 = mj * d.mh;
     const int w = min(d.mw, d.W - x0), h = min(d.mh, d.H - y0);
     const int n = w * h;
+    const bool int_vals = d.dtype == kDtypeU16;
 
     float v[PPT];
     int cnt_t = 0;
@@ -406,8 +570,8 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
             mx = fmaxf(mx, v[k]);
         }
     }
-    int cnt = 0, unused = 0;
-    block_stats<NT>(s1, s2, cnt, unused, mn, mx, sh);
+    int cnt = 0, unused = 0, par = 0;
+    block_stats<NT>(s1, s2, cnt, unused, mn, mx, par, sh);
     const int out_idx = mj * d.nx + mi;
     if (mn == mx) {
         if (tid == 0) {
@@ -424,24 +588,19 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
     double mean = c0 + m1;
     double sig = sig0;
 
-    // the thread's run, sorted, in LDS; its FP64 sums shifted by a float
-    // near the mean (so every shifted value is exact)
-    sort_regs<PPT>(v);
+    // the thread's run: its values sorted, in LDS.  The first median reads the
+    // values from registers while they are still unsorted (the lanes of a
+    // wavefront then bin unrelated values at each step, so the histogram's
+    // atomics rarely collide); the run is stored afterwards, or before a
+    // bisection, which needs it.
+    bool stored = false;
+    auto store_run = [&]() __attribute__((always_inline)) {
+        sort_regs<PPT>(v);
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) T[k * NT + tid] = v[k];
-    const double cs = (double)(float)mean;
-    double t1 = 0.0, t2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        if (k < cnt_t) {
-            const double e = (double)v[k] - cs;
-            t1 += e;
-            t2 = fma(e, e, t2);
-        }
-    }
+        for (int k = 0; k < PPT; ++k) T[k * NT + tid] = v[k];
+        stored = true;
+    };
     Runs<NT> run{T, 0, cnt_t};
-    float vlo = (cnt_t > 0) ? T[tid] : INFINITY;
-    float vhi = (cnt_t > 0) ? T[(cnt_t - 1) * NT + tid] : -INFINITY;
 
     int ncur = n;
     int R0 = -1, bm = 0;      // rank of win[0] in the alive set (-1: no window)
@@ -456,20 +615,36 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
             if (k < cnt_t) f(v[k]);
     };
     auto each_run = [&](auto&& f) __attribute__((always_inline)) { run.each(f); };
+    auto each2_reg = [&](auto&& f1, auto&& f2) __attribute__((always_inline)) {
+        int r[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) r[k] = (k < cnt_t) ? f1(v[k]) : -1;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+            if (r[k] >= 0) f2(r[k], v[k]);
+    };
+    auto each2_run = [&](auto&& f1, auto&& f2) __attribute__((always_inline)) {
+        run.each([&](float x) {
+            const int r = f1(x);
+            if (r >= 0) f2(r, x);
+        });
+    };
     // exact median (an unevaluated pair when the count is even) of the alive
     // set, from the window, rebuilding it when the median has left it
-    auto median = [&](float wlo, float whi, auto&& each) __attribute__((always_inline)) {
+    auto median = [&](float wlo, float whi, auto&& each, auto&& each2) __attribute__((always_inline)) {
         const int r2 = ncur / 2;
         const int r1 = (ncur & 1) ? r2 : r2 - 1;
         float o1, o2;
         if (R0 < 0 || r1 - R0 < 0 || r2 - R0 >= bm) {
-            R0 = build_window<NT>(each, wlo, whi, max(r1 - kHalf, 0), min(r2 + kHalf, ncur - 1), bm, win, sh);
-            if (R0 < 0) R0 = build_window<NT>(each, wlo, whi, r1, r2, bm, win, sh);
+            R0 = build_window<NT>(each, each2, wlo, whi, max(r1 - kHalf, 0), min(r2 + kHalf, ncur - 1), int_vals, bm, win,
+                                  sh);
+            if (R0 < 0) R0 = build_window<NT>(each, each2, wlo, whi, r1, r2, int_vals, bm, win, sh);
         }
         if (R0 >= 0) {
             o1 = win[r1 - R0];
             o2 = win[r2 - R0];
         } else {
+            if (!stored) store_run();
             bisect_pair<NT>(run, lmn, lmx, r1, r2, o1, o2, sh);
         }
         if (r1 == r2) {
@@ -484,7 +659,22 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
         }
     };
     // the median of all pixels lies within one sigma of their mean
-    median((float)(mean - sig0), (float)(mean + sig0), each_reg);
+    median((float)(mean - sig0), (float)(mean + sig0), each_reg, each2_reg);
+    if (!stored) store_run();
+    // the run's FP64 sums, shifted by a float near the mean (so every shifted
+    // value is exact)
+    const double cs = (double)(float)mean;
+    double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if (k < cnt_t) {
+            const double e = (double)v[k] - cs;
+            t1 += e;
+            t2 = fma(e, e, t2);
+        }
+    }
+    float vlo = (cnt_t > 0) ? T[tid] : INFINITY;
+    float vhi = (cnt_t > 0) ? T[(cnt_t - 1) * NT + tid] : -INFINITY;
 
     int iters = 0;
     for (int it = 0; it < a.max_iter; ++it) {
@@ -513,7 +703,7 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
         double q1s = t1, q2s = t2;
         int nn = run.hi - run.lo, nrem = rem;
         float tmn = (run.lo < run.hi) ? vlo : INFINITY, tmx = (run.lo < run.hi) ? vhi : -INFINITY;
-        block_stats<NT>(q1s, q2s, nn, nrem, tmn, tmx, sh);
+        block_stats<NT>(q1s, q2s, nn, nrem, tmn, tmx, par, sh);
         ++iters;
         if (nn == ncur || nn == 0) break;
         ncur = nn;
@@ -525,7 +715,7 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
         const double vv = q2s / nd - q1 * q1;
         mean = cs + q1;
         sig = (lmn == lmx) ? 0.0 : sqrt(vv > 0.0 ? vv : 0.0);
-        median(lmn, lmx, each_run);
+        median(lmn, lmx, each_run, each2_run);
     }
     if (tid == 0) {
         const double med = (double)med_h + (double)med_l;
