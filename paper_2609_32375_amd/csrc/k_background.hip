@@ -134,27 +134,6 @@ __device__ __forceinline__ void block_stats(double& a, double& b, int& n, int& n
     }
 }
 
-// ascending bitonic sorting network over a thread's registers
-template <int PPT>
-__device__ __forceinline__ void sort_regs(float (&v)[PPT]) {
-#pragma unroll
-    for (int k = 2; k <= PPT; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-            for (int i = 0; i < PPT; ++i) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const float a = v[i], b = v[l];
-                    const bool up = (i & k) == 0;
-                    v[i] = up ? fminf(a, b) : fmaxf(a, b);
-                    v[l] = up ? fmaxf(a, b) : fminf(a, b);
-                }
-            }
-        }
-    }
-}
-
 // Ascending bitonic sort of the SEG = 64 E values a wavefront holds, E per
 // lane (lane l holds positions l E .. l E + E - 1): partners closer than E sit
 // in the same lane, the others are exchanged with a lane shuffle.
@@ -262,27 +241,6 @@ __device__ __forceinline__ float* sort_window(float* a, float* b, int P) {
     return a;
 }
 
-// The pixels of a mesh as per-thread sorted runs in LDS: thread t holds
-// T[k * NT + t] for k in [lo, hi), ascending.
-template <int NT>
-struct Runs {
-    const float* T;
-    int lo, hi;
-    template <typename F>
-    __device__ __forceinline__ void each(F&& f) const {
-        for (int k = lo; k < hi; ++k) f(T[k * NT + threadIdx.x]);
-    }
-    // number of this thread's values <= x (binary search in the run)
-    __device__ __forceinline__ int count_le(float x) const {
-        int a = lo, b = hi;
-        while (a < b) {
-            const int m = (a + b) >> 1;
-            if (T[m * NT + threadIdx.x] <= x) a = m + 1;
-            else b = m;
-        }
-        return a - lo;
-    }
-};
 
 // Bin b of a histogram is stored at slot hist_slot(b): the low bits are
 // XORed with a function of the thread b / per that owns the bin in the scan,
@@ -496,15 +454,16 @@ __device__ __forceinline__ int build_window(Each&& each, Each2&& each2, float wl
 }
 
 // Values of ranks r1 <= r2 of the alive set by bisection on the
-// order-preserving keys (count_le per run); for windows the buffer cannot hold.
-template <int NT, typename SH>
-__device__ void bisect_pair(const Runs<NT>& run, float lmn, float lmx, int r1, int r2, float& o1, float& o2,
+// order-preserving keys; count_le(x) gives the thread's alive values <= x.
+// For windows the buffer cannot hold.
+template <int NT, typename SH, typename CountLe>
+__device__ void bisect_pair(CountLe&& count_le, float lmn, float lmx, int r1, int r2, float& o1, float& o2,
                             SH& sh) {
     auto kth = [&](int k) {
         uint32_t a = f2ord(lmn), z = f2ord(lmx);
         while (a < z) {
             const uint32_t mid = a + ((z - a) >> 1);
-            const int cnt = block_sum_i<NT>(run.count_le(ord2f(mid)), sh);
+            const int cnt = block_sum_i<NT>(count_le(ord2f(mid)), sh);
             if (cnt > k) z = mid;
             else a = mid + 1;
         }
@@ -514,16 +473,23 @@ __device__ void bisect_pair(const Runs<NT>& run, float lmn, float lmx, int r1, i
     o2 = (r2 == r1) ? o1 : kth(r2);
 }
 
-// One workgroup per mesh.  Pass 0 gives sigma0 of all pixels; the pixels are
-// then sorted per thread and kept in LDS as runs.  The clipped set is a value
-// interval, so a clipping pass only moves each run's ends inward, taking the
-// dropped values off the thread's FP64 sums.  The median comes from a sorted
-// window of ranks around it (built through a histogram of the runs), which
-// stays valid while the ranks removed below keep the median inside it.
+// One workgroup per mesh; the mesh's pixels stay in registers (PPT per
+// thread) for the whole clipping loop, a clipped value being replaced by NaN
+// (pixel values are finite).  Pass 0 gives sigma0 of all pixels.  A clipping
+// pass tests every alive value against the interval, taking the dropped
+// values off the thread's FP64 sums.  The median comes from a sorted window of
+// ranks around it (built through a histogram of the alive values), which
+// stays valid while the ranks removed below keep the median inside it.  With
+// no pixel array in LDS, several meshes share a compute unit.
+// waves per SIMD the register budget is set for: two 8-wave or four 4-wave
+// workgroups per compute unit
 template <int NT, int PPT>
-__global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__ desc, int nframes, BkgArgs a) {
+constexpr int mesh_waves_per_eu() { return 4; }
+
+template <int NT, int PPT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(mesh_waves_per_eu<NT, PPT>())))
+void k_mesh_stats(const FrameDesc* __restrict__ desc, int nframes, BkgArgs a) {
     __shared__ MeshShared<kBins> sh;
-    __shared__ float T[NT * PPT];
     const int tid = threadIdx.x;
     const int gm = blockIdx.x;
     const int f = frame_of(nframes, gm, [&](int i) { return desc[i].mesh_base; });
@@ -543,7 +509,7 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
         int yy = tid / w, xx = tid - yy * w;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            v[k] = INFINITY;
+            v[k] = NAN;
             if (k * NT + tid < n) {
                 v[k] = load_px(d, x0 + xx, y0 + yy);
                 ++cnt_t;
@@ -588,64 +554,52 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
     double mean = c0 + m1;
     double sig = sig0;
 
-    // the thread's run: its values sorted, in LDS.  The first median reads the
-    // values from registers while they are still unsorted (the lanes of a
-    // wavefront then bin unrelated values at each step, so the histogram's
-    // atomics rarely collide); the run is stored afterwards, or before a
-    // bisection, which needs it.
-    bool stored = false;
-    auto store_run = [&]() __attribute__((always_inline)) {
-        sort_regs<PPT>(v);
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) T[k * NT + tid] = v[k];
-        stored = true;
-    };
-    Runs<NT> run{T, 0, cnt_t};
-
     int ncur = n;
     int R0 = -1, bm = 0;      // rank of win[0] in the alive set (-1: no window)
     const float* win = sh.buf;
     float med_h, med_l;
     float lmn = mn, lmx = mx;
-    // every alive value of the thread: from its registers before the first
-    // clipping pass, from its run in LDS afterwards
-    auto each_reg = [&](auto&& f) __attribute__((always_inline)) {
+    // every alive value of the thread (NaN marks the padding and clipped ones);
+    // each2 claims all results of f1 (in groups of 16) before calling f2
+    auto each_alive = [&](auto&& f) __attribute__((always_inline)) {
 #pragma unroll
         for (int k = 0; k < PPT; ++k)
-            if (k < cnt_t) f(v[k]);
+            if (v[k] == v[k]) f(v[k]);
     };
-    auto each_run = [&](auto&& f) __attribute__((always_inline)) { run.each(f); };
-    auto each2_reg = [&](auto&& f1, auto&& f2) __attribute__((always_inline)) {
-        int r[PPT];
+    auto each2_alive = [&](auto&& f1, auto&& f2) __attribute__((always_inline)) {
+        constexpr int C = PPT < 16 ? PPT : 16;
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) r[k] = (k < cnt_t) ? f1(v[k]) : -1;
+        for (int k0 = 0; k0 < PPT; k0 += C) {
+            int r[C];
 #pragma unroll
-        for (int k = 0; k < PPT; ++k)
-            if (r[k] >= 0) f2(r[k], v[k]);
+            for (int k = 0; k < C; ++k) r[k] = (v[k0 + k] == v[k0 + k]) ? f1(v[k0 + k]) : -1;
+#pragma unroll
+            for (int k = 0; k < C; ++k)
+                if (r[k] >= 0) f2(r[k], v[k0 + k]);
+        }
     };
-    auto each2_run = [&](auto&& f1, auto&& f2) __attribute__((always_inline)) {
-        run.each([&](float x) {
-            const int r = f1(x);
-            if (r >= 0) f2(r, x);
-        });
+    auto count_le = [&](float x) {
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) c += (v[k] <= x) ? 1 : 0;   // false for NaN
+        return c;
     };
     // exact median (an unevaluated pair when the count is even) of the alive
     // set, from the window, rebuilding it when the median has left it
-    auto median = [&](float wlo, float whi, auto&& each, auto&& each2) __attribute__((always_inline)) {
+    auto median = [&](float wlo, float whi) __attribute__((always_inline)) {
         const int r2 = ncur / 2;
         const int r1 = (ncur & 1) ? r2 : r2 - 1;
         float o1, o2;
         if (R0 < 0 || r1 - R0 < 0 || r2 - R0 >= bm) {
-            R0 = build_window<NT>(each, each2, wlo, whi, max(r1 - kHalf, 0), min(r2 + kHalf, ncur - 1), int_vals, bm, win,
-                                  sh);
-            if (R0 < 0) R0 = build_window<NT>(each, each2, wlo, whi, r1, r2, int_vals, bm, win, sh);
+            R0 = build_window<NT>(each_alive, each2_alive, wlo, whi, max(r1 - kHalf, 0), min(r2 + kHalf, ncur - 1),
+                                  int_vals, bm, win, sh);
+            if (R0 < 0) R0 = build_window<NT>(each_alive, each2_alive, wlo, whi, r1, r2, int_vals, bm, win, sh);
         }
         if (R0 >= 0) {
             o1 = win[r1 - R0];
             o2 = win[r2 - R0];
         } else {
-            if (!stored) store_run();
-            bisect_pair<NT>(run, lmn, lmx, r1, r2, o1, o2, sh);
+            bisect_pair<NT>(count_le, lmn, lmx, r1, r2, o1, o2, sh);
         }
         if (r1 == r2) {
             med_h = o1;
@@ -659,10 +613,9 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
         }
     };
     // the median of all pixels lies within one sigma of their mean
-    median((float)(mean - sig0), (float)(mean + sig0), each_reg, each2_reg);
-    if (!stored) store_run();
-    // the run's FP64 sums, shifted by a float near the mean (so every shifted
-    // value is exact)
+    median((float)(mean - sig0), (float)(mean + sig0));
+    // the alive set's FP64 sums, shifted by a float near the mean (so every
+    // shifted value is exact)
     const double cs = (double)(float)mean;
     double t1 = 0.0, t2 = 0.0;
 #pragma unroll
@@ -673,36 +626,32 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
             t2 = fma(e, e, t2);
         }
     }
-    float vlo = (cnt_t > 0) ? T[tid] : INFINITY;
-    float vhi = (cnt_t > 0) ? T[(cnt_t - 1) * NT + tid] : -INFINITY;
 
-    int iters = 0;
+    int iters = 0, na = cnt_t;   // alive values of the thread
     for (int it = 0; it < a.max_iter; ++it) {
         const float thr = (float)((double)a.clip * sig);
-        auto keep = [&](float x) { return fabsf((x - med_h) - med_l) <= thr; };
-        auto below = [&](float x) { return ((x - med_h) - med_l) < -thr; };
-        // clipping pass: move the run's ends inward.  Only values clipped for
-        // lying below the window shift the ranks of the survivors; a run
-        // lying wholly above it is emptied from the top.
-        int rem = 0;
-        while (run.lo < run.hi && below(vlo)) {
-            const double e = (double)vlo - cs;
-            t1 -= e;
-            t2 = fma(-e, e, t2);
-            ++run.lo;
-            ++rem;
-            if (run.lo < run.hi) vlo = T[run.lo * NT + tid];
+        // clipping pass: every alive value outside the interval is dropped;
+        // only those below it shift the ranks of the survivors.  A NaN (dead)
+        // value compares false, and fminf / fmaxf pass over it.
+        int nrem = 0;
+        float tmn = INFINITY, tmx = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const float x = v[k];
+            const float dx = (x - med_h) - med_l;
+            if (fabsf(dx) > thr) {
+                const double e = (double)x - cs;
+                t1 -= e;
+                t2 = fma(-e, e, t2);
+                nrem += (dx < -thr) ? 1 : 0;
+                --na;
+                v[k] = NAN;
+            }
+            tmn = fminf(tmn, v[k]);
+            tmx = fmaxf(tmx, v[k]);
         }
-        while (run.lo < run.hi && !keep(vhi)) {
-            const double e = (double)vhi - cs;
-            t1 -= e;
-            t2 = fma(-e, e, t2);
-            --run.hi;
-            if (run.lo < run.hi) vhi = T[(run.hi - 1) * NT + tid];
-        }
+        int nn = na;
         double q1s = t1, q2s = t2;
-        int nn = run.hi - run.lo, nrem = rem;
-        float tmn = (run.lo < run.hi) ? vlo : INFINITY, tmx = (run.lo < run.hi) ? vhi : -INFINITY;
         block_stats<NT>(q1s, q2s, nn, nrem, tmn, tmx, par, sh);
         ++iters;
         if (nn == ncur || nn == 0) break;
@@ -715,7 +664,7 @@ __global__ __launch_bounds__(NT) void k_mesh_stats(const FrameDesc* __restrict__
         const double vv = q2s / nd - q1 * q1;
         mean = cs + q1;
         sig = (lmn == lmx) ? 0.0 : sqrt(vv > 0.0 ? vv : 0.0);
-        median(lmn, lmx, each_run, each2_run);
+        median(lmn, lmx);
     }
     if (tid == 0) {
         const double med = (double)med_h + (double)med_l;
