@@ -70,8 +70,8 @@ typedef enum gp_precision { GP_PREC_F32 = 0, GP_PREC_F64 = 1 } gp_precision;
 
 /* One frame: row-major pixels, x = column in [0, width), y = row in
  * [0, height), element (x, y) at data[y * pitch + x] (pitch in elements,
- * >= width).  Values must be finite.  Every call takes 1 to 1024 frames
- * (more: GP_ERR_UNSUPPORTED). */
+ * >= width, pitch * height < 2^31, else GP_ERR_UNSUPPORTED).  Values must
+ * be finite.  Every call takes 1 to 1024 frames (more: GP_ERR_UNSUPPORTED). */
 typedef struct gp_frame {
     const void* data;      /* device pointer */
     int32_t width, height;

@@ -504,21 +504,44 @@ void k_mesh_stats(const FrameDesc* __restrict__ desc, int nframes, BkgArgs a) {
     float v[PPT];
     int cnt_t = 0;
     {
-        // pixel k * NT + tid of the mesh, stepped by NT without divisions
+        // pixel k * NT + tid of the mesh.  A full mesh whose width divides NT
+        // puts every thread's k-th pixel dy = NT / w rows below its previous
+        // one: buffer loads with the row step as a scalar offset.  Other
+        // meshes step by NT without divisions.
         const int dy = NT / w, dx = NT - dy * w;
         int yy = tid / w, xx = tid - yy * w;
+        const bool u16 = d.dtype == kDtypeU16;
+        const int es = u16 ? 2 : 4;
+        // (byte offsets within the mesh must fit the 32-bit buffer offsets)
+        if (n == NT * PPT && dx == 0 && (int64_t)h * d.pitch * es < ((int64_t)1 << 31)) {
+            const int64_t o0 = ((int64_t)y0 * d.pitch + x0) * es;
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)d.data + o0), (short)0, 0x7fffffff, 0x00020000);
+            const int vo = (yy * (int)d.pitch + xx) * es;
+            const int so = dy * (int)d.pitch * es;
+            if (u16) {
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            v[k] = NAN;
-            if (k * NT + tid < n) {
-                v[k] = load_px(d, x0 + xx, y0 + yy);
-                ++cnt_t;
+                for (int k = 0; k < PPT; ++k) v[k] = (float)__builtin_amdgcn_raw_buffer_load_b16(rs, vo, k * so, 0);
+            } else {
+#pragma unroll
+                for (int k = 0; k < PPT; ++k)
+                    v[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, k * so, 0));
             }
-            xx += dx;
-            yy += dy;
-            if (xx >= w) {
-                xx -= w;
-                ++yy;
+            cnt_t = PPT;
+        } else {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                v[k] = NAN;
+                if (k * NT + tid < n) {
+                    v[k] = load_px(d, x0 + xx, y0 + yy);
+                    ++cnt_t;
+                }
+                xx += dx;
+                yy += dy;
+                if (xx >= w) {
+                    xx -= w;
+                    ++yy;
+                }
             }
         }
     }

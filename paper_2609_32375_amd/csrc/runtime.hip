@@ -136,8 +136,8 @@ gp_status check_frames(const gp_frame* frames, int32_t nframes) {
         if (F.pitch < F.width) return fail(GP_ERR_INVALID_ARG, "frame %d: pitch < width", f);
         if (F.dtype != GP_U16 && F.dtype != GP_F32)
             return fail(GP_ERR_INVALID_ARG, "frame %d: unknown dtype %d", f, F.dtype);
-        if ((int64_t)F.width * F.height >= (int64_t)1 << 31)
-            return fail(GP_ERR_UNSUPPORTED, "frame %d: more than 2^31 pixels", f);
+        if (F.pitch * F.height >= (int64_t)1 << 31)
+            return fail(GP_ERR_UNSUPPORTED, "frame %d: pitch * height >= 2^31 elements", f);
     }
     return GP_OK;
 }

@@ -58,6 +58,10 @@ def test_layout_and_validation_errors_are_synchronous():
         L.gp_background_layout([L.gp_frame(1, 10, 10, 5, 2)], bp)     # pitch < width
     with pytest.raises(L.GpError):
         L.gp_background_layout([L.gp_frame(1, 10, 10, 10, 7)], bp)    # dtype
+    # a frame spans pitch * height elements, addressed with 32-bit offsets
+    with pytest.raises(L.GpError) as e:
+        L.gp_background_layout([L.gp_frame(1, 1024, 1 << 16, 1 << 15, 2)], bp)
+    assert e.value.status == L.GP_ERR_UNSUPPORTED
     # at most 1024 frames per call
     with pytest.raises(L.GpError) as e:
         L.gp_background_layout([_frame(32, 32)] * 1025, bp)
