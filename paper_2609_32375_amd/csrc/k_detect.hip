@@ -188,38 +188,39 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     //    while the row cubics and the column pieces are built
     constexpr int REG = kSep ? kTile + 2 * kR : kRegion;   // region row stride
     constexpr int NL = (REG * REG + 255) / 256;
-    float pv[NL];
-    // a region inside the frame (no reflection) is addressed from its first
-    // pixel with 32-bit offsets; tiles at the frame border take the general path
-    const bool inner = x0 >= rx && y0 >= ry && x0 + tw + rx <= d.W && y0 + th + ry <= d.H &&
-                       d.pitch < (int64_t)(1 << 24);
+    // a region inside the frame (no reflection) of a separable filter: each
+    // lane owns one of the tile's 64 columns and steps down the rows of its
+    // wavefront (wv, wv + 4, ...) with buffer loads whose row offset is
+    // scalar; the 2 R halo columns are spread over the block
+    constexpr int CR = (REG + 3) / 4;                          // rows per wavefront
+    constexpr int HW = 2 * kR;                                 // halo columns
+    constexpr int HL = (REG * HW + 255) / 256;                 // halo values per thread
+    constexpr int NV = (NL > CR + HL) ? NL : CR + HL;
+    float pv[NV];
+    const bool u16 = d.dtype == kDtypeU16;
+    const int es = u16 ? 2 : 4;
+    const bool inner = kSep && x0 >= rx && y0 >= ry && x0 + tw + rx <= d.W && y0 + th + ry <= d.H &&
+                       (int64_t)RH * d.pitch * es < ((int64_t)1 << 31);
+    auto halo_col = [&](int c) { return c < kR ? c : c + kTile; };
     if (inner) {
-        const int64_t o0 = (int64_t)(y0 - ry) * d.pitch + (x0 - rx);
-        const int pitch = (int)d.pitch;
-        if (d.dtype == kDtypeU16) {
-            gu16_t* b = (gu16_t*)d.data + o0;
+        const int64_t o0 = ((int64_t)(y0 - ry) * d.pitch + (x0 - rx)) * es;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)d.data + o0), (short)0, 0x7fffffff, 0x00020000);
+        const int rowb = (int)d.pitch * es;
+        auto ld = [&](int vo, int so) __attribute__((always_inline)) {
+            return u16 ? (float)__builtin_amdgcn_raw_buffer_load_b16(rs, vo, so, 0)
+                       : __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
+        };
 #pragma unroll
-            for (int i = 0; i < NL; ++i) {
-                const int e = tid + 256 * i;
-                const int r = e / REG, c = e - r * REG;
-                const bool ok = r < RH && c < RW;
-                // every lane loads (offset 0 = the region's first pixel when
-                // outside it), so the loads issue back to back
-                const float v = (float)b[ok ? __umul24(r, pitch) + c : 0u];
-                pv[i] = ok ? v : 0.0f;
-            }
-        } else {
-            gfloat_t* b = (gfloat_t*)d.data + o0;
+        for (int q = 0; q < CR; ++q) {
+            const int r = wv + 4 * q;
+            pv[q] = (r < RH) ? ld((rx + lane) * es, r * rowb) : 0.0f;
+        }
 #pragma unroll
-            for (int i = 0; i < NL; ++i) {
-                const int e = tid + 256 * i;
-                const int r = e / REG, c = e - r * REG;
-                const bool ok = r < RH && c < RW;
-                // every lane loads (offset 0 = the region's first pixel when
-                // outside it), so the loads issue back to back
-                const float v = b[ok ? __umul24(r, pitch) + c : 0u];
-                pv[i] = ok ? v : 0.0f;
-            }
+        for (int i = 0; i < HL; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e / (HW > 0 ? HW : 1), c = e - r * HW;
+            pv[CR + i] = (r < RH) ? ld((r * (int)d.pitch + halo_col(c)) * es, 0) : 0.0f;
         }
     } else {
 #pragma unroll
@@ -245,12 +246,30 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     }
     __syncthreads();
     // 2. M = I - B over the region
+    if (inner) {
+        const int c = rx + lane;
+        const int pc = sh.colp[c];
+        const Real sx = sh.colsx[c];
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-        const int e = tid + 256 * i;
-        const int r = e / REG, c = e - r * REG;
-        if (r < RH && c < RW)
-            sh.u2.ms[r * MS + c] = eval_M(sh.u1.tab[r * kNixMax + sh.colp[c]], sh.colsx[c], (Real)pv[i]);
+        for (int q = 0; q < CR; ++q) {
+            const int r = wv + 4 * q;
+            if (r < RH) sh.u2.ms[r * MS + c] = eval_M(sh.u1.tab[r * kNixMax + pc], sx, (Real)pv[q]);
+        }
+#pragma unroll
+        for (int i = 0; i < HL; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e / (HW > 0 ? HW : 1), hc = halo_col(e - r * HW);
+            if (r < RH)
+                sh.u2.ms[r * MS + hc] = eval_M(sh.u1.tab[r * kNixMax + sh.colp[hc]], sh.colsx[hc], (Real)pv[CR + i]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e / REG, c = e - r * REG;
+            if (r < RH && c < RW)
+                sh.u2.ms[r * MS + c] = eval_M(sh.u1.tab[r * kNixMax + sh.colp[c]], sh.colsx[c], (Real)pv[i]);
+        }
     }
     // thresholds t R of the 16 pixels this lane owns: column `lane`, rows 16 wv ..
     const bool colok = lane < tw;
