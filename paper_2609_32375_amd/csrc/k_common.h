@@ -14,7 +14,7 @@ namespace gpk {
 constexpr int kTile = 64;          // detection tile edge; equals the wavefront width
 constexpr int kMaxK = 15;          // largest filter edge
 constexpr int kMaxR = kMaxK / 2;   // largest filter half-width
-constexpr int kNixMax = 8;         // spline x-pieces a tile region can touch (mesh >= 16)
+constexpr int kNixMax = 6;         // spline x-pieces a tile region (<= 78 columns) can touch (mesh >= 16)
 constexpr int kRegion = kTile + 2 * kMaxR;  // 78: tile plus filter halo
 constexpr int kLocalRecs = 160;    // components per tile accumulated in LDS
 constexpr int kMaxRadii = 8;

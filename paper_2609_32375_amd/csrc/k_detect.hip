@@ -42,28 +42,28 @@ struct LocalRec {
     int32_t rootpix, pad;
 };
 
-// LDS regions are reused phase by phase:
-//   u1: row cubics (build M, R) -> horizontal pass -> labels + piece ids
+// LDS regions are reused phase by phase (REG: region width and height, the
+// tile plus the filter halo; 40 KB for FP32 and REG <= 72, four workgroups
+// per compute unit):
+//   u1: row cubics (build M, R) -> horizontal pass -> labels -> piece ids
 //   u2: M over tile + halo      -> piece records (M is then held in VGPRs)
-template <typename Real>
+template <typename Real, int REG>
 struct DetShared {
     union U1 {
-        RowT<Real> tab[kRegion * kNixMax];
-        Real hs[kRegion * kTile];
-        struct {
-            int32_t lab[kTile * kTile];
-            int16_t comp[kTile * kTile];
-        } l;
+        RowT<Real> tab[REG * kNixMax];
+        Real hs[REG * kTile];
+        int32_t lab[kTile * kTile];
+        int16_t comp[kTile * kTile];   // written once no label is read any more
     } u1;
     union U2 {
-        Real ms[kRegion * (kRegion + 1)];
+        Real ms[REG * REG];
         LocalRec rec[kLocalRecs];
     } u2;
     uint64_t rowmask[kTile];
     int32_t rowoff[kTile + 1];
     int32_t misc[4];
-    int32_t colp[kRegion];      // x piece of each region column (relative to the first)
-    Real colsx[kRegion];        // its local coordinate in that piece
+    int32_t colp[REG];      // x piece of each region column (relative to the first)
+    Real colsx[REG];        // its local coordinate in that piece
 };
 
 // find with path halving: every link points to a smaller index, so writing a
@@ -161,11 +161,12 @@ struct RunAcc<double> {
 // (taps in registers, fully unrolled); RAD < 0: any kernel, applied densely.
 template <typename Real, int RAD>
 __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs* __restrict__ pa) {
-    __shared__ DetShared<Real> sh;
     constexpr bool kSep = RAD >= 0;
     constexpr int kR = kSep ? RAD : 0;
     constexpr bool kDbl = sizeof(Real) == 8;
-    constexpr int MS = kRegion + 1;
+    constexpr int REG = kSep ? kTile + 2 * kR : kRegion;   // region row stride
+    constexpr int MS = REG;
+    __shared__ DetShared<Real, REG> sh;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int gt = xcd_item(blockIdx.x, (wk.total_tiles + kXcds - 1) / kXcds);
     if (gt >= wk.total_tiles) return;
@@ -186,7 +187,6 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     // 1. the region's pixels (tile + halo, reflected at the frame border),
     //    flattened over the block so the loads coalesce and are all in flight
     //    while the row cubics and the column pieces are built
-    constexpr int REG = kSep ? kTile + 2 * kR : kRegion;   // region row stride
     constexpr int NL = (REG * REG + 255) / 256;
     // a region inside the frame (no reflection) of a separable filter: each
     // lane owns one of the tile's 64 columns and steps down the rows of its
@@ -233,6 +233,7 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     }
     for (int e = tid; e < RH * nix; e += 256) {
         const int r = e / nix, pi = e - r * nix;
+        if (pi >= kNixMax) continue;
         const int ys = reflect_idx(y0 - ry + r, d.H);
         const int jy = piece_of(ys, d.H, d.mh);
         const double u = (double)ys - piece_ref(jy, d.H, d.mh);
@@ -363,8 +364,8 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     //    adjacent rows are then united once per touching pair, in an LDS
     //    union-find whose roots are the smallest raster index of each
     //    component.
-    int32_t* lab = sh.u1.l.lab;
-    int16_t* comp = sh.u1.l.comp;
+    int32_t* lab = sh.u1.lab;
+    int16_t* comp = sh.u1.comp;
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));   // lanes < lane
     // the wavefront's own row masks stay in registers; the row above its
     // first row is read from LDS
@@ -395,7 +396,7 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     // pairs in its own share of the (now free) M region, then the whole
     // block applies them concurrently; a full list falls back to uniting at
     // once.  Pixel indices are < 4096: a pair packs into 24 bits.
-    constexpr int PCAP = (int)(sizeof(typename DetShared<Real>::U2) / sizeof(uint32_t)) / 4;
+    constexpr int PCAP = (int)(sizeof(typename DetShared<Real, REG>::U2) / sizeof(uint32_t)) / 4;
     uint32_t* plist = reinterpret_cast<uint32_t*>(&sh.u2) + wv * PCAP;
     int npair = 0;
     const uint64_t mtop = (wv > 0) ? sh.rowmask[16 * wv - 1] : 0ull;
