@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
     ap.add_argument("--traffic", nargs=5, metavar=("KERNEL", "FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"))
+    ap.add_argument("--traffic-last", type=int, default=5,
+                    help="dispatches counted: the last N of the kernel (the profiled run's steps)")
     return ap.parse_args()
 
 
@@ -79,18 +81,21 @@ def copy_calibration(mib):
     print(json.dumps({"calibration_bytes_each_way": n * 4}), flush=True)
 
 
-def counter_mean(path, fragment, counter):
+def counter_mean(path, fragment, counter, last=None):
     """Mean of a counter (summed over its instances) per dispatch of the kernels
-    whose name contains `fragment`, from a rocprofv3 counter_collection.csv."""
+    whose name contains `fragment`, from a rocprofv3 counter_collection.csv;
+    `last`: only the last that many such dispatches (the timed steps, after the
+    launch-shape autotuning that runs the kernel's other shapes first)."""
     import csv
     per = {}
     with open(path) as fh:
         for r in csv.DictReader(fh):
             if fragment in r["Kernel_Name"] and r["Counter_Name"] == counter:
-                per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+                per[int(r["Dispatch_Id"])] = per.get(int(r["Dispatch_Id"]), 0.0) + float(r["Counter_Value"])
     if not per:
         raise SystemExit(f"no {counter} rows for kernels named *{fragment}* in {path}")
-    return sum(per.values()) / len(per), len(per)
+    ids = sorted(per)[-last:] if last else sorted(per)
+    return sum(per[i] for i in ids) / len(ids), len(ids)
 
 
 def write_traffic(a):
@@ -99,8 +104,8 @@ def write_traffic(a):
     cal_bytes = None
     # the calibration copy moves the same bytes each way: its last dispatch is
     # the timed one (the first is a warm-up of identical size)
-    fk, nf = counter_mean(fetch, frag, "FETCH_SIZE")
-    wk, nw = counter_mean(write, frag, "WRITE_SIZE")
+    fk, nf = counter_mean(fetch, frag, "FETCH_SIZE", a.traffic_last)
+    wk, nw = counter_mean(write, frag, "WRITE_SIZE", a.traffic_last)
     cfk, _ = counter_mean(cfetch, CAL_KERNEL, "FETCH_SIZE")
     cwk, _ = counter_mean(cwrite, CAL_KERNEL, "WRITE_SIZE")
     cal_bytes = a.copy_calibration * (1 << 20) if a.copy_calibration else 1 << 30
