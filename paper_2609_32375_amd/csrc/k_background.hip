@@ -818,8 +818,142 @@ __device__ void piece_poly(int n, const double* t, const double* f, int fs, cons
 }
 
 constexpr int kSplThreads = 256;
+constexpr int kSplCols = 64;       // small grids: columns per workgroup (one wavefront)
+constexpr int kSplSmallN = 100;    // small grids: knots per axis held in LDS
 
-// y-splines: blockIdx.y = frame; one thread per (quantity, mesh column)
+// The same elimination with reciprocals: ih[k] = 1 / (t_{k+1} - t_k) (every
+// thread computes its share before the call), c[k] and iden[k] = 1 / den[k]
+// (one thread), so the column solves are chains of FMAs.
+__device__ __forceinline__ void spline_factor_inv(int n, const double* t, double* c, double* iden) {
+    double cp = 0.0;
+    for (int k = 1; k <= n - 2; ++k) {
+        const double h0 = t[k] - t[k - 1], h1 = t[k + 1] - t[k];
+        const double b = 2.0 * (h0 + h1);
+        const double id = 1.0 / ((k == 1) ? b : b - h0 * cp);
+        iden[k] = id;
+        cp = h1 * id;
+        c[k] = cp;
+    }
+}
+
+// second derivatives m (stride ms) of the column f (stride fs); m holds the
+// forward sweep's values until the back sweep overwrites them in place
+__device__ __forceinline__ void spline_solve_inv(int n, const double* t, const double* c, const double* iden,
+                                                 const double* ih, const double* f, int fs, double* m, int ms) {
+    m[0] = 0.0;
+    if (n > 1) m[(n - 1) * ms] = 0.0;
+    if (n < 3) return;
+    double rp = 0.0;
+    double f0 = f[0], f1 = f[fs];
+    for (int k = 1; k <= n - 2; ++k) {
+        const double f2 = f[(k + 1) * fs];
+        const double rhs = 6.0 * ((f2 - f1) * ih[k] - (f1 - f0) * ih[k - 1]);
+        rp = (rhs - (t[k] - t[k - 1]) * rp) * iden[k];
+        m[k * ms] = rp;
+        f0 = f1;
+        f1 = f2;
+    }
+    double mk = rp;
+    for (int k = n - 3; k >= 1; --k) {
+        mk = m[k * ms] - c[k] * mk;
+        m[k * ms] = mk;
+    }
+}
+
+// piece_poly with the reciprocal spacings
+__device__ __forceinline__ void piece_poly_inv(int n, const double* t, const double* ih, const double* f, int fs,
+                                               const double* m, int ms, int piece, double out[4]) {
+    constexpr double kSixth = 1.0 / 6.0;
+    out[0] = out[1] = out[2] = out[3] = 0.0;
+    if (n == 1) {
+        out[0] = f[0];
+        return;
+    }
+    if (piece == 0) {
+        const double h = t[1] - t[0];
+        out[0] = f[0];
+        out[1] = (f[fs] - f[0]) * ih[0] - h * (2.0 * m[0] + m[ms]) * kSixth;
+        return;
+    }
+    if (piece == n) {
+        const double h = t[n - 1] - t[n - 2];
+        out[0] = f[(n - 1) * fs];
+        out[1] = (f[(n - 1) * fs] - f[(n - 2) * fs]) * ih[n - 2] + h * (m[(n - 2) * ms] + 2.0 * m[(n - 1) * ms]) * kSixth;
+        return;
+    }
+    const int j = piece - 1;
+    const double h = t[j + 1] - t[j];
+    const double mj = m[j * ms], mj1 = m[(j + 1) * ms];
+    out[0] = f[j * fs];
+    out[1] = (f[(j + 1) * fs] - f[j * fs]) * ih[j] - h * (2.0 * mj + mj1) * kSixth;
+    out[2] = 0.5 * mj;
+    out[3] = (mj1 - mj) * ih[j] * kSixth;
+}
+
+// Small grids (at most kSplSmallN knots on the solved axis): a wavefront takes
+// 64 columns; their values are loaded into LDS at once (all loads in flight),
+// solved and cut into pieces there, and only the pieces go to global memory.
+// blockIdx.y = frame.  Y: one column per (quantity, mesh column).
+__global__ __launch_bounds__(kSplCols) void k_spline_y_small(const FrameDesc* __restrict__ desc) {
+    __shared__ double tk[kSplSmallN], cf[kSplSmallN], idn[kSplSmallN], ih[kSplSmallN];
+    __shared__ double fl[kSplSmallN * kSplCols], ml[kSplSmallN * kSplCols];
+    const FrameDesc& d = desc[blockIdx.y];
+    const int ny = d.ny, nx = d.nx, lane = threadIdx.x;
+    if (blockIdx.x * kSplCols >= 2 * nx) return;
+    const int g = blockIdx.x * kSplCols + lane;
+    const bool on = g < 2 * nx;
+    const int q = on ? g / nx : 0, i = on ? g - q * nx : 0;
+    const double* col = (q ? d.rms : d.back) + i;
+    for (int k = 0; k < ny; ++k) fl[k * kSplCols + lane] = on ? col[(size_t)k * nx] : 0.0;
+    for (int k = lane; k < ny; k += kSplCols) tk[k] = knot_at(k, d.H, d.mh);
+    __syncthreads();
+    for (int k = lane; k + 1 < ny; k += kSplCols) ih[k] = 1.0 / (tk[k + 1] - tk[k]);
+    if (lane == 0) spline_factor_inv(ny, tk, cf, idn);
+    __syncthreads();
+    if (!on) return;
+    spline_solve_inv(ny, tk, cf, idn, ih, fl + lane, kSplCols, ml + lane, kSplCols);
+    for (int jy = 0; jy <= ny; ++jy) {
+        double c[4];
+        piece_poly_inv(ny, tk, ih, fl + lane, kSplCols, ml + lane, kSplCols, jy, c);
+        double* o = d.ycoef + (((size_t)q * (ny + 1) + jy) * nx + i) * 4;
+        o[0] = c[0];
+        o[1] = c[1];
+        o[2] = c[2];
+        o[3] = c[3];
+    }
+}
+
+// X: one column per (quantity, y piece, power of u), as k_spline_x
+__global__ __launch_bounds__(kSplCols) void k_spline_x_small(const FrameDesc* __restrict__ desc) {
+    __shared__ double tk[kSplSmallN], cf[kSplSmallN], idn[kSplSmallN], ih[kSplSmallN];
+    __shared__ double fl[kSplSmallN * kSplCols], ml[kSplSmallN * kSplCols];
+    const FrameDesc& d = desc[blockIdx.y];
+    const int nx = d.nx, ny = d.ny, lane = threadIdx.x;
+    const int G = 8 * (ny + 1);
+    if (blockIdx.x * kSplCols >= G) return;
+    const int g = blockIdx.x * kSplCols + lane;
+    const bool on = g < G;
+    const int r = g & 3;
+    const int jy = on ? (g >> 2) % (ny + 1) : 0;
+    const int q = on ? (g >> 2) / (ny + 1) : 0;
+    const double* vals = d.ycoef + (((size_t)q * (ny + 1) + jy) * nx) * 4 + r;  // stride 4
+    for (int k = 0; k < nx; ++k) fl[k * kSplCols + lane] = on ? vals[(size_t)k * 4] : 0.0;
+    for (int k = lane; k < nx; k += kSplCols) tk[k] = knot_at(k, d.W, d.mw);
+    __syncthreads();
+    for (int k = lane; k + 1 < nx; k += kSplCols) ih[k] = 1.0 / (tk[k + 1] - tk[k]);
+    if (lane == 0) spline_factor_inv(nx, tk, cf, idn);
+    __syncthreads();
+    if (!on) return;
+    spline_solve_inv(nx, tk, cf, idn, ih, fl + lane, kSplCols, ml + lane, kSplCols);
+    for (int ix = 0; ix <= nx; ++ix) {
+        double c[4];
+        piece_poly_inv(nx, tk, ih, fl + lane, kSplCols, ml + lane, kSplCols, ix, c);
+        double* o = d.coef + (((size_t)q * (ny + 1) + jy) * (nx + 1) + ix) * 16;
+        for (int p = 0; p < 4; ++p) o[p * 4 + r] = c[p];
+    }
+}
+
+// Larger grids: y-splines, blockIdx.y = frame; one thread per (quantity, mesh column)
 __global__ __launch_bounds__(kSplThreads) void k_spline_y(const FrameDesc* __restrict__ desc) {
     __shared__ double tk[kSplineMaxKnots], cf[kSplineMaxKnots], dn[kSplineMaxKnots];
     const FrameDesc& d = desc[blockIdx.y];
@@ -907,8 +1041,14 @@ void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, in
 }
 
 void launch_spline(const FrameDesc* desc, int nframes, int max_nx, int max_ny, hipStream_t s) {
-    k_spline_y<<<dim3((2 * max_nx + kSplThreads - 1) / kSplThreads, nframes), kSplThreads, 0, s>>>(desc);
-    k_spline_x<<<dim3((8 * (max_ny + 1) + kSplThreads - 1) / kSplThreads, nframes), kSplThreads, 0, s>>>(desc);
+    if (max_ny <= kSplSmallN)
+        k_spline_y_small<<<dim3((2 * max_nx + kSplCols - 1) / kSplCols, nframes), kSplCols, 0, s>>>(desc);
+    else
+        k_spline_y<<<dim3((2 * max_nx + kSplThreads - 1) / kSplThreads, nframes), kSplThreads, 0, s>>>(desc);
+    if (max_nx <= kSplSmallN)
+        k_spline_x_small<<<dim3((8 * (max_ny + 1) + kSplCols - 1) / kSplCols, nframes), kSplCols, 0, s>>>(desc);
+    else
+        k_spline_x<<<dim3((8 * (max_ny + 1) + kSplThreads - 1) / kSplThreads, nframes), kSplThreads, 0, s>>>(desc);
 }
 
 // ---------------------------------------------------------------------------

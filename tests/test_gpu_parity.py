@@ -138,7 +138,10 @@ def test_mesh_statistics_match_oracle(P, case):
     ph.close()
 
 
-@pytest.mark.parametrize("shape", [(300, 200, 64, 64), (130, 77, 32, 16), (50, 20, 64, 64), (1000, 40, 128, 16)])
+# the spline kernels hold up to 100 knots per axis in LDS; longer axes take
+# the global-scratch path: 100 knots (LDS), 107 along x, 107 along y
+@pytest.mark.parametrize("shape", [(300, 200, 64, 64), (130, 77, 32, 16), (50, 20, 64, 64), (1000, 40, 128, 16),
+                                   (1600, 24, 16, 16), (1700, 40, 16, 16), (40, 1700, 16, 16)])
 def test_background_maps_match_oracle_spline(P, shape):
     W, H, mw, mh = shape
     _say("map case", shape)
