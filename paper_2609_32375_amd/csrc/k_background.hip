@@ -717,27 +717,61 @@ __device__ double median_small(double* w, int n, int S) {
     return (n & 1) ? w[(n / 2) * S] : 0.5 * (w[(n / 2 - 1) * S] + w[(n / 2) * S]);
 }
 
-// one thread per mesh; each thread's window sits in its own LDS column
+// median of the first n of w[0, N) (the rest +inf) by rank counting: the value
+// of rank k has k smaller values (equal ones ranked by position)
+template <int N>
+__device__ __forceinline__ double median_regs(const double (&w)[N], int n) {
+    const int k1 = (n - 1) / 2, k2 = n / 2;
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        int r = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) r += (w[j] < w[i] || (w[j] == w[i] && j < i)) ? 1 : 0;
+        a = (r == k1) ? w[i] : a;
+        b = (r == k2) ? w[i] : b;
+    }
+    return (n & 1) ? a : 0.5 * (a + b);
+}
+
+// one thread per mesh.  F > 0: the F x F window in registers (all loads in
+// flight); F == 0: any size, the window in the thread's own LDS column
 constexpr int kGridThreads = 64;
+template <int F>
 __global__ __launch_bounds__(kGridThreads) void k_grid_filter(const FrameDesc* __restrict__ desc, int nframes,
                                                               int total, int fsize) {
-    __shared__ double w[49 * kGridThreads];
+    __shared__ double w[(F > 0) ? 1 : 49 * kGridThreads];
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total) return;
     const int f = frame_of(nframes, g, [&](int i) { return desc[i].mesh_base; });
     const FrameDesc& d = desc[f];
     const int lm = g - d.mesh_base;
     const int i = lm % d.nx, j = lm / d.nx;
-    const int hh = fsize / 2;
-    double* wt = w + threadIdx.x;
-    for (int q = 0; q < 2; ++q) {
-        const double* src = q ? d.rms_raw : d.back_raw;
-        double* dst = q ? d.rms : d.back;
+    const int hh = (F > 0) ? F / 2 : fsize / 2;
+    if constexpr (F > 0) {
+        double wb[F * F], wr[F * F];
         int n = 0;
-        for (int b = j - hh; b <= j + hh; ++b)
-            for (int c = i - hh; c <= i + hh; ++c)
-                if (b >= 0 && b < d.ny && c >= 0 && c < d.nx) wt[(n++) * kGridThreads] = src[b * d.nx + c];
-        dst[lm] = median_small(wt, n, kGridThreads);
+#pragma unroll
+        for (int e = 0; e < F * F; ++e) {
+            const int b = j - hh + e / F, c = i - hh + e % F;
+            const bool in = b >= 0 && b < d.ny && c >= 0 && c < d.nx;
+            wb[e] = in ? d.back_raw[b * d.nx + c] : INFINITY;
+            wr[e] = in ? d.rms_raw[b * d.nx + c] : INFINITY;
+            n += in ? 1 : 0;
+        }
+        d.back[lm] = median_regs(wb, n);
+        d.rms[lm] = median_regs(wr, n);
+    } else {
+        double* wt = w + threadIdx.x;
+        for (int q = 0; q < 2; ++q) {
+            const double* src = q ? d.rms_raw : d.back_raw;
+            double* dst = q ? d.rms : d.back;
+            int n = 0;
+            for (int b = j - hh; b <= j + hh; ++b)
+                for (int c = i - hh; c <= i + hh; ++c)
+                    if (b >= 0 && b < d.ny && c >= 0 && c < d.nx) wt[(n++) * kGridThreads] = src[b * d.nx + c];
+            dst[lm] = median_small(wt, n, kGridThreads);
+        }
     }
 }
 
@@ -1036,8 +1070,13 @@ void launch_mesh_stats(const FrameDesc* desc, int nframes, int total_meshes, int
 }
 
 void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, int fsize, hipStream_t s) {
-    k_grid_filter<<<(total_meshes + kGridThreads - 1) / kGridThreads, kGridThreads, 0, s>>>(desc, nframes,
-                                                                                         total_meshes, fsize);
+    const int blocks = (total_meshes + kGridThreads - 1) / kGridThreads;
+    switch (fsize) {
+        case 1: k_grid_filter<1><<<blocks, kGridThreads, 0, s>>>(desc, nframes, total_meshes, fsize); break;
+        case 3: k_grid_filter<3><<<blocks, kGridThreads, 0, s>>>(desc, nframes, total_meshes, fsize); break;
+        case 5: k_grid_filter<5><<<blocks, kGridThreads, 0, s>>>(desc, nframes, total_meshes, fsize); break;
+        default: k_grid_filter<0><<<blocks, kGridThreads, 0, s>>>(desc, nframes, total_meshes, fsize); break;
+    }
 }
 
 void launch_spline(const FrameDesc* desc, int nframes, int max_nx, int max_ny, hipStream_t s) {

@@ -138,6 +138,19 @@ def test_mesh_statistics_match_oracle(P, case):
     ph.close()
 
 
+@pytest.mark.parametrize("f", [1, 3, 5, 7])
+def test_grid_filter_every_size(P, f):
+    # sizes 1-5 keep the window in registers, 7 in LDS; ragged grid edges
+    fr = make_frame("c1", seed=5, W=700, H=430, dtype="f32")
+    p = _params("c1", mesh_w=32, mesh_h=32, mesh_filter=f)
+    ph = P.Photometry([_dev(fr.image)], p, p.kernel(), capacity=64)
+    ph.background()
+    g = ph.grids(0)
+    np.testing.assert_array_equal(g["back"], oracle.median_filter(g["back_raw"], f))
+    np.testing.assert_array_equal(g["rms"], oracle.median_filter(g["rms_raw"], f))
+    ph.close()
+
+
 # the spline kernels hold up to 100 knots per axis in LDS; longer axes take
 # the global-scratch path: 100 knots (LDS), 107 along x, 107 along y
 @pytest.mark.parametrize("shape", [(300, 200, 64, 64), (130, 77, 32, 16), (50, 20, 64, 64), (1000, 40, 128, 16),
