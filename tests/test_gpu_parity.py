@@ -54,6 +54,7 @@ MESH_CASES = [
     ("c2", 390, 270, "f32", 128, 128, 2),
     ("c1", 200, 150, "f32", 17, 23, 3),
     ("c1", 40, 30, "f32", 64, 64, 4),        # frame smaller than one mesh
+    ("c1", 300, 250, "u16", 96, 80, 5),      # 7680-pixel meshes: the 512 x 16 launch shape
 ]
 
 
