@@ -191,7 +191,7 @@ struct ApLayout {
 // runs.
 template <typename Real, int NC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 3 : 1))) void k_aperture(const FrameDesc* __restrict__ desc, ApArgs a, ApCat cat,
-                                                  int total_rows, int band, int nixmax) {
+                                                  int band, int nixmax) {
     extern __shared__ __align__(16) unsigned char ap_dyn[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const ApLayout<Real, NC> L(band, nixmax);
@@ -507,8 +507,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real
 }
 
 template <typename Real, int NC>
-static void launch_ap_nc(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int total_rows, int blocks,
-                         int band, int nixmax, hipStream_t s) {
+static void launch_ap_nc(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int blocks, int band,
+                         int nixmax, hipStream_t s) {
     const ApLayout<Real, NC> L(band, nixmax);
     // waves per workgroup: as many (up to kApWaves) as keep the workgroup's
     // LDS within 64 KB; the grid keeps the same number of wavefronts
@@ -517,21 +517,21 @@ static void launch_ap_nc(const FrameDesc* desc, const ApArgs& a, const ApCat& ca
     const size_t lds = (size_t)kApPrefixBytes + (size_t)L.bytes * nw;
     const int wg = blocks * (kApWaves / nw);
     const int g = kXcds * std::max(1, (wg + kXcds - 1) / kXcds);
-    k_aperture<Real, NC><<<g, 64 * nw, lds, s>>>(desc, a, cat, total_rows, band, nixmax);
+    k_aperture<Real, NC><<<g, 64 * nw, lds, s>>>(desc, a, cat, band, nixmax);
 }
 
 template <typename Real>
-static void launch_ap_t(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int total_rows, int blocks,
-                        int band, int nixmax, hipStream_t s) {
+static void launch_ap_t(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int blocks, int band,
+                        int nixmax, hipStream_t s) {
     switch (a.nr + 2) {
-        case 3: launch_ap_nc<Real, 3>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
-        case 4: launch_ap_nc<Real, 4>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
-        case 5: launch_ap_nc<Real, 5>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
-        case 6: launch_ap_nc<Real, 6>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
-        case 7: launch_ap_nc<Real, 7>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
-        case 8: launch_ap_nc<Real, 8>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
-        case 9: launch_ap_nc<Real, 9>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
-        default: launch_ap_nc<Real, 10>(desc, a, cat, total_rows, blocks, band, nixmax, s); break;
+        case 3: launch_ap_nc<Real, 3>(desc, a, cat, blocks, band, nixmax, s); break;
+        case 4: launch_ap_nc<Real, 4>(desc, a, cat, blocks, band, nixmax, s); break;
+        case 5: launch_ap_nc<Real, 5>(desc, a, cat, blocks, band, nixmax, s); break;
+        case 6: launch_ap_nc<Real, 6>(desc, a, cat, blocks, band, nixmax, s); break;
+        case 7: launch_ap_nc<Real, 7>(desc, a, cat, blocks, band, nixmax, s); break;
+        case 8: launch_ap_nc<Real, 8>(desc, a, cat, blocks, band, nixmax, s); break;
+        case 9: launch_ap_nc<Real, 9>(desc, a, cat, blocks, band, nixmax, s); break;
+        default: launch_ap_nc<Real, 10>(desc, a, cat, blocks, band, nixmax, s); break;
     }
 }
 
@@ -549,8 +549,8 @@ void launch_aperture(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, i
     const int side = 2 * R + 2;
     const int nixmax = ap_nixmax(side, mesh_w, max_nx);
     const int band = kApBand;
-    if (f64) launch_ap_t<double>(desc, a, cat, total_rows, blocks, band, nixmax, s);
-    else launch_ap_t<float>(desc, a, cat, total_rows, blocks, band, nixmax, s);
+    if (f64) launch_ap_t<double>(desc, a, cat, blocks, band, nixmax, s);
+    else launch_ap_t<float>(desc, a, cat, blocks, band, nixmax, s);
 }
 
 }  // namespace gpk

@@ -933,7 +933,7 @@ __global__ __launch_bounds__(kSplCols) void k_spline_y_small(const FrameDesc* __
     __shared__ double fl[kSplSmallN * kSplCols], ml[kSplSmallN * kSplCols];
     const FrameDesc& d = desc[blockIdx.y];
     const int ny = d.ny, nx = d.nx, lane = threadIdx.x;
-    if (blockIdx.x * kSplCols >= 2 * nx) return;
+    if ((int)blockIdx.x * kSplCols >= 2 * nx) return;
     const int g = blockIdx.x * kSplCols + lane;
     const bool on = g < 2 * nx;
     const int q = on ? g / nx : 0, i = on ? g - q * nx : 0;
@@ -964,7 +964,7 @@ __global__ __launch_bounds__(kSplCols) void k_spline_x_small(const FrameDesc* __
     const FrameDesc& d = desc[blockIdx.y];
     const int nx = d.nx, ny = d.ny, lane = threadIdx.x;
     const int G = 8 * (ny + 1);
-    if (blockIdx.x * kSplCols >= G) return;
+    if ((int)blockIdx.x * kSplCols >= G) return;
     const int g = blockIdx.x * kSplCols + lane;
     const bool on = g < G;
     const int r = g & 3;
@@ -992,7 +992,7 @@ __global__ __launch_bounds__(kSplThreads) void k_spline_y(const FrameDesc* __res
     __shared__ double tk[kSplineMaxKnots], cf[kSplineMaxKnots], dn[kSplineMaxKnots];
     const FrameDesc& d = desc[blockIdx.y];
     const int ny = d.ny, nx = d.nx;
-    if (blockIdx.x * kSplThreads >= 2 * nx) return;
+    if ((int)blockIdx.x * kSplThreads >= 2 * nx) return;
     for (int k = threadIdx.x; k < ny; k += kSplThreads) tk[k] = knot_at(k, d.H, d.mh);
     __syncthreads();
     if (threadIdx.x == 0) spline_factor(ny, tk, cf, dn);
@@ -1028,7 +1028,7 @@ __global__ __launch_bounds__(kSplThreads) void k_spline_x(const FrameDesc* __res
     const FrameDesc& d = desc[blockIdx.y];
     const int nx = d.nx, ny = d.ny;
     const int G = 8 * (ny + 1);
-    if (blockIdx.x * kSplThreads >= G) return;
+    if ((int)blockIdx.x * kSplThreads >= G) return;
     for (int k = threadIdx.x; k < nx; k += kSplThreads) tk[k] = knot_at(k, d.W, d.mw);
     __syncthreads();
     if (threadIdx.x == 0) spline_factor(nx, tk, cf, dn);
