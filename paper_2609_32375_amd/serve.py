@@ -6,8 +6,10 @@ slot is free and their HBM footprint fits the budget, launches every request
 admitted at one poll as one batch (one gp_background / gp_detect /
 gp_aperture sequence over all of them) on the next stream of a small pool, and
 keeps going: batches from consecutive polls run concurrently on the device
-while earlier ones finish.  A finished batch releases its slots and footprint
-and hands each request its catalogue and photometry.
+while earlier ones finish.  A finished batch's results are downloaded by a
+worker thread, so admission never waits on a copy; once they are on the host
+the batch releases its slots and footprint and hands each request its
+catalogue and photometry.
 
 Everything per pixel runs in the HIP library; this module schedules.
 """
@@ -16,6 +18,7 @@ from __future__ import annotations
 import math
 import time
 from collections import deque
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import Any, List, Optional
 
@@ -81,6 +84,8 @@ class Server:
         self._next_stream = 0
         self.waiting: deque = deque()
         self.inflight: List[_Epoch] = []
+        self.downloading: list = []          # (epoch, future of its results)
+        self._pool = ThreadPoolExecutor(max_workers=1)
         self.resident = 0
         self.t0 = time.perf_counter()
         self.finished: List[Request] = []
@@ -119,20 +124,31 @@ class Server:
         self.waiting.append(req)
 
     # ------------------------------------------------------------------
+    def _download(self, ep):
+        res = [ep.ph.results(i, sync=False) for i in range(len(ep.reqs))]
+        return res, self.now()
+
     def _retire(self):
         keep = []
         for ep in self.inflight:
             if ep.done.query():
-                t = self.now()
-                for i, r in enumerate(ep.reqs):
-                    r.result = ep.ph.results(i, sync=False)
+                self.downloading.append((ep, self._pool.submit(self._download, ep)))
+            else:
+                keep.append(ep)
+        self.inflight = keep
+        still = []
+        for ep, fut in self.downloading:
+            if fut.done():
+                res, t = fut.result()
+                for r, out in zip(ep.reqs, res):
+                    r.result = out
                     r.t_done = t
                     self.resident -= r.footprint
                     self.finished.append(r)
                 self._idle.setdefault(ep.key, []).append(ep.ph)
             else:
-                keep.append(ep)
-        self.inflight = keep
+                still.append((ep, fut))
+        self.downloading = still
 
     def _key(self, r):
         return (id(r.params) if r.params is not None else None, id(r.kernel) if r.kernel is not None else None)
@@ -141,7 +157,7 @@ class Server:
         """Start one batch: the oldest arrived request plus every other arrived
         request with the same parameters, while slots and footprint allow."""
         batch = []
-        n_inflight = sum(len(e.reqs) for e in self.inflight)
+        n_inflight = sum(len(e.reqs) for e in self.inflight) + sum(len(e.reqs) for e, _ in self.downloading)
         now = self.now()
         key = None
         keep = deque()
@@ -194,9 +210,9 @@ class Server:
             pass
 
     def drain(self, poll_sleep: float = 2e-4):
-        while self.waiting or self.inflight:
+        while self.waiting or self.inflight or self.downloading:
             self.poll()
-            if self.inflight or self.waiting:
+            if self.inflight or self.waiting or self.downloading:
                 time.sleep(poll_sleep)
 
     def run(self, requests: List[Request], poll_sleep: float = 2e-4):
@@ -213,6 +229,11 @@ class Server:
             ep.done.synchronize()
             ep.ph.close()
         self.inflight = []
+        for ep, fut in self.downloading:
+            fut.result()
+            ep.ph.close()
+        self.downloading = []
+        self._pool.shutdown(wait=True)
         for lst in self._idle.values():
             for ph in lst:
                 ph.close()
