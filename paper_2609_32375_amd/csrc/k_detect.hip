@@ -630,7 +630,7 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
             rpk = -INFINITY;
             rfl = 0u;
         };
-#pragma unroll 1
+#pragma unroll
         for (int k = 0; k < 16; ++k) {
             const bool m = (mbits >> k) & 1u;
             const int c = co[k];
