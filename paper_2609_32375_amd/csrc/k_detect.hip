@@ -399,32 +399,37 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     constexpr int PCAP = (int)(sizeof(typename DetShared<Real, REG>::U2) / sizeof(uint32_t)) / 4;
     uint32_t* plist = reinterpret_cast<uint32_t*>(&sh.u2) + wv * PCAP;
     int npair = 0;
-    const uint64_t mtop = (wv > 0) ? sh.rowmask[16 * wv - 1] : 0ull;
+    uint64_t mtop = 0ull;
+    if (wv > 0) {
+        const uint64_t t = sh.rowmask[16 * wv - 1];
+        // (readfirstlane returns int: widen through uint32_t, not by sign)
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(t >> 32));
+        mtop = (uint64_t)lo | ((uint64_t)hi << 32);
+    }
+    // The pairs of a row are bit masks over its columns, computed on the
+    // scalar unit from the row's mask m and the mask above mu (runs start
+    // where m rises, end where it falls):
+    //   vertical link at the first column of each overlap: m & mu & (start | ~(mu << 1))
+    //   8-connectivity, up-left of a run start:           start & (mu << 1)
+    //   8-connectivity, up-right of a run end, none above: end & (mu >> 1) & ~mu
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int ly = 16 * wv + k;
         const uint64_t m = rm[k], mu = (k > 0) ? rm[k - 1] : mtop;
-        if (conn8 ? (m & (mu | (mu << 1) | (mu >> 1))) == 0ull : (m & mu) == 0ull) continue;
-        const bool on = (m >> lane) & 1ull;
+        const uint64_t start = m & ~(m << 1), end = m & ~(m >> 1);
+        const uint64_t cm[3] = {m & mu & (start | ~(mu << 1)), conn8 ? (start & (mu << 1)) : 0ull,
+                                conn8 ? (end & (mu >> 1) & ~mu) : 0ull};
+        if ((cm[0] | cm[1] | cm[2]) == 0ull) continue;
         const int p = ly * kTile + lane;
-        const uint64_t zb = ~m & below;
-        const int a0 = zb ? 64 - __clzll(zb) : 0;                     // run start
-        const uint64_t za = (lane == 63) ? 0ull : (~m & ((~0ull) << (lane + 1)));
-        const int a1 = za ? __ffsll((long long)za) - 2 : 63;            // run end
-        const bool up = (mu >> lane) & 1ull;
-        const bool upl = lane > 0 && ((mu >> (lane - 1)) & 1ull);
-        const bool upr = lane < 63 && ((mu >> (lane + 1)) & 1ull);
-        const bool c0 = on && up && (lane == a0 || !upl);
-        const bool c1 = on && conn8 && lane == a0 && upl;
-        const bool c2 = on && conn8 && lane == a1 && upr && !up;
         const int qq[3] = {p - kTile, p - kTile - 1, p - kTile + 1};
-        const bool cc[3] = {c0, c1, c2};
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
-            const uint64_t bm = __ballot(cc[t]);
+            const uint64_t bm = cm[t];
             if (bm == 0ull) continue;
-            const int pos = npair + __popcll(bm & below);
-            if (cc[t]) {
+            const int pos = npair + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+            if ((bm >> lane) & 1ull) {
                 if (pos < PCAP) plist[pos] = ((uint32_t)p << 12) | (uint32_t)qq[t];
                 else lds_union(lab, p, qq[t]);
             }
