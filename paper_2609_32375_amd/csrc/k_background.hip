@@ -924,6 +924,19 @@ __device__ __forceinline__ void piece_poly_inv(int n, const double* t, const dou
     out[3] = (mj1 - mj) * ih[j] * kSixth;
 }
 
+// column of n values (stride s) into the LDS column `lane` of fl, 16 loads in
+// flight at a time (indices clamped to the column, so the loads need no branch)
+__device__ __forceinline__ void load_column(double* fl, int lane, const double* v, int s, int n) {
+    for (int k0 = 0; k0 < n; k0 += 16) {
+        double x[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) x[j] = v[(size_t)min(k0 + j, n - 1) * s];
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (k0 + j < n) fl[(k0 + j) * kSplCols + lane] = x[j];
+    }
+}
+
 // Small grids (at most kSplSmallN knots on the solved axis): a wavefront takes
 // 64 columns; their values are loaded into LDS at once (all loads in flight),
 // solved and cut into pieces there, and only the pieces go to global memory.
@@ -938,7 +951,7 @@ __global__ __launch_bounds__(kSplCols) void k_spline_y_small(const FrameDesc* __
     const bool on = g < 2 * nx;
     const int q = on ? g / nx : 0, i = on ? g - q * nx : 0;
     const double* col = (q ? d.rms : d.back) + i;
-    for (int k = 0; k < ny; ++k) fl[k * kSplCols + lane] = on ? col[(size_t)k * nx] : 0.0;
+    load_column(fl, lane, col, nx, ny);
     for (int k = lane; k < ny; k += kSplCols) tk[k] = knot_at(k, d.H, d.mh);
     __syncthreads();
     for (int k = lane; k + 1 < ny; k += kSplCols) ih[k] = 1.0 / (tk[k + 1] - tk[k]);
@@ -946,6 +959,7 @@ __global__ __launch_bounds__(kSplCols) void k_spline_y_small(const FrameDesc* __
     __syncthreads();
     if (!on) return;
     spline_solve_inv(ny, tk, cf, idn, ih, fl + lane, kSplCols, ml + lane, kSplCols);
+#pragma unroll 4
     for (int jy = 0; jy <= ny; ++jy) {
         double c[4];
         piece_poly_inv(ny, tk, ih, fl + lane, kSplCols, ml + lane, kSplCols, jy, c);
@@ -971,7 +985,7 @@ __global__ __launch_bounds__(kSplCols) void k_spline_x_small(const FrameDesc* __
     const int jy = on ? (g >> 2) % (ny + 1) : 0;
     const int q = on ? (g >> 2) / (ny + 1) : 0;
     const double* vals = d.ycoef + (((size_t)q * (ny + 1) + jy) * nx) * 4 + r;  // stride 4
-    for (int k = 0; k < nx; ++k) fl[k * kSplCols + lane] = on ? vals[(size_t)k * 4] : 0.0;
+    load_column(fl, lane, vals, 4, nx);
     for (int k = lane; k < nx; k += kSplCols) tk[k] = knot_at(k, d.W, d.mw);
     __syncthreads();
     for (int k = lane; k + 1 < nx; k += kSplCols) ih[k] = 1.0 / (tk[k + 1] - tk[k]);
@@ -979,6 +993,7 @@ __global__ __launch_bounds__(kSplCols) void k_spline_x_small(const FrameDesc* __
     __syncthreads();
     if (!on) return;
     spline_solve_inv(nx, tk, cf, idn, ih, fl + lane, kSplCols, ml + lane, kSplCols);
+#pragma unroll 4
     for (int ix = 0; ix <= nx; ++ix) {
         double c[4];
         piece_poly_inv(nx, tk, ih, fl + lane, kSplCols, ml + lane, kSplCols, ix, c);
