@@ -238,7 +238,9 @@ gp_status gp_background(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
  * pointers, each NULL or a device int32 [height][width] map (row pitch =
  * width) that receives per pixel the label (>= 1), -1 for pixels above
  * threshold in a dropped component, 0 below threshold.  comp_status (device int32[2], may be
- * NULL) receives {GP_OK or GP_ERR_WORKSPACE, pieces needed}. */
+ * NULL) receives {GP_OK or GP_ERR_WORKSPACE, pieces needed}.  A batch holds at
+ * most 2^31 pixels, each frame counted as ceil(width * height / 1024) * 1024
+ * (more: GP_ERR_UNSUPPORTED). */
 gp_status gp_detect(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
                     const gp_bkg_params* bp, const void* bkg, const gp_det_params* dp,
                     gp_catalog* cat, int32_t* const* seg, int32_t* comp_status, void* ws,

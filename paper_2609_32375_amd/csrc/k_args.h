@@ -69,7 +69,6 @@ void launch_mesh_stats(const FrameDesc* desc, int nframes, int total_meshes, int
                        hipStream_t s);
 void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, int fsize, hipStream_t s);
 void launch_spline(const FrameDesc* desc, int nframes, int max_nx, int max_ny, hipStream_t s);
-void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, int rad, hipStream_t s);
 void launch_merge(const DetWork& wk, int conn, int minarea, int persist_blocks, hipStream_t s);
 void launch_catalog(const DetWork& wk, const CatOut& cat, int minarea, int persist_blocks, int32_t* comp_status,
@@ -79,6 +78,7 @@ void launch_aperture(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, i
                      int mesh_w, int max_nx, bool f64, hipStream_t s);
 void launch_bkg_map(const FrameDesc& d, double* bmap, double* rmap, bool f64, hipStream_t s);
 void launch_write_desc(const DescChunk& c, FrameDesc* table, hipStream_t s);
-void launch_write_detargs(const DetArgsIn& in, DetArgs* out, hipStream_t s);
+void launch_det_setup(const DescChunk& c, FrameDesc* table, const DetArgsIn& in, DetArgs* out, uint32_t* counters,
+                      uint32_t* bitmap, size_t nwords, hipStream_t s);
 
 }  // namespace gpk

@@ -19,6 +19,9 @@ constexpr int kRegion = kTile + 2 * kMaxR;  // 78: tile plus filter halo
 constexpr int kLocalRecs = 160;    // components per tile accumulated in LDS
 constexpr int kMaxRadii = 8;
 constexpr int kDescChunk = 8;      // descriptors written per init launch
+constexpr int kNumCounters = 64;   // detection counters (zeroed per call)
+constexpr int kScanChunk = 512;    // rank bitmap: 1024-bit blocks per scan workgroup
+constexpr int kMaxScanChunks = 4096;   // scan workgroups of one batch (2^31 pixels)
 
 enum : int { kDtypeU16 = 1, kDtypeF32 = 2 };
 enum : uint32_t { kFlagSat = 1u, kFlagEdge = 2u, kFlagNonpos = 4u, kFlagTrunc = 8u };

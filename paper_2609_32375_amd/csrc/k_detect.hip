@@ -15,9 +15,10 @@
 //  k_merge_records adds every non-root piece into its root record.
 //  k_mark_kept     sets the first-pixel bit of every component with
 //                  npix >= minarea in a per-frame bitmap.
-//  k_scan_*        prefix sums of the bitmap's popcounts -> label = rank of
+//  k_popc_scan     prefix sums of the bitmap's popcounts -> label = rank of
 //                  the first pixel in raster order.
-//  k_write_catalog moment normalisation (FP64) and catalogue rows.
+//  k_write_catalog moment normalisation (FP64), catalogue rows and the
+//                  per-frame object counts and status.
 //  k_seg_finalize  optional per-pixel label map.
 //
 // The paper's detection is a matched filter normalised by the noise map with a
@@ -791,81 +792,123 @@ __global__ __launch_bounds__(256) void k_mark_kept(DetWork wk, int minarea) {
     }
 }
 
-// popcount of each 1024-bit block
-__global__ __launch_bounds__(256) void k_block_popc(const uint32_t* __restrict__ bm, uint32_t* cnt, int nblocks) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nblocks) return;
-    const uint4* p = (const uint4*)(bm + (size_t)b * 32);
-    uint32_t c = 0;
+// Ranks of the bitmap's bits.  k_popc_scan: each workgroup takes kScanChunk
+// consecutive 1024-bit blocks, counts their bits and writes the exclusive
+// prefix of the counts within the chunk to blockcnt; the chunk's total goes to
+// chunksum.  The exclusive prefix of the chunk totals (formed by every
+// catalogue workgroup in LDS, chunk_prefix) then gives the prefix of block b
+// as blockcnt[b] + prefix[b / kScanChunk] (block_prefix).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        uint4 q = p[i];
-        c += __popc(q.x) + __popc(q.y) + __popc(q.z) + __popc(q.w);
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
     }
-    cnt[b] = c;
+    return x;
 }
 
-// exclusive scan in chunks of 2048 (8 per thread) with chunk totals
-__global__ __launch_bounds__(256) void k_scan_chunks(uint32_t* a, uint32_t* chunksum, int n) {
+// exclusive prefix of x over the workgroup's 256 threads; *total = the sum
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* ws, uint32_t* total) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint32_t incl = wave_incl_scan(x, lane);
+    __syncthreads();   // ws may still be read by a previous call
+    if (lane == 63) ws[wv] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int i = 0; i < wv; ++i) off += ws[i];
+    *total = ws[0] + ws[1] + ws[2] + ws[3];
+    return off + incl - x;
+}
+
+__global__ __launch_bounds__(256) void k_popc_scan(const uint32_t* __restrict__ bm, uint32_t* blockcnt,
+                                                   uint32_t* chunksum, int nb) {
+    static_assert(kScanChunk == 512, "four wavefronts of 16 x 64 lanes x 8 words per block");
+    __shared__ uint32_t cnt[kScanChunk];
     __shared__ uint32_t ws[4];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int base = blockIdx.x * 2048 + tid * 8;
-    uint32_t v[8], t = 0;
-    for (int i = 0; i < 8; ++i) {
-        v[i] = (base + i < n) ? a[base + i] : 0u;
-        t += v[i];
+    // bit counts of the chunk's blocks: a wavefront reads 1 KB (eight blocks of
+    // eight 16-byte words) per load, all 16 loads in flight; eight lanes
+    // reduce each block
+    {
+        const uint4* src = (const uint4*)bm + (size_t)blockIdx.x * kScanChunk * 8;
+        const int nvec = min(kScanChunk, nb - (int)blockIdx.x * kScanChunk) * 8;
+        uint4 q[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = wv * 1024 + i * 64 + lane;
+            q[i] = (e < nvec) ? src[e] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            uint32_t c = __popc(q[i].x) + __popc(q[i].y) + __popc(q[i].z) + __popc(q[i].w);
+            c += __shfl_xor(c, 1);
+            c += __shfl_xor(c, 2);
+            c += __shfl_xor(c, 4);
+            if ((lane & 7) == 0) cnt[(wv * 1024 + i * 64 + lane) >> 3] = c;
+        }
     }
-    uint32_t incl = t;
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
-    }
-    if (lane == 63) ws[wv] = incl;
     __syncthreads();
-    uint32_t off = 0;
-    for (int i = 0; i < wv; ++i) off += ws[i];
-    uint32_t run = off + incl - t;
-    for (int i = 0; i < 8; ++i) {
-        if (base + i < n) a[base + i] = run;
-        run += v[i];
-    }
-    if (tid == 255) chunksum[blockIdx.x] = off + incl;
+    const int b0 = blockIdx.x * kScanChunk + 2 * tid;
+    const uint32_t v0 = (b0 < nb) ? cnt[2 * tid] : 0u, v1 = (b0 + 1 < nb) ? cnt[2 * tid + 1] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(v0 + v1, ws, &tot);
+    if (b0 < nb) blockcnt[b0] = ex;
+    if (b0 + 1 < nb) blockcnt[b0 + 1] = ex + v0;
+    if (tid == 0) chunksum[blockIdx.x] = tot;
 }
 
-// exclusive scan of the chunk totals (one workgroup, up to 1024 * 8 chunks);
-// writes the grand total to a[n]
-__global__ __launch_bounds__(1024) void k_scan_tops(uint32_t* chunksum, int nchunks, uint32_t* a, int n) {
-    __shared__ uint32_t ws[16];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int base = tid * 8;
-    uint32_t v[8], t = 0;
-    for (int i = 0; i < 8; ++i) {
-        v[i] = (base + i < nchunks) ? chunksum[base + i] : 0u;
-        t += v[i];
+// Every catalogue workgroup scans the chunk totals into LDS itself: a batch
+// holds at most kMaxScanChunks chunks (2^31 pixels, checked by the caller).
+struct ChunkPrefix {
+    const uint32_t* p;   // exclusive prefix of the chunk totals, [nchunks] = total
+};
+
+__device__ ChunkPrefix chunk_prefix(const DetWork& wk, uint32_t* lds, uint32_t* ws) {
+    static_assert(kMaxScanChunks == 256 * 16, "16 chunk totals per thread");
+    const int nchunks = (wk.total_blocks + kScanChunk - 1) / kScanChunk;
+    const int tid = threadIdx.x, c0 = tid * 16;
+    uint32_t cv[16], ct = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        cv[i] = (c0 + i < nchunks) ? wk.chunksum[c0 + i] : 0u;
+        ct += cv[i];
     }
-    uint32_t incl = t;
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
+    uint32_t tot;
+    uint32_t run = block_excl_scan(ct, ws, &tot);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (c0 + i < nchunks) lds[c0 + i] = run;
+        run += cv[i];
     }
-    if (lane == 63) ws[wv] = incl;
+    if (tid == 0) lds[nchunks] = tot;
     __syncthreads();
-    uint32_t off = 0;
-    for (int i = 0; i < wv; ++i) off += ws[i];
-    uint32_t run = off + incl - t;
-    for (int i = 0; i < 8; ++i) {
-        if (base + i < nchunks) chunksum[base + i] = run;
-        run += v[i];
+    return ChunkPrefix{lds};
+}
+
+// number of kept components whose first pixel lies in blocks [0, b)
+__device__ __forceinline__ uint32_t block_prefix(const DetWork& wk, const ChunkPrefix& cp, int b) {
+    if (b >= wk.total_blocks) return cp.p[(wk.total_blocks + kScanChunk - 1) / kScanChunk];
+    return wk.blockcnt[b] + cp.p[b / kScanChunk];
+}
+
+__global__ __launch_bounds__(256) void k_write_catalog(DetWork wk, CatOut cat, int minarea, int32_t* comp_status) {
+    __shared__ uint32_t ctop[kMaxScanChunks + 1];
+    __shared__ uint32_t ws[4];
+    const ChunkPrefix cp = chunk_prefix(wk, ctop, ws);
+    // per-frame object counts and status (workgroup 0)
+    if (blockIdx.x == 0) {
+        for (int f = threadIdx.x; f < wk.nframes; f += blockDim.x) {
+            const FrameDesc& d = wk.desc[f];
+            const int n =
+                (int)(block_prefix(wk, cp, d.bm_block_base + d.nblocks) - block_prefix(wk, cp, d.bm_block_base));
+            cat.n_obj[f] = n;
+            cat.status[f] = (wk.counters[1] != 0u) ? 3 : ((n > cat.capacity) ? 4 : 0);
+        }
+        if (threadIdx.x == 0 && comp_status) {
+            comp_status[0] = (wk.counters[1] != 0u) ? 3 : 0;
+            comp_status[1] = (int32_t)wk.counters[0];
+        }
     }
-    if (tid == 1023) a[n] = off + incl;
-}
-
-__global__ __launch_bounds__(256) void k_scan_add(uint32_t* a, const uint32_t* chunksum, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] += chunksum[i / 2048];
-}
-
-__global__ __launch_bounds__(256) void k_write_catalog(DetWork wk, CatOut cat, int minarea) {
     if (wk.counters[1] != 0u) return;
     const int total = min((int)wk.counters[0], wk.rec_cap);
     for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
@@ -878,11 +921,22 @@ __global__ __launch_bounds__(256) void k_write_catalog(DetWork wk, CatOut cat, i
         const FrameDesc& d = wk.desc[R.frame];
         const uint32_t pm = R.pmin;
         const int blk = (int)(pm >> 10);
-        const uint32_t* bw = d.bitmap + (size_t)blk * 32;
-        uint32_t rank = wk.blockcnt[d.bm_block_base + blk] - wk.blockcnt[d.bm_block_base];
+        // bits before pm in its 1024-bit block: the block's eight 16-byte
+        // words are loaded at once and masked
+        const uint4* bw = (const uint4*)(d.bitmap + (size_t)blk * 32);
+        uint32_t rank = block_prefix(wk, cp, d.bm_block_base + blk) - block_prefix(wk, cp, d.bm_block_base);
         const int wi = (int)((pm >> 5) & 31u);
-        for (int i = 0; i < wi; ++i) rank += __popc(bw[i]);
-        rank += __popc(bw[wi] & ((1u << (pm & 31u)) - 1u));
+        const uint32_t part = (1u << (pm & 31u)) - 1u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint4 q = bw[k];
+            const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = 4 * k + j;
+                rank += __popc(i < wi ? w4[j] : (i == wi ? (w4[j] & part) : 0u));
+            }
+        }
         wk.label[id] = (int)rank + 1;
         if ((int)rank >= cat.capacity) continue;
         const size_t row = (size_t)d.cat_base + rank;
@@ -907,20 +961,6 @@ __global__ __launch_bounds__(256) void k_write_catalog(DetWork wk, CatOut cat, i
         if (nonpos) fl |= kFlagNonpos;
         if (R.xmin == 0 || R.ymin == 0 || R.xmax == d.W - 1 || R.ymax == d.H - 1) fl |= kFlagEdge;
         cat.flags[row] = fl;
-    }
-}
-
-__global__ void k_frame_status(DetWork wk, CatOut cat, int32_t* comp_status) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < wk.nframes) {
-        const FrameDesc& d = wk.desc[f];
-        const int n = (int)(wk.blockcnt[d.bm_block_base + d.nblocks] - wk.blockcnt[d.bm_block_base]);
-        cat.n_obj[f] = n;
-        cat.status[f] = (wk.counters[1] != 0u) ? 3 : ((n > cat.capacity) ? 4 : 0);
-    }
-    if (f == 0 && comp_status) {
-        comp_status[0] = (wk.counters[1] != 0u) ? 3 : 0;
-        comp_status[1] = (int32_t)wk.counters[0];
     }
 }
 
@@ -949,19 +989,8 @@ __global__ __launch_bounds__(256) void k_seg_finalize(DetWork wk, int f) {
     }
 }
 
-__global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-
 // ---------------------------------------------------------------------------
 // launchers
-void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
-    if (n == 0) return;
-    int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
-    k_fill_u32<<<blocks, 256, 0, s>>>(p, n, v);
-}
-
 template <typename Real>
 static void launch_detect_t(const DetWork& wk, const DetArgs* args, int rad, hipStream_t s) {
     // 8 * ceil(tiles / 8) workgroups: a contiguous band of tiles per XCD
@@ -990,17 +1019,13 @@ void launch_merge(const DetWork& wk, int conn, int minarea, int persist_blocks, 
     k_merge_records<<<persist_blocks, 256, 0, s>>>(wk);
     k_mark_kept<<<persist_blocks, 256, 0, s>>>(wk, minarea);
     const int nb = wk.total_blocks;
-    k_block_popc<<<(nb + 255) / 256, 256, 0, s>>>(wk.bitmap, wk.blockcnt, nb);
-    const int nchunks = (nb + 2047) / 2048;
-    k_scan_chunks<<<nchunks, 256, 0, s>>>(wk.blockcnt, wk.chunksum, nb);
-    k_scan_tops<<<1, 1024, 0, s>>>(wk.chunksum, nchunks, wk.blockcnt, nb);
-    k_scan_add<<<(nb + 255) / 256, 256, 0, s>>>(wk.blockcnt, wk.chunksum, nb);
+    const int nchunks = (nb + kScanChunk - 1) / kScanChunk;
+    k_popc_scan<<<nchunks, 256, 0, s>>>(wk.bitmap, wk.blockcnt, wk.chunksum, nb);
 }
 
 void launch_catalog(const DetWork& wk, const CatOut& cat, int minarea, int persist_blocks,
                     int32_t* comp_status, hipStream_t s) {
-    k_write_catalog<<<persist_blocks, 256, 0, s>>>(wk, cat, minarea);
-    k_frame_status<<<(wk.nframes + 63) / 64, 64, 0, s>>>(wk, cat, comp_status);
+    k_write_catalog<<<persist_blocks, 256, 0, s>>>(wk, cat, minarea, comp_status);
 }
 
 void launch_seg(const DetWork& wk, int f, int64_t npx, hipStream_t s) {
@@ -1014,9 +1039,18 @@ __global__ void k_write_desc(DescChunk c, FrameDesc* table) {
     if (i < c.count) table[c.first + i] = c.d[i];
 }
 
-// the dense kernel is normalised here (sum in FP64, fixed order)
-__global__ void k_write_detargs(DetArgsIn in, DetArgs* out) {
+// Per-call set-up of the detection, one launch: workgroup 0 writes the last
+// descriptors, the filter arguments (the dense kernel normalised with an FP64
+// sum in a fixed order) and zeroes the counters; every workgroup zeroes its
+// share of the rank bitmap (nvec 16-byte words).
+__global__ __launch_bounds__(256) void k_det_setup(DescChunk c, FrameDesc* table, DetArgsIn in, DetArgs* out,
+                                                   uint32_t* counters, uint4* bitmap, size_t nvec) {
     const int t = threadIdx.x;
+    for (size_t i = (size_t)blockIdx.x * 256 + t; i < nvec; i += (size_t)gridDim.x * 256)
+        bitmap[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (blockIdx.x != 0) return;
+    if (t < c.count) table[c.first + t] = c.d[t];
+    if (t < kNumCounters) counters[t] = 0u;
     if (t == 0) {
         out->kw = in.kw;
         out->kh = in.kh;
@@ -1032,7 +1066,7 @@ __global__ void k_write_detargs(DetArgsIn in, DetArgs* out) {
     const int n = in.kw * in.kh;
     for (int i = 0; i < n; ++i) sum += (double)in.kraw[i];
     const double norm = (sum != 0.0) ? sum : 1.0;
-    for (int i = t; i < kMaxK * kMaxK; i += blockDim.x) {
+    for (int i = t; i < kMaxK * kMaxK; i += 256) {
         const double v = (i < n) ? (double)in.kraw[i] / norm : 0.0;
         out->kdd[i] = v;
         out->kd[i] = (float)v;
@@ -1049,8 +1083,11 @@ void launch_write_desc(const DescChunk& c, FrameDesc* table, hipStream_t s) {
     k_write_desc<<<1, 64, 0, s>>>(c, table);
 }
 
-void launch_write_detargs(const DetArgsIn& in, DetArgs* out, hipStream_t s) {
-    k_write_detargs<<<1, 256, 0, s>>>(in, out);
+void launch_det_setup(const DescChunk& c, FrameDesc* table, const DetArgsIn& in, DetArgs* out, uint32_t* counters,
+                      uint32_t* bitmap, size_t nwords, hipStream_t s) {
+    const size_t nvec = nwords / 4;   // whole 1024-bit blocks: a multiple of 4 words
+    const int blocks = (int)std::max<size_t>(1, std::min<size_t>((nvec + 255) / 256, 1024));
+    k_det_setup<<<blocks, 256, 0, s>>>(c, table, in, out, counters, (uint4*)bitmap, nvec);
 }
 
 }  // namespace gpk

@@ -250,12 +250,12 @@ void plan_fixed(int32_t nframes, Plan& P) {
     };
     P.o_desc = sec(sizeof(FrameDesc) * nframes);
     P.o_detargs = sec(sizeof(DetArgs));
-    P.o_counters = sec(64 * sizeof(uint32_t));
+    P.o_counters = sec(kNumCounters * sizeof(uint32_t));
     P.o_tiles = sec(sizeof(TileInfo) * P.total_tiles);
     P.o_edges = sec(sizeof(int16_t) * 4 * kTile * P.total_tiles);
     P.o_bitmap = sec(128 * (size_t)P.total_blocks);
     P.o_blockcnt = sec(sizeof(uint32_t) * (P.total_blocks + 1));
-    P.o_chunks = sec(sizeof(uint32_t) * (ceil_div(P.total_blocks, 2048) + 1));
+    P.o_chunks = sec(sizeof(uint32_t) * (ceil_div(P.total_blocks, kScanChunk) + 1));
     P.o_spline = o;
     for (int f = 0; f < nframes; ++f) {
         FramePlan& F = P.fr[f];
@@ -291,8 +291,11 @@ int64_t cap_for(const Plan& P, size_t ws_bytes) {
     return lo;
 }
 
+// descriptors -> workspace table, kDescChunk per launch; with `tail` the last
+// chunk is returned instead, for the caller's own set-up launch
 gp_status upload_desc(const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp, const Plan& P,
-                      const void* bkg, void* ws, int32_t cat_capacity, int32_t* const* seg, hipStream_t s) {
+                      const void* bkg, void* ws, int32_t cat_capacity, int32_t* const* seg, hipStream_t s,
+                      DescChunk* tail = nullptr) {
     char* W = (char*)ws;
     char* B = (char*)bkg;
     FrameDesc* table = (FrameDesc*)(W + P.o_desc);
@@ -334,7 +337,9 @@ gp_status upload_desc(const gp_frame* frames, int32_t nframes, const gp_bkg_para
         blk_base += F.nblocks;
         if (ch.count == 0) ch.first = f;
         ch.d[ch.count++] = d;
-        if (ch.count == kDescChunk || f == nframes - 1) {
+        if (tail && f == nframes - 1) {
+            *tail = ch;
+        } else if (ch.count == kDescChunk || f == nframes - 1) {
             launch_write_desc(ch, table, s);
             HIP_TRY(hipGetLastError());
             ch = DescChunk{};
@@ -652,10 +657,12 @@ extern "C" gp_status gp_detect(gp_ctx* ctx, const gp_frame* frames, int32_t nfra
     if ((st = check_ws(P, ws, ws_bytes)) != GP_OK) return st;
     plan_recs(cap_for(P, ws_bytes), P);
     if (P.total_tiles >= ((int64_t)1 << 31)) return fail(GP_ERR_UNSUPPORTED, "too many tiles in one batch");
-    if (ceil_div(P.total_blocks, 2048) > 8192) return fail(GP_ERR_UNSUPPORTED, "batch too large for one call");
+    if (ceil_div(P.total_blocks, kScanChunk) > kMaxScanChunks)
+        return fail(GP_ERR_UNSUPPORTED, "a detection batch holds at most 2^31 pixels (1024-pixel blocks per frame)");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(ctx->device));
-    if ((st = upload_desc(frames, nframes, bp, P, bkg, ws, cat->capacity, seg, s)) != GP_OK) return st;
+    DescChunk tail{};
+    if ((st = upload_desc(frames, nframes, bp, P, bkg, ws, cat->capacity, seg, s, &tail)) != GP_OK) return st;
     char* W = (char*)ws;
     // filter arguments
     DetArgsIn in{};
@@ -676,8 +683,6 @@ extern "C" gp_status gp_detect(gp_ctx* ctx, const gp_frame* frames, int32_t nfra
         in.kyd[i] = ky[i];
     }
     DetArgs* dargs = (DetArgs*)(W + P.o_detargs);
-    launch_write_detargs(in, dargs, s);
-    HIP_TRY(hipGetLastError());
     DetWork wk{};
     wk.desc = (FrameDesc*)(W + P.o_desc);
     wk.nframes = nframes;
@@ -695,10 +700,11 @@ extern "C" gp_status gp_detect(gp_ctx* ctx, const gp_frame* frames, int32_t nfra
     wk.rec_cap = (int32_t)P.rec_cap;
     wk.total_blocks = (int32_t)P.total_blocks;
     {
-        ProfScope ps(ctx, s, "clear");
-        launch_fill_u32(wk.counters, 64, 0u, s);
-        launch_fill_u32(wk.bitmap, (size_t)P.total_blocks * 32, 0u, s);
+        ProfScope ps(ctx, s, "setup");
+        launch_det_setup(tail, (FrameDesc*)(W + P.o_desc), in, dargs, wk.counters, wk.bitmap,
+                         (size_t)P.total_blocks * 32, s);
     }
+    HIP_TRY(hipGetLastError());
     const bool f64 = dp->precision == GP_PREC_F64;
     {
         ProfScope ps(ctx, s, "detect_tiles");

@@ -493,6 +493,13 @@ def test_invalid_arguments_fail_synchronously(P):
         L.gp_detect(ph.ctx, ph.frames, ph.bp, ph.bkg.data_ptr(), ph.dp, ph.gcat, None, None,
                     ph.ws.data_ptr(), 1024, ph.stream_ptr())
     assert e.value.status == L.GP_ERR_WORKSPACE
+    # a detection batch holds at most 2^31 pixels (rejected while planning,
+    # before any device access: the frame pointers are dummies)
+    big = [L.gp_frame(1, 32768, 40000, 32768, 1)] * 2
+    with pytest.raises(L.GpError) as e:
+        L.gp_detect(ph.ctx, big, ph.bp, ph.bkg.data_ptr(), ph.dp, ph.gcat, None, None,
+                    ph.ws.data_ptr(), 1 << 40, ph.stream_ptr())
+    assert e.value.status == L.GP_ERR_UNSUPPORTED and "2^31" in L.load().gp_last_error().decode()
     ph.close()
 
 
