@@ -202,7 +202,8 @@ def main():
     torch.cuda.synchronize()
     L.gp_profile_enable(ph.ctx, False)
     kern = {}
-    for name in ("mesh_stats", "grid_filter", "spline", "setup", "detect_tiles", "merge", "catalog", "aperture"):
+    for name in ("mesh_stats", "filter_spline", "grid_filter", "spline", "setup", "detect_tiles", "merge", "catalog",
+                 "aperture"):
         tot, cnt = L.gp_profile_read(ph.ctx, name)
         if cnt:
             kern[name] = tot / cnt

@@ -9,9 +9,15 @@
 //                 a gather of the (few) pixels in the target bin.  All float
 //                 reductions run in a fixed order, so a mesh gives bit-identical
 //                 results wherever it is scheduled.
-//  k_grid_filter  f x f median over the mesh grid (truncated at the edges).
-//  k_spline_*     natural cubic splines through the mesh centres, solved in
-//                 FP64 (Thomas), turned into bicubic pieces per mesh cell.
+//  k_spline_y_pcr, k_spline_x_pcr
+//                 grids of at most 63 knots per axis: the f x f median over the
+//                 mesh grid (truncated at the edges) and the natural cubic
+//                 splines through the mesh centres, one wavefront per spline,
+//                 solved in FP64 by parallel cyclic reduction across lanes and
+//                 turned into bicubic pieces per mesh cell.
+//  k_grid_filter, k_spline_*
+//                 the same for larger grids: one thread per mesh for the
+//                 filter, one per spline for the FP64 Thomas solve.
 //
 // The statistics follow the SExtractor method the paper cites for local
 // background estimation; the paper's background subsection fixes the output
@@ -879,6 +885,7 @@ __device__ __forceinline__ void spline_solve_inv(int n, const double* t, const d
     if (n < 3) return;
     double rp = 0.0;
     double f0 = f[0], f1 = f[fs];
+#pragma unroll 4
     for (int k = 1; k <= n - 2; ++k) {
         const double f2 = f[(k + 1) * fs];
         const double rhs = 6.0 * ((f2 - f1) * ih[k] - (f1 - f0) * ih[k - 1]);
@@ -888,6 +895,7 @@ __device__ __forceinline__ void spline_solve_inv(int n, const double* t, const d
         f1 = f2;
     }
     double mk = rp;
+#pragma unroll 4
     for (int k = n - 3; k >= 1; --k) {
         mk = m[k * ms] - c[k] * mk;
         m[k * ms] = mk;
@@ -924,16 +932,32 @@ __device__ __forceinline__ void piece_poly_inv(int n, const double* t, const dou
     out[3] = (mj1 - mj) * ih[j] * kSixth;
 }
 
-// column of n values (stride s) into the LDS column `lane` of fl, 16 loads in
-// flight at a time (indices clamped to the column, so the loads need no branch)
-__device__ __forceinline__ void load_column(double* fl, int lane, const double* v, int s, int n) {
-    for (int k0 = 0; k0 < n; k0 += 16) {
-        double x[16];
+// A column of n values (stride s) into the LDS column `lane` of fl.  The
+// first kSplPre loads are issued by prefetch_column and waited for only in
+// store_column, so the knot factorisation runs while they are in flight; the
+// rest follow 16 at a time.  Indices are clamped to the column, so no load
+// needs a branch.
+constexpr int kSplPre = 64;
+
+__device__ __forceinline__ void prefetch_column(double (&x)[kSplPre], const double* v, int s, int n) {
+    const gdouble_t* g = (const gdouble_t*)v;   // global loads: they do not hold up LDS waits
 #pragma unroll
-        for (int j = 0; j < 16; ++j) x[j] = v[(size_t)min(k0 + j, n - 1) * s];
+    for (int j = 0; j < kSplPre; ++j) x[j] = g[(size_t)min(j, n - 1) * s];
+}
+
+__device__ __forceinline__ void store_column(double* fl, int lane, const double (&x)[kSplPre], const double* v,
+                                             int s, int n) {
+#pragma unroll
+    for (int j = 0; j < kSplPre; ++j)
+        if (j < n) fl[j * kSplCols + lane] = x[j];
+    const gdouble_t* g = (const gdouble_t*)v;
+    for (int k0 = kSplPre; k0 < n; k0 += 16) {
+        double y[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) y[j] = g[(size_t)min(k0 + j, n - 1) * s];
 #pragma unroll
         for (int j = 0; j < 16; ++j)
-            if (k0 + j < n) fl[(k0 + j) * kSplCols + lane] = x[j];
+            if (k0 + j < n) fl[(k0 + j) * kSplCols + lane] = y[j];
     }
 }
 
@@ -951,11 +975,13 @@ __global__ __launch_bounds__(kSplCols) void k_spline_y_small(const FrameDesc* __
     const bool on = g < 2 * nx;
     const int q = on ? g / nx : 0, i = on ? g - q * nx : 0;
     const double* col = (q ? d.rms : d.back) + i;
-    load_column(fl, lane, col, nx, ny);
     for (int k = lane; k < ny; k += kSplCols) tk[k] = knot_at(k, d.H, d.mh);
     __syncthreads();
+    double x[kSplPre];
+    prefetch_column(x, col, nx, ny);
     for (int k = lane; k + 1 < ny; k += kSplCols) ih[k] = 1.0 / (tk[k + 1] - tk[k]);
     if (lane == 0) spline_factor_inv(ny, tk, cf, idn);
+    store_column(fl, lane, x, col, nx, ny);
     __syncthreads();
     if (!on) return;
     spline_solve_inv(ny, tk, cf, idn, ih, fl + lane, kSplCols, ml + lane, kSplCols);
@@ -985,11 +1011,13 @@ __global__ __launch_bounds__(kSplCols) void k_spline_x_small(const FrameDesc* __
     const int jy = on ? (g >> 2) % (ny + 1) : 0;
     const int q = on ? (g >> 2) / (ny + 1) : 0;
     const double* vals = d.ycoef + (((size_t)q * (ny + 1) + jy) * nx) * 4 + r;  // stride 4
-    load_column(fl, lane, vals, 4, nx);
     for (int k = lane; k < nx; k += kSplCols) tk[k] = knot_at(k, d.W, d.mw);
     __syncthreads();
+    double x[kSplPre];
+    prefetch_column(x, vals, 4, nx);
     for (int k = lane; k + 1 < nx; k += kSplCols) ih[k] = 1.0 / (tk[k + 1] - tk[k]);
     if (lane == 0) spline_factor_inv(nx, tk, cf, idn);
+    store_column(fl, lane, x, vals, 4, nx);
     __syncthreads();
     if (!on) return;
     spline_solve_inv(nx, tk, cf, idn, ih, fl + lane, kSplCols, ml + lane, kSplCols);
@@ -998,6 +1026,133 @@ __global__ __launch_bounds__(kSplCols) void k_spline_x_small(const FrameDesc* __
         double c[4];
         piece_poly_inv(nx, tk, ih, fl + lane, kSplCols, ml + lane, kSplCols, ix, c);
         double* o = d.coef + (((size_t)q * (ny + 1) + jy) * (nx + 1) + ix) * 16;
+        for (int p = 0; p < 4; ++p) o[p * 4 + r] = c[p];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Grids of at most kPcrMax knots per axis: one wavefront per spline, lane k =
+// knot k.  The tridiagonal system of the natural spline's second derivatives
+// (interior rows h_{k-1} m_{k-1} + 2 (h_{k-1} + h_k) m_k + h_k m_{k+1} =
+// 6 (f_{k+1} - f_k) / h_k - 6 (f_k - f_{k-1}) / h_{k-1}, m_0 = m_{n-1} = 0)
+// is solved by parallel cyclic reduction: six rounds, each eliminating the
+// couplings to the rows at distance 1, 2, ..., 32 (fetched by lane shuffles;
+// rows outside the spline are identity rows).  The matrix is strictly
+// diagonally dominant, so the reduction is stable.  Lane p then forms piece p
+// from the values of lanes clamp(p - 1, 0, n - 2) and the next one.  The
+// y splines also apply the mesh filter (lane k takes mesh (k, i)).
+constexpr int kPcrMax = 63;   // knots: the n + 1 pieces fit one wavefront
+
+// second derivatives at the knots; t0 = t_{k-1}, t1 = t_k, t2 = t_{k+1}
+__device__ __forceinline__ double pcr_second_derivs(int n, int lane, double t0, double t1, double t2, double fm,
+                                                    double f, double fp) {
+    const bool row = lane >= 1 && lane <= n - 2;
+    const double h0 = t1 - t0, h1 = t2 - t1;
+    double a = row ? h0 : 0.0, b = row ? 2.0 * (h0 + h1) : 1.0, c = row ? h1 : 0.0;
+    double d = row ? 6.0 * ((fp - f) / h1 - (f - fm) / h0) : 0.0;
+#pragma unroll
+    for (int st = 1; st < 64; st <<= 1) {
+        const double rb = 1.0 / b;
+        const bool okl = lane >= st, okh = lane + st < 64;
+        const int sl = okl ? lane - st : lane, sh = okh ? lane + st : lane;
+        const double al = __shfl(a, sl), cl = __shfl(c, sl), dl = __shfl(d, sl), rl = __shfl(rb, sl);
+        const double ah = __shfl(a, sh), ch = __shfl(c, sh), dh = __shfl(d, sh), rh = __shfl(rb, sh);
+        const double al_ = okl ? al : 0.0, cl_ = okl ? cl : 0.0, dl_ = okl ? dl : 0.0, rl_ = okl ? rl : 1.0;
+        const double ah_ = okh ? ah : 0.0, ch_ = okh ? ch : 0.0, dh_ = okh ? dh : 0.0, rh_ = okh ? rh : 1.0;
+        const double alpha = -a * rl_, gamma = -c * rh_;
+        b = b + alpha * cl_ + gamma * ah_;
+        d = d + alpha * dl_ + gamma * dh_;
+        a = alpha * al_;
+        c = gamma * ch_;
+    }
+    return d / b;
+}
+
+// piece p (lane) of the spline through n knots, from lane values f, m and the
+// knot spacings; out[r] = coefficient of u^r, u = position - reference knot
+__device__ __forceinline__ void pcr_piece(int n, int lane, double f, double m, double h, double out[4]) {
+    constexpr double kSixth = 1.0 / 6.0;
+    const int A = min(max(lane - 1, 0), max(n - 2, 0));
+    const double fA = __shfl(f, A), fB = __shfl(f, A + 1), mA = __shfl(m, A), mB = __shfl(m, A + 1);
+    const double hA = __shfl(h, A);
+    const double ih = 1.0 / hA;
+    out[0] = out[1] = out[2] = out[3] = 0.0;
+    if (n == 1) {
+        out[0] = fA;
+    } else if (lane == 0) {
+        out[0] = fA;
+        out[1] = (fB - fA) * ih - hA * (2.0 * mA + mB) * kSixth;
+    } else if (lane == n) {
+        out[0] = fB;
+        out[1] = (fB - fA) * ih + hA * (mA + 2.0 * mB) * kSixth;
+    } else {
+        out[0] = fA;
+        out[1] = (fB - fA) * ih - hA * (2.0 * mA + mB) * kSixth;
+        out[2] = 0.5 * mA;
+        out[3] = (mB - mA) * ih * kSixth;
+    }
+}
+
+// y splines (and the mesh filter when F > 0): blockIdx.y = frame, one
+// wavefront per (quantity, mesh column), four per workgroup
+template <int F>
+__global__ __launch_bounds__(256) void k_spline_y_pcr(const FrameDesc* __restrict__ desc) {
+    const FrameDesc& d = desc[blockIdx.y];
+    const int nx = d.nx, ny = d.ny, lane = threadIdx.x & 63;
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= 2 * nx) return;
+    const int q = g / nx, i = g - q * nx;
+    const int k = min(lane, ny - 1);
+    double f;
+    if constexpr (F > 0) {
+        constexpr int hh = F / 2;
+        const gdouble_t* raw = (const gdouble_t*)(q ? d.rms_raw : d.back_raw);
+        double w[F * F];
+        int cnt = 0;
+#pragma unroll
+        for (int e = 0; e < F * F; ++e) {
+            const int b = k - hh + e / F, c = i - hh + e % F;
+            const bool in = b >= 0 && b < ny && c >= 0 && c < nx;
+            w[e] = in ? raw[b * nx + c] : INFINITY;
+            cnt += in ? 1 : 0;
+        }
+        f = median_regs(w, cnt);
+        if (lane < ny) (q ? d.rms : d.back)[k * nx + i] = f;
+    } else {
+        f = ((const gdouble_t*)(q ? d.rms : d.back))[k * nx + i];
+    }
+    const double t0 = knot_at(max(k - 1, 0), d.H, d.mh), t1 = knot_at(k, d.H, d.mh);
+    const double t2 = knot_at(min(k + 1, ny - 1), d.H, d.mh);
+    const double fm = __shfl(f, max(lane - 1, 0)), fp = __shfl(f, min(lane + 1, 63));
+    const double m = pcr_second_derivs(ny, lane, t0, t1, t2, fm, f, fp);
+    double c[4];
+    pcr_piece(ny, lane, f, m, t2 - t1, c);
+    if (lane <= ny) {
+        double* o = d.ycoef + (((size_t)q * (ny + 1) + lane) * nx + i) * 4;
+        o[0] = c[0];
+        o[1] = c[1];
+        o[2] = c[2];
+        o[3] = c[3];
+    }
+}
+
+// x splines: blockIdx.y = frame; workgroup = (quantity, y piece), its four
+// wavefronts the four powers of u
+__global__ __launch_bounds__(256) void k_spline_x_pcr(const FrameDesc* __restrict__ desc) {
+    const FrameDesc& d = desc[blockIdx.y];
+    const int nx = d.nx, ny = d.ny, lane = threadIdx.x & 63, r = threadIdx.x >> 6;
+    const int b = blockIdx.x;
+    if (b >= 2 * (ny + 1)) return;
+    const int k = min(lane, nx - 1);
+    const double f = ((const gdouble_t*)d.ycoef)[((size_t)b * nx + k) * 4 + r];   // b = q (ny + 1) + jy
+    const double t0 = knot_at(max(k - 1, 0), d.W, d.mw), t1 = knot_at(k, d.W, d.mw);
+    const double t2 = knot_at(min(k + 1, nx - 1), d.W, d.mw);
+    const double fm = __shfl(f, max(lane - 1, 0)), fp = __shfl(f, min(lane + 1, 63));
+    const double m = pcr_second_derivs(nx, lane, t0, t1, t2, fm, f, fp);
+    double c[4];
+    pcr_piece(nx, lane, f, m, t2 - t1, c);
+    if (lane <= nx) {
+        double* o = d.coef + ((size_t)b * (nx + 1) + lane) * 16;
         for (int p = 0; p < 4; ++p) o[p * 4 + r] = c[p];
     }
 }
@@ -1092,6 +1247,24 @@ void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, in
         case 5: k_grid_filter<5><<<blocks, kGridThreads, 0, s>>>(desc, nframes, total_meshes, fsize); break;
         default: k_grid_filter<0><<<blocks, kGridThreads, 0, s>>>(desc, nframes, total_meshes, fsize); break;
     }
+}
+
+// mesh filter of size fsize (0: none, the grids are given) and the splines
+// in two launches, for grids of at most kPcrMax knots per axis and filters of
+// at most 5 x 5 (filter_spline_fits)
+bool filter_spline_fits(int max_nx, int max_ny, int fsize) {
+    return max_nx <= kPcrMax && max_ny <= kPcrMax && fsize <= 5;
+}
+
+void launch_filter_spline(const FrameDesc* desc, int nframes, int max_nx, int max_ny, int fsize, hipStream_t s) {
+    const dim3 gy((2 * max_nx + 3) / 4, nframes);
+    switch (fsize) {
+        case 0: k_spline_y_pcr<0><<<gy, 256, 0, s>>>(desc); break;
+        case 1: k_spline_y_pcr<1><<<gy, 256, 0, s>>>(desc); break;
+        case 3: k_spline_y_pcr<3><<<gy, 256, 0, s>>>(desc); break;
+        default: k_spline_y_pcr<5><<<gy, 256, 0, s>>>(desc); break;
+    }
+    k_spline_x_pcr<<<dim3(2 * (max_ny + 1), nframes), 256, 0, s>>>(desc);
 }
 
 void launch_spline(const FrameDesc* desc, int nframes, int max_nx, int max_ny, hipStream_t s) {

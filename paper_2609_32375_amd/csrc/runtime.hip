@@ -583,12 +583,21 @@ extern "C" gp_status gp_background(gp_ctx* ctx, const gp_frame* frames, int32_t 
             launch_mesh_stats(desc, nframes, (int)P.total_meshes, P.max_area, a, cfg, s);
         }
         HIP_TRY(hipGetLastError());
-        {
-            ProfScope ps(ctx, s, "grid_filter");
-            launch_grid_filter(desc, nframes, (int)P.total_meshes, bp->filter_size, s);
-        }
-        HIP_TRY(hipGetLastError());
     }
+    // small grids: the filter inside the y-spline launch
+    const bool given = (bp->flags & GP_BKG_GRID_GIVEN) != 0;
+    const int fsize = given ? 0 : bp->filter_size;
+    if (filter_spline_fits(P.max_nx, P.max_ny, fsize)) {
+        ProfScope ps(ctx, s, "filter_spline");
+        launch_filter_spline(desc, nframes, P.max_nx, P.max_ny, fsize, s);
+        HIP_TRY(hipGetLastError());
+        return GP_OK;
+    }
+    if (!given) {
+        ProfScope ps(ctx, s, "grid_filter");
+        launch_grid_filter(desc, nframes, (int)P.total_meshes, bp->filter_size, s);
+    }
+    HIP_TRY(hipGetLastError());
     {
         ProfScope ps(ctx, s, "spline");
         launch_spline(desc, nframes, P.max_nx, P.max_ny, s);
