@@ -697,34 +697,51 @@ __global__ __launch_bounds__(256) void k_merge_edges(DetWork wk, int conn) {
     const int tx = lt % d.ntx, ty = lt / d.ntx;
     const int tw = min(kTile, d.W - tx * kTile), th = min(kTile, d.H - ty * kTile);
     const int16_t* EA = wk.edges + (size_t)gt * 4 * kTile;
-    const int dj0 = (conn == 8) ? -1 : 0, dj1 = (conn == 8) ? 1 : 0;
+    const bool conn8 = conn == 8;
+    // One seam: lane l holds A's piece a at position l and B's piece at l
+    // (-1: none, or past the seam's length).  Lane l unites (a, b_j) for
+    // j = l (and l +- 1 with 8-connectivity), skipping a pair that one of its
+    // earlier offsets or the previous lane also forms: the first lane and
+    // offset forming a pair always unites it, and runs along the seam give
+    // one union each instead of one per pixel and offset.
+    auto seam = [&](int a, int bl, int baseA, int baseB) {
+        // (every lane runs the shuffles: a lane outside the exec mask would
+        // hand its neighbours an undefined value)
+        const int sa1 = __shfl(a, max(lane - 1, 0)), sb1 = __shfl(bl, max(lane - 1, 0));
+        const int sb2 = __shfl(bl, max(lane - 2, 0)), sbp = __shfl(bl, min(lane + 1, 63));
+        const int pa = (lane >= 1) ? sa1 : -1, bm1 = (lane >= 1) ? sb1 : -1;
+        const int bm2 = (lane >= 2) ? sb2 : -1, bp1 = (lane <= 62) ? sbp : -1;
+        if (a < 0) return;
+        const int cand[3] = {conn8 ? bm1 : -1, bl, conn8 ? bp1 : -1};   // b at l - 1, l, l + 1
+        const int prev[3] = {conn8 ? bm2 : -1, bm1, conn8 ? bl : -1};   // the previous lane's
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int b = cand[t];
+            if (b < 0) continue;
+            bool dup = false;
+#pragma unroll
+            for (int u = 0; u < t; ++u) dup = dup || cand[u] == b;
+            if (pa == a) dup = dup || prev[0] == b || prev[1] == b || prev[2] == b;
+            if (!dup) g_union(wk.parent, baseA + a, baseB + b);
+        }
+    };
     if (tx + 1 < d.ntx) {
         const TileInfo B = wk.tiles[gt + 1];
-        if (B.ncomp > 0 && lane < th) {
+        if (B.ncomp > 0) {
             const int16_t* EB = wk.edges + (size_t)(gt + 1) * 4 * kTile;
-            const int a = EA[3 * kTile + lane];
-            if (a >= 0)
-                for (int dj = dj0; dj <= dj1; ++dj) {
-                    const int j = lane + dj;
-                    if (j < 0 || j >= th) continue;
-                    const int b = EB[2 * kTile + j];
-                    if (b >= 0) g_union(wk.parent, A.base + a, B.base + b);
-                }
+            const int a = (lane < th) ? EA[3 * kTile + lane] : -1;
+            const int bl = (lane < th) ? EB[2 * kTile + lane] : -1;
+            seam(a, bl, A.base, B.base);
         }
     }
     if (ty + 1 < d.nty) {
         const int gc = gt + d.ntx;
         const TileInfo C = wk.tiles[gc];
-        if (C.ncomp > 0 && lane < tw) {
+        if (C.ncomp > 0) {
             const int16_t* EC = wk.edges + (size_t)gc * 4 * kTile;
-            const int a = EA[1 * kTile + lane];
-            if (a >= 0)
-                for (int dj = dj0; dj <= dj1; ++dj) {
-                    const int j = lane + dj;
-                    if (j < 0 || j >= tw) continue;
-                    const int b = EC[0 * kTile + j];
-                    if (b >= 0) g_union(wk.parent, A.base + a, C.base + b);
-                }
+            const int a = (lane < tw) ? EA[1 * kTile + lane] : -1;
+            const int bl = (lane < tw) ? EC[0 * kTile + lane] : -1;
+            seam(a, bl, A.base, C.base);
         }
         if (conn == 8) {
             // down-right corner: (x0+63, y0+63) with (x0+64, y0+64)
