@@ -510,14 +510,19 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     // piece id of a pixel = rank of its root among the tile's roots
     int co[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int r = rt[k] & (kTile * kTile - 1);
-        const int ry_ = r >> 6, rx_ = r & 63;
-        const uint64_t lowr = (rx_ == 0) ? 0ull : ((~0ull) >> (64 - rx_));
-        const int c = sh.rowoff[ry_] + __popcll(sh.rowmask[ry_] & lowr);
-        co[k] = ((mbits >> k) & 1u) ? c : -1;
-        comp[(16 * wv + k) * kTile + lane] = (int16_t)co[k];
+    for (int k = 0; k < 16; ++k) co[k] = -1;
+    if (__ballot(mbits != 0u) != 0ull) {   // (no pieces in a wavefront without detections)
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int r = rt[k] & (kTile * kTile - 1);
+            const int ry_ = r >> 6, rx_ = r & 63;
+            const uint64_t lowr = (rx_ == 0) ? 0ull : ((~0ull) >> (64 - rx_));
+            const int c = sh.rowoff[ry_] + __popcll(sh.rowmask[ry_] & lowr);
+            co[k] = ((mbits >> k) & 1u) ? c : -1;
+        }
     }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) comp[(16 * wv + k) * kTile + lane] = (int16_t)co[k];
     // 5. records for the tile's pieces (LDS for the first kLocalRecs, in u2,
     //    now free: M lives in VGPRs)
     if (tid == 0) {
@@ -588,7 +593,8 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
         }
     }
     // 6. moments: column runs, compensated, flushed into the piece records
-    {
+    //    (a wavefront whose rows hold no detection has none to add)
+    if (__ballot(mbits != 0u) != 0ull) {
         const float sat = pa->sat;
         const bool has_sat = sat < INFINITY;
         const int gx = x0 + lane;
