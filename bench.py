@@ -121,7 +121,9 @@ def write_traffic(a):
 
 
 def kernel_bytes(name, W, H, bpp, n_obj, rmax):
-    """Algorithmic bytes one launch of a kernel must move."""
+    """Algorithmic bytes one launch of a kernel must move: one read of the
+    frame for the mesh statistics and the detection, the pixels of every
+    object's outer circle for the apertures."""
     if name in ("mesh_stats", "detect_tiles"):
         return W * H * bpp
     if name == "aperture":
