@@ -28,6 +28,15 @@ import torch
 from . import _lib as L
 from .pipeline import Photometry
 
+# a detection batch holds at most 2^31 pixels, each frame counted in whole
+# 1024-pixel blocks (larger batches are refused by gp_detect)
+MAX_BATCH_BLOCKS = 1 << 21
+
+
+def pixel_blocks(frame) -> int:
+    h, w = frame.shape[-2], frame.shape[-1]
+    return -(-(int(h) * int(w)) // 1024)
+
 
 @dataclass
 class Request:
@@ -66,7 +75,7 @@ class Server:
     """
 
     def __init__(self, params, kernel, capacity: int = 65536, hbm_budget: Optional[int] = None,
-                 slots: int = 8, streams: int = 2, device: int = 0, max_batch: Optional[int] = None):
+                 slots: int = 16, streams: int = 2, device: int = 0, max_batch: Optional[int] = None):
         self.params = params
         self.kernel = np.ascontiguousarray(kernel, dtype=np.float32)
         self.capacity = capacity
@@ -161,14 +170,17 @@ class Server:
         now = self.now()
         key = None
         keep = deque()
+        blocks = 0
         while self.waiting:
             r = self.waiting.popleft()
             fits = (len(batch) < self.max_batch and r.arrival <= now and n_inflight + len(batch) < self.slots
-                    and self.resident + r.footprint <= self.budget)
+                    and self.resident + r.footprint <= self.budget
+                    and blocks + pixel_blocks(r.frame) <= MAX_BATCH_BLOCKS)
             if fits and (key is None or self._key(r) == key):
                 key = self._key(r)
                 r.t_admit = now
                 self.resident += r.footprint
+                blocks += pixel_blocks(r.frame)
                 batch.append(r)
             else:
                 keep.append(r)

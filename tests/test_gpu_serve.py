@@ -62,3 +62,41 @@ def test_results_alone_equal_results_in_the_mix():
     with pytest.raises(ValueError):
         srv.submit(Request(99, np.zeros((4096, 4096), np.float32)))
     srv.close()
+
+
+def test_batches_stay_within_the_detection_pixel_limit():
+    # sixteen 151 MP requests queued at once with room for all of them: one
+    # batch would hold 2.4 G pixels, above gp_detect's 2^31, so the server
+    # splits them; every request gets the result it gets alone
+    from paper_2609_32375_amd import pipeline as P
+    from paper_2609_32375_amd.serve import MAX_BATCH_BLOCKS, Request, Server, pixel_blocks
+    from synth import config_params, render_gpu
+    img = render_gpu(12300, 12300, 2000, 71)
+    p = config_params("c3")
+    K = p.kernel()
+    cap = 65536
+    ph = P.Photometry([img], p, K, cap)
+    ph.run()
+    solo = ph.results(0)
+    ph.close()
+    assert 16 * pixel_blocks(img) > MAX_BATCH_BLOCKS and MAX_BATCH_BLOCKS * 1024 == 1 << 31
+    srv = Server(p, K, capacity=cap, slots=32, streams=2)
+    sizes = []
+    orig = srv._admit
+
+    def admit():
+        n0 = len(srv.inflight)
+        ok = orig()
+        if ok and len(srv.inflight) > n0:
+            sizes.append(len(srv.inflight[-1].reqs))
+        return ok
+    srv._admit = admit
+    reqs = [Request(i, img, arrival=0.0) for i in range(16)]
+    srv.run(reqs)
+    srv.close()
+    assert sizes and max(sizes) * pixel_blocks(img) <= MAX_BATCH_BLOCKS
+    for r in reqs:
+        a = r.result
+        assert a["status"] == 0 and a["n_obj"] == solo["n_obj"] > 0
+        np.testing.assert_array_equal(a["cat"]["pmin"], solo["cat"]["pmin"])
+        np.testing.assert_array_equal(a["phot"]["flux"], solo["phot"]["flux"])
