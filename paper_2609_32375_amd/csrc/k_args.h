@@ -81,6 +81,6 @@ void launch_aperture(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, i
 void launch_bkg_map(const FrameDesc& d, double* bmap, double* rmap, bool f64, hipStream_t s);
 void launch_write_desc(const DescChunk& c, FrameDesc* table, hipStream_t s);
 void launch_det_setup(const DescChunk& c, FrameDesc* table, const DetArgsIn& in, DetArgs* out, uint32_t* counters,
-                      uint32_t* bitmap, size_t nwords, hipStream_t s);
+                      hipStream_t s);
 
 }  // namespace gpk

@@ -177,6 +177,22 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     const int tx = lt % d.ntx, ty = lt / d.ntx;
     const int x0 = tx * kTile, y0 = ty * kTile;
     const int tw = min(kTile, d.W - x0), th = min(kTile, d.H - y0);
+    // the tile's words of the frame's rank bitmap start at zero (bits are set
+    // only after every tile has finished; words shared with a neighbouring
+    // tile are cleared by both); the frame's last tile also clears the words
+    // past its last pixel up to the end of the last 1024-bit block
+    {
+        const int r = tid >> 2, j = tid & 3;   // a row of 64 pixels spans at most 3 words
+        if (r < th) {
+            const int64_t p0 = (int64_t)(y0 + r) * d.W + x0;
+            const int64_t w = (p0 >> 5) + j;
+            if (w <= ((p0 + tw - 1) >> 5)) d.bitmap[w] = 0u;
+        }
+        if (tx == d.ntx - 1 && ty == d.nty - 1) {
+            const int64_t wlim = (int64_t)d.nblocks * 32;
+            for (int64_t w = (((int64_t)d.W * d.H + 31) >> 5) + tid; w < wlim; w += 256) d.bitmap[w] = 0u;
+        }
+    }
     const int kw = kSep ? 2 * kR + 1 : pa->kw;
     const int kh = kSep ? 2 * kR + 1 : pa->kh;
     const int rx = kw >> 1, ry = kh >> 1;
@@ -1062,16 +1078,12 @@ __global__ void k_write_desc(DescChunk c, FrameDesc* table) {
     if (i < c.count) table[c.first + i] = c.d[i];
 }
 
-// Per-call set-up of the detection, one launch: workgroup 0 writes the last
-// descriptors, the filter arguments (the dense kernel normalised with an FP64
-// sum in a fixed order) and zeroes the counters; every workgroup zeroes its
-// share of the rank bitmap (nvec 16-byte words).
+// Per-call set-up of the detection, one workgroup: the last descriptors, the
+// filter arguments (the dense kernel normalised with an FP64 sum in a fixed
+// order) and zeroed counters.  (The detection tiles clear the rank bitmap.)
 __global__ __launch_bounds__(256) void k_det_setup(DescChunk c, FrameDesc* table, DetArgsIn in, DetArgs* out,
-                                                   uint32_t* counters, uint4* bitmap, size_t nvec) {
+                                                   uint32_t* counters) {
     const int t = threadIdx.x;
-    for (size_t i = (size_t)blockIdx.x * 256 + t; i < nvec; i += (size_t)gridDim.x * 256)
-        bitmap[i] = make_uint4(0u, 0u, 0u, 0u);
-    if (blockIdx.x != 0) return;
     if (t < c.count) table[c.first + t] = c.d[t];
     if (t < kNumCounters) counters[t] = 0u;
     if (t == 0) {
@@ -1107,10 +1119,8 @@ void launch_write_desc(const DescChunk& c, FrameDesc* table, hipStream_t s) {
 }
 
 void launch_det_setup(const DescChunk& c, FrameDesc* table, const DetArgsIn& in, DetArgs* out, uint32_t* counters,
-                      uint32_t* bitmap, size_t nwords, hipStream_t s) {
-    const size_t nvec = nwords / 4;   // whole 1024-bit blocks: a multiple of 4 words
-    const int blocks = (int)std::max<size_t>(1, std::min<size_t>((nvec + 255) / 256, 1024));
-    k_det_setup<<<blocks, 256, 0, s>>>(c, table, in, out, counters, (uint4*)bitmap, nvec);
+                      hipStream_t s) {
+    k_det_setup<<<1, 256, 0, s>>>(c, table, in, out, counters);
 }
 
 }  // namespace gpk

@@ -710,8 +710,7 @@ extern "C" gp_status gp_detect(gp_ctx* ctx, const gp_frame* frames, int32_t nfra
     wk.total_blocks = (int32_t)P.total_blocks;
     {
         ProfScope ps(ctx, s, "setup");
-        launch_det_setup(tail, (FrameDesc*)(W + P.o_desc), in, dargs, wk.counters, wk.bitmap,
-                         (size_t)P.total_blocks * 32, s);
+        launch_det_setup(tail, (FrameDesc*)(W + P.o_desc), in, dargs, wk.counters, s);
     }
     HIP_TRY(hipGetLastError());
     const bool f64 = dp->precision == GP_PREC_F64;
