@@ -12,8 +12,8 @@
 //                  kept for the merge.
 //  k_merge_edges   unions pieces that touch across tile borders (8- or
 //                  4-neighbourhood) in a global union-find.
-//  k_merge_records adds every non-root piece into its root record.
-//  k_mark_kept     sets the first-pixel bit of every component with
+//  k_merge_records adds every non-root piece into its root record and sets
+//                  the first-pixel bit of every component with
 //                  npix >= minarea in a per-frame bitmap.
 //  k_popc_scan     prefix sums of the bitmap's popcounts -> label = rank of
 //                  the first pixel in raster order.
@@ -111,21 +111,23 @@ __device__ __forceinline__ int g_find(int* P, int x) {
         x = q;
     }
 }
-__device__ __forceinline__ void g_union(int* P, int a, int b) {
+// The root with the later first pixel (raster order; pieces have distinct
+// first pixels) is linked under the other, so a component's root is the piece
+// that holds the component's first pixel.  A failed link (the root was linked
+// meanwhile) retries from the new roots; links follow one strict order, so no
+// cycle can form.
+__device__ __forceinline__ void g_union(int* P, const CompRec* R, int a, int b) {
     while (true) {
         a = g_find(P, a);
         b = g_find(P, b);
-        if (a < b) {
-            int old = atomicMin(&P[b], a);
-            if (old == b) return;
-            b = old;
-        } else if (b < a) {
-            int old = atomicMin(&P[a], b);
-            if (old == a) return;
-            a = old;
-        } else {
-            return;
+        if (a == b) return;
+        const uint32_t ka = R[a].pmin, kb = R[b].pmin;
+        if (kb < ka || (kb == ka && b < a)) {
+            const int t = a;
+            a = b;
+            b = t;
         }
+        if (atomicCAS(&P[b], b, a) == b) return;
     }
 }
 
@@ -744,7 +746,7 @@ __global__ __launch_bounds__(256) void k_merge_edges(DetWork wk, int conn) {
 #pragma unroll
             for (int u = 0; u < t; ++u) dup = dup || cand[u] == b;
             if (pa == a) dup = dup || prev[0] == b || prev[1] == b || prev[2] == b;
-            if (!dup) g_union(wk.parent, baseA + a, baseB + b);
+            if (!dup) g_union(wk.parent, wk.recs, baseA + a, baseB + b);
         }
     };
     if (tx + 1 < d.ntx) {
@@ -772,7 +774,7 @@ __global__ __launch_bounds__(256) void k_merge_edges(DetWork wk, int conn) {
                 const int a = EA[1 * kTile + tw - 1];
                 if (D.ncomp > 0 && a >= 0) {
                     const int b = wk.edges[(size_t)(gc + 1) * 4 * kTile + 0];
-                    if (b >= 0) g_union(wk.parent, A.base + a, D.base + b);
+                    if (b >= 0) g_union(wk.parent, wk.recs, A.base + a, D.base + b);
                 }
             }
             // down-left corner: (x0, y0+63) with (x0-1, y0+64)
@@ -781,53 +783,56 @@ __global__ __launch_bounds__(256) void k_merge_edges(DetWork wk, int conn) {
                 const int a = EA[1 * kTile + 0];
                 if (D.ncomp > 0 && a >= 0) {
                     const int b = wk.edges[(size_t)(gc - 1) * 4 * kTile + kTile - 1];
-                    if (b >= 0) g_union(wk.parent, A.base + a, D.base + b);
+                    if (b >= 0) g_union(wk.parent, wk.recs, A.base + a, D.base + b);
                 }
             }
         }
     }
 }
 
-// every piece finds its root; non-roots add their sums into the root record
-__global__ __launch_bounds__(256) void k_merge_records(DetWork wk) {
+// Every piece finds its root; non-roots add their sums into the root record.
+// A component is kept when its pixel count reaches minarea: the bit of its
+// first pixel (the root's own) is set by the root when its own pixels already
+// reach it, else by the piece whose addition carries the count across it
+// (counts are exact in FP64, so exactly one addition crosses).
+__global__ __launch_bounds__(256) void k_merge_records(DetWork wk, int minarea) {
     if (wk.counters[1] != 0u) return;
     const int total = min((int)wk.counters[0], wk.rec_cap);
+    const double ma = (double)minarea;
     for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
         const int r = g_find(wk.parent, id);
         wk.root[id] = r;
-        if (r == id) continue;
-        const CompRec& S = wk.recs[id];
         CompRec& R = wk.recs[r];
-        const double ox = (double)(S.x0 - R.x0), oy = (double)(S.y0 - R.y0);
-        for (int h = 0; h < 2; ++h) {
-            const double* s = S.s + 6 * h;
-            double* t = R.s + 6 * h;
-            unsafeAtomicAdd(&t[0], s[0]);
-            unsafeAtomicAdd(&t[1], s[1] + ox * s[0]);
-            unsafeAtomicAdd(&t[2], s[2] + oy * s[0]);
-            unsafeAtomicAdd(&t[3], s[3] + 2.0 * ox * s[1] + ox * ox * s[0]);
-            unsafeAtomicAdd(&t[4], s[4] + 2.0 * oy * s[2] + oy * oy * s[0]);
-            unsafeAtomicAdd(&t[5], s[5] + ox * s[2] + oy * s[1] + ox * oy * s[0]);
+        bool mark;
+        if (r == id) {
+            mark = __hip_atomic_load(&R.s[6], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= ma;
+        } else {
+            const CompRec& S = wk.recs[id];
+            const double ox = (double)(S.x0 - R.x0), oy = (double)(S.y0 - R.y0);
+            double before = 0.0;
+            for (int h = 0; h < 2; ++h) {
+                const double* s = S.s + 6 * h;
+                double* t = R.s + 6 * h;
+                const double old = unsafeAtomicAdd(&t[0], s[0]);
+                if (h == 1) before = old;
+                unsafeAtomicAdd(&t[1], s[1] + ox * s[0]);
+                unsafeAtomicAdd(&t[2], s[2] + oy * s[0]);
+                unsafeAtomicAdd(&t[3], s[3] + 2.0 * ox * s[1] + ox * ox * s[0]);
+                unsafeAtomicAdd(&t[4], s[4] + 2.0 * oy * s[2] + oy * oy * s[0]);
+                unsafeAtomicAdd(&t[5], s[5] + ox * s[2] + oy * s[1] + ox * oy * s[0]);
+            }
+            atomicMin(&R.xmin, S.xmin);
+            atomicMax(&R.xmax, S.xmax);
+            atomicMin(&R.ymin, S.ymin);
+            atomicMax(&R.ymax, S.ymax);
+            atomicMax(&R.peak, S.peak);
+            if (S.flags) atomicOr(&R.flags, S.flags);
+            mark = before < ma && before + S.s[6] >= ma;
         }
-        atomicMin(&R.xmin, S.xmin);
-        atomicMax(&R.xmax, S.xmax);
-        atomicMin(&R.ymin, S.ymin);
-        atomicMax(&R.ymax, S.ymax);
-        atomicMin(&R.pmin, S.pmin);
-        atomicMax(&R.peak, S.peak);
-        if (S.flags) atomicOr(&R.flags, S.flags);
-    }
-}
-
-__global__ __launch_bounds__(256) void k_mark_kept(DetWork wk, int minarea) {
-    if (wk.counters[1] != 0u) return;
-    const int total = min((int)wk.counters[0], wk.rec_cap);
-    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
-        if (wk.root[id] != id) continue;
-        const CompRec& R = wk.recs[id];
-        if (R.s[6] < (double)minarea) continue;
-        const FrameDesc& d = wk.desc[R.frame];
-        atomicOr(&d.bitmap[R.pmin >> 5], 1u << (R.pmin & 31u));
+        if (mark) {
+            const FrameDesc& d = wk.desc[R.frame];
+            atomicOr(&d.bitmap[R.pmin >> 5], 1u << (R.pmin & 31u));
+        }
     }
 }
 
@@ -1055,8 +1060,7 @@ void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, int r
 
 void launch_merge(const DetWork& wk, int conn, int minarea, int persist_blocks, hipStream_t s) {
     k_merge_edges<<<(wk.total_tiles + 3) / 4, 256, 0, s>>>(wk, conn);
-    k_merge_records<<<persist_blocks, 256, 0, s>>>(wk);
-    k_mark_kept<<<persist_blocks, 256, 0, s>>>(wk, minarea);
+    k_merge_records<<<persist_blocks, 256, 0, s>>>(wk, minarea);
     const int nb = wk.total_blocks;
     const int nchunks = (nb + kScanChunk - 1) / kScanChunk;
     k_popc_scan<<<nchunks, 256, 0, s>>>(wk.bitmap, wk.blockcnt, wk.chunksum, nb);
