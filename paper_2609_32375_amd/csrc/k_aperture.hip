@@ -189,8 +189,10 @@ struct ApLayout {
 // spread over the lanes.  Sums are kept per lane (FP64 for the flux) and
 // reduced in a fixed order, so an object's result does not depend on what else
 // runs.
-template <typename Real, int NC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 3 : 1))) void k_aperture(const FrameDesc* __restrict__ desc, ApArgs a, ApCat cat,
+// ONE: a one-frame call, whose descriptor comes with the launch (d1) instead
+// of from the workspace table
+template <typename Real, int NC, bool ONE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 3 : 1))) void k_aperture(const FrameDesc* __restrict__ desc, FrameDesc d1, ApArgs a, ApCat cat,
                                                   int band, int nixmax) {
     extern __shared__ __align__(16) unsigned char ap_dyn[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -265,7 +267,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real
         }
         const int f = lo, k = o - fpre[f];
         const int row = f * a.capacity + k;
-        const FrameDesc& d = desc[f];
+        const FrameDesc& d = ONE ? d1 : desc[f];
         const double xc = cat.x[row], yc = cat.y[row];
         const int cxi = (int)floor(xc), cyi = (int)floor(yc);
         const Real fx = (Real)(xc - (double)cxi), fy = (Real)(yc - (double)cyi);
@@ -507,8 +509,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real
 }
 
 template <typename Real, int NC>
-static void launch_ap_nc(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int blocks, int band,
-                         int nixmax, hipStream_t s) {
+static void launch_ap_nc(const FrameDesc* desc, const FrameDesc* one, const ApArgs& a, const ApCat& cat, int blocks,
+                         int band, int nixmax, hipStream_t s) {
     const ApLayout<Real, NC> L(band, nixmax);
     // waves per workgroup: as many (up to kApWaves) as keep the workgroup's
     // LDS within 64 KB; the grid keeps the same number of wavefronts
@@ -517,21 +519,22 @@ static void launch_ap_nc(const FrameDesc* desc, const ApArgs& a, const ApCat& ca
     const size_t lds = (size_t)kApPrefixBytes + (size_t)L.bytes * nw;
     const int wg = blocks * (kApWaves / nw);
     const int g = kXcds * std::max(1, (wg + kXcds - 1) / kXcds);
-    k_aperture<Real, NC><<<g, 64 * nw, lds, s>>>(desc, a, cat, band, nixmax);
+    if (one) k_aperture<Real, NC, true><<<g, 64 * nw, lds, s>>>(desc, *one, a, cat, band, nixmax);
+    else k_aperture<Real, NC, false><<<g, 64 * nw, lds, s>>>(desc, FrameDesc{}, a, cat, band, nixmax);
 }
 
 template <typename Real>
-static void launch_ap_t(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int blocks, int band,
-                        int nixmax, hipStream_t s) {
+static void launch_ap_t(const FrameDesc* desc, const FrameDesc* one, const ApArgs& a, const ApCat& cat, int blocks,
+                        int band, int nixmax, hipStream_t s) {
     switch (a.nr + 2) {
-        case 3: launch_ap_nc<Real, 3>(desc, a, cat, blocks, band, nixmax, s); break;
-        case 4: launch_ap_nc<Real, 4>(desc, a, cat, blocks, band, nixmax, s); break;
-        case 5: launch_ap_nc<Real, 5>(desc, a, cat, blocks, band, nixmax, s); break;
-        case 6: launch_ap_nc<Real, 6>(desc, a, cat, blocks, band, nixmax, s); break;
-        case 7: launch_ap_nc<Real, 7>(desc, a, cat, blocks, band, nixmax, s); break;
-        case 8: launch_ap_nc<Real, 8>(desc, a, cat, blocks, band, nixmax, s); break;
-        case 9: launch_ap_nc<Real, 9>(desc, a, cat, blocks, band, nixmax, s); break;
-        default: launch_ap_nc<Real, 10>(desc, a, cat, blocks, band, nixmax, s); break;
+        case 3: launch_ap_nc<Real, 3>(desc, one, a, cat, blocks, band, nixmax, s); break;
+        case 4: launch_ap_nc<Real, 4>(desc, one, a, cat, blocks, band, nixmax, s); break;
+        case 5: launch_ap_nc<Real, 5>(desc, one, a, cat, blocks, band, nixmax, s); break;
+        case 6: launch_ap_nc<Real, 6>(desc, one, a, cat, blocks, band, nixmax, s); break;
+        case 7: launch_ap_nc<Real, 7>(desc, one, a, cat, blocks, band, nixmax, s); break;
+        case 8: launch_ap_nc<Real, 8>(desc, one, a, cat, blocks, band, nixmax, s); break;
+        case 9: launch_ap_nc<Real, 9>(desc, one, a, cat, blocks, band, nixmax, s); break;
+        default: launch_ap_nc<Real, 10>(desc, one, a, cat, blocks, band, nixmax, s); break;
     }
 }
 
@@ -542,15 +545,15 @@ static int ap_nixmax(int side, int mesh, int nmesh) {
     return std::max(1, std::min(nmesh + 1, (side - 1) / std::max(mesh, 1) + 3));
 }
 
-void launch_aperture(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int total_rows, int blocks,
-                     int mesh_w, int max_nx, bool f64, hipStream_t s) {
+void launch_aperture(const FrameDesc* desc, const FrameDesc* one, const ApArgs& a, const ApCat& cat, int total_rows,
+                     int blocks, int mesh_w, int max_nx, bool f64, hipStream_t s) {
     if (total_rows <= 0) return;
     const int R = (int)ceilf(a.rmax) + 1;
     const int side = 2 * R + 2;
     const int nixmax = ap_nixmax(side, mesh_w, max_nx);
     const int band = kApBand;
-    if (f64) launch_ap_t<double>(desc, a, cat, blocks, band, nixmax, s);
-    else launch_ap_t<float>(desc, a, cat, blocks, band, nixmax, s);
+    if (f64) launch_ap_t<double>(desc, one, a, cat, blocks, band, nixmax, s);
+    else launch_ap_t<float>(desc, one, a, cat, blocks, band, nixmax, s);
 }
 
 }  // namespace gpk

@@ -76,8 +76,10 @@ void launch_merge(const DetWork& wk, int conn, int minarea, int persist_blocks, 
 void launch_catalog(const DetWork& wk, const CatOut& cat, int minarea, int persist_blocks, int32_t* comp_status,
                     hipStream_t s);
 void launch_seg(const DetWork& wk, int f, int64_t npx, hipStream_t s);
-void launch_aperture(const FrameDesc* desc, const ApArgs& a, const ApCat& cat, int total_rows, int blocks,
-                     int mesh_w, int max_nx, bool f64, hipStream_t s);
+// one: the descriptor of a one-frame call, passed with the launch (the
+// workspace table is then not read), or null
+void launch_aperture(const FrameDesc* desc, const FrameDesc* one, const ApArgs& a, const ApCat& cat, int total_rows,
+                     int blocks, int mesh_w, int max_nx, bool f64, hipStream_t s);
 void launch_bkg_map(const FrameDesc& d, double* bmap, double* rmap, bool f64, hipStream_t s);
 void launch_write_desc(const DescChunk& c, FrameDesc* table, hipStream_t s);
 void launch_det_setup(const DescChunk& c, FrameDesc* table, const DetArgsIn& in, DetArgs* out, uint32_t* counters,

@@ -761,8 +761,12 @@ extern "C" gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nf
     if ((st = check_ws(P, ws, ws_bytes)) != GP_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(ctx->device));
-    // only the descriptor table is needed; it sits at the start of the workspace
-    if ((st = upload_desc(frames, nframes, bp, P, bkg, ws, cat->capacity, nullptr, s)) != GP_OK) return st;
+    // only the descriptors are needed: a one-frame call passes its descriptor
+    // with the launch, a batch reads the table at the start of the workspace
+    const bool one = nframes == 1;
+    DescChunk tail{};
+    if ((st = upload_desc(frames, nframes, bp, P, bkg, ws, cat->capacity, nullptr, s, one ? &tail : nullptr)) != GP_OK)
+        return st;
     ApArgs a{};
     a.nr = ap->nr;
     a.want_err = ap->want_err ? 1 : 0;
@@ -798,8 +802,8 @@ extern "C" gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nf
         const bool f64 = ap->precision == GP_PREC_F64;
         auto run = [&](int per_cu) {
             const int blocks = std::max(1, std::min(ctx->cus * per_cu, (total_rows + 3) / 4));
-            launch_aperture((const FrameDesc*)((char*)ws + P.o_desc), a, c, total_rows, blocks, bp->mesh_w, max_nx,
-                            f64, s);
+            launch_aperture((const FrameDesc*)((char*)ws + P.o_desc), one ? &tail.d[0] : nullptr, a, c, total_rows,
+                            blocks, bp->mesh_w, max_nx, f64, s);
         };
         // workgroups per CU of the persistent grid
         const std::string key = "aperture:" + std::to_string(ap->nr) + ":" + std::to_string((int)std::ceil(rmax)) +
