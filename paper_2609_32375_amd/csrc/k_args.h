@@ -65,8 +65,10 @@ struct CatOut {
     uint32_t* flags;
 };
 
-void launch_mesh_stats(const FrameDesc* desc, int nframes, int total_meshes, int max_area, BkgArgs a, int cfg,
-                       hipStream_t s);
+// one: the descriptor of a one-frame call, passed with the launch (the kernel
+// stores it in the table for the launches that follow), or null
+void launch_mesh_stats(FrameDesc* desc, const FrameDesc* one, int nframes, int total_meshes, int max_area, BkgArgs a,
+                       int cfg, hipStream_t s);
 void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, int fsize, hipStream_t s);
 void launch_spline(const FrameDesc* desc, int nframes, int max_nx, int max_ny, hipStream_t s);
 bool filter_spline_fits(int max_nx, int max_ny, int fsize);

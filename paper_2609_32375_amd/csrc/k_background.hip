@@ -492,14 +492,17 @@ __device__ void bisect_pair(CountLe&& count_le, float lmn, float lmx, int r1, in
 template <int NT, int PPT>
 constexpr int mesh_waves_per_eu() { return 4; }
 
-template <int NT, int PPT>
+// ONE: a one-frame call, whose descriptor comes with the launch (d1);
+// workgroup 0 stores it in the table for the launches that follow
+template <int NT, int PPT, bool ONE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(mesh_waves_per_eu<NT, PPT>())))
-void k_mesh_stats(const FrameDesc* __restrict__ desc, int nframes, BkgArgs a) {
+void k_mesh_stats(FrameDesc* __restrict__ desc, FrameDesc d1, int nframes, BkgArgs a) {
     __shared__ MeshShared<kBins> sh;
     const int tid = threadIdx.x;
     const int gm = blockIdx.x;
-    const int f = frame_of(nframes, gm, [&](int i) { return desc[i].mesh_base; });
-    const FrameDesc d = desc[f];
+    if (ONE && gm == 0 && tid == 0) desc[0] = d1;
+    const int f = ONE ? 0 : frame_of(nframes, gm, [&](int i) { return desc[i].mesh_base; });
+    const FrameDesc d = ONE ? d1 : desc[f];
     const int lm = gm - d.mesh_base;
     const int mi = lm % d.nx, mj = lm / d.nx;
     const int x0 = mi * d.mw, y0 = mj * d.mh;
@@ -1226,16 +1229,23 @@ __global__ __launch_bounds__(kSplThreads) void k_spline_x(const FrameDesc* __res
 // launchers
 // cfg: 0 = automatic, 1 = 256 x 16, 2 = 512 x 16, 3 = 512 x 32, 4 = 1024 x 16
 // (threads x pixels per thread; the product must cover the largest mesh)
-void launch_mesh_stats(const FrameDesc* desc, int nframes, int total_meshes, int max_area, BkgArgs a, int cfg,
-                       hipStream_t s) {
+template <int NT, int PPT>
+static void launch_mesh_nt(FrameDesc* desc, const FrameDesc* one, int nframes, int total_meshes, BkgArgs a,
+                           hipStream_t s) {
+    if (one) k_mesh_stats<NT, PPT, true><<<total_meshes, NT, 0, s>>>(desc, *one, nframes, a);
+    else k_mesh_stats<NT, PPT, false><<<total_meshes, NT, 0, s>>>(desc, FrameDesc{}, nframes, a);
+}
+
+void launch_mesh_stats(FrameDesc* desc, const FrameDesc* one, int nframes, int total_meshes, int max_area, BkgArgs a,
+                       int cfg, hipStream_t s) {
     if (cfg == 0) cfg = (max_area <= 4096) ? 1 : (max_area <= 8192) ? 2 : 3;
     if (cfg == 1 && max_area > 4096) cfg = 3;
     if (cfg == 2 && max_area > 8192) cfg = 3;
     switch (cfg) {
-        case 1: k_mesh_stats<256, 16><<<total_meshes, 256, 0, s>>>(desc, nframes, a); break;
-        case 2: k_mesh_stats<512, 16><<<total_meshes, 512, 0, s>>>(desc, nframes, a); break;
-        case 4: k_mesh_stats<1024, 16><<<total_meshes, 1024, 0, s>>>(desc, nframes, a); break;
-        default: k_mesh_stats<512, 32><<<total_meshes, 512, 0, s>>>(desc, nframes, a); break;
+        case 1: launch_mesh_nt<256, 16>(desc, one, nframes, total_meshes, a, s); break;
+        case 2: launch_mesh_nt<512, 16>(desc, one, nframes, total_meshes, a, s); break;
+        case 4: launch_mesh_nt<1024, 16>(desc, one, nframes, total_meshes, a, s); break;
+        default: launch_mesh_nt<512, 32>(desc, one, nframes, total_meshes, a, s); break;
     }
 }
 

@@ -563,8 +563,12 @@ extern "C" gp_status gp_background(gp_ctx* ctx, const gp_frame* frames, int32_t 
     if ((st = check_ws(P, ws, ws_bytes)) != GP_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(ctx->device));
-    if ((st = upload_desc(frames, nframes, bp, P, bkg, ws, 0, nullptr, s)) != GP_OK) return st;
-    const FrameDesc* desc = (const FrameDesc*)((char*)ws + P.o_desc);
+    // a one-frame call passes its descriptor with the mesh-statistics launch,
+    // which stores it in the table for the launches that follow
+    const bool one = nframes == 1 && !(bp->flags & GP_BKG_GRID_GIVEN);
+    DescChunk tail{};
+    if ((st = upload_desc(frames, nframes, bp, P, bkg, ws, 0, nullptr, s, one ? &tail : nullptr)) != GP_OK) return st;
+    FrameDesc* desc = (FrameDesc*)((char*)ws + P.o_desc);
     if (!(bp->flags & GP_BKG_GRID_GIVEN)) {
         BkgArgs a{bp->clip_sigma, bp->crowd_tol, bp->mode_a, bp->mode_b, bp->max_iter, bp->filter_size};
         {
@@ -577,10 +581,11 @@ extern "C" gp_status gp_background(gp_ctx* ctx, const gp_frame* frames, int32_t 
             const int cfg = ctx->mesh_cfg ? ctx->mesh_cfg
                                           : choose(ctx, "mesh_stats:" + std::to_string(P.max_area), cands, 0, s,
                                                    [&](int k) {
-                                                       launch_mesh_stats(desc, nframes, (int)P.total_meshes,
+                                                       launch_mesh_stats(desc, one ? &tail.d[0] : nullptr,
+                                                                         nframes, (int)P.total_meshes,
                                                                          P.max_area, a, k, s);
                                                    });
-            launch_mesh_stats(desc, nframes, (int)P.total_meshes, P.max_area, a, cfg, s);
+            launch_mesh_stats(desc, one ? &tail.d[0] : nullptr, nframes, (int)P.total_meshes, P.max_area, a, cfg, s);
         }
         HIP_TRY(hipGetLastError());
     }
