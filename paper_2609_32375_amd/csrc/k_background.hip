@@ -9,12 +9,13 @@
 //                 a gather of the (few) pixels in the target bin.  All float
 //                 reductions run in a fixed order, so a mesh gives bit-identical
 //                 results wherever it is scheduled.
-//  k_spline_y_pcr, k_spline_x_pcr
-//                 grids of at most 63 knots per axis: the f x f median over the
-//                 mesh grid (truncated at the edges) and the natural cubic
-//                 splines through the mesh centres, one wavefront per spline,
-//                 solved in FP64 by parallel cyclic reduction across lanes and
-//                 turned into bicubic pieces per mesh cell.
+//  k_spline_y_pcr, k_spline_x_pcr (and the *_blk variants)
+//                 grids of at most 127 knots per axis: the f x f median over
+//                 the mesh grid (truncated at the edges) and the natural cubic
+//                 splines through the mesh centres, one wavefront per spline up
+//                 to 63 knots on the solved axis, one 128-thread workgroup up to
+//                 127, solved in FP64 by parallel cyclic reduction and turned
+//                 into bicubic pieces per mesh cell.
 //  k_grid_filter, k_spline_*
 //                 the same for larger grids: one thread per mesh for the
 //                 filter, one per spline for the FP64 Thomas solve.
@@ -1071,21 +1072,20 @@ __device__ __forceinline__ double pcr_second_derivs(int n, int lane, double t0, 
     return d / b;
 }
 
-// piece p (lane) of the spline through n knots, from lane values f, m and the
-// knot spacings; out[r] = coefficient of u^r, u = position - reference knot
-__device__ __forceinline__ void pcr_piece(int n, int lane, double f, double m, double h, double out[4]) {
+// piece p of the spline through n knots from the values at knots A =
+// clamp(p - 1, 0, n - 2) and A + 1 and their spacing hA; out[r] = coefficient
+// of u^r, u = position - reference knot
+__device__ __forceinline__ void spline_piece(int n, int p, double fA, double fB, double mA, double mB, double hA,
+                                             double out[4]) {
     constexpr double kSixth = 1.0 / 6.0;
-    const int A = min(max(lane - 1, 0), max(n - 2, 0));
-    const double fA = __shfl(f, A), fB = __shfl(f, A + 1), mA = __shfl(m, A), mB = __shfl(m, A + 1);
-    const double hA = __shfl(h, A);
     const double ih = 1.0 / hA;
     out[0] = out[1] = out[2] = out[3] = 0.0;
     if (n == 1) {
         out[0] = fA;
-    } else if (lane == 0) {
+    } else if (p == 0) {
         out[0] = fA;
         out[1] = (fB - fA) * ih - hA * (2.0 * mA + mB) * kSixth;
-    } else if (lane == n) {
+    } else if (p == n) {
         out[0] = fB;
         out[1] = (fB - fA) * ih + hA * (mA + 2.0 * mB) * kSixth;
     } else {
@@ -1093,6 +1093,128 @@ __device__ __forceinline__ void pcr_piece(int n, int lane, double f, double m, d
         out[1] = (fB - fA) * ih - hA * (2.0 * mA + mB) * kSixth;
         out[2] = 0.5 * mA;
         out[3] = (mB - mA) * ih * kSixth;
+    }
+}
+
+// piece p = lane, the values of knots A and A + 1 fetched by lane shuffles
+__device__ __forceinline__ void pcr_piece(int n, int lane, double f, double m, double h, double out[4]) {
+    const int A = min(max(lane - 1, 0), max(n - 2, 0));
+    const double fA = __shfl(f, A), fB = __shfl(f, A + 1), mA = __shfl(m, A), mB = __shfl(m, A + 1);
+    const double hA = __shfl(h, A);
+    spline_piece(n, lane, fA, fB, mA, mB, hA, out);
+}
+
+// Grids of 64 to kPcrBlkMax knots on the solved axis: the same reduction over
+// a workgroup of 128 threads (thread = knot), seven rounds, the rows exchanged
+// through LDS (s*: 128 doubles each)
+constexpr int kPcrBlkMax = 127;
+
+__device__ double pcr_second_derivs_blk(int n, int k, double t0, double t1, double t2, double fm, double f,
+                                        double fp, double* sa, double* sc, double* sd, double* sr) {
+    const bool row = k >= 1 && k <= n - 2;
+    const double h0 = t1 - t0, h1 = t2 - t1;
+    double a = row ? h0 : 0.0, b = row ? 2.0 * (h0 + h1) : 1.0, c = row ? h1 : 0.0;
+    double d = row ? 6.0 * ((fp - f) / h1 - (f - fm) / h0) : 0.0;
+    for (int st = 1; st < 128; st <<= 1) {
+        sa[k] = a;
+        sc[k] = c;
+        sd[k] = d;
+        sr[k] = 1.0 / b;
+        __syncthreads();
+        const bool okl = k >= st, okh = k + st < 128;
+        const double al = okl ? sa[k - st] : 0.0, cl = okl ? sc[k - st] : 0.0, dl = okl ? sd[k - st] : 0.0;
+        const double rl = okl ? sr[k - st] : 1.0;
+        const double ah = okh ? sa[k + st] : 0.0, ch = okh ? sc[k + st] : 0.0, dh = okh ? sd[k + st] : 0.0;
+        const double rh = okh ? sr[k + st] : 1.0;
+        __syncthreads();
+        const double alpha = -a * rl, gamma = -c * rh;
+        b = b + alpha * cl + gamma * ah;
+        d = d + alpha * dl + gamma * dh;
+        a = alpha * al;
+        c = gamma * ch;
+    }
+    return d / b;
+}
+
+// y splines (and the mesh filter when F > 0), one workgroup per (quantity,
+// mesh column); blockIdx.y = frame
+template <int F>
+__global__ __launch_bounds__(128) void k_spline_y_pcr_blk(const FrameDesc* __restrict__ desc) {
+    __shared__ double sa[128], sc[128], sd[128], sr[128];
+    const FrameDesc& d = desc[blockIdx.y];
+    const int nx = d.nx, ny = d.ny, t = threadIdx.x;
+    const int g = blockIdx.x;
+    if (g >= 2 * nx) return;
+    const int q = g / nx, i = g - q * nx;
+    const int k = min(t, ny - 1);
+    double f;
+    if constexpr (F > 0) {
+        constexpr int hh = F / 2;
+        const gdouble_t* raw = (const gdouble_t*)(q ? d.rms_raw : d.back_raw);
+        double w[F * F];
+        int cnt = 0;
+#pragma unroll
+        for (int e = 0; e < F * F; ++e) {
+            const int b = k - hh + e / F, c = i - hh + e % F;
+            const bool in = b >= 0 && b < ny && c >= 0 && c < nx;
+            w[e] = in ? raw[b * nx + c] : INFINITY;
+            cnt += in ? 1 : 0;
+        }
+        f = median_regs(w, cnt);
+        if (t < ny) (q ? d.rms : d.back)[k * nx + i] = f;
+    } else {
+        f = ((const gdouble_t*)(q ? d.rms : d.back))[k * nx + i];
+    }
+    const double t0 = knot_at(max(k - 1, 0), d.H, d.mh), t1 = knot_at(k, d.H, d.mh);
+    const double t2 = knot_at(min(k + 1, ny - 1), d.H, d.mh);
+    sd[t] = f;
+    __syncthreads();
+    const double fm = sd[max(t - 1, 0)], fp = sd[min(t + 1, 127)];
+    __syncthreads();
+    const double m = pcr_second_derivs_blk(ny, t, t0, t1, t2, fm, f, fp, sa, sc, sd, sr);
+    sa[t] = f;
+    sc[t] = m;
+    sd[t] = t2 - t1;
+    __syncthreads();
+    if (t <= ny) {
+        const int A = min(max(t - 1, 0), max(ny - 2, 0));
+        double cf[4];
+        spline_piece(ny, t, sa[A], sa[A + 1], sc[A], sc[A + 1], sd[A], cf);
+        double* o = d.ycoef + (((size_t)q * (ny + 1) + t) * nx + i) * 4;
+        o[0] = cf[0];
+        o[1] = cf[1];
+        o[2] = cf[2];
+        o[3] = cf[3];
+    }
+}
+
+// x splines, one workgroup per (quantity, y piece, power of u); blockIdx.y = frame
+__global__ __launch_bounds__(128) void k_spline_x_pcr_blk(const FrameDesc* __restrict__ desc) {
+    __shared__ double sa[128], sc[128], sd[128], sr[128];
+    const FrameDesc& d = desc[blockIdx.y];
+    const int nx = d.nx, ny = d.ny, t = threadIdx.x;
+    const int g = blockIdx.x;
+    if (g >= 8 * (ny + 1)) return;
+    const int b = g >> 2, r = g & 3;   // b = q (ny + 1) + jy
+    const int k = min(t, nx - 1);
+    const double f = ((const gdouble_t*)d.ycoef)[((size_t)b * nx + k) * 4 + r];
+    const double t0 = knot_at(max(k - 1, 0), d.W, d.mw), t1 = knot_at(k, d.W, d.mw);
+    const double t2 = knot_at(min(k + 1, nx - 1), d.W, d.mw);
+    sd[t] = f;
+    __syncthreads();
+    const double fm = sd[max(t - 1, 0)], fp = sd[min(t + 1, 127)];
+    __syncthreads();
+    const double m = pcr_second_derivs_blk(nx, t, t0, t1, t2, fm, f, fp, sa, sc, sd, sr);
+    sa[t] = f;
+    sc[t] = m;
+    sd[t] = t2 - t1;
+    __syncthreads();
+    if (t <= nx) {
+        const int A = min(max(t - 1, 0), max(nx - 2, 0));
+        double cf[4];
+        spline_piece(nx, t, sa[A], sa[A + 1], sc[A], sc[A + 1], sd[A], cf);
+        double* o = d.coef + ((size_t)b * (nx + 1) + t) * 16;
+        for (int pp = 0; pp < 4; ++pp) o[pp * 4 + r] = cf[pp];
     }
 }
 
@@ -1263,18 +1385,31 @@ void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, in
 // in two launches, for grids of at most kPcrMax knots per axis and filters of
 // at most 5 x 5 (filter_spline_fits)
 bool filter_spline_fits(int max_nx, int max_ny, int fsize) {
-    return max_nx <= kPcrMax && max_ny <= kPcrMax && fsize <= 5;
+    return max_nx <= kPcrBlkMax && max_ny <= kPcrBlkMax && fsize <= 5;
 }
 
+// each axis by its own knot count: up to kPcrMax one wavefront per spline,
+// up to kPcrBlkMax one 128-thread workgroup
 void launch_filter_spline(const FrameDesc* desc, int nframes, int max_nx, int max_ny, int fsize, hipStream_t s) {
-    const dim3 gy((2 * max_nx + 3) / 4, nframes);
-    switch (fsize) {
-        case 0: k_spline_y_pcr<0><<<gy, 256, 0, s>>>(desc); break;
-        case 1: k_spline_y_pcr<1><<<gy, 256, 0, s>>>(desc); break;
-        case 3: k_spline_y_pcr<3><<<gy, 256, 0, s>>>(desc); break;
-        default: k_spline_y_pcr<5><<<gy, 256, 0, s>>>(desc); break;
+    if (max_ny <= kPcrMax) {
+        const dim3 gy((2 * max_nx + 3) / 4, nframes);
+        switch (fsize) {
+            case 0: k_spline_y_pcr<0><<<gy, 256, 0, s>>>(desc); break;
+            case 1: k_spline_y_pcr<1><<<gy, 256, 0, s>>>(desc); break;
+            case 3: k_spline_y_pcr<3><<<gy, 256, 0, s>>>(desc); break;
+            default: k_spline_y_pcr<5><<<gy, 256, 0, s>>>(desc); break;
+        }
+    } else {
+        const dim3 gy(2 * max_nx, nframes);
+        switch (fsize) {
+            case 0: k_spline_y_pcr_blk<0><<<gy, 128, 0, s>>>(desc); break;
+            case 1: k_spline_y_pcr_blk<1><<<gy, 128, 0, s>>>(desc); break;
+            case 3: k_spline_y_pcr_blk<3><<<gy, 128, 0, s>>>(desc); break;
+            default: k_spline_y_pcr_blk<5><<<gy, 128, 0, s>>>(desc); break;
+        }
     }
-    k_spline_x_pcr<<<dim3(2 * (max_ny + 1), nframes), 256, 0, s>>>(desc);
+    if (max_nx <= kPcrMax) k_spline_x_pcr<<<dim3(2 * (max_ny + 1), nframes), 256, 0, s>>>(desc);
+    else k_spline_x_pcr_blk<<<dim3(8 * (max_ny + 1), nframes), 128, 0, s>>>(desc);
 }
 
 void launch_spline(const FrameDesc* desc, int nframes, int max_nx, int max_ny, hipStream_t s) {

@@ -140,11 +140,11 @@ def test_mesh_statistics_match_oracle(P, case):
 
 
 @pytest.mark.parametrize("f", [1, 3, 5, 7])
-@pytest.mark.parametrize("W", [700, 2100])
+@pytest.mark.parametrize("W", [700, 4200])
 def test_grid_filter_every_size(P, f, W):
     # sizes 1-5 keep the window in registers, 7 in LDS; ragged grid edges.
-    # 22 x 14 meshes: sizes 1-5 run inside the y-spline launch; 66 x 14: the
-    # separate filter kernel
+    # 22 x 14 meshes: sizes 1-5 run inside the y-spline launch; 132 x 14 (more
+    # than 127 knots along x) and size 7: the separate filter kernel
     fr = make_frame("c1", seed=5, W=W, H=430, dtype="f32")
     p = _params("c1", mesh_w=32, mesh_h=32, mesh_filter=f)
     ph = P.Photometry([_dev(fr.image)], p, p.kernel(), capacity=64)
@@ -155,13 +155,15 @@ def test_grid_filter_every_size(P, f, W):
     ph.close()
 
 
-# grids of at most 63 knots per axis take the lane-parallel (cyclic reduction)
-# splines: 5x4, 5x5, 1x1, 8x3, 2x63, 63x3 and 63x63 with ragged last meshes;
-# larger grids the Thomas kernels, with up to 100 knots in LDS (64x3, 100x2)
-# and longer axes on global scratch (107 along x, 107 along y)
+# the splines by knots on the solved axis: up to 63 one wavefront per spline
+# (5x4, 5x5, 1x1, 8x3, 2x63, 63x3, 63x63 with ragged last meshes), 64 to 127
+# one workgroup (64x3, 100x2, 107x3, 3x107, 127x127), above 127 the Thomas
+# kernels, with up to 100 knots in LDS and longer axes on global scratch
+# (132x3: x on global scratch, y in LDS; 3x132: the converse)
 @pytest.mark.parametrize("shape", [(300, 200, 64, 64), (130, 77, 32, 16), (50, 20, 64, 64), (1000, 40, 128, 16),
                                    (100, 2000, 64, 32), (1008, 40, 16, 16), (1003, 999, 16, 16),
-                                   (1024, 40, 16, 16), (1600, 24, 16, 16), (1700, 40, 16, 16), (40, 1700, 16, 16)])
+                                   (1024, 40, 16, 16), (1600, 24, 16, 16), (1700, 40, 16, 16), (40, 1700, 16, 16),
+                                   (2025, 2030, 16, 16), (2100, 40, 16, 16), (40, 2100, 16, 16)])
 def test_background_maps_match_oracle_spline(P, shape):
     W, H, mw, mh = shape
     _say("map case", shape)
