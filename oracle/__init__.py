@@ -50,6 +50,8 @@ def lib():
         lp = C.POINTER(C.c_int64)
         up = C.POINTER(C.c_uint32)
         L.or_mesh_one.argtypes = [dp, C.c_long, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, dp]
+        L.or_mesh_one_policy.argtypes = [dp, C.c_long, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
+                                         C.c_double, C.c_double, C.c_int, dp]
         L.or_mesh_stats.argtypes = [dp, C.c_long, C.c_long, C.c_long, C.c_int, C.c_int, C.c_double,
                                     C.c_double, C.c_double, C.c_double, C.c_int, dp]
         L.or_median_filter.argtypes = [dp, C.c_long, C.c_long, C.c_int, dp]
@@ -66,7 +68,7 @@ def lib():
         L.or_overlap.restype = C.c_double
         L.or_aperture.argtypes = [dp, dp, C.c_long, C.c_long, dp, dp, C.c_long, dp, C.c_int, C.c_double,
                                   C.c_double, C.c_double, C.c_int, dp, dp, dp, dp, up]
-        for f in ("or_mesh_one", "or_mesh_stats", "or_median_filter", "or_grid_eval", "or_grid_map",
+        for f in ("or_mesh_one", "or_mesh_one_policy", "or_mesh_stats", "or_median_filter", "or_grid_eval", "or_grid_map",
                   "or_filter", "or_threshold_label", "or_measure", "or_aperture"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -97,6 +99,37 @@ def mesh_one(values, clip=3.0, crowd=0.2, mode_a=2.5, mode_b=1.5, max_iter=100):
     out = np.zeros(8)
     _check(lib().or_mesh_one(_p(v), v.size, clip, crowd, mode_a, mode_b, max_iter, _p(out)), "mesh_one")
     return dict(zip(MESH_FIELDS, out))
+
+
+# Branch policies for decisions inside the rounding band (the reading that such
+# a decision may go either way): low-side and high-side clip decisions taken as
+# computed (0), kept (1) or dropped (2); bit 4 flips the estimator decision.
+MESH_POLICIES = tuple(lo | (hi << 2) | fl for fl in (0, 16) for hi in (0, 1, 2) for lo in (0, 1, 2))
+
+
+def mesh_one_policy(values, policy, eps_clip, eps_mode, clip=3.0, crowd=0.2, mode_a=2.5, mode_b=1.5,
+                    max_iter=100):
+    """Mesh statistics with the decisions whose relative margins fall below
+    eps_clip / eps_mode taken by `policy` (see MESH_POLICIES)."""
+    v = _f64(np.ravel(values))
+    out = np.zeros(8)
+    _check(lib().or_mesh_one_policy(_p(v), v.size, clip, crowd, mode_a, mode_b, max_iter, eps_clip, eps_mode,
+                                    int(policy), _p(out)), "mesh_one_policy")
+    return dict(zip(MESH_FIELDS, out))
+
+
+def mesh_variants(values, eps_clip, eps_mode, clip=3.0, crowd=0.2, mode_a=2.5, mode_b=1.5, max_iter=100):
+    """Every distinct result of the mesh statistics over the branch policies:
+    the plain result first, then the results with the ambiguous decisions
+    taken the other way."""
+    out, seen = [], set()
+    for pol in MESH_POLICIES:
+        st = mesh_one_policy(values, pol, eps_clip, eps_mode, clip, crowd, mode_a, mode_b, max_iter)
+        key = (st["back"], st["rms"], st["iters"])
+        if key not in seen:
+            seen.add(key)
+            out.append(st)
+    return out
 
 
 def mesh_stats(img, mesh_w, mesh_h, clip=3.0, crowd=0.2, mode_a=2.5, mode_b=1.5, max_iter=100):

@@ -97,9 +97,18 @@ static void mean_std(const double* s, long n, double* mean, double* sd) {
  * The margins report how close the clip and estimator decisions came to their
  * boundaries (relative to clip*sigma and sigma0): where they are below the
  * rounding of a single-precision evaluation both outcomes are legitimate.
+ *
+ * Branch policy for those decisions (the reading that a decision within the
+ * rounding band may go either way, so the other branch is an equally valid
+ * result): a clip decision whose relative margin is below eps_clip is taken
+ * as computed (policy field 0), forced to keep the value (1) or forced to
+ * drop it (2); the low side (values below the median) is bits 0-1 of
+ * `policy`, the high side bits 2-3.  Bit 4 flips the estimator decision when
+ * its relative margin is below eps_mode.  policy = 0 is the plain method.
  */
-int or_mesh_one(const double* vals, long n, double clip, double crowd, double mode_a,
-                double mode_b, int max_iter, double* out) {
+static int mesh_one_policy(const double* vals, long n, double clip, double crowd, double mode_a,
+                           double mode_b, int max_iter, double eps_clip, double eps_mode, int policy,
+                           double* out) {
     if (n <= 0 || !vals || !out) return OR_EINVAL;
     double* S = (double*)malloc(sizeof(double) * (size_t)n);
     double* T = (double*)malloc(sizeof(double) * (size_t)n);
@@ -128,6 +137,7 @@ int or_mesh_one(const double* vals, long n, double clip, double crowd, double mo
         free(T);
         return OR_OK;
     }
+    const int pol_lo = policy & 3, pol_hi = (policy >> 2) & 3;
     long ns = n;
     int iters = 0;
     for (int it = 0; it < max_iter; ++it) {
@@ -138,11 +148,14 @@ int or_mesh_one(const double* vals, long n, double clip, double crowd, double mo
         long nk = 0;
         for (long i = 0; i < ns; ++i) {
             double d = fabs(S[i] - med);
+            int keep = d <= lim;
             if (lim > 0.0) {
                 double mg = fabs(d - lim) / lim;
                 if (mg < margin_clip) margin_clip = mg;
+                int pol = (S[i] < med) ? pol_lo : pol_hi;
+                if (mg < eps_clip && pol != 0) keep = (pol == 1);
             }
-            if (d <= lim) T[nk++] = S[i];
+            if (keep) T[nk++] = S[i];
         }
         iters++;
         if (nk == ns || nk == 0) break;
@@ -156,7 +169,9 @@ int or_mesh_one(const double* vals, long n, double clip, double crowd, double mo
     mean_std(S, ns, &mean, &sig);
     double dsig = fabs(sig - sig0);
     margin_mode = fabs(dsig - crowd * sig0) / sig0;
-    double back = (dsig < crowd * sig0) ? mean : (mode_a * med - mode_b * mean);
+    int use_mean = dsig < crowd * sig0;
+    if ((policy & 16) && margin_mode < eps_mode) use_mean = !use_mean;
+    double back = use_mean ? mean : (mode_a * med - mode_b * mean);
     out[0] = back;
     out[1] = sig;
     out[2] = med;
@@ -168,6 +183,20 @@ int or_mesh_one(const double* vals, long n, double clip, double crowd, double mo
     free(S);
     free(T);
     return OR_OK;
+}
+
+int or_mesh_one(const double* vals, long n, double clip, double crowd, double mode_a,
+                double mode_b, int max_iter, double* out) {
+    return mesh_one_policy(vals, n, clip, crowd, mode_a, mode_b, max_iter, 0.0, 0.0, 0, out);
+}
+
+/* The same statistics with the decisions inside the rounding band taken by
+ * `policy` (see above). */
+int or_mesh_one_policy(const double* vals, long n, double clip, double crowd, double mode_a,
+                       double mode_b, int max_iter, double eps_clip, double eps_mode, int policy,
+                       double* out) {
+    if (policy < 0 || policy > 31 || (policy & 3) == 3 || ((policy >> 2) & 3) == 3) return OR_EINVAL;
+    return mesh_one_policy(vals, n, clip, crowd, mode_a, mode_b, max_iter, eps_clip, eps_mode, policy, out);
 }
 
 /* number of meshes along one axis */

@@ -292,6 +292,67 @@ def test_mesh_against_numpy_restatement():
         assert st["rms"] == pytest.approx(s, rel=1e-12, abs=1e-12)
 
 
+def _brute_mesh_policy(v, eps, lo, hi, flip, clip=3.0, crowd=0.2, a=2.5, b=1.5, max_iter=100):
+    """numpy re-statement of the clip loop in which every decision whose
+    relative margin |(|v - med| - k sigma)| / (k sigma) is below eps is forced:
+    0 = as computed, 1 = keep, 2 = drop (lo: values below the median, hi: the
+    rest); flip: the estimator decision is flipped when its margin is below eps."""
+    S = np.sort(np.asarray(v, float))
+    s0 = np.std(S)
+    for _ in range(max_iter):
+        med = np.median(S)
+        lim = clip * np.std(S)
+        d = np.abs(S - med)
+        keep = d <= lim
+        amb = np.abs(d - lim) / lim < eps
+        pol = np.where(S < med, lo, hi)
+        keep = np.where(amb & (pol == 1), True, np.where(amb & (pol == 2), False, keep))
+        if keep.all() or not keep.any():
+            break
+        S = S[keep]
+    med, mean, sd = np.median(S), np.mean(S), np.std(S)
+    use_mean = abs(sd - s0) < crowd * s0
+    if flip and abs(abs(sd - s0) - crowd * s0) / s0 < eps:
+        use_mean = not use_mean
+    return (mean if use_mean else a * med - b * mean), sd
+
+
+def test_mesh_branch_policy_against_numpy_restatement():
+    # a wide band (5% of the clip limit) makes many decisions ambiguous, so
+    # every forced branch changes the result; each policy must equal the
+    # numpy re-statement of the same forcing, and policy 0 the plain method
+    rng = np.random.default_rng(9)
+    eps = 0.05
+    changed = 0
+    for trial in range(12):
+        n = int(rng.integers(200, 3000))
+        v = rng.normal(500, 20, n)
+        v[: n // 8] += rng.uniform(50, 3000, n // 8)
+        if trial % 3 == 0:
+            v = np.round(v)
+        plain = oracle.mesh_one(v)
+        st0 = oracle.mesh_one_policy(v, 0, eps, eps)
+        assert (st0["back"], st0["rms"], st0["iters"]) == (plain["back"], plain["rms"], plain["iters"])
+        distinct = set()
+        for pol in oracle.MESH_POLICIES:
+            lo, hi, flip = pol & 3, (pol >> 2) & 3, bool(pol & 16)
+            st = oracle.mesh_one_policy(v, pol, eps, eps)
+            bb, ss = _brute_mesh_policy(v, eps, lo, hi, flip)
+            assert st["back"] == pytest.approx(bb, rel=1e-12, abs=1e-9), (trial, pol)
+            assert st["rms"] == pytest.approx(ss, rel=1e-12, abs=1e-12), (trial, pol)
+            distinct.add(round(st["back"], 9))
+        changed += len(distinct) > 1
+    assert changed >= 8, changed
+    # with a band of zero width no policy changes anything
+    v = rng.normal(0, 1, 1000)
+    ref = oracle.mesh_one(v)
+    for pol in oracle.MESH_POLICIES:
+        st = oracle.mesh_one_policy(v, pol, 0.0, 0.0)
+        assert (st["back"], st["rms"]) == (ref["back"], ref["rms"])
+    with pytest.raises(RuntimeError):
+        oracle.mesh_one_policy(v, 3, 0.1, 0.1)
+
+
 def test_mesh_gaussian_sky_statistics():
     rng = np.random.default_rng(2)
     c, sn = 1000.0, 10.0
