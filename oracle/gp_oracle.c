@@ -630,10 +630,22 @@ static double Gcorner(double x, double y, double r) {
     return sx * sy * a;
 }
 
-/* exact area of disk(c, r) intersected with [x0, x1] x [y0, y1] */
+/* exact area of disk(c, r) intersected with [x0, x1] x [y0, y1].  A rectangle
+ * whose nearest point lies on or outside the circle shares no area with the
+ * disk, and one whose farthest corner lies on or inside it lies wholly in the
+ * disk: those two cases are returned as exactly 0 and the rectangle's area
+ * (the corner-integral sum below would leave a rounding residue of a few
+ * units of r^2 * 2^-53 instead). */
 double or_overlap(double x0, double x1, double y0, double y1, double cx, double cy, double r) {
     if (!(r > 0.0)) return 0.0;
+    const double rect = (x1 - x0) * (y1 - y0);
     x0 -= cx; x1 -= cx; y0 -= cy; y1 -= cy;
+    double nx = (x0 > 0.0) ? x0 : ((x1 < 0.0) ? -x1 : 0.0);
+    double ny = (y0 > 0.0) ? y0 : ((y1 < 0.0) ? -y1 : 0.0);
+    if (nx * nx + ny * ny >= r * r) return 0.0;
+    double fx = (fabs(x0) > fabs(x1)) ? fabs(x0) : fabs(x1);
+    double fy = (fabs(y0) > fabs(y1)) ? fabs(y0) : fabs(y1);
+    if (fx * fx + fy * fy <= r * r) return rect;
     return Gcorner(x1, y1, r) - Gcorner(x0, y1, r) - Gcorner(x1, y0, r) + Gcorner(x0, y0, r);
 }
 

@@ -65,6 +65,30 @@ def test_overlap_special_cases():
     assert oracle.overlap(-.5, .5, -.5, .5, 0, 0, 0.0) == 0.0
 
 
+def test_overlap_exact_outside_and_inside():
+    # a pixel whose nearest point is just outside the circle shares no area,
+    # and one whose farthest corner is just inside lies wholly in the disk,
+    # exactly (no rounding residue of the corner integrals)
+    rng = np.random.default_rng(8)
+    for _ in range(400):
+        cx, cy = rng.uniform(-0.5, 0.5, 2)
+        px, py = (int(v) for v in rng.integers(-15, 16, 2))
+        x0, x1, y0, y1 = px - .5, px + .5, py - .5, py + .5
+        nx = max(x0 - cx, cx - x1, 0.0)
+        ny = max(y0 - cy, cy - y1, 0.0)
+        fx = max(abs(x0 - cx), abs(x1 - cx))
+        fy = max(abs(y0 - cy), abs(y1 - cy))
+        gap = 10.0 ** rng.uniform(-9, -2)
+        near, far = math.hypot(nx, ny), math.hypot(fx, fy)
+        if near > 2 * gap:
+            assert oracle.overlap(x0, x1, y0, y1, cx, cy, near * (1 - gap)) == 0.0
+        assert oracle.overlap(x0, x1, y0, y1, cx, cy, far * (1 + gap)) == 1.0
+    # a circle ending just beyond the last row contributes nothing to the frame
+    M = np.ones((50, 40))
+    o = oracle.aperture(M, None, [20.3], [52.5 + 1e-6], [3.0], 5.0, 8.0, want_err=False)
+    assert o["area"][0, 0] == 0.0 and o["flux"][0, 0] == 0.0
+
+
 def test_overlap_symmetries_and_quadrature():
     rng = np.random.default_rng(7)
     for _ in range(300):
