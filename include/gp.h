@@ -123,8 +123,11 @@ typedef struct gp_bkg_layout {
 /* Detection parameters.  kernel: HOST pointer to kh x kw floats, row-major,
  * both odd and <= 15; it is normalised to unit sum by the library (used as
  * given when its sum is zero) and applied as a correlation with half-sample
- * reflected borders.  A rank-one kernel (e.g. a circular Gaussian) is applied
- * as two 1-D passes.  Pixels with F > thresh * R form the mask. */
+ * reflected borders.  A kernel whose every tap equals the product of its row
+ * and column through the peak tap to within 4 float32 rounding units of the
+ * tap (a rank-one kernel such as a circular Gaussian) is applied as two 1-D
+ * passes; any other kernel is applied densely.  Pixels with F > thresh * R
+ * form the mask. */
 typedef struct gp_det_params {
     const float* kernel;
     int32_t kw, kh;

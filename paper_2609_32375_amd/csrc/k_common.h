@@ -54,21 +54,42 @@ struct DescChunk {
     FrameDesc d[kDescChunk];
 };
 
-// Per-component partial record (one per connected piece inside one tile;
-// after merging, the root record holds the whole component).  Sums are taken
-// about the reference (x0, y0) = origin of the tile that produced the piece:
+// Per-component partial record (one per connected piece inside one tile).
+// Sums are taken about the reference (x0, y0) = origin of the tile that
+// produced the piece:
 //   s[0..5]  = sum M, M dx, M dy, M dx^2, M dy^2, M dx dy
 //   s[6..11] = the same with unit weights (n, dx, dy, ...)
+// Every term added into s[] or acc[] is first rounded to a multiple of a power
+// of two (quantum) chosen from exact integer bounds of the sum, so that every
+// partial sum is an exact multiple of the quantum within the double range and
+// the result does not depend on the order of the additions.  After the merge
+// the component's root record holds in acc[] the sums of all its pieces about
+// the root's tile origin, in cnpix its pixel count and in camax its max |M|.
 struct CompRec {
     double s[12];
-    int32_t xmin, xmax, ymin, ymax;  // frame coordinates
+    double acc[12];
+    int32_t xmin, xmax, ymin, ymax;  // frame coordinates (the component's, at the root)
     uint32_t pmin;                   // raster index of the first pixel in the frame
     uint32_t peak;                   // order-preserving bits of max M
     uint32_t flags;
     int32_t frame;
     int32_t x0, y0;
-    int32_t pad[2];
+    uint32_t amax;                   // float bits of the piece's max |M|
+    uint32_t camax;                  // float bits of the component's max |M| (root)
+    int32_t cnpix;                   // pixels of the component (root)
+    int32_t pad[3];
 };
+
+// Quantum of a sum bounded by `bound` (sum of |terms| <= bound): 2^e with
+// bound < 2^(e + 51), so that the sum of the rounded terms stays an exact
+// multiple of 2^e below 2^53 2^e.  Zero bound: every term is zero.
+__device__ __forceinline__ int quantum_exp(double bound) {
+    if (!(bound > 0.0)) return 0;
+    int ex;
+    (void)frexp(bound, &ex);   // bound < 2^ex
+    return ex - 51;
+}
+__device__ __forceinline__ double quantize(double v, int e) { return ldexp(rint(ldexp(v, -e)), e); }
 
 struct TileInfo {
     int32_t base;   // first record id (-1 when the tile holds no component)

@@ -32,15 +32,17 @@
 
 namespace gpk {
 
-// A piece's sums while its tile is labelled: the M-weighted sums in FP64 and
-// the pixel-count sums (n, x n, y-sums, ...) as exact 32-bit integers (a tile
-// holds 4096 pixels with offsets below 64, so every count sum is < 2^24).
+// A piece's sums while its tile is labelled: the M-weighted sums in FP64
+// (quantised terms, exact additions) and the pixel-count sums (n, x n,
+// y-sums, ...) as exact 32-bit integers (a tile holds 4096 pixels with offsets
+// below 64, so every count sum is < 2^24).
 struct LocalRec {
     double s[6];
     int32_t c[6];
     int32_t xmin, xmax, ymin, ymax;
     uint32_t peak, flags;
-    int32_t rootpix, pad;
+    int32_t rootpix;
+    uint32_t amax;   // float bits of max |M| (non-negative: ordered as integers)
 };
 
 // LDS regions are reused phase by phase (REG: region width and height, the
@@ -570,9 +572,13 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
             R.xmax = R.ymax = -1;
             R.peak = 0u;
             R.flags = 0u;
+            R.amax = 0u;
         } else {
             CompRec& R = wk.recs[base + c];
-            for (int z = 0; z < 12; ++z) R.s[z] = 0.0;
+            for (int z = 0; z < 12; ++z) {
+                R.s[z] = 0.0;
+                R.acc[z] = 0.0;
+            }
             R.xmin = R.ymin = 0x7fffffff;
             R.xmax = R.ymax = -1;
             R.peak = 0u;
@@ -580,6 +586,9 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
             R.frame = f;
             R.x0 = x0;
             R.y0 = y0;
+            R.amax = 0u;
+            R.camax = 0u;
+            R.cnpix = 0;
         }
     }
     // border labels for the merge, and the per-pixel piece ids
@@ -610,54 +619,51 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
             else wk.recs[base + c].pmin = pm;
         }
     }
-    // 6. moments: column runs, compensated, flushed into the piece records
-    //    (a wavefront whose rows hold no detection has none to add)
-    if (__ballot(mbits != 0u) != 0ull) {
+    // 6. moments, in two passes over the lane's column runs.  (a) Each run
+    //    adds its exact integer quantities into its piece: pixel-count sums,
+    //    bounding box, peak, max |M|, flags.  (b) Once every run has done so,
+    //    each run adds its M-weighted sums (compensated along the run), every
+    //    term rounded to the piece's quantum for that sum (from its pixel count
+    //    and max |M|): the additions are exact, so the piece's sums do not
+    //    depend on the order in which the runs arrive.
+    //    (A wavefront whose rows hold no detection has no run.)
+    const bool wave_has = __ballot(mbits != 0u) != 0ull;
+    const int gx = x0 + lane;
+    if (wave_has) {
         const float sat = pa->sat;
         const bool has_sat = sat < INFINITY;
-        const int gx = x0 + lane;
-        RunAcc<Real> run;
-        run.reset();
         int cur = -1, rcnt = 0, rdy = 0, rdy2 = 0, ry0 = 0, ry1 = 0;
-        float rpk = -INFINITY;
+        float rpk = -INFINITY, ram = 0.0f;
         uint32_t rfl = 0u;
         auto flush = [&]() {
-            const bool loc = cur < kLocalRecs;
-            const double dxd = (double)lane;
-            const double S = run.s(), T = run.t(), U = run.u();
-            const double add[6] = {S, dxd * S, T, dxd * dxd * S, U, dxd * T};
             const int addc[6] = {rcnt, lane * rcnt, rdy, lane * lane * rcnt, rdy2, lane * rdy};
-            if (loc) {
+            if (cur < kLocalRecs) {
                 LocalRec& R = sh.u2.rec[cur];
 #pragma unroll
-                for (int z = 0; z < 6; ++z) {
-                    atomicAdd(&R.s[z], add[z]);
-                    atomicAdd(&R.c[z], addc[z]);
-                }
+                for (int z = 0; z < 6; ++z) atomicAdd(&R.c[z], addc[z]);
                 atomicMin(&R.xmin, gx);
                 atomicMax(&R.xmax, gx);
                 atomicMin(&R.ymin, y0 + ry0);
                 atomicMax(&R.ymax, y0 + ry1);
                 atomicMax(&R.peak, f2ord(rpk));
+                atomicMax(&R.amax, __float_as_uint(ram));
                 if (rfl) atomicOr(&R.flags, rfl);
             } else {
                 CompRec& R = wk.recs[base + cur];
 #pragma unroll
-                for (int z = 0; z < 6; ++z) {
-                    unsafeAtomicAdd(&R.s[z], add[z]);
-                    unsafeAtomicAdd(&R.s[6 + z], (double)addc[z]);
-                }
+                for (int z = 0; z < 6; ++z) unsafeAtomicAdd(&R.s[6 + z], (double)addc[z]);
                 atomicMin(&R.xmin, gx);
                 atomicMax(&R.xmax, gx);
                 atomicMin(&R.ymin, y0 + ry0);
                 atomicMax(&R.ymax, y0 + ry1);
                 atomicMax(&R.peak, f2ord(rpk));
+                atomicMax(&R.amax, __float_as_uint(ram));
                 if (rfl) atomicOr(&R.flags, rfl);
             }
-            run.reset();
             cur = -1;
             rcnt = rdy = rdy2 = 0;
             rpk = -INFINITY;
+            ram = 0.0f;
             rfl = 0u;
         };
 #pragma unroll
@@ -672,12 +678,62 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
                     ry0 = ly;
                 }
                 ry1 = ly;
-                run.add(Mo[k], (Real)ly);
                 rcnt += 1;
                 rdy += ly;
                 rdy2 += ly * ly;
                 rpk = fmaxf(rpk, (float)Mo[k]);
+                // (float)|M| of an FP64 M may round down by half an ulp; the
+                // quantum keeps a factor two of headroom over the bound
+                ram = fmaxf(ram, fabsf((float)Mo[k]));
                 if (has_sat && load_px(d, gx, y0 + ly) >= sat) rfl |= kFlagSat;
+            }
+        }
+        if (cur >= 0) flush();
+    }
+    __syncthreads();
+    if (wave_has) {
+        RunAcc<Real> run;
+        run.reset();
+        int cur = -1;
+        auto flush = [&]() {
+            const bool loc = cur < kLocalRecs;
+            double npix, amax;
+            if (loc) {
+                npix = (double)sh.u2.rec[cur].c[0];
+                amax = (double)__uint_as_float(sh.u2.rec[cur].amax);
+            } else {
+                CompRec& G = wk.recs[base + cur];
+                npix = __hip_atomic_load(&G.s[6], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                amax = (double)__uint_as_float(__hip_atomic_load(&G.amax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            }
+            // |offsets| < 64 inside a tile: bounds amax npix 64^p for the
+            // sums weighted by p coordinates
+            const double b0 = amax * npix;
+            const int e0 = quantum_exp(b0), e1 = quantum_exp(b0 * 64.0), e2 = quantum_exp(b0 * 4096.0);
+            const double dxd = (double)lane;
+            const double S = run.s(), T = run.t(), U = run.u();
+            const double add[6] = {quantize(S, e0),           quantize(dxd * S, e1), quantize(T, e1),
+                                   quantize(dxd * dxd * S, e2), quantize(U, e2),      quantize(dxd * T, e2)};
+            if (loc) {
+                LocalRec& R = sh.u2.rec[cur];
+#pragma unroll
+                for (int z = 0; z < 6; ++z) atomicAdd(&R.s[z], add[z]);
+            } else {
+                CompRec& R = wk.recs[base + cur];
+#pragma unroll
+                for (int z = 0; z < 6; ++z) unsafeAtomicAdd(&R.s[z], add[z]);
+            }
+            run.reset();
+            cur = -1;
+        };
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const bool m = (mbits >> k) & 1u;
+            const int c = co[k];
+            if (cur >= 0 && (!m || c != cur)) flush();
+            if (m) {
+                if (cur < 0) cur = c;
+                run.add(Mo[k], (Real)(16 * wv + k));
             }
         }
         if (cur >= 0) flush();
@@ -701,6 +757,10 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
         R.frame = f;
         R.x0 = x0;
         R.y0 = y0;
+        R.amax = Lr.amax;
+        R.camax = 0u;
+        R.cnpix = 0;
+        for (int z = 0; z < 12; ++z) R.acc[z] = 0.0;
     }
     if (tid == 0) wk.tiles[gt] = TileInfo{base, ncomp};
 }
@@ -790,48 +850,68 @@ __global__ __launch_bounds__(256) void k_merge_edges(DetWork wk, int conn) {
     }
 }
 
-// Every piece finds its root; non-roots add their sums into the root record.
-// A component is kept when its pixel count reaches minarea: the bit of its
-// first pixel (the root's own) is set by the root when its own pixels already
-// reach it, else by the piece whose addition carries the count across it
-// (counts are exact in FP64, so exactly one addition crosses).
+// Merge, pass 1: every piece finds its root and adds its exact integer
+// quantities into the root record (pixel count, max |M|, bounding box, peak,
+// flags).  A component is kept when its pixel count reaches minarea: the
+// piece whose addition carries the count across minarea (exactly one, the
+// counts being integers) sets the bit of the component's first pixel, the
+// root's own, in the per-frame rank bitmap.
 __global__ __launch_bounds__(256) void k_merge_records(DetWork wk, int minarea) {
     if (wk.counters[1] != 0u) return;
     const int total = min((int)wk.counters[0], wk.rec_cap);
-    const double ma = (double)minarea;
     for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
         const int r = g_find(wk.parent, id);
         wk.root[id] = r;
         CompRec& R = wk.recs[r];
-        bool mark;
-        if (r == id) {
-            mark = __hip_atomic_load(&R.s[6], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= ma;
-        } else {
-            const CompRec& S = wk.recs[id];
-            const double ox = (double)(S.x0 - R.x0), oy = (double)(S.y0 - R.y0);
-            double before = 0.0;
-            for (int h = 0; h < 2; ++h) {
-                const double* s = S.s + 6 * h;
-                double* t = R.s + 6 * h;
-                const double old = unsafeAtomicAdd(&t[0], s[0]);
-                if (h == 1) before = old;
-                unsafeAtomicAdd(&t[1], s[1] + ox * s[0]);
-                unsafeAtomicAdd(&t[2], s[2] + oy * s[0]);
-                unsafeAtomicAdd(&t[3], s[3] + 2.0 * ox * s[1] + ox * ox * s[0]);
-                unsafeAtomicAdd(&t[4], s[4] + 2.0 * oy * s[2] + oy * oy * s[0]);
-                unsafeAtomicAdd(&t[5], s[5] + ox * s[2] + oy * s[1] + ox * oy * s[0]);
-            }
+        const CompRec& S = wk.recs[id];
+        const int np = (int)S.s[6];
+        const int before = atomicAdd(&R.cnpix, np);
+        atomicMax(&R.camax, S.amax);
+        if (r != id) {
             atomicMin(&R.xmin, S.xmin);
             atomicMax(&R.xmax, S.xmax);
             atomicMin(&R.ymin, S.ymin);
             atomicMax(&R.ymax, S.ymax);
             atomicMax(&R.peak, S.peak);
             if (S.flags) atomicOr(&R.flags, S.flags);
-            mark = before < ma && before + S.s[6] >= ma;
         }
-        if (mark) {
+        if (before < minarea && before + np >= minarea) {
             const FrameDesc& d = wk.desc[R.frame];
             atomicOr(&d.bitmap[R.pmin >> 5], 1u << (R.pmin & 31u));
+        }
+    }
+}
+
+// Merge, pass 2: every piece (the root too) moves its sums to the root's tile
+// origin and adds them into the root's accumulators, each term rounded to the
+// component's quantum for that sum.  The bounds are exact integers known
+// after pass 1: max |M| times the pixel count times the extent of the
+// bounding box about the root's origin (X, Y) to the power of the sum's
+// coordinates, and the pixel count times the same for the unit-weight sums.
+__global__ __launch_bounds__(256) void k_merge_sums(DetWork wk) {
+    if (wk.counters[1] != 0u) return;
+    const int total = min((int)wk.counters[0], wk.rec_cap);
+    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
+        const int r = wk.root[id];
+        CompRec& R = wk.recs[r];
+        const CompRec& S = wk.recs[id];
+        const double ox = (double)(S.x0 - R.x0), oy = (double)(S.y0 - R.y0);
+        const double X = (double)(max(abs(R.xmin - R.x0), abs(R.xmax - R.x0)) + 1);
+        const double Y = (double)(max(abs(R.ymin - R.y0), abs(R.ymax - R.y0)) + 1);
+        const double np = (double)R.cnpix;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double* s = S.s + 6 * h;
+            const double b0 = (h == 0 ? (double)__uint_as_float(R.camax) : 1.0) * np;
+            const double c[6] = {s[0],
+                                 s[1] + ox * s[0],
+                                 s[2] + oy * s[0],
+                                 s[3] + 2.0 * ox * s[1] + ox * ox * s[0],
+                                 s[4] + 2.0 * oy * s[2] + oy * oy * s[0],
+                                 s[5] + ox * s[2] + oy * s[1] + ox * oy * s[0]};
+            const double b[6] = {b0, b0 * X, b0 * Y, b0 * X * X, b0 * Y * Y, b0 * X * Y};
+#pragma unroll
+            for (int z = 0; z < 6; ++z) unsafeAtomicAdd(&R.acc[6 * h + z], quantize(c[z], quantum_exp(b[z])));
         }
     }
 }
@@ -958,7 +1038,7 @@ __global__ __launch_bounds__(256) void k_write_catalog(DetWork wk, CatOut cat, i
     for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
         if (wk.root[id] != id) continue;
         const CompRec& R = wk.recs[id];
-        if (R.s[6] < (double)minarea) {
+        if (R.cnpix < minarea) {
             wk.label[id] = -1;
             continue;
         }
@@ -984,17 +1064,17 @@ __global__ __launch_bounds__(256) void k_write_catalog(DetWork wk, CatOut cat, i
         wk.label[id] = (int)rank + 1;
         if ((int)rank >= cat.capacity) continue;
         const size_t row = (size_t)d.cat_base + rank;
-        const bool nonpos = !(R.s[0] > 0.0);
-        const double* w = nonpos ? R.s + 6 : R.s;
+        const bool nonpos = !(R.acc[0] > 0.0);
+        const double* w = nonpos ? R.acc + 6 : R.acc;
         const double W0 = w[0];
         const double mx = w[1] / W0, my = w[2] / W0;
-        cat.npix[row] = (int32_t)R.s[6];
+        cat.npix[row] = R.cnpix;
         cat.xmin[row] = R.xmin;
         cat.xmax[row] = R.xmax;
         cat.ymin[row] = R.ymin;
         cat.ymax[row] = R.ymax;
         cat.pmin[row] = (int64_t)pm;
-        cat.flux[row] = R.s[0];
+        cat.flux[row] = R.acc[0];
         cat.x[row] = (double)R.x0 + mx;
         cat.y[row] = (double)R.y0 + my;
         cat.x2[row] = w[3] / W0 - mx * mx;
@@ -1061,6 +1141,7 @@ void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, int r
 void launch_merge(const DetWork& wk, int conn, int minarea, int persist_blocks, hipStream_t s) {
     k_merge_edges<<<(wk.total_tiles + 3) / 4, 256, 0, s>>>(wk, conn);
     k_merge_records<<<persist_blocks, 256, 0, s>>>(wk, minarea);
+    k_merge_sums<<<persist_blocks, 256, 0, s>>>(wk);
     const int nb = wk.total_blocks;
     const int nchunks = (nb + kScanChunk - 1) / kScanChunk;
     k_popc_scan<<<nchunks, 256, 0, s>>>(wk.bitmap, wk.blockcnt, wk.chunksum, nb);

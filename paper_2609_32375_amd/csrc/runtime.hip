@@ -72,8 +72,9 @@ struct ProfScope {
     hipStream_t s;
     const char* name;
     hipEvent_t a = nullptr;
-    ProfScope(gp_ctx* c_, hipStream_t s_, const char* n) : c(c_), s(s_), name(n) {
-        if (!c->profiling) return;
+    // enable = false: never record (a call that must create nothing)
+    ProfScope(gp_ctx* c_, hipStream_t s_, const char* n, bool enable = true) : c(c_), s(s_), name(n) {
+        if (!enable || !c->profiling) return;
         std::lock_guard<std::mutex> g(c->mu);
         a = take();
         (void)hipEventRecord(a, s);
@@ -89,7 +90,7 @@ struct ProfScope {
         return e;
     }
     ~ProfScope() {
-        if (!c->profiling || !a) return;
+        if (!a) return;
         std::lock_guard<std::mutex> g(c->mu);
         hipEvent_t b = take();
         (void)hipEventRecord(b, s);
@@ -348,7 +349,12 @@ gp_status upload_desc(const gp_frame* frames, int32_t nframes, const gp_bkg_para
     return GP_OK;
 }
 
-// rank-one test of the filter kernel; on success fills normalised factors
+// rank-one test of the filter kernel; on success fills normalised factors.
+// The kernel counts as rank one only when every tap equals the product of
+// the factors (the tap's column through the peak times its row through the
+// peak, over the peak) to within 4 float32 rounding units of the tap itself:
+// the two 1-D passes then apply the given kernel up to the rounding already in
+// its float taps.  Anything else is applied densely.
 bool separable_factors(const gp_det_params* dp, double* kx, double* ky) {
     const int kw = dp->kw, kh = dp->kh;
     const float* K = dp->kernel;
@@ -367,7 +373,8 @@ bool separable_factors(const gp_det_params* dp, double* kx, double* ky) {
     for (int b = 0; b < kw; ++b) v[b] = (double)K[am * kw + b] / (double)K[am * kw + bm];
     for (int a = 0; a < kh; ++a)
         for (int b = 0; b < kw; ++b)
-            if (std::fabs((double)K[a * kw + b] - u[a] * v[b]) > 1e-6 * vmax) return false;
+            if (std::fabs((double)K[a * kw + b] - u[a] * v[b]) > 4.0 * 0x1p-24 * std::fabs((double)K[a * kw + b]))
+                return false;
     double su = 0.0, sv = 0.0;
     for (double x : u) su += x;
     for (double x : v) sv += x;
@@ -654,9 +661,10 @@ static gp_status check_cat(const gp_catalog* cat, bool need_moments) {
     return GP_OK;
 }
 
-extern "C" gp_status gp_detect(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
-                               const void* bkg, const gp_det_params* dp, gp_catalog* cat, int32_t* const* seg,
-                               int32_t* comp_status, void* ws, size_t ws_bytes, void* stream) {
+// prof = false: no timing events (nothing is created during the call)
+static gp_status detect_run(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
+                            const void* bkg, const gp_det_params* dp, gp_catalog* cat, int32_t* const* seg,
+                            int32_t* comp_status, void* ws, size_t ws_bytes, void* stream, bool prof) {
     if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
     gp_status st;
     if ((st = check_frames(frames, nframes)) != GP_OK) return st;
@@ -714,37 +722,43 @@ extern "C" gp_status gp_detect(gp_ctx* ctx, const gp_frame* frames, int32_t nfra
     wk.rec_cap = (int32_t)P.rec_cap;
     wk.total_blocks = (int32_t)P.total_blocks;
     {
-        ProfScope ps(ctx, s, "setup");
+        ProfScope ps(ctx, s, "setup", prof);
         launch_det_setup(tail, (FrameDesc*)(W + P.o_desc), in, dargs, wk.counters, s);
     }
     HIP_TRY(hipGetLastError());
     const bool f64 = dp->precision == GP_PREC_F64;
     {
-        ProfScope ps(ctx, s, "detect_tiles");
+        ProfScope ps(ctx, s, "detect_tiles", prof);
         const int rad = (in.separable && dp->kw == dp->kh) ? dp->kw / 2 : -1;
         launch_detect_tiles(wk, dargs, f64, rad, s);
     }
     HIP_TRY(hipGetLastError());
     const int persist = ctx->cus * 4;
     {
-        ProfScope ps(ctx, s, "merge");
+        ProfScope ps(ctx, s, "merge", prof);
         launch_merge(wk, dp->connectivity, dp->minarea, persist, s);
     }
     HIP_TRY(hipGetLastError());
     CatOut co{cat->capacity, cat->n_obj, cat->status, cat->npix, cat->xmin, cat->xmax, cat->ymin, cat->ymax,
               cat->pmin, cat->flux, cat->x, cat->y, cat->x2, cat->y2, cat->xy, cat->peak, cat->flags};
     {
-        ProfScope ps(ctx, s, "catalog");
+        ProfScope ps(ctx, s, "catalog", prof);
         launch_catalog(wk, co, dp->minarea, persist, comp_status, s);
     }
     HIP_TRY(hipGetLastError());
     if (seg) {
-        ProfScope ps(ctx, s, "seg");
+        ProfScope ps(ctx, s, "seg", prof);
         for (int f = 0; f < nframes; ++f)
             if (seg[f]) launch_seg(wk, f, (int64_t)frames[f].width * frames[f].height, s);
     }
     HIP_TRY(hipGetLastError());
     return GP_OK;
+}
+
+extern "C" gp_status gp_detect(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
+                               const void* bkg, const gp_det_params* dp, gp_catalog* cat, int32_t* const* seg,
+                               int32_t* comp_status, void* ws, size_t ws_bytes, void* stream) {
+    return detect_run(ctx, frames, nframes, bp, bkg, dp, cat, seg, comp_status, ws, ws_bytes, stream, true);
 }
 
 extern "C" gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,

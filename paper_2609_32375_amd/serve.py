@@ -17,7 +17,7 @@ from __future__ import annotations
 
 import math
 import time
-from collections import deque
+from collections import OrderedDict, deque
 from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import Any, List, Optional
@@ -68,8 +68,11 @@ class _Epoch:
 class Server:
     """Continuous-batching server for one GPU.
 
-    hbm_budget: bytes of HBM the in-flight requests may hold (frames, background
-    buffers, workspace, catalogue); None = 90% of the free memory at start.
+    hbm_budget: bytes of HBM the server may hold: the in-flight requests
+    (frames, background buffers, workspace, catalogue) plus the finished batch
+    objects kept for reuse; None = 90% of the free memory at start.  Idle batch
+    objects are released, least recently used first, whenever a request would
+    not fit otherwise.
     slots: most requests in flight.  streams: concurrent batches.  max_batch:
     most requests per batch (default: slots / streams).
     """
@@ -99,9 +102,12 @@ class Server:
         self.t0 = time.perf_counter()
         self.finished: List[Request] = []
         self._ws_cache = {}
-        # batch objects (buffers sized for a set of shapes) kept for reuse:
-        # key -> list of idle Photometry
-        self._idle = {}
+        # batch objects (buffers sized for a set of shapes) kept for reuse, in
+        # least-recently-used order: (key, serial) -> Photometry; their HBM is
+        # counted in idle_bytes against the budget
+        self._idle: "OrderedDict" = OrderedDict()
+        self._idle_serial = 0
+        self.idle_bytes = 0
 
     # ------------------------------------------------------------------
     def now(self) -> float:
@@ -154,10 +160,44 @@ class Server:
                     r.t_done = t
                     self.resident -= r.footprint
                     self.finished.append(r)
-                self._idle.setdefault(ep.key, []).append(ep.ph)
+                self._park(ep.key, ep.ph)
             else:
                 still.append((ep, fut))
         self.downloading = still
+
+    # ------------------------------------------------------------------
+    @staticmethod
+    def _bytes(ph) -> int:
+        """HBM held by a batch object's buffers."""
+        n = ph.bkg.numel() + ph.ws.numel()
+        for t in list(ph.cat.values()) + list(ph.phot.values()) + [ph.n_obj, ph.status, ph.comp_status]:
+            n += t.numel() * t.element_size()
+        if ph.seg is not None:
+            n += sum(t.numel() * t.element_size() for t in ph.seg)
+        return int(n)
+
+    def _park(self, key, ph):
+        self._idle_serial += 1
+        self._idle[(key, self._idle_serial)] = ph
+        self.idle_bytes += self._bytes(ph)
+
+    def _take_idle(self, key):
+        for k in reversed(self._idle):
+            if k[0] == key:
+                ph = self._idle.pop(k)
+                self.idle_bytes -= self._bytes(ph)
+                return ph
+        return None
+
+    def _evict(self, need: int) -> bool:
+        """Release idle batch objects, oldest first, until `need` more bytes fit
+        the budget; True when they do."""
+        while self._idle and self.resident + self.idle_bytes + need > self.budget:
+            _, ph = self._idle.popitem(last=False)
+            self.idle_bytes -= self._bytes(ph)
+            ph.close()
+            del ph
+        return self.resident + self.idle_bytes + need <= self.budget
 
     def _key(self, r):
         return (id(r.params) if r.params is not None else None, id(r.kernel) if r.kernel is not None else None)
@@ -174,8 +214,8 @@ class Server:
         while self.waiting:
             r = self.waiting.popleft()
             fits = (len(batch) < self.max_batch and r.arrival <= now and n_inflight + len(batch) < self.slots
-                    and self.resident + r.footprint <= self.budget
-                    and blocks + pixel_blocks(r.frame) <= MAX_BATCH_BLOCKS)
+                    and blocks + pixel_blocks(r.frame) <= MAX_BATCH_BLOCKS
+                    and self._evict(r.footprint))
             if fits and (key is None or self._key(r) == key):
                 key = self._key(r)
                 r.t_admit = now
@@ -204,9 +244,8 @@ class Server:
             params = batch[0].params if batch[0].params is not None else self.params
             kernel = batch[0].kernel if batch[0].kernel is not None else self.kernel
             bkey = (key, tuple((tuple(t.shape), t.dtype) for t in devs))
-            idle = self._idle.get(bkey)
-            if idle:
-                ph = idle.pop()
+            ph = self._take_idle(bkey)
+            if ph is not None:
                 ph.rebind(devs)
             else:
                 ph = Photometry(devs, params, kernel, self.capacity, ctx=self.ctx)
@@ -246,10 +285,10 @@ class Server:
             ep.ph.close()
         self.downloading = []
         self._pool.shutdown(wait=True)
-        for lst in self._idle.values():
-            for ph in lst:
-                ph.close()
-        self._idle = {}
+        for ph in self._idle.values():
+            ph.close()
+        self._idle = OrderedDict()
+        self.idle_bytes = 0
         if self.ctx:
             L.gp_ctx_destroy(self.ctx)
             self.ctx = None

@@ -14,8 +14,8 @@ import pytest
 
 import oracle
 from synth import Params, gaussian_kernel, make_frame
-from tests._util import (AMBIG_T, TOL_BKG_REL, box_max_abs, cmp_catalog, cmp_phot, f32_params,
-                         mesh_ambiguous, phot_condition, thresh_ambiguous)
+from tests._util import (AMBIG_T, TOL_BKG_REL, check_meshes, cmp_catalog, cmp_phot, f32_params, mesh_ambiguous,
+                         phot_condition, thresh_ambiguous, weight_allowance)
 
 pytestmark = pytest.mark.gpu
 
@@ -100,15 +100,12 @@ def test_mesh_statistics_structured(P, m):
     ph = P.Photometry([_dev(img)], p, p.kernel(), capacity=64)
     ph.background()
     g = ph.grids(0)
+    # every mesh: those with a decision inside the rounding band must match
+    # the oracle re-run with that decision taken either way
+    _, _, flipped = check_meshes(img, g, p)
     st = oracle.mesh_stats(img.astype(np.float64), m, m, p.clip_sigma, p.crowd_tol, p.mode_a, p.mode_b, p.max_iter)
-    ok = ~mesh_ambiguous(st)
-    _say("ambiguous", int((~ok).sum()), "iters", st["iters"].ravel().tolist())
-    assert ok.sum() >= 7
-    rel_b = np.abs(g["back_raw"] - st["back"]) / np.maximum(np.abs(st["back"]), 1e-30)
-    rel_r = np.abs(g["rms_raw"] - st["rms"]) / np.maximum(np.abs(st["rms"]), 1e-30)
-    _say("max rel back", rel_b[ok].max(), "rms", rel_r[ok].max())
-    assert np.all(rel_b[ok] <= TOL_BKG_REL) and np.all((rel_r[ok] <= TOL_BKG_REL) | (st["rms"][ok] == 0))
-    np.testing.assert_array_equal(g["iters"][ok], st["iters"][ok].astype(np.int32))
+    _say("ambiguous", int(mesh_ambiguous(st).sum()), "matched a flipped branch", flipped,
+         "iters", st["iters"].ravel().tolist())
     ph.close()
 
 
@@ -122,17 +119,9 @@ def test_mesh_statistics_match_oracle(P, case):
     ph = P.Photometry([_dev(img)], p, p.kernel(), capacity=64)
     ph.background()
     g = ph.grids(0)
+    _, _, flipped = check_meshes(img, g, p)
     st = oracle.mesh_stats(img.astype(np.float64), mw, mh, p.clip_sigma, p.crowd_tol, p.mode_a, p.mode_b, p.max_iter)
-    amb = mesh_ambiguous(st)
-    ok = ~amb
-    _say("meshes", st["back"].size, "ambiguous", int(amb.sum()))
-    assert amb.sum() <= max(1, st["back"].size // 20)
-    rel_b = np.abs(g["back_raw"] - st["back"]) / np.abs(st["back"])
-    rel_r = np.abs(g["rms_raw"] - st["rms"]) / np.maximum(np.abs(st["rms"]), 1e-30)
-    _say("max rel back", rel_b[ok].max(), "rms", rel_r[ok].max())
-    assert np.all(rel_b[ok] <= TOL_BKG_REL) and np.all(rel_r[ok] <= TOL_BKG_REL)
-    # identical clipping decisions: same number of passes
-    np.testing.assert_array_equal(g["iters"][ok], st["iters"][ok].astype(np.int32))
+    _say("meshes", st["back"].size, "ambiguous", int(mesh_ambiguous(st).sum()), "matched a flipped branch", flipped)
     # the grid filter is exact given the same raw grid
     np.testing.assert_array_equal(g["back"], oracle.median_filter(g["back_raw"], p.mesh_filter))
     np.testing.assert_array_equal(g["rms"], oracle.median_filter(g["rms_raw"], p.mesh_filter))
@@ -288,49 +277,83 @@ def _field(case):
     return fr, p
 
 
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "fp64"])
-@pytest.mark.parametrize("case", FIELD_CASES, ids=lambda c: f"{c[0]}-{c[1]}x{c[2]}-{c[3]}")
-def test_detection_stage_isolated(P, case, prec):
-    _say("detect case", case, prec)
+def _kernel_cases():
+    """Filter kernels beyond the workloads' own: square Gaussians of every
+    separable radius (0..7), a non-square rank-one kernel and two kernels that
+    are not rank one (asymmetric random, and a Gaussian with one tap changed by
+    1e-5 of its peak), all through the detection kernel's other code paths."""
+    rng = np.random.default_rng(77)
+    out = [(f"gauss{k}", gaussian_kernel(k, 3.0)) for k in (1, 3, 7, 11, 13, 15)]
+    g = np.exp(-0.5 * (np.arange(-1, 2) / 1.2) ** 2)
+    h = np.exp(-0.5 * (np.arange(-3, 4) / 1.7) ** 2)
+    out.append(("rank1_3x7", np.outer(g, h).astype(np.float32)))
+    out.append(("dense_7x5", (0.2 + rng.random((7, 5))).astype(np.float32)))
+    near = gaussian_kernel(9, 3.5).copy()
+    near[3, 5] += 1e-5 * near.max()
+    out.append(("near_rank1_9x9", near))
+    return out
+
+
+def _detect_stage(P, case, prec, K=None):
     fr, p = _field(case)
     img = fr.image
     I = img.astype(np.float64)
-    H, W = img.shape
     ob = oracle.background(I, p, maps=True)
     M = I - ob.B
-    K = p.kernel()
+    K = p.kernel() if K is None else K
     F = oracle.filter_image(M, K)
     ph = P.Photometry([_dev(img)], p, K, capacity=4096, seg=True, precision=prec)
     ph.set_grids(0, ob.back, ob.rms)
     ph.background(grid_given=True)
     ph.detect()
-    ph.aperture()
     r = ph.results(0)
     assert r["status"] == 0 and r["comp_status"][0] == 0
     seg_g = r["seg"]
     mask_g = seg_g != 0
+    # the oracle's mask, with every decision inside the rounding band taken the
+    # way the GPU took it (both branches are correct there)
     mask_o = F > p.thresh * ob.R
     amb = thresh_ambiguous(F, ob.R, p.thresh)
     diff = mask_g != mask_o
     _say("mask pixels", int(mask_o.sum()), "differ", int(diff.sum()), "ambiguous", int(amb.sum()))
     assert np.all(amb[diff])
-    # labels bit-exact for the GPU's own mask
-    seg_chk, n_chk = oracle.threshold_label(mask_g.astype(np.float64), np.zeros_like(I), 0.0, p.minarea, p.conn)
-    np.testing.assert_array_equal(seg_g, seg_chk)
-    assert r["n_obj"] == n_chk
-    # moments: oracle measurements of the same labels
-    ocat = oracle.measure(I, M, seg_g, n_chk, p.sat_level)
-    err = cmp_catalog(r["cat"], ocat, M, seg_g, tag=str(case))
+    mask_ref = np.where(amb, mask_g, mask_o)
+    seg_o, n_o = oracle.label_mask(mask_ref, p.conn, p.minarea)
+    np.testing.assert_array_equal(seg_g, seg_o)
+    assert r["n_obj"] == n_o
+    ocat = oracle.measure(I, M, seg_o, n_o, p.sat_level)
+    err = cmp_catalog(r["cat"], ocat, M, seg_o, tag=str(case))
     _say("catalogue errors", err)
-    # apertures at the GPU's centres on the oracle's M and R
-    xs, ys = r["cat"]["x"], r["cat"]["y"]
+    return fr, p, ph, ob, M, ocat
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("case", FIELD_CASES, ids=lambda c: f"{c[0]}-{c[1]}x{c[2]}-{c[3]}")
+def test_detection_stage_isolated(P, case, prec):
+    _say("detect case", case, prec)
+    fr, p, ph, ob, M, ocat = _detect_stage(P, case, prec)
+    # apertures at the oracle's centroids, on the same background
+    xs, ys = ocat["x"], ocat["y"]
+    ph.set_catalog(0, xs, ys, ocat["flags"])
+    ph.aperture()
+    r = ph.results(0)
     oph = oracle.aperture(M, ob.R, xs, ys, list(p.radii), p.r_in, p.r_out, p.gain, p.want_err)
     cond, cond_ann = phot_condition(M, xs, ys, p)
-    mmax = box_max_abs(M, xs, ys, max(p.r_out, max(p.radii)))
-    err = cmp_phot(r["phot"], oph, cond, cond_ann, tag=str(case), mmax=mmax)
+    allow = weight_allowance(M, xs, ys, p, oph, precision=prec)
+    err = cmp_phot(r["phot"], oph, cond, cond_ann, allow, tag=str(case))
     _say("photometry errors", err)
     trunc = (r["cat"]["flags"] & 8) != 0
     np.testing.assert_array_equal(trunc, (oph["flags"] & 8) != 0)
+    ph.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("kcase", _kernel_cases(), ids=lambda c: c[0])
+def test_detection_every_filter_path(P, kcase, prec):
+    name, K = kcase
+    _say("kernel case", name, K.shape, prec)
+    case = ("c1", 300, 230, "f32", 17)
+    _, _, ph, _, _, _ = _detect_stage(P, case, prec, K=K)
     ph.close()
 
 
@@ -355,8 +378,8 @@ def test_aperture_stage_isolated_exact_centres(P, case):
     r = ph.results(0)
     oph = oracle.aperture(M, ob.R, xs, ys, list(p.radii), p.r_in, p.r_out, p.gain, p.want_err)
     cond, cond_ann = phot_condition(M, xs, ys, p)
-    mmax = box_max_abs(M, xs, ys, max(p.r_out, max(p.radii)))
-    err = cmp_phot(r["phot"], oph, cond, cond_ann, tag=str(case), mmax=mmax)
+    allow = weight_allowance(M, xs, ys, p, oph)
+    err = cmp_phot(r["phot"], oph, cond, cond_ann, allow, tag=str(case))
     _say("photometry errors", err)
     np.testing.assert_array_equal((r["cat"]["flags"] & 8) != 0, (oph["flags"] & 8) != 0)
     ph.close()
@@ -387,35 +410,69 @@ def test_aperture_constant_image_closed_form(P):
 # ----------------------------------------------------------------------------
 # whole chain, batches and failure paths
 # ----------------------------------------------------------------------------
-def test_end_to_end_against_oracle(P):
-    fr = make_frame("c1", seed=21, W=384, H=320, nstars=40)
+def _grown(mask):
+    """mask grown by one pixel in the 8-neighbourhood"""
+    g = mask.copy()
+    g[1:, :] |= mask[:-1, :]
+    g[:-1, :] |= mask[1:, :]
+    g2 = g.copy()
+    g2[:, 1:] |= g[:, :-1]
+    g2[:, :-1] |= g[:, 1:]
+    return g2
+
+
+@pytest.mark.parametrize("seed", [21, 22, 23])
+def test_end_to_end_against_oracle(P, seed):
+    """GPU chain vs oracle chain.  Meshes are checked one by one (a mesh with a
+    decision inside the rounding band may match the oracle with that decision
+    flipped); the oracle chain then runs downstream of the grids it accepts.
+    Objects whose pixels (grown by one) hold no ambiguous threshold decision
+    must appear identically in both catalogues; every other GPU object must
+    touch an ambiguous pixel."""
+    fr = make_frame("c1", seed=seed, W=384, H=320, nstars=40)
     p = f32_params(fr.params)
     img = fr.image
     I = img.astype(np.float64)
-    res = oracle.run(I, p)
     ph = P.Photometry([_dev(img)], p, p.kernel(), capacity=2048, seg=True)
     ph.run()
     r = ph.results(0)
     g = ph.grids(0)
-    amb = mesh_ambiguous(res.bkg.stats)
-    _say("ambiguous meshes", int(amb.sum()))
-    rel = np.abs(g["back_raw"] - res.bkg.stats["back"]) / np.abs(res.bkg.stats["back"])
-    assert np.all(rel[~amb] <= TOL_BKG_REL)
-    if amb.any():
-        pytest.skip("an ambiguous mesh decision: the stage-isolated tests cover the rest")
-    ocat = res.cat
-    gcat = r["cat"]
+    back_raw, rms_raw, flipped = check_meshes(img, g, p)
+    back = oracle.median_filter(back_raw, p.mesh_filter)
+    rms = oracle.median_filter(rms_raw, p.mesh_filter)
+    res = oracle.run(I, p, grids=(back, rms))
     amb_px = thresh_ambiguous(res.F, res.bkg.R, p.thresh)
-    same = np.array_equal(r["seg"] != 0, res.seg != 0)
-    _say("objects", r["n_obj"], len(ocat["npix"]), "masks equal", same, "ambiguous px", int(amb_px.sum()))
-    if same:
-        np.testing.assert_array_equal(r["seg"], res.seg)
-        err = cmp_catalog(gcat, ocat, res.M, res.seg, tag="e2e")
-        cond, cond_ann = phot_condition(res.M, ocat["x"], ocat["y"], p)
-        cmp_phot(r["phot"], res.phot, cond, cond_ann, tag="e2e")
-        _say("e2e errors", err)
-    else:
-        assert np.all(amb_px[(r["seg"] != 0) != (res.seg != 0)])
+    ocat, gcat = res.cat, r["cat"]
+    n_o = len(ocat["npix"])
+    clean = np.array([not np.any(amb_px & _grown(res.seg == k + 1)) for k in range(n_o)], bool)
+    _say("meshes matched a flipped branch", flipped, "objects gpu", r["n_obj"], "oracle", n_o,
+         "ambiguous objects", int((~clean).sum()), "ambiguous px", int(amb_px.sum()))
+    assert clean.sum() >= max(1, 0.8 * n_o)
+    gi = {int(pm): i for i, pm in enumerate(gcat["pmin"])}
+    idx_o = np.nonzero(clean)[0]
+    assert all(int(ocat["pmin"][k]) in gi for k in idx_o), "a clean oracle object is missing on the GPU"
+    idx_g = np.array([gi[int(ocat["pmin"][k])] for k in idx_o])
+    # the same pixels: each clean object's GPU label covers exactly its pixels
+    for k, kg in zip(idx_o, idx_g):
+        np.testing.assert_array_equal(r["seg"] == kg + 1, res.seg == k + 1)
+    sub_g = {q: v[idx_g] for q, v in gcat.items()}
+    sub_o = {q: v[idx_o] for q, v in ocat.items()}
+    seg_sub = np.zeros_like(res.seg)
+    for t, k in enumerate(idx_o):
+        seg_sub[res.seg == k + 1] = t + 1
+    err = cmp_catalog(sub_g, sub_o, res.M, seg_sub, tag="e2e")
+    # GPU objects not among the clean ones lie on ambiguous pixels
+    others = np.setdiff1d(np.arange(r["n_obj"]), idx_g)
+    for kg in others:
+        assert np.any(amb_px & _grown(r["seg"] == kg + 1)), ("unexplained GPU object", int(kg))
+    # apertures of the clean objects at the oracle's centres
+    xs, ys = sub_o["x"], sub_o["y"]
+    oph = {q: v[idx_o] for q, v in res.phot.items()}
+    cond, cond_ann = phot_condition(res.M, xs, ys, p)
+    gph = {q: v[idx_g] for q, v in r["phot"].items()}
+    perr = cmp_phot(gph, oph, cond, cond_ann, weight_allowance(res.M, xs, ys, p, oph), tag="e2e")
+    _say("e2e errors", err, perr)
+    ph.close()
 
 
 def test_batch_matches_single_frames(P):
@@ -433,11 +490,9 @@ def test_batch_matches_single_frames(P):
         a, b = batch.results(i), one.results(0)
         assert a["n_obj"] == b["n_obj"] > 0
         np.testing.assert_array_equal(a["seg"], b["seg"])
+        # bit for bit: every sum is formed in a fixed order or from exact terms
         for k in a["cat"]:
-            if a["cat"][k].dtype.kind in "iu":
-                np.testing.assert_array_equal(a["cat"][k], b["cat"][k], err_msg=k)
-            else:
-                np.testing.assert_allclose(a["cat"][k], b["cat"][k], rtol=1e-12, atol=1e-12, err_msg=k)
+            np.testing.assert_array_equal(a["cat"][k], b["cat"][k], err_msg=k)
         for k in a["phot"]:
             np.testing.assert_array_equal(a["phot"][k], b["phot"][k], err_msg=k)
         ga, gb = batch.grids(i), one.grids(0)
@@ -445,6 +500,60 @@ def test_batch_matches_single_frames(P):
             np.testing.assert_array_equal(ga[k], gb[k])
         one.close()
     batch.close()
+
+
+def _same_results(a, b, tag):
+    assert a["n_obj"] == b["n_obj"] and a["status"] == b["status"], tag
+    for grp in ("cat", "phot"):
+        for k in a[grp]:
+            np.testing.assert_array_equal(a[grp][k], b[grp][k], err_msg=f"{tag} {grp}.{k}")
+
+
+def test_graph_replay_matches_direct_calls(P):
+    """The three calls over an uneven uint16/float32 batch captured once into a
+    HIP graph: every replay (with other work and synchronisations between the
+    replays) gives, bit for bit, the results of direct calls and of per-frame
+    calls."""
+    frs = [make_frame("c1", seed=91, W=700, H=520, nstars=60, dtype="u16"),
+           make_frame("c1", seed=92, W=257, H=190, nstars=15),
+           make_frame("c1", seed=93, W=1030, H=300, nstars=70, dtype="u16"),
+           make_frame("c1", seed=94, W=64, H=900, nstars=12)]
+    p = f32_params(frs[0].params)
+    K = p.kernel()
+    devs = [_dev(f.image) for f in frs]
+    direct = P.Photometry(devs, p, K, capacity=2048)
+    direct.run()
+    ref = [direct.results(i) for i in range(len(devs))]
+    singles = []
+    for i, d in enumerate(devs):
+        one = P.Photometry([d], p, K, capacity=2048)
+        one.run()
+        singles.append(one.results(0))
+        one.close()
+        _same_results(ref[i], singles[i], f"frame {i} batch vs alone")
+    gb = P.Photometry(devs, p, K, capacity=2048)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        gb.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gb.run()
+    for rep in range(4):
+        # eager work between replays: another batch through direct calls
+        direct.run()
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(devs)):
+            _same_results(gb.results(i), ref[i], f"replay {rep} frame {i}")
+        del junk
+    del g
+    gb.close()
+    direct.close()
 
 
 def test_capacity_overflow_keeps_first_labels(P):
