@@ -249,6 +249,26 @@ gp_status gp_detect(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
                     gp_catalog* cat, int32_t* const* seg, int32_t* comp_status, void* ws,
                     size_t ws_bytes, void* stream);
 
+/* gp_detect for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same detection, with the workspace replaced by a static device array of
+ * GP_DETECT_NOALLOC_MAX_BYTES that the library holds on every device it runs
+ * on until the process ends (its address is looked up when a context is
+ * created on the device).  The caller still passes frames, the background
+ * buffer (from gp_background) and the catalogue.  The component-piece
+ * capacity is whatever the array holds after the batch's fixed sections;
+ * overflow is reported through comp_status as with gp_detect.  A batch whose
+ * fixed sections alone do not fit returns GP_ERR_UNSUPPORTED (use gp_detect
+ * with a workspace).  Every call on a device shares that device's array, and
+ * each call writes every part of it that it later reads (nothing needs
+ * clearing between calls); two calls that overlap on one device (other
+ * streams, other host threads, other contexts) race on the array and their
+ * results are undefined.  No allocation, event or stream is created. */
+#define GP_DETECT_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+gp_status gp_detect_noalloc(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                            const gp_bkg_params* bp, const void* bkg, const gp_det_params* dp,
+                            gp_catalog* cat, int32_t* const* seg, int32_t* comp_status, void* stream);
+
 /* Aperture photometry of every catalogued object; also ORs GP_FLAG_APER_TRUNC
  * into cat->flags. */
 gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,

@@ -64,7 +64,8 @@ class gp_phot(C.Structure):
 
 
 EXPORTS = ("gp_ctx_create", "gp_ctx_destroy", "gp_last_error", "gp_version", "gp_background_layout",
-           "gp_workspace_size", "gp_background", "gp_background_map", "gp_detect", "gp_aperture",
+           "gp_workspace_size", "gp_background", "gp_background_map", "gp_detect", "gp_detect_noalloc",
+           "gp_aperture",
            "gp_profile_enable",
            "gp_profile_read", "gp_profile_reset", "gp_ctx_set_tuning")
 
@@ -102,6 +103,8 @@ def load(path: str = LIB_PATH):
     L.gp_detect.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp,
                             C.POINTER(gp_det_params), C.POINTER(gp_catalog), C.POINTER(vp), vp, vp,
                             C.c_size_t, vp]
+    L.gp_detect_noalloc.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp,
+                                    C.POINTER(gp_det_params), C.POINTER(gp_catalog), C.POINTER(vp), vp, vp]
     L.gp_aperture.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp,
                               C.POINTER(gp_catalog), C.POINTER(gp_ap_params), C.POINTER(gp_phot), vp,
                               C.c_size_t, vp]
@@ -110,7 +113,7 @@ def load(path: str = LIB_PATH):
     L.gp_profile_read.argtypes = [vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)]
     L.gp_profile_reset.argtypes = [vp]
     for f in ("gp_ctx_create", "gp_background_layout", "gp_workspace_size", "gp_background",
-              "gp_background_map", "gp_detect",
+              "gp_background_map", "gp_detect", "gp_detect_noalloc",
               "gp_aperture", "gp_profile_enable", "gp_profile_read", "gp_profile_reset"):
         getattr(L, f).restype = C.c_int
     _lib = L
@@ -175,6 +178,17 @@ def gp_detect(ctx, frames, bp, bkg_ptr, dp, cat, seg_ptrs, comp_status_ptr, ws_p
     segarr = (C.c_void_p * n)(*seg_ptrs) if seg_ptrs is not None else None
     check(load().gp_detect(ctx, arr, n, C.byref(bp), bkg_ptr, C.byref(dp), C.byref(cat), segarr,
                            comp_status_ptr, ws_ptr, ws_bytes, stream))
+
+
+def gp_detect_noalloc(ctx, frames, bp, bkg_ptr, dp, cat, seg_ptrs, comp_status_ptr, stream):
+    n = len(frames)
+    arr = (gp_frame * n)(*frames)
+    segarr = (C.c_void_p * n)(*seg_ptrs) if seg_ptrs is not None else None
+    check(load().gp_detect_noalloc(ctx, arr, n, C.byref(bp), bkg_ptr, C.byref(dp), C.byref(cat), segarr,
+                                   comp_status_ptr, stream))
+
+
+GP_DETECT_NOALLOC_MAX_BYTES = 128 << 20
 
 
 def gp_aperture(ctx, frames, bp, bkg_ptr, cat, ap, phot, ws_ptr, ws_bytes, stream):

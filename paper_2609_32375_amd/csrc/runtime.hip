@@ -43,6 +43,35 @@ static gp_status fail(gp_status st, const char* fmt, ...) {
     } while (0)
 
 extern "C" const char* gp_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Static device scratch for gp_detect_noalloc: each device the library runs
+// on holds one copy until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it only stands for the symbol): the
+// device address of each device's copy is looked up once, with that device
+// current, when a context is created on it, and kept per device.
+constexpr size_t kStaticScratchBytes = GP_DETECT_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// the calling thread's current device is `device` on entry
+static hipError_t scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch_ptr[device] = ptr;
+    return e;
+}
+
+static void* scratch_of(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 extern "C" const char* gp_version(void) { return "gpphot 0.1 (gfx950)"; }
 
 // ---------------------------------------------------------------------------
@@ -489,6 +518,17 @@ extern "C" gp_status gp_ctx_create(int device, const char* tune_cache, gp_ctx** 
     HIP_TRY(hipGetDeviceProperties(&prop, device));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(GP_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+    {
+        // the static scratch's address on this device (the previous current
+        // device is restored)
+        int prev = 0;
+        HIP_TRY(hipGetDevice(&prev));
+        HIP_TRY(hipSetDevice(device));
+        const hipError_t e = scratch_setup(device);
+        HIP_TRY(hipSetDevice(prev));
+        if (e != hipSuccess)
+            return fail(GP_ERR_HIP, "device %d: address of the static scratch: %s", device, hipGetErrorString(e));
+    }
     gp_ctx* c = new gp_ctx;
     c->device = device;
     c->cus = prop.multiProcessorCount;
@@ -759,6 +799,28 @@ extern "C" gp_status gp_detect(gp_ctx* ctx, const gp_frame* frames, int32_t nfra
                                const void* bkg, const gp_det_params* dp, gp_catalog* cat, int32_t* const* seg,
                                int32_t* comp_status, void* ws, size_t ws_bytes, void* stream) {
     return detect_run(ctx, frames, nframes, bp, bkg, dp, cat, seg, comp_status, ws, ws_bytes, stream, true);
+}
+
+extern "C" gp_status gp_detect_noalloc(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                                       const gp_bkg_params* bp, const void* bkg, const gp_det_params* dp,
+                                       gp_catalog* cat, int32_t* const* seg, int32_t* comp_status, void* stream) {
+    if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
+    gp_status st;
+    if ((st = check_frames(frames, nframes)) != GP_OK) return st;
+    if ((st = check_bkg(bp, frames, nframes)) != GP_OK) return st;
+    Plan P;
+    plan_bkg(frames, nframes, bp, P);
+    plan_fixed(nframes, P);
+    plan_recs(1, P);
+    if (P.ws_bytes > kStaticScratchBytes)
+        return fail(GP_ERR_UNSUPPORTED,
+                    "batch too large for the static scratch: its detection needs at least %zu bytes, the scratch "
+                    "holds %zu (use gp_detect with a workspace)",
+                    P.ws_bytes, kStaticScratchBytes);
+    void* ws = scratch_of(ctx->device);
+    if (!ws) return fail(GP_ERR_HIP, "no static scratch address for device %d", ctx->device);
+    return detect_run(ctx, frames, nframes, bp, bkg, dp, cat, seg, comp_status, ws, kStaticScratchBytes, stream,
+                      false);
 }
 
 extern "C" gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
