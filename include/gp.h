@@ -276,6 +276,27 @@ gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
                       const gp_ap_params* ap, gp_phot* out, void* ws, size_t ws_bytes,
                       void* stream);
 
+/* Captured batch: gp_background -> gp_detect -> gp_aperture over one batch
+ * (the arguments of the three calls, one workspace for all of them) recorded
+ * once into a HIP graph on a private stream and instantiated; every launch
+ * replays the whole sequence with one graph launch on the given stream.  The
+ * parameter structs and their host arrays are copied at creation; every
+ * device pointer must stay valid while the graph lives.  Creation returns the
+ * errors the three calls would (nothing is enqueued then).  Launches of one
+ * graph must not overlap (they share its buffers). */
+typedef struct gp_graph gp_graph;
+gp_status gp_graph_create(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                          const gp_bkg_params* bp, void* bkg, const gp_det_params* dp,
+                          gp_catalog* cat, int32_t* const* seg, int32_t* comp_status,
+                          const gp_ap_params* ap, gp_phot* phot, void* ws, size_t ws_bytes,
+                          gp_graph** out);
+gp_status gp_graph_launch(gp_graph* g, void* stream);
+/* Point the graph at other frames of the same sizes, pitches and dtypes (a
+ * new batch of the same shape class, as a server gets it): the sequence is
+ * recorded again and the instantiated graph updated in place. */
+gp_status gp_graph_rebind(gp_graph* g, const gp_frame* frames, int32_t nframes);
+void gp_graph_destroy(gp_graph* g);
+
 /* Per-kernel timing with HIP events recorded on the launch stream.  When
  * enabled, every kernel launch is bracketed by events; gp_profile_read
  * synchronises and returns the summed milliseconds and launch count for the

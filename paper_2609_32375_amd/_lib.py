@@ -67,7 +67,8 @@ EXPORTS = ("gp_ctx_create", "gp_ctx_destroy", "gp_last_error", "gp_version", "gp
            "gp_workspace_size", "gp_background", "gp_background_map", "gp_detect", "gp_detect_noalloc",
            "gp_aperture",
            "gp_profile_enable",
-           "gp_profile_read", "gp_profile_reset", "gp_ctx_set_tuning")
+           "gp_profile_read", "gp_profile_reset", "gp_ctx_set_tuning", "gp_graph_create", "gp_graph_launch",
+           "gp_graph_rebind", "gp_graph_destroy")
 
 _lib = None
 
@@ -108,13 +109,21 @@ def load(path: str = LIB_PATH):
     L.gp_aperture.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp,
                               C.POINTER(gp_catalog), C.POINTER(gp_ap_params), C.POINTER(gp_phot), vp,
                               C.c_size_t, vp]
+    L.gp_graph_create.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp,
+                                  C.POINTER(gp_det_params), C.POINTER(gp_catalog), C.POINTER(vp), vp,
+                                  C.POINTER(gp_ap_params), C.POINTER(gp_phot), vp, C.c_size_t, C.POINTER(vp)]
+    L.gp_graph_launch.argtypes = [vp, vp]
+    L.gp_graph_rebind.argtypes = [vp, C.POINTER(gp_frame), i32]
+    L.gp_graph_destroy.argtypes = [vp]
+    L.gp_graph_destroy.restype = None
     L.gp_profile_enable.argtypes = [vp, C.c_int]
     L.gp_ctx_set_tuning.argtypes = [vp, i32]
     L.gp_profile_read.argtypes = [vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)]
     L.gp_profile_reset.argtypes = [vp]
     for f in ("gp_ctx_create", "gp_background_layout", "gp_workspace_size", "gp_background",
               "gp_background_map", "gp_detect", "gp_detect_noalloc",
-              "gp_aperture", "gp_profile_enable", "gp_profile_read", "gp_profile_reset"):
+              "gp_aperture", "gp_profile_enable", "gp_profile_read", "gp_profile_reset", "gp_graph_create",
+              "gp_graph_launch", "gp_graph_rebind"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -196,6 +205,30 @@ def gp_aperture(ctx, frames, bp, bkg_ptr, cat, ap, phot, ws_ptr, ws_bytes, strea
     arr = (gp_frame * n)(*frames)
     check(load().gp_aperture(ctx, arr, n, C.byref(bp), bkg_ptr, C.byref(cat), C.byref(ap), C.byref(phot),
                              ws_ptr, ws_bytes, stream))
+
+
+def gp_graph_create(ctx, frames, bp, bkg_ptr, dp, cat, seg_ptrs, comp_status_ptr, ap, phot, ws_ptr, ws_bytes):
+    n = len(frames)
+    arr = (gp_frame * n)(*frames)
+    segarr = (C.c_void_p * n)(*seg_ptrs) if seg_ptrs is not None else None
+    h = C.c_void_p()
+    check(load().gp_graph_create(ctx, arr, n, C.byref(bp), bkg_ptr, C.byref(dp), C.byref(cat), segarr,
+                                 comp_status_ptr, C.byref(ap), C.byref(phot), ws_ptr, ws_bytes, C.byref(h)))
+    return h
+
+
+def gp_graph_launch(graph, stream):
+    check(load().gp_graph_launch(graph, stream))
+
+
+def gp_graph_rebind(graph, frames):
+    n = len(frames)
+    arr = (gp_frame * n)(*frames)
+    check(load().gp_graph_rebind(graph, arr, n))
+
+
+def gp_graph_destroy(graph):
+    load().gp_graph_destroy(graph)
 
 
 def gp_ctx_set_tuning(ctx, on: bool):

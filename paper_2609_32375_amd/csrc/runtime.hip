@@ -895,6 +895,174 @@ extern "C" gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nf
     return GP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Captured batches: the three calls over one batch recorded once into a HIP
+// graph (on a private stream) and replayed with one launch.  The parameters
+// and host arrays are copied, so the caller's may be freed after creation.
+struct gp_graph {
+    gp_ctx* ctx = nullptr;
+    std::vector<gp_frame> frames;
+    gp_bkg_params bp{};
+    void* bkg = nullptr;
+    gp_det_params dp{};
+    std::vector<float> kernel;
+    gp_catalog cat{};
+    std::vector<int32_t*> seg;
+    bool has_seg = false;
+    int32_t* comp_status = nullptr;
+    gp_ap_params ap{};
+    std::vector<float> radii;
+    gp_phot phot{};
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+// record the three calls into a new graph (the context's per-kernel timing is
+// off while recording: its events would belong to the capture, not a replay)
+gp_status graph_record(gp_graph* g, hipGraph_t* out) {
+    gp_ctx* c = g->ctx;
+    const bool prof = c->profiling;
+    c->profiling = false;
+    HIP_TRY(hipSetDevice(c->device));
+    hipError_t e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        c->profiling = prof;
+        return fail(GP_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    const int n = (int)g->frames.size();
+    gp_status st = gp_background(c, g->frames.data(), n, &g->bp, g->bkg, g->ws, g->ws_bytes, g->cap);
+    if (st == GP_OK)
+        st = gp_detect(c, g->frames.data(), n, &g->bp, g->bkg, &g->dp, &g->cat, g->has_seg ? g->seg.data() : nullptr,
+                       g->comp_status, g->ws, g->ws_bytes, g->cap);
+    if (st == GP_OK)
+        st = gp_aperture(c, g->frames.data(), n, &g->bp, g->bkg, &g->cat, &g->ap, &g->phot, g->ws, g->ws_bytes,
+                         g->cap);
+    const std::string msg = g_err;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(g->cap, &graph);
+    c->profiling = prof;
+    if (st != GP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        g_err = msg;
+        return st;
+    }
+    if (e != hipSuccess) return fail(GP_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    *out = graph;
+    return GP_OK;
+}
+
+void graph_free(gp_graph* g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    delete g;
+}
+}  // namespace
+
+extern "C" gp_status gp_graph_create(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
+                                     void* bkg, const gp_det_params* dp, gp_catalog* cat, int32_t* const* seg,
+                                     int32_t* comp_status, const gp_ap_params* ap, gp_phot* phot, void* ws,
+                                     size_t ws_bytes, gp_graph** out) {
+    if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
+    if (!out) return fail(GP_ERR_INVALID_ARG, "out is NULL");
+    gp_status st;
+    if ((st = check_frames(frames, nframes)) != GP_OK) return st;
+    if ((st = check_bkg(bp, frames, nframes)) != GP_OK) return st;
+    if ((st = check_det(dp)) != GP_OK) return st;
+    if ((st = check_ap(ap)) != GP_OK) return st;
+    if ((st = check_cat(cat, true)) != GP_OK) return st;
+    if (!phot) return fail(GP_ERR_INVALID_ARG, "photometry output is NULL");
+    gp_graph* g = new gp_graph;
+    g->ctx = ctx;
+    g->frames.assign(frames, frames + nframes);
+    g->bp = *bp;
+    g->bkg = bkg;
+    g->dp = *dp;
+    g->kernel.assign(dp->kernel, dp->kernel + (size_t)dp->kw * dp->kh);
+    g->dp.kernel = g->kernel.data();
+    g->cat = *cat;
+    g->has_seg = seg != nullptr;
+    if (seg) g->seg.assign(seg, seg + nframes);
+    g->comp_status = comp_status;
+    g->ap = *ap;
+    g->radii.assign(ap->radii, ap->radii + ap->nr);
+    g->ap.radii = g->radii.data();
+    g->phot = *phot;
+    g->ws = ws;
+    g->ws_bytes = ws_bytes;
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking)) != hipSuccess) {
+        graph_free(g);
+        return fail(GP_ERR_HIP, "capture stream: %s", hipGetErrorString(e));
+    }
+    hipGraph_t graph = nullptr;
+    if ((st = graph_record(g, &graph)) != GP_OK) {
+        graph_free(g);
+        return st;
+    }
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        g->exec = nullptr;
+        graph_free(g);
+        return fail(GP_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return GP_OK;
+}
+
+extern "C" gp_status gp_graph_launch(gp_graph* g, void* stream) {
+    if (!g || !g->exec) return fail(GP_ERR_INVALID_ARG, "graph is NULL");
+    HIP_TRY(hipSetDevice(g->ctx->device));
+    HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return GP_OK;
+}
+
+extern "C" gp_status gp_graph_rebind(gp_graph* g, const gp_frame* frames, int32_t nframes) {
+    if (!g || !g->exec) return fail(GP_ERR_INVALID_ARG, "graph is NULL");
+    gp_status st;
+    if ((st = check_frames(frames, nframes)) != GP_OK) return st;
+    if (nframes != (int32_t)g->frames.size())
+        return fail(GP_ERR_INVALID_ARG, "rebind needs %zu frames (got %d)", g->frames.size(), nframes);
+    for (int f = 0; f < nframes; ++f) {
+        const gp_frame &a = frames[f], &b = g->frames[f];
+        if (a.width != b.width || a.height != b.height || a.pitch != b.pitch || a.dtype != b.dtype)
+            return fail(GP_ERR_INVALID_ARG, "frame %d: rebind needs the same size, pitch and dtype", f);
+    }
+    const std::vector<gp_frame> keep = g->frames;
+    g->frames.assign(frames, frames + nframes);
+    hipGraph_t graph = nullptr;
+    if ((st = graph_record(g, &graph)) != GP_OK) {
+        g->frames = keep;
+        return st;
+    }
+    hipGraphNode_t bad = nullptr;
+    hipGraphExecUpdateResult res = hipGraphExecUpdateSuccess;
+    hipError_t e = hipGraphExecUpdate(g->exec, graph, &bad, &res);
+    if (e != hipSuccess || res != hipGraphExecUpdateSuccess) {
+        // the topology differs (it should not for equal shapes): instantiate anew
+        (void)hipGetLastError();
+        hipGraphExec_t fresh = nullptr;
+        e = hipGraphInstantiate(&fresh, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            g->frames = keep;
+            return fail(GP_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+        (void)hipGraphExecDestroy(g->exec);
+        g->exec = fresh;
+    }
+    (void)hipGraphDestroy(graph);
+    return GP_OK;
+}
+
+extern "C" void gp_graph_destroy(gp_graph* g) {
+    if (g) graph_free(g);
+}
+
 extern "C" gp_status gp_profile_enable(gp_ctx* ctx, int on) {
     if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
     ctx->profiling = on != 0;

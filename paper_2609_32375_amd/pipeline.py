@@ -126,6 +126,7 @@ class Photometry:
         ph = self.phot
         self.gphot = L.gp_phot(ph["flux"].data_ptr(), ph["area"].data_ptr(), ph["bkg"].data_ptr(),
                                ph["fluxerr"].data_ptr())
+        self.graph = None
         self.seg = None
         if seg:
             self.seg = [torch.zeros(t.shape[0], t.shape[1], dtype=torch.int32, device=dev) for t in self.frames_t]
@@ -138,6 +139,9 @@ class Photometry:
                 L.gp_ctx_set_tuning(self.ctx, False)
 
     def close(self):
+        if self.graph is not None and self.ctx:
+            L.gp_graph_destroy(self.graph)
+            self.graph = None
         if self._own_ctx and self.ctx:
             L.gp_ctx_destroy(self.ctx)
             self.ctx = None
@@ -155,10 +159,12 @@ class Photometry:
             raise ValueError("rebind needs the same number of frames")
         new = [make_frame(t) for t in frames]
         for a, b in zip(new, self.frames):
-            if (a.width, a.height, a.dtype) != (b.width, b.height, b.dtype):
-                raise ValueError("rebind needs the same shapes and dtypes")
+            if (a.width, a.height, a.pitch, a.dtype) != (b.width, b.height, b.pitch, b.dtype):
+                raise L.GpError(L.GP_ERR_INVALID_ARG, "rebind needs the same shapes, pitches and dtypes")
         self.frames_t = list(frames)
         self.frames = new
+        if self.graph is not None:
+            L.gp_graph_rebind(self.graph, self.frames)
 
     def stream_ptr(self, stream=None):
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -185,6 +191,22 @@ class Photometry:
         self.background(stream)
         self.detect(stream)
         self.aperture(stream)
+
+    def capture(self):
+        """Record the three calls over this batch into a library graph (once);
+        replay() then runs them with one graph launch, and rebind() updates
+        the graph for other frames of the same shapes."""
+        if self.graph is None:
+            seg = [s.data_ptr() for s in self.seg] if self.seg is not None else None
+            self.graph = L.gp_graph_create(self.ctx, self.frames, self.bp, C.c_void_p(self.bkg.data_ptr()), self.dp,
+                                           self.gcat, seg, C.c_void_p(self.comp_status.data_ptr()), self.ap,
+                                           self.gphot, C.c_void_p(self.ws.data_ptr()), self.ws_bytes)
+        return self
+
+    def replay(self, stream=None):
+        if self.graph is None:
+            self.capture()
+        L.gp_graph_launch(self.graph, self.stream_ptr(stream))
 
     # ------------------------------------------------------------------
     # host-side inspection (tests, bench)

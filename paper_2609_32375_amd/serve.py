@@ -78,7 +78,8 @@ class Server:
     """
 
     def __init__(self, params, kernel, capacity: int = 65536, hbm_budget: Optional[int] = None,
-                 slots: int = 16, streams: int = 2, device: int = 0, max_batch: Optional[int] = None):
+                 slots: int = 16, streams: int = 2, device: int = 0, max_batch: Optional[int] = None,
+                 graphs: bool = True):
         self.params = params
         self.kernel = np.ascontiguousarray(kernel, dtype=np.float32)
         self.capacity = capacity
@@ -89,6 +90,9 @@ class Server:
             hbm_budget = int(0.9 * free)
         self.budget = int(hbm_budget)
         self.slots = slots
+        # run each batch as a captured library graph, kept with its batch
+        # object per shape class and rebound to the next batch's frames
+        self.graphs = graphs
         # a batch takes at most its stream's share of the slots, so the next
         # batch can start on the other stream while one is being retired
         self.max_batch = max_batch or max(1, slots // max(1, streams))
@@ -249,7 +253,12 @@ class Server:
                 ph.rebind(devs)
             else:
                 ph = Photometry(devs, params, kernel, self.capacity, ctx=self.ctx)
-            ph.run(stream)
+                if self.graphs:
+                    ph.capture()
+            if self.graphs:
+                ph.replay(stream)
+            else:
+                ph.run(stream)
             done = torch.cuda.Event()
             done.record(stream)
         self.inflight.append(_Epoch(batch, ph, stream, done, devs, bkey))

@@ -556,6 +556,55 @@ def test_graph_replay_matches_direct_calls(P):
     direct.close()
 
 
+def test_library_graph_replay_and_rebind(P):
+    """gp_graph_create records the three calls over an uneven batch once;
+    every gp_graph_launch (with other work and synchronisations between
+    launches) reproduces direct calls bit for bit, and gp_graph_rebind to other
+    frames of the same shapes gives what direct calls give on those frames."""
+    def frames(seed0):
+        return [make_frame("c1", seed=seed0, W=610, H=480, nstars=50, dtype="u16"),
+                make_frame("c1", seed=seed0 + 1, W=300, H=199, nstars=20),
+                make_frame("c1", seed=seed0 + 2, W=900, H=257, nstars=40, dtype="u16")]
+    a = [_dev(f.image) for f in frames(110)]
+    b = [_dev(f.image) for f in frames(120)]
+    p = f32_params(frames(110)[0].params)
+    K = p.kernel()
+
+    def direct(devs):
+        ph = P.Photometry(devs, p, K, capacity=2048)
+        ph.run()
+        out = [ph.results(i) for i in range(len(devs))]
+        ph.close()
+        return out
+    ra, rb = direct(a), direct(b)
+    g = P.Photometry(a, p, K, capacity=2048).capture()
+    other = P.Photometry(b, p, K, capacity=2048)
+    for rep in range(3):
+        other.run()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(a)):
+            _same_results(g.results(i), ra[i], f"launch {rep} frame {i}")
+    g.rebind(b)
+    for rep in range(2):
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(b)):
+            _same_results(g.results(i), rb[i], f"rebound launch {rep} frame {i}")
+    g.rebind(a)
+    g.replay()
+    for i in range(len(a)):
+        _same_results(g.results(i), ra[i], f"rebound back, frame {i}")
+    from paper_2609_32375_amd import _lib as L
+    with pytest.raises(L.GpError):
+        g.rebind([a[1], a[0], a[2]])        # other shapes: refused, graph unchanged
+    g.replay()
+    _same_results(g.results(0), ra[0], "after a refused rebind")
+    g.close()
+    other.close()
+
+
 def test_capacity_overflow_keeps_first_labels(P):
     fr = make_frame("c1", seed=41, W=320, H=320, nstars=60)
     p = f32_params(fr.params)
