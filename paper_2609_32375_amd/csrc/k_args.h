@@ -14,6 +14,7 @@ struct BkgArgs {
     float clip, crowd, mode_a, mode_b;
     int32_t max_iter;
     int32_t fsize;
+    int32_t skip_u16;   // the float kernel leaves uint16 meshes to the integer kernel
 };
 
 // matched-filter and detection arguments, stored in the workspace
@@ -69,6 +70,8 @@ struct CatOut {
 // stores it in the table for the launches that follow), or null
 void launch_mesh_stats(FrameDesc* desc, const FrameDesc* one, int nframes, int total_meshes, int max_area, BkgArgs a,
                        int cfg, hipStream_t s);
+void launch_mesh_stats_u16(FrameDesc* desc, const FrameDesc* one, int nframes, int total_meshes, int max_area,
+                           BkgArgs a, int cfg, hipStream_t s);
 void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, int fsize, hipStream_t s);
 void launch_spline(const FrameDesc* desc, int nframes, int max_nx, int max_ny, hipStream_t s);
 bool filter_spline_fits(int max_nx, int max_ny, int fsize);

@@ -504,6 +504,7 @@ void k_mesh_stats(FrameDesc* __restrict__ desc, FrameDesc d1, int nframes, BkgAr
     if (ONE && gm == 0 && tid == 0) desc[0] = d1;
     const int f = ONE ? 0 : frame_of(nframes, gm, [&](int i) { return desc[i].mesh_base; });
     const FrameDesc d = ONE ? d1 : desc[f];
+    if (a.skip_u16 && d.dtype == kDtypeU16) return;
     const int lm = gm - d.mesh_base;
     const int mi = lm % d.nx, mj = lm / d.nx;
     const int x0 = mi * d.mw, y0 = mj * d.mh;
@@ -710,6 +711,368 @@ void k_mesh_stats(FrameDesc* __restrict__ desc, FrameDesc d1, int nframes, BkgAr
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// uint16 frames: exact integer statistics.  Each clipping pass keeps the
+// values within k sigma of the current median, so the surviving set is
+// always every pixel value inside an interval [L, H] of integers.  With one
+// LDS histogram of the mesh's values (1-ADU bins over a 4096-value window
+// around the median; a bright star that stretches the range first gets a
+// coarse histogram that locates that window) the counts, sums and exact
+// median of every pass come from the histogram's prefix, and all sums are
+// exact integers: no per-pixel work after the histogram, unless an interval
+// or a median leaves the window (then exact passes over the registers).
+// The clip decisions are taken in FP64 on exact statistics, like the FP64
+// definition.
+constexpr int kU16Bins = 1024;            // 64 lanes x 16 bins
+constexpr int kU16Per = kU16Bins / 64;
+
+// The window's prefix sums: p0[b] = pixels in bins [0, b), p1[b] and p2[b]
+// their sums of (bin) and (bin)^2; index kU16Bins holds the totals.
+struct MeshU16Shared {
+    uint32_t p0[kU16Bins + 1];          // histogram, then its prefix
+    uint32_t p1[kU16Bins + 1];
+    uint64_t p2[kU16Bins + 1];
+    uint64_t pa[2][kMaxWaves][2];       // block partials, double-buffered
+    uint32_t pc[2][kMaxWaves][4];
+    uint64_t ws[kMaxWaves][2];          // wavefront totals of the scan
+    uint32_t wc[kMaxWaves];
+};
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int o) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, o), hi = __shfl_xor((uint32_t)(v >> 32), o);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int o) {
+    const uint32_t lo = __shfl_up((uint32_t)v, o), hi = __shfl_up((uint32_t)(v >> 32), o);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// exact block sums: two counts, two 64-bit sums, min and max (integers: the
+// order of the additions does not matter)
+template <int NT>
+__device__ __forceinline__ void block_u16(uint32_t& c0, uint32_t& c1, uint64_t& s1, uint64_t& s2, uint32_t& mn,
+                                          uint32_t& mx, int& par, MeshU16Shared& sh) {
+    constexpr int NW = NT / 64;
+    const int w = threadIdx.x >> 6;
+    const int P = par;
+    par ^= 1;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        c0 += __shfl_xor(c0, o);
+        c1 += __shfl_xor(c1, o);
+        s1 += shfl_xor_u64(s1, o);
+        s2 += shfl_xor_u64(s2, o);
+        mn = min(mn, (uint32_t)__shfl_xor(mn, o));
+        mx = max(mx, (uint32_t)__shfl_xor(mx, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh.pc[P][w][0] = c0;
+        sh.pc[P][w][1] = c1;
+        sh.pc[P][w][2] = mn;
+        sh.pc[P][w][3] = mx;
+        sh.pa[P][w][0] = s1;
+        sh.pa[P][w][1] = s2;
+    }
+    __syncthreads();
+    c0 = c1 = 0u;
+    s1 = s2 = 0ull;
+    mn = 0xffffffffu;
+    mx = 0u;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        c0 += sh.pc[P][i][0];
+        c1 += sh.pc[P][i][1];
+        mn = min(mn, sh.pc[P][i][2]);
+        mx = max(mx, sh.pc[P][i][3]);
+        s1 += sh.pa[P][i][0];
+        s2 += sh.pa[P][i][1];
+    }
+}
+
+// histogram in p0 -> exclusive prefix sums p0, p1, p2 (bins split evenly
+// over the block, each thread a contiguous run)
+template <int NT>
+__device__ __forceinline__ void u16_prefix(MeshU16Shared& sh) {
+    constexpr int PER = kU16Bins / NT;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t c[PER], tc = 0, t1 = 0;
+    uint64_t t2 = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const uint32_t b = (uint32_t)(t * PER + i);
+        c[i] = sh.p0[b];
+        tc += c[i];
+        t1 += c[i] * b;
+        t2 += (uint64_t)c[i] * b * b;
+    }
+    uint32_t ic = tc, i1 = t1;
+    uint64_t i2 = t2;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t yc = __shfl_up(ic, o), y1 = __shfl_up(i1, o);
+        const uint64_t y2 = shfl_up_u64(i2, o);
+        if (lane >= o) {
+            ic += yc;
+            i1 += y1;
+            i2 += y2;
+        }
+    }
+    if (lane == 63) {
+        sh.wc[w] = ic;
+        sh.ws[w][0] = i1;
+        sh.ws[w][1] = i2;
+    }
+    __syncthreads();
+    uint32_t rc = ic - tc, r1 = i1 - t1;
+    uint64_t r2 = i2 - t2;
+    for (int i = 0; i < w; ++i) {
+        rc += sh.wc[i];
+        r1 += (uint32_t)sh.ws[i][0];
+        r2 += sh.ws[i][1];
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const uint32_t b = (uint32_t)(t * PER + i);
+        sh.p0[b] = rc;
+        sh.p1[b] = r1;
+        sh.p2[b] = r2;
+        rc += c[i];
+        r1 += c[i] * b;
+        r2 += (uint64_t)c[i] * b * b;
+    }
+    if (t == NT - 1) {
+        sh.p0[kU16Bins] = rc;
+        sh.p1[kU16Bins] = r1;
+        sh.p2[kU16Bins] = r2;
+    }
+    __syncthreads();
+}
+
+// largest bin b with p0[b] <= g (0 <= g < total): two LDS reads and ballots
+// per wavefront, no barrier
+__device__ __forceinline__ int u16_find(const MeshU16Shared& sh, uint32_t g) {
+    const int lane = threadIdx.x & 63;
+    const int c = __popcll(__ballot(sh.p0[lane * kU16Per] <= g)) - 1;
+    const bool le = lane < kU16Per && sh.p0[c * kU16Per + lane] <= g;
+    return c * kU16Per + __popcll(__ballot(le)) - 1;
+}
+
+template <int NT, int PPT, bool ONE>
+__global__ __launch_bounds__(NT) void k_mesh_stats_u16(FrameDesc* __restrict__ desc, FrameDesc d1, int nframes,
+                                                       BkgArgs a) {
+    __shared__ MeshU16Shared sh;
+    constexpr uint32_t kNone = 0xffffffffu;   // padding / not a pixel
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int gm = blockIdx.x;
+    if (ONE && gm == 0 && tid == 0) desc[0] = d1;
+    const int f = ONE ? 0 : frame_of(nframes, gm, [&](int i) { return desc[i].mesh_base; });
+    const FrameDesc d = ONE ? d1 : desc[f];
+    if (d.dtype != kDtypeU16) return;   // float32 frames of a mixed batch: the float kernel
+    const int lm = gm - d.mesh_base;
+    const int mi = lm % d.nx, mj = lm / d.nx;
+    const int x0 = mi * d.mw, y0 = mj * d.mh;
+    const int w = min(d.mw, d.W - x0), h = min(d.mh, d.H - y0);
+    const int n = w * h;
+    const int out_idx = mj * d.nx + mi;
+
+    // 1. the mesh's pixels into registers (pixel k * NT + tid of the mesh)
+    uint32_t u[PPT];
+    {
+        const int dy = NT / w, dx = NT - dy * w;
+        int yy = tid / w, xx = tid - yy * w;
+        if (n == NT * PPT && dx == 0 && (int64_t)h * d.pitch * 2 < ((int64_t)1 << 31)) {
+            const int64_t o0 = ((int64_t)y0 * d.pitch + x0) * 2;
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)d.data + o0), (short)0, 0x7fffffff, 0x00020000);
+            const int vo = (yy * (int)d.pitch + xx) * 2;
+            const int so = dy * (int)d.pitch * 2;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) u[k] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, vo, k * so, 0);
+        } else {
+            const gu16_t* src = (const gu16_t*)d.data;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                u[k] = kNone;
+                if (k * NT + tid < n) u[k] = (uint32_t)src[(int64_t)(y0 + yy) * d.pitch + x0 + xx];
+                xx += dx;
+                yy += dy;
+                if (xx >= w) {
+                    xx -= w;
+                    ++yy;
+                }
+            }
+        }
+    }
+    // 2. count, min, max and the exact sums of (v - c0), (v - c0)^2 about the
+    //    mesh's first pixel c0 (then re-centred on the minimum), one barrier
+    const uint32_t c0 = (uint32_t)((const gu16_t*)d.data)[(int64_t)y0 * d.pitch + x0];
+    uint32_t na = 0u, unused = 0u, mn = 0xffffffffu, mx = 0u;
+    uint64_t t1 = 0ull, t2 = 0ull;   // (v - c0) as two's complement, (v - c0)^2
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const uint32_t v = u[k];
+        if (v != kNone) {
+            const int64_t e = (int64_t)v - (int64_t)c0;
+            ++na;
+            t1 += (uint64_t)e;
+            t2 += (uint64_t)(e * e);
+            mn = min(mn, v);
+            mx = max(mx, v);
+        }
+    }
+    int par = 0;
+    block_u16<NT>(na, unused, t1, t2, mn, mx, par, sh);
+    if (mn == mx) {
+        if (tid == 0) {
+            d.back_raw[out_idx] = (double)mn;
+            d.rms_raw[out_idx] = 0.0;
+            d.iters[out_idx] = 0;
+        }
+        return;
+    }
+    {
+        // about the minimum: S1' = S1 + n (c0 - mn), S2' = S2 + 2 (c0 - mn) S1 + n (c0 - mn)^2
+        const int64_t sh0 = (int64_t)c0 - (int64_t)mn;
+        const int64_t s1 = (int64_t)t1;
+        t2 = (uint64_t)((int64_t)t2 + 2 * sh0 * s1 + (int64_t)na * sh0 * sh0);
+        t1 = (uint64_t)(s1 + (int64_t)na * sh0);
+    }
+    // exact statistics of the pixels in [lo, hi] from the registers (all
+    // wavefronts, one barrier): count, count below lo, sums of (v - mn)^p
+    auto reg_stats = [&](uint32_t lo, uint32_t hi, uint32_t& c, uint32_t& below, uint64_t& s1, uint64_t& s2) {
+        c = below = 0u;
+        s1 = s2 = 0ull;
+        uint32_t z0 = 0xffffffffu, z1 = 0u;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const uint32_t v = u[k];
+            const bool in = v != kNone && v >= lo && v <= hi;
+            const uint64_t dd = (uint64_t)(v - mn);
+            c += in ? 1u : 0u;
+            below += (v < lo) ? 1u : 0u;
+            s1 += in ? dd : 0ull;
+            s2 += in ? dd * dd : 0ull;
+        }
+        block_u16<NT>(c, below, s1, s2, z0, z1, par, sh);
+    };
+    // 3. histogram window: 1-ADU bins over [wlo, wlo + NB) holding the
+    //    median, with prefix sums; cbw = pixels below it
+    int sft = 0;
+    while (((mx - mn) >> sft) >= (uint32_t)kU16Bins) ++sft;
+    for (int b = tid; b < kU16Bins; b += NT) sh.p0[b] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PPT; ++k)
+        if (u[k] != kNone) atomicAdd(&sh.p0[(u[k] - mn) >> sft], 1u);
+    __syncthreads();
+    u16_prefix<NT>(sh);
+    uint32_t wlo = mn, cbw = 0u;
+    if (sft > 0) {
+        // the coarse bin of the lower median; the window starts half a window
+        // below it, on a coarse-bin boundary
+        const int bm = u16_find(sh, (na - 1) / 2);
+        const int b0 = max(0, bm - ((kU16Bins / 2) >> sft));
+        cbw = sh.p0[b0];
+        wlo = mn + ((uint32_t)b0 << sft);
+        __syncthreads();
+        for (int b = tid; b < kU16Bins; b += NT) sh.p0[b] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const uint32_t r = u[k] - wlo;   // (kNone and values below wlo wrap above NB)
+            if (u[k] != kNone && r < (uint32_t)kU16Bins) atomicAdd(&sh.p0[r], 1u);
+        }
+        __syncthreads();
+        u16_prefix<NT>(sh);
+    }
+    const uint32_t wtot = sh.p0[kU16Bins];
+    const uint32_t whi = wlo + (uint32_t)kU16Bins - 1u;   // last value inside the window
+    // From here every wavefront runs the clipping loop by itself on the same
+    // data (uniform results, no barrier), except for the rare intervals or
+    // ranks outside the window, which take block-wide register passes.
+    auto stats = [&](uint32_t lo, uint32_t hi, uint32_t& c, uint32_t& below, uint64_t& s1, uint64_t& s2) {
+        if (lo >= wlo && hi <= whi) {
+            const uint32_t a0 = lo - wlo, a1 = hi - wlo + 1;
+            c = sh.p0[a1] - sh.p0[a0];
+            const uint64_t q1 = (uint64_t)(sh.p1[a1] - sh.p1[a0]);
+            const uint64_t q2 = sh.p2[a1] - sh.p2[a0];
+            // sums of (v - mn) = (bin + off)
+            const uint64_t off = (uint64_t)(wlo - mn);
+            s1 = q1 + off * c;
+            s2 = q2 + 2ull * off * q1 + off * off * c;
+            below = cbw + sh.p0[a0];
+        } else {
+            reg_stats(lo, hi, c, below, s1, s2);
+        }
+    };
+    // value of global rank g (0-based over all the mesh's pixels) within [lo, hi]
+    auto value_at = [&](uint32_t g, uint32_t lo, uint32_t hi) -> uint32_t {
+        if (g >= cbw && g < cbw + wtot) return wlo + (uint32_t)u16_find(sh, g - cbw);
+        // outside the window: bisection on the smallest x with #(v <= x) > g
+        uint32_t zl = lo, zh = hi;
+        while (zl < zh) {
+            const uint32_t mid = zl + ((zh - zl) >> 1);
+            uint32_t c, bl;
+            uint64_t s1, s2;
+            reg_stats(0u, mid, c, bl, s1, s2);
+            if (c > g) zh = mid;
+            else zl = mid + 1;
+        }
+        return zl;
+    };
+    auto sigma_of = [&](uint32_t c, uint64_t s1, uint64_t s2) {
+        // n^2 var = n S2 - S1^2, exact in 64-bit integers (< 2^61)
+        const uint64_t num = (uint64_t)c * s2 - s1 * s1;
+        const double nd = (double)c;
+        return sqrt((double)num / (nd * nd));
+    };
+    const double sig0 = sigma_of(na, t1, t2);
+    double sig = sig0;
+    double mean = (double)mn + (double)t1 / (double)na;
+    uint32_t L = mn, H = mx, below = 0u;
+    auto median = [&]() {
+        const uint32_t r2 = na / 2, r1 = (na & 1) ? r2 : r2 - 1;
+        const uint32_t v1 = value_at(below + r1, L, H);
+        const uint32_t v2 = (r2 == r1) ? v1 : value_at(below + r2, L, H);
+        return 0.5 * ((double)v1 + (double)v2);
+    };
+    double med = median();
+    const double clip = (double)a.clip;
+    int iters = 0;
+    for (int it = 0; it < a.max_iter; ++it) {
+        const double lim = clip * sig;
+        // the new interval: every integer v of [L, H] with |v - med| <= lim
+        // (the differences are exact; the bounds from FP64 are nudged to the
+        // exact decision)
+        double cl = ceil(med - lim), ch = floor(med + lim);
+        while (cl - 1.0 >= (double)L && med - (cl - 1.0) <= lim) cl -= 1.0;
+        while (cl <= (double)H && med - cl > lim) cl += 1.0;
+        while (ch + 1.0 <= (double)H && (ch + 1.0) - med <= lim) ch += 1.0;
+        while (ch >= (double)L && ch - med > lim) ch -= 1.0;
+        const uint32_t Ln = (uint32_t)fmax(cl, (double)L), Hn = (uint32_t)fmin(ch, (double)H);
+        uint32_t c = 0u, bl = 0u;
+        uint64_t s1 = 0ull, s2 = 0ull;
+        if (Ln <= Hn) stats(Ln, Hn, c, bl, s1, s2);
+        ++iters;
+        if (c == na || c == 0u) break;
+        L = Ln;
+        H = Hn;
+        na = c;
+        below = bl;
+        sig = (L == H) ? 0.0 : sigma_of(c, s1, s2);
+        mean = (double)mn + (double)s1 / (double)c;
+        med = median();
+    }
+    if (tid == 0) {
+        const double dsig = fabs(sig - sig0);
+        const double back = (dsig < (double)a.crowd * sig0) ? mean
+                                                             : ((double)a.mode_a * med - (double)a.mode_b * mean);
+        d.back_raw[out_idx] = back;
+        d.rms_raw[out_idx] = sig;
+        d.iters[out_idx] = iters;
+    }
+}
 
 // ---------------------------------------------------------------------------
 // f x f median over the mesh grid, back and rms separately
@@ -1356,6 +1719,27 @@ static void launch_mesh_nt(FrameDesc* desc, const FrameDesc* one, int nframes, i
                            hipStream_t s) {
     if (one) k_mesh_stats<NT, PPT, true><<<total_meshes, NT, 0, s>>>(desc, *one, nframes, a);
     else k_mesh_stats<NT, PPT, false><<<total_meshes, NT, 0, s>>>(desc, FrameDesc{}, nframes, a);
+}
+
+template <int NT, int PPT>
+static void launch_mesh_u16_nt(FrameDesc* desc, const FrameDesc* one, int nframes, int total_meshes, BkgArgs a,
+                               hipStream_t s) {
+    if (one) k_mesh_stats_u16<NT, PPT, true><<<total_meshes, NT, 0, s>>>(desc, *one, nframes, a);
+    else k_mesh_stats_u16<NT, PPT, false><<<total_meshes, NT, 0, s>>>(desc, FrameDesc{}, nframes, a);
+}
+
+// uint16 meshes; cfg as for the float kernel (threads x pixels per thread)
+void launch_mesh_stats_u16(FrameDesc* desc, const FrameDesc* one, int nframes, int total_meshes, int max_area,
+                           BkgArgs a, int cfg, hipStream_t s) {
+    if (cfg == 0) cfg = (max_area <= 4096) ? 1 : (max_area <= 8192) ? 2 : 3;
+    if (cfg == 1 && max_area > 4096) cfg = 3;
+    if (cfg == 2 && max_area > 8192) cfg = 3;
+    switch (cfg) {
+        case 1: launch_mesh_u16_nt<256, 16>(desc, one, nframes, total_meshes, a, s); break;
+        case 2: launch_mesh_u16_nt<512, 16>(desc, one, nframes, total_meshes, a, s); break;
+        case 4: launch_mesh_u16_nt<1024, 16>(desc, one, nframes, total_meshes, a, s); break;
+        default: launch_mesh_u16_nt<512, 32>(desc, one, nframes, total_meshes, a, s); break;
+    }
 }
 
 void launch_mesh_stats(FrameDesc* desc, const FrameDesc* one, int nframes, int total_meshes, int max_area, BkgArgs a,

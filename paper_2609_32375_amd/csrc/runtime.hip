@@ -617,7 +617,10 @@ extern "C" gp_status gp_background(gp_ctx* ctx, const gp_frame* frames, int32_t 
     if ((st = upload_desc(frames, nframes, bp, P, bkg, ws, 0, nullptr, s, one ? &tail : nullptr)) != GP_OK) return st;
     FrameDesc* desc = (FrameDesc*)((char*)ws + P.o_desc);
     if (!(bp->flags & GP_BKG_GRID_GIVEN)) {
-        BkgArgs a{bp->clip_sigma, bp->crowd_tol, bp->mode_a, bp->mode_b, bp->max_iter, bp->filter_size};
+        bool any_u16 = false, any_f32 = false;
+        for (int f = 0; f < nframes; ++f) (frames[f].dtype == GP_U16 ? any_u16 : any_f32) = true;
+        BkgArgs a{bp->clip_sigma, bp->crowd_tol, bp->mode_a, bp->mode_b, bp->max_iter, bp->filter_size,
+                  any_u16 ? 1 : 0};
         {
             ProfScope ps(ctx, s, "mesh_stats");
             std::vector<int> cands;
@@ -625,14 +628,26 @@ extern "C" gp_status gp_background(gp_ctx* ctx, const gp_frame* frames, int32_t 
             if (P.max_area <= 8192) cands.push_back(2);
             cands.push_back(3);
             cands.push_back(4);
-            const int cfg = ctx->mesh_cfg ? ctx->mesh_cfg
-                                          : choose(ctx, "mesh_stats:" + std::to_string(P.max_area), cands, 0, s,
-                                                   [&](int k) {
-                                                       launch_mesh_stats(desc, one ? &tail.d[0] : nullptr,
-                                                                         nframes, (int)P.total_meshes,
-                                                                         P.max_area, a, k, s);
-                                                   });
-            launch_mesh_stats(desc, one ? &tail.d[0] : nullptr, nframes, (int)P.total_meshes, P.max_area, a, cfg, s);
+            const FrameDesc* d1 = one ? &tail.d[0] : nullptr;
+            if (any_u16) {
+                // uint16 frames: exact integer statistics
+                const int cfg = ctx->mesh_cfg ? ctx->mesh_cfg
+                                              : choose(ctx, "mesh_stats_u16:" + std::to_string(P.max_area), cands, 0,
+                                                       s, [&](int k) {
+                                                           launch_mesh_stats_u16(desc, d1, nframes, (int)P.total_meshes,
+                                                                                 P.max_area, a, k, s);
+                                                       });
+                launch_mesh_stats_u16(desc, d1, nframes, (int)P.total_meshes, P.max_area, a, cfg, s);
+            }
+            if (any_f32) {
+                const int cfg = ctx->mesh_cfg ? ctx->mesh_cfg
+                                              : choose(ctx, "mesh_stats:" + std::to_string(P.max_area), cands, 0, s,
+                                                       [&](int k) {
+                                                           launch_mesh_stats(desc, d1, nframes, (int)P.total_meshes,
+                                                                             P.max_area, a, k, s);
+                                                       });
+                launch_mesh_stats(desc, d1, nframes, (int)P.total_meshes, P.max_area, a, cfg, s);
+            }
         }
         HIP_TRY(hipGetLastError());
     }

@@ -109,6 +109,46 @@ def test_mesh_statistics_structured(P, m):
     ph.close()
 
 
+def _structured_meshes_u16(m, seed):
+    """uint16 meshes (4 x 3 of m x m) for the integer statistics kernel: the
+    float structured set rounded and clipped (ties, a bright source over a
+    third, two levels, bimodal, saturated pixels, a saturated star with a
+    bleed trail, a steep ramp), plus a Gaussian sky, values spread over the
+    whole 16-bit range, a tight cluster with a far saturated block, and a
+    mesh of one value plus a single different pixel."""
+    base = _structured_meshes(m, seed).astype(np.float64)
+    blocks = [base[:m, i * m:(i + 1) * m] for i in range(4)] + [base[m:, i * m:(i + 1) * m] for i in range(4)]
+    blocks[2] = 20.0 + blocks[2] * 1e4                   # the tiny mesh, lifted into integers
+    rng = np.random.default_rng(seed + 1)
+    n = m * m
+    sky = (1000.0 + 33.0 * rng.standard_normal(n)).reshape(m, m)
+    spread = rng.uniform(0, 65535, n).reshape(m, m)
+    far = (500.0 + 3.0 * rng.standard_normal(n))
+    far[: n // 10] = 65535.0
+    rng.shuffle(far)
+    one = np.full(n, 4321.0)
+    one[n // 2] = 4400.0
+    blocks += [sky, spread, far.reshape(m, m), one.reshape(m, m)]
+    img = np.block([blocks[0:4], blocks[4:8], blocks[8:12]])
+    return np.ascontiguousarray(np.clip(np.rint(img), 0, 65535).astype(np.uint16))
+
+
+@pytest.mark.parametrize("m", [64, 96, 128])
+def test_mesh_statistics_structured_u16(P, m):
+    """The integer statistics kernel of uint16 frames on meshes that stress
+    its window, bisection and interval paths (4096, 9216 and 16384 pixels)."""
+    _say("structured uint16 meshes", m)
+    img = _structured_meshes_u16(m, 17 + m)
+    p = _params("c1", mesh_w=m, mesh_h=m, mesh_filter=1)
+    ph = P.Photometry([_dev(img)], p, p.kernel(), capacity=64)
+    ph.background()
+    g = ph.grids(0)
+    _, _, flipped = check_meshes(img, g, p)
+    st = oracle.mesh_stats(img.astype(np.float64), m, m, p.clip_sigma, p.crowd_tol, p.mode_a, p.mode_b, p.max_iter)
+    _say("ambiguous", int(mesh_ambiguous(st).sum()), "flipped", flipped, "iters", st["iters"].ravel().tolist())
+    ph.close()
+
+
 @pytest.mark.parametrize("case", MESH_CASES, ids=lambda c: f"{c[0]}-{c[1]}x{c[2]}-{c[3]}-m{c[4]}x{c[5]}")
 def test_mesh_statistics_match_oracle(P, case):
     name, W, H, dt, mw, mh, seed = case
