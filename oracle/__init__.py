@@ -64,12 +64,14 @@ def lib():
                                          C.POINTER(C.c_long)]
         L.or_measure.argtypes = [dp, dp, ip, C.c_long, C.c_long, C.c_long, C.c_double, ip, ip, ip, ip, ip,
                                  lp, dp, dp, dp, dp, dp, dp, dp, up]
+        L.or_peaks.argtypes = [dp, dp, dp, dp, C.c_long, C.c_long, C.c_double, C.c_int, C.c_int, C.c_double,
+                               C.c_long, ip, ip, ip, ip, ip, lp, dp, dp, dp, dp, dp, dp, dp, up, C.POINTER(C.c_long)]
         L.or_overlap.argtypes = [C.c_double] * 7
         L.or_overlap.restype = C.c_double
         L.or_aperture.argtypes = [dp, dp, C.c_long, C.c_long, dp, dp, C.c_long, dp, C.c_int, C.c_double,
                                   C.c_double, C.c_double, C.c_int, dp, dp, dp, dp, up]
         for f in ("or_mesh_one", "or_mesh_one_policy", "or_mesh_stats", "or_median_filter", "or_grid_eval", "or_grid_map",
-                  "or_filter", "or_threshold_label", "or_measure", "or_aperture"):
+                  "or_filter", "or_threshold_label", "or_measure", "or_aperture", "or_peaks"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -241,6 +243,51 @@ def measure(I, M, seg, nobj, sat=np.inf):
     cat.update(dbl)
     cat["flags"] = flags
     return {k: v[:nobj] for k, v in cat.items()}
+
+
+PEAK_FIELDS = ("npix", "xmin", "xmax", "ymin", "ymax", "pmin", "flux", "x", "y", "x2", "y2", "xy", "peak",
+               "flags")
+
+
+def peaks(I, M, F, R, thresh, sep, cwin, sat=np.inf, cap=None):
+    """Local maxima of F / R above the threshold with first-moment centroids
+    (catalogue columns as measure(); `peak` holds the significance)."""
+    Ii, Mm, Ff, Rr = _f64(I), _f64(M), _f64(F), _f64(R)
+    H, W = Mm.shape
+    cap = W * H if cap is None else cap
+    n = C.c_long(0)
+    c = max(cap, 1)
+    ints = {k: np.zeros(c, np.int32) for k in ("npix", "xmin", "xmax", "ymin", "ymax")}
+    pidx = np.zeros(c, np.int64)
+    dbl = {k: np.zeros(c) for k in ("flux", "x", "y", "x2", "y2", "xy", "peak")}
+    flags = np.zeros(c, np.uint32)
+    _check(lib().or_peaks(_p(Ii), _p(Mm), _p(Ff), _p(Rr), W, H, thresh, sep, cwin, sat, cap,
+                          *[_p(ints[k], C.c_int32) for k in ("npix", "xmin", "xmax", "ymin", "ymax")],
+                          _p(pidx, C.c_int64), *[_p(dbl[k]) for k in ("flux", "x", "y", "x2", "y2", "xy", "peak")],
+                          _p(flags, C.c_uint32), C.byref(n)), "peaks")
+    k = min(int(n.value), cap)
+    out = {q: v[:k] for q, v in ints.items()}
+    out["pmin"] = pidx[:k]
+    out.update({q: v[:k] for q, v in dbl.items()})
+    out["flags"] = flags[:k]
+    out["n"] = int(n.value)
+    return out
+
+
+def run_peaks(img, p, sep, cwin, K=None, grids=None):
+    """Background -> M = I - B -> F = Khat (x) M -> local maxima of F / R."""
+    I = _f64(img)
+    H, W = I.shape
+    if grids is None:
+        bk = background(I, p)
+    else:
+        back, rms = (_f64(g) for g in grids)
+        bk = Background({}, back, rms, grid_map(back, W, H, p.mesh_w, p.mesh_h),
+                        grid_map(rms, W, H, p.mesh_w, p.mesh_h))
+    M = I - bk.B
+    K = p.kernel() if K is None else K
+    F = filter_image(M, K)
+    return bk, M, F, peaks(I, M, F, bk.R, p.thresh, sep, cwin, p.sat_level)
 
 
 # ----------------------------------------------------------------------------

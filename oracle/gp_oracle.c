@@ -719,3 +719,108 @@ int or_aperture(const double* M, const double* R, long W, long H, const double* 
     }
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Peak detection (the paper's own detection: local maxima of the matched-   */
+/* filter significance)                                                      */
+/* ------------------------------------------------------------------------ */
+/* significance of pixel p: the filtered frame divided by the noise map (a
+ * zero noise map leaves F itself) */
+static double nu_of(const double* F, const double* R, long p) { return (R[p] > 0.0) ? F[p] / R[p] : F[p]; }
+
+/*
+ * Sources are the local maxima of the significance nu = F / R above the
+ * threshold (Source Detection subsection: matched filter divided by the noise
+ * map, local maxima above a significance threshold found with a maximum
+ * filter, sub-pixel positions from a first-moment centroid; the FWHM sets the
+ * separation and centroid windows).  Readings:
+ *   - candidate: F > thresh * R (the strict threshold of the mask);
+ *   - local maximum: nu(p) >= nu(q) for every q of the (2 sep + 1)^2 window
+ *     around p inside the frame, strictly > for q earlier in raster order
+ *     (one peak per plateau, its first pixel);
+ *   - centroid over the (2 cwin + 1)^2 window around the peak inside the
+ *     frame with weights max(M, 0): x = px + sum w dx / sum w, and the second
+ *     moments about it; with no positive weight the peak pixel itself and
+ *     NONPOS;
+ *   - flux = sum of M over that window; npix = its pixel count; bbox = the
+ *     window; EDGE when the window is cut by the frame border; SATURATED when
+ *     a raw pixel of the window reaches sat.
+ * Peaks come in raster order of the peak pixel; at most cap are stored, *n
+ * receives how many there are.
+ */
+int or_peaks(const double* I, const double* M, const double* F, const double* R, long W, long H,
+             double thresh, int sep, int cwin, double sat, long cap, int32_t* npix, int32_t* xmin,
+             int32_t* xmax, int32_t* ymin, int32_t* ymax, int64_t* pidx, double* flux, double* xc,
+             double* yc, double* x2, double* y2, double* xy, double* nu, uint32_t* flags, long* n) {
+    if (!I || !M || !F || !R || !n || W <= 0 || H <= 0 || sep < 0 || cwin < 0 || cap < 0) return OR_EINVAL;
+    long k = 0;
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) {
+            const long p = y * W + x;
+            if (!(F[p] > thresh * R[p])) continue;
+            const double v = nu_of(F, R, p);
+            int is_max = 1;
+            for (long qy = y - sep; qy <= y + sep && is_max; ++qy)
+                for (long qx = x - sep; qx <= x + sep; ++qx) {
+                    if (qx < 0 || qx >= W || qy < 0 || qy >= H || (qx == x && qy == y)) continue;
+                    const long q = qy * W + qx;
+                    const double vq = nu_of(F, R, q);
+                    if (vq > v || (vq == v && q < p)) {
+                        is_max = 0;
+                        break;
+                    }
+                }
+            if (!is_max) continue;
+            if (k < cap) {
+                double sw = 0.0, sx = 0.0, sy = 0.0, sxx = 0.0, syy = 0.0, sxy = 0.0, fl = 0.0;
+                long cnt = 0;
+                uint32_t f = 0u;
+                const long x0 = x - cwin < 0 ? 0 : x - cwin, x1 = x + cwin >= W ? W - 1 : x + cwin;
+                const long y0 = y - cwin < 0 ? 0 : y - cwin, y1 = y + cwin >= H ? H - 1 : y + cwin;
+                if (x0 != x - cwin || x1 != x + cwin || y0 != y - cwin || y1 != y + cwin) f |= OR_FLAG_EDGE;
+                for (long qy = y0; qy <= y1; ++qy)
+                    for (long qx = x0; qx <= x1; ++qx) {
+                        const long q = qy * W + qx;
+                        const double m = M[q];
+                        const double w = m > 0.0 ? m : 0.0;
+                        const double dx = (double)(qx - x), dy = (double)(qy - y);
+                        sw += w;
+                        sx += w * dx;
+                        sy += w * dy;
+                        sxx += w * dx * dx;
+                        syy += w * dy * dy;
+                        sxy += w * dx * dy;
+                        fl += m;
+                        ++cnt;
+                        if (I[q] >= sat) f |= OR_FLAG_SATURATED;
+                    }
+                double mx = 0.0, my = 0.0, vx = 0.0, vy = 0.0, cxy = 0.0;
+                if (sw > 0.0) {
+                    mx = sx / sw;
+                    my = sy / sw;
+                    vx = sxx / sw - mx * mx;
+                    vy = syy / sw - my * my;
+                    cxy = sxy / sw - mx * my;
+                } else {
+                    f |= OR_FLAG_NONPOS;
+                }
+                npix[k] = (int32_t)cnt;
+                xmin[k] = (int32_t)x0;
+                xmax[k] = (int32_t)x1;
+                ymin[k] = (int32_t)y0;
+                ymax[k] = (int32_t)y1;
+                pidx[k] = p;
+                flux[k] = fl;
+                xc[k] = (double)x + mx;
+                yc[k] = (double)y + my;
+                x2[k] = vx;
+                y2[k] = vy;
+                xy[k] = cxy;
+                nu[k] = v;
+                flags[k] = f;
+            }
+            ++k;
+        }
+    *n = k;
+    return OR_OK;
+}

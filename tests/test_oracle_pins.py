@@ -588,3 +588,105 @@ def test_chain_finds_injected_stars():
     assert found == bright.sum()
     # large-aperture fluxes of bright isolated stars approach the injected flux
     assert np.all(np.isfinite(res.phot["flux"]))
+
+
+# ----------------------------------------------------------------------------
+# peak detection (local maxima of the significance, first-moment centroids)
+# ----------------------------------------------------------------------------
+def test_peaks_equal_scipy_maximum_filter():
+    # continuous random significance (no ties): peaks = above threshold and
+    # equal to the maximum filter over the window truncated at the edges
+    from scipy import ndimage
+    rng = np.random.default_rng(21)
+    for trial in range(8):
+        H, W = rng.integers(20, 70, 2)
+        F = rng.normal(0, 3, (H, W))
+        R = rng.uniform(0.5, 2.0, (H, W))
+        M = rng.normal(0, 1, (H, W))
+        sep = int(rng.integers(0, 5))
+        t = 1.0
+        nu = F / R
+        mx = ndimage.maximum_filter(nu, size=2 * sep + 1, mode="constant", cval=-np.inf)
+        want = np.flatnonzero(((F > t * R) & (nu == mx)).ravel())
+        got = oracle.peaks(M, M, F, R, t, sep, 1)
+        np.testing.assert_array_equal(got["pmin"], want)
+        assert got["n"] == want.size
+        np.testing.assert_array_equal(got["peak"], nu.ravel()[want])
+
+
+def test_peaks_plateau_and_separation():
+    F = np.zeros((20, 30))
+    R = np.ones_like(F)
+    F[5:8, 10:13] = 7.0                 # a 3 x 3 plateau: one peak, its first pixel
+    F[12, 4] = 5.0                      # two maxima 3 px apart
+    F[12, 7] = 6.0
+    M = F.copy()
+    got = oracle.peaks(M, M, F, R, 1.0, 3, 1)
+    assert list(got["pmin"]) == [5 * 30 + 10, 12 * 30 + 7]
+    got = oracle.peaks(M, M, F, R, 1.0, 2, 1)
+    assert list(got["pmin"]) == [5 * 30 + 10, 12 * 30 + 4, 12 * 30 + 7]
+    # threshold strict: F == t R is not a candidate
+    got = oracle.peaks(M, M, F, R, 7.0, 1, 1)
+    assert list(got["pmin"]) == []
+
+
+def test_peak_centroid_closed_forms():
+    # a blob symmetric about a pixel centre: centroid at that pixel, xy = 0
+    H, W = 41, 37
+    yy, xx = np.mgrid[0:H, 0:W]
+    M = np.exp(-((xx - 17) ** 2 + (yy - 21) ** 2) / (2 * 1.7 ** 2)) * 100
+    F, R = M.copy(), np.ones_like(M)
+    got = oracle.peaks(M, M, F, R, 1.0, 3, 4)
+    assert got["n"] == 1 and got["pmin"][0] == 21 * W + 17
+    assert got["x"][0] == 17.0 and got["y"][0] == 21.0 and abs(got["xy"][0]) < 1e-14
+    assert got["x2"][0] == pytest.approx(got["y2"][0], rel=1e-14)
+    # a uniform 3 x 3 block with a 1-pixel window: x2 = y2 = 2/3
+    M = np.zeros((9, 9))
+    M[3:6, 3:6] = 2.0
+    F = M.copy()
+    F[4, 4] = 3.0
+    got = oracle.peaks(M, M, F, np.ones_like(F), 1.0, 1, 1)
+    assert got["n"] == 1 and got["x"][0] == 4.0 and got["y"][0] == 4.0
+    assert got["x2"][0] == pytest.approx(2 / 3, rel=1e-14) and got["y2"][0] == pytest.approx(2 / 3, rel=1e-14)
+    assert got["flux"][0] == pytest.approx(18.0) and got["npix"][0] == 9
+    # translation invariance of the centroid offset
+    rng = np.random.default_rng(5)
+    M = rng.uniform(-1, 5, (30, 30))
+    F = np.zeros_like(M)
+    F[12, 14] = 10.0
+    a = oracle.peaks(M, M, F, np.ones_like(F), 1.0, 2, 3)
+    M2 = np.roll(np.roll(M, 4, axis=0), 3, axis=1)
+    F2 = np.roll(np.roll(F, 4, axis=0), 3, axis=1)
+    b = oracle.peaks(M2, M2, F2, np.ones_like(F2), 1.0, 2, 3)
+    assert b["x"][0] == pytest.approx(a["x"][0] + 3, abs=1e-12)
+    assert b["y"][0] == pytest.approx(a["y"][0] + 4, abs=1e-12)
+
+
+def test_peak_centroid_against_numpy_and_flags():
+    rng = np.random.default_rng(8)
+    H, W = 60, 50
+    I = rng.uniform(0, 100, (H, W))
+    I[2, 30] = 65535.0
+    M = rng.normal(2, 3, (H, W))
+    F = rng.normal(0, 2, (H, W))
+    R = rng.uniform(0.8, 1.2, (H, W))
+    c = 3
+    got = oracle.peaks(I, M, F, R, 1.5, 2, c, sat=65535.0)
+    assert got["n"] > 10
+    for k in range(got["n"]):
+        y, x = divmod(int(got["pmin"][k]), W)
+        y0, y1, x0, x1 = max(y - c, 0), min(y + c, H - 1), max(x - c, 0), min(x + c, W - 1)
+        win = M[y0:y1 + 1, x0:x1 + 1]
+        w = np.maximum(win, 0)
+        gy, gx = np.mgrid[y0:y1 + 1, x0:x1 + 1]
+        mx, my = (w * (gx - x)).sum() / w.sum(), (w * (gy - y)).sum() / w.sum()
+        assert got["x"][k] == pytest.approx(x + mx, abs=1e-12) and got["y"][k] == pytest.approx(y + my, abs=1e-12)
+        assert got["x2"][k] == pytest.approx((w * (gx - x) ** 2).sum() / w.sum() - mx * mx, abs=1e-10)
+        assert got["flux"][k] == pytest.approx(win.sum(), abs=1e-10)
+        edge = (x - c < 0) or (y - c < 0) or (x + c >= W) or (y + c >= H)
+        assert bool(got["flags"][k] & oracle.FLAG_EDGE) == edge
+        sat = bool((I[y0:y1 + 1, x0:x1 + 1] >= 65535.0).any())
+        assert bool(got["flags"][k] & oracle.FLAG_SATURATED) == sat
+    # capacity: the first peaks in raster order are kept, the count is whole
+    few = oracle.peaks(I, M, F, R, 1.5, 2, c, sat=65535.0, cap=3)
+    assert few["n"] == got["n"] and list(few["pmin"]) == list(got["pmin"][:3])
