@@ -334,6 +334,8 @@ def main():
         for w in ("c2", "c3"):
             out["forms"][w] = frame_form(torch, w, a)
             torch.cuda.empty_cache()
+        out["forms"]["peaks"] = form_peaks(torch, a)
+        torch.cuda.empty_cache()
         out["forms"]["served"] = form_served(torch, a)
         torch.cuda.empty_cache()
     if not a.no_cpu:
@@ -434,6 +436,48 @@ def single_frame_line(a):
             "dtype": "f32", "data": "synthetic", "config": {"workload": r["workload"], "mp": round(mp, 2),
                                                            "objects": f["objects"]},
             "kernels_ms": f["kernels_ms"], "roofline": f["roofline"], "fp64_variant": r["fp64"]}
+
+
+def form_peaks(torch, a):
+    """The paper's own detection on the batch: gp_background -> gp_peaks (local
+    maxima of F / R above 5 sigma, the paper's default; separation and
+    centroid half-widths 3 px = ceil(FWHM)) -> gp_aperture, direct calls."""
+    from paper_2609_32375_amd import _lib as L
+    from paper_2609_32375_amd.pipeline import Photometry
+    from synth import config_params
+    frames = batch_frames(torch)
+    p = config_params("c1")
+    p.thresh = 5.0
+    npx = [f.shape[0] * f.shape[1] for f in frames]
+    mp = sum(npx) / 1e6
+    ph = Photometry(frames, p, p.kernel(), capacity=65536)
+
+    def step():
+        ph.background()
+        ph.peaks(3, 3)
+        ph.aperture()
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    ms = event_time(torch, step, max(3, a.steps // 4))
+    n = int(ph.n_obj.sum().item())
+    L.gp_profile_reset(ph.ctx)
+    L.gp_profile_enable(ph.ctx, True)
+    for _ in range(a.profile_steps):
+        step()
+    torch.cuda.synchronize()
+    L.gp_profile_enable(ph.ctx, False)
+    kern = {}
+    for name in ("mesh_stats", "peaks", "aperture"):
+        tot, cnt = L.gp_profile_read(ph.ctx, name)
+        if cnt:
+            kern[name] = round(tot / cnt, 4)
+    ph.close()
+    del frames
+    log(f"peaks form: {ms:.3f} ms per batch, {n} peaks")
+    return {"workload": "the 64-frame uint16 batch; background, peaks (5 sigma, sep 3, cwin 3), apertures",
+            "ms": round(ms, 3), "mp_s": round(mp / ms * 1e3, 1), "peaks": n, "kernels_ms": kern,
+            "peaks_hbm_frac": round(2 * sum(npx) / (kern.get("peaks", 1e9) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def form_served(torch, a):

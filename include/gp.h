@@ -269,6 +269,31 @@ gp_status gp_detect_noalloc(gp_ctx* ctx, const gp_frame* frames, int32_t nframes
                             const gp_bkg_params* bp, const void* bkg, const gp_det_params* dp,
                             gp_catalog* cat, int32_t* const* seg, int32_t* comp_status, void* stream);
 
+/* Peak detection, the paper's own detection (source detection subsection):
+ * the frame minus the background is correlated with the unit-sum kernel and
+ * divided by the noise map, nu = F / R (F itself where R = 0); sources are
+ * the pixels with F > thresh * R whose nu is a maximum over the
+ * (2 sep + 1)^2 window around them inside the frame (ties go to the earlier
+ * pixel in raster order, so a plateau gives one peak), refined by a
+ * first-moment centroid over the (2 cwin + 1)^2 window inside the frame with
+ * weights max(M, 0).  The paper sets both windows from the PSF's FWHM.
+ * Uses the kernel, thresh, sat_level and precision of dp (minarea and
+ * connectivity are checked but unused).  Catalogue rows, in raster order of
+ * the peak pixel: pmin = its index, peak = nu there, x, y, x2, y2, xy = the
+ * centroid and second moments, flux = sum of M over the centroid window,
+ * npix and the bounding box = that window, flags EDGE (window cut by the
+ * border), SATURATED (a raw pixel of the window >= sat_level), NONPOS (no
+ * positive M in the window: the peak pixel itself).  n_obj, status and
+ * comp_status (peaks recorded) as for gp_detect; gp_aperture runs on the
+ * result like on a gp_detect catalogue.  sep and cwin in [0, 7]. */
+typedef struct gp_peak_params {
+    int32_t sep, cwin;
+} gp_peak_params;
+gp_status gp_peaks(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                   const gp_bkg_params* bp, const void* bkg, const gp_det_params* dp,
+                   const gp_peak_params* pp, gp_catalog* cat, int32_t* comp_status, void* ws,
+                   size_t ws_bytes, void* stream);
+
 /* Aperture photometry of every catalogued object; also ORs GP_FLAG_APER_TRUNC
  * into cat->flags. */
 gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,

@@ -59,13 +59,17 @@ class gp_catalog(C.Structure):
                 ("peak", C.c_void_p), ("flags", C.c_void_p)]
 
 
+class gp_peak_params(C.Structure):
+    _fields_ = [("sep", C.c_int32), ("cwin", C.c_int32)]
+
+
 class gp_phot(C.Structure):
     _fields_ = [("flux", C.c_void_p), ("area", C.c_void_p), ("bkg", C.c_void_p), ("fluxerr", C.c_void_p)]
 
 
 EXPORTS = ("gp_ctx_create", "gp_ctx_destroy", "gp_last_error", "gp_version", "gp_background_layout",
            "gp_workspace_size", "gp_background", "gp_background_map", "gp_detect", "gp_detect_noalloc",
-           "gp_aperture",
+           "gp_peaks", "gp_aperture",
            "gp_profile_enable",
            "gp_profile_read", "gp_profile_reset", "gp_ctx_set_tuning", "gp_graph_create", "gp_graph_launch",
            "gp_graph_rebind", "gp_graph_destroy")
@@ -106,6 +110,8 @@ def load(path: str = LIB_PATH):
                             C.c_size_t, vp]
     L.gp_detect_noalloc.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp,
                                     C.POINTER(gp_det_params), C.POINTER(gp_catalog), C.POINTER(vp), vp, vp]
+    L.gp_peaks.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp, C.POINTER(gp_det_params),
+                           C.POINTER(gp_peak_params), C.POINTER(gp_catalog), vp, vp, C.c_size_t, vp]
     L.gp_aperture.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp,
                               C.POINTER(gp_catalog), C.POINTER(gp_ap_params), C.POINTER(gp_phot), vp,
                               C.c_size_t, vp]
@@ -121,7 +127,7 @@ def load(path: str = LIB_PATH):
     L.gp_profile_read.argtypes = [vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)]
     L.gp_profile_reset.argtypes = [vp]
     for f in ("gp_ctx_create", "gp_background_layout", "gp_workspace_size", "gp_background",
-              "gp_background_map", "gp_detect", "gp_detect_noalloc",
+              "gp_background_map", "gp_detect", "gp_detect_noalloc", "gp_peaks",
               "gp_aperture", "gp_profile_enable", "gp_profile_read", "gp_profile_reset", "gp_graph_create",
               "gp_graph_launch", "gp_graph_rebind"):
         getattr(L, f).restype = C.c_int
@@ -198,6 +204,13 @@ def gp_detect_noalloc(ctx, frames, bp, bkg_ptr, dp, cat, seg_ptrs, comp_status_p
 
 
 GP_DETECT_NOALLOC_MAX_BYTES = 128 << 20
+
+
+def gp_peaks(ctx, frames, bp, bkg_ptr, dp, pp, cat, comp_status_ptr, ws_ptr, ws_bytes, stream):
+    n = len(frames)
+    arr = (gp_frame * n)(*frames)
+    check(load().gp_peaks(ctx, arr, n, C.byref(bp), bkg_ptr, C.byref(dp), C.byref(pp), C.byref(cat),
+                          comp_status_ptr, ws_ptr, ws_bytes, stream))
 
 
 def gp_aperture(ctx, frames, bp, bkg_ptr, cat, ap, phot, ws_ptr, ws_bytes, stream):

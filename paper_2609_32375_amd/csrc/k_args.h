@@ -66,6 +66,12 @@ struct CatOut {
     uint32_t* flags;
 };
 
+// peak detection: separation and centroid half-widths (pixels)
+struct PeakArgs {
+    int32_t sep, cwin;
+};
+constexpr int kMaxPeakWin = 7;
+
 // one: the descriptor of a one-frame call, passed with the launch (the kernel
 // stores it in the table for the launches that follow), or null
 void launch_mesh_stats(FrameDesc* desc, const FrameDesc* one, int nframes, int total_meshes, int max_area, BkgArgs a,
@@ -81,6 +87,9 @@ void launch_merge(const DetWork& wk, int conn, int minarea, int persist_blocks, 
 void launch_catalog(const DetWork& wk, const CatOut& cat, int minarea, int persist_blocks, int32_t* comp_status,
                     hipStream_t s);
 void launch_seg(const DetWork& wk, int f, int64_t npx, hipStream_t s);
+void launch_peaks(const DetWork& wk, const DetArgs* args, const CatOut& cat, int32_t* comp_status, bool f64, int sep,
+                  int cwin, int kw, int kh, int persist_blocks, hipStream_t s);
+size_t peak_lds_bytes(int sep, int cwin, int kw, int kh, bool f64);
 // one: the descriptor of a one-frame call, passed with the launch (the
 // workspace table is then not read), or null
 void launch_aperture(const FrameDesc* desc, const FrameDesc* one, const ApArgs& a, const ApCat& cat, int total_rows,

@@ -1114,6 +1114,375 @@ __global__ __launch_bounds__(256) void k_seg_finalize(DetWork wk, int f) {
 }
 
 // ---------------------------------------------------------------------------
+// Peak detection, the paper's own: local maxima of the significance
+// nu = F / R above the threshold, a maximum over a (2 sep + 1)^2 window
+// (truncated at the frame, ties to the earlier pixel in raster order), and a
+// first-moment centroid over a (2 cwin + 1)^2 window with weights max(M, 0).
+// One workgroup per 64x64 tile: M over the tile plus a halo of
+// max(sep + filter radius, cwin) (reflected at the frame edges, as the filter
+// reads it), then F, R and nu over the tile plus sep, in LDS.  A peak's
+// record goes to a slot taken with an atomic counter (its content does not
+// depend on the slot); the rank bitmap then numbers the peaks in raster order.
+struct PeakLayout {
+    int hmx, hmy, rmw, rmh, rf, nix;
+    int o_ms, o_nu, o_tab, o_colp, o_cols, o_cand, bytes;
+    __host__ __device__ PeakLayout(int sep, int cwin, int rx, int ry, int real_bytes, int row_bytes) {
+        hmx = max(sep + rx, cwin);
+        hmy = max(sep + ry, cwin);
+        rmw = kTile + 2 * hmx;
+        rmh = kTile + 2 * hmy;
+        rf = kTile + 2 * sep;
+        nix = (rmw - 1) / 16 + 3;   // spline x-pieces rmw columns can touch (mesh >= 16)
+        int o = 0;
+        auto take = [&](int n) {
+            o = (o + 15) / 16 * 16;
+            const int r = o;
+            o += n;
+            return r;
+        };
+        o_ms = take(rmw * rmh * real_bytes);
+        // nu, or before it the horizontal pass of a rank-one filter over the
+        // rows the vertical pass reads
+        o_nu = take(max(rf * rf, (rf + 2 * ry) * rf) * real_bytes);
+        // row cubics, later the row maxima of nu (rf rows of the tile's columns)
+        o_tab = take(max(rmh * nix * row_bytes, rf * kTile * real_bytes));
+        o_colp = take(rmw * 4);
+        o_cols = take(rmw * real_bytes);
+        o_cand = take(kTile * 2 * 4);
+        bytes = (o + 15) / 16 * 16;
+    }
+};
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* __restrict__ pa, PeakArgs pk) {
+    extern __shared__ __align__(16) unsigned char pk_dyn[];
+    constexpr bool kDbl = sizeof(Real) == 8;
+    const int tid = threadIdx.x;
+    const int gt = xcd_item(blockIdx.x, (wk.total_tiles + kXcds - 1) / kXcds);
+    if (gt >= wk.total_tiles) return;
+    const int f = frame_of(wk.nframes, gt, [&](int i) { return wk.desc[i].tile_base; });
+    const FrameDesc d = wk.desc[f];
+    const int lt = gt - d.tile_base;
+    const int tx = lt % d.ntx, ty = lt / d.ntx;
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int tw = min(kTile, d.W - x0), th = min(kTile, d.H - y0);
+    const int kw = pa->kw, kh = pa->kh, rx = kw >> 1, ry = kh >> 1;
+    const int sep = pk.sep, cw = pk.cwin;
+    const PeakLayout L(sep, cw, rx, ry, (int)sizeof(Real), (int)sizeof(RowT<Real>));
+    Real* ms = reinterpret_cast<Real*>(pk_dyn + L.o_ms);
+    Real* nus = reinterpret_cast<Real*>(pk_dyn + L.o_nu);
+    RowT<Real>* tab = reinterpret_cast<RowT<Real>*>(pk_dyn + L.o_tab);
+    int32_t* colp = reinterpret_cast<int32_t*>(pk_dyn + L.o_colp);
+    Real* colsx = reinterpret_cast<Real*>(pk_dyn + L.o_cols);
+    uint32_t* cand = reinterpret_cast<uint32_t*>(pk_dyn + L.o_cand);
+    // the tile's words of the frame's rank bitmap start at zero (bits are set
+    // by a later launch); the frame's last tile also clears the words past its
+    // last pixel up to the end of the last 1024-bit block
+    {
+        const int r = tid >> 2, j = tid & 3;
+        if (r < th) {
+            const int64_t p0 = (int64_t)(y0 + r) * d.W + x0;
+            const int64_t w = (p0 >> 5) + j;
+            if (w <= ((p0 + tw - 1) >> 5)) d.bitmap[w] = 0u;
+        }
+        if (tx == d.ntx - 1 && ty == d.nty - 1) {
+            const int64_t wlim = (int64_t)d.nblocks * 32;
+            for (int64_t w = (((int64_t)d.W * d.H + 31) >> 5) + tid; w < wlim; w += 256) d.bitmap[w] = 0u;
+        }
+    }
+    if (tid < kTile * 2) cand[tid] = 0u;
+    __shared__ Real taps[kMaxK * kMaxK];
+    for (int i = tid; i < kw * kh; i += 256) taps[i] = kDbl ? (Real)pa->kdd[i] : (Real)pa->kd[i];
+    // 1. raw pixels of the M region (reflected at the frame), row cubics and
+    //    column pieces
+    const int gx0 = x0 - L.hmx, gy0 = y0 - L.hmy;
+    const int mw = tw + 2 * L.hmx, mh = th + 2 * L.hmy;
+    const int xs_lo = max(0, gx0), xs_hi = min(d.W - 1, gx0 + mw - 1);
+    const int ixlo = piece_of(xs_lo, d.W, d.mw);
+    const int nix = min(piece_of(xs_hi, d.W, d.mw) - ixlo + 1, L.nix);
+    // (12 loads per thread in flight at a time; a region holds at most
+    // 92 x 92 pixels, 34 per thread)
+    constexpr int kPkBatch = 12;
+    for (int e0 = tid; e0 < mw * mh; e0 += 256 * kPkBatch) {
+        float v[kPkBatch];
+#pragma unroll
+        for (int u = 0; u < kPkBatch; ++u) {
+            const int e = e0 + 256 * u;
+            const int r = e / mw, c = e - r * mw;
+            v[u] = (e < mw * mh) ? load_px(d, reflect_idx(gx0 + c, d.W), reflect_idx(gy0 + r, d.H)) : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kPkBatch; ++u) {
+            const int e = e0 + 256 * u;
+            const int r = e / mw, c = e - r * mw;
+            if (e < mw * mh) ms[r * L.rmw + c] = (Real)v[u];
+        }
+    }
+    for (int e = tid; e < mh * nix; e += 256) {
+        const int r = e / nix, pi = e - r * nix;
+        const int ys = reflect_idx(gy0 + r, d.H);
+        const int jy = piece_of(ys, d.H, d.mh);
+        const double u = (double)ys - piece_ref(jy, d.H, d.mh);
+        tab[r * L.nix + pi] = make_row<Real>(d.coef, d.nx, d.ny, ixlo + pi, jy, u);
+    }
+    for (int c = tid; c < mw; c += 256) {
+        const int xs = reflect_idx(gx0 + c, d.W);
+        const int ix = piece_of(xs, d.W, d.mw);
+        colp[c] = min(ix - ixlo, L.nix - 1);
+        colsx[c] = (Real)((double)xs - piece_ref(ix, d.W, d.mw));
+    }
+    __syncthreads();
+    // 2. M = I - B over the region, in place
+    for (int e = tid; e < mw * mh; e += 256) {
+        const int r = e / mw, c = e - r * mw;
+        Real* q = &ms[r * L.rmw + c];
+        *q = eval_M(tab[r * L.nix + colp[c]], colsx[c], *q);
+    }
+    __syncthreads();
+    // 3. F (two 1-D passes for a rank-one kernel, else dense), R and nu over
+    //    the tile plus sep (nu = -inf outside the frame, so the maximum
+    //    filter below skips those positions); candidates F > t R inside the tile
+    const Real ts = (Real)pa->thresh;
+    const int fw = tw + 2 * sep, fh = th + 2 * sep;
+    const bool sepk = pa->separable != 0;
+    if (sepk) {
+        // horizontal pass over the M rows the vertical pass reads
+        const int hr = fh + 2 * ry;
+        const int m0 = L.hmy - sep - ry, c0 = L.hmx - sep - rx;
+        for (int e = tid; e < hr * fw; e += 256) {
+            const int t = e / fw, i = e - t * fw;
+            const Real* mrow = &ms[(m0 + t) * L.rmw + c0 + i];
+            Real acc = 0;
+            for (int b = 0; b < kw; ++b) acc = fma(kDbl ? (Real)pa->kxd[b] : (Real)pa->kx[b], mrow[b], acc);
+            nus[t * L.rf + i] = acc;
+        }
+        __syncthreads();
+    }
+    constexpr int kPkVals = (kTile + 2 * kMaxPeakWin) * (kTile + 2 * kMaxPeakWin) / 256 + 1;   // <= 24
+    Real nv[kPkVals];
+#pragma unroll
+    for (int q = 0; q < kPkVals; ++q) {
+        const int e = tid + 256 * q;
+        nv[q] = 0;
+        if (e < fw * fh) {
+            const int j = e / fw, i = e - j * fw;
+            const int mr = j - sep + L.hmy, mc = i - sep + L.hmx;   // M-region position of (x, y)
+            Real acc = 0;
+            if (sepk) {
+                for (int a = 0; a < kh; ++a)
+                    acc = fma(kDbl ? (Real)pa->kyd[a] : (Real)pa->ky[a], nus[(j + a) * L.rf + i], acc);
+            } else {
+                for (int a = 0; a < kh; ++a) {
+                    const Real* mrow = &ms[(mr + a - ry) * L.rmw + mc - rx];
+                    const Real* krow = &taps[a * kw];
+                    for (int b = 0; b < kw; ++b) acc = fma(krow[b], mrow[b], acc);
+                }
+            }
+            const Real R = eval_R(tab[mr * L.nix + colp[mc]], colsx[mc]);
+            const int gx = x0 - sep + i, gy = y0 - sep + j;
+            const bool in = gx >= 0 && gx < d.W && gy >= 0 && gy < d.H;
+            nv[q] = in ? ((R > (Real)0) ? acc / R : acc) : (Real)-INFINITY;
+            const int lx = i - sep, ly = j - sep;
+            if (lx >= 0 && lx < tw && ly >= 0 && ly < th && acc > ts * R)
+                atomicOr(&cand[ly * 2 + (lx >> 5)], 1u << (lx & 31));
+        }
+    }
+    __syncthreads();   // (the horizontal pass and the row cubics are read no more)
+#pragma unroll
+    for (int q = 0; q < kPkVals; ++q) {
+        const int e = tid + 256 * q;
+        if (e < fw * fh) {
+            const int j = e / fw, i = e - j * fw;
+            nus[j * L.rf + i] = nv[q];
+        }
+    }
+    __syncthreads();
+    // 4. maximum of nu over each row's (2 sep + 1) window, for the tile's
+    //    columns (into the row-cubic buffer), then per candidate the maximum
+    //    over its window; a candidate equal to it is a peak unless an earlier
+    //    pixel of the window (raster order) holds the same value
+    Real* rmx = reinterpret_cast<Real*>(pk_dyn + L.o_tab);
+    for (int e = tid; e < fh * tw; e += 256) {
+        const int j = e / tw, c = e - j * tw;
+        const Real* row = &nus[j * L.rf + c];
+        Real m = row[0];
+        for (int b = 1; b <= 2 * sep; ++b) m = fmax(m, row[b]);
+        rmx[j * kTile + c] = m;
+    }
+    __syncthreads();
+    const int lane = tid & 63, wv = tid >> 6;
+    const float sat = pa->sat;
+    for (int k = 0; k < 16; ++k) {
+        const int ly = 16 * wv + k, lx = lane;
+        if (ly >= th || lx >= tw || !((cand[ly * 2 + (lx >> 5)] >> (lx & 31)) & 1u)) continue;
+        const int gx = x0 + lx, gy = y0 + ly;
+        const Real v = nus[(ly + sep) * L.rf + lx + sep];
+        Real wmax = rmx[ly * kTile + lx];
+        for (int a = 1; a <= 2 * sep; ++a) wmax = fmax(wmax, rmx[(ly + a) * kTile + lx]);
+        if (v < wmax) continue;
+        // v is the window's maximum: a tie with an earlier pixel loses
+        bool is_max = true;
+        for (int dy = -sep; dy <= 0 && is_max; ++dy) {
+            for (int dx = -sep; dx <= sep; ++dx) {
+                if (dy == 0 && dx >= 0) break;
+                if (nus[(ly + sep + dy) * L.rf + lx + sep + dx] == v) {
+                    is_max = false;
+                    break;
+                }
+            }
+        }
+        if (!is_max) continue;
+        // centroid window, inside the frame; FP64 sums in a fixed order
+        const int wx0 = max(gx - cw, 0), wx1 = min(gx + cw, d.W - 1);
+        const int wy0 = max(gy - cw, 0), wy1 = min(gy + cw, d.H - 1);
+        uint32_t fl = (wx0 != gx - cw || wx1 != gx + cw || wy0 != gy - cw || wy1 != gy + cw) ? kFlagEdge : 0u;
+        double sw = 0.0, sx = 0.0, sy = 0.0, sxx = 0.0, syy = 0.0, sxy = 0.0, flux = 0.0;
+        for (int qy = wy0; qy <= wy1; ++qy)
+            for (int qx = wx0; qx <= wx1; ++qx) {
+                const double m = (double)ms[(qy - gy0) * L.rmw + (qx - gx0)];
+                const double w = m > 0.0 ? m : 0.0;
+                const double dx = (double)(qx - gx), dy = (double)(qy - gy);
+                sw += w;
+                sx += w * dx;
+                sy += w * dy;
+                sxx += w * dx * dx;
+                syy += w * dy * dy;
+                sxy += w * dx * dy;
+                flux += m;
+                if (sat < INFINITY && load_px(d, qx, qy) >= sat) fl |= kFlagSat;
+            }
+        double mx = 0.0, my = 0.0, vx = 0.0, vy = 0.0, cxy = 0.0;
+        if (sw > 0.0) {
+            mx = sx / sw;
+            my = sy / sw;
+            vx = sxx / sw - mx * mx;
+            vy = syy / sw - my * my;
+            cxy = sxy / sw - mx * my;
+        } else {
+            fl |= kFlagNonpos;
+        }
+        const uint32_t pm = (uint32_t)((int64_t)gy * d.W + gx);
+        const uint32_t slot = atomicAdd(&wk.counters[0], 1u);
+        if ((int64_t)slot >= (int64_t)wk.rec_cap) {
+            atomicOr(&wk.counters[1], 1u);
+            continue;
+        }
+        CompRec& R = wk.recs[slot];
+        R.acc[0] = flux;
+        R.acc[1] = (double)gx + mx;
+        R.acc[2] = (double)gy + my;
+        R.acc[3] = vx;
+        R.acc[4] = vy;
+        R.acc[5] = cxy;
+        R.xmin = wx0;
+        R.xmax = wx1;
+        R.ymin = wy0;
+        R.ymax = wy1;
+        R.pmin = pm;
+        R.peak = __float_as_uint((float)v);
+        R.flags = fl;
+        R.frame = f;
+        R.cnpix = (wx1 - wx0 + 1) * (wy1 - wy0 + 1);
+    }
+}
+
+// the rank bitmap's bits of the recorded peaks (after every tile has cleared
+// its words)
+__global__ __launch_bounds__(256) void k_peak_bits(DetWork wk) {
+    if (wk.counters[1] != 0u) return;
+    const int total = min((int)wk.counters[0], wk.rec_cap);
+    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
+        const CompRec& R = wk.recs[id];
+        const FrameDesc& d = wk.desc[R.frame];
+        atomicOr(&d.bitmap[R.pmin >> 5], 1u << (R.pmin & 31u));
+    }
+}
+
+// catalogue rows of the peaks in raster order, per-frame counts and status
+__global__ __launch_bounds__(256) void k_write_peaks(DetWork wk, CatOut cat, int32_t* comp_status) {
+    __shared__ uint32_t ctop[kMaxScanChunks + 1];
+    __shared__ uint32_t ws[4];
+    const ChunkPrefix cp = chunk_prefix(wk, ctop, ws);
+    if (blockIdx.x == 0) {
+        for (int f = threadIdx.x; f < wk.nframes; f += blockDim.x) {
+            const FrameDesc& d = wk.desc[f];
+            const int n =
+                (int)(block_prefix(wk, cp, d.bm_block_base + d.nblocks) - block_prefix(wk, cp, d.bm_block_base));
+            cat.n_obj[f] = n;
+            cat.status[f] = (wk.counters[1] != 0u) ? 3 : ((n > cat.capacity) ? 4 : 0);
+        }
+        if (threadIdx.x == 0 && comp_status) {
+            comp_status[0] = (wk.counters[1] != 0u) ? 3 : 0;
+            comp_status[1] = (int32_t)wk.counters[0];
+        }
+    }
+    if (wk.counters[1] != 0u) return;
+    const int total = min((int)wk.counters[0], wk.rec_cap);
+    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
+        const CompRec& R = wk.recs[id];
+        const FrameDesc& d = wk.desc[R.frame];
+        const uint32_t pm = R.pmin;
+        const int blk = (int)(pm >> 10);
+        const uint4* bw = (const uint4*)(d.bitmap + (size_t)blk * 32);
+        uint32_t rank = block_prefix(wk, cp, d.bm_block_base + blk) - block_prefix(wk, cp, d.bm_block_base);
+        const int wi = (int)((pm >> 5) & 31u);
+        const uint32_t part = (1u << (pm & 31u)) - 1u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint4 q = bw[k];
+            const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = 4 * k + j;
+                rank += __popc(i < wi ? w4[j] : (i == wi ? (w4[j] & part) : 0u));
+            }
+        }
+        if ((int)rank >= cat.capacity) continue;
+        const size_t row = (size_t)d.cat_base + rank;
+        cat.npix[row] = R.cnpix;
+        cat.xmin[row] = R.xmin;
+        cat.xmax[row] = R.xmax;
+        cat.ymin[row] = R.ymin;
+        cat.ymax[row] = R.ymax;
+        cat.pmin[row] = (int64_t)pm;
+        cat.flux[row] = R.acc[0];
+        cat.x[row] = R.acc[1];
+        cat.y[row] = R.acc[2];
+        cat.x2[row] = R.acc[3];
+        cat.y2[row] = R.acc[4];
+        cat.xy[row] = R.acc[5];
+        cat.peak[row] = __uint_as_float(R.peak);
+        cat.flags[row] = R.flags;
+    }
+}
+
+void launch_peaks(const DetWork& wk, const DetArgs* args, const CatOut& cat, int32_t* comp_status, bool f64, int sep,
+                  int cwin, int kw, int kh, int persist_blocks, hipStream_t s) {
+    const PeakArgs pk{sep, cwin};
+    const int g = kXcds * ((wk.total_tiles + kXcds - 1) / kXcds);
+    if (f64) {
+        const PeakLayout L(sep, cwin, kw / 2, kh / 2, 8, (int)sizeof(RowT<double>));
+        (void)hipFuncSetAttribute((const void*)k_peaks_tiles<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  L.bytes);
+        k_peaks_tiles<double><<<g, 256, L.bytes, s>>>(wk, args, pk);
+    } else {
+        const PeakLayout L(sep, cwin, kw / 2, kh / 2, 4, (int)sizeof(RowT<float>));
+        (void)hipFuncSetAttribute((const void*)k_peaks_tiles<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  L.bytes);
+        k_peaks_tiles<float><<<g, 256, L.bytes, s>>>(wk, args, pk);
+    }
+    k_peak_bits<<<persist_blocks, 256, 0, s>>>(wk);
+    const int nb = wk.total_blocks;
+    k_popc_scan<<<(nb + kScanChunk - 1) / kScanChunk, 256, 0, s>>>(wk.bitmap, wk.blockcnt, wk.chunksum, nb);
+    k_write_peaks<<<persist_blocks, 256, 0, s>>>(wk, cat, comp_status);
+}
+
+size_t peak_lds_bytes(int sep, int cwin, int kw, int kh, bool f64) {
+    return f64 ? PeakLayout(sep, cwin, kw / 2, kh / 2, 8, (int)sizeof(RowT<double>)).bytes
+               : PeakLayout(sep, cwin, kw / 2, kh / 2, 4, (int)sizeof(RowT<float>)).bytes;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 template <typename Real>
 static void launch_detect_t(const DetWork& wk, const DetArgs* args, int rad, hipStream_t s) {

@@ -838,6 +838,77 @@ extern "C" gp_status gp_detect_noalloc(gp_ctx* ctx, const gp_frame* frames, int3
                       false);
 }
 
+extern "C" gp_status gp_peaks(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
+                              const void* bkg, const gp_det_params* dp, const gp_peak_params* pp, gp_catalog* cat,
+                              int32_t* comp_status, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
+    gp_status st;
+    if ((st = check_frames(frames, nframes)) != GP_OK) return st;
+    if ((st = check_bkg(bp, frames, nframes)) != GP_OK) return st;
+    if ((st = check_det(dp)) != GP_OK) return st;
+    if (!pp) return fail(GP_ERR_INVALID_ARG, "peak parameters are NULL");
+    if (pp->sep < 0 || pp->sep > kMaxPeakWin || pp->cwin < 0 || pp->cwin > kMaxPeakWin)
+        return fail(GP_ERR_INVALID_ARG, "sep and cwin must be in [0, %d] (got %d, %d)", kMaxPeakWin, pp->sep, pp->cwin);
+    if ((st = check_cat(cat, true)) != GP_OK) return st;
+    if (!bkg) return fail(GP_ERR_INVALID_ARG, "background buffer is NULL");
+    Plan P;
+    plan_bkg(frames, nframes, bp, P);
+    plan_fixed(nframes, P);
+    plan_recs(1, P);
+    if ((st = check_ws(P, ws, ws_bytes)) != GP_OK) return st;
+    plan_recs(cap_for(P, ws_bytes), P);
+    if (P.total_tiles >= ((int64_t)1 << 31)) return fail(GP_ERR_UNSUPPORTED, "too many tiles in one batch");
+    if (ceil_div(P.total_blocks, kScanChunk) > kMaxScanChunks)
+        return fail(GP_ERR_UNSUPPORTED, "a detection batch holds at most 2^31 pixels (1024-pixel blocks per frame)");
+    const bool f64 = dp->precision == GP_PREC_F64;
+    if (peak_lds_bytes(pp->sep, pp->cwin, dp->kw, dp->kh, f64) > 160 * 1024)
+        return fail(GP_ERR_UNSUPPORTED, "peak windows and filter too large for one tile's LDS");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    DescChunk tail{};
+    if ((st = upload_desc(frames, nframes, bp, P, bkg, ws, cat->capacity, nullptr, s, &tail)) != GP_OK) return st;
+    char* W = (char*)ws;
+    DetArgsIn in{};
+    in.kw = dp->kw;
+    in.kh = dp->kh;
+    in.conn = dp->connectivity;
+    in.thresh = dp->thresh;
+    in.sat = dp->sat_level;
+    in.minarea = dp->minarea;
+    in.want_seg = 0;
+    for (int i = 0; i < dp->kw * dp->kh; ++i) in.kraw[i] = dp->kernel[i];
+    DetArgs* dargs = (DetArgs*)(W + P.o_detargs);
+    DetWork wk{};
+    wk.desc = (FrameDesc*)(W + P.o_desc);
+    wk.nframes = nframes;
+    wk.total_tiles = (int32_t)P.total_tiles;
+    wk.counters = (uint32_t*)(W + P.o_counters);
+    wk.tiles = (TileInfo*)(W + P.o_tiles);
+    wk.edges = (int16_t*)(W + P.o_edges);
+    wk.recs = (CompRec*)(W + P.o_recs);
+    wk.parent = (int32_t*)(W + P.o_parent);
+    wk.root = (int32_t*)(W + P.o_root);
+    wk.label = (int32_t*)(W + P.o_label);
+    wk.blockcnt = (uint32_t*)(W + P.o_blockcnt);
+    wk.chunksum = (uint32_t*)(W + P.o_chunks);
+    wk.bitmap = (uint32_t*)(W + P.o_bitmap);
+    wk.rec_cap = (int32_t)P.rec_cap;
+    wk.total_blocks = (int32_t)P.total_blocks;
+    {
+        ProfScope ps(ctx, s, "setup");
+        launch_det_setup(tail, (FrameDesc*)(W + P.o_desc), in, dargs, wk.counters, s);
+    }
+    HIP_TRY(hipGetLastError());
+    CatOut co{cat->capacity, cat->n_obj, cat->status, cat->npix, cat->xmin, cat->xmax, cat->ymin, cat->ymax,
+              cat->pmin, cat->flux, cat->x, cat->y, cat->x2, cat->y2, cat->xy, cat->peak, cat->flags};
+    {
+        ProfScope ps(ctx, s, "peaks");
+        launch_peaks(wk, dargs, co, comp_status, f64, pp->sep, pp->cwin, dp->kw, dp->kh, ctx->cus * 4, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return GP_OK;
+}
+
 extern "C" gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
                                  const void* bkg, const gp_catalog* cat, const gp_ap_params* ap, gp_phot* out,
                                  void* ws, size_t ws_bytes, void* stream) {

@@ -183,6 +183,13 @@ class Photometry:
                     C.c_void_p(self.comp_status.data_ptr()), C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
                     self.stream_ptr(stream))
 
+    def peaks(self, sep: int, cwin: int, stream=None):
+        """The paper's detection (local maxima of F / R, first-moment
+        centroids) into the catalogue, in place of detect()."""
+        L.gp_peaks(self.ctx, self.frames, self.bp, C.c_void_p(self.bkg.data_ptr()), self.dp,
+                   L.gp_peak_params(int(sep), int(cwin)), self.gcat, C.c_void_p(self.comp_status.data_ptr()),
+                   C.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.stream_ptr(stream))
+
     def aperture(self, stream=None):
         L.gp_aperture(self.ctx, self.frames, self.bp, C.c_void_p(self.bkg.data_ptr()), self.gcat, self.ap,
                       self.gphot, C.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.stream_ptr(stream))

@@ -224,3 +224,21 @@ def weight_allowance(M, xs, ys, p, ophot, precision=0):
             s_j, n_j = _near_circle(M, xc, yc, r)
             af[k, j] = eps(r) * (s_j + bk * n_j) + float(ophot["area"][k, j]) * ab[k]
     return {"flux": af, "bkg": ab}
+
+
+def peak_ambiguous(F, R, t, sep):
+    """Pixels whose peak decision FP32 may take either way: the threshold test
+    within the rounding band, or nu = F / R within 1e-5 (relative) of the
+    largest other nu of its window."""
+    from scipy import ndimage
+    nu = np.where(R > 0, F / np.where(R > 0, R, 1.0), F)
+    H, W = nu.shape
+    best = np.full_like(nu, -np.inf)
+    pad = np.pad(nu, sep, mode="constant", constant_values=-np.inf)
+    for dy in range(-sep, sep + 1):
+        for dx in range(-sep, sep + 1):
+            if dx == 0 and dy == 0:
+                continue
+            best = np.maximum(best, pad[sep + dy:sep + dy + H, sep + dx:sep + dx + W])
+    close = np.abs(nu - best) <= AMBIG_T * (np.abs(nu) + np.abs(best))
+    return thresh_ambiguous(F, R, t) | (close & (F > t * R))

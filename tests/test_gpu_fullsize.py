@@ -33,8 +33,8 @@ import pytest
 
 import oracle
 from synth import config_params, make_frame
-from tests._util import (TOL_BKG_REL, check_meshes, cmp_phot, f32_params, phot_condition, thresh_ambiguous,
-                         weight_allowance)
+from tests._util import (TOL_BKG_REL, TOL_CEN, TOL_MOM_ABS, check_meshes, cmp_phot, f32_params, peak_ambiguous,
+                         phot_condition, thresh_ambiguous, weight_allowance)
 
 pytestmark = pytest.mark.gpu
 
@@ -311,6 +311,58 @@ def test_fullsize_apertures_at_given_centres(full):
         errs["bkg"].append(e["bkg"])
     _say("apertures checked", len(xs))
     ERRORS[full["name"]].update({f"ap_{q}_rel": _stats(v) for q, v in errs.items()})
+
+
+def test_fullsize_peaks_sampled(full):
+    """gp_peaks (separation and centroid half-widths 3 px, the workload's
+    threshold) on the whole frame; the oracle recomputes every peak of 16
+    sampled 96 x 96 windows (M from the oracle's grids): the two sets differ
+    only on ambiguous decisions, and common peaks agree."""
+    img, p, og, ph = full["img"], full["p"], full["og"], full["ph"]
+    H, W = img.shape
+    sep = cw = 3
+    ph.peaks(sep, cw)
+    r = ph.results(0)
+    assert r["status"] == 0 and r["n_obj"] > 0
+    g = r["cat"]
+    gpy, gpx = np.divmod(g["pmin"], W)
+    h = max(sep, cw)
+    kr = p.kernel_size // 2
+    rng = np.random.default_rng(15)
+    n_cmp = n_diff = 0
+    errs = {q: [] for q in ("x", "y", "x2", "y2", "xy")}
+    for _ in range(16):
+        wx0 = int(rng.integers(40, W - 40 - 96))
+        wy0 = int(rng.integers(40, H - 40 - 96))
+        rx0, rx1, ry0, ry1 = wx0 - h, wx0 + 96 + h, wy0 - h, wy0 + 96 + h
+        I, M, R, F = _window(img, og["back"], og["rms"], p, rx0, rx1, ry0, ry1, kr)
+        o = oracle.peaks(I, M, F, R, p.thresh, sep, cw, p.sat_level)
+        oy, ox = np.divmod(o["pmin"], rx1 - rx0)
+        keep = (ox >= h) & (ox < h + 96) & (oy >= h) & (oy < h + 96)
+        o_set = {(int(y) + ry0, int(x) + rx0): k for k, (y, x) in enumerate(zip(oy, ox)) if keep[k]}
+        gin = (gpx >= wx0) & (gpx < wx0 + 96) & (gpy >= wy0) & (gpy < wy0 + 96)
+        g_set = {(int(gpy[k]), int(gpx[k])): k for k in np.nonzero(gin)[0]}
+        amb = peak_ambiguous(F, R, p.thresh, sep)
+        for q in set(g_set) ^ set(o_set):
+            assert amb[q[0] - ry0, q[1] - rx0], ("peak differs without an ambiguous decision", q)
+            n_diff += 1
+        for q in set(g_set) & set(o_set):
+            kg, ko = g_set[q], o_set[q]
+            for c in ("x", "y"):
+                off = rx0 if c == "x" else ry0
+                d = abs(g[c][kg] - (o[c][ko] + off))
+                assert d <= TOL_CEN, (q, c, d)
+                errs[c].append(d)
+            for c in ("x2", "y2", "xy"):
+                d = abs(g[c][kg] - o[c][ko])
+                assert d <= TOL_MOM_ABS + 1e-6 * abs(o[c][ko]), (q, c, d)
+                errs[c].append(d)
+            assert abs(float(g["peak"][kg]) - o["peak"][ko]) <= 2e-6 * abs(o["peak"][ko]) + 1e-6, q
+            assert int(g["npix"][kg]) == int(o["npix"][ko]) and int(g["flags"][kg] & 7) == int(o["flags"][ko] & 7)
+            n_cmp += 1
+    _say("peaks compared", n_cmp, "differing on ambiguous decisions", n_diff, "of", r["n_obj"], "in the frame")
+    assert n_cmp > 0
+    ERRORS[full["name"]].update({f"peak_{q}": _stats(v) for q, v in errs.items()})
 
 
 def test_fullsize_zz_error_table(full):

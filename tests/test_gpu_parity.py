@@ -14,8 +14,8 @@ import pytest
 
 import oracle
 from synth import Params, gaussian_kernel, make_frame
-from tests._util import (AMBIG_T, TOL_BKG_REL, check_meshes, cmp_catalog, cmp_phot, f32_params, mesh_ambiguous,
-                         phot_condition, thresh_ambiguous, weight_allowance)
+from tests._util import (AMBIG_T, TOL_BKG_REL, TOL_CEN, TOL_MOM_ABS, check_meshes, cmp_catalog, cmp_phot, f32_params,
+                         mesh_ambiguous, peak_ambiguous, phot_condition, thresh_ambiguous, weight_allowance)
 
 pytestmark = pytest.mark.gpu
 
@@ -450,6 +450,78 @@ def test_aperture_constant_image_closed_form(P):
 # ----------------------------------------------------------------------------
 # whole chain, batches and failure paths
 # ----------------------------------------------------------------------------
+# ----------------------------------------------------------------------------
+# peak detection (the paper's own), stage-isolated
+# ----------------------------------------------------------------------------
+PEAK_CASES = [
+    # name, W, H, dtype, seed, thresh, sep, cwin, kernel
+    ("c1", 333, 257, "f32", 51, 1.5, 3, 3, None),
+    ("c1", 300, 211, "u16", 52, 5.0, 3, 4, None),
+    ("c1", 420, 180, "f32", 53, 3.0, 1, 2, "dense"),
+    ("c1", 257, 300, "f32", 54, 2.0, 6, 7, None),
+    ("c1", 129, 70, "f32", 55, 1.5, 0, 0, None),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("case", PEAK_CASES, ids=lambda c: f"{c[1]}x{c[2]}-{c[3]}-t{c[5]}-s{c[6]}-c{c[7]}-{c[8] or 'gauss'}")
+def test_peaks_stage_isolated(P, case, prec):
+    name, W, H, dt, seed, t, sep, cw, kk = case
+    _say("peak case", case, prec)
+    fr = make_frame(name, seed=seed, W=W, H=H, dtype=dt, nstars=max(8, W * H // 2500))
+    p = f32_params(fr.params)
+    p.mesh_w = p.mesh_h = 64
+    p.thresh = t
+    p.sat_level = 60000.0
+    K = p.kernel() if kk is None else (0.3 + np.random.default_rng(seed).random((7, 5))).astype(np.float32)
+    I = fr.image.astype(np.float64)
+    ob = oracle.background(I, p, maps=True)
+    M = I - ob.B
+    F = oracle.filter_image(M, K)
+    o = oracle.peaks(I, M, F, ob.R, p.thresh, sep, cw, p.sat_level)
+    ph = P.Photometry([_dev(fr.image)], p, K, capacity=8192, precision=prec)
+    ph.set_grids(0, ob.back, ob.rms)
+    ph.background(grid_given=True)
+    ph.peaks(sep, cw)
+    r = ph.results(0)
+    assert r["status"] == 0 and r["comp_status"][0] == 0
+    amb = peak_ambiguous(F, ob.R, p.thresh, sep).ravel()
+    g_set, o_set = set(r["cat"]["pmin"].tolist()), set(o["pmin"].tolist())
+    diff = sorted(g_set ^ o_set)
+    _say("peaks gpu", len(g_set), "oracle", len(o_set), "differ", len(diff), "ambiguous px", int(amb.sum()))
+    assert len(o_set) > 3
+    assert all(amb[q] for q in diff), [q for q in diff if not amb[q]]
+    assert np.all(np.diff(r["cat"]["pmin"]) > 0)
+    common = sorted(g_set & o_set)
+    gi = {q: i for i, q in enumerate(r["cat"]["pmin"].tolist())}
+    oi = {q: i for i, q in enumerate(o["pmin"].tolist())}
+    ig = np.array([gi[q] for q in common])
+    io = np.array([oi[q] for q in common])
+    g, c = r["cat"], {k: v[io] for k, v in o.items() if k != "n"}
+    for k in ("npix", "xmin", "xmax", "ymin", "ymax"):
+        np.testing.assert_array_equal(g[k][ig], c[k], err_msg=k)
+    np.testing.assert_array_equal(g["flags"][ig], c["flags"])
+    # flux of the window: tolerance on the sum of |M| over it
+    absM = np.array([np.abs(M[c["ymin"][k]:c["ymax"][k] + 1, c["xmin"][k]:c["xmax"][k] + 1]).sum()
+                     for k in range(len(io))])
+    assert np.all(np.abs(g["flux"][ig] - c["flux"]) <= 1e-6 * np.maximum(np.abs(c["flux"]), absM))
+    for k in ("x", "y"):
+        assert np.all(np.abs(g[k][ig] - c[k]) <= TOL_CEN), (k, np.abs(g[k][ig] - c[k]).max())
+    for k in ("x2", "y2", "xy"):
+        assert np.all(np.abs(g[k][ig] - c[k]) <= TOL_MOM_ABS + 1e-6 * np.abs(c[k])), k
+    assert np.all(np.abs(g["peak"][ig] - c["peak"]) <= 2e-6 * np.abs(c["peak"]) + 1e-6)
+    # the apertures run on the peak catalogue
+    ph.aperture()
+    ra = ph.results(0)
+    rad = np.asarray(p.radii)
+    rm = max(max(p.radii), p.r_out)
+    x, y = ra["cat"]["x"], ra["cat"]["y"]
+    inner = (x - rm >= -0.5) & (x + rm <= W - 0.5) & (y - rm >= -0.5) & (y + rm <= H - 0.5)
+    np.testing.assert_allclose(ra["phot"]["area"][inner], np.broadcast_to(np.pi * rad ** 2, (inner.sum(), rad.size)),
+                               rtol=1e-6)
+    ph.close()
+
+
 def _grown(mask):
     """mask grown by one pixel in the 8-neighbourhood"""
     g = mask.copy()
