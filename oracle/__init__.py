@@ -70,7 +70,10 @@ def lib():
         L.or_overlap.restype = C.c_double
         L.or_aperture.argtypes = [dp, dp, C.c_long, C.c_long, dp, dp, C.c_long, dp, C.c_int, C.c_double,
                                   C.c_double, C.c_double, C.c_int, dp, dp, dp, dp, up]
-        for f in ("or_mesh_one", "or_mesh_one_policy", "or_mesh_stats", "or_median_filter", "or_grid_eval", "or_grid_map",
+        L.or_growth_radii.argtypes = [C.c_double, C.c_int, ip, C.POINTER(C.c_int)]
+        L.or_tophat_taps.argtypes = [C.c_int, dp]
+        L.or_growth.argtypes = [dp, dp, C.c_long, C.c_long, dp, dp, C.c_long, ip, C.c_int, dp, dp, dp, up]
+        for f in ("or_growth_radii", "or_tophat_taps", "or_growth", "or_mesh_one", "or_mesh_one_policy", "or_mesh_stats", "or_median_filter", "or_grid_eval", "or_grid_map",
                   "or_filter", "or_threshold_label", "or_measure", "or_aperture", "or_peaks"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -315,6 +318,45 @@ def aperture(M, R, xs, ys, radii, r_in, r_out, gain=0.0, want_err=True):
                              int(bool(want_err) and Rr is not None), _p(flux), _p(area), _p(bkg),
                              _p(err), _p(flags, C.c_uint32)), "aperture")
     return dict(flux=flux[:n], area=area[:n], bkg=bkg[:n], fluxerr=err[:n], flags=flags[:n])
+
+
+# ----------------------------------------------------------------------------
+# Growth curves on top-hat kernels
+# ----------------------------------------------------------------------------
+def growth_radii(fwhm):
+    """Integer radii ceil(0.75 fwhm) .. ceil(5 fwhm)."""
+    n = C.c_int(0)
+    _check(lib().or_growth_radii(float(fwhm), 0, C.POINTER(C.c_int32)(), C.byref(n)), "growth_radii")
+    out = np.zeros(max(n.value, 1), np.int32)
+    _check(lib().or_growth_radii(float(fwhm), n.value, _p(out, C.c_int32), C.byref(n)), "growth_radii")
+    return out[: n.value]
+
+
+def tophat_taps(r):
+    """(2r+1)^2 exact-overlap taps of the top-hat kernel of integer radius r."""
+    t = np.zeros((2 * r + 1, 2 * r + 1))
+    _check(lib().or_tophat_taps(int(r), _p(t)), "tophat_taps")
+    return t
+
+
+def growth(M, V, xs, ys, radii):
+    """Growth curves: per source and radius, the top-hat correlation of M and
+    of V read at the source's pixel.  Returns dict(sum, var, area, flags)."""
+    Mm = _f64(M)
+    H, W = Mm.shape
+    Vv = _f64(V) if V is not None else None
+    xs, ys = _f64(xs), _f64(ys)
+    n = xs.size
+    rad = np.ascontiguousarray(radii, dtype=np.int32)
+    nr = rad.size
+    s = np.zeros((max(n, 1), nr))
+    v = np.zeros((max(n, 1), nr))
+    a = np.zeros((max(n, 1), nr))
+    fl = np.zeros(max(n, 1), np.uint32)
+    vp = _p(Vv) if Vv is not None else C.POINTER(C.c_double)()
+    _check(lib().or_growth(_p(Mm), vp, W, H, _p(xs), _p(ys), n, _p(rad, C.c_int32), nr, _p(s), _p(v), _p(a),
+                           _p(fl, C.c_uint32)), "growth")
+    return dict(sum=s[:n], var=v[:n], area=a[:n], flags=fl[:n])
 
 
 # ----------------------------------------------------------------------------

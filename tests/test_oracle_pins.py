@@ -690,3 +690,138 @@ def test_peak_centroid_against_numpy_and_flags():
     # capacity: the first peaks in raster order are kept, the count is whole
     few = oracle.peaks(I, M, F, R, 1.5, 2, c, sat=65535.0, cap=3)
     assert few["n"] == got["n"] and list(few["pmin"]) == list(got["pmin"][:3])
+
+
+# ----------------------------------------------------------------------------
+# growth curves on top-hat kernels
+# ----------------------------------------------------------------------------
+def test_growth_radii_rule():
+    # ceil(0.75 F) .. ceil(5 F): FWHM 3 gives 3..15
+    assert list(oracle.growth_radii(3.0)) == list(range(3, 16))
+    assert list(oracle.growth_radii(3.5)) == list(range(3, 19))
+    assert list(oracle.growth_radii(4.0)) == list(range(3, 21))   # 0.75 * 4 = 3 exactly
+    assert list(oracle.growth_radii(1.0)) == [1, 2, 3, 4, 5]
+    assert list(oracle.growth_radii(0.5)) == [1, 2, 3]
+    assert list(oracle.growth_radii(2.2)) == list(range(2, 12))
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(RuntimeError):
+            oracle.growth_radii(bad)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 6, 15])
+def test_tophat_taps_against_quadrature(r):
+    t = oracle.tophat_taps(r)
+    assert t.shape == (2 * r + 1, 2 * r + 1)
+    # sum of the taps = pi r^2; eight-fold symmetry (up to the corner sums' rounding)
+    assert abs(t.sum() - math.pi * r * r) <= 1e-13 * math.pi * r * r
+    for tt in (t[::-1, :], t[:, ::-1], t.T):
+        np.testing.assert_allclose(t, tt, rtol=0, atol=1e-14 * r * r)
+    # interior taps exactly 1, taps wholly outside exactly 0, the rest by quadrature
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            w = t[dy + r, dx + r]
+            far = math.hypot(abs(dx) + .5, abs(dy) + .5)
+            near = math.hypot(max(abs(dx) - .5, 0), max(abs(dy) - .5, 0))
+            if far <= r:
+                assert w == 1.0
+            elif near >= r:
+                assert w == 0.0
+            elif (dx + dy) % 3 == 0 or r <= 3:
+                q = _quad_overlap(dx - .5, dx + .5, dy - .5, dy + .5, 0.0, 0.0, float(r))
+                assert abs(w - q) < 1e-10, (r, dx, dy, w, q)
+
+
+def _segment(d, r):
+    """Area of the part of a disk of radius r beyond a line at distance d from its centre."""
+    if d >= r:
+        return 0.0
+    return r * r * math.acos(d / r) - d * math.sqrt(r * r - d * d)
+
+
+def test_growth_constant_image_and_one_edge():
+    H, W = 70, 90
+    c, v = 3.5, 0.75
+    M = np.full((H, W), c)
+    V = np.full((H, W), v)
+    radii = [2, 3, 5, 8, 11]
+    # interior sources: c pi r^2, v pi r^2 (a variance through the squared taps would differ)
+    xs = np.array([45.2, 44.5, 50.49])
+    ys = np.array([35.0, 30.7, 29.51])
+    o = oracle.growth(M, V, xs, ys, radii)
+    for k, r in enumerate(radii):
+        np.testing.assert_allclose(o["area"][:, k], math.pi * r * r, rtol=1e-13)
+        np.testing.assert_allclose(o["sum"][:, k], c * math.pi * r * r, rtol=1e-13)
+        np.testing.assert_allclose(o["var"][:, k], v * math.pi * r * r, rtol=1e-13)
+    assert not np.any(o["flags"])
+    # a source at column cx near the left edge only: the frame edge x = -1/2 is a
+    # straight line at distance cx + 1/2 from the centre, cutting off a segment
+    for cx in (0, 1, 3, 6, 10):
+        o = oracle.growth(M, V, [cx + 0.2], [35.0], radii)
+        for k, r in enumerate(radii):
+            want = math.pi * r * r - _segment(cx + 0.5, r)
+            assert abs(o["area"][0, k] - want) < 1e-11 * r * r, (cx, r, o["area"][0, k], want)
+            assert abs(o["sum"][0, k] - c * want) < 1e-11 * c * r * r
+        assert bool(o["flags"][0] & oracle.FLAG_APER_TRUNC) == (cx < max(radii))
+
+
+def _fft_correlate_zero_padded(M, t):
+    """Correlation of the zero-padded frame with taps t by the FFT (the
+    paper's evaluation), full output indexed like M."""
+    H, W = M.shape
+    r = t.shape[0] // 2
+    sh = (H + 2 * r, W + 2 * r)
+    FM = np.fft.rfft2(M, sh)
+    FK = np.fft.rfft2(t[::-1, ::-1], sh)   # correlation = convolution with the flipped kernel
+    full = np.fft.irfft2(FM * FK, sh)
+    return full[r:r + H, r:r + W]
+
+
+def test_growth_equals_scipy_correlate_and_fft():
+    rng = np.random.default_rng(11)
+    H, W = 61, 83
+    M = rng.normal(0, 10, (H, W)) + 20 * np.sin(np.arange(W) / 7.0)[None, :] + np.arange(H)[:, None]
+    V = rng.uniform(0.5, 4.0, (H, W))
+    radii = [1, 3, 4, 7, 12]
+    xs = rng.uniform(-0.49, W - 0.51, 60)
+    ys = rng.uniform(-0.49, H - 0.51, 60)
+    xs[:4] = [0.0, W - 1.0, 10.5, 20.5 - 1e-12]
+    ys[:4] = [0.0, H - 1.0, 7.5, 30.5]
+    o = oracle.growth(M, V, xs, ys, radii)
+    cx = np.floor(xs + 0.5).astype(int)
+    cy = np.floor(ys + 0.5).astype(int)
+    assert cx[2] == 11 and cx[3] == 20
+    for k, r in enumerate(radii):
+        t = oracle.tophat_taps(r)
+        cm = ndimage.correlate(M, t, mode="constant", cval=0.0)
+        cv = ndimage.correlate(V, t, mode="constant", cval=0.0)
+        ca = ndimage.correlate(np.ones_like(M), t, mode="constant", cval=0.0)
+        scale = ndimage.correlate(np.abs(M), t, mode="constant", cval=0.0)
+        np.testing.assert_allclose(o["sum"][:, k], cm[cy, cx], rtol=0, atol=1e-12 * scale[cy, cx].max())
+        np.testing.assert_allclose(o["var"][:, k], cv[cy, cx], rtol=1e-13)
+        np.testing.assert_allclose(o["area"][:, k], ca[cy, cx], rtol=1e-13)
+        ff = _fft_correlate_zero_padded(M, t)
+        np.testing.assert_allclose(o["sum"][:, k], ff[cy, cx], rtol=0, atol=1e-10 * scale[cy, cx].max())
+    trunc = (cx - max(radii) < 0) | (cx + max(radii) >= W) | (cy - max(radii) < 0) | (cy + max(radii) >= H)
+    np.testing.assert_array_equal((o["flags"] & oracle.FLAG_APER_TRUNC) != 0, trunc)
+
+
+def test_growth_delta_reads_the_centroid_pixel_and_is_monotone():
+    H, W = 40, 50
+    M = np.zeros((H, W))
+    M[20, 11] = 1.0
+    radii = [1, 2]
+    t1 = oracle.tophat_taps(1)
+    # x = 10.5 rounds to pixel 11 (the delta at the kernel centre); 10.49 to pixel 10
+    o = oracle.growth(M, None, [10.5, 10.49, 11.0], [20.0, 20.0, 19.4], radii)
+    assert o["sum"][0, 0] == t1[1, 1] == 1.0
+    assert o["sum"][1, 0] == t1[1, 2]
+    assert o["sum"][2, 0] == t1[2, 1]   # reads (11, 19): the delta is one row below
+    # sources far off the frame: nothing reaches it
+    o = oracle.growth(M, None, [-40.0, 1e30, 10.0], [5.0, 5.0, float("nan")], radii)
+    assert not np.any(o["sum"]) and not np.any(o["area"])
+    assert np.all(o["flags"] == oracle.FLAG_APER_TRUNC)
+    # non-negative frames: growth curves are non-decreasing in r
+    rng = np.random.default_rng(3)
+    P = rng.uniform(0, 5, (H, W))
+    o = oracle.growth(P, P, rng.uniform(0, W, 30), rng.uniform(0, H, 30), list(range(1, 13)))
+    assert np.all(np.diff(o["sum"], axis=1) >= 0) and np.all(np.diff(o["area"], axis=1) > 0)
