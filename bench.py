@@ -439,15 +439,18 @@ def single_frame_line(a):
 
 
 def form_peaks(torch, a):
-    """The paper's own detection on the batch: gp_background -> gp_peaks (local
+    """The paper's own path on the batch: gp_background -> gp_peaks (local
     maxima of F / R above 5 sigma, the paper's default; separation and
-    centroid half-widths 3 px = ceil(FWHM)) -> gp_aperture, direct calls."""
+    centroid half-widths 3 px = ceil(FWHM)) -> gp_growth (top-hat growth
+    curves over the radii ceil(0.75 FWHM) .. ceil(5 FWHM) = 3..15 px for
+    FWHM 3), direct calls."""
     from paper_2609_32375_amd import _lib as L
-    from paper_2609_32375_amd.pipeline import Photometry
+    from paper_2609_32375_amd.pipeline import Photometry, growth_radii
     from synth import config_params
     frames = batch_frames(torch)
     p = config_params("c1")
     p.thresh = 5.0
+    radii = growth_radii(3.0)
     npx = [f.shape[0] * f.shape[1] for f in frames]
     mp = sum(npx) / 1e6
     ph = Photometry(frames, p, p.kernel(), capacity=65536)
@@ -455,7 +458,7 @@ def form_peaks(torch, a):
     def step():
         ph.background()
         ph.peaks(3, 3)
-        ph.aperture()
+        ph.growth(radii)
     for _ in range(3):
         step()
     torch.cuda.synchronize()
@@ -468,16 +471,18 @@ def form_peaks(torch, a):
     torch.cuda.synchronize()
     L.gp_profile_enable(ph.ctx, False)
     kern = {}
-    for name in ("mesh_stats", "peaks", "aperture"):
+    for name in ("mesh_stats", "peaks", "growth"):
         tot, cnt = L.gp_profile_read(ph.ctx, name)
         if cnt:
             kern[name] = round(tot / cnt, 4)
     ph.close()
     del frames
-    log(f"peaks form: {ms:.3f} ms per batch, {n} peaks")
-    return {"workload": "the 64-frame uint16 batch; background, peaks (5 sigma, sep 3, cwin 3), apertures",
+    log(f"paper path: {ms:.3f} ms per batch, {n} peaks")
+    return {"workload": "the 64-frame uint16 batch; background, peaks (5 sigma, sep 3, cwin 3), "
+                        "growth curves (radii 3..15)",
             "ms": round(ms, 3), "mp_s": round(mp / ms * 1e3, 1), "peaks": n, "kernels_ms": kern,
-            "peaks_hbm_frac": round(2 * sum(npx) / (kern.get("peaks", 1e9) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "peaks_hbm_frac": round(2 * sum(npx) / (kern.get("peaks", 1e9) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "growth_sources_per_s": round(n / (kern.get("growth", 1e9) * 1e-3), 1)}
 
 
 def form_served(torch, a):

@@ -1,7 +1,7 @@
 /*
  * gp.h -- C ABI of the MI355X (gfx950) photometry hot path.
  *
- * Three calls carry the method, in the order the paper's GPU Implementation
+ * These calls carry the method, in the order the paper's GPU Implementation
  * section applies its stages to a frame:
  *
  *   gp_background  mesh background: per-mesh kappa-sigma clipped mode and rms
@@ -19,8 +19,13 @@
  *   gp_aperture    circular aperture photometry (adaptive aperture photometry
  *                  subsection): exact pixel/disk overlap sums for each radius,
  *                  an annulus background, and the propagated noise.
+ *   gp_peaks       the paper's own detection: local maxima of the significance
+ *                  F / R above the threshold with first-moment centroids (in
+ *                  place of gp_detect's connected components).
+ *   gp_growth      growth curves: top-hat sums of M and of R^2 at every source
+ *                  for the integer radii ceil(0.75 FWHM) .. ceil(5 FWHM).
  *
- * All three work on a batch of nframes >= 1 frames of any sizes at once; the
+ * All of them work on a batch of nframes >= 1 frames of any sizes at once; the
  * plain per-frame use is nframes = 1.
  *
  * Memory.  Every pointer inside gp_frame, gp_catalog, gp_phot and the
@@ -300,6 +305,49 @@ gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
                       const gp_bkg_params* bp, const void* bkg, const gp_catalog* cat,
                       const gp_ap_params* ap, gp_phot* out, void* ws, size_t ws_bytes,
                       void* stream);
+
+/* Growth curves on top-hat kernels (Adaptive Aperture Photometry subsection:
+ * circular apertures of integer radii from ceil(0.75 FWHM) to ceil(5 FWHM),
+ * each radius one correlation of the frame with a top-hat kernel, the noise
+ * variance propagated through the same kernel, sums in float64).
+ *
+ * gp_growth_radii: the radii of that rule for a given FWHM (pixels); stores at
+ * most cap of them in radii (host memory), *n = how many there are.
+ *
+ * gp_growth: for every catalogued row (x, y from gp_detect, gp_peaks or the
+ * caller) and every radius r_k,
+ *   sum[row][k]  = sum over pixels p of T_k(p - c) M(p)
+ *   var[row][k]  = sum over pixels p of T_k(p - c) R(p)^2
+ *   area[row][k] = sum over pixels p inside the frame of T_k(p - c)
+ * where c = (floor(x + 1/2), floor(y + 1/2)) is the pixel holding the
+ * centroid, M = I - B and R are the background and noise maps of the
+ * background buffer, and T_k(dx, dy) is the exact area of the disk of radius
+ * r_k about the centre of pixel (0, 0) inside pixel (dx, dy) (so the interior
+ * area is pi r_k^2).  Pixels off the frame contribute nothing.  flags[row] =
+ * GP_FLAG_APER_TRUNC when a nonzero tap of the largest kernel falls off the
+ * frame (or the position is not a number), else 0; a pixel so far out that
+ * no tap reaches the frame gets zero sums.  The catalogue is only read.
+ * radii: HOST pointer to nr (1..32) strictly increasing integers in [1, 32].
+ * Outputs: device, rows as in the catalogue, [row][nr] doubles; var and flags
+ * may be NULL.  Result bits do not depend on the batch or on scheduling.
+ * The workspace must hold gp_workspace_size's fixed part plus the tap table
+ * (a gp_workspace_size workspace for the same batch always does). */
+typedef struct gp_growth_params {
+    const int32_t* radii;
+    int32_t nr;
+    int32_t precision;     /* gp_precision: working precision of M and R */
+} gp_growth_params;
+typedef struct gp_growth_out {
+    double* sum;
+    double* var;
+    double* area;
+    uint32_t* flags;
+} gp_growth_out;
+gp_status gp_growth_radii(double fwhm, int32_t cap, int32_t* radii, int32_t* n);
+gp_status gp_growth(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                    const gp_bkg_params* bp, const void* bkg, const gp_catalog* cat,
+                    const gp_growth_params* gp, gp_growth_out* out, void* ws,
+                    size_t ws_bytes, void* stream);
 
 /* Captured batch: gp_background -> gp_detect -> gp_aperture over one batch
  * (the arguments of the three calls, one workspace for all of them) recorded

@@ -63,13 +63,21 @@ class gp_peak_params(C.Structure):
     _fields_ = [("sep", C.c_int32), ("cwin", C.c_int32)]
 
 
+class gp_growth_params(C.Structure):
+    _fields_ = [("radii", C.POINTER(C.c_int32)), ("nr", C.c_int32), ("precision", C.c_int32)]
+
+
+class gp_growth_out(C.Structure):
+    _fields_ = [("sum", C.c_void_p), ("var", C.c_void_p), ("area", C.c_void_p), ("flags", C.c_void_p)]
+
+
 class gp_phot(C.Structure):
     _fields_ = [("flux", C.c_void_p), ("area", C.c_void_p), ("bkg", C.c_void_p), ("fluxerr", C.c_void_p)]
 
 
 EXPORTS = ("gp_ctx_create", "gp_ctx_destroy", "gp_last_error", "gp_version", "gp_background_layout",
            "gp_workspace_size", "gp_background", "gp_background_map", "gp_detect", "gp_detect_noalloc",
-           "gp_peaks", "gp_aperture",
+           "gp_peaks", "gp_aperture", "gp_growth_radii", "gp_growth",
            "gp_profile_enable",
            "gp_profile_read", "gp_profile_reset", "gp_ctx_set_tuning", "gp_graph_create", "gp_graph_launch",
            "gp_graph_rebind", "gp_graph_destroy")
@@ -115,6 +123,9 @@ def load(path: str = LIB_PATH):
     L.gp_aperture.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp,
                               C.POINTER(gp_catalog), C.POINTER(gp_ap_params), C.POINTER(gp_phot), vp,
                               C.c_size_t, vp]
+    L.gp_growth_radii.argtypes = [C.c_double, i32, C.POINTER(i32), C.POINTER(i32)]
+    L.gp_growth.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp, C.POINTER(gp_catalog),
+                            C.POINTER(gp_growth_params), C.POINTER(gp_growth_out), vp, C.c_size_t, vp]
     L.gp_graph_create.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp,
                                   C.POINTER(gp_det_params), C.POINTER(gp_catalog), C.POINTER(vp), vp,
                                   C.POINTER(gp_ap_params), C.POINTER(gp_phot), vp, C.c_size_t, C.POINTER(vp)]
@@ -128,7 +139,7 @@ def load(path: str = LIB_PATH):
     L.gp_profile_reset.argtypes = [vp]
     for f in ("gp_ctx_create", "gp_background_layout", "gp_workspace_size", "gp_background",
               "gp_background_map", "gp_detect", "gp_detect_noalloc", "gp_peaks",
-              "gp_aperture", "gp_profile_enable", "gp_profile_read", "gp_profile_reset", "gp_graph_create",
+              "gp_aperture", "gp_growth_radii", "gp_growth", "gp_profile_enable", "gp_profile_read", "gp_profile_reset", "gp_graph_create",
               "gp_graph_launch", "gp_graph_rebind"):
         getattr(L, f).restype = C.c_int
     _lib = L
@@ -218,6 +229,21 @@ def gp_aperture(ctx, frames, bp, bkg_ptr, cat, ap, phot, ws_ptr, ws_bytes, strea
     arr = (gp_frame * n)(*frames)
     check(load().gp_aperture(ctx, arr, n, C.byref(bp), bkg_ptr, C.byref(cat), C.byref(ap), C.byref(phot),
                              ws_ptr, ws_bytes, stream))
+
+
+def gp_growth_radii(fwhm):
+    n = C.c_int32(0)
+    check(load().gp_growth_radii(float(fwhm), 0, None, C.byref(n)))
+    out = (C.c_int32 * max(n.value, 1))()
+    check(load().gp_growth_radii(float(fwhm), n.value, out, C.byref(n)))
+    return [int(out[i]) for i in range(n.value)]
+
+
+def gp_growth(ctx, frames, bp, bkg_ptr, cat, gp, out, ws_ptr, ws_bytes, stream):
+    n = len(frames)
+    arr = (gp_frame * n)(*frames)
+    check(load().gp_growth(ctx, arr, n, C.byref(bp), bkg_ptr, C.byref(cat), C.byref(gp), C.byref(out),
+                           ws_ptr, ws_bytes, stream))
 
 
 def gp_graph_create(ctx, frames, bp, bkg_ptr, dp, cat, seg_ptrs, comp_status_ptr, ap, phot, ws_ptr, ws_bytes):

@@ -72,6 +72,30 @@ struct PeakArgs {
 };
 constexpr int kMaxPeakWin = 7;
 
+// growth curves: integer radii (strictly increasing, <= kMaxGrowthRadius),
+// the window half-width R = largest radius, and the offsets of the full and
+// cut lists of each radius in the tap table (computed on the host from the
+// same exact classification the table kernel uses)
+constexpr int kMaxGrowthRadii = 32;
+constexpr int kMaxGrowthRadius = 32;
+struct GrowArgs {
+    int32_t nr, R, side, capacity, nframes, want_var, nixmax, nfull, ncut;
+    int32_t div_magic;   // i / side == (i * div_magic) >> 20 for i < side^2
+    int32_t radii[kMaxGrowthRadii];
+    int32_t full_off[kMaxGrowthRadii + 1], cut_off[kMaxGrowthRadii + 1];
+};
+struct GrowTab {
+    int32_t* full;   // (wy << 16) | wx of each full-list offset
+    int32_t* cut;
+    double* cutw;    // exact area of the cut pixel for that list's radius
+};
+struct GrowOut {
+    const int32_t* n_obj;
+    const double *x, *y;
+    double *sum, *var, *area;
+    uint32_t* flags;
+};
+
 // one: the descriptor of a one-frame call, passed with the launch (the kernel
 // stores it in the table for the launches that follow), or null
 void launch_mesh_stats(FrameDesc* desc, const FrameDesc* one, int nframes, int total_meshes, int max_area, BkgArgs a,
@@ -94,6 +118,10 @@ size_t peak_lds_bytes(int sep, int cwin, int kw, int kh, bool f64);
 // workspace table is then not read), or null
 void launch_aperture(const FrameDesc* desc, const FrameDesc* one, const ApArgs& a, const ApCat& cat, int total_rows,
                      int blocks, int mesh_w, int max_nx, bool f64, hipStream_t s);
+void launch_growth_table(const GrowArgs& a, const GrowTab& t, hipStream_t s);
+hipError_t launch_growth(const FrameDesc* desc, const FrameDesc* one, const GrowArgs& a, const GrowTab& t,
+                         const GrowOut& g, int blocks, int waves, bool f64, hipStream_t s);
+size_t growth_lds_bytes(int nfull, int ncut, int side, int nixmax, int want_var, bool f64, int waves);
 void launch_bkg_map(const FrameDesc& d, double* bmap, double* rmap, bool f64, hipStream_t s);
 void launch_write_desc(const DescChunk& c, FrameDesc* table, hipStream_t s);
 void launch_det_setup(const DescChunk& c, FrameDesc* table, const DetArgsIn& in, DetArgs* out, uint32_t* counters,

@@ -981,6 +981,131 @@ extern "C" gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nf
     return GP_OK;
 }
 
+extern "C" gp_status gp_growth_radii(double fwhm, int32_t cap, int32_t* radii, int32_t* n) {
+    if (!n) return fail(GP_ERR_INVALID_ARG, "n is NULL");
+    if (!(fwhm > 0.0) || !std::isfinite(fwhm)) return fail(GP_ERR_INVALID_ARG, "fwhm must be positive and finite");
+    if (cap < 0 || (cap > 0 && !radii)) return fail(GP_ERR_INVALID_ARG, "radii is NULL with cap > 0");
+    const double lo = std::ceil(0.75 * fwhm), hi = std::ceil(5.0 * fwhm);
+    if (hi > 1.0e6) return fail(GP_ERR_INVALID_ARG, "fwhm too large");
+    int32_t k = 0;
+    for (double r = lo; r <= hi; r += 1.0, ++k)
+        if (k < cap) radii[k] = (int32_t)r;
+    *n = k;
+    return GP_OK;
+}
+
+namespace {
+// The nested top-hat kernels' offset classes (exact: squared distances are
+// multiples of 1/4): for each radius, how many offsets join the running sums
+// with weight 1 and how many it cuts.  Only the counts are taken here (list
+// offsets and the launch's LDS size); k_growth_table classifies the offsets
+// itself and computes the areas.
+void growth_lists(const gp_growth_params* gp, GrowArgs& a) {
+    const int R = gp->radii[gp->nr - 1];
+    std::vector<int> nfull(gp->nr, 0), ncut(gp->nr, 0);
+    for (int dy = -R; dy <= R; ++dy)
+        for (int dx = -R; dx <= R; ++dx) {
+            const double ax = std::fabs((double)dx), ay = std::fabs((double)dy);
+            const double nx = std::max(ax - 0.5, 0.0), ny = std::max(ay - 0.5, 0.0);
+            const double dmin2 = nx * nx + ny * ny;
+            const double dmax2 = (ax + 0.5) * (ax + 0.5) + (ay + 0.5) * (ay + 0.5);
+            for (int k = 0; k < gp->nr; ++k) {
+                const double r2 = (double)gp->radii[k] * gp->radii[k];
+                const double rp2 = (k > 0) ? (double)gp->radii[k - 1] * gp->radii[k - 1] : -1.0;
+                if (dmax2 <= r2 && dmax2 > rp2) ++nfull[k];
+                if (dmin2 < r2 && r2 < dmax2) ++ncut[k];
+            }
+        }
+    a.full_off[0] = a.cut_off[0] = 0;
+    for (int k = 0; k < gp->nr; ++k) {
+        a.full_off[k + 1] = a.full_off[k] + nfull[k];
+        a.cut_off[k + 1] = a.cut_off[k] + ncut[k];
+    }
+    a.nfull = a.full_off[gp->nr];
+    a.ncut = a.cut_off[gp->nr];
+}
+
+size_t growth_table_bytes(const GrowArgs& a) {
+    return align256(4 * (size_t)a.nfull) + align256(4 * (size_t)a.ncut) + align256(8 * (size_t)a.ncut);
+}
+}  // namespace
+
+extern "C" gp_status gp_growth(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
+                               const void* bkg, const gp_catalog* cat, const gp_growth_params* gp,
+                               gp_growth_out* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
+    gp_status st;
+    if ((st = check_frames(frames, nframes)) != GP_OK) return st;
+    if ((st = check_bkg(bp, frames, nframes)) != GP_OK) return st;
+    if ((st = check_cat(cat, false)) != GP_OK) return st;
+    if (!gp || !gp->radii) return fail(GP_ERR_INVALID_ARG, "growth parameters or radii are NULL");
+    if (gp->nr < 1 || gp->nr > kMaxGrowthRadii) return fail(GP_ERR_INVALID_ARG, "nr must be in [1, %d]", kMaxGrowthRadii);
+    for (int k = 0; k < gp->nr; ++k) {
+        if (gp->radii[k] < 1 || gp->radii[k] > kMaxGrowthRadius)
+            return fail(GP_ERR_INVALID_ARG, "radius %d must be in [1, %d]", k, kMaxGrowthRadius);
+        if (k > 0 && gp->radii[k] <= gp->radii[k - 1])
+            return fail(GP_ERR_INVALID_ARG, "radii must be strictly increasing");
+    }
+    if (gp->precision != GP_PREC_F32 && gp->precision != GP_PREC_F64)
+        return fail(GP_ERR_INVALID_ARG, "unknown precision %d", gp->precision);
+    if (!out || !out->sum || !out->area) return fail(GP_ERR_INVALID_ARG, "growth output sum/area is NULL");
+    if (!bkg) return fail(GP_ERR_INVALID_ARG, "background buffer is NULL");
+    const bool f64 = gp->precision == GP_PREC_F64;
+    GrowArgs a{};
+    a.nr = gp->nr;
+    a.R = gp->radii[gp->nr - 1];
+    a.side = 2 * a.R + 1;
+    a.capacity = cat->capacity;
+    a.nframes = nframes;
+    a.want_var = out->var ? 1 : 0;
+    for (int k = 0; k < gp->nr; ++k) a.radii[k] = gp->radii[k];
+    a.div_magic = (int32_t)(((1u << 20) + a.side - 1) / a.side);
+    for (int i = 0; i < a.side * a.side; ++i)
+        if ((int)(((uint32_t)i * (uint32_t)a.div_magic) >> 20) != i / a.side)
+            return fail(GP_ERR_UNSUPPORTED, "window index split fails for side %d", a.side);
+    growth_lists(gp, a);
+    int max_nx = 1;
+    for (int i = 0; i < nframes; ++i) max_nx = std::max(max_nx, (frames[i].width + bp->mesh_w - 1) / bp->mesh_w);
+    // spline pieces a window of `side` columns can touch (knots one mesh apart,
+    // the last at least half a mesh from its neighbour)
+    a.nixmax = std::max(1, std::min(max_nx + 1, (a.side - 1) / std::max(bp->mesh_w, 1) + 3));
+    // wavefronts per workgroup: as many (up to 8) as fit the 160 KB of LDS
+    int waves = 8;
+    while (waves > 1 && growth_lds_bytes(a.nfull, a.ncut, a.side, a.nixmax, a.want_var, f64, waves) > 160 * 1024)
+        --waves;
+    if (growth_lds_bytes(a.nfull, a.ncut, a.side, a.nixmax, a.want_var, f64, waves) > 160 * 1024)
+        return fail(GP_ERR_UNSUPPORTED, "growth window of radius %d does not fit in LDS", a.R);
+    Plan P;
+    plan_bkg(frames, nframes, bp, P);
+    plan_fixed(nframes, P);
+    const size_t o_tab = P.o_recs;
+    P.ws_bytes = o_tab + growth_table_bytes(a);
+    if ((st = check_ws(P, ws, ws_bytes)) != GP_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const bool one = nframes == 1;
+    DescChunk tail{};
+    if ((st = upload_desc(frames, nframes, bp, P, bkg, ws, cat->capacity, nullptr, s, one ? &tail : nullptr)) != GP_OK)
+        return st;
+    char* W = (char*)ws;
+    GrowTab t;
+    t.full = (int32_t*)(W + o_tab);
+    t.cut = (int32_t*)(W + o_tab + align256(4 * (size_t)a.nfull));
+    t.cutw = (double*)(W + o_tab + align256(4 * (size_t)a.nfull) + align256(4 * (size_t)a.ncut));
+    GrowOut g{cat->n_obj, cat->x, cat->y, out->sum, out->var, out->area, out->flags};
+    {
+        ProfScope ps(ctx, s, "growth");
+        launch_growth_table(a, t, s);
+        const int total_rows = nframes * cat->capacity;
+        const int blocks = std::max(1, std::min(ctx->cus * 4, (total_rows + waves - 1) / waves));
+        hipError_t e = launch_growth((const FrameDesc*)(W + P.o_desc), one ? &tail.d[0] : nullptr, a, t, g, blocks,
+                                     waves, f64, s);
+        if (e != hipSuccess) return fail(GP_ERR_HIP, "growth launch: %s", hipGetErrorString(e));
+    }
+    HIP_TRY(hipGetLastError());
+    return GP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Captured batches: the three calls over one batch recorded once into a HIP
 // graph (on a private stream) and replayed with one launch.  The parameters

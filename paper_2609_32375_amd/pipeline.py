@@ -127,6 +127,8 @@ class Photometry:
         self.gphot = L.gp_phot(ph["flux"].data_ptr(), ph["area"].data_ptr(), ph["bkg"].data_ptr(),
                                ph["fluxerr"].data_ptr())
         self.graph = None
+        self.grow = None
+        self.precision = precision
         self.seg = None
         if seg:
             self.seg = [torch.zeros(t.shape[0], t.shape[1], dtype=torch.int32, device=dev) for t in self.frames_t]
@@ -193,6 +195,27 @@ class Photometry:
     def aperture(self, stream=None):
         L.gp_aperture(self.ctx, self.frames, self.bp, C.c_void_p(self.bkg.data_ptr()), self.gcat, self.ap,
                       self.gphot, C.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.stream_ptr(stream))
+
+    def growth(self, radii, stream=None, want_var: bool = True):
+        """Growth curves of every catalogued source: top-hat sums of M (and of
+        R^2) at the source's pixel for each integer radius (see
+        growth_radii()).  Results come back under "growth" in results()."""
+        rad = np.ascontiguousarray(radii, dtype=np.int32)
+        nr = rad.size
+        rows = max(self.n * self.capacity, 1)
+        if self.grow is None or self.grow["sum"].shape[1] != nr:
+            dev = self.device
+            self.grow = {"sum": torch.empty(rows, nr, dtype=torch.float64, device=dev),
+                         "var": torch.empty(rows, nr, dtype=torch.float64, device=dev),
+                         "area": torch.empty(rows, nr, dtype=torch.float64, device=dev),
+                         "flags": torch.empty(rows, dtype=torch.int32, device=dev)}
+        g = self.grow
+        self._grow_radii = rad
+        gp = L.gp_growth_params(rad.ctypes.data_as(C.POINTER(C.c_int32)), nr, self.precision)
+        out = L.gp_growth_out(g["sum"].data_ptr(), g["var"].data_ptr() if want_var else None, g["area"].data_ptr(),
+                              g["flags"].data_ptr())
+        L.gp_growth(self.ctx, self.frames, self.bp, C.c_void_p(self.bkg.data_ptr()), self.gcat, gp, out,
+                    C.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.stream_ptr(stream))
 
     def run(self, stream=None):
         self.background(stream)
@@ -275,10 +298,12 @@ class Photometry:
         base = f * self.capacity
         cols = [("cat", name, t) for name, t in self.cat.items()] + \
                [("phot", name, t) for name, t in self.phot.items()]
+        if self.grow is not None:
+            cols += [("growth", name, t) for name, t in self.grow.items()]
         parts = [t[base: base + k].reshape(-1).view(torch.uint8) for _, _, t in cols]
         parts.append(self.comp_status.reshape(-1).view(torch.uint8))
         flat = torch.cat(parts).cpu().numpy()
-        out = {"cat": {}, "phot": {}}
+        out = {"cat": {}, "phot": {}, "growth": {}}
         off = 0
         for (grp, name, t), pt in zip(cols, parts):
             nb = pt.numel()
@@ -287,7 +312,9 @@ class Photometry:
             off += nb
         comp = flat[off:].view(_NP_DTYPE[self.comp_status.dtype]).tolist()
         out["cat"]["flags"] = out["cat"]["flags"].astype(np.uint32)
-        return dict(n_obj=n, status=st, cat=out["cat"], phot=out["phot"], comp_status=comp,
+        if self.grow is not None:
+            out["growth"]["flags"] = out["growth"]["flags"].astype(np.uint32)
+        return dict(n_obj=n, status=st, cat=out["cat"], phot=out["phot"], growth=out["growth"], comp_status=comp,
                     seg=self.seg[f].cpu().numpy() if self.seg is not None else None)
 
 
@@ -299,3 +326,9 @@ def run_plain(frame: torch.Tensor, params, kernel: np.ndarray, capacity: int, **
     out["grids"] = ph.grids(0)
     ph.close()
     return out
+
+
+def growth_radii(fwhm: float) -> List[int]:
+    """Integer radii ceil(0.75 fwhm) .. ceil(5 fwhm) of the growth curves (the
+    library's rule)."""
+    return L.gp_growth_radii(fwhm)

@@ -13,6 +13,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # tolerances of the contract
 TOL_BKG_REL = 1e-5      # background and rms maps / grids, relative
 TOL_FLUX_REL = 1e-6     # fluxes, relative to the sum's condition sum(w |M|)
+TOL_B64_ABS = 1e-9      # FP64 background map against the oracle's spline, ADU
+TOL_R64_REL = 1e-12     # FP64 noise map against the oracle's spline, relative
 TOL_CEN = 1e-4          # centroid, px
 TOL_MOM_ABS = 1e-4      # second moments, px^2 (+ 1e-6 relative)
 # a threshold decision within this relative margin may go either way in FP32
@@ -242,3 +244,29 @@ def peak_ambiguous(F, R, t, sep):
             best = np.maximum(best, pad[sep + dy:sep + dy + H, sep + dx:sep + dx + W])
     close = np.abs(nu - best) <= AMBIG_T * (np.abs(nu) + np.abs(best))
     return thresh_ambiguous(F, R, t) | (close & (F > t * R))
+
+
+def growth_allowance(A, xs, ys, radii):
+    """What the FP64 top-hat taps of cut pixels may differ by between the two
+    sides, as (sum over cut pixels of |A| times it, cut-pixel count times it)
+    per source and radius.  The oracle's tap is a signed sum of four corner
+    integrals, each a sum of up to three terms of magnitude <= r^2, each
+    rounded within a few units of 2^-53 (32 u r^2 in all; the same formula in
+    long double puts the largest actual difference at 15.6 u r^2, radius
+    32); the device's cancellation-free area is within 8 u (r + 1).  Only the oracle-side frame and positions enter: the
+    circle is centred on the pixel holding the position."""
+    n, nr = len(xs), len(radii)
+    sa = np.zeros((n, nr))
+    na = np.zeros((n, nr))
+    H, W = A.shape
+    R = max(radii)
+    for i in range(n):
+        fx, fy = np.floor(xs[i] + 0.5), np.floor(ys[i] + 0.5)
+        if not (np.isfinite(fx) and np.isfinite(fy)) or not (-R - 1 <= fx <= W + R and -R - 1 <= fy <= H + R):
+            continue
+        for j, r in enumerate(radii):
+            e = 32 * U64 * r * r + EPS_W_ULPS * U64 * (r + 1.0)
+            s, c = _near_circle(A, float(fx), float(fy), float(r))
+            sa[i, j] = e * s
+            na[i, j] = e * c
+    return sa, na

@@ -93,3 +93,27 @@ def test_product_path_does_not_import_the_oracle():
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, fn
                 assert "gp_oracle" not in txt, fn
+
+
+def test_growth_radii_rule_matches_oracle():
+    import oracle
+    from paper_2609_32375_amd import _lib as L
+    for fwhm in (0.3, 0.5, 1.0, 1.33, 2.2, 3.0, 3.5, 4.0, 4.8, 6.4, 10.0):
+        assert L.gp_growth_radii(fwhm) == list(oracle.growth_radii(fwhm)), fwhm
+    for bad in (0.0, -2.0, float("nan"), float("inf")):
+        with pytest.raises(L.GpError) as e:
+            L.gp_growth_radii(bad)
+        assert e.value.status == L.GP_ERR_INVALID_ARG
+
+
+def test_growth_arguments_are_checked_synchronously():
+    from paper_2609_32375_amd import _lib as L
+    lib = L.load()
+    bp = L.gp_bkg_params(64, 64, 3, 3.0, 0.2, 2.5, 1.5, 100, 0)
+    fr = (L.gp_frame * 1)(_frame(100, 100))
+    rad = (C.c_int32 * 3)(3, 4, 5)
+    gp = L.gp_growth_params(rad, 3, 0)
+    out = L.gp_growth_out(1, None, 1, None)
+    cat = L.gp_catalog()
+    assert lib.gp_growth(None, fr, 1, C.byref(bp), None, C.byref(cat), C.byref(gp), C.byref(out), None, 0,
+                         None) == L.GP_ERR_INVALID_ARG

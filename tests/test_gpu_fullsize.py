@@ -33,7 +33,7 @@ import pytest
 
 import oracle
 from synth import config_params, make_frame
-from tests._util import (TOL_BKG_REL, TOL_CEN, TOL_MOM_ABS, check_meshes, cmp_phot, f32_params, peak_ambiguous,
+from tests._util import (growth_allowance, TOL_B64_ABS, TOL_R64_REL, TOL_BKG_REL, TOL_CEN, TOL_MOM_ABS, check_meshes, cmp_phot, f32_params, peak_ambiguous,
                          phot_condition, thresh_ambiguous, weight_allowance)
 
 pytestmark = pytest.mark.gpu
@@ -311,6 +311,67 @@ def test_fullsize_apertures_at_given_centres(full):
         errs["bkg"].append(e["bkg"])
     _say("apertures checked", len(xs))
     ERRORS[full["name"]].update({f"ap_{q}_rel": _stats(v) for q, v in errs.items()})
+
+
+def test_fullsize_growth_at_given_centres(full):
+    """gp_growth (radii 3..18: the rule for FWHM 3.5) at centres the test
+    chooses (the oracle centroids of the checked objects, random points,
+    points on and off the edges), on the oracle's grids (given to the device
+    for this test, the frame's own background restored after it), against
+    the oracle on a window around each centre."""
+    from paper_2609_32375_amd.pipeline import growth_radii
+    img, p, og, ph = full["img"], full["p"], full["og"], full["ph"]
+    H, W = img.shape
+    rng = np.random.default_rng(15)
+    pts = list(full.get("centres", []))
+    pts += [(rng.uniform(0, W - 1), rng.uniform(0, H - 1)) for _ in range(40)]
+    pts += [(rng.uniform(-20, 12), rng.uniform(0, H - 1)) for _ in range(6)]
+    pts += [(rng.uniform(0, W - 1), rng.uniform(H - 12, H + 20)) for _ in range(6)]
+    xs = np.array([q[0] for q in pts])
+    ys = np.array([q[1] for q in pts])
+    radii = growth_radii(3.5)
+    R = max(radii)
+    ph.set_grids(0, og["back"], og["rms"])
+    ph.background(grid_given=True)
+    ph.set_catalog(0, xs, ys)
+    ph.growth(radii)
+    g = ph.results(0)["growth"]
+    ph.background()
+    torch.cuda.synchronize()
+    u = 2.0 ** -24 if full["prec"] == 0 else 2.0 ** -53
+    errs = []
+    for k in range(len(xs)):
+        cx, cy = int(math.floor(xs[k] + 0.5)), int(math.floor(ys[k] + 0.5))
+        x0, x1 = max(cx - R - 1, 0), min(cx + R + 2, W)
+        y0, y1 = max(cy - R - 1, 0), min(cy + R + 2, H)
+        if x0 >= x1 or y0 >= y1:
+            assert not np.any(g["sum"][k]) and not np.any(g["area"][k])
+            continue
+        yy, xx = np.meshgrid(np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
+        fx, fy = xx.ravel().astype(np.float64), yy.ravel().astype(np.float64)
+        B = oracle.grid_eval(og["back"], W, H, p.mesh_w, p.mesh_h, fx, fy).reshape(xx.shape)
+        Rm = oracle.grid_eval(og["rms"], W, H, p.mesh_w, p.mesh_h, fx, fy).reshape(xx.shape)
+        M = img[y0:y1, x0:x1].astype(np.float64) - B
+        lx, ly = np.array([xs[k] - x0]), np.array([ys[k] - y0])
+        o = oracle.growth(M, Rm ** 2, lx, ly, radii)
+        cond = oracle.growth(np.abs(M) + np.abs(B), None, lx, ly, radii)["sum"]
+        sa_m, na = growth_allowance(np.abs(M), lx, ly, radii)
+        sa_v, _ = growth_allowance(Rm ** 2, lx, ly, radii)
+        ds = np.abs(g["sum"][k:k + 1] - o["sum"])
+        # FP64: M and R within the FP64 maps' agreement with the spline
+        f64 = full["prec"] == 1
+        ts = 8 * u * cond + sa_m + (TOL_B64_ABS * o["area"] if f64 else 0.0)
+        assert np.all(ds <= ts), (full["name"], k, float(np.max(ds - ts)))
+        assert np.all(np.abs(g["area"][k:k + 1] - o["area"]) <= na + 8 * 2.0 ** -53 * o["area"])
+        tv = (16 * u + (2.5 * TOL_R64_REL if f64 else 0.0)) * o["var"] + sa_v
+        dv = np.abs(g["var"][k:k + 1] - o["var"])
+        assert np.all(dv <= tv), (full["name"], k, float(np.max(dv / np.maximum(o["var"], 1e-300))))
+        # truncation: the frame's own edges (the window's are not frame edges)
+        trunc = cx - R < 0 or cx + R >= W or cy - R < 0 or cy + R >= H
+        assert bool(g["flags"][k] & 8) == trunc
+        errs.append(float(np.max(ds / np.maximum(cond, 1e-300))))
+    _say("growth curves checked", len(errs))
+    ERRORS[full["name"]].update({"growth_sum_over_cond": _stats(errs)})
 
 
 def test_fullsize_peaks_sampled(full):

@@ -14,8 +14,8 @@ import pytest
 
 import oracle
 from synth import Params, gaussian_kernel, make_frame
-from tests._util import (AMBIG_T, TOL_BKG_REL, TOL_CEN, TOL_MOM_ABS, check_meshes, cmp_catalog, cmp_phot, f32_params,
-                         mesh_ambiguous, peak_ambiguous, phot_condition, thresh_ambiguous, weight_allowance)
+from tests._util import (AMBIG_T, TOL_B64_ABS, TOL_BKG_REL, TOL_R64_REL, TOL_CEN, TOL_MOM_ABS, check_meshes, cmp_catalog, cmp_phot, f32_params,
+                         growth_allowance, mesh_ambiguous, peak_ambiguous, phot_condition, thresh_ambiguous, weight_allowance)
 
 pytestmark = pytest.mark.gpu
 
@@ -214,7 +214,7 @@ def test_background_maps_match_oracle_spline(P, shape):
     assert eb <= 5e-5                      # ADU: ~5e-8 relative, far inside 1e-5
     assert er <= TOL_BKG_REL
     B64, R64 = ph.maps(0, precision=1)
-    assert np.abs(B64 - Bo).max() <= 1e-9 and (np.abs(R64 - Ro) / Ro).max() <= 1e-12
+    assert np.abs(B64 - Bo).max() <= TOL_B64_ABS and (np.abs(R64 - Ro) / Ro).max() <= TOL_R64_REL
     ph.close()
 
 
@@ -520,6 +520,165 @@ def test_peaks_stage_isolated(P, case, prec):
     np.testing.assert_allclose(ra["phot"]["area"][inner], np.broadcast_to(np.pi * rad ** 2, (inner.sum(), rad.size)),
                                rtol=1e-6)
     ph.close()
+
+
+# ----------------------------------------------------------------------------
+# growth curves on top-hat kernels, stage-isolated
+# ----------------------------------------------------------------------------
+GROWTH_CASES = [
+    # name, W, H, dtype, seed, radii
+    ("c1", 333, 257, "f32", 61, list(range(3, 16))),    # FWHM 3: radii 3..15
+    ("c2", 300, 211, "u16", 62, list(range(3, 19))),    # FWHM 3.5: radii 3..18
+    ("c1", 129, 70, "f32", 63, [1, 2, 5, 9]),
+    ("c1", 200, 150, "f32", 64, list(range(1, 33))),    # the largest window (radius 32)
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("case", GROWTH_CASES, ids=lambda c: f"{c[1]}x{c[2]}-{c[3]}-r{c[5][0]}..{c[5][-1]}")
+def test_growth_stage_isolated(P, case, prec):
+    """Top-hat sums of M and R^2 at given positions against the oracle on the
+    oracle's own background grids.  The FP64 path pins the tap table (areas
+    to FP64 rounding); the FP32 path adds the FP32 evaluation of M and R."""
+    name, W, H, dt, seed, radii = case
+    _say("growth case", case, prec)
+    fr = make_frame(name, seed=seed, W=W, H=H, dtype=dt, nstars=max(8, W * H // 2500))
+    p = f32_params(fr.params)
+    p.mesh_w = p.mesh_h = 64
+    I = fr.image.astype(np.float64)
+    ob = oracle.background(I, p, maps=True)
+    M = I - ob.B
+    V = ob.R ** 2
+    rng = np.random.default_rng(seed)
+    n = 400
+    xs = rng.uniform(-40, W + 40, n)
+    ys = rng.uniform(-40, H + 40, n)
+    # half-integers round up; far off the frame; not a number
+    xs[:8] = [10.5, -0.5, W - 0.5, W - 0.5 - 1e-9, -1e6, 1e30, np.nan, W / 2]
+    ys[:8] = [20.5, H / 2, H / 2, 7.0, 5.0, 5.0, 5.0, np.inf]
+    ph = P.Photometry([_dev(fr.image)], p, p.kernel(), capacity=n, precision=prec)
+    ph.set_grids(0, ob.back, ob.rms)
+    ph.background(grid_given=True)
+    ph.set_catalog(0, xs, ys)
+    ph.growth(radii)
+    r = ph.results(0)["growth"]
+    o = oracle.growth(M, V, xs, ys, radii)
+    np.testing.assert_array_equal(r["flags"], o["flags"])
+    # taps: both sides FP64 exact-overlap areas, which may differ at cut pixels
+    # by the allowance below; summation adds a few units of 2^-53 of the area
+    sa_m, na = growth_allowance(np.abs(M), xs, ys, radii)
+    sa_v, _ = growth_allowance(V, xs, ys, radii)
+    da = np.abs(r["area"] - o["area"])
+    assert np.all(da <= na + 8 * 2.0 ** -53 * o["area"]), float(np.max(da - na))
+    # sums: per pixel M within a few units of the working precision of |M| + |B|
+    # (FP64: within the FP64 background map's agreement with the spline)
+    u = 2.0 ** -24 if prec == 0 else 2.0 ** -53
+    cond = oracle.growth(np.abs(M) + np.abs(ob.B), None, xs, ys, radii)["sum"]
+    tol = 8 * u * cond + sa_m + (TOL_B64_ABS * o["area"] if prec == 1 else 0.0)
+    ds = np.abs(r["sum"] - o["sum"])
+    q = ds / np.maximum(cond, 1e-300)
+    i, k = np.unravel_index(int(np.argmax(q)), q.shape)
+    _say("growth sum err / cond", float(q[i, k]), "at", (xs[i], ys[i]), "r", radii[k], "tap allowance share",
+         float(np.max(sa_m / np.maximum(tol, 1e-300))))
+    assert np.all(ds <= tol), float(np.max(ds - tol))
+    dv = np.abs(r["var"] - o["var"])
+    tv = (16 * u + (2.5 * TOL_R64_REL if prec == 1 else 0.0)) * o["var"] + sa_v
+    assert np.all(dv <= tv), float(np.max(dv / np.maximum(o["var"], 1e-300)))
+    # sources that no tap reaches: zero sums
+    far = ~np.isfinite(xs) | ~np.isfinite(ys) | (np.abs(xs) > 1e5)
+    assert not np.any(r["sum"][far]) and not np.any(r["area"][far])
+    ph.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "fp64"])
+def test_growth_taps_on_a_zero_background(P, prec):
+    """With B = 0 both sides sum the same float32 pixels: only the taps and
+    the summation order differ, so the sums agree to FP64 rounding in both
+    working precisions (this pins the tap table and its lists)."""
+    W, H = 170, 140
+    rng = np.random.default_rng(81)
+    img = (rng.normal(0, 30, (H, W)) + 5 * np.arange(W)[None, :]).astype(np.float32)
+    p = _params("c1")
+    nx, ny = -(-W // p.mesh_w), -(-H // p.mesh_h)
+    ph = P.Photometry([_dev(img)], p, p.kernel(), capacity=300, precision=prec)
+    ph.set_grids(0, np.zeros((ny, nx)), np.full((ny, nx), 3.0))
+    ph.background(grid_given=True)
+    xs = rng.uniform(-5, W + 5, 300)
+    ys = rng.uniform(-5, H + 5, 300)
+    ph.set_catalog(0, xs, ys)
+    radii = list(range(1, 33))
+    ph.growth(radii)
+    r = ph.results(0)["growth"]
+    M = img.astype(np.float64)
+    o = oracle.growth(M, np.full((H, W), 9.0), xs, ys, radii)
+    cond = oracle.growth(np.abs(M), None, xs, ys, radii)["sum"]
+    sa_m, na = growth_allowance(np.abs(M), xs, ys, radii)
+    ds = np.abs(r["sum"] - o["sum"])
+    _say("zero-background growth err / cond", float(np.max(ds / np.maximum(cond, 1e-300))))
+    assert np.all(ds <= 8 * 2.0 ** -53 * cond + sa_m), float(np.max(ds - 8 * 2.0 ** -53 * cond - sa_m))
+    assert np.all(np.abs(r["area"] - o["area"]) <= na + 8 * 2.0 ** -53 * o["area"])
+    assert np.all(np.abs(r["var"] - o["var"]) <= 9.0 * (na + 8 * 2.0 ** -53 * o["area"]))
+    np.testing.assert_array_equal(r["flags"], o["flags"])
+    ph.close()
+
+
+def test_growth_constant_image_closed_form(P):
+    c = 7.25
+    W, H = 150, 120
+    img = np.full((H, W), c, np.float32)
+    p = _params("c2")
+    nx, ny = -(-W // p.mesh_w), -(-H // p.mesh_h)
+    ph = P.Photometry([_dev(img)], p, p.kernel(), capacity=64)
+    ph.set_grids(0, np.zeros((ny, nx)), np.full((ny, nx), 2.0))
+    ph.background(grid_given=True)
+    rng = np.random.default_rng(2)
+    xs = 75 + rng.uniform(-3, 3, 40)
+    ys = 60 + rng.uniform(-3, 3, 40)
+    ph.set_catalog(0, xs, ys)
+    radii = P.growth_radii(3.5)
+    ph.growth(radii)
+    r = ph.results(0)["growth"]
+    a = np.pi * np.asarray(radii, np.float64) ** 2
+    np.testing.assert_allclose(r["area"], np.broadcast_to(a, r["area"].shape), rtol=1e-13)
+    np.testing.assert_allclose(r["sum"], c * r["area"], rtol=1e-15)
+    np.testing.assert_allclose(r["var"], 4.0 * r["area"], rtol=1e-7)
+    assert not np.any(r["flags"])
+    ph.close()
+
+
+def test_growth_batch_matches_single_frames(P):
+    frs = [make_frame("c1", seed=71, W=300, H=260, nstars=30),
+           make_frame("c1", seed=72, W=130, H=90, nstars=8, dtype="u16"),
+           make_frame("c2", seed=73, W=450, H=128, nstars=25)]
+    p = f32_params(frs[0].params)
+    K = p.kernel()
+    devs = [_dev(f.image) for f in frs]
+    radii = P.growth_radii(3.0)
+    batch = P.Photometry(devs, p, K, capacity=1024)
+    batch.background()
+    batch.peaks(3, 3)
+    batch.growth(radii)
+    for i, d in enumerate(devs):
+        one = P.Photometry([d], p, K, capacity=1024)
+        one.background()
+        one.peaks(3, 3)
+        one.growth(radii)
+        a, b = batch.results(i), one.results(0)
+        assert a["n_obj"] == b["n_obj"] > 0
+        for k in a["growth"]:
+            np.testing.assert_array_equal(a["growth"][k], b["growth"][k], err_msg=k)
+        # interior sources: area pi r^2
+        W, H = frs[i].image.shape[1], frs[i].image.shape[0]
+        cx = np.floor(a["cat"]["x"] + 0.5)
+        cy = np.floor(a["cat"]["y"] + 0.5)
+        R = max(radii)
+        inner = (cx - R >= 0) & (cx + R < W) & (cy - R >= 0) & (cy + R < H)
+        np.testing.assert_array_equal(a["growth"]["flags"] != 0, ~inner)
+        np.testing.assert_allclose(a["growth"]["area"][inner],
+                                   np.broadcast_to(np.pi * np.asarray(radii, float) ** 2,
+                                                   (int(inner.sum()), len(radii))), rtol=1e-13)
+        one.close()
+    batch.close()
 
 
 def _grown(mask):
