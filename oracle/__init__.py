@@ -70,10 +70,12 @@ def lib():
         L.or_overlap.restype = C.c_double
         L.or_aperture.argtypes = [dp, dp, C.c_long, C.c_long, dp, dp, C.c_long, dp, C.c_int, C.c_double,
                                   C.c_double, C.c_double, C.c_int, dp, dp, dp, dp, up]
+        L.or_filter_varying.argtypes = [dp, C.c_long, C.c_long, dp, C.c_int, C.c_int, C.c_int, dp, C.c_long,
+                                        C.c_long, C.c_int, dp]
         L.or_growth_radii.argtypes = [C.c_double, C.c_int, ip, C.POINTER(C.c_int)]
         L.or_tophat_taps.argtypes = [C.c_int, dp]
         L.or_growth.argtypes = [dp, dp, C.c_long, C.c_long, dp, dp, C.c_long, ip, C.c_int, dp, dp, dp, up]
-        for f in ("or_growth_radii", "or_tophat_taps", "or_growth", "or_mesh_one", "or_mesh_one_policy", "or_mesh_stats", "or_median_filter", "or_grid_eval", "or_grid_map",
+        for f in ("or_filter_varying", "or_growth_radii", "or_tophat_taps", "or_growth", "or_mesh_one", "or_mesh_one_policy", "or_mesh_stats", "or_median_filter", "or_grid_eval", "or_grid_map",
                   "or_filter", "or_threshold_label", "or_measure", "or_aperture", "or_peaks"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -206,6 +208,26 @@ def filter_image(M, K):
     F = np.zeros_like(Mm)
     _check(lib().or_filter(_p(Mm), W, H, _p(Kk), kw, kh, _p(F)), "filter")
     return F
+
+
+def filter_varying(M, kernels, coef=None, bin=1):
+    """S = M corr P0 + sum_k c_k (M corr e_k) with reflected borders; kernels
+    (K+1, kh, kw) with P0 first, coef (K, ny, nx) maps of bin x bin pixels."""
+    Mm = _f64(M)
+    H, W = Mm.shape
+    ks = _f64(kernels)
+    K = ks.shape[0] - 1
+    kh, kw = ks.shape[1], ks.shape[2]
+    S = np.zeros_like(Mm)
+    if K > 0:
+        c = _f64(coef)
+        assert c.shape[0] == K
+        cp, pitch, plane = _p(c), c.shape[2], c.shape[1] * c.shape[2]
+    else:
+        cp, pitch, plane = C.POINTER(C.c_double)(), 0, 0
+    _check(lib().or_filter_varying(_p(Mm), W, H, _p(ks), K, kw, kh, cp, pitch, plane, int(bin), _p(S)),
+           "filter_varying")
+    return S
 
 
 def threshold_label(F, R, thresh, minarea, conn):

@@ -20,7 +20,9 @@
  *     ceil(0.75 FWHM) to ceil(5 FWHM) is one top-hat correlation per radius
  *     read at the sources, with the variance map through the same kernel;
  *   - the paper's own detection keeps the local maxima of the matched-filter
- *     significance above the threshold, with first-moment centroids.
+ *     significance above the threshold, with first-moment centroids; with a
+ *     spatially varying PSF (reference plus eigenmodes with coefficient maps)
+ *     the filter is K + 1 correlations weighted by the maps.
  * The paper's own background/detection/photometry use FFTs and peak finding;
  * the mesh statistics follow the published SExtractor method the paper cites
  * (Bertin & Arnouts 1996: kappa-sigma clipping about the median until
@@ -427,6 +429,40 @@ int or_filter(const double* M, long W, long H, const double* K, int kw, int kh, 
                 }
             }
             F[y * W + x] = acc;
+        }
+    return OR_OK;
+}
+
+/*
+ * Spatially varying matched filter (Source Detection subsection): with the
+ * PSF written as a fixed reference P0 plus K fixed eigenmodes e_k whose
+ * amplitudes c_k vary over the frame,
+ *   S(x, y) = (M corr P0)(x, y) + sum_k c_k(x, y) (M corr e_k)(x, y),
+ * each term a correlation with reflected borders as in or_filter, the
+ * kernels used as given (no normalisation).  kernels: (K + 1) kernels of
+ * kh x kw, P0 first.  coef: K maps, map k at coef + k * plane, the value for
+ * pixel (x, y) at [(y / bin) * pitch + x / bin] (bin = 1: full-frame maps).
+ */
+int or_filter_varying(const double* M, long W, long H, const double* kernels, int K, int kw, int kh,
+                      const double* coef, long pitch, long plane, int bin, double* S) {
+    if (!M || !kernels || !S || W <= 0 || H <= 0 || K < 0 || kw <= 0 || kh <= 0 || !(kw % 2) || !(kh % 2) ||
+        bin < 1 || (K > 0 && !coef))
+        return OR_EINVAL;
+    const int hx = kw / 2, hy = kh / 2;
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) {
+            double s = 0.0;
+            for (int k = 0; k <= K; ++k) {
+                const double* Kk = kernels + (long)k * kh * kw;
+                double acc = 0.0;
+                for (int a = 0; a < kh; ++a) {
+                    const long yy = reflect(y + a - hy, H);
+                    for (int b = 0; b < kw; ++b) acc += Kk[a * kw + b] * M[yy * W + reflect(x + b - hx, W)];
+                }
+                const double c = (k == 0) ? 1.0 : coef[(long)(k - 1) * plane + (y / bin) * pitch + x / bin];
+                s += c * acc;
+            }
+            S[y * W + x] = s;
         }
     return OR_OK;
 }

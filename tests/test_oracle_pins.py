@@ -825,3 +825,66 @@ def test_growth_delta_reads_the_centroid_pixel_and_is_monotone():
     P = rng.uniform(0, 5, (H, W))
     o = oracle.growth(P, P, rng.uniform(0, W, 30), rng.uniform(0, H, 30), list(range(1, 13)))
     assert np.all(np.diff(o["sum"], axis=1) >= 0) and np.all(np.diff(o["area"], axis=1) > 0)
+
+
+# ----------------------------------------------------------------------------
+# spatially varying matched filter
+# ----------------------------------------------------------------------------
+def _eigen_model(K, kw, kh, seed):
+    """A reference kernel of unit sum and K zero-sum deviation patterns."""
+    rng = np.random.default_rng(seed)
+    P0 = gaussian_kernel(kw, 2.5).astype(np.float64) if kw == kh else rng.random((kh, kw))
+    P0 = P0 / P0.sum()
+    modes = rng.normal(0, 0.02, (K, kh, kw))
+    modes -= modes.mean(axis=(1, 2), keepdims=True)
+    return np.concatenate([P0[None], modes])
+
+
+def test_varying_filter_without_modes_is_the_plain_filter():
+    rng = np.random.default_rng(4)
+    M = rng.normal(0, 10, (37, 53))
+    ks = _eigen_model(0, 7, 7, 1)
+    S = oracle.filter_varying(M, ks)
+    np.testing.assert_allclose(S, oracle.filter_image(M, ks[0]), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(S, ndimage.correlate(M, ks[0], mode="reflect"), rtol=0, atol=1e-12)
+
+
+def test_varying_filter_with_constant_maps_is_one_correlation():
+    rng = np.random.default_rng(5)
+    H, W = 41, 29
+    M = rng.normal(0, 10, (H, W)) + np.arange(W)[None, :]
+    ks = _eigen_model(5, 9, 5, 2)
+    a = rng.normal(0, 2, 5)
+    coef = np.broadcast_to(a[:, None, None], (5, H, W)).copy()
+    S = oracle.filter_varying(M, ks, coef)
+    Keff = ks[0] + np.tensordot(a, ks[1:], axes=1)
+    np.testing.assert_allclose(S, ndimage.correlate(M, Keff, mode="reflect"), rtol=0, atol=1e-11)
+
+
+def test_varying_filter_is_the_local_psf_at_each_pixel():
+    """Brute force: at each output pixel assemble that pixel's kernel
+    P0 + sum c_k(x, y) e_k and correlate the mirrored window with it."""
+    rng = np.random.default_rng(6)
+    H, W = 23, 31
+    K, kh, kw = 3, 5, 7
+    M = rng.normal(0, 10, (H, W))
+    ks = _eigen_model(K, kw, kh, 3)
+    yy, xx = np.mgrid[0:H, 0:W]
+    coef = np.stack([np.sin(xx / 5.0) + yy / 10.0, np.cos(yy / 3.0) * xx / 20.0, (xx - yy) / 15.0])
+    S = oracle.filter_varying(M, ks, coef)
+    Mp = np.pad(M, ((kh // 2, kh // 2), (kw // 2, kw // 2)), mode="symmetric")   # half-sample mirror
+    for y in range(H):
+        for x in range(W):
+            Kp = ks[0] + np.tensordot(coef[:, y, x], ks[1:], axes=1)
+            want = float(np.sum(Kp * Mp[y:y + kh, x:x + kw]))
+            assert abs(S[y, x] - want) <= 1e-11 * (1 + abs(want)), (x, y)
+
+
+def test_varying_filter_binned_maps_equal_expanded_maps():
+    rng = np.random.default_rng(7)
+    H, W, b = 45, 38, 8
+    M = rng.normal(0, 10, (H, W))
+    ks = _eigen_model(2, 5, 5, 4)
+    small = rng.normal(0, 1, (2, -(-H // b), -(-W // b)))
+    full = np.repeat(np.repeat(small, b, axis=1), b, axis=2)[:, :H, :W]
+    np.testing.assert_array_equal(oracle.filter_varying(M, ks, small, bin=b), oracle.filter_varying(M, ks, full))
