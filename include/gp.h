@@ -21,7 +21,8 @@
  *                  an annulus background, and the propagated noise.
  *   gp_peaks       the paper's own detection: local maxima of the significance
  *                  F / R above the threshold with first-moment centroids (in
- *                  place of gp_detect's connected components).
+ *                  place of gp_detect's connected components); gp_peaks_psf
+ *                  the same with the spatially varying PSF's filter.
  *   gp_growth      growth curves: top-hat sums of M and of R^2 at every source
  *                  for the integer radii ceil(0.75 FWHM) .. ceil(5 FWHM).
  *
@@ -298,6 +299,37 @@ gp_status gp_peaks(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
                    const gp_bkg_params* bp, const void* bkg, const gp_det_params* dp,
                    const gp_peak_params* pp, gp_catalog* cat, int32_t* comp_status, void* ws,
                    size_t ws_bytes, void* stream);
+
+/* The paper's detection with its spatially varying PSF (Source Detection
+ * subsection): the PSF is a reference kernel P0 plus K eigenmodes e_k whose
+ * amplitudes c_k vary over the frame, and the matched filter is
+ *   S(x, y) = (M corr P0)(x, y) + sum_k c_k(x, y) (M corr e_k)(x, y),
+ * K + 1 correlations with half-sample reflected borders, the kernels used as
+ * given (no normalisation), the coefficients taken at the output pixel.
+ * Peaks, centroids and the catalogue then follow gp_peaks with S in place of
+ * F.  kernels: HOST pointer to (nmodes + 1) kernels of kh x kw floats
+ * (P0 first, row-major; odd sides <= 15); nmodes in [0, 8]; maps: HOST array
+ * of nframes entries, frame f's map k at maps[f].data + k * plane (DEVICE
+ * floats), the value for pixel (x, y) at [(y / bin) * pitch + x / bin]
+ * (bin = 1: full-frame maps; pitch >= ceil(width / bin)); maps may be NULL
+ * when nmodes = 0.  dp: thresh, sat_level and precision are used, its
+ * kernel is not.  Each output pixel costs (nmodes + 1) kw kh multiply-adds. */
+typedef struct gp_coef_maps {
+    const float* data;
+    int64_t pitch;         /* elements per map row          */
+    int64_t plane;         /* elements between two maps     */
+} gp_coef_maps;
+typedef struct gp_psf_model {
+    const float* kernels;
+    int32_t kw, kh;
+    int32_t nmodes;
+    int32_t bin;
+    const gp_coef_maps* maps;
+} gp_psf_model;
+gp_status gp_peaks_psf(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                       const gp_bkg_params* bp, const void* bkg, const gp_det_params* dp,
+                       const gp_peak_params* pp, const gp_psf_model* psf, gp_catalog* cat,
+                       int32_t* comp_status, void* ws, size_t ws_bytes, void* stream);
 
 /* Aperture photometry of every catalogued object; also ORs GP_FLAG_APER_TRUNC
  * into cat->flags. */

@@ -63,6 +63,15 @@ class gp_peak_params(C.Structure):
     _fields_ = [("sep", C.c_int32), ("cwin", C.c_int32)]
 
 
+class gp_coef_maps(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("pitch", C.c_int64), ("plane", C.c_int64)]
+
+
+class gp_psf_model(C.Structure):
+    _fields_ = [("kernels", C.POINTER(C.c_float)), ("kw", C.c_int32), ("kh", C.c_int32), ("nmodes", C.c_int32),
+                ("bin", C.c_int32), ("maps", C.POINTER(gp_coef_maps))]
+
+
 class gp_growth_params(C.Structure):
     _fields_ = [("radii", C.POINTER(C.c_int32)), ("nr", C.c_int32), ("precision", C.c_int32)]
 
@@ -77,7 +86,7 @@ class gp_phot(C.Structure):
 
 EXPORTS = ("gp_ctx_create", "gp_ctx_destroy", "gp_last_error", "gp_version", "gp_background_layout",
            "gp_workspace_size", "gp_background", "gp_background_map", "gp_detect", "gp_detect_noalloc",
-           "gp_peaks", "gp_aperture", "gp_growth_radii", "gp_growth",
+           "gp_peaks", "gp_peaks_psf", "gp_aperture", "gp_growth_radii", "gp_growth",
            "gp_profile_enable",
            "gp_profile_read", "gp_profile_reset", "gp_ctx_set_tuning", "gp_graph_create", "gp_graph_launch",
            "gp_graph_rebind", "gp_graph_destroy")
@@ -123,6 +132,9 @@ def load(path: str = LIB_PATH):
     L.gp_aperture.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp,
                               C.POINTER(gp_catalog), C.POINTER(gp_ap_params), C.POINTER(gp_phot), vp,
                               C.c_size_t, vp]
+    L.gp_peaks_psf.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp,
+                               C.POINTER(gp_det_params), C.POINTER(gp_peak_params), C.POINTER(gp_psf_model),
+                               C.POINTER(gp_catalog), vp, vp, C.c_size_t, vp]
     L.gp_growth_radii.argtypes = [C.c_double, i32, C.POINTER(i32), C.POINTER(i32)]
     L.gp_growth.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp, C.POINTER(gp_catalog),
                             C.POINTER(gp_growth_params), C.POINTER(gp_growth_out), vp, C.c_size_t, vp]
@@ -139,7 +151,7 @@ def load(path: str = LIB_PATH):
     L.gp_profile_reset.argtypes = [vp]
     for f in ("gp_ctx_create", "gp_background_layout", "gp_workspace_size", "gp_background",
               "gp_background_map", "gp_detect", "gp_detect_noalloc", "gp_peaks",
-              "gp_aperture", "gp_growth_radii", "gp_growth", "gp_profile_enable", "gp_profile_read", "gp_profile_reset", "gp_graph_create",
+              "gp_aperture", "gp_peaks_psf", "gp_growth_radii", "gp_growth", "gp_profile_enable", "gp_profile_read", "gp_profile_reset", "gp_graph_create",
               "gp_graph_launch", "gp_graph_rebind"):
         getattr(L, f).restype = C.c_int
     _lib = L
@@ -229,6 +241,13 @@ def gp_aperture(ctx, frames, bp, bkg_ptr, cat, ap, phot, ws_ptr, ws_bytes, strea
     arr = (gp_frame * n)(*frames)
     check(load().gp_aperture(ctx, arr, n, C.byref(bp), bkg_ptr, C.byref(cat), C.byref(ap), C.byref(phot),
                              ws_ptr, ws_bytes, stream))
+
+
+def gp_peaks_psf(ctx, frames, bp, bkg_ptr, dp, pp, psf, cat, comp_status_ptr, ws_ptr, ws_bytes, stream):
+    n = len(frames)
+    arr = (gp_frame * n)(*frames)
+    check(load().gp_peaks_psf(ctx, arr, n, C.byref(bp), bkg_ptr, C.byref(dp), C.byref(pp), C.byref(psf),
+                              C.byref(cat), comp_status_ptr, ws_ptr, ws_bytes, stream))
 
 
 def gp_growth_radii(fwhm):

@@ -66,9 +66,29 @@ struct CatOut {
     uint32_t* flags;
 };
 
-// peak detection: separation and centroid half-widths (pixels)
+// spatially varying matched filter: a reference kernel and up to kMaxModes
+// eigenmodes (taps as given, [row][column][mode] with P0 as mode 0, modes
+// padded to kMaxModes + 1) and, per frame,
+// the coefficient maps (map k of frame f at pf[f].data + k * plane; pixel
+// (x, y) reads [(y / bin) * pitch + x / bin])
+constexpr int kMaxModes = 8;
+constexpr int kPsfTaps = (kMaxModes + 1) * kMaxK * kMaxK;
+struct PsfArgs {
+    int32_t nmodes, bin, kw, kh;
+    float taps[kPsfTaps];
+    double tapsd[kPsfTaps];
+};
+struct PsfFrame {
+    const float* data;
+    int64_t pitch, plane;
+};
+
+// peak detection: separation and centroid half-widths (pixels); psf and pf
+// set for the spatially varying filter, else null
 struct PeakArgs {
     int32_t sep, cwin;
+    const PsfArgs* psf;
+    const PsfFrame* pf;
 };
 constexpr int kMaxPeakWin = 7;
 
@@ -112,7 +132,11 @@ void launch_catalog(const DetWork& wk, const CatOut& cat, int minarea, int persi
                     hipStream_t s);
 void launch_seg(const DetWork& wk, int f, int64_t npx, hipStream_t s);
 void launch_peaks(const DetWork& wk, const DetArgs* args, const CatOut& cat, int32_t* comp_status, bool f64, int sep,
-                  int cwin, int kw, int kh, int persist_blocks, hipStream_t s);
+                  int cwin, int kw, int kh, int persist_blocks, const PsfArgs* psf, const PsfFrame* pf,
+                  int nmodes, hipStream_t s);
+// copy `bytes` (a multiple of 4) from host memory to device memory through
+// kernel arguments (no copy engine, so the call can be captured)
+void launch_write_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
 size_t peak_lds_bytes(int sep, int cwin, int kw, int kh, bool f64);
 // one: the descriptor of a one-frame call, passed with the launch (the
 // workspace table is then not read), or null

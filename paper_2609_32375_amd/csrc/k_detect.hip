@@ -1153,8 +1153,12 @@ struct PeakLayout {
     }
 };
 
-template <typename Real>
+// NM > 0: the spatially varying filter (NM dense correlations, the reference
+// and up to NM - 1 modes, weighted by the coefficient maps at the output
+// pixel) in place of the plain one; modes past the model's are zero taps
+template <typename Real, int NM>
 __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* __restrict__ pa, PeakArgs pk) {
+    constexpr bool VARY = NM > 0;
     extern __shared__ __align__(16) unsigned char pk_dyn[];
     constexpr bool kDbl = sizeof(Real) == 8;
     const int tid = threadIdx.x;
@@ -1192,7 +1196,8 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
     }
     if (tid < kTile * 2) cand[tid] = 0u;
     __shared__ Real taps[kMaxK * kMaxK];
-    for (int i = tid; i < kw * kh; i += 256) taps[i] = kDbl ? (Real)pa->kdd[i] : (Real)pa->kd[i];
+    if (!VARY)
+        for (int i = tid; i < kw * kh; i += 256) taps[i] = kDbl ? (Real)pa->kdd[i] : (Real)pa->kd[i];
     // 1. raw pixels of the M region (reflected at the frame), row cubics and
     //    column pieces
     const int gx0 = x0 - L.hmx, gy0 = y0 - L.hmy;
@@ -1244,7 +1249,65 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
     //    filter below skips those positions); candidates F > t R inside the tile
     const Real ts = (Real)pa->thresh;
     const int fw = tw + 2 * sep, fh = th + 2 * sep;
-    const bool sepk = pa->separable != 0;
+    const bool sepk = !VARY && pa->separable != 0;
+    if (VARY) {
+        // S = sum_m c_m (M corr e_m) (c_0 = 1) over the tile plus sep, into
+        // nus.  A work item is kVaryRows output rows of one column: per tap
+        // the item reads its kVaryRows M values once and updates
+        // (K + 1) x kVaryRows accumulators; the taps come through the scalar
+        // cache (uniform addresses, [row][column][mode] layout)
+        typedef __attribute__((address_space(4))) const Real ctap_t;
+        const ctap_t* tp = (const ctap_t*)(kDbl ? (const void*)pk.psf->tapsd : (const void*)pk.psf->taps);
+        const int nmodes = pk.psf->nmodes;
+        constexpr int kVaryRows = 8;
+        const int nrb = (fh + kVaryRows - 1) / kVaryRows;
+        for (int it = tid; it < fw * nrb; it += 256) {
+            const int i = it % fw, j0 = (it / fw) * kVaryRows;
+            const int mc = i - sep + L.hmx - rx;           // first M column read
+            const int mr0 = j0 - sep + L.hmy - ry;         // first M row read
+            constexpr int NA = VARY ? NM : 1;
+            Real acc[NA][kVaryRows];
+#pragma unroll
+            for (int m = 0; m < NA; ++m)
+#pragma unroll
+                for (int r = 0; r < kVaryRows; ++r) acc[m][r] = 0;
+            for (int a = 0; a < kh; ++a) {
+                int rowoff[kVaryRows];
+#pragma unroll
+                for (int r = 0; r < kVaryRows; ++r) rowoff[r] = min(mr0 + a + r, L.rmh - 1) * L.rmw + mc;
+                for (int b = 0; b < kw; ++b) {
+                    const ctap_t* tq = tp + (a * kw + b) * (kMaxModes + 1);
+                    Real t[NA];
+#pragma unroll
+                    for (int m = 0; m < NA; ++m) t[m] = tq[m];
+                    Real mv[kVaryRows];
+#pragma unroll
+                    for (int r = 0; r < kVaryRows; ++r) mv[r] = ms[rowoff[r] + b];
+#pragma unroll
+                    for (int m = 0; m < NA; ++m)
+#pragma unroll
+                        for (int r = 0; r < kVaryRows; ++r) acc[m][r] = fma(t[m], mv[r], acc[m][r]);
+                }
+            }
+            const PsfFrame pfr = pk.pf[f];
+            const int bin = pk.psf->bin;
+            const int gx = x0 - sep + i;
+#pragma unroll
+            for (int r = 0; r < kVaryRows; ++r) {
+                const int j = j0 + r, gy = y0 - sep + j;
+                if (j >= fh) break;
+                Real sv = acc[0][r];
+                if (gx >= 0 && gx < d.W && gy >= 0 && gy < d.H) {
+                    const float* cp = pfr.data + (int64_t)(gy / bin) * pfr.pitch + gx / bin;
+#pragma unroll
+                    for (int m = 1; m < NA; ++m)
+                        if (m <= nmodes) sv = fma((Real)cp[(int64_t)(m - 1) * pfr.plane], acc[m][r], sv);
+                }
+                nus[j * L.rf + i] = sv;
+            }
+        }
+        __syncthreads();
+    }
     if (sepk) {
         // horizontal pass over the M rows the vertical pass reads
         const int hr = fh + 2 * ry;
@@ -1268,7 +1331,11 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
             const int j = e / fw, i = e - j * fw;
             const int mr = j - sep + L.hmy, mc = i - sep + L.hmx;   // M-region position of (x, y)
             Real acc = 0;
-            if (sepk) {
+            const int gx = x0 - sep + i, gy = y0 - sep + j;
+            const bool in = gx >= 0 && gx < d.W && gy >= 0 && gy < d.H;
+            if (VARY) {
+                acc = nus[j * L.rf + i];
+            } else if (sepk) {
                 for (int a = 0; a < kh; ++a)
                     acc = fma(kDbl ? (Real)pa->kyd[a] : (Real)pa->ky[a], nus[(j + a) * L.rf + i], acc);
             } else {
@@ -1279,8 +1346,6 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
                 }
             }
             const Real R = eval_R(tab[mr * L.nix + colp[mc]], colsx[mc]);
-            const int gx = x0 - sep + i, gy = y0 - sep + j;
-            const bool in = gx >= 0 && gx < d.W && gy >= 0 && gy < d.H;
             nv[q] = in ? ((R > (Real)0) ? acc / R : acc) : (Real)-INFINITY;
             const int lx = i - sep, ly = j - sep;
             if (lx >= 0 && lx < tw && ly >= 0 && ly < th && acc > ts * R)
@@ -1456,21 +1521,32 @@ __global__ __launch_bounds__(256) void k_write_peaks(DetWork wk, CatOut cat, int
     }
 }
 
-void launch_peaks(const DetWork& wk, const DetArgs* args, const CatOut& cat, int32_t* comp_status, bool f64, int sep,
-                  int cwin, int kw, int kh, int persist_blocks, hipStream_t s) {
-    const PeakArgs pk{sep, cwin};
+template <typename Real, int NM>
+static void launch_peak_tiles(const DetWork& wk, const DetArgs* args, const PeakArgs& pk, int kw, int kh,
+                              hipStream_t s) {
+    const PeakLayout L(pk.sep, pk.cwin, kw / 2, kh / 2, (int)sizeof(Real), (int)sizeof(RowT<Real>));
     const int g = kXcds * ((wk.total_tiles + kXcds - 1) / kXcds);
-    if (f64) {
-        const PeakLayout L(sep, cwin, kw / 2, kh / 2, 8, (int)sizeof(RowT<double>));
-        (void)hipFuncSetAttribute((const void*)k_peaks_tiles<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  L.bytes);
-        k_peaks_tiles<double><<<g, 256, L.bytes, s>>>(wk, args, pk);
-    } else {
-        const PeakLayout L(sep, cwin, kw / 2, kh / 2, 4, (int)sizeof(RowT<float>));
-        (void)hipFuncSetAttribute((const void*)k_peaks_tiles<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  L.bytes);
-        k_peaks_tiles<float><<<g, 256, L.bytes, s>>>(wk, args, pk);
-    }
+    (void)hipFuncSetAttribute((const void*)k_peaks_tiles<Real, NM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              L.bytes);
+    k_peaks_tiles<Real, NM><<<g, 256, L.bytes, s>>>(wk, args, pk);
+}
+
+template <typename Real>
+static void launch_peak_tiles_t(const DetWork& wk, const DetArgs* args, const PeakArgs& pk, int kw, int kh,
+                                int nmodes, hipStream_t s) {
+    if (!pk.psf) launch_peak_tiles<Real, 0>(wk, args, pk, kw, kh, s);
+    else if (nmodes < 2) launch_peak_tiles<Real, 2>(wk, args, pk, kw, kh, s);
+    else if (nmodes < 4) launch_peak_tiles<Real, 4>(wk, args, pk, kw, kh, s);
+    else if (nmodes < 6) launch_peak_tiles<Real, 6>(wk, args, pk, kw, kh, s);
+    else launch_peak_tiles<Real, kMaxModes + 1>(wk, args, pk, kw, kh, s);
+}
+
+void launch_peaks(const DetWork& wk, const DetArgs* args, const CatOut& cat, int32_t* comp_status, bool f64, int sep,
+                  int cwin, int kw, int kh, int persist_blocks, const PsfArgs* psf, const PsfFrame* pf,
+                  int nmodes, hipStream_t s) {
+    const PeakArgs pk{sep, cwin, psf, pf};
+    if (f64) launch_peak_tiles_t<double>(wk, args, pk, kw, kh, nmodes, s);
+    else launch_peak_tiles_t<float>(wk, args, pk, kw, kh, nmodes, s);
     k_peak_bits<<<persist_blocks, 256, 0, s>>>(wk);
     const int nb = wk.total_blocks;
     k_popc_scan<<<(nb + kScanChunk - 1) / kScanChunk, 256, 0, s>>>(wk.bitmap, wk.blockcnt, wk.chunksum, nb);
@@ -1565,6 +1641,29 @@ __global__ __launch_bounds__(256) void k_det_setup(DescChunk c, FrameDesc* table
         out->ky[t] = in.ky[t];
         out->kxd[t] = in.kxd[t];
         out->kyd[t] = in.kyd[t];
+    }
+}
+
+struct WordChunk {
+    uint32_t n;
+    uint32_t w[960];
+};
+__global__ void k_write_words(uint32_t* dst, WordChunk c) {
+    for (uint32_t i = threadIdx.x; i < c.n; i += blockDim.x) dst[i] = c.w[i];
+}
+
+void launch_write_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    const uint32_t* w = (const uint32_t*)src;
+    size_t nw = bytes / 4;
+    uint32_t* d = (uint32_t*)dst;
+    while (nw > 0) {
+        WordChunk c;
+        c.n = (uint32_t)std::min<size_t>(nw, 960);
+        for (uint32_t i = 0; i < c.n; ++i) c.w[i] = w[i];
+        k_write_words<<<1, 256, 0, s>>>(d, c);
+        w += c.n;
+        d += c.n;
+        nw -= c.n;
     }
 }
 

@@ -149,7 +149,8 @@ struct Plan {
     size_t bkg_bytes = 0;
     // workspace sections
     size_t o_desc = 0, o_detargs = 0, o_counters = 0, o_tiles = 0, o_edges = 0, o_recs = 0, o_parent = 0,
-           o_root = 0, o_label = 0, o_bitmap = 0, o_blockcnt = 0, o_chunks = 0, o_spline = 0, ws_bytes = 0;
+           o_root = 0, o_label = 0, o_bitmap = 0, o_blockcnt = 0, o_chunks = 0, o_spline = 0, o_psf = 0,
+           ws_bytes = 0;
     int64_t rec_cap = 0;
 };
 
@@ -286,6 +287,7 @@ void plan_fixed(int32_t nframes, Plan& P) {
     P.o_bitmap = sec(128 * (size_t)P.total_blocks);
     P.o_blockcnt = sec(sizeof(uint32_t) * (P.total_blocks + 1));
     P.o_chunks = sec(sizeof(uint32_t) * (ceil_div(P.total_blocks, kScanChunk) + 1));
+    P.o_psf = sec(sizeof(PsfArgs) + sizeof(PsfFrame) * nframes);
     P.o_spline = o;
     for (int f = 0; f < nframes; ++f) {
         FramePlan& F = P.fr[f];
@@ -411,6 +413,29 @@ bool separable_factors(const gp_det_params* dp, double* kx, double* ky) {
     for (int a = 0; a < kh; ++a) ky[a] = u[a] / su;
     for (int b = 0; b < kw; ++b) kx[b] = v[b] / sv;
     return true;
+}
+
+// filter arguments of a detection call (the dense kernel is normalised on the
+// device; a rank-one kernel also gets its normalised factors)
+DetArgsIn det_in(const gp_det_params* dp) {
+    DetArgsIn in{};
+    in.kw = dp->kw;
+    in.kh = dp->kh;
+    in.conn = dp->connectivity;
+    in.thresh = dp->thresh;
+    in.sat = dp->sat_level;
+    in.minarea = dp->minarea;
+    in.want_seg = 0;
+    for (int i = 0; i < dp->kw * dp->kh; ++i) in.kraw[i] = dp->kernel[i];
+    double kx[kMaxK] = {0}, ky[kMaxK] = {0};
+    in.separable = separable_factors(dp, kx, ky) ? 1 : 0;
+    for (int i = 0; i < kMaxK; ++i) {
+        in.kx[i] = (float)kx[i];
+        in.ky[i] = (float)ky[i];
+        in.kxd[i] = kx[i];
+        in.kyd[i] = ky[i];
+    }
+    return in;
 }
 
 gp_status check_ws(const Plan& P, void* ws, size_t ws_bytes) {
@@ -742,23 +767,8 @@ static gp_status detect_run(gp_ctx* ctx, const gp_frame* frames, int32_t nframes
     if ((st = upload_desc(frames, nframes, bp, P, bkg, ws, cat->capacity, seg, s, &tail)) != GP_OK) return st;
     char* W = (char*)ws;
     // filter arguments
-    DetArgsIn in{};
-    in.kw = dp->kw;
-    in.kh = dp->kh;
-    in.conn = dp->connectivity;
-    in.thresh = dp->thresh;
-    in.sat = dp->sat_level;
-    in.minarea = dp->minarea;
+    DetArgsIn in = det_in(dp);
     in.want_seg = seg ? 1 : 0;
-    for (int i = 0; i < dp->kw * dp->kh; ++i) in.kraw[i] = dp->kernel[i];
-    double kx[kMaxK] = {0}, ky[kMaxK] = {0};
-    in.separable = separable_factors(dp, kx, ky) ? 1 : 0;
-    for (int i = 0; i < kMaxK; ++i) {
-        in.kx[i] = (float)kx[i];
-        in.ky[i] = (float)ky[i];
-        in.kxd[i] = kx[i];
-        in.kyd[i] = ky[i];
-    }
     DetArgs* dargs = (DetArgs*)(W + P.o_detargs);
     DetWork wk{};
     wk.desc = (FrameDesc*)(W + P.o_desc);
@@ -838,19 +848,49 @@ extern "C" gp_status gp_detect_noalloc(gp_ctx* ctx, const gp_frame* frames, int3
                       false);
 }
 
-extern "C" gp_status gp_peaks(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
-                              const void* bkg, const gp_det_params* dp, const gp_peak_params* pp, gp_catalog* cat,
-                              int32_t* comp_status, void* ws, size_t ws_bytes, void* stream) {
+// gp_peaks and gp_peaks_psf (psf null: the plain filter of dp)
+static gp_status peaks_run(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
+                           const void* bkg, const gp_det_params* dp, const gp_peak_params* pp,
+                           const gp_psf_model* psf, gp_catalog* cat, int32_t* comp_status, void* ws, size_t ws_bytes,
+                           void* stream) {
     if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
     gp_status st;
     if ((st = check_frames(frames, nframes)) != GP_OK) return st;
     if ((st = check_bkg(bp, frames, nframes)) != GP_OK) return st;
-    if ((st = check_det(dp)) != GP_OK) return st;
+    if (psf) {
+        if (!dp) return fail(GP_ERR_INVALID_ARG, "detection parameters are NULL");
+        if (!std::isfinite(dp->thresh)) return fail(GP_ERR_INVALID_ARG, "thresh must be finite");
+        if (std::isnan(dp->sat_level)) return fail(GP_ERR_INVALID_ARG, "sat_level is NaN");
+        if (dp->precision != GP_PREC_F32 && dp->precision != GP_PREC_F64)
+            return fail(GP_ERR_INVALID_ARG, "unknown precision %d", dp->precision);
+        if (!psf->kernels) return fail(GP_ERR_INVALID_ARG, "PSF kernels are NULL");
+        if (psf->kw < 1 || psf->kh < 1 || psf->kw > kMaxK || psf->kh > kMaxK || !(psf->kw & 1) || !(psf->kh & 1))
+            return fail(GP_ERR_INVALID_ARG, "PSF kernels must be odd and at most 15 per side (got %dx%d)", psf->kw,
+                        psf->kh);
+        if (psf->nmodes < 0 || psf->nmodes > kMaxModes)
+            return fail(GP_ERR_INVALID_ARG, "nmodes must be in [0, %d]", kMaxModes);
+        if (psf->bin < 1) return fail(GP_ERR_INVALID_ARG, "coefficient-map bin must be >= 1");
+        for (int i = 0; i < (psf->nmodes + 1) * psf->kw * psf->kh; ++i)
+            if (!std::isfinite(psf->kernels[i])) return fail(GP_ERR_INVALID_ARG, "PSF kernel has a non-finite tap");
+        if (psf->nmodes > 0) {
+            if (!psf->maps) return fail(GP_ERR_INVALID_ARG, "coefficient maps are NULL");
+            for (int f = 0; f < nframes; ++f) {
+                const gp_coef_maps& m = psf->maps[f];
+                const int64_t mx = ceil_div(frames[f].width, psf->bin), my = ceil_div(frames[f].height, psf->bin);
+                if (!m.data) return fail(GP_ERR_INVALID_ARG, "coefficient maps of frame %d are NULL", f);
+                if (m.pitch < mx || (psf->nmodes > 1 && m.plane < m.pitch * my) || m.plane < 0)
+                    return fail(GP_ERR_INVALID_ARG, "coefficient maps of frame %d: pitch or plane too small", f);
+            }
+        }
+    } else if ((st = check_det(dp)) != GP_OK) {
+        return st;
+    }
     if (!pp) return fail(GP_ERR_INVALID_ARG, "peak parameters are NULL");
     if (pp->sep < 0 || pp->sep > kMaxPeakWin || pp->cwin < 0 || pp->cwin > kMaxPeakWin)
         return fail(GP_ERR_INVALID_ARG, "sep and cwin must be in [0, %d] (got %d, %d)", kMaxPeakWin, pp->sep, pp->cwin);
     if ((st = check_cat(cat, true)) != GP_OK) return st;
     if (!bkg) return fail(GP_ERR_INVALID_ARG, "background buffer is NULL");
+    const int kw = psf ? psf->kw : dp->kw, kh = psf ? psf->kh : dp->kh;
     Plan P;
     plan_bkg(frames, nframes, bp, P);
     plan_fixed(nframes, P);
@@ -861,7 +901,8 @@ extern "C" gp_status gp_peaks(gp_ctx* ctx, const gp_frame* frames, int32_t nfram
     if (ceil_div(P.total_blocks, kScanChunk) > kMaxScanChunks)
         return fail(GP_ERR_UNSUPPORTED, "a detection batch holds at most 2^31 pixels (1024-pixel blocks per frame)");
     const bool f64 = dp->precision == GP_PREC_F64;
-    if (peak_lds_bytes(pp->sep, pp->cwin, dp->kw, dp->kh, f64) > 160 * 1024)
+    const size_t taps_lds = (size_t)kMaxK * kMaxK * (f64 ? 8 : 4);
+    if (peak_lds_bytes(pp->sep, pp->cwin, kw, kh, f64) + taps_lds > 160 * 1024)
         return fail(GP_ERR_UNSUPPORTED, "peak windows and filter too large for one tile's LDS");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(ctx->device));
@@ -869,14 +910,19 @@ extern "C" gp_status gp_peaks(gp_ctx* ctx, const gp_frame* frames, int32_t nfram
     if ((st = upload_desc(frames, nframes, bp, P, bkg, ws, cat->capacity, nullptr, s, &tail)) != GP_OK) return st;
     char* W = (char*)ws;
     DetArgsIn in{};
-    in.kw = dp->kw;
-    in.kh = dp->kh;
-    in.conn = dp->connectivity;
-    in.thresh = dp->thresh;
-    in.sat = dp->sat_level;
-    in.minarea = dp->minarea;
-    in.want_seg = 0;
-    for (int i = 0; i < dp->kw * dp->kh; ++i) in.kraw[i] = dp->kernel[i];
+    if (psf) {
+        // the plain-filter fields are unused: a dense reference tap keeps the
+        // device normalisation finite
+        in.kw = kw;
+        in.kh = kh;
+        in.conn = 8;
+        in.thresh = dp->thresh;
+        in.sat = dp->sat_level;
+        in.minarea = 1;
+        in.kraw[(kh / 2) * kw + kw / 2] = 1.0f;
+    } else {
+        in = det_in(dp);
+    }
     DetArgs* dargs = (DetArgs*)(W + P.o_detargs);
     DetWork wk{};
     wk.desc = (FrameDesc*)(W + P.o_desc);
@@ -894,19 +940,60 @@ extern "C" gp_status gp_peaks(gp_ctx* ctx, const gp_frame* frames, int32_t nfram
     wk.bitmap = (uint32_t*)(W + P.o_bitmap);
     wk.rec_cap = (int32_t)P.rec_cap;
     wk.total_blocks = (int32_t)P.total_blocks;
+    PsfArgs* pargs = nullptr;
+    PsfFrame* pframes = nullptr;
     {
         ProfScope ps(ctx, s, "setup");
         launch_det_setup(tail, (FrameDesc*)(W + P.o_desc), in, dargs, wk.counters, s);
+        if (psf) {
+            // the model's header and taps (FP32 as given and their exact FP64
+            // values), then the frames' map descriptors
+            pargs = (PsfArgs*)(W + P.o_psf);
+            pframes = (PsfFrame*)(W + P.o_psf + sizeof(PsfArgs));
+            // taps as [row][column][mode], modes padded to kMaxModes + 1
+            const int nt = kw * kh * (kMaxModes + 1);
+            std::vector<float> tf(nt, 0.0f);
+            std::vector<double> td(nt, 0.0);
+            for (int m = 0; m <= psf->nmodes; ++m)
+                for (int i = 0; i < kw * kh; ++i) {
+                    tf[i * (kMaxModes + 1) + m] = psf->kernels[m * kw * kh + i];
+                    td[i * (kMaxModes + 1) + m] = (double)psf->kernels[m * kw * kh + i];
+                }
+            const int32_t hdr[4] = {psf->nmodes, psf->bin, kw, kh};
+            launch_write_bytes(pargs, hdr, sizeof(hdr), s);
+            launch_write_bytes(pargs->taps, tf.data(), tf.size() * 4, s);
+            launch_write_bytes(pargs->tapsd, td.data(), td.size() * 8, s);
+            std::vector<PsfFrame> pf(nframes);
+            for (int f = 0; f < nframes; ++f)
+                pf[f] = psf->nmodes > 0 ? PsfFrame{psf->maps[f].data, psf->maps[f].pitch, psf->maps[f].plane}
+                                        : PsfFrame{nullptr, 0, 0};
+            launch_write_bytes(pframes, pf.data(), pf.size() * sizeof(PsfFrame), s);
+        }
     }
     HIP_TRY(hipGetLastError());
     CatOut co{cat->capacity, cat->n_obj, cat->status, cat->npix, cat->xmin, cat->xmax, cat->ymin, cat->ymax,
               cat->pmin, cat->flux, cat->x, cat->y, cat->x2, cat->y2, cat->xy, cat->peak, cat->flags};
     {
-        ProfScope ps(ctx, s, "peaks");
-        launch_peaks(wk, dargs, co, comp_status, f64, pp->sep, pp->cwin, dp->kw, dp->kh, ctx->cus * 4, s);
+        ProfScope ps(ctx, s, psf ? "peaks_psf" : "peaks");
+        launch_peaks(wk, dargs, co, comp_status, f64, pp->sep, pp->cwin, kw, kh, ctx->cus * 4, pargs, pframes,
+                     psf ? psf->nmodes : 0, s);
     }
     HIP_TRY(hipGetLastError());
     return GP_OK;
+}
+
+extern "C" gp_status gp_peaks(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
+                              const void* bkg, const gp_det_params* dp, const gp_peak_params* pp, gp_catalog* cat,
+                              int32_t* comp_status, void* ws, size_t ws_bytes, void* stream) {
+    return peaks_run(ctx, frames, nframes, bp, bkg, dp, pp, nullptr, cat, comp_status, ws, ws_bytes, stream);
+}
+
+extern "C" gp_status gp_peaks_psf(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,
+                                  const void* bkg, const gp_det_params* dp, const gp_peak_params* pp,
+                                  const gp_psf_model* psf, gp_catalog* cat, int32_t* comp_status, void* ws,
+                                  size_t ws_bytes, void* stream) {
+    if (!psf) return fail(GP_ERR_INVALID_ARG, "PSF model is NULL");
+    return peaks_run(ctx, frames, nframes, bp, bkg, dp, pp, psf, cat, comp_status, ws, ws_bytes, stream);
 }
 
 extern "C" gp_status gp_aperture(gp_ctx* ctx, const gp_frame* frames, int32_t nframes, const gp_bkg_params* bp,

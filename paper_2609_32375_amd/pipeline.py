@@ -192,6 +192,29 @@ class Photometry:
                    L.gp_peak_params(int(sep), int(cwin)), self.gcat, C.c_void_p(self.comp_status.data_ptr()),
                    C.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.stream_ptr(stream))
 
+    def peaks_psf(self, sep: int, cwin: int, kernels: np.ndarray, coef: Optional[Sequence[torch.Tensor]] = None,
+                  bin: int = 1, stream=None):
+        """The paper's detection with a spatially varying PSF: kernels
+        (K+1, kh, kw) float32 with the reference first, coef one device
+        tensor (K, ceil(H / bin), ceil(W / bin)) float32 per frame."""
+        ks = np.ascontiguousarray(kernels, dtype=np.float32)
+        K, kh, kw = ks.shape[0] - 1, ks.shape[1], ks.shape[2]
+        maps = None
+        if K > 0:
+            if coef is None or len(coef) != self.n:
+                raise ValueError("one coefficient-map tensor per frame is needed")
+            arr = []
+            for c in coef:
+                if c.dtype != torch.float32 or c.dim() != 3 or c.shape[0] != K or c.stride(2) != 1:
+                    raise ValueError("coefficient maps must be float32 (K, rows, cols) with unit column stride")
+                arr.append(L.gp_coef_maps(c.data_ptr(), c.stride(1), c.stride(0)))
+            maps = (L.gp_coef_maps * self.n)(*arr)
+        psf = L.gp_psf_model(ks.ctypes.data_as(C.POINTER(C.c_float)), kw, kh, K, int(bin), maps)
+        L.gp_peaks_psf(self.ctx, self.frames, self.bp, C.c_void_p(self.bkg.data_ptr()), self.dp,
+                       L.gp_peak_params(int(sep), int(cwin)), psf, self.gcat,
+                       C.c_void_p(self.comp_status.data_ptr()), C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                       self.stream_ptr(stream))
+
     def aperture(self, stream=None):
         L.gp_aperture(self.ctx, self.frames, self.bp, C.c_void_p(self.bkg.data_ptr()), self.gcat, self.ap,
                       self.gphot, C.c_void_p(self.ws.data_ptr()), self.ws_bytes, self.stream_ptr(stream))

@@ -408,3 +408,55 @@ def batch_shapes(count_scale: float = 1.0, seed0: int = 1000):
         n = int(round(300.0 * (40000.0 / 300.0) ** r.random()))
         out.append((w, h, n, seed0 + i))
     return out
+
+
+def psf_model(nmodes: int = 5, size: int = 9, fwhm: float = 3.0, seed: int = 0) -> np.ndarray:
+    """A reference kernel plus nmodes eigenmodes, float32 (nmodes + 1, size,
+    size): the reference is a unit-sum circular Gaussian, the modes are
+    zero-sum deviation patterns (the Gaussian times dx, dy, dx^2 - dy^2,
+    dx dy, r^2 - <r^2>, then random smooth patterns), each scaled to a peak of
+    a few percent of the reference's, as a PCA of star stamps about their
+    mean gives.  Synthetic stand-in for a fitted eigen-PSF model."""
+    rng = np.random.default_rng(seed)
+    g = gaussian_kernel(size, fwhm).astype(np.float64)
+    g /= g.sum()
+    h = size // 2
+    yy, xx = np.mgrid[-h:h + 1, -h:h + 1].astype(np.float64)
+    shapes = [xx, yy, xx * xx - yy * yy, xx * yy, xx * xx + yy * yy]
+    out = [g]
+    for k in range(nmodes):
+        base = shapes[k] if k < len(shapes) else rng.normal(0, 1, (size, size))
+        e = base * g
+        e -= e.mean()
+        e *= rng.uniform(0.02, 0.05) * g.max() / max(np.abs(e).max(), 1e-30)
+        out.append(e)
+    return np.ascontiguousarray(np.stack(out), dtype=np.float32)
+
+
+def coef_maps(nmodes: int, W: int, H: int, bin: int = 1, seed: int = 0) -> np.ndarray:
+    """Smooth coefficient maps, float32 (nmodes, ceil(H / bin), ceil(W /
+    bin)): low-order polynomials of the normalised position with O(1)
+    amplitude, evaluated at each bin's first pixel (the amplitudes of the PSF
+    modes vary slowly over a wide field)."""
+    rng = np.random.default_rng(seed)
+    ny, nx = -(-H // bin), -(-W // bin)
+    v = (np.arange(ny) * bin / max(H, 1))[:, None] - 0.5
+    u = (np.arange(nx) * bin / max(W, 1))[None, :] - 0.5
+    out = np.empty((nmodes, ny, nx))
+    for k in range(nmodes):
+        c = rng.normal(0, 1, 6)
+        out[k] = c[0] + c[1] * u + c[2] * v + c[3] * u * u + c[4] * u * v + c[5] * v * v
+    return np.ascontiguousarray(out, dtype=np.float32)
+
+
+def coef_maps_gpu(torch, nmodes: int, W: int, H: int, seed: int = 0, device: str = "cuda"):
+    """coef_maps at full resolution (bin 1), rendered on the device as one
+    float32 tensor (nmodes, H, W) (large frames: no host round trip)."""
+    rng = np.random.default_rng(seed)
+    v = (torch.arange(H, device=device, dtype=torch.float32) / max(H, 1) - 0.5)[:, None]
+    u = (torch.arange(W, device=device, dtype=torch.float32) / max(W, 1) - 0.5)[None, :]
+    out = torch.empty(nmodes, H, W, device=device, dtype=torch.float32)
+    for k in range(nmodes):
+        c = [float(x) for x in rng.normal(0, 1, 6)]
+        out[k] = c[0] + c[1] * u + c[2] * v + c[3] * u * u + c[4] * u * v + c[5] * v * v
+    return out

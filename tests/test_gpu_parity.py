@@ -463,29 +463,12 @@ PEAK_CASES = [
 ]
 
 
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "fp64"])
-@pytest.mark.parametrize("case", PEAK_CASES, ids=lambda c: f"{c[1]}x{c[2]}-{c[3]}-t{c[5]}-s{c[6]}-c{c[7]}-{c[8] or 'gauss'}")
-def test_peaks_stage_isolated(P, case, prec):
-    name, W, H, dt, seed, t, sep, cw, kk = case
-    _say("peak case", case, prec)
-    fr = make_frame(name, seed=seed, W=W, H=H, dtype=dt, nstars=max(8, W * H // 2500))
-    p = f32_params(fr.params)
-    p.mesh_w = p.mesh_h = 64
-    p.thresh = t
-    p.sat_level = 60000.0
-    K = p.kernel() if kk is None else (0.3 + np.random.default_rng(seed).random((7, 5))).astype(np.float32)
-    I = fr.image.astype(np.float64)
-    ob = oracle.background(I, p, maps=True)
-    M = I - ob.B
-    F = oracle.filter_image(M, K)
-    o = oracle.peaks(I, M, F, ob.R, p.thresh, sep, cw, p.sat_level)
-    ph = P.Photometry([_dev(fr.image)], p, K, capacity=8192, precision=prec)
-    ph.set_grids(0, ob.back, ob.rms)
-    ph.background(grid_given=True)
-    ph.peaks(sep, cw)
-    r = ph.results(0)
+def _cmp_peak_catalogues(r, o, M, F, R, thresh, sep):
+    """GPU peaks against the oracle's: the two sets differ only at pixels
+    whose decisions are ambiguous in FP32 (threshold or window maximum), and
+    every common peak agrees field by field."""
     assert r["status"] == 0 and r["comp_status"][0] == 0
-    amb = peak_ambiguous(F, ob.R, p.thresh, sep).ravel()
+    amb = peak_ambiguous(F, R, thresh, sep).ravel()
     g_set, o_set = set(r["cat"]["pmin"].tolist()), set(o["pmin"].tolist())
     diff = sorted(g_set ^ o_set)
     _say("peaks gpu", len(g_set), "oracle", len(o_set), "differ", len(diff), "ambiguous px", int(amb.sum()))
@@ -510,6 +493,98 @@ def test_peaks_stage_isolated(P, case, prec):
     for k in ("x2", "y2", "xy"):
         assert np.all(np.abs(g[k][ig] - c[k]) <= TOL_MOM_ABS + 1e-6 * np.abs(c[k])), k
     assert np.all(np.abs(g["peak"][ig] - c["peak"]) <= 2e-6 * np.abs(c["peak"]) + 1e-6)
+    return len(common)
+
+
+PSF_CASES = [
+    # W, H, dtype, seed, thresh, sep, cwin, nmodes, kernel side, coefficient-map bin
+    (333, 257, "f32", 91, 3.0, 3, 3, 5, 9, 1),
+    (300, 211, "u16", 92, 5.0, 3, 3, 5, 9, 16),
+    (257, 190, "f32", 93, 2.0, 2, 4, 8, 15, 7),
+    (200, 150, "f32", 94, 2.0, 4, 2, 0, 7, 1),
+    (190, 130, "f32", 95, 2.5, 3, 3, 3, (7, 5), 1),   # a non-square kernel
+    (400, 300, "f32", 96, 1.0, 2, 2, 5, 13, 1),       # low threshold: hundreds of noise peaks
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("case", PSF_CASES, ids=lambda c: f"{c[0]}x{c[1]}-{c[2]}-K{c[7]}-k{c[8]}-bin{c[9]}")
+def test_peaks_psf_stage_isolated(P, case, prec):
+    """gp_peaks_psf against the oracle's varying filter and peaks on the
+    oracle's background grids, with synthetic eigen-PSF models and smooth
+    coefficient maps (full-frame and binned)."""
+    from synth import coef_maps, psf_model
+    W, H, dt, seed, t, sep, cw, K, side, b = case
+    _say("psf peak case", case, prec)
+    fr = make_frame("c1", seed=seed, W=W, H=H, dtype=dt, nstars=max(8, W * H // 2500))
+    p = f32_params(fr.params)
+    p.mesh_w = p.mesh_h = 64
+    p.thresh = t
+    p.sat_level = 60000.0
+    if isinstance(side, tuple):
+        kw, kh = side
+        ks = psf_model(K, max(kw, kh), 3.0, seed)[:, (max(kw, kh) - kh) // 2:(max(kw, kh) + kh) // 2,
+                                                   (max(kw, kh) - kw) // 2:(max(kw, kh) + kw) // 2].copy()
+    else:
+        ks = psf_model(K, side, 3.0, seed)
+    cm = coef_maps(K, W, H, b, seed + 1)
+    I = fr.image.astype(np.float64)
+    ob = oracle.background(I, p, maps=True)
+    M = I - ob.B
+    S = oracle.filter_varying(M, ks.astype(np.float64), cm.astype(np.float64) if K else None, bin=b)
+    o = oracle.peaks(I, M, S, ob.R, p.thresh, sep, cw, p.sat_level)
+    ph = P.Photometry([_dev(fr.image)], p, p.kernel(), capacity=8192, precision=prec)
+    ph.set_grids(0, ob.back, ob.rms)
+    ph.background(grid_given=True)
+    ph.peaks_psf(sep, cw, ks, [torch.from_numpy(cm).cuda()] if K else None, bin=b)
+    n = _cmp_peak_catalogues(ph.results(0), o, M, S, ob.R, p.thresh, sep)
+    _say("common peaks", n)
+    ph.close()
+
+
+def test_peaks_psf_without_modes_equals_gp_peaks(P):
+    """With no eigenmodes and P0 of unit sum, gp_peaks_psf finds what gp_peaks
+    finds with P0 as its kernel (up to FP32 ties at the threshold)."""
+    from synth import psf_model
+    fr = make_frame("c1", seed=97, W=300, H=220, nstars=30)
+    p = f32_params(fr.params)
+    ks = psf_model(0, 9, 3.0, 1)
+    a = P.Photometry([_dev(fr.image)], p, ks[0], capacity=4096)
+    a.background()
+    a.peaks(3, 3)
+    ra = a.results(0)
+    a.peaks_psf(3, 3, ks)
+    rb = a.results(0)
+    _say("plain", ra["n_obj"], ra["status"], ra["cat"]["pmin"][:6], ra["cat"]["peak"][:6])
+    _say("psf", rb["n_obj"], rb["status"], rb["cat"]["pmin"][:6], rb["cat"]["peak"][:6])
+    assert ra["n_obj"] > 5
+    common = np.intersect1d(ra["cat"]["pmin"], rb["cat"]["pmin"])
+    assert len(common) >= ra["n_obj"] - 2 and len(common) >= rb["n_obj"] - 2
+    a.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("case", PEAK_CASES, ids=lambda c: f"{c[1]}x{c[2]}-{c[3]}-t{c[5]}-s{c[6]}-c{c[7]}-{c[8] or 'gauss'}")
+def test_peaks_stage_isolated(P, case, prec):
+    name, W, H, dt, seed, t, sep, cw, kk = case
+    _say("peak case", case, prec)
+    fr = make_frame(name, seed=seed, W=W, H=H, dtype=dt, nstars=max(8, W * H // 2500))
+    p = f32_params(fr.params)
+    p.mesh_w = p.mesh_h = 64
+    p.thresh = t
+    p.sat_level = 60000.0
+    K = p.kernel() if kk is None else (0.3 + np.random.default_rng(seed).random((7, 5))).astype(np.float32)
+    I = fr.image.astype(np.float64)
+    ob = oracle.background(I, p, maps=True)
+    M = I - ob.B
+    F = oracle.filter_image(M, K)
+    o = oracle.peaks(I, M, F, ob.R, p.thresh, sep, cw, p.sat_level)
+    ph = P.Photometry([_dev(fr.image)], p, K, capacity=8192, precision=prec)
+    ph.set_grids(0, ob.back, ob.rms)
+    ph.background(grid_given=True)
+    ph.peaks(sep, cw)
+    r = ph.results(0)
+    _cmp_peak_catalogues(r, o, M, F, ob.R, p.thresh, sep)
     # the apertures run on the peak catalogue
     ph.aperture()
     ra = ph.results(0)
