@@ -67,7 +67,7 @@ struct CatOut {
 };
 
 // spatially varying matched filter: a reference kernel and up to kMaxModes
-// eigenmodes (taps as given, [row][column][mode] with P0 as mode 0, modes
+// eigenmodes (taps as given, [column][row][mode] with P0 as mode 0, modes
 // padded to kMaxModes + 1) and, per frame,
 // the coefficient maps (map k of frame f at pf[f].data + k * plane; pixel
 // (x, y) reads [(y / bin) * pitch + x / bin])

@@ -1252,10 +1252,9 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
     const bool sepk = !VARY && pa->separable != 0;
     if (VARY) {
         // S = sum_m c_m (M corr e_m) (c_0 = 1) over the tile plus sep, into
-        // nus.  A work item is kVaryRows output rows of one column: per tap
-        // the item reads its kVaryRows M values once and updates
+        // nus.  A work item is kVaryRows output rows of one column and keeps
         // (K + 1) x kVaryRows accumulators; the taps come through the scalar
-        // cache (uniform addresses, [row][column][mode] layout)
+        // cache (uniform addresses, [column][row][mode] layout)
         typedef __attribute__((address_space(4))) const Real ctap_t;
         const ctap_t* tp = (const ctap_t*)(kDbl ? (const void*)pk.psf->tapsd : (const void*)pk.psf->taps);
         const int nmodes = pk.psf->nmodes;
@@ -1266,44 +1265,56 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
             const int mc = i - sep + L.hmx - rx;           // first M column read
             const int mr0 = j0 - sep + L.hmy - ry;         // first M row read
             constexpr int NA = VARY ? NM : 1;
+            // this item's coefficients, loaded first so that they arrive
+            // during the correlations (positions clamped into the frame; the
+            // values of outside positions are not used)
+            const PsfFrame pfr = pk.pf[f];
+            const int bin = pk.psf->bin;
+            const int gx = x0 - sep + i;
+            float cf[NA > 1 ? NA - 1 : 1][kVaryRows];
+#pragma unroll
+            for (int r = 0; r < kVaryRows; ++r) {
+                const int gxc = min(max(gx, 0), d.W - 1), gyc = min(max(y0 - sep + j0 + r, 0), d.H - 1);
+                const float* cp = pfr.data + (int64_t)(gyc / bin) * pfr.pitch + gxc / bin;
+#pragma unroll
+                for (int m = 1; m < NA; ++m) cf[m - 1][r] = (m <= nmodes) ? cp[(int64_t)(m - 1) * pfr.plane] : 0.0f;
+            }
             Real acc[NA][kVaryRows];
 #pragma unroll
             for (int m = 0; m < NA; ++m)
 #pragma unroll
                 for (int r = 0; r < kVaryRows; ++r) acc[m][r] = 0;
-            for (int a = 0; a < kh; ++a) {
-                int rowoff[kVaryRows];
+            // per tap column b: the M column strip the item's rows read for
+            // every tap row (kh + kVaryRows - 1 values) in registers, then
+            // all tap rows (unrolled; taps of one column contiguous)
+            constexpr int NC = kMaxK + kVaryRows - 1;
+            for (int b = 0; b < kw; ++b) {
+                Real col[NC];
 #pragma unroll
-                for (int r = 0; r < kVaryRows; ++r) rowoff[r] = min(mr0 + a + r, L.rmh - 1) * L.rmw + mc;
-                for (int b = 0; b < kw; ++b) {
-                    const ctap_t* tq = tp + (a * kw + b) * (kMaxModes + 1);
-                    Real t[NA];
+                for (int t = 0; t < NC; ++t)
+                    col[t] = (t < kh + kVaryRows - 1) ? ms[min(mr0 + t, L.rmh - 1) * L.rmw + mc + b] : (Real)0;
+                const ctap_t* tb = tp + b * kh * (kMaxModes + 1);
 #pragma unroll
-                    for (int m = 0; m < NA; ++m) t[m] = tq[m];
-                    Real mv[kVaryRows];
+                for (int a = 0; a < kMaxK; ++a) {
+                    if (a < kh) {
+                        Real t[NA];
 #pragma unroll
-                    for (int r = 0; r < kVaryRows; ++r) mv[r] = ms[rowoff[r] + b];
+                        for (int m = 0; m < NA; ++m) t[m] = tb[a * (kMaxModes + 1) + m];
 #pragma unroll
-                    for (int m = 0; m < NA; ++m)
+                        for (int m = 0; m < NA; ++m)
 #pragma unroll
-                        for (int r = 0; r < kVaryRows; ++r) acc[m][r] = fma(t[m], mv[r], acc[m][r]);
+                            for (int r = 0; r < kVaryRows; ++r) acc[m][r] = fma(t[m], col[a + r], acc[m][r]);
+                    }
                 }
             }
-            const PsfFrame pfr = pk.pf[f];
-            const int bin = pk.psf->bin;
-            const int gx = x0 - sep + i;
 #pragma unroll
             for (int r = 0; r < kVaryRows; ++r) {
-                const int j = j0 + r, gy = y0 - sep + j;
-                if (j >= fh) break;
+                const int j = j0 + r;
                 Real sv = acc[0][r];
-                if (gx >= 0 && gx < d.W && gy >= 0 && gy < d.H) {
-                    const float* cp = pfr.data + (int64_t)(gy / bin) * pfr.pitch + gx / bin;
 #pragma unroll
-                    for (int m = 1; m < NA; ++m)
-                        if (m <= nmodes) sv = fma((Real)cp[(int64_t)(m - 1) * pfr.plane], acc[m][r], sv);
-                }
-                nus[j * L.rf + i] = sv;
+                for (int m = 1; m < NA; ++m)
+                    if (m <= nmodes) sv = fma((Real)cf[m - 1][r], acc[m][r], sv);
+                if (j < fh) nus[j * L.rf + i] = sv;
             }
         }
         __syncthreads();

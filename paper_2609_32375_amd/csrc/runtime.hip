@@ -950,15 +950,17 @@ static gp_status peaks_run(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
             // values), then the frames' map descriptors
             pargs = (PsfArgs*)(W + P.o_psf);
             pframes = (PsfFrame*)(W + P.o_psf + sizeof(PsfArgs));
-            // taps as [row][column][mode], modes padded to kMaxModes + 1
+            // taps as [column][row][mode], modes padded to kMaxModes + 1
             const int nt = kw * kh * (kMaxModes + 1);
             std::vector<float> tf(nt, 0.0f);
             std::vector<double> td(nt, 0.0);
             for (int m = 0; m <= psf->nmodes; ++m)
-                for (int i = 0; i < kw * kh; ++i) {
-                    tf[i * (kMaxModes + 1) + m] = psf->kernels[m * kw * kh + i];
-                    td[i * (kMaxModes + 1) + m] = (double)psf->kernels[m * kw * kh + i];
-                }
+                for (int a = 0; a < kh; ++a)
+                    for (int b = 0; b < kw; ++b) {
+                        const float v = psf->kernels[(m * kh + a) * kw + b];
+                        tf[(b * kh + a) * (kMaxModes + 1) + m] = v;
+                        td[(b * kh + a) * (kMaxModes + 1) + m] = (double)v;
+                    }
             const int32_t hdr[4] = {psf->nmodes, psf->bin, kw, kh};
             launch_write_bytes(pargs, hdr, sizeof(hdr), s);
             launch_write_bytes(pargs->taps, tf.data(), tf.size() * 4, s);
