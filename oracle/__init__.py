@@ -72,10 +72,13 @@ def lib():
                                   C.c_double, C.c_double, C.c_int, dp, dp, dp, dp, up]
         L.or_filter_varying.argtypes = [dp, C.c_long, C.c_long, dp, C.c_int, C.c_int, C.c_int, dp, C.c_long,
                                         C.c_long, C.c_int, dp]
+        L.or_background_conv.argtypes = [dp, C.c_long, C.c_long, C.POINTER(C.c_uint8), C.c_double, dp, C.c_int, dp,
+                                         C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp,
+                                         C.POINTER(C.c_long)]
         L.or_growth_radii.argtypes = [C.c_double, C.c_int, ip, C.POINTER(C.c_int)]
         L.or_tophat_taps.argtypes = [C.c_int, dp]
         L.or_growth.argtypes = [dp, dp, C.c_long, C.c_long, dp, dp, C.c_long, ip, C.c_int, dp, dp, dp, up]
-        for f in ("or_filter_varying", "or_growth_radii", "or_tophat_taps", "or_growth", "or_mesh_one", "or_mesh_one_policy", "or_mesh_stats", "or_median_filter", "or_grid_eval", "or_grid_map",
+        for f in ("or_background_conv", "or_filter_varying", "or_growth_radii", "or_tophat_taps", "or_growth", "or_mesh_one", "or_mesh_one_policy", "or_mesh_stats", "or_median_filter", "or_grid_eval", "or_grid_map",
                   "or_filter", "or_threshold_label", "or_measure", "or_aperture", "or_peaks"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -208,6 +211,26 @@ def filter_image(M, K):
     F = np.zeros_like(Mm)
     _check(lib().or_filter(_p(Mm), W, H, _p(Kk), kw, kh, _p(F)), "filter")
     return F
+
+
+def background_conv(I, kx, ky, mask=None, sat=np.inf, gain=1.0, rn=0.0, dark=0.0, texp=0.0):
+    """Local background by convolution with reflected borders, invalid pixels
+    (mask != 0 or I >= sat) filled from their valid neighbours, and the noise
+    map of a dark-subtracted frame.  Returns (B, R, unfilled)."""
+    Ii = _f64(I)
+    H, W = Ii.shape
+    kx, ky = _f64(kx), _f64(ky)
+    B = np.zeros_like(Ii)
+    R = np.zeros_like(Ii)
+    mp = C.POINTER(C.c_uint8)()
+    if mask is not None:
+        m8 = np.ascontiguousarray(mask, dtype=np.uint8)
+        mp = _p(m8, C.c_uint8)
+    n = C.c_long(0)
+    _check(lib().or_background_conv(_p(Ii), W, H, mp, float(sat), _p(kx), kx.size, _p(ky), ky.size, float(gain),
+                                    float(rn), float(dark), float(texp), _p(B), _p(R), C.byref(n)),
+           "background_conv")
+    return B, R, n.value
 
 
 def filter_varying(M, kernels, coef=None, bin=1):

@@ -19,6 +19,9 @@
  *     the growth curve of every source over the integer radii from
  *     ceil(0.75 FWHM) to ceil(5 FWHM) is one top-hat correlation per radius
  *     read at the sources, with the variance map through the same kernel;
+ *   - the local background can instead be a convolution of the frame with
+ *     reflected borders, invalid pixels first filled from their valid
+ *     neighbours, with a noise map from the sky, read and dark variances;
  *   - the paper's own detection keeps the local maxima of the matched-filter
  *     significance above the threshold, with first-moment centroids; with a
  *     spatially varying PSF (reference plus eigenmodes with coefficient maps)
@@ -958,5 +961,84 @@ int or_growth(const double* M, const double* V, long W, long H, const double* xs
         }
     }
     free(taps);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Local background by convolution (Image Preprocessing and Background      */
+/* Estimation subsection)                                                   */
+/* ------------------------------------------------------------------------ */
+/*
+ * B = K corr I' with K = ky kx^T / (sum ky sum kx) (a separable smoothing
+ * kernel, normalised to unit sum) and reflected borders as in or_filter,
+ * where I' is the frame with its invalid pixels filled from their valid
+ * neighbours: an invalid pixel p takes
+ *   N(p) = sum_q K(q - p) v(q) I(q) / sum_q K(q - p) v(q),
+ * the kernel-weighted mean of the valid pixels around it (v = 1 valid, 0
+ * invalid; the same reflected borders).  A pixel is invalid when mask[p] != 0
+ * (mask may be NULL) or I(p) >= sat.  An invalid pixel with no valid pixel
+ * under the kernel is filled with 0 and counted in *unfilled.
+ * Noise map, for a dark-subtracted frame in ADU with gain g (e-/ADU), read
+ * noise rn (e-), dark current dark (e-/s) and exposure texp (s): the sky,
+ * read and dark variances add in electrons,
+ *   R^2 = (g max(B, 0) + rn^2 + dark texp) / g^2.
+ * kx: lx taps, ky: ly taps, both odd.
+ */
+int or_background_conv(const double* I, long W, long H, const uint8_t* mask, double sat, const double* kx, int lx,
+                       const double* ky, int ly, double gain, double rn, double dark, double texp, double* B,
+                       double* R, long* unfilled) {
+    if (!I || !kx || !ky || !B || W <= 0 || H <= 0 || lx <= 0 || ly <= 0 || !(lx % 2) || !(ly % 2) ||
+        !(gain > 0.0))
+        return OR_EINVAL;
+    double sx = 0.0, sy = 0.0;
+    for (int b = 0; b < lx; ++b) sx += kx[b];
+    for (int a = 0; a < ly; ++a) sy += ky[a];
+    if (sx == 0.0 || sy == 0.0) return OR_EINVAL;
+    const int hx = lx / 2, hy = ly / 2;
+    double* F = (double*)malloc(sizeof(double) * (size_t)W * (size_t)H);
+    if (!F) return OR_EINVAL;
+    long nun = 0;
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) {
+            const long p = y * W + x;
+            const int valid = !(mask && mask[p]) && I[p] < sat;
+            if (valid) {
+                F[p] = I[p];
+                continue;
+            }
+            double num = 0.0, den = 0.0;
+            for (int a = 0; a < ly; ++a) {
+                const long yy = reflect(y + a - hy, H);
+                for (int b = 0; b < lx; ++b) {
+                    const long q = yy * W + reflect(x + b - hx, W);
+                    if ((mask && mask[q]) || !(I[q] < sat)) continue;
+                    const double k = (ky[a] / sy) * (kx[b] / sx);
+                    num += k * I[q];
+                    den += k;
+                }
+            }
+            if (den != 0.0) {
+                F[p] = num / den;
+            } else {
+                F[p] = 0.0;
+                ++nun;
+            }
+        }
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) {
+            double acc = 0.0;
+            for (int a = 0; a < ly; ++a) {
+                const long yy = reflect(y + a - hy, H);
+                for (int b = 0; b < lx; ++b)
+                    acc += (ky[a] / sy) * (kx[b] / sx) * F[yy * W + reflect(x + b - hx, W)];
+            }
+            B[y * W + x] = acc;
+            if (R) {
+                const double sky = acc > 0.0 ? acc : 0.0;
+                R[y * W + x] = sqrt((gain * sky + rn * rn + dark * texp) / (gain * gain));
+            }
+        }
+    free(F);
+    if (unfilled) *unfilled = nun;
     return OR_OK;
 }

@@ -888,3 +888,99 @@ def test_varying_filter_binned_maps_equal_expanded_maps():
     small = rng.normal(0, 1, (2, -(-H // b), -(-W // b)))
     full = np.repeat(np.repeat(small, b, axis=1), b, axis=2)[:, :H, :W]
     np.testing.assert_array_equal(oracle.filter_varying(M, ks, small, bin=b), oracle.filter_varying(M, ks, full))
+
+
+# ----------------------------------------------------------------------------
+# local background by convolution
+# ----------------------------------------------------------------------------
+def _k2(kx, ky):
+    kx = np.asarray(kx, float) / np.sum(kx)
+    ky = np.asarray(ky, float) / np.sum(ky)
+    return np.outer(ky, kx)
+
+
+@pytest.mark.parametrize("lx,ly", [(1, 1), (9, 5), (31, 31), (65, 129)])
+def test_background_conv_constant_image(lx, ly):
+    I = np.full((37, 53), 812.25)
+    B, R, n = oracle.background_conv(I, np.hanning(lx + 2)[1:-1], np.ones(ly), gain=1.5)
+    np.testing.assert_allclose(B, 812.25, rtol=1e-14)
+    assert n == 0
+
+
+def test_background_conv_delta_kernel_is_identity():
+    rng = np.random.default_rng(21)
+    I = rng.normal(100, 10, (20, 30))
+    mask = np.zeros(I.shape, np.uint8)
+    mask[5, 7] = mask[11, 2] = 1
+    B, _, n = oracle.background_conv(I, [2.0], [3.0], mask=mask)
+    ok = mask == 0
+    np.testing.assert_array_equal(B[ok], I[ok])
+    # an invalid pixel with only itself under the kernel cannot be filled
+    assert n == 2 and B[5, 7] == 0.0 and B[11, 2] == 0.0
+
+
+def test_background_conv_equals_scipy_separable_reflect():
+    rng = np.random.default_rng(22)
+    H, W = 41, 67
+    I = rng.normal(500, 20, (H, W)) + 3 * np.arange(W)[None, :]
+    kx = rng.uniform(0.2, 1.0, 11)      # asymmetric: a flipped kernel would differ
+    ky = rng.uniform(0.2, 1.0, 7)
+    B, _, n = oracle.background_conv(I, kx, ky)
+    t = ndimage.correlate1d(I, kx / kx.sum(), axis=1, mode="reflect")
+    t = ndimage.correlate1d(t, ky / ky.sum(), axis=0, mode="reflect")
+    np.testing.assert_allclose(B, t, rtol=1e-13)
+    assert n == 0
+
+
+def test_background_conv_fill_equals_normalised_convolution():
+    rng = np.random.default_rng(23)
+    H, W = 45, 60
+    I = rng.normal(300, 15, (H, W))
+    I[10:14, 20:26] = 70000.0              # a saturated blob (invalid through sat)
+    mask = np.zeros((H, W), np.uint8)
+    mask[30:37, 40:45] = 1                 # a masked compact source
+    mask[0, 0] = 1
+    kx = rng.uniform(0.1, 1.0, 9)
+    ky = rng.uniform(0.1, 1.0, 13)
+    B, _, n = oracle.background_conv(I, kx, ky, mask=mask, sat=65535.0)
+    K = _k2(kx, ky)
+    v = ((mask == 0) & (I < 65535.0)).astype(float)
+    num = ndimage.correlate(v * I, K, mode="reflect")
+    den = ndimage.correlate(v, K, mode="reflect")
+    Ip = np.where(v > 0, I, num / den)
+    np.testing.assert_allclose(B, ndimage.correlate(Ip, K, mode="reflect"), rtol=1e-12)
+    assert n == 0
+
+
+def test_background_conv_counts_unfillable_pixels():
+    H, W = 40, 40
+    I = np.full((H, W), 10.0)
+    mask = np.zeros((H, W), np.uint8)
+    mask[5:30, 5:30] = 1                    # a hole far wider than the kernel
+    B, _, n = oracle.background_conv(I, np.ones(5), np.ones(3), mask=mask)
+    v = (mask == 0).astype(float)
+    reach = ndimage.correlate(v, np.ones((3, 5)), mode="reflect")
+    want = int(np.sum((mask != 0) & (reach == 0)))
+    assert n == want > 0
+
+
+def test_noise_map_adds_sky_dark_and_read_variances():
+    """Monte Carlo: a dark-subtracted pixel of sky s (ADU) with gain g, read
+    noise rn and dark current d over texp has variance (g s + rn^2 + d texp) / g^2."""
+    rng = np.random.default_rng(24)
+    g, rn, d, texp, s = 1.7, 6.5, 0.8, 30.0, 240.0
+    n = 400_000
+    e = rng.poisson(g * s, n) + rng.poisson(d * texp, n) - d * texp + rng.normal(0, rn, n)
+    adu = e / g
+    _, R, _ = oracle.background_conv(np.full((8, 8), s), [1.0], [1.0], gain=g, rn=rn, dark=d, texp=texp)
+    assert abs(np.var(adu) / R[0, 0] ** 2 - 1.0) < 0.01
+    assert abs(np.mean(adu) - s) < 0.1
+
+
+def test_background_conv_keeps_planes_inside():
+    """A symmetric unit-sum kernel reproduces a plane away from the borders."""
+    H, W = 50, 70
+    yy, xx = np.mgrid[0:H, 0:W]
+    I = 100.0 + 0.5 * xx - 0.25 * yy
+    B, _, _ = oracle.background_conv(I, np.hanning(13)[1:-1], np.hanning(9)[1:-1])
+    np.testing.assert_allclose(B[6:-6, 8:-8], I[6:-6, 8:-8], rtol=1e-13)
