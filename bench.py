@@ -336,6 +336,8 @@ def main():
             torch.cuda.empty_cache()
         out["forms"]["peaks"] = form_peaks(torch, a)
         torch.cuda.empty_cache()
+        out["forms"]["background_conv"] = form_background_conv(torch, a)
+        torch.cuda.empty_cache()
         out["forms"]["served"] = form_served(torch, a)
         torch.cuda.empty_cache()
     if not a.no_cpu:
@@ -491,6 +493,32 @@ def form_peaks(torch, a):
             "peaks_psf_tflops": round(2 * (K + 1) * 13 * 13 * sum(npx) / (kern.get("peaks_psf", 1e9) * 1e-3) / 1e12,
                                       1),
             "growth_sources_per_s": round(n / (kern.get("growth", 1e9) * 1e-3), 1)}
+
+
+def form_background_conv(torch, a):
+    """The paper's own background on the batch: gp_background_conv with a
+    separable Gaussian of FWHM 32 px (65 taps per axis), saturated pixels
+    (>= 65535) filled from their valid neighbours, and the noise map of a
+    gain 1.5 e-/ADU, 5 e- read-noise frame; one call over the 64 frames."""
+    import numpy as np
+    from paper_2609_32375_amd.pipeline import ConvBackground
+    frames = batch_frames(torch)
+    npx = sum(f.shape[0] * f.shape[1] for f in frames)
+    t = np.arange(-32, 33, dtype=np.float64)
+    k = np.exp(-0.5 * (t / (32.0 / 2.3548)) ** 2).astype(np.float32)
+    cb = ConvBackground(frames, k, k, 1.5, 5.0, 0.0, 0.0, sat_level=65535.0)
+    for _ in range(2):
+        cb.run()
+    torch.cuda.synchronize()
+    ms = event_time(torch, cb.run, max(3, a.steps // 4))
+    unf = int(cb.unfilled.sum().item())
+    cb.close()
+    del frames, cb
+    log(f"background by convolution: {ms:.3f} ms per batch")
+    return {"workload": "the 64-frame uint16 batch; background by convolution (65 x 65 separable Gaussian, "
+                        "saturated pixels filled), noise map", "ms": round(ms, 3),
+            "mp_s": round(npx / 1e6 / ms * 1e3, 1), "unfilled": unf,
+            "fp64_tflops": round(2 * 2 * 2 * 65 * npx / (ms * 1e-3) / 1e12, 2)}
 
 
 def form_served(torch, a):

@@ -25,6 +25,9 @@
  *                  the same with the spatially varying PSF's filter.
  *   gp_growth      growth curves: top-hat sums of M and of R^2 at every source
  *                  for the integer radii ceil(0.75 FWHM) .. ceil(5 FWHM).
+ *   gp_background_conv  the paper's own background: a convolution with
+ *                  reflected borders, invalid pixels filled from their valid
+ *                  neighbours, and a sky/read/dark noise map (full-frame maps).
  *
  * All of them work on a batch of nframes >= 1 frames of any sizes at once; the
  * plain per-frame use is nframes = 1.
@@ -226,6 +229,41 @@ gp_status gp_background_layout(const gp_frame* frames, int32_t nframes, const gp
 gp_status gp_background_map(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
                             const gp_bkg_params* bp, const void* bkg, int32_t index,
                             int32_t precision, double* back_map, double* rms_map, void* stream);
+
+/* Local background by convolution (Image Preprocessing and Background
+ * Estimation subsection), an alternative to the mesh background:
+ *   B = K corr I'  with K = ky kx^T / (sum ky sum kx) and half-sample reflected
+ *   borders, where I' is the frame with each invalid pixel (mask != 0, or a
+ *   raw value >= sat_level) replaced by the kernel-weighted mean of the valid
+ *   pixels around it, (K corr vI) / (K corr v) with v = 1 on valid pixels;
+ *   R^2 = (gain max(B, 0) + read_noise^2 + dark_current exptime) / gain^2,
+ *   the sky, read-out and dark-current variances of a dark-subtracted frame
+ *   in ADU (gain in e-/ADU, read_noise in e-, dark_current in e-/s, exptime
+ *   in s).
+ * kx, ky: HOST pointers to lx, ly taps (odd, 1..129, non-zero sums).
+ * masks: HOST array of nframes DEVICE pointers to uint8 masks with the
+ * frame's pitch (NULL array or entries: no mask).  back, rms: HOST arrays of
+ * nframes DEVICE pointers to width x height maps (row-major, pitch = width) of
+ * float (GP_PREC_F32) or double (GP_PREC_F64).  unfilled: DEVICE int64
+ * [nframes], the invalid pixels with no valid pixel under the kernel (filled
+ * with 0).  Sums accumulate in FP64; intermediates are stored in the working
+ * precision.  Workspace: gp_background_conv_ws bytes (the frames share it, so
+ * they are processed one after the other on the stream). */
+typedef struct gp_conv_params {
+    const float* kx;
+    int32_t lx;
+    const float* ky;
+    int32_t ly;
+    float sat_level;
+    float gain, read_noise, dark_current, exptime;
+    int32_t precision;     /* gp_precision */
+} gp_conv_params;
+gp_status gp_background_conv_ws(const gp_frame* frames, int32_t nframes, const gp_conv_params* cp,
+                                size_t* bytes);
+gp_status gp_background_conv(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                             const uint8_t* const* masks, const gp_conv_params* cp,
+                             void* const* back, void* const* rms, int64_t* unfilled, void* ws,
+                             size_t ws_bytes, void* stream);
 
 /* Workspace bytes for running gp_background, gp_detect and gp_aperture on this
  * batch with catalogues of cat_capacity rows per frame and room for

@@ -72,6 +72,12 @@ class gp_psf_model(C.Structure):
                 ("bin", C.c_int32), ("maps", C.POINTER(gp_coef_maps))]
 
 
+class gp_conv_params(C.Structure):
+    _fields_ = [("kx", C.POINTER(C.c_float)), ("lx", C.c_int32), ("ky", C.POINTER(C.c_float)), ("ly", C.c_int32),
+                ("sat_level", C.c_float), ("gain", C.c_float), ("read_noise", C.c_float),
+                ("dark_current", C.c_float), ("exptime", C.c_float), ("precision", C.c_int32)]
+
+
 class gp_growth_params(C.Structure):
     _fields_ = [("radii", C.POINTER(C.c_int32)), ("nr", C.c_int32), ("precision", C.c_int32)]
 
@@ -86,7 +92,8 @@ class gp_phot(C.Structure):
 
 EXPORTS = ("gp_ctx_create", "gp_ctx_destroy", "gp_last_error", "gp_version", "gp_background_layout",
            "gp_workspace_size", "gp_background", "gp_background_map", "gp_detect", "gp_detect_noalloc",
-           "gp_peaks", "gp_peaks_psf", "gp_aperture", "gp_growth_radii", "gp_growth",
+           "gp_peaks", "gp_peaks_psf", "gp_aperture", "gp_growth_radii", "gp_growth", "gp_background_conv_ws",
+           "gp_background_conv",
            "gp_profile_enable",
            "gp_profile_read", "gp_profile_reset", "gp_ctx_set_tuning", "gp_graph_create", "gp_graph_launch",
            "gp_graph_rebind", "gp_graph_destroy")
@@ -135,6 +142,9 @@ def load(path: str = LIB_PATH):
     L.gp_peaks_psf.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp,
                                C.POINTER(gp_det_params), C.POINTER(gp_peak_params), C.POINTER(gp_psf_model),
                                C.POINTER(gp_catalog), vp, vp, C.c_size_t, vp]
+    L.gp_background_conv_ws.argtypes = [C.POINTER(gp_frame), i32, C.POINTER(gp_conv_params), C.POINTER(C.c_size_t)]
+    L.gp_background_conv.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(vp), C.POINTER(gp_conv_params),
+                                     C.POINTER(vp), C.POINTER(vp), vp, vp, C.c_size_t, vp]
     L.gp_growth_radii.argtypes = [C.c_double, i32, C.POINTER(i32), C.POINTER(i32)]
     L.gp_growth.argtypes = [vp, C.POINTER(gp_frame), i32, C.POINTER(gp_bkg_params), vp, C.POINTER(gp_catalog),
                             C.POINTER(gp_growth_params), C.POINTER(gp_growth_out), vp, C.c_size_t, vp]
@@ -151,7 +161,7 @@ def load(path: str = LIB_PATH):
     L.gp_profile_reset.argtypes = [vp]
     for f in ("gp_ctx_create", "gp_background_layout", "gp_workspace_size", "gp_background",
               "gp_background_map", "gp_detect", "gp_detect_noalloc", "gp_peaks",
-              "gp_aperture", "gp_peaks_psf", "gp_growth_radii", "gp_growth", "gp_profile_enable", "gp_profile_read", "gp_profile_reset", "gp_graph_create",
+              "gp_aperture", "gp_peaks_psf", "gp_background_conv_ws", "gp_background_conv", "gp_growth_radii", "gp_growth", "gp_profile_enable", "gp_profile_read", "gp_profile_reset", "gp_graph_create",
               "gp_graph_launch", "gp_graph_rebind"):
         getattr(L, f).restype = C.c_int
     _lib = L
@@ -248,6 +258,22 @@ def gp_peaks_psf(ctx, frames, bp, bkg_ptr, dp, pp, psf, cat, comp_status_ptr, ws
     arr = (gp_frame * n)(*frames)
     check(load().gp_peaks_psf(ctx, arr, n, C.byref(bp), bkg_ptr, C.byref(dp), C.byref(pp), C.byref(psf),
                               C.byref(cat), comp_status_ptr, ws_ptr, ws_bytes, stream))
+
+
+def gp_background_conv_ws(frames, cp):
+    n = len(frames)
+    arr = (gp_frame * n)(*frames)
+    out = C.c_size_t()
+    check(load().gp_background_conv_ws(arr, n, C.byref(cp), C.byref(out)))
+    return out.value
+
+
+def gp_background_conv(ctx, frames, mask_ptrs, cp, back_ptrs, rms_ptrs, unfilled_ptr, ws_ptr, ws_bytes, stream):
+    n = len(frames)
+    arr = (gp_frame * n)(*frames)
+    masks = (C.c_void_p * n)(*mask_ptrs) if mask_ptrs is not None else None
+    check(load().gp_background_conv(ctx, arr, n, masks, C.byref(cp), (C.c_void_p * n)(*back_ptrs),
+                                    (C.c_void_p * n)(*rms_ptrs), unfilled_ptr, ws_ptr, ws_bytes, stream))
 
 
 def gp_growth_radii(fwhm):

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgpphot.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["k_background.hip", "k_detect.hip", "k_aperture.hip", "k_growth.hip", "runtime.hip"]
+SOURCES = ["k_background.hip", "k_detect.hip", "k_aperture.hip", "k_growth.hip", "k_bkgconv.hip", "runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",

@@ -116,6 +116,15 @@ struct GrowOut {
     uint32_t* flags;
 };
 
+// local background by convolution: raw separable taps (normalised on the
+// device) and the noise-model constants
+constexpr int kMaxConvTaps = 129;
+struct CvArgs {
+    int32_t lx, ly;
+    float gain, read_noise, dark, exptime;
+    float kx[kMaxConvTaps], ky[kMaxConvTaps];
+};
+
 // one: the descriptor of a one-frame call, passed with the launch (the kernel
 // stores it in the table for the launches that follow), or null
 void launch_mesh_stats(FrameDesc* desc, const FrameDesc* one, int nframes, int total_meshes, int max_area, BkgArgs a,
@@ -146,6 +155,8 @@ void launch_growth_table(const GrowArgs& a, const GrowTab& t, hipStream_t s);
 hipError_t launch_growth(const FrameDesc* desc, const FrameDesc* one, const GrowArgs& a, const GrowTab& t,
                          const GrowOut& g, int blocks, int waves, bool f64, hipStream_t s);
 size_t growth_lds_bytes(int nfull, int ncut, int side, int nixmax, int want_var, bool f64, int waves);
+hipError_t launch_conv_frame(const FrameDesc& d, const uint8_t* mask, float sat, const CvArgs& a, void* hA, void* hC,
+                             void* G, void* back, void* rms, int* flag, int64_t* unfilled, bool f64, hipStream_t s);
 void launch_bkg_map(const FrameDesc& d, double* bmap, double* rmap, bool f64, hipStream_t s);
 void launch_write_desc(const DescChunk& c, FrameDesc* table, hipStream_t s);
 void launch_det_setup(const DescChunk& c, FrameDesc* table, const DetArgsIn& in, DetArgs* out, uint32_t* counters,

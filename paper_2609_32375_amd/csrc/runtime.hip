@@ -1195,6 +1195,102 @@ extern "C" gp_status gp_growth(gp_ctx* ctx, const gp_frame* frames, int32_t nfra
     return GP_OK;
 }
 
+namespace {
+gp_status check_conv(const gp_frame* frames, int32_t nframes, const gp_conv_params* cp) {
+    gp_status st;
+    if ((st = check_frames(frames, nframes)) != GP_OK) return st;
+    if (!cp) return fail(GP_ERR_INVALID_ARG, "convolution parameters are NULL");
+    if (!cp->kx || !cp->ky) return fail(GP_ERR_INVALID_ARG, "convolution taps are NULL");
+    if (cp->lx < 1 || cp->ly < 1 || cp->lx > kMaxConvTaps || cp->ly > kMaxConvTaps || !(cp->lx & 1) || !(cp->ly & 1))
+        return fail(GP_ERR_INVALID_ARG, "tap counts must be odd and at most %d (got %d, %d)", kMaxConvTaps, cp->lx,
+                    cp->ly);
+    double sx = 0.0, sy = 0.0;
+    for (int i = 0; i < cp->lx; ++i) {
+        if (!std::isfinite(cp->kx[i])) return fail(GP_ERR_INVALID_ARG, "kx has a non-finite tap");
+        sx += cp->kx[i];
+    }
+    for (int i = 0; i < cp->ly; ++i) {
+        if (!std::isfinite(cp->ky[i])) return fail(GP_ERR_INVALID_ARG, "ky has a non-finite tap");
+        sy += cp->ky[i];
+    }
+    if (sx == 0.0 || sy == 0.0) return fail(GP_ERR_INVALID_ARG, "kernel taps sum to zero");
+    if (!(cp->gain > 0.f) || !std::isfinite(cp->gain)) return fail(GP_ERR_INVALID_ARG, "gain must be positive");
+    if (!(cp->read_noise >= 0.f) || !(cp->dark_current >= 0.f) || !(cp->exptime >= 0.f) ||
+        !std::isfinite(cp->read_noise) || !std::isfinite(cp->dark_current) || !std::isfinite(cp->exptime))
+        return fail(GP_ERR_INVALID_ARG, "read_noise, dark_current and exptime must be finite and >= 0");
+    if (std::isnan(cp->sat_level)) return fail(GP_ERR_INVALID_ARG, "sat_level is NaN");
+    if (cp->precision != GP_PREC_F32 && cp->precision != GP_PREC_F64)
+        return fail(GP_ERR_INVALID_ARG, "unknown precision %d", cp->precision);
+    return GP_OK;
+}
+
+size_t conv_ws_bytes(const gp_frame* frames, int32_t nframes, const gp_conv_params* cp) {
+    int64_t mx = 1;
+    for (int f = 0; f < nframes; ++f) mx = std::max<int64_t>(mx, (int64_t)frames[f].width * frames[f].height);
+    const size_t real = cp->precision == GP_PREC_F64 ? 8 : 4;
+    return 256 + 3 * align256(real * (size_t)mx);
+}
+}  // namespace
+
+extern "C" gp_status gp_background_conv_ws(const gp_frame* frames, int32_t nframes, const gp_conv_params* cp,
+                                           size_t* bytes) {
+    gp_status st;
+    if ((st = check_conv(frames, nframes, cp)) != GP_OK) return st;
+    if (!bytes) return fail(GP_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = conv_ws_bytes(frames, nframes, cp);
+    return GP_OK;
+}
+
+extern "C" gp_status gp_background_conv(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
+                                        const uint8_t* const* masks, const gp_conv_params* cp, void* const* back,
+                                        void* const* rms, int64_t* unfilled, void* ws, size_t ws_bytes,
+                                        void* stream) {
+    if (!ctx) return fail(GP_ERR_INVALID_ARG, "context is NULL");
+    gp_status st;
+    if ((st = check_conv(frames, nframes, cp)) != GP_OK) return st;
+    if (!back || !rms) return fail(GP_ERR_INVALID_ARG, "back/rms arrays are NULL");
+    for (int f = 0; f < nframes; ++f)
+        if (!back[f] || !rms[f]) return fail(GP_ERR_INVALID_ARG, "back/rms of frame %d is NULL", f);
+    if (!unfilled) return fail(GP_ERR_INVALID_ARG, "unfilled is NULL");
+    if (!ws) return fail(GP_ERR_INVALID_ARG, "workspace is NULL");
+    const size_t need = conv_ws_bytes(frames, nframes, cp);
+    if (ws_bytes < need)
+        return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    const bool f64 = cp->precision == GP_PREC_F64;
+    const size_t real = f64 ? 8 : 4;
+    int64_t mx = 1;
+    for (int f = 0; f < nframes; ++f) mx = std::max<int64_t>(mx, (int64_t)frames[f].width * frames[f].height);
+    char* W = (char*)ws;
+    int* flag = (int*)W;
+    void* hA = W + 256;
+    void* hC = W + 256 + align256(real * (size_t)mx);
+    void* G = W + 256 + 2 * align256(real * (size_t)mx);
+    CvArgs a{};
+    a.lx = cp->lx;
+    a.ly = cp->ly;
+    a.gain = cp->gain;
+    a.read_noise = cp->read_noise;
+    a.dark = cp->dark_current;
+    a.exptime = cp->exptime;
+    for (int i = 0; i < cp->lx; ++i) a.kx[i] = cp->kx[i];
+    for (int i = 0; i < cp->ly; ++i) a.ky[i] = cp->ky[i];
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    ProfScope ps(ctx, s, "background_conv");
+    for (int f = 0; f < nframes; ++f) {
+        FrameDesc d{};
+        d.data = frames[f].data;
+        d.pitch = frames[f].pitch;
+        d.W = frames[f].width;
+        d.H = frames[f].height;
+        d.dtype = frames[f].dtype;
+        const hipError_t e = launch_conv_frame(d, masks ? masks[f] : nullptr, cp->sat_level, a, hA, hC, G, back[f],
+                                               rms[f], flag, unfilled + f, f64, s);
+        if (e != hipSuccess) return fail(GP_ERR_HIP, "background convolution: %s", hipGetErrorString(e));
+    }
+    return GP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Captured batches: the three calls over one batch recorded once into a HIP
 // graph (on a private stream) and replayed with one launch.  The parameters

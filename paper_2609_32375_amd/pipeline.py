@@ -355,3 +355,53 @@ def growth_radii(fwhm: float) -> List[int]:
     """Integer radii ceil(0.75 fwhm) .. ceil(5 fwhm) of the growth curves (the
     library's rule)."""
     return L.gp_growth_radii(fwhm)
+
+
+class ConvBackground:
+    """The paper's own background for a batch of frames: a convolution with
+    reflected borders (separable taps kx, ky), invalid pixels (mask or
+    >= sat_level) filled from their valid neighbours, and the noise map of a
+    dark-subtracted frame from gain, read noise and dark current.  run()
+    fills self.back / self.rms (one (H, W) tensor per frame, float32 or
+    float64 by precision) and self.unfilled (int64 per frame)."""
+
+    def __init__(self, frames: Sequence[torch.Tensor], kx, ky, gain: float, read_noise: float = 0.0,
+                 dark_current: float = 0.0, exptime: float = 0.0, sat_level: float = math.inf,
+                 precision: int = L.GP_PREC_F32, device: int = 0, ctx=None):
+        self.device = torch.device("cuda", device)
+        self.ctx = ctx if ctx is not None else L.gp_ctx_create(device, None)
+        self._own_ctx = ctx is None
+        self.frames_t = list(frames)
+        self.frames = [make_frame(t) for t in self.frames_t]
+        self.kx = np.ascontiguousarray(kx, dtype=np.float32)
+        self.ky = np.ascontiguousarray(ky, dtype=np.float32)
+        self.cp = L.gp_conv_params(self.kx.ctypes.data_as(C.POINTER(C.c_float)), self.kx.size,
+                                   self.ky.ctypes.data_as(C.POINTER(C.c_float)), self.ky.size, sat_level, gain,
+                                   read_noise, dark_current, exptime, precision)
+        self.ws_bytes = L.gp_background_conv_ws(self.frames, self.cp)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        dt = torch.float64 if precision == L.GP_PREC_F64 else torch.float32
+        self.back = [torch.empty(t.shape[0], t.shape[1], dtype=dt, device=self.device) for t in self.frames_t]
+        self.rms = [torch.empty(t.shape[0], t.shape[1], dtype=dt, device=self.device) for t in self.frames_t]
+        self.unfilled = torch.zeros(len(self.frames), dtype=torch.int64, device=self.device)
+
+    def run(self, masks: Optional[Sequence[Optional[torch.Tensor]]] = None, stream=None):
+        mp = None
+        if masks is not None:
+            mp = []
+            for m, t in zip(masks, self.frames_t):
+                if m is None:
+                    mp.append(None)
+                    continue
+                if m.dtype != torch.uint8 or m.shape != t.shape or m.stride() != t.stride():
+                    raise ValueError("masks must be uint8 with the frame's shape and strides")
+                mp.append(m.data_ptr())
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        L.gp_background_conv(self.ctx, self.frames, mp, self.cp, [b.data_ptr() for b in self.back],
+                             [r.data_ptr() for r in self.rms], C.c_void_p(self.unfilled.data_ptr()),
+                             C.c_void_p(self.ws.data_ptr()), self.ws_bytes, C.c_void_p(s.cuda_stream))
+
+    def close(self):
+        if self._own_ctx and self.ctx:
+            L.gp_ctx_destroy(self.ctx)
+            self.ctx = None

@@ -756,6 +756,119 @@ def test_growth_batch_matches_single_frames(P):
     batch.close()
 
 
+# ----------------------------------------------------------------------------
+# local background by convolution
+# ----------------------------------------------------------------------------
+CONV_CASES = [
+    # W, H, dtype, seed, lx, ly, mask kind, sat
+    (600, 400, "f32", 111, 33, 33, "blobs", np.inf),
+    (333, 211, "u16", 112, 31, 9, "blobs", 60000.0),
+    (300, 200, "f32", 113, 129, 129, "none", np.inf),   # the largest kernel
+    (257, 131, "f32", 114, 1, 1, "blobs", np.inf),      # delta kernel: holes stay unfilled
+    (200, 150, "f32", 115, 65, 17, "hole", np.inf),     # a hole wider than the kernel
+]
+
+
+def _conv_inputs(case):
+    W, H, dt, seed, lx, ly, mk, sat = case
+    fr = make_frame("c1", seed=seed, W=W, H=H, dtype=dt, nstars=max(8, W * H // 3000))
+    rng = np.random.default_rng(seed)
+    kx = (0.2 + rng.random(lx)).astype(np.float32)     # asymmetric taps
+    ky = (0.2 + rng.random(ly)).astype(np.float32)
+    mask = None
+    if mk == "blobs":
+        mask = np.zeros((H, W), np.uint8)
+        for _ in range(12):
+            cx, cy, r = rng.integers(0, W), rng.integers(0, H), rng.integers(1, 6)
+            mask[max(cy - r, 0):cy + r + 1, max(cx - r, 0):cx + r + 1] = 1
+    elif mk == "hole":
+        mask = np.zeros((H, W), np.uint8)
+        mask[20:130, 30:160] = 1
+    return fr.image, kx, ky, mask, sat
+
+
+def _conv_tolerances(I, kx, ky, mask, sat, B, prec, gain):
+    """Bounds from oracle-side quantities: the condition K corr |I'| of the
+    sums, the FP32 storage of the intermediates (FP32 path) or the oracle's own
+    2-D summation (FP64 path), and the fill's division by K corr v."""
+    from scipy import ndimage
+    K = np.outer(ky.astype(float) / ky.astype(float).sum(), kx.astype(float) / kx.astype(float).sum())
+    I = I.astype(np.float64)
+    v = np.ones_like(I) if mask is None else (mask == 0).astype(float)
+    v *= (I < sat)
+    Aabs = ndimage.correlate(v * np.abs(I), K, mode="reflect")
+    Cv = ndimage.correlate(v, K, mode="reflect")
+    with np.errstate(divide="ignore", invalid="ignore"):
+        Nabs = np.where(Cv > 0, Aabs / Cv, 0.0)
+    lx, ly = kx.size, ky.size
+    if prec == 0:
+        g = 8 * 2.0 ** -24
+    else:
+        g = (lx * ly + 2 * (lx + ly) + 8) * 2.0 ** -53
+    with np.errstate(divide="ignore", invalid="ignore"):
+        eN = np.where((v == 0) & (Cv > 0), g * (Aabs + Nabs * Cv) / Cv, 0.0)
+    cond = Aabs + ndimage.correlate((1 - v) * Nabs, K, mode="reflect")
+    return g * cond + ndimage.correlate(eN, K, mode="reflect") + g * np.abs(B)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("case", CONV_CASES, ids=lambda c: f"{c[0]}x{c[1]}-{c[2]}-k{c[4]}x{c[5]}-{c[6]}")
+def test_background_conv_against_oracle(P, case, prec):
+    _say("conv case", case, prec)
+    I, kx, ky, mask, sat = _conv_inputs(case)
+    # the parameters as the float32 values the library receives
+    gain, rn, dark, texp = (float(np.float32(q)) for q in (1.6, 7.0, 0.05, 120.0))
+    Bo, Ro, no = oracle.background_conv(I, kx.astype(np.float64), ky.astype(np.float64), mask=mask, sat=sat,
+                                        gain=gain, rn=rn, dark=dark, texp=texp)
+    cb = P.ConvBackground([_dev(I)], kx, ky, gain, rn, dark, texp, sat, precision=prec)
+    cb.run([_dev(mask)] if mask is not None else None)
+    torch.cuda.synchronize()
+    B = cb.back[0].cpu().numpy().astype(np.float64)
+    R = cb.rms[0].cpu().numpy().astype(np.float64)
+    ng = int(cb.unfilled[0].item())
+    assert ng == no, (ng, no)
+    tol = _conv_tolerances(I, kx, ky, mask, sat, Bo, prec, gain)
+    dB = np.abs(B - Bo)
+    _say("conv |dB| max", float(dB.max()), "share of tolerance", float(np.max(dB / np.maximum(tol, 1e-300))),
+         "unfilled", no)
+    assert np.all(dB <= tol), float(np.max(dB - tol))
+    u = 2.0 ** -24 if prec == 0 else 2.0 ** -53
+    tR = 0.5 * tol / (gain * np.maximum(Ro, 1e-300)) + 4 * u * Ro
+    assert np.all(np.abs(R - Ro) <= tR), float(np.max(np.abs(R - Ro) - tR))
+    cb.close()
+
+
+def test_background_conv_constant_frame_and_batch(P):
+    """A constant frame comes back unchanged; a batch of frames (uint16 and
+    float32, several sizes) equals per-frame calls bit for bit."""
+    c = np.full((150, 260), 812.0, np.float32)
+    kx = np.hanning(67)[1:-1].astype(np.float32)
+    ky = np.hanning(35)[1:-1].astype(np.float32)
+    cb = P.ConvBackground([_dev(c)], kx, ky, 2.0)
+    cb.run()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(cb.back[0].cpu().numpy(), c)
+    np.testing.assert_allclose(cb.rms[0].cpu().numpy(), np.sqrt(812.0 / 2.0), rtol=1e-6)
+    cb.close()
+    frs = [make_frame("c1", seed=121, W=300, H=260, nstars=30).image,
+           make_frame("c1", seed=122, W=130, H=90, nstars=8, dtype="u16").image,
+           make_frame("c1", seed=123, W=450, H=128, nstars=25).image]
+    masks = [None, (np.random.default_rng(1).random((90, 130)) < 0.02).astype(np.uint8), None]
+    devs = [_dev(f) for f in frs]
+    mdev = [None if m is None else _dev(m) for m in masks]
+    batch = P.ConvBackground(devs, kx, ky, 1.5, 5.0, sat_level=60000.0)
+    batch.run(mdev)
+    for i, d in enumerate(devs):
+        one = P.ConvBackground([d], kx, ky, 1.5, 5.0, sat_level=60000.0)
+        one.run([mdev[i]])
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(batch.back[i].cpu().numpy(), one.back[0].cpu().numpy())
+        np.testing.assert_array_equal(batch.rms[i].cpu().numpy(), one.rms[0].cpu().numpy())
+        assert int(batch.unfilled[i].item()) == int(one.unfilled[0].item())
+        one.close()
+    batch.close()
+
+
 def _grown(mask):
     """mask grown by one pixel in the 8-neighbourhood"""
     g = mask.copy()
