@@ -10,8 +10,10 @@ one launch of the library's captured graph.  The same frames through plain
 per-frame calls are timed beside it (queued back to back on one stream, and
 as a client that waits for each frame's catalogue).  Further forms: the
 6144^2 and 12300^2 float32 fields per frame (FP32 and FP64 variants of the
-path) and a served Poisson stream of mixed uint16 frames.  Prints one JSON
-line.
+path); the paper's own path over the batch (peaks with the fixed kernel, then
+with the spatially varying PSF, then top-hat growth curves); the background
+by convolution over the batch; and a served Poisson stream of mixed uint16
+frames.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-forms]
                   [--stream-seconds S]
