@@ -26,6 +26,7 @@ Helper modes for the roofline's `traffic` figure (rocprofv3 counters):
                                             FETCH_SIZE / WRITE_SIZE
   python bench.py --traffic KERNEL FETCH.csv WRITE.csv CAL_FETCH.csv CAL_WRITE.csv
                                             writes profiles/traffic_<KERNEL>_<workload>.json
+  python bench.py --form paper|background_conv   one form of the batch alone
 """
 from __future__ import annotations
 
@@ -64,6 +65,8 @@ def parse():
     ap.add_argument("--profile-only", action="store_true",
                     help="only the workload's direct calls (autotuned), for counter collection")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
+    ap.add_argument("--form", choices=["paper", "background_conv"], default=None,
+                    help="run only this form of the batch (for a kernel trace of its kernels)")
     ap.add_argument("--traffic", nargs=5, metavar=("KERNEL", "FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"))
     ap.add_argument("--traffic-last", type=int, default=5,
                     help="dispatches counted: the last N of the kernel (the profiled run's steps)")
@@ -243,6 +246,11 @@ def main():
         sys.exit(2)
     if a.profile_only:
         profile_only(a)
+        return
+    if a.form:
+        import torch
+        fn = {"paper": form_peaks, "background_conv": form_background_conv}[a.form]
+        print(json.dumps(fn(torch, a)), flush=True)
         return
     if a.workload != "batch":
         out = single_frame_line(a)
