@@ -113,6 +113,8 @@ struct DetWork {
     uint32_t* bitmap;      // all frames' first-pixel bitmaps
     int32_t rec_cap;
     int32_t total_blocks;
+    int32_t ahead;         // tiles an XCD's resident workgroups span (the L2 warm-up distance)
+    int32_t pad;
 };
 
 // ---------------------------------------------------------------------------

@@ -786,6 +786,8 @@ static gp_status detect_run(gp_ctx* ctx, const gp_frame* frames, int32_t nframes
     wk.bitmap = (uint32_t*)(W + P.o_bitmap);
     wk.rec_cap = (int32_t)P.rec_cap;
     wk.total_blocks = (int32_t)P.total_blocks;
+    // tiles an XCD holds in flight (four detection workgroups per CU)
+    wk.ahead = std::max(0, ctx->cus / kXcds) * 4;
     {
         ProfScope ps(ctx, s, "setup", prof);
         launch_det_setup(tail, (FrameDesc*)(W + P.o_desc), in, dargs, wk.counters, s);
