@@ -1254,6 +1254,33 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
             if (e < mw * mh) ms[r * L.rmw + c] = (Real)v[u];
         }
     }
+    // warm the L2 with the region of the tile this XCD takes up one round of
+    // resident workgroups later (one load per 128-byte line of its rows,
+    // folded away at the end of this tile)
+    float pf1 = 0.0f;
+    bool pfo = false;
+    {
+        const int chunk = (wk.total_tiles + kXcds - 1) / kXcds;
+        const int g2 = gt + wk.ahead;
+        if (wk.ahead > 0 && g2 < min(wk.total_tiles, (blockIdx.x % kXcds + 1) * chunk)) {
+            const int f2 = frame_of(wk.nframes, g2, [&](int i) { return wk.desc[i].tile_base; });
+            const FrameDesc& d2 = wk.desc[f2];
+            const int l2 = g2 - d2.tile_base;
+            const int x2 = (l2 % d2.ntx) * kTile, y2 = (l2 / d2.ntx) * kTile;
+            const int es2 = d2.dtype == kDtypeU16 ? 2 : 4;
+            const int xa = max(x2 - L.hmx, 0), xb = min(x2 + kTile + L.hmx, d2.W) - 1;
+            const int ya = max(y2 - L.hmy, 0), yb = min(y2 + kTile + L.hmy, d2.H) - 1;
+            const int lpr = (int)((((int64_t)xb * es2) >> 7) - (((int64_t)xa * es2) >> 7)) + 1;
+            for (int t = tid; t < lpr * (yb - ya + 1) && xb >= xa; t += 256) {
+                const int r = t / lpr, li = t - r * lpr;
+                const int64_t line0 = (((int64_t)xa * es2) >> 7) + li;
+                const int64_t px = max(line0 * 128 / es2, (int64_t)xa);
+                const int64_t off = (int64_t)(ya + r) * d2.pitch + px;
+                pf1 += es2 == 2 ? (float)((const gu16_t*)d2.data)[off] : ((const gfloat_t*)d2.data)[off];
+                pfo = true;
+            }
+        }
+    }
     for (int e = tid; e < mh * nix; e += 256) {
         const int r = e / nix, pi = e - r * nix;
         const int ys = reflect_idx(gy0 + r, d.H);
@@ -1491,6 +1518,8 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
         R.frame = f;
         R.cnpix = (wx1 - wx0 + 1) * (wy1 - wy0 + 1);
     }
+    // (never true for the finite values of a frame: it keeps the warm-up loads)
+    if (pfo && __float_as_uint(pf1) == 0x7fc01234u) wk.counters[kNumCounters - 1] = 1u;
 }
 
 // the rank bitmap's bits of the recorded peaks (after every tile has cleared

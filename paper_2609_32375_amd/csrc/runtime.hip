@@ -942,6 +942,8 @@ static gp_status peaks_run(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
     wk.bitmap = (uint32_t*)(W + P.o_bitmap);
     wk.rec_cap = (int32_t)P.rec_cap;
     wk.total_blocks = (int32_t)P.total_blocks;
+    // tiles an XCD holds in flight (two peak workgroups per CU)
+    wk.ahead = std::max(0, ctx->cus / kXcds) * 2;
     PsfArgs* pargs = nullptr;
     PsfFrame* pframes = nullptr;
     {
