@@ -73,8 +73,10 @@ class Server:
     objects kept for reuse; None = 90% of the free memory at start.  Idle batch
     objects are released, least recently used first, whenever a request would
     not fit otherwise.
-    slots: most requests in flight.  streams: concurrent batches.  max_batch:
-    most requests per batch (default: slots / streams).
+    slots: most requests queued or running on the device (a finished batch
+    whose results are still being downloaded no longer holds slots, only its
+    HBM).  streams: concurrent batches.  max_batch: most requests per batch
+    (default: slots / streams).
     """
 
     def __init__(self, params, kernel, capacity: int = 65536, hbm_budget: Optional[int] = None,
@@ -210,7 +212,8 @@ class Server:
         """Start one batch: the oldest arrived request plus every other arrived
         request with the same parameters, while slots and footprint allow."""
         batch = []
-        n_inflight = sum(len(e.reqs) for e in self.inflight) + sum(len(e.reqs) for e, _ in self.downloading)
+        # requests on the device: a batch being downloaded holds only its HBM
+        n_inflight = sum(len(e.reqs) for e in self.inflight)
         now = self.now()
         key = None
         keep = deque()
