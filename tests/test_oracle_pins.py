@@ -377,6 +377,38 @@ def test_mesh_branch_policy_against_numpy_restatement():
         oracle.mesh_one_policy(v, 3, 0.1, 0.1)
 
 
+def test_mesh_decision_margins_against_numpy_restatement():
+    """The clip margin is the smallest | |v - med| - k sigma | / (k sigma) over
+    every value of every pass, the mode margin | |sigma - sigma0| - crowd
+    sigma0 | / sigma0 at the end: both recomputed here with numpy."""
+    rng = np.random.default_rng(13)
+    for trial in range(25):
+        n = int(rng.integers(50, 2500))
+        v = rng.normal(800, 25, n)
+        if trial % 2 == 0:
+            v[: n // 6] += rng.uniform(30, 2000, n // 6)
+        if trial % 4 == 0:
+            v = np.round(v)
+        S = np.sort(v)
+        s0 = np.std(S)
+        mclip = np.inf
+        for _ in range(100):
+            med, lim = np.median(S), 3.0 * np.std(S)
+            d = np.abs(S - med)
+            mclip = min(mclip, float(np.min(np.abs(d - lim) / lim)))
+            keep = d <= lim
+            if keep.all() or not keep.any():
+                break
+            S = S[keep]
+        mmode = abs(abs(np.std(S) - s0) - 0.2 * s0) / s0
+        st = oracle.mesh_one(v)
+        assert st["margin_clip"] == pytest.approx(mclip, rel=1e-9, abs=1e-15), trial
+        assert st["margin_mode"] == pytest.approx(mmode, rel=1e-9, abs=1e-15), trial
+    # a constant mesh decides nothing: both margins infinite
+    st = oracle.mesh_one(np.full(100, 7.0))
+    assert st["margin_clip"] == np.inf and st["margin_mode"] == np.inf
+
+
 def test_mesh_gaussian_sky_statistics():
     rng = np.random.default_rng(2)
     c, sn = 1000.0, 10.0
