@@ -49,8 +49,8 @@ struct ApLayout {
             return r;
         };
         o_s = take(NC * 64 * 8, 16);
-        o_a = take(NC * 64 * (int)sizeof(Real), 16);
-        o_v = take(NC * 64 * (int)sizeof(Real), 16);
+        o_a = take(NC * 64 * 8, 16);
+        o_v = take(NC * 64 * 8, 16);
         o_colp = take(kApBox * 4, 16);
         o_cols = take(kApBox * (int)sizeof(Real), 16);
         o_rxl = take(band * 4, 16);
@@ -74,7 +74,7 @@ struct ApLayout {
 // Only the pixels the outer circle can touch are visited: each row of the box
 // contributes the run of columns within half a pixel plus the chord of the
 // outer circle, and the runs of a band of rows are numbered consecutively and
-// spread over the lanes.  Sums are kept per lane (FP64 for the flux) and
+// spread over the lanes.  Sums are kept per lane (FP64: flux, area, variance) and
 // reduced in a fixed order, so an object's result does not depend on what else
 // runs.
 // ONE: a one-frame call, whose descriptor comes with the launch (d1) instead
@@ -88,8 +88,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real
     int32_t* fpre = reinterpret_cast<int32_t*>(ap_dyn);     // kApPrefixBytes
     unsigned char* base = ap_dyn + kApPrefixBytes + (size_t)wv * L.bytes;
     double* binS = (double*)(base + L.o_s);
-    Real* binA = (Real*)(base + L.o_a);
-    Real* binV = (Real*)(base + L.o_v);
+    double* binA = (double*)(base + L.o_a);
+    double* binV = (double*)(base + L.o_v);
     int32_t* colp = (int32_t*)(base + L.o_colp);
     Real* cols = (Real*)(base + L.o_cols);
     int32_t* rxl = (int32_t*)(base + L.o_rxl);
@@ -175,8 +175,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
             binS[j * 64 + lane] = 0.0;
-            binA[j * 64 + lane] = (Real)0;
-            binV[j * 64 + lane] = (Real)0;
+            binA[j * 64 + lane] = 0.0;
+            binV[j * 64 + lane] = 0.0;
         }
         int listn = 0;
         // exact weights of the queued cut pixels
@@ -190,12 +190,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real
                 const Real wa = w, wvv = w * w * E.var;
                 const int i0 = E.j * 64 + lane;
                 binS[i0] += ws;
-                binA[i0] += wa;
-                binV[i0] += wvv;
+                binA[i0] += (double)wa;
+                binV[i0] += (double)wvv;
                 if (E.j + 1 < NC) {
                     binS[i0 + 64] -= ws;
-                    binA[i0 + 64] -= wa;
-                    binV[i0 + 64] -= wvv;
+                    binA[i0 + 64] -= (double)wa;
+                    binV[i0 + 64] -= (double)wvv;
                 }
             }
             listn = 0;
@@ -298,8 +298,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real
                         if (kin < NC) {
                             const int i0 = kin * 64 + lane;
                             binS[i0] += (double)m;
-                            binA[i0] += (Real)1;
-                            binV[i0] += var;
+                            binA[i0] += 1.0;
+                            binV[i0] += (double)var;
                         }
                     }
                     // circles that cut the pixel: queue (pixel, circle) pairs
@@ -325,11 +325,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real
             for (int j = 0; j < NC; ++j) {
                 const int i0 = j * 64 + lane;
                 ps += binS[i0];
-                pa += (double)binA[i0];
-                pv += (double)binV[i0];
+                pa += binA[i0];
+                pv += binV[i0];
                 binS[i0] = ps;
-                binA[i0] = (Real)pa;
-                binV[i0] = (Real)pv;
+                binA[i0] = pa;
+                binV[i0] = pv;
             }
         }
         wave_sync();
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real
                 if (q < NC) {
                     for (int t = 0; t < SPAN; ++t) part += binS[s0 + t];
                 } else {
-                    const Real* src = (q < 2 * NC) ? binA : binV;
+                    const double* src = (q < 2 * NC) ? binA : binV;
                     for (int t = 0; t < SPAN; ++t) part += (double)src[s0 + t];
                 }
             }
