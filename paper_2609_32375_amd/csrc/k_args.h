@@ -116,13 +116,15 @@ struct GrowOut {
     uint32_t* flags;
 };
 
-// local background by convolution: raw separable taps (normalised on the
-// device) and the noise-model constants
+// local background by convolution: separable taps and the noise-model constants
 constexpr int kMaxConvTaps = 129;
+// taps normalised to unit sum in FP64 on the host and zero-padded to a whole
+// number of 8-tap blocks (the kernels' register blocking)
+constexpr int kConvTapsPad = (kMaxConvTaps + 7) / 8 * 8;
 struct CvArgs {
     int32_t lx, ly;
     float gain, read_noise, dark, exptime;
-    float kx[kMaxConvTaps], ky[kMaxConvTaps];
+    double kx[kConvTapsPad], ky[kConvTapsPad];
 };
 
 // one: the descriptor of a one-frame call, passed with the launch (the kernel

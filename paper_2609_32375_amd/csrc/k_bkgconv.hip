@@ -12,88 +12,125 @@
 //   2. vertical pass: A, C; fill image G = (1 - v) A / C  -> A, G
 //   3. horizontal pass of G (only if the frame has invalid pixels) -> hG
 //   4. vertical pass of hG, B = A + (K corr G), noise map R from B
-// Sums accumulate in FP64 from values stored in the working precision; each
-// pass stages its rows (or a column band) in LDS with the reflection applied
-// on load.  Noise map for a dark-subtracted frame in ADU:
+// Sums accumulate in FP64 from values stored in the working precision, with
+// the unit-sum FP64 taps read as uniform kernel arguments (zero-padded to a
+// multiple of 8: a zero tap adds an exact zero).  Each pass stages its rows
+// (or a column band) in LDS with the reflection applied on load, and every
+// thread keeps a block of 8 consecutive outputs in registers, sliding a
+// 16-value window through the staged data: one LDS read per 8 FMAs per
+// channel.  Each output's sum runs over the taps in order.  Noise map for a
+// dark-subtracted frame in ADU:
 //   R^2 = (g max(B, 0) + rn^2 + dark texp) / g^2.
 #include "k_args.h"
 
 namespace gpk {
 
-constexpr int kCvSeg = 256;    // outputs per horizontal workgroup
-constexpr int kCvCols = 64;    // columns per vertical workgroup
-constexpr int kCvRows = 64;    // output rows per vertical workgroup
+constexpr int kCvT = 8;                     // outputs per thread (register block)
+constexpr int kCvThreads = 256;
+constexpr int kCvSeg = kCvThreads * kCvT;   // outputs per horizontal workgroup
+constexpr int kCvCols = 64;                 // columns per vertical workgroup
+constexpr int kCvRows = 64;                 // output rows per vertical workgroup (4 groups x 2 blocks)
 
-// normalised taps in LDS (every thread forms the same FP64 sum in one order)
-__device__ __forceinline__ void cv_taps(const float* raw, int n, double* out) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += (double)raw[i];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = (double)raw[i] / s;
-}
+__host__ __device__ __forceinline__ int cv_pad(int n) { return (n + kCvT - 1) / kCvT * kCvT; }
 
 __device__ __forceinline__ bool cv_valid(const FrameDesc& d, const uint8_t* mask, int x, int y, float sat, float& v) {
     v = load_px(d, x, y);
     return !(mask && mask[(int64_t)y * d.pitch + x]) && v < sat;
 }
 
+// acc[j] += sum_b k[b] w(j + b) over the padded taps, w(i) = src[i * step]:
+// the window w[0..15] holds w(c + 0..15) for the 8-tap block at c
+template <typename Real>
+__device__ __forceinline__ void cv_block(const Real* src, int step, const double* k, int np, double* acc) {
+    double w[2 * kCvT];
+#pragma unroll
+    for (int q = 0; q < kCvT; ++q) w[q] = (double)src[q * step];
+    for (int c = 0; c < np; c += kCvT) {
+#pragma unroll
+        for (int q = 0; q < kCvT; ++q) w[kCvT + q] = (double)src[(c + kCvT + q) * step];
+#pragma unroll
+        for (int b = 0; b < kCvT; ++b) {
+            const double kb = k[c + b];
+#pragma unroll
+            for (int j = 0; j < kCvT; ++j) acc[j] = fma(kb, w[j + b], acc[j]);
+        }
+#pragma unroll
+        for (int q = 0; q < kCvT; ++q) w[q] = w[kCvT + q];
+    }
+}
+
 // FIRST: the two channels vI and v from the frame; else one channel from src
 template <typename Real, bool FIRST>
-__global__ __launch_bounds__(kCvSeg) void k_conv_h(FrameDesc d, const uint8_t* __restrict__ mask, float sat,
-                                                   const Real* __restrict__ src, Real* __restrict__ out0,
-                                                   Real* __restrict__ out1, CvArgs a, int* __restrict__ flag) {
+__global__ __launch_bounds__(kCvThreads) void k_conv_h(FrameDesc d, const uint8_t* __restrict__ mask, float sat,
+                                                       const Real* __restrict__ src, Real* __restrict__ out0,
+                                                       Real* __restrict__ out1, CvArgs a, int* __restrict__ flag) {
     extern __shared__ __align__(16) unsigned char cv_dyn[];
     if (!FIRST && flag[0] == 0) return;   // nothing to fill in this frame
-    double* kx = reinterpret_cast<double*>(cv_dyn);
-    Real* s0 = reinterpret_cast<Real*>(cv_dyn + sizeof(double) * kMaxConvTaps);
-    Real* s1 = s0 + (kCvSeg + kMaxConvTaps);
-    cv_taps(a.kx, a.lx, kx);
+    const int np = cv_pad(a.lx), span = kCvSeg + np;
+    Real* s0 = reinterpret_cast<Real*>(cv_dyn);
+    Real* s1 = s0 + span;
     const int y = blockIdx.y, x0 = blockIdx.x * kCvSeg, hx = a.lx >> 1;
-    const int n = min(kCvSeg, d.W - x0) + a.lx - 1;
-    for (int i = threadIdx.x; i < n; i += kCvSeg) {
-        const int xs = reflect_idx(x0 - hx + i, d.W);
-        if (FIRST) {
-            float v;
-            const bool ok = cv_valid(d, mask, xs, y, sat, v);
-            s0[i] = ok ? (Real)v : (Real)0;
-            s1[i] = ok ? (Real)1 : (Real)0;
-        } else {
-            s0[i] = src[(int64_t)y * d.W + xs];
+    const int n = min(kCvSeg, d.W - x0) + a.lx - 1;   // staged values any written output reads
+    for (int i = threadIdx.x; i < span; i += kCvThreads) {
+        Real v0 = (Real)0, v1 = (Real)0;
+        if (i < n) {
+            const int xs = reflect_idx(x0 - hx + i, d.W);
+            if (FIRST) {
+                float v;
+                if (cv_valid(d, mask, xs, y, sat, v)) {
+                    v0 = (Real)v;
+                    v1 = (Real)1;
+                }
+            } else {
+                v0 = src[(int64_t)y * d.W + xs];
+            }
         }
+        s0[i] = v0;
+        if (FIRST) s1[i] = v1;
     }
     __syncthreads();
-    const int x = x0 + threadIdx.x;
-    if (x >= d.W) return;
-    double a0 = 0.0, a1 = 0.0;
-    for (int b = 0; b < a.lx; ++b) {
-        a0 = fma(kx[b], (double)s0[threadIdx.x + b], a0);
-        if (FIRST) a1 = fma(kx[b], (double)s1[threadIdx.x + b], a1);
-    }
-    out0[(int64_t)y * d.W + x] = (Real)a0;
-    if (FIRST) out1[(int64_t)y * d.W + x] = (Real)a1;
-}
-
-// vertical sum of one channel over the staged band: out[r] for this thread's
-// column, rows r0, r0 + 4, ... (4 row groups of the 256 threads)
-template <typename Real>
-__device__ __forceinline__ void cv_vsum(const Real* band, const double* ky, int ly, int c, int g, int nr,
-                                        double* acc) {
+    const int i0 = threadIdx.x * kCvT;
+    if (x0 + i0 >= d.W) return;
+    double a0[kCvT], a1[kCvT];
 #pragma unroll
-    for (int q = 0; q < kCvRows / 4; ++q) {
-        const int r = g + 4 * q;
-        double s = 0.0;
-        if (r < nr)
-            for (int t = 0; t < ly; ++t) s = fma(ky[t], (double)band[(r + t) * kCvCols + c], s);
-        acc[q] = s;
-    }
+    for (int j = 0; j < kCvT; ++j) a0[j] = a1[j] = 0.0;
+    cv_block(s0 + i0, 1, a.kx, np, a0);
+    if (FIRST) cv_block(s1 + i0, 1, a.kx, np, a1);
+    Real* o0 = out0 + (int64_t)y * d.W + x0 + i0;
+    Real* o1 = FIRST ? out1 + (int64_t)y * d.W + x0 + i0 : nullptr;
+    const int m = min(kCvT, d.W - x0 - i0);
+#pragma unroll
+    for (int j = 0; j < kCvT; ++j)
+        if (j < m) {
+            o0[j] = (Real)a0[j];
+            if (FIRST) o1[j] = (Real)a1[j];
+        }
 }
 
+// rows y0 - hy + i, i < nrows, of a 64-column band (columns clamped to the
+// frame; the values are only read for columns inside it), zero beyond nrows
 template <typename Real>
 __device__ __forceinline__ void cv_stage(const Real* __restrict__ src, const FrameDesc& d, int xc0, int y0, int hy,
-                                         int nrows, Real* band) {
-    for (int i = threadIdx.x; i < nrows * kCvCols; i += blockDim.x) {
+                                         int nrows, int rows, Real* band) {
+    for (int i = threadIdx.x; i < rows * kCvCols; i += blockDim.x) {
         const int r = i / kCvCols, c = i - r * kCvCols;
         const int x = min(xc0 + c, d.W - 1);
-        band[i] = src[(int64_t)reflect_idx(y0 - hy + r, d.H) * d.W + x];
+        band[i] = r < nrows ? src[(int64_t)reflect_idx(y0 - hy + r, d.H) * d.W + x] : (Real)0;
+    }
+}
+
+// the vertical sums of one channel for this thread's column and its two
+// blocks of 8 rows, g * 16 + 0..7 and g * 16 + 8..15 (blocks wholly below
+// the last output row are skipped)
+template <typename Real>
+__device__ __forceinline__ void cv_vsum(const Real* band, const double* k, int np, int c, int g, int nr,
+                                        double* acc) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r0 = g * 2 * kCvT + h * kCvT;
+#pragma unroll
+        for (int j = 0; j < kCvT; ++j) acc[h * kCvT + j] = 0.0;
+        if (r0 < nr) cv_block(band + r0 * kCvCols + c, kCvCols, k, np, acc + h * kCvT);
     }
 }
 
@@ -105,32 +142,31 @@ __global__ __launch_bounds__(256) void k_conv_v(FrameDesc d, const uint8_t* __re
                                                 Real* outA, Real* outG, Real* back, Real* rms, CvArgs a,
                                                 int* __restrict__ flag, int64_t* __restrict__ unfilled) {
     extern __shared__ __align__(16) unsigned char cv_dyn[];
-    double* ky = reinterpret_cast<double*>(cv_dyn);
-    Real* band = reinterpret_cast<Real*>(cv_dyn + sizeof(double) * kMaxConvTaps);
-    cv_taps(a.ky, a.ly, ky);
+    Real* band = reinterpret_cast<Real*>(cv_dyn);
+    const int np = cv_pad(a.ly), rows = kCvRows + np;
     const int xc0 = blockIdx.x * kCvCols, y0 = blockIdx.y * kCvRows, hy = a.ly >> 1;
     const int nr = min(kCvRows, d.H - y0), nrows = nr + a.ly - 1;
     const int c = threadIdx.x & (kCvCols - 1), g = threadIdx.x / kCvCols;
     const int x = xc0 + c;
-    double s0[kCvRows / 4], s1[kCvRows / 4];
+    double s0[2 * kCvT], s1[2 * kCvT];
     const bool fill = FIRST || flag[0] != 0;
-    if (FIRST || fill) {
-        cv_stage(in0, d, xc0, y0, hy, nrows, band);
+    if (fill) {
+        cv_stage(in0, d, xc0, y0, hy, nrows, rows, band);
         __syncthreads();
-        cv_vsum(band, ky, a.ly, c, g, nr, s0);
+        cv_vsum(band, a.ky, np, c, g, nr, s0);
     }
     if (FIRST) {
         __syncthreads();
-        cv_stage(in1, d, xc0, y0, hy, nrows, band);
+        cv_stage(in1, d, xc0, y0, hy, nrows, rows, band);
         __syncthreads();
-        cv_vsum(band, ky, a.ly, c, g, nr, s1);
+        cv_vsum(band, a.ky, np, c, g, nr, s1);
     }
     if (x >= d.W) return;
     int64_t nun = 0;
     bool any = false;
 #pragma unroll
-    for (int q = 0; q < kCvRows / 4; ++q) {
-        const int r = g + 4 * q;
+    for (int q = 0; q < 2 * kCvT; ++q) {
+        const int r = g * 2 * kCvT + q;
         if (r >= nr) break;
         const int y = y0 + r;
         const int64_t o = (int64_t)y * d.W + x;
@@ -167,17 +203,21 @@ __global__ void k_conv_clear(int* flag, int64_t* unfilled) {
     }
 }
 
-size_t conv_h_lds(bool f64) { return sizeof(double) * kMaxConvTaps + 2 * (kCvSeg + kMaxConvTaps) * (f64 ? 8 : 4); }
-size_t conv_v_lds(int ly, bool f64) {
-    return sizeof(double) * kMaxConvTaps + (size_t)(kCvRows + ly - 1) * kCvCols * (f64 ? 8 : 4);
-}
+size_t conv_h_lds(int lx, bool f64) { return 2 * (size_t)(kCvSeg + cv_pad(lx)) * (f64 ? 8 : 4); }
+size_t conv_v_lds(int ly, bool f64) { return (size_t)(kCvRows + cv_pad(ly)) * kCvCols * (f64 ? 8 : 4); }
 
 template <typename Real>
 static hipError_t conv_frame_t(const FrameDesc& d, const uint8_t* mask, float sat, const CvArgs& a, Real* hA,
                                Real* hC, Real* G, Real* back, Real* rms, int* flag, int64_t* unfilled,
                                hipStream_t s) {
-    const size_t lh = conv_h_lds(sizeof(Real) == 8), lv = conv_v_lds(a.ly, sizeof(Real) == 8);
+    const size_t lh = conv_h_lds(a.lx, sizeof(Real) == 8), lv = conv_v_lds(a.ly, sizeof(Real) == 8);
     hipError_t e;
+    if ((e = hipFuncSetAttribute((const void*)k_conv_h<Real, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lh)) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void*)k_conv_h<Real, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lh)) != hipSuccess)
+        return e;
     if ((e = hipFuncSetAttribute((const void*)k_conv_v<Real, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lv)) != hipSuccess)
         return e;
@@ -187,11 +227,11 @@ static hipError_t conv_frame_t(const FrameDesc& d, const uint8_t* mask, float sa
     const dim3 gh((d.W + kCvSeg - 1) / kCvSeg, d.H), gv((d.W + kCvCols - 1) / kCvCols, (d.H + kCvRows - 1) / kCvRows);
     k_conv_clear<<<1, 64, 0, s>>>(flag, unfilled);
     // 1. horizontal: vI -> hA, v -> hC
-    k_conv_h<Real, true><<<gh, kCvSeg, lh, s>>>(d, mask, sat, nullptr, hA, hC, a, flag);
+    k_conv_h<Real, true><<<gh, kCvThreads, lh, s>>>(d, mask, sat, nullptr, hA, hC, a, flag);
     // 2. vertical: A -> back (kept until step 4), fill image -> G
     k_conv_v<Real, true><<<gv, 256, lv, s>>>(d, mask, sat, hA, hC, back, G, nullptr, nullptr, a, flag, unfilled);
     // 3. horizontal pass of G into hA (skipped without invalid pixels)
-    k_conv_h<Real, false><<<gh, kCvSeg, lh, s>>>(d, mask, sat, G, hA, nullptr, a, flag);
+    k_conv_h<Real, false><<<gh, kCvThreads, lh, s>>>(d, mask, sat, G, hA, nullptr, a, flag);
     // 4. B = A + vertical pass of it; noise map
     k_conv_v<Real, false><<<gv, 256, lv, s>>>(d, mask, sat, hA, nullptr, back, nullptr, back, rms, a, flag, nullptr);
     return hipGetLastError();

@@ -1276,8 +1276,12 @@ extern "C" gp_status gp_background_conv(gp_ctx* ctx, const gp_frame* frames, int
     a.read_noise = cp->read_noise;
     a.dark = cp->dark_current;
     a.exptime = cp->exptime;
-    for (int i = 0; i < cp->lx; ++i) a.kx[i] = cp->kx[i];
-    for (int i = 0; i < cp->ly; ++i) a.ky[i] = cp->ky[i];
+    // unit-sum taps: the FP64 sum in tap order, then each tap divided by it
+    double sx = 0.0, sy = 0.0;
+    for (int i = 0; i < cp->lx; ++i) sx += (double)cp->kx[i];
+    for (int i = 0; i < cp->ly; ++i) sy += (double)cp->ky[i];
+    for (int i = 0; i < cp->lx; ++i) a.kx[i] = (double)cp->kx[i] / sx;
+    for (int i = 0; i < cp->ly; ++i) a.ky[i] = (double)cp->ky[i] / sy;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(ctx->device));
     ProfScope ps(ctx, s, "background_conv");
