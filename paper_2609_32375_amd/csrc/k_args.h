@@ -157,8 +157,10 @@ void launch_growth_table(const GrowArgs& a, const GrowTab& t, hipStream_t s);
 hipError_t launch_growth(const FrameDesc* desc, const FrameDesc* one, const GrowArgs& a, const GrowTab& t,
                          const GrowOut& g, int blocks, int waves, bool f64, hipStream_t s);
 size_t growth_lds_bytes(int nfull, int ncut, int side, int nixmax, int want_var, bool f64, int waves);
-hipError_t launch_conv_frame(const FrameDesc& d, const uint8_t* mask, float sat, const CvArgs& a, void* hA, void* hC,
-                             void* G, void* back, void* rms, int* flag, int64_t* unfilled, bool f64, hipStream_t s);
+// inval: (height x ceil(width / 64)) bytes of per-row band flags
+hipError_t launch_conv_frame(const FrameDesc& d, const uint8_t* mask, float sat, const CvArgs& a, void* hA,
+                             void* inval, void* G, void* back, void* rms, int* flag, int64_t* unfilled, bool f64,
+                             hipStream_t s);
 void launch_bkg_map(const FrameDesc& d, double* bmap, double* rmap, bool f64, hipStream_t s);
 void launch_write_desc(const DescChunk& c, FrameDesc* table, hipStream_t s);
 void launch_det_setup(const DescChunk& c, FrameDesc* table, const DetArgsIn& in, DetArgs* out, uint32_t* counters,

@@ -1228,11 +1228,23 @@ gp_status check_conv(const gp_frame* frames, int32_t nframes, const gp_conv_para
     return GP_OK;
 }
 
-size_t conv_ws_bytes(const gp_frame* frames, int32_t nframes, const gp_conv_params* cp) {
-    int64_t mx = 1;
-    for (int f = 0; f < nframes; ++f) mx = std::max<int64_t>(mx, (int64_t)frames[f].width * frames[f].height);
+// flag word; two working-precision planes (hA / hG, G) and the per-row band
+// flags of the largest frame
+struct ConvWs {
+    size_t plane, flags;
+};
+ConvWs conv_ws_parts(const gp_frame* frames, int32_t nframes, const gp_conv_params* cp) {
+    int64_t mx = 1, mf = 1;
+    for (int f = 0; f < nframes; ++f) {
+        mx = std::max<int64_t>(mx, (int64_t)frames[f].width * frames[f].height);
+        mf = std::max<int64_t>(mf, (int64_t)frames[f].height * ((frames[f].width + 63) / 64));
+    }
     const size_t real = cp->precision == GP_PREC_F64 ? 8 : 4;
-    return 256 + 3 * align256(real * (size_t)mx);
+    return {align256(real * (size_t)mx), align256((size_t)mf)};
+}
+size_t conv_ws_bytes(const gp_frame* frames, int32_t nframes, const gp_conv_params* cp) {
+    const ConvWs w = conv_ws_parts(frames, nframes, cp);
+    return 256 + 2 * w.plane + w.flags;
 }
 }  // namespace
 
@@ -1261,14 +1273,12 @@ extern "C" gp_status gp_background_conv(gp_ctx* ctx, const gp_frame* frames, int
     if (ws_bytes < need)
         return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
     const bool f64 = cp->precision == GP_PREC_F64;
-    const size_t real = f64 ? 8 : 4;
-    int64_t mx = 1;
-    for (int f = 0; f < nframes; ++f) mx = std::max<int64_t>(mx, (int64_t)frames[f].width * frames[f].height);
+    const ConvWs wp = conv_ws_parts(frames, nframes, cp);
     char* W = (char*)ws;
     int* flag = (int*)W;
     void* hA = W + 256;
-    void* hC = W + 256 + align256(real * (size_t)mx);
-    void* G = W + 256 + 2 * align256(real * (size_t)mx);
+    void* G = W + 256 + wp.plane;
+    void* inval = W + 256 + 2 * wp.plane;
     CvArgs a{};
     a.lx = cp->lx;
     a.ly = cp->ly;
@@ -1292,8 +1302,8 @@ extern "C" gp_status gp_background_conv(gp_ctx* ctx, const gp_frame* frames, int
         d.W = frames[f].width;
         d.H = frames[f].height;
         d.dtype = frames[f].dtype;
-        const hipError_t e = launch_conv_frame(d, masks ? masks[f] : nullptr, cp->sat_level, a, hA, hC, G, back[f],
-                                               rms[f], flag, unfilled + f, f64, s);
+        const hipError_t e = launch_conv_frame(d, masks ? masks[f] : nullptr, cp->sat_level, a, hA, inval, G,
+                                               back[f], rms[f], flag, unfilled + f, f64, s);
         if (e != hipSuccess) return fail(GP_ERR_HIP, "background convolution: %s", hipGetErrorString(e));
     }
     return GP_OK;

@@ -766,6 +766,11 @@ CONV_CASES = [
     (300, 200, "f32", 113, 129, 129, "none", np.inf),   # the largest kernel
     (257, 131, "f32", 114, 1, 1, "blobs", np.inf),      # delta kernel: holes stay unfilled
     (200, 150, "f32", 115, 65, 17, "hole", np.inf),     # a hole wider than the kernel
+    # two horizontal segments; invalid pixels on the four borders, at the
+    # segment seam and at band edges (the reach of the fill passes)
+    (2300, 150, "f32", 116, 65, 65, "edges", np.inf),
+    (40, 30, "u16", 117, 65, 33, "blobs", 60000.0),   # narrower than the kernel: repeated reflections
+    (700, 300, "u16", 118, 65, 65, "none", 30000.0),  # saturated star cores only
 ]
 
 
@@ -784,6 +789,11 @@ def _conv_inputs(case):
     elif mk == "hole":
         mask = np.zeros((H, W), np.uint8)
         mask[20:130, 30:160] = 1
+    elif mk == "edges":
+        mask = np.zeros((H, W), np.uint8)
+        for x, y in ((0, 17), (W - 1, 40), (90, 0), (1500, H - 1), (0, 0), (W - 1, H - 1), (2047, 70), (2048, 71),
+                     (2040, 110), (63, 120), (64, 121), (W - 2, 5)):
+            mask[y, x] = 1
     return fr.image, kx, ky, mask, sat
 
 
