@@ -93,6 +93,70 @@ __device__ __forceinline__ void cv_reach(int a, int b, int n, int& lo, int& hi) 
     }
 }
 
+// A horizontal workgroup's staging: position i = tid + 256 k of the row
+// segment plus halo, every load issued before the first store (the loads of
+// positions past n repeat position n - 1 and are discarded).  FIRST: vI from
+// the frame (T: its pixel type) and the band flags; else G where the row's
+// band flag fr says it was written, zero elsewhere.
+constexpr int kHStage = (kCvSeg + kConvTapsPad + kCvThreads - 1) / kCvThreads;
+
+// half-sample reflection into [0, n) for -n <= i < 2n (one reflection), as selects
+__device__ __forceinline__ int reflect1(int i, int n) {
+    i = i < 0 ? -i - 1 : i;
+    return i >= n ? 2 * n - 1 - i : i;
+}
+
+// ONE: the frame is at least half a kernel wide, so one reflection reaches
+// every staged position; the loads then have no branch between them
+template <typename Real, bool FIRST, typename T, bool ONE>
+__device__ __forceinline__ void cv_stage_h(const FrameDesc& d, const uint8_t* __restrict__ mask, float sat,
+                                           const Real* __restrict__ src, const uint8_t* fr, int x0, int hx, int n,
+                                           int nseg, int span, int y, Real* s0, int* bfl) {
+    typedef __attribute__((address_space(1))) const T gT;
+    Real pv[kHStage];
+    uint8_t mv[kHStage];
+    const int64_t row = FIRST ? (int64_t)y * d.pitch : (int64_t)y * d.W;
+    // without a mask, read the frame's first byte in its place (ignored)
+    const uint8_t* mp = mask ? mask + row : (const uint8_t*)d.data;
+    const int mstep = mask ? 1 : 0;
+#pragma unroll
+    for (int k = 0; k < kHStage; ++k) {
+        const int i = min((int)threadIdx.x + k * kCvThreads, n - 1);
+        const int xs = ONE ? reflect1(x0 - hx + i, d.W) : reflect_idx(x0 - hx + i, d.W);
+        if (FIRST) {
+            pv[k] = (Real)((gT*)d.data)[row + xs];
+            mv[k] = mp[xs * mstep];
+        } else {
+            pv[k] = src[row + xs];
+            mv[k] = fr[xs / kCvCols];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kHStage; ++k) {
+        const int i = threadIdx.x + k * kCvThreads;
+        if (i < span) {
+            Real v0 = (Real)0;
+            if (i < n) {
+                if (FIRST) {
+                    if (!(mstep && mv[k]) && (float)pv[k] < sat) v0 = pv[k];
+                    else if (i >= hx && i < hx + nseg) bfl[(i - hx) / kCvCols] = 1;
+                } else if (mv[k]) {
+                    v0 = pv[k];
+                }
+            }
+            s0[i] = v0;
+        }
+    }
+}
+
+template <typename Real, bool FIRST, typename T>
+__device__ __forceinline__ void cv_stage_h(const FrameDesc& d, const uint8_t* __restrict__ mask, float sat,
+                                           const Real* __restrict__ src, const uint8_t* fr, int x0, int hx, int n,
+                                           int nseg, int span, int y, Real* s0, int* bfl) {
+    if (d.W >= hx) cv_stage_h<Real, FIRST, T, true>(d, mask, sat, src, fr, x0, hx, n, nseg, span, y, s0, bfl);
+    else cv_stage_h<Real, FIRST, T, false>(d, mask, sat, src, fr, x0, hx, n, nseg, span, y, s0, bfl);
+}
+
 // FIRST: vI from the frame, and the invalid-pixel flags of the segment's
 // bands; else G from src in the rows whose reach holds an invalid pixel
 template <typename Real, bool FIRST>
@@ -120,19 +184,13 @@ __global__ __launch_bounds__(kCvThreads) void k_conv_h(FrameDesc d, const uint8_
         for (int b = lo / kCvCols + (int)threadIdx.x; b <= hi / kCvCols; b += kCvThreads) any |= fr[b] != 0;
         if (!__syncthreads_or(any)) return;   // G is zero wherever this row segment reads it
     }
-    for (int i = threadIdx.x; i < span; i += kCvThreads) {
-        Real v0 = (Real)0;
-        if (i < n) {
-            const int xs = reflect_idx(x0 - hx + i, d.W);
-            if (FIRST) {
-                float v;
-                if (cv_valid(d, mask, xs, y, sat, v)) v0 = (Real)v;
-                else if (i >= hx && i < hx + nseg) bfl[(i - hx) / kCvCols] = 1;
-            } else if (fr[xs / kCvCols]) {
-                v0 = src[(int64_t)y * d.W + xs];
-            }
-        }
-        s0[i] = v0;
+    if (FIRST) {
+        if (d.dtype == kDtypeU16)
+            cv_stage_h<Real, true, uint16_t>(d, mask, sat, src, fr, x0, hx, n, nseg, span, y, s0, bfl);
+        else
+            cv_stage_h<Real, true, float>(d, mask, sat, src, fr, x0, hx, n, nseg, span, y, s0, bfl);
+    } else {
+        cv_stage_h<Real, false, float>(d, mask, sat, src, fr, x0, hx, n, nseg, span, y, s0, bfl);
     }
     __syncthreads();
     if (FIRST && threadIdx.x < kCvSeg / kCvCols) {
@@ -156,16 +214,29 @@ __global__ __launch_bounds__(kCvThreads) void k_conv_h(FrameDesc d, const uint8_
         if (j < m) o0[j] = (Real)a0[j];
 }
 
-// rows y0 - hy + i, i < nrows, of a 64-column band (columns clamped to the
+// rows y0 - hy + r, r < nrows, of a 64-column band (columns clamped to the
 // frame; the values are only read for columns inside it); zero beyond nrows
-// and, with act, in the rows act marks as zero
+// and, with act, in the rows act marks as zero.  Thread (c, g) stages column
+// c of rows g, g + 4, ..., kVStage loads in flight before their stores.
+constexpr int kVStage = 16;
 template <typename Real>
 __device__ __forceinline__ void cv_stage(const Real* __restrict__ src, const FrameDesc& d, int xc0, int y0, int hy,
                                          int nrows, int rows, const uint8_t* act, Real* band) {
-    for (int i = threadIdx.x; i < rows * kCvCols; i += blockDim.x) {
-        const int r = i / kCvCols, c = i - r * kCvCols;
-        const int x = min(xc0 + c, d.W - 1);
-        band[i] = r < nrows && (!act || act[r]) ? src[(int64_t)reflect_idx(y0 - hy + r, d.H) * d.W + x] : (Real)0;
+    const int c = threadIdx.x & (kCvCols - 1), g = threadIdx.x / kCvCols;
+    const Real* col = src + min(xc0 + c, d.W - 1);
+    for (int r0 = g; r0 < rows; r0 += 4 * kVStage) {
+        Real v[kVStage];
+#pragma unroll
+        for (int k = 0; k < kVStage; ++k) {
+            const int r = r0 + 4 * k;
+            v[k] = (Real)0;
+            if (r < nrows && (!act || act[r])) v[k] = col[(int64_t)reflect_idx(y0 - hy + r, d.H) * d.W];
+        }
+#pragma unroll
+        for (int k = 0; k < kVStage; ++k) {
+            const int r = r0 + 4 * k;
+            if (r < rows) band[r * kCvCols + c] = v[k];
+        }
     }
 }
 
@@ -217,8 +288,18 @@ __device__ __forceinline__ void cv_hbits(const uint64_t* bits, const double* k, 
     }
 }
 
-// FIRST: A from hA; in tiles with an invalid pixel, C, the fill image G and
-// the unfilled count.  Else: B = A + (K corr G) and the noise map.
+// noise map of a dark-subtracted frame in ADU from B
+template <typename Real>
+__device__ __forceinline__ Real cv_noise(double b, const CvArgs& a) {
+    const double sky = b > 0.0 ? b : 0.0;
+    const double var_e =
+        fma((double)a.gain, sky, fma((double)a.read_noise, (double)a.read_noise, (double)a.dark * (double)a.exptime));
+    return (Real)sqrt(var_e / ((double)a.gain * (double)a.gain));
+}
+
+// FIRST: A from hA; B and R where the fill round adds nothing; in tiles with
+// an invalid pixel, C, the fill image G and the unfilled count.  Else, in the
+// tiles the fill round reaches: B = A + (K corr G) and the noise map.
 template <typename Real, bool FIRST>
 __global__ __launch_bounds__(256) void k_conv_v(FrameDesc d, const uint8_t* __restrict__ mask, float sat,
                                                 const Real* __restrict__ in0, Real* outA, Real* outG, Real* back,
@@ -234,36 +315,35 @@ __global__ __launch_bounds__(256) void k_conv_v(FrameDesc d, const uint8_t* __re
     const int c = threadIdx.x & (kCvCols - 1), g = threadIdx.x / kCvCols;
     const int x = xc0 + c;
     double s0[2 * kCvT], s1[2 * kCvT];
-    bool fill;   // FIRST: the tile holds an invalid pixel; else: K corr G may be non-zero here
+    // late: K corr G may be non-zero in this tile (some staged row's reach
+    // along x holds an invalid pixel; act marks those rows).  Known from the
+    // flags of the first horizontal pass, so the first vertical pass already
+    // finishes B and R where it is not.
+    bool late = false;
+    if (flag[0] != 0) {
+        int lo, hi;
+        cv_reach(xc0 - hx, min(xc0 + kCvCols, d.W) - 1 + hx, d.W, lo, hi);
+        bool mine = false;
+        for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+            const uint8_t* fr = inval + (int64_t)reflect_idx(y0 - hy + r, d.H) * nb;
+            bool on = false;
+            for (int b = lo / kCvCols; b <= hi / kCvCols; ++b) on |= fr[b] != 0;
+            act[r] = on;
+            mine |= on;
+        }
+        late = __syncthreads_or(mine);
+    }
+    bool fill;   // FIRST: the tile holds an invalid pixel
     if (FIRST) {
         const bool mine = (int)threadIdx.x < nr && inval[(int64_t)(y0 + threadIdx.x) * nb + blockIdx.x] != 0;
         fill = __syncthreads_or(mine);
     } else {
-        if (flag[0] == 0) {
-            fill = false;
-        } else {
-            // staged rows whose reach along x holds an invalid pixel
-            int lo, hi;
-            cv_reach(xc0 - hx, min(xc0 + kCvCols, d.W) - 1 + hx, d.W, lo, hi);
-            bool mine = false;
-            for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
-                const uint8_t* fr = inval + (int64_t)reflect_idx(y0 - hy + r, d.H) * nb;
-                bool on = false;
-                for (int b = lo / kCvCols; b <= hi / kCvCols; ++b) on |= fr[b] != 0;
-                act[r] = on;
-                mine |= on;
-            }
-            fill = __syncthreads_or(mine);
-        }
+        if (!late) return;   // B and R were written by the first vertical pass
+        fill = true;
     }
-    if (FIRST || fill) {
-        cv_stage(in0, d, xc0, y0, hy, nrows, rows, FIRST ? nullptr : act, band);
-        __syncthreads();
-        cv_vsum(band, a.ky, np, c, g, nr, s0);
-    } else {
-#pragma unroll
-        for (int q = 0; q < 2 * kCvT; ++q) s0[q] = 0.0;
-    }
+    cv_stage(in0, d, xc0, y0, hy, nrows, rows, FIRST ? nullptr : act, band);
+    __syncthreads();
+    cv_vsum(band, a.ky, np, c, g, nr, s0);
     if (FIRST && fill) {
         // C over the tile: validity bits of its neighbourhood, then both passes
         uint64_t* bits = reinterpret_cast<uint64_t*>(cv_dyn + conv_v_band_bytes(a.ly, sizeof(Real) == 8));
@@ -285,6 +365,14 @@ __global__ __launch_bounds__(256) void k_conv_v(FrameDesc d, const uint8_t* __re
     }
     if (x >= d.W) return;
     int64_t nun = 0;
+    double av[2 * kCvT];   // A of this thread's outputs, all loaded before back (its own plane) is written
+    if (!FIRST) {
+#pragma unroll
+        for (int q = 0; q < 2 * kCvT; ++q) {
+            const int r = g * 2 * kCvT + q;
+            av[q] = r < nr ? (double)outA[(int64_t)(y0 + r) * d.W + x] : 0.0;
+        }
+    }
 #pragma unroll
     for (int q = 0; q < 2 * kCvT; ++q) {
         const int r = g * 2 * kCvT + q;
@@ -292,7 +380,14 @@ __global__ __launch_bounds__(256) void k_conv_v(FrameDesc d, const uint8_t* __re
         const int y = y0 + r;
         const int64_t o = (int64_t)y * d.W + x;
         if (FIRST) {
-            outA[o] = (Real)s0[q];
+            const Real ar = (Real)s0[q];
+            if (late) {
+                outA[o] = ar;   // finished by the fill round
+            } else {
+                const double b = (double)ar + 0.0;   // B = A + (K corr G), the latter an exact +0 here
+                back[o] = (Real)b;
+                rms[o] = cv_noise<Real>(b, a);
+            }
             if (fill) {
                 float v;
                 const bool ok = cv_valid(d, mask, x, y, sat, v);
@@ -304,12 +399,9 @@ __global__ __launch_bounds__(256) void k_conv_v(FrameDesc d, const uint8_t* __re
                 outG[o] = (Real)gv;
             }
         } else {
-            const double b = (double)outA[o] + s0[q];
+            const double b = av[q] + s0[q];
             back[o] = (Real)b;
-            const double sky = b > 0.0 ? b : 0.0;
-            const double var_e = fma((double)a.gain, sky, fma((double)a.read_noise, (double)a.read_noise,
-                                                                (double)a.dark * (double)a.exptime));
-            rms[o] = (Real)sqrt(var_e / ((double)a.gain * (double)a.gain));
+            rms[o] = cv_noise<Real>(b, a);
         }
     }
     if (FIRST && nun) atomicAdd((unsigned long long*)unfilled, (unsigned long long)nun);
@@ -349,11 +441,12 @@ static hipError_t conv_frame_t(const FrameDesc& d, const uint8_t* mask, float sa
     k_conv_clear<<<1, 64, 0, s>>>(flag, unfilled);
     // 1. horizontal: vI -> hA, invalid-pixel flags
     k_conv_h<Real, true><<<gh, kCvThreads, lh, s>>>(d, mask, sat, nullptr, hA, inval, a, flag);
-    // 2. vertical: A -> back (kept until step 4); C and the fill image G in flagged tiles
-    k_conv_v<Real, true><<<gv, 256, lv, s>>>(d, mask, sat, hA, back, G, nullptr, nullptr, inval, a, flag, unfilled);
+    // 2. vertical: A -> back (B and R where step 4 adds nothing); C and the
+    //    fill image G in flagged tiles
+    k_conv_v<Real, true><<<gv, 256, lv, s>>>(d, mask, sat, hA, back, G, back, rms, inval, a, flag, unfilled);
     // 3. horizontal pass of G into hA, rows within reach of an invalid pixel
     k_conv_h<Real, false><<<gh, kCvThreads, lh, s>>>(d, mask, sat, G, hA, inval, a, flag);
-    // 4. B = A + vertical pass of it; noise map
+    // 4. B = A + vertical pass of it and the noise map, in the tiles it reaches
     k_conv_v<Real, false><<<gv, 256, lv, s>>>(d, mask, sat, hA, back, nullptr, back, rms, inval, a, flag, nullptr);
     return hipGetLastError();
 }
