@@ -124,6 +124,7 @@ constexpr int kConvTapsPad = (kMaxConvTaps + 7) / 8 * 8;
 struct CvArgs {
     int32_t lx, ly;
     float gain, read_noise, dark, exptime;
+    double nm_c0, nm_c1;   // R^2 = nm_c1 max(B, 0) + nm_c0 (FP32 maps): 1 / g and (rn^2 + dark t) / g^2
     double kx[kConvTapsPad], ky[kConvTapsPad];
 };
 
@@ -157,10 +158,11 @@ void launch_growth_table(const GrowArgs& a, const GrowTab& t, hipStream_t s);
 hipError_t launch_growth(const FrameDesc* desc, const FrameDesc* one, const GrowArgs& a, const GrowTab& t,
                          const GrowOut& g, int blocks, int waves, bool f64, hipStream_t s);
 size_t growth_lds_bytes(int nfull, int ncut, int side, int nixmax, int want_var, bool f64, int waves);
-// inval: (height x ceil(width / 64)) bytes of per-row band flags
+// inval: (height x ceil(width / 64)) bytes of per-row band flags; late: a
+// byte per 64 x 64 tile
 hipError_t launch_conv_frame(const FrameDesc& d, const uint8_t* mask, float sat, const CvArgs& a, void* hA,
-                             void* inval, void* G, void* back, void* rms, int* flag, int64_t* unfilled, bool f64,
-                             hipStream_t s);
+                             void* inval, uint8_t* late, void* G, void* back, void* rms, int* flag,
+                             int64_t* unfilled, bool f64, hipStream_t s);
 void launch_bkg_map(const FrameDesc& d, double* bmap, double* rmap, bool f64, hipStream_t s);
 void launch_write_desc(const DescChunk& c, FrameDesc* table, hipStream_t s);
 void launch_det_setup(const DescChunk& c, FrameDesc* table, const DetArgsIn& in, DetArgs* out, uint32_t* counters,

@@ -288,10 +288,14 @@ __device__ __forceinline__ void cv_hbits(const uint64_t* bits, const double* k, 
     }
 }
 
-// noise map of a dark-subtracted frame in ADU from B
+// noise map of a dark-subtracted frame in ADU from B.  FP64 maps: the
+// formula as written, in FP64.  FP32 maps: R^2 = max(B, 0) / g + (rn^2 +
+// dark t) / g^2 from the host's FP64 constants, rounded to FP32, and its
+// correctly rounded FP32 square root (within 1.25 ulp of R).
 template <typename Real>
 __device__ __forceinline__ Real cv_noise(double b, const CvArgs& a) {
     const double sky = b > 0.0 ? b : 0.0;
+    if (sizeof(Real) == 4) return (Real)sqrtf((float)fma(a.nm_c1, sky, a.nm_c0));
     const double var_e =
         fma((double)a.gain, sky, fma((double)a.read_noise, (double)a.read_noise, (double)a.dark * (double)a.exptime));
     return (Real)sqrt(var_e / ((double)a.gain * (double)a.gain));
@@ -303,8 +307,9 @@ __device__ __forceinline__ Real cv_noise(double b, const CvArgs& a) {
 template <typename Real, bool FIRST>
 __global__ __launch_bounds__(256) void k_conv_v(FrameDesc d, const uint8_t* __restrict__ mask, float sat,
                                                 const Real* __restrict__ in0, Real* outA, Real* outG, Real* back,
-                                                Real* rms, const uint8_t* __restrict__ inval, CvArgs a,
-                                                int* __restrict__ flag, int64_t* __restrict__ unfilled) {
+                                                Real* rms, const uint8_t* __restrict__ inval,
+                                                uint8_t* __restrict__ late_tile, CvArgs a, int* __restrict__ flag,
+                                                int64_t* __restrict__ unfilled) {
     extern __shared__ __align__(16) unsigned char cv_dyn[];
     __shared__ uint8_t act[kCvRows + kConvTapsPad];
     const int np = cv_pad(a.ly), rows = kCvRows + np;
@@ -320,6 +325,8 @@ __global__ __launch_bounds__(256) void k_conv_v(FrameDesc d, const uint8_t* __re
     // flags of the first horizontal pass, so the first vertical pass already
     // finishes B and R where it is not.
     bool late = false;
+    const int64_t tile = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (!FIRST && late_tile[tile] == 0) return;   // B and R were written by the first vertical pass
     if (flag[0] != 0) {
         int lo, hi;
         cv_reach(xc0 - hx, min(xc0 + kCvCols, d.W) - 1 + hx, d.W, lo, hi);
@@ -333,12 +340,12 @@ __global__ __launch_bounds__(256) void k_conv_v(FrameDesc d, const uint8_t* __re
         }
         late = __syncthreads_or(mine);
     }
+    if (FIRST && threadIdx.x == 0) late_tile[tile] = late;
     bool fill;   // FIRST: the tile holds an invalid pixel
     if (FIRST) {
         const bool mine = (int)threadIdx.x < nr && inval[(int64_t)(y0 + threadIdx.x) * nb + blockIdx.x] != 0;
         fill = __syncthreads_or(mine);
     } else {
-        if (!late) return;   // B and R were written by the first vertical pass
         fill = true;
     }
     cv_stage(in0, d, xc0, y0, hy, nrows, rows, FIRST ? nullptr : act, band);
@@ -421,8 +428,8 @@ size_t conv_v_lds(int ly, bool f64) {
 
 template <typename Real>
 static hipError_t conv_frame_t(const FrameDesc& d, const uint8_t* mask, float sat, const CvArgs& a, Real* hA,
-                               uint8_t* inval, Real* G, Real* back, Real* rms, int* flag, int64_t* unfilled,
-                               hipStream_t s) {
+                               uint8_t* inval, uint8_t* late, Real* G, Real* back, Real* rms, int* flag,
+                               int64_t* unfilled, hipStream_t s) {
     const size_t lh = conv_h_lds(a.lx, sizeof(Real) == 8), lv = conv_v_lds(a.ly, sizeof(Real) == 8);
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void*)k_conv_h<Real, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -443,22 +450,23 @@ static hipError_t conv_frame_t(const FrameDesc& d, const uint8_t* mask, float sa
     k_conv_h<Real, true><<<gh, kCvThreads, lh, s>>>(d, mask, sat, nullptr, hA, inval, a, flag);
     // 2. vertical: A -> back (B and R where step 4 adds nothing); C and the
     //    fill image G in flagged tiles
-    k_conv_v<Real, true><<<gv, 256, lv, s>>>(d, mask, sat, hA, back, G, back, rms, inval, a, flag, unfilled);
+    k_conv_v<Real, true><<<gv, 256, lv, s>>>(d, mask, sat, hA, back, G, back, rms, inval, late, a, flag, unfilled);
     // 3. horizontal pass of G into hA, rows within reach of an invalid pixel
     k_conv_h<Real, false><<<gh, kCvThreads, lh, s>>>(d, mask, sat, G, hA, inval, a, flag);
     // 4. B = A + vertical pass of it and the noise map, in the tiles it reaches
-    k_conv_v<Real, false><<<gv, 256, lv, s>>>(d, mask, sat, hA, back, nullptr, back, rms, inval, a, flag, nullptr);
+    k_conv_v<Real, false><<<gv, 256, lv, s>>>(d, mask, sat, hA, back, nullptr, back, rms, inval, late, a, flag,
+                                              nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_conv_frame(const FrameDesc& d, const uint8_t* mask, float sat, const CvArgs& a, void* hA,
-                             void* inval, void* G, void* back, void* rms, int* flag, int64_t* unfilled, bool f64,
-                             hipStream_t s) {
+                             void* inval, uint8_t* late, void* G, void* back, void* rms, int* flag,
+                             int64_t* unfilled, bool f64, hipStream_t s) {
     if (f64)
-        return conv_frame_t<double>(d, mask, sat, a, (double*)hA, (uint8_t*)inval, (double*)G, (double*)back,
+        return conv_frame_t<double>(d, mask, sat, a, (double*)hA, (uint8_t*)inval, late, (double*)G, (double*)back,
                                     (double*)rms, flag, unfilled, s);
-    return conv_frame_t<float>(d, mask, sat, a, (float*)hA, (uint8_t*)inval, (float*)G, (float*)back, (float*)rms,
-                               flag, unfilled, s);
+    return conv_frame_t<float>(d, mask, sat, a, (float*)hA, (uint8_t*)inval, late, (float*)G, (float*)back,
+                               (float*)rms, flag, unfilled, s);
 }
 
 }  // namespace gpk

@@ -1231,20 +1231,22 @@ gp_status check_conv(const gp_frame* frames, int32_t nframes, const gp_conv_para
 // flag word; two working-precision planes (hA / hG, G) and the per-row band
 // flags of the largest frame
 struct ConvWs {
-    size_t plane, flags;
+    size_t plane, flags, tiles;
 };
 ConvWs conv_ws_parts(const gp_frame* frames, int32_t nframes, const gp_conv_params* cp) {
-    int64_t mx = 1, mf = 1;
+    int64_t mx = 1, mf = 1, mt = 1;
     for (int f = 0; f < nframes; ++f) {
+        const int64_t bx = (frames[f].width + 63) / 64, by = (frames[f].height + 63) / 64;
         mx = std::max<int64_t>(mx, (int64_t)frames[f].width * frames[f].height);
-        mf = std::max<int64_t>(mf, (int64_t)frames[f].height * ((frames[f].width + 63) / 64));
+        mf = std::max<int64_t>(mf, (int64_t)frames[f].height * bx);
+        mt = std::max<int64_t>(mt, bx * by);
     }
     const size_t real = cp->precision == GP_PREC_F64 ? 8 : 4;
-    return {align256(real * (size_t)mx), align256((size_t)mf)};
+    return {align256(real * (size_t)mx), align256((size_t)mf), align256((size_t)mt)};
 }
 size_t conv_ws_bytes(const gp_frame* frames, int32_t nframes, const gp_conv_params* cp) {
     const ConvWs w = conv_ws_parts(frames, nframes, cp);
-    return 256 + 2 * w.plane + w.flags;
+    return 256 + 2 * w.plane + w.flags + w.tiles;
 }
 }  // namespace
 
@@ -1279,6 +1281,7 @@ extern "C" gp_status gp_background_conv(gp_ctx* ctx, const gp_frame* frames, int
     void* hA = W + 256;
     void* G = W + 256 + wp.plane;
     void* inval = W + 256 + 2 * wp.plane;
+    uint8_t* late = (uint8_t*)W + 256 + 2 * wp.plane + wp.flags;
     CvArgs a{};
     a.lx = cp->lx;
     a.ly = cp->ly;
@@ -1286,6 +1289,9 @@ extern "C" gp_status gp_background_conv(gp_ctx* ctx, const gp_frame* frames, int
     a.read_noise = cp->read_noise;
     a.dark = cp->dark_current;
     a.exptime = cp->exptime;
+    a.nm_c1 = 1.0 / (double)cp->gain;
+    a.nm_c0 = ((double)cp->read_noise * (double)cp->read_noise + (double)cp->dark_current * (double)cp->exptime) /
+              ((double)cp->gain * (double)cp->gain);
     // unit-sum taps: the FP64 sum in tap order, then each tap divided by it
     double sx = 0.0, sy = 0.0;
     for (int i = 0; i < cp->lx; ++i) sx += (double)cp->kx[i];
@@ -1302,8 +1308,8 @@ extern "C" gp_status gp_background_conv(gp_ctx* ctx, const gp_frame* frames, int
         d.W = frames[f].width;
         d.H = frames[f].height;
         d.dtype = frames[f].dtype;
-        const hipError_t e = launch_conv_frame(d, masks ? masks[f] : nullptr, cp->sat_level, a, hA, inval, G,
-                                               back[f], rms[f], flag, unfilled + f, f64, s);
+        const hipError_t e = launch_conv_frame(d, masks ? masks[f] : nullptr, cp->sat_level, a, hA, inval, late,
+                                               G, back[f], rms[f], flag, unfilled + f, f64, s);
         if (e != hipSuccess) return fail(GP_ERR_HIP, "background convolution: %s", hipGetErrorString(e));
     }
     return GP_OK;
