@@ -247,8 +247,10 @@ gp_status gp_background_map(gp_ctx* ctx, const gp_frame* frames, int32_t nframes
  * float (GP_PREC_F32) or double (GP_PREC_F64).  unfilled: DEVICE int64
  * [nframes], the invalid pixels with no valid pixel under the kernel (filled
  * with 0).  Sums accumulate in FP64; intermediates are stored in the working
- * precision.  Workspace: gp_background_conv_ws bytes (the frames share it, so
- * they are processed one after the other on the stream). */
+ * precision.  Workspace: gp_background_conv_ws bytes, which holds two
+ * working-precision planes of every frame (8 bytes per pixel of the batch in
+ * FP32, 16 in FP64) plus small per-frame tables: the four passes each run
+ * once over all the frames. */
 typedef struct gp_conv_params {
     const float* kx;
     int32_t lx;

@@ -123,7 +123,7 @@ constexpr int kMaxConvTaps = 129;
 constexpr int kConvTapsPad = (kMaxConvTaps + 7) / 8 * 8;
 struct CvArgs {
     int32_t lx, ly;
-    float gain, read_noise, dark, exptime;
+    float sat, gain, read_noise, dark, exptime;
     double nm_c0, nm_c1;   // R^2 = nm_c1 max(B, 0) + nm_c0 (FP32 maps): 1 / g and (rn^2 + dark t) / g^2
     double kx[kConvTapsPad], ky[kConvTapsPad];
 };
@@ -158,11 +158,40 @@ void launch_growth_table(const GrowArgs& a, const GrowTab& t, hipStream_t s);
 hipError_t launch_growth(const FrameDesc* desc, const FrameDesc* one, const GrowArgs& a, const GrowTab& t,
                          const GrowOut& g, int blocks, int waves, bool f64, hipStream_t s);
 size_t growth_lds_bytes(int nfull, int ncut, int side, int nixmax, int want_var, bool f64, int waves);
-// inval: (height x ceil(width / 64)) bytes of per-row band flags; late: a
-// byte per 64 x 64 tile
-hipError_t launch_conv_frame(const FrameDesc& d, const uint8_t* mask, float sat, const CvArgs& a, void* hA,
-                             void* inval, uint8_t* late, void* G, void* back, void* rms, int* flag,
-                             int64_t* unfilled, bool f64, hipStream_t s);
+// One frame of a convolution-background call.  Every frame has its own
+// slices of the working planes (hA / hG and G: element offset plane), of the
+// per-row band flags (height x ceil(width / 64) bytes at flags) and of the
+// per-tile fill-round flags (one byte per 64 x 64 tile at tiles).
+struct CvFrame {
+    const void* data;
+    const uint8_t* mask;
+    void* back;
+    void* rms;
+    int64_t pitch;
+    int64_t plane, flags, tiles;
+    int32_t W, H, dtype, pad;
+};
+constexpr int kCvChunk = 16;   // frame records written per set-up launch
+constexpr int kCvSegPx = 2048; // outputs per horizontal workgroup (one row segment)
+constexpr int kCvTilePx = 64;  // side of a vertical workgroup's tile and width of a flag band
+struct CvChunk {
+    int32_t first, count;
+    CvFrame f[kCvChunk];
+    int32_t hbase[kCvChunk], vbase[kCvChunk];   // first horizontal / vertical workgroup of each frame
+};
+// device memory of a call: the frame table, the workgroup bases, a flag per
+// frame, the two planes, the band and tile flags
+struct CvWork {
+    CvFrame* tab;
+    int32_t *hbase, *vbase, *fflag;
+    void *hA, *G;
+    uint8_t *flags, *tiles;
+    int64_t* unfilled;
+};
+// chunks: the frame records in kCvChunk groups; htotal / vtotal: workgroups
+// of the horizontal / vertical passes over all frames
+hipError_t launch_conv(const CvChunk* chunks, int nchunks, int nframes, int htotal, int vtotal, const CvArgs& a,
+                       const CvWork& w, bool f64, hipStream_t s);
 void launch_bkg_map(const FrameDesc& d, double* bmap, double* rmap, bool f64, hipStream_t s);
 void launch_write_desc(const DescChunk& c, FrameDesc* table, hipStream_t s);
 void launch_det_setup(const DescChunk& c, FrameDesc* table, const DetArgsIn& in, DetArgs* out, uint32_t* counters,

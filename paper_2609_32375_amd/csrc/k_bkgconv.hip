@@ -38,6 +38,31 @@ constexpr int kCvThreads = 256;
 constexpr int kCvSeg = kCvThreads * kCvT;   // outputs per horizontal workgroup
 constexpr int kCvCols = 64;                 // columns per vertical workgroup
 constexpr int kCvRows = 64;                 // output rows per vertical workgroup (4 groups x 2 blocks)
+static_assert(kCvSeg == kCvSegPx && kCvCols == kCvTilePx && kCvRows == kCvTilePx, "workgroup shapes");
+
+// the frame of a flattened workgroup index: base[] ascending from 0, so the
+// bases <= item form a prefix (one ballot per 64 frames; all lanes active)
+__device__ __forceinline__ int cv_frame_of(const int32_t* __restrict__ base, int n, int item) {
+    const int lane = threadIdx.x & 63;
+    int f = -1;
+    for (int i0 = 0; i0 < n; i0 += 64) {
+        const int i = i0 + lane;
+        const uint64_t m = __ballot(i < n && base[i] <= item);
+        f += __popcll(m);
+        if (m != ~0ull) break;
+    }
+    return f;
+}
+
+__device__ __forceinline__ FrameDesc cv_desc(const CvFrame& F) {
+    FrameDesc d{};
+    d.data = F.data;
+    d.pitch = F.pitch;
+    d.W = F.W;
+    d.H = F.H;
+    d.dtype = F.dtype;
+    return d;
+}
 
 // 64-bit words of validity bits per staged row in a tile: columns
 // xc0 - hx + 0 .. 63 + padded taps + 7
@@ -160,16 +185,25 @@ __device__ __forceinline__ void cv_stage_h(const FrameDesc& d, const uint8_t* __
 // FIRST: vI from the frame, and the invalid-pixel flags of the segment's
 // bands; else G from src in the rows whose reach holds an invalid pixel
 template <typename Real, bool FIRST>
-__global__ __launch_bounds__(kCvThreads) void k_conv_h(FrameDesc d, const uint8_t* __restrict__ mask, float sat,
-                                                       const Real* __restrict__ src, Real* __restrict__ out,
-                                                       uint8_t* __restrict__ inval, CvArgs a,
-                                                       int* __restrict__ flag) {
+__global__ __launch_bounds__(kCvThreads) void k_conv_h(CvWork w, int nframes, int total, CvArgs a) {
     extern __shared__ __align__(16) unsigned char cv_dyn[];
     __shared__ int bfl[kCvSeg / kCvCols];
+    const int item = xcd_item(blockIdx.x, (total + kXcds - 1) / kXcds);
+    if (item >= total) return;
+    const int f = cv_frame_of(w.hbase, nframes, item);
+    int* flag = w.fflag + f;
     if (!FIRST && flag[0] == 0) return;   // nothing to fill in this frame
+    const CvFrame F = w.tab[f];
+    const FrameDesc d = cv_desc(F);
+    const uint8_t* mask = F.mask;
+    const float sat = a.sat;
+    const Real* src = (const Real*)w.G + F.plane;
+    Real* out = (Real*)w.hA + F.plane;
+    uint8_t* inval = w.flags + F.flags;
+    const int nsegs = (d.W + kCvSeg - 1) / kCvSeg, local = item - w.hbase[f];
     const int np = cv_pad(a.lx), span = kCvSeg + np;
     Real* s0 = reinterpret_cast<Real*>(cv_dyn);
-    const int y = blockIdx.y, x0 = blockIdx.x * kCvSeg, hx = a.lx >> 1;
+    const int y = local / nsegs, x0 = (local - y * nsegs) * kCvSeg, hx = a.lx >> 1;
     const int nb = (d.W + kCvCols - 1) / kCvCols;
     const int nseg = min(kCvSeg, d.W - x0);
     const int n = nseg + a.lx - 1;   // staged values any written output reads
@@ -305,16 +339,31 @@ __device__ __forceinline__ Real cv_noise(double b, const CvArgs& a) {
 // an invalid pixel, C, the fill image G and the unfilled count.  Else, in the
 // tiles the fill round reaches: B = A + (K corr G) and the noise map.
 template <typename Real, bool FIRST>
-__global__ __launch_bounds__(256) void k_conv_v(FrameDesc d, const uint8_t* __restrict__ mask, float sat,
-                                                const Real* __restrict__ in0, Real* outA, Real* outG, Real* back,
-                                                Real* rms, const uint8_t* __restrict__ inval,
-                                                uint8_t* __restrict__ late_tile, CvArgs a, int* __restrict__ flag,
-                                                int64_t* __restrict__ unfilled) {
+__global__ __launch_bounds__(256) void k_conv_v(CvWork w, int nframes, int total, CvArgs a) {
     extern __shared__ __align__(16) unsigned char cv_dyn[];
     __shared__ uint8_t act[kCvRows + kConvTapsPad];
+    const int item = xcd_item(blockIdx.x, (total + kXcds - 1) / kXcds);
+    if (item >= total) return;
+    const int f = cv_frame_of(w.vbase, nframes, item);
+    const int local = item - w.vbase[f];
+    const CvFrame F = w.tab[f];
+    uint8_t* late_tile = w.tiles + F.tiles;
+    if (!FIRST && late_tile[local] == 0) return;   // B and R were written by the first vertical pass
+    const FrameDesc d = cv_desc(F);
+    const uint8_t* mask = F.mask;
+    const float sat = a.sat;
+    const Real* in0 = (const Real*)w.hA + F.plane;
+    Real* outG = (Real*)w.G + F.plane;
+    Real* back = (Real*)F.back;   // also A until the fill round adds to it
+    Real* outA = back;
+    Real* rms = (Real*)F.rms;
+    const uint8_t* inval = w.flags + F.flags;
+    int* flag = w.fflag + f;
+    int64_t* unfilled = w.unfilled + f;
+    const int ntx = (d.W + kCvCols - 1) / kCvCols, ty = local / ntx, tx = local - ty * ntx;
     const int np = cv_pad(a.ly), rows = kCvRows + np;
     Real* band = reinterpret_cast<Real*>(cv_dyn);
-    const int xc0 = blockIdx.x * kCvCols, y0 = blockIdx.y * kCvRows, hy = a.ly >> 1, hx = a.lx >> 1;
+    const int xc0 = tx * kCvCols, y0 = ty * kCvRows, hy = a.ly >> 1, hx = a.lx >> 1;
     const int nr = min(kCvRows, d.H - y0), nrows = nr + a.ly - 1;
     const int nb = (d.W + kCvCols - 1) / kCvCols;
     const int c = threadIdx.x & (kCvCols - 1), g = threadIdx.x / kCvCols;
@@ -325,8 +374,6 @@ __global__ __launch_bounds__(256) void k_conv_v(FrameDesc d, const uint8_t* __re
     // flags of the first horizontal pass, so the first vertical pass already
     // finishes B and R where it is not.
     bool late = false;
-    const int64_t tile = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    if (!FIRST && late_tile[tile] == 0) return;   // B and R were written by the first vertical pass
     if (flag[0] != 0) {
         int lo, hi;
         cv_reach(xc0 - hx, min(xc0 + kCvCols, d.W) - 1 + hx, d.W, lo, hi);
@@ -340,10 +387,10 @@ __global__ __launch_bounds__(256) void k_conv_v(FrameDesc d, const uint8_t* __re
         }
         late = __syncthreads_or(mine);
     }
-    if (FIRST && threadIdx.x == 0) late_tile[tile] = late;
+    if (FIRST && threadIdx.x == 0) late_tile[local] = late;
     bool fill;   // FIRST: the tile holds an invalid pixel
     if (FIRST) {
-        const bool mine = (int)threadIdx.x < nr && inval[(int64_t)(y0 + threadIdx.x) * nb + blockIdx.x] != 0;
+        const bool mine = (int)threadIdx.x < nr && inval[(int64_t)(y0 + threadIdx.x) * nb + tx] != 0;
         fill = __syncthreads_or(mine);
     } else {
         fill = true;
@@ -414,10 +461,16 @@ __global__ __launch_bounds__(256) void k_conv_v(FrameDesc d, const uint8_t* __re
     if (FIRST && nun) atomicAdd((unsigned long long*)unfilled, (unsigned long long)nun);
 }
 
-__global__ void k_conv_clear(int* flag, int64_t* unfilled) {
-    if (threadIdx.x == 0) {
-        flag[0] = 0;
-        if (unfilled) unfilled[0] = 0;
+// the frame records and workgroup bases of one chunk; the per-frame flags
+// and unfilled counts start at zero
+__global__ void k_conv_setup(CvChunk c, CvWork w) {
+    const int i = threadIdx.x;
+    if (i < c.count) {
+        w.tab[c.first + i] = c.f[i];
+        w.hbase[c.first + i] = c.hbase[i];
+        w.vbase[c.first + i] = c.vbase[i];
+        w.fflag[c.first + i] = 0;
+        w.unfilled[c.first + i] = 0;
     }
 }
 
@@ -427,46 +480,38 @@ size_t conv_v_lds(int ly, bool f64) {
 }
 
 template <typename Real>
-static hipError_t conv_frame_t(const FrameDesc& d, const uint8_t* mask, float sat, const CvArgs& a, Real* hA,
-                               uint8_t* inval, uint8_t* late, Real* G, Real* back, Real* rms, int* flag,
-                               int64_t* unfilled, hipStream_t s) {
+static hipError_t conv_t(int nframes, int htotal, int vtotal, const CvArgs& a, const CvWork& w, hipStream_t s) {
     const size_t lh = conv_h_lds(a.lx, sizeof(Real) == 8), lv = conv_v_lds(a.ly, sizeof(Real) == 8);
     hipError_t e;
-    if ((e = hipFuncSetAttribute((const void*)k_conv_h<Real, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lh)) != hipSuccess)
-        return e;
-    if ((e = hipFuncSetAttribute((const void*)k_conv_h<Real, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lh)) != hipSuccess)
-        return e;
-    if ((e = hipFuncSetAttribute((const void*)k_conv_v<Real, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lv)) != hipSuccess)
-        return e;
-    if ((e = hipFuncSetAttribute((const void*)k_conv_v<Real, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lv)) != hipSuccess)
-        return e;
-    const dim3 gh((d.W + kCvSeg - 1) / kCvSeg, d.H), gv((d.W + kCvCols - 1) / kCvCols, (d.H + kCvRows - 1) / kCvRows);
-    k_conv_clear<<<1, 64, 0, s>>>(flag, unfilled);
+    const void* hk[2] = {(const void*)k_conv_h<Real, true>, (const void*)k_conv_h<Real, false>};
+    const void* vk[2] = {(const void*)k_conv_v<Real, true>, (const void*)k_conv_v<Real, false>};
+    for (int i = 0; i < 2; ++i) {
+        if ((e = hipFuncSetAttribute(hk[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lh)) != hipSuccess)
+            return e;
+        if ((e = hipFuncSetAttribute(vk[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lv)) != hipSuccess)
+            return e;
+    }
+    // grids of whole XCD chunks over every frame's workgroups
+    const unsigned gh = (unsigned)((htotal + kXcds - 1) / kXcds) * kXcds;
+    const unsigned gv = (unsigned)((vtotal + kXcds - 1) / kXcds) * kXcds;
     // 1. horizontal: vI -> hA, invalid-pixel flags
-    k_conv_h<Real, true><<<gh, kCvThreads, lh, s>>>(d, mask, sat, nullptr, hA, inval, a, flag);
+    k_conv_h<Real, true><<<gh, kCvThreads, lh, s>>>(w, nframes, htotal, a);
     // 2. vertical: A -> back (B and R where step 4 adds nothing); C and the
     //    fill image G in flagged tiles
-    k_conv_v<Real, true><<<gv, 256, lv, s>>>(d, mask, sat, hA, back, G, back, rms, inval, late, a, flag, unfilled);
+    k_conv_v<Real, true><<<gv, 256, lv, s>>>(w, nframes, vtotal, a);
     // 3. horizontal pass of G into hA, rows within reach of an invalid pixel
-    k_conv_h<Real, false><<<gh, kCvThreads, lh, s>>>(d, mask, sat, G, hA, inval, a, flag);
+    k_conv_h<Real, false><<<gh, kCvThreads, lh, s>>>(w, nframes, htotal, a);
     // 4. B = A + vertical pass of it and the noise map, in the tiles it reaches
-    k_conv_v<Real, false><<<gv, 256, lv, s>>>(d, mask, sat, hA, back, nullptr, back, rms, inval, late, a, flag,
-                                              nullptr);
+    k_conv_v<Real, false><<<gv, 256, lv, s>>>(w, nframes, vtotal, a);
     return hipGetLastError();
 }
 
-hipError_t launch_conv_frame(const FrameDesc& d, const uint8_t* mask, float sat, const CvArgs& a, void* hA,
-                             void* inval, uint8_t* late, void* G, void* back, void* rms, int* flag,
-                             int64_t* unfilled, bool f64, hipStream_t s) {
-    if (f64)
-        return conv_frame_t<double>(d, mask, sat, a, (double*)hA, (uint8_t*)inval, late, (double*)G, (double*)back,
-                                    (double*)rms, flag, unfilled, s);
-    return conv_frame_t<float>(d, mask, sat, a, (float*)hA, (uint8_t*)inval, late, (float*)G, (float*)back,
-                               (float*)rms, flag, unfilled, s);
+hipError_t launch_conv(const CvChunk* chunks, int nchunks, int nframes, int htotal, int vtotal, const CvArgs& a,
+                       const CvWork& w, bool f64, hipStream_t s) {
+    for (int i = 0; i < nchunks; ++i) k_conv_setup<<<1, 64, 0, s>>>(chunks[i], w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return f64 ? conv_t<double>(nframes, htotal, vtotal, a, w, s) : conv_t<float>(nframes, htotal, vtotal, a, w, s);
 }
 
 }  // namespace gpk

@@ -1228,25 +1228,47 @@ gp_status check_conv(const gp_frame* frames, int32_t nframes, const gp_conv_para
     return GP_OK;
 }
 
-// flag word; two working-precision planes (hA / hG, G) and the per-row band
-// flags of the largest frame
-struct ConvWs {
-    size_t plane, flags, tiles;
+// Workspace of a convolution-background call: the frame table, the
+// workgroup bases and a flag per frame, then every frame's slice of the two
+// working-precision planes (hA / hG and G), of the per-row band flags and of
+// the per-tile flags.
+struct ConvPlan {
+    size_t tab, hb, vb, ff, hA, G, flags, tiles, total;
+    std::vector<int64_t> plane, fl, tl;
+    std::vector<int32_t> hbase, vbase;
+    int64_t htotal = 0, vtotal = 0;
 };
-ConvWs conv_ws_parts(const gp_frame* frames, int32_t nframes, const gp_conv_params* cp) {
-    int64_t mx = 1, mf = 1, mt = 1;
-    for (int f = 0; f < nframes; ++f) {
-        const int64_t bx = (frames[f].width + 63) / 64, by = (frames[f].height + 63) / 64;
-        mx = std::max<int64_t>(mx, (int64_t)frames[f].width * frames[f].height);
-        mf = std::max<int64_t>(mf, (int64_t)frames[f].height * bx);
-        mt = std::max<int64_t>(mt, bx * by);
-    }
+ConvPlan conv_plan(const gp_frame* frames, int32_t nframes, const gp_conv_params* cp) {
+    ConvPlan p;
     const size_t real = cp->precision == GP_PREC_F64 ? 8 : 4;
-    return {align256(real * (size_t)mx), align256((size_t)mf), align256((size_t)mt)};
+    int64_t pe = 0, fb = 0, tb = 0;
+    for (int f = 0; f < nframes; ++f) {
+        const int64_t W = frames[f].width, H = frames[f].height;
+        const int64_t bx = (W + kCvTilePx - 1) / kCvTilePx, by = (H + kCvTilePx - 1) / kCvTilePx;
+        p.plane.push_back(pe);
+        pe += (W * H + 63) / 64 * 64;
+        p.fl.push_back(fb);
+        fb += (H * bx + 255) / 256 * 256;
+        p.tl.push_back(tb);
+        tb += (bx * by + 255) / 256 * 256;
+        p.hbase.push_back((int32_t)p.htotal);
+        p.htotal += (W + kCvSegPx - 1) / kCvSegPx * H;
+        p.vbase.push_back((int32_t)p.vtotal);
+        p.vtotal += bx * by;
+    }
+    p.tab = 256;
+    p.hb = p.tab + align256(sizeof(CvFrame) * (size_t)nframes);
+    p.vb = p.hb + align256(4 * (size_t)nframes);
+    p.ff = p.vb + align256(4 * (size_t)nframes);
+    p.hA = p.ff + align256(4 * (size_t)nframes);
+    p.G = p.hA + align256(real * (size_t)pe);
+    p.flags = p.G + align256(real * (size_t)pe);
+    p.tiles = p.flags + align256((size_t)fb);
+    p.total = p.tiles + align256((size_t)tb);
+    return p;
 }
 size_t conv_ws_bytes(const gp_frame* frames, int32_t nframes, const gp_conv_params* cp) {
-    const ConvWs w = conv_ws_parts(frames, nframes, cp);
-    return 256 + 2 * w.plane + w.flags + w.tiles;
+    return conv_plan(frames, nframes, cp).total;
 }
 }  // namespace
 
@@ -1275,13 +1297,42 @@ extern "C" gp_status gp_background_conv(gp_ctx* ctx, const gp_frame* frames, int
     if (ws_bytes < need)
         return fail(GP_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
     const bool f64 = cp->precision == GP_PREC_F64;
-    const ConvWs wp = conv_ws_parts(frames, nframes, cp);
+    const ConvPlan P = conv_plan(frames, nframes, cp);
+    if (P.htotal >= INT32_MAX - 8 || P.vtotal >= INT32_MAX - 8)
+        return fail(GP_ERR_UNSUPPORTED, "too many workgroups for one call (%lld, %lld)", (long long)P.htotal,
+                    (long long)P.vtotal);
     char* W = (char*)ws;
-    int* flag = (int*)W;
-    void* hA = W + 256;
-    void* G = W + 256 + wp.plane;
-    void* inval = W + 256 + 2 * wp.plane;
-    uint8_t* late = (uint8_t*)W + 256 + 2 * wp.plane + wp.flags;
+    CvWork w{};
+    w.tab = (CvFrame*)(W + P.tab);
+    w.hbase = (int32_t*)(W + P.hb);
+    w.vbase = (int32_t*)(W + P.vb);
+    w.fflag = (int32_t*)(W + P.ff);
+    w.hA = W + P.hA;
+    w.G = W + P.G;
+    w.flags = (uint8_t*)(W + P.flags);
+    w.tiles = (uint8_t*)(W + P.tiles);
+    w.unfilled = unfilled;
+    std::vector<CvChunk> chunks((nframes + kCvChunk - 1) / kCvChunk);
+    for (int f = 0; f < nframes; ++f) {
+        CvChunk& c = chunks[f / kCvChunk];
+        if (c.count == 0) c.first = f;
+        CvFrame& r = c.f[c.count];
+        r = CvFrame{};
+        r.data = frames[f].data;
+        r.mask = masks ? masks[f] : nullptr;
+        r.back = back[f];
+        r.rms = rms[f];
+        r.pitch = frames[f].pitch;
+        r.plane = P.plane[f];
+        r.flags = P.fl[f];
+        r.tiles = P.tl[f];
+        r.W = frames[f].width;
+        r.H = frames[f].height;
+        r.dtype = frames[f].dtype;
+        c.hbase[c.count] = P.hbase[f];
+        c.vbase[c.count] = P.vbase[f];
+        ++c.count;
+    }
     CvArgs a{};
     a.lx = cp->lx;
     a.ly = cp->ly;
@@ -1289,6 +1340,7 @@ extern "C" gp_status gp_background_conv(gp_ctx* ctx, const gp_frame* frames, int
     a.read_noise = cp->read_noise;
     a.dark = cp->dark_current;
     a.exptime = cp->exptime;
+    a.sat = cp->sat_level;
     a.nm_c1 = 1.0 / (double)cp->gain;
     a.nm_c0 = ((double)cp->read_noise * (double)cp->read_noise + (double)cp->dark_current * (double)cp->exptime) /
               ((double)cp->gain * (double)cp->gain);
@@ -1301,17 +1353,9 @@ extern "C" gp_status gp_background_conv(gp_ctx* ctx, const gp_frame* frames, int
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(ctx->device));
     ProfScope ps(ctx, s, "background_conv");
-    for (int f = 0; f < nframes; ++f) {
-        FrameDesc d{};
-        d.data = frames[f].data;
-        d.pitch = frames[f].pitch;
-        d.W = frames[f].width;
-        d.H = frames[f].height;
-        d.dtype = frames[f].dtype;
-        const hipError_t e = launch_conv_frame(d, masks ? masks[f] : nullptr, cp->sat_level, a, hA, inval, late,
-                                               G, back[f], rms[f], flag, unfilled + f, f64, s);
-        if (e != hipSuccess) return fail(GP_ERR_HIP, "background convolution: %s", hipGetErrorString(e));
-    }
+    const hipError_t e = launch_conv(chunks.data(), (int)chunks.size(), nframes, (int)P.htotal, (int)P.vtotal, a, w,
+                                     f64, s);
+    if (e != hipSuccess) return fail(GP_ERR_HIP, "background convolution: %s", hipGetErrorString(e));
     return GP_OK;
 }
 
