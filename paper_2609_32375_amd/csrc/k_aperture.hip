@@ -19,7 +19,7 @@
 
 namespace gpk {
 
-constexpr int kApBand = 16;    // rows per band
+constexpr int kApBand = 17;    // rows per band (two bands cover the 34-row box of r_max <= 15)
 constexpr int kApBox = 2 * 66; // widest box (r <= 64)
 constexpr int kApWaves = 4;
 
@@ -178,27 +178,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real
             binA[j * 64 + lane] = 0.0;
             binV[j * 64 + lane] = 0.0;
         }
-        int listn = 0;
+        // queued cuts: pixels within one quadrant from the bottom of the list
+        // (listn entries), pixels that straddle an axis through the centre
+        // from the top (nstr entries), so that a lane-parallel round of the
+        // former evaluates a single quadrant piece
+        int listn = 0, nstr = 0;
+        auto add_w = [&](const ApEntry<Real>& E, Real w) __attribute__((always_inline)) {
+            const double ws = (double)w * (double)E.m;
+            const Real wa = w, wvv = w * w * E.var;
+            const int i0 = E.j * 64 + lane;
+            binS[i0] += ws;
+            binA[i0] += (double)wa;
+            binV[i0] += (double)wvv;
+            if (E.j + 1 < NC) {
+                binS[i0 + 64] -= ws;
+                binA[i0 + 64] -= (double)wa;
+                binV[i0 + 64] -= (double)wvv;
+            }
+        };
         // exact weights of the queued cut pixels
         auto flush = [&]() __attribute__((always_inline)) {
             wave_sync();
             for (int e = lane; e < listn; e += 64) {
                 const ApEntry<Real> E = list[e];
                 const Real rj = rad[E.j];
-                const Real w = pixel_area<Real>(E.dx, E.dy, rj, rj * rj);
-                const double ws = (double)w * (double)E.m;
-                const Real wa = w, wvv = w * w * E.var;
-                const int i0 = E.j * 64 + lane;
-                binS[i0] += ws;
-                binA[i0] += (double)wa;
-                binV[i0] += (double)wvv;
-                if (E.j + 1 < NC) {
-                    binS[i0 + 64] -= ws;
-                    binA[i0 + 64] -= (double)wa;
-                    binV[i0 + 64] -= (double)wvv;
-                }
+                const Real ax = fabs(E.dx), ay = fabs(E.dy);
+                const Real w = quad_area<Real>(ax - (Real)0.5, ax + (Real)0.5, ay - (Real)0.5, ay + (Real)0.5, rj,
+                                               rj * rj);
+                add_w(E, w);
+            }
+            for (int e = lane; e < nstr; e += 64) {
+                const ApEntry<Real> E = list[kApList - 1 - e];
+                const Real rj = rad[E.j];
+                add_w(E, pixel_area<Real>(E.dx, E.dy, rj, rj * rj));
             }
             listn = 0;
+            nstr = 0;
             wave_sync();
         };
         const int ry0 = max(by0, 0), ry1 = min(by0 + side - 1, d.H - 1);
@@ -304,14 +319,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real
                     }
                     // circles that cut the pixel: queue (pixel, circle) pairs
                     const int ncut = kin - kout;
+                    const bool str = ax < (Real)0.5 || ay < (Real)0.5;
                     for (int q = 0;; ++q) {
                         const bool has = q < ncut;
-                        const uint64_t bm = __ballot(has);
-                        if (bm == 0ull) break;
-                        const int pos = listn + __popcll(bm & below);
-                        if (has) list[pos] = ApEntry<Real>{dx, dy, m, var, kout + q};
+                        const uint64_t bm = __ballot(has && !str), bs = __ballot(has && str);
+                        if ((bm | bs) == 0ull) break;
+                        if (has) {
+                            const int pos = str ? kApList - 1 - (nstr + __popcll(bs & below))
+                                                : listn + __popcll(bm & below);
+                            list[pos] = ApEntry<Real>{dx, dy, m, var, kout + q};
+                        }
                         listn += __popcll(bm);
-                        if (listn > kApList - 64) flush();
+                        nstr += __popcll(bs);
+                        if (listn + nstr > kApList - 64) flush();
                     }
                 }
             }
