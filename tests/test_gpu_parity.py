@@ -771,6 +771,7 @@ CONV_CASES = [
     (2300, 150, "f32", 116, 65, 65, "edges", np.inf),
     (40, 30, "u16", 117, 65, 33, "blobs", 60000.0),   # narrower than the kernel: repeated reflections
     (700, 300, "u16", 118, 65, 65, "none", 30000.0),  # saturated star cores only
+    (260, 190, "f32", 119, 129, 129, "blobs", np.inf),  # the largest kernel with fills (largest LDS stage)
 ]
 
 
