@@ -138,7 +138,8 @@ void launch_grid_filter(const FrameDesc* desc, int nframes, int total_meshes, in
 void launch_spline(const FrameDesc* desc, int nframes, int max_nx, int max_ny, hipStream_t s);
 bool filter_spline_fits(int max_nx, int max_ny, int fsize);
 void launch_filter_spline(const FrameDesc* desc, int nframes, int max_nx, int max_ny, int fsize, hipStream_t s);
-void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, int rad, hipStream_t s);
+void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, int rad, int mesh_w, hipStream_t s);
+int detect_tiles_per_cu(bool f64, int rad, int mesh_w);
 void launch_merge(const DetWork& wk, int conn, int minarea, int persist_blocks, hipStream_t s);
 void launch_catalog(const DetWork& wk, const CatOut& cat, int minarea, int persist_blocks, int32_t* comp_status,
                     hipStream_t s);

@@ -46,20 +46,20 @@ struct LocalRec {
 };
 
 // LDS regions are reused phase by phase (REG: region width and height, the
-// tile plus the filter halo; 40 KB for FP32 and REG <= 72, four workgroups
-// per compute unit):
-//   u1: row cubics (build M, R) -> horizontal pass -> labels -> piece ids
-//   u2: M over tile + halo      -> piece records (M is then held in VGPRs)
-template <typename Real, int REG>
+// tile plus the filter halo; NIX: spline pieces of a region row; 29 KB for
+// FP32, REG = 68 and NIX = 4, five workgroups per compute unit):
+//   u1: row cubics (build M, R) -> union pair lists -> piece ids
+//   u2: M over tile + halo (the horizontal pass in place) -> labels -> piece
+//       records (M is held in VGPRs from the labels on)
+template <typename Real, int REG, int NIX>
 struct DetShared {
     union U1 {
-        RowT<Real> tab[REG * kNixMax];
-        Real hs[REG * kTile];
-        int32_t lab[kTile * kTile];
-        int16_t comp[kTile * kTile];   // written once no label is read any more
+        RowT<Real> tab[REG * NIX];
+        int16_t comp[kTile * kTile];
     } u1;
     union U2 {
         Real ms[REG * REG];
+        int32_t lab[kTile * kTile];
         LocalRec rec[kLocalRecs];
     } u2;
     uint64_t rowmask[kTile];
@@ -164,14 +164,18 @@ struct RunAcc<double> {
 
 // RAD >= 0: square rank-one kernel of radius RAD applied as two 1-D passes
 // (taps in registers, fully unrolled); RAD < 0: any kernel, applied densely.
-template <typename Real, int RAD>
-__global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs* __restrict__ pa) {
+// FP32, radius 1..4, row cubics of at most 4 pieces: under 32 KB of LDS, so
+// five workgroups per CU when the registers fit 96 (they do, without spills)
+template <typename Real, int RAD, int NIX>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu((NIX <= 4 && sizeof(Real) == 4 && RAD >= 1 && RAD <= 4) ? 5 : 1))) void
+k_detect_tiles(DetWork wk, const DetArgs* __restrict__ pa) {
     constexpr bool kSep = RAD >= 0;
     constexpr int kR = kSep ? RAD : 0;
     constexpr bool kDbl = sizeof(Real) == 8;
     constexpr int REG = kSep ? kTile + 2 * kR : kRegion;   // region row stride
     constexpr int MS = REG;
-    __shared__ DetShared<Real, REG> sh;
+    __shared__ DetShared<Real, REG, NIX> sh;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int gt = xcd_item(blockIdx.x, (wk.total_tiles + kXcds - 1) / kXcds);
     if (gt >= wk.total_tiles) return;
@@ -283,11 +287,11 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     }
     for (int e = tid; e < RH * nix; e += 256) {
         const int r = e / nix, pi = e - r * nix;
-        if (pi >= kNixMax) continue;
+        if (pi >= NIX) continue;
         const int ys = reflect_idx(y0 - ry + r, d.H);
         const int jy = piece_of(ys, d.H, d.mh);
         const double u = (double)ys - piece_ref(jy, d.H, d.mh);
-        sh.u1.tab[r * kNixMax + pi] = make_row<Real>(d.coef, d.nx, d.ny, ixlo + pi, jy, u);
+        sh.u1.tab[r * NIX + pi] = make_row<Real>(d.coef, d.nx, d.ny, ixlo + pi, jy, u);
     }
     for (int c = tid; c < RW; c += 256) {
         const int xs = reflect_idx(x0 - rx + c, d.W);
@@ -304,14 +308,14 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
 #pragma unroll
         for (int q = 0; q < CR; ++q) {
             const int r = wv + 4 * q;
-            if (r < RH) sh.u2.ms[r * MS + c] = eval_M(sh.u1.tab[r * kNixMax + pc], sx, (Real)pv[q]);
+            if (r < RH) sh.u2.ms[r * MS + c] = eval_M(sh.u1.tab[r * NIX + pc], sx, (Real)pv[q]);
         }
 #pragma unroll
         for (int i = 0; i < HL; ++i) {
             const int e = tid + 256 * i;
             const int r = e / (HW > 0 ? HW : 1), hc = halo_col(e - r * HW);
             if (r < RH)
-                sh.u2.ms[r * MS + hc] = eval_M(sh.u1.tab[r * kNixMax + sh.colp[hc]], sh.colsx[hc], (Real)pv[CR + i]);
+                sh.u2.ms[r * MS + hc] = eval_M(sh.u1.tab[r * NIX + sh.colp[hc]], sh.colsx[hc], (Real)pv[CR + i]);
         }
     } else {
 #pragma unroll
@@ -319,7 +323,7 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
             const int e = tid + 256 * i;
             const int r = e / REG, c = e - r * REG;
             if (r < RH && c < RW)
-                sh.u2.ms[r * MS + c] = eval_M(sh.u1.tab[r * kNixMax + sh.colp[c]], sh.colsx[c], (Real)pv[i]);
+                sh.u2.ms[r * MS + c] = eval_M(sh.u1.tab[r * NIX + sh.colp[c]], sh.colsx[c], (Real)pv[i]);
         }
     }
     // thresholds t R of the 16 pixels this lane owns: column `lane`, rows 16 wv ..
@@ -334,7 +338,7 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             const int ly = 16 * wv + k;
-            To[k] = (colok && ly < th) ? ts * eval_R(sh.u1.tab[(ly + ry) * kNixMax + pc], sx) : (Real)0;
+            To[k] = (colok && ly < th) ? ts * eval_R(sh.u1.tab[(ly + ry) * NIX + pc], sx) : (Real)0;
         }
     }
     __syncthreads();
@@ -352,13 +356,17 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
             kx[b] = kDbl ? (Real)pa->kxd[b] : (Real)pa->kx[b];
             ky[b] = kDbl ? (Real)pa->kyd[b] : (Real)pa->ky[b];
         }
+        // horizontal pass in place over M's rows (a row is one wavefront's:
+        // each lane's reads of its row come before its write), once every
+        // wavefront holds its own M values
+        __syncthreads();
         if (colok) {
             for (int r = wv; r < RH; r += 4) {
-                const Real* mr = &sh.u2.ms[r * MS + lane];
+                Real* mr = &sh.u2.ms[r * MS + lane];
                 Real acc = 0;
 #pragma unroll
                 for (int b = 0; b <= 2 * kR; ++b) acc = fma(kx[b], mr[b], acc);
-                sh.u1.hs[r * kTile + lane] = acc;
+                mr[0] = acc;
             }
         }
         __syncthreads();
@@ -366,7 +374,7 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
 #pragma unroll
         for (int q = 0; q < 16 + 2 * kR; ++q) {
             const int r = 16 * wv + q;
-            win[q] = (colok && r < RH) ? sh.u1.hs[r * kTile + lane] : (Real)0;
+            win[q] = (colok && r < RH) ? sh.u2.ms[r * MS + lane] : (Real)0;
         }
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
@@ -414,7 +422,7 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     //    adjacent rows are then united once per touching pair, in an LDS
     //    union-find whose roots are the smallest raster index of each
     //    component.
-    int32_t* lab = sh.u1.lab;
+    int32_t* lab = sh.u2.lab;      // M is held in VGPRs from here on
     int16_t* comp = sh.u1.comp;
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));   // lanes < lane
     // the wavefront's own row masks stay in registers; the row above its
@@ -425,8 +433,8 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
         rm[k] = __ballot((mbits >> k) & 1u);
         if (lane == 0) sh.rowmask[16 * wv + k] = rm[k];
     }
-    // (the horizontal pass that shared lab's LDS was finished by every
-    // wavefront before the barrier above)
+    // (the vertical pass that read the M region lab now occupies was
+    // finished by every wavefront before the barrier above)
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int ly = 16 * wv + k;
@@ -443,11 +451,11 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
     const bool conn8 = pa->conn == 8;
     // Union pairs (pixel, pixel above) for every pair of touching runs, one
     // at the first column of their overlap.  Each wavefront lists its rows'
-    // pairs in its own share of the (now free) M region, then the whole
-    // block applies them concurrently; a full list falls back to uniting at
-    // once.  Pixel indices are < 4096: a pair packs into 24 bits.
-    constexpr int PCAP = (int)(sizeof(typename DetShared<Real, REG>::U2) / sizeof(uint32_t)) / 4;
-    uint32_t* plist = reinterpret_cast<uint32_t*>(&sh.u2) + wv * PCAP;
+    // pairs in its own share of the (now free) row-cubic region, then the
+    // whole block applies them concurrently; a full list falls back to
+    // uniting at once.  Pixel indices are < 4096: a pair packs into 24 bits.
+    constexpr int PCAP = (int)(sizeof(typename DetShared<Real, REG, NIX>::U1) / sizeof(uint32_t)) / 4;
+    uint32_t* plist = reinterpret_cast<uint32_t*>(&sh.u1) + wv * PCAP;
     int npair = 0;
     uint64_t mtop = 0ull;
     if (wv > 0) {
@@ -505,7 +513,7 @@ __global__ __launch_bounds__(256) void k_detect_tiles(DetWork wk, const DetArgs*
                     }
                 }
             }
-            const uint32_t e = reinterpret_cast<const uint32_t*>(&sh.u2)[w * PCAP + o];
+            const uint32_t e = reinterpret_cast<const uint32_t*>(&sh.u1)[w * PCAP + o];
             lds_union(lab, (int)(e >> 12), (int)(e & 4095u));
         }
     }
@@ -1631,27 +1639,61 @@ size_t peak_lds_bytes(int sep, int cwin, int kw, int kh, bool f64) {
 
 // ---------------------------------------------------------------------------
 // launchers
-template <typename Real>
-static void launch_detect_t(const DetWork& wk, const DetArgs* args, int rad, hipStream_t s) {
+template <typename Real, int NIX>
+static void launch_detect_n(const DetWork& wk, const DetArgs* args, int rad, hipStream_t s) {
     // 8 * ceil(tiles / 8) workgroups: a contiguous band of tiles per XCD
     const int g = kXcds * ((wk.total_tiles + kXcds - 1) / kXcds);
     switch (rad) {
-        case 0: k_detect_tiles<Real, 0><<<g, 256, 0, s>>>(wk, args); break;
-        case 1: k_detect_tiles<Real, 1><<<g, 256, 0, s>>>(wk, args); break;
-        case 2: k_detect_tiles<Real, 2><<<g, 256, 0, s>>>(wk, args); break;
-        case 3: k_detect_tiles<Real, 3><<<g, 256, 0, s>>>(wk, args); break;
-        case 4: k_detect_tiles<Real, 4><<<g, 256, 0, s>>>(wk, args); break;
-        case 5: k_detect_tiles<Real, 5><<<g, 256, 0, s>>>(wk, args); break;
-        case 6: k_detect_tiles<Real, 6><<<g, 256, 0, s>>>(wk, args); break;
-        case 7: k_detect_tiles<Real, 7><<<g, 256, 0, s>>>(wk, args); break;
-        default: k_detect_tiles<Real, -1><<<g, 256, 0, s>>>(wk, args); break;
+        case 0: k_detect_tiles<Real, 0, NIX><<<g, 256, 0, s>>>(wk, args); break;
+        case 1: k_detect_tiles<Real, 1, NIX><<<g, 256, 0, s>>>(wk, args); break;
+        case 2: k_detect_tiles<Real, 2, NIX><<<g, 256, 0, s>>>(wk, args); break;
+        case 3: k_detect_tiles<Real, 3, NIX><<<g, 256, 0, s>>>(wk, args); break;
+        case 4: k_detect_tiles<Real, 4, NIX><<<g, 256, 0, s>>>(wk, args); break;
+        case 5: k_detect_tiles<Real, 5, NIX><<<g, 256, 0, s>>>(wk, args); break;
+        case 6: k_detect_tiles<Real, 6, NIX><<<g, 256, 0, s>>>(wk, args); break;
+        case 7: k_detect_tiles<Real, 7, NIX><<<g, 256, 0, s>>>(wk, args); break;
+        default: k_detect_tiles<Real, -1, NIX><<<g, 256, 0, s>>>(wk, args); break;
     }
 }
 
-// rad: radius of a square rank-one kernel (two 1-D passes), -1 for the dense path
-void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, int rad, hipStream_t s) {
-    if (f64) launch_detect_t<double>(wk, args, rad, s);
-    else launch_detect_t<float>(wk, args, rad, s);
+// rad: radius of a square rank-one kernel (two 1-D passes), -1 for the dense
+// path.  The row cubics of a tile region (at most 78 columns) span at most
+// three spline pieces along x when meshes are at least 64 pixels wide (two
+// knots fit in 77 columns: 64 apart, and the last one at least 32 from its
+// neighbour) and six at the smallest mesh of 16.
+template <typename Real, int NIX>
+static int detect_per_cu_n(int rad) {
+    const void* k;
+    switch (rad) {
+        case 0: k = (const void*)k_detect_tiles<Real, 0, NIX>; break;
+        case 1: k = (const void*)k_detect_tiles<Real, 1, NIX>; break;
+        case 2: k = (const void*)k_detect_tiles<Real, 2, NIX>; break;
+        case 3: k = (const void*)k_detect_tiles<Real, 3, NIX>; break;
+        case 4: k = (const void*)k_detect_tiles<Real, 4, NIX>; break;
+        case 5: k = (const void*)k_detect_tiles<Real, 5, NIX>; break;
+        case 6: k = (const void*)k_detect_tiles<Real, 6, NIX>; break;
+        case 7: k = (const void*)k_detect_tiles<Real, 7, NIX>; break;
+        default: k = (const void*)k_detect_tiles<Real, -1, NIX>; break;
+    }
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 256, 0) != hipSuccess || n < 1) n = 4;
+    return n;
+}
+
+// detection workgroups resident per CU for this launch configuration
+int detect_tiles_per_cu(bool f64, int rad, int mesh_w) {
+    if (mesh_w >= 64) return f64 ? detect_per_cu_n<double, 4>(rad) : detect_per_cu_n<float, 4>(rad);
+    return f64 ? detect_per_cu_n<double, kNixMax>(rad) : detect_per_cu_n<float, kNixMax>(rad);
+}
+
+void launch_detect_tiles(const DetWork& wk, const DetArgs* args, bool f64, int rad, int mesh_w, hipStream_t s) {
+    if (mesh_w >= 64) {
+        if (f64) launch_detect_n<double, 4>(wk, args, rad, s);
+        else launch_detect_n<float, 4>(wk, args, rad, s);
+    } else {
+        if (f64) launch_detect_n<double, kNixMax>(wk, args, rad, s);
+        else launch_detect_n<float, kNixMax>(wk, args, rad, s);
+    }
 }
 
 void launch_merge(const DetWork& wk, int conn, int minarea, int persist_blocks, hipStream_t s) {

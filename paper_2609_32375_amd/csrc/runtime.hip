@@ -786,18 +786,19 @@ static gp_status detect_run(gp_ctx* ctx, const gp_frame* frames, int32_t nframes
     wk.bitmap = (uint32_t*)(W + P.o_bitmap);
     wk.rec_cap = (int32_t)P.rec_cap;
     wk.total_blocks = (int32_t)P.total_blocks;
-    // tiles an XCD holds in flight (four detection workgroups per CU)
-    wk.ahead = std::max(0, ctx->cus / kXcds) * 4;
+    const bool f64 = dp->precision == GP_PREC_F64;
+    const int rad = (in.separable && dp->kw == dp->kh) ? dp->kw / 2 : -1;
+    // tiles an XCD holds in flight (its CUs times the detection workgroups
+    // resident per CU)
+    wk.ahead = std::max(0, ctx->cus / kXcds) * detect_tiles_per_cu(f64, rad, bp->mesh_w);
     {
         ProfScope ps(ctx, s, "setup", prof);
         launch_det_setup(tail, (FrameDesc*)(W + P.o_desc), in, dargs, wk.counters, s);
     }
     HIP_TRY(hipGetLastError());
-    const bool f64 = dp->precision == GP_PREC_F64;
     {
         ProfScope ps(ctx, s, "detect_tiles", prof);
-        const int rad = (in.separable && dp->kw == dp->kh) ? dp->kw / 2 : -1;
-        launch_detect_tiles(wk, dargs, f64, rad, s);
+        launch_detect_tiles(wk, dargs, f64, rad, bp->mesh_w, s);
     }
     HIP_TRY(hipGetLastError());
     const int persist = ctx->cus * 4;
