@@ -164,11 +164,14 @@ struct RunAcc<double> {
 
 // RAD >= 0: square rank-one kernel of radius RAD applied as two 1-D passes
 // (taps in registers, fully unrolled); RAD < 0: any kernel, applied densely.
-// FP32, radius 1..4, row cubics of at most 4 pieces: under 32 KB of LDS, so
-// five workgroups per CU when the registers fit 96 (they do, without spills)
+// FP32, radius 1..2, row cubics of at most 4 pieces: under 32 KB of LDS, and
+// the registers fit 96 without spills, so five workgroups per CU (radius 2:
+// 9.56 -> 8.43 ms on the 64-frame batch).  Radius 4 fits too but its code
+// under that limit was slower (1.77 -> 1.94 ms on a 12300^2 frame): it keeps
+// four workgroups per CU.
 template <typename Real, int RAD, int NIX>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu((NIX <= 4 && sizeof(Real) == 4 && RAD >= 1 && RAD <= 4) ? 5 : 1))) void
+__attribute__((amdgpu_waves_per_eu((NIX <= 4 && sizeof(Real) == 4 && RAD >= 1 && RAD <= 2) ? 5 : 1))) void
 k_detect_tiles(DetWork wk, const DetArgs* __restrict__ pa) {
     constexpr bool kSep = RAD >= 0;
     constexpr int kR = kSep ? RAD : 0;
