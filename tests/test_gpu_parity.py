@@ -267,21 +267,22 @@ def _mask_cases():
     return cases
 
 
+@pytest.mark.parametrize("mesh", [16, 64])   # 64: row cubics of at most 4 pieces, union pairs in less LDS
 @pytest.mark.parametrize("conn", [8, 4])
 @pytest.mark.parametrize("case", _mask_cases(), ids=lambda c: c[0])
-def test_labels_bit_exact_for_given_mask(P, case, conn):
+def test_labels_bit_exact_for_given_mask(P, case, conn, mesh):
     name, mask = case
-    _say("mask case", name, conn)
+    _say("mask case", name, conn, mesh)
     H, W = mask.shape
     c, A = 500.0, 100.0
     rng = np.random.default_rng(H * W)
     amp = A + 50.0 * rng.random(mask.shape)
     img = (c + np.where(mask, amp, 0.0)).astype(np.float32)
     minarea = 3
-    p = _params("c1", mesh_w=16, mesh_h=16, conn=conn, minarea=minarea, thresh=1.5)
+    p = _params("c1", mesh_w=mesh, mesh_h=mesh, conn=conn, minarea=minarea, thresh=1.5)
     K = np.zeros((3, 3), np.float32)
     K[1, 1] = 1.0
-    nx, ny = -(-W // 16), -(-H // 16)
+    nx, ny = -(-W // mesh), -(-H // mesh)
     ph = P.Photometry([_dev(img)], p, K, capacity=max(8, W * H), seg=True)
     ph.set_grids(0, np.full((ny, nx), c), np.zeros((ny, nx)))
     ph.background(grid_given=True)
