@@ -26,8 +26,10 @@
 // (or a column band) in LDS with the reflection applied on load, and every
 // thread keeps a block of 8 consecutive outputs in registers, sliding a
 // 16-value window through the staged data: one LDS read per 8 FMAs per
-// channel.  Each output's sum runs over the taps in order.  Noise map for a
-// dark-subtracted frame in ADU:
+// channel.  Each output's sum runs over the taps in order.  Each pass is one
+// launch over every frame of the call: a frame table in the workspace gives
+// each frame's slices of the planes and flags and its first workgroup of
+// each pass.  Noise map for a dark-subtracted frame in ADU:
 //   R^2 = (g max(B, 0) + rn^2 + dark texp) / g^2.
 #include "k_args.h"
 
