@@ -276,6 +276,23 @@ __device__ __forceinline__ void cv_stage(const Real* __restrict__ src, const Fra
     }
 }
 
+// The same band of FP32 rows loaded straight into LDS (global_load_lds: no
+// register round trip, every row's load in flight at once); rows past nrows
+// repeat row nrows - 1, finite values that only the zero-padded taps and the
+// discarded outputs below the tile read.  Each wavefront waits for its own
+// loads; the caller's barrier then publishes the band.
+__device__ __forceinline__ void cv_stage_direct(const float* __restrict__ src, const FrameDesc& d, int xc0, int y0,
+                                                int hy, int nrows, int rows, float* band) {
+    const int c = threadIdx.x & (kCvCols - 1), g = threadIdx.x / kCvCols;
+    const float* col = src + min(xc0 + c, d.W - 1);
+    for (int r = g; r < rows; r += kCvThreads / kCvCols) {
+        const float* p = col + (int64_t)reflect_idx(y0 - hy + min(r, nrows - 1), d.H) * d.W;
+        __builtin_amdgcn_global_load_lds((const void*)p, (void __attribute__((address_space(3)))*)&band[r * kCvCols],
+                                         4, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
 // the vertical sums of one channel for this thread's column and its two
 // blocks of 8 rows, g * 16 + 0..7 and g * 16 + 8..15 (blocks wholly below
 // the last output row are skipped)
@@ -397,7 +414,11 @@ __global__ __launch_bounds__(256) void k_conv_v(CvWork w, int nframes, int total
     } else {
         fill = true;
     }
-    cv_stage(in0, d, xc0, y0, hy, nrows, rows, FIRST ? nullptr : act, band);
+    if constexpr (FIRST && sizeof(Real) == 4)
+        cv_stage_direct(reinterpret_cast<const float*>(in0), d, xc0, y0, hy, nrows, rows,
+                        reinterpret_cast<float*>(band));
+    else
+        cv_stage(in0, d, xc0, y0, hy, nrows, rows, FIRST ? nullptr : act, band);
     __syncthreads();
     cv_vsum(band, a.ky, np, c, g, nr, s0);
     if (FIRST && fill) {
