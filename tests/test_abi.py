@@ -117,3 +117,52 @@ def test_growth_arguments_are_checked_synchronously():
     cat = L.gp_catalog()
     assert lib.gp_growth(None, fr, 1, C.byref(bp), None, C.byref(cat), C.byref(gp), C.byref(out), None, 0,
                          None) == L.GP_ERR_INVALID_ARG
+
+
+def _conv_params(L, lx=65, ly=33, gain=1.5, sat=65535.0, prec=0, taps=None):
+    kx = (C.c_float * max(lx, 1))(*([1.0] * max(lx, 1) if taps is None else taps))
+    ky = (C.c_float * max(ly, 1))(*([1.0] * max(ly, 1)))
+    cp = L.gp_conv_params(kx, lx, ky, ly, sat, gain, 5.0, 0.0, 0.0, prec)
+    cp._keep = (kx, ky)      # the taps live as long as the struct
+    return cp
+
+
+def test_background_conv_workspace_and_argument_checks():
+    """gp_background_conv_ws: two working-precision planes of every frame
+    plus small tables (FP64 planes twice the size); bad arguments fail
+    synchronously with GP_ERR_INVALID_ARG."""
+    from paper_2609_32375_amd import _lib as L
+    a, b = _frame(300, 200), _frame(2300, 150, 1)
+    cp = _conv_params(L)
+    wa, wb = L.gp_background_conv_ws([a], cp), L.gp_background_conv_ws([b], cp)
+    wab = L.gp_background_conv_ws([a, b], cp)
+    planes = lambda w, h, real: 2 * real * w * h
+    assert wa >= planes(300, 200, 4) and wb >= planes(2300, 150, 4)
+    assert wab >= planes(300, 200, 4) + planes(2300, 150, 4)
+    assert wab - wa >= planes(2300, 150, 4)          # a frame added costs its own planes
+    w64 = L.gp_background_conv_ws([a, b], _conv_params(L, prec=L.GP_PREC_F64))
+    assert w64 - wab >= planes(300, 200, 4) + planes(2300, 150, 4)
+    bad = [
+        _conv_params(L, lx=64),                   # even tap count
+        _conv_params(L, lx=131),                  # more than 129 taps
+        _conv_params(L, ly=0),
+        _conv_params(L, lx=3, taps=[1.0, -2.0, 1.0]),   # taps summing to zero
+        _conv_params(L, gain=0.0),
+        _conv_params(L, sat=float("nan")),
+        _conv_params(L, prec=7),
+    ]
+    for cpb in bad:
+        with pytest.raises(L.GpError) as e:
+            L.gp_background_conv_ws([a], cpb)
+        assert e.value.status == L.GP_ERR_INVALID_ARG
+    nul = L.gp_conv_params(None, 65, None, 33, 65535.0, 1.5, 5.0, 0.0, 0.0, 0)
+    with pytest.raises(L.GpError) as e:
+        L.gp_background_conv_ws([a], nul)
+    assert e.value.status == L.GP_ERR_INVALID_ARG
+    # no context: refused before anything is enqueued
+    lib = L.load()
+    fr = (L.gp_frame * 1)(a)
+    ptrs = (C.c_void_p * 1)(C.c_void_p(1))
+    u = C.c_int64(0)
+    assert lib.gp_background_conv(None, fr, 1, None, C.byref(cp), ptrs, ptrs, C.byref(u), C.c_void_p(1), wa,
+                                  None) == L.GP_ERR_INVALID_ARG
