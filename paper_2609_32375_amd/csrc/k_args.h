@@ -89,6 +89,7 @@ struct PeakArgs {
     int32_t sep, cwin;
     const PsfArgs* psf;
     const PsfFrame* pf;
+    int32_t mesh_w;   // mesh width of the call (sizes the row cubics of a region row)
 };
 constexpr int kMaxPeakWin = 7;
 
@@ -146,11 +147,11 @@ void launch_catalog(const DetWork& wk, const CatOut& cat, int minarea, int persi
 void launch_seg(const DetWork& wk, int f, int64_t npx, hipStream_t s);
 void launch_peaks(const DetWork& wk, const DetArgs* args, const CatOut& cat, int32_t* comp_status, bool f64, int sep,
                   int cwin, int kw, int kh, int persist_blocks, const PsfArgs* psf, const PsfFrame* pf,
-                  int nmodes, hipStream_t s);
+                  int nmodes, int mesh_w, int xcd_cus, hipStream_t s);
 // copy `bytes` (a multiple of 4) from host memory to device memory through
 // kernel arguments (no copy engine, so the call can be captured)
 void launch_write_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
-size_t peak_lds_bytes(int sep, int cwin, int kw, int kh, bool f64);
+size_t peak_lds_bytes(int sep, int cwin, int kw, int kh, bool f64, int mesh_w);
 // one: the descriptor of a one-frame call, passed with the launch (the
 // workspace table is then not read), or null
 void launch_aperture(const FrameDesc* desc, const FrameDesc* one, const ApArgs& a, const ApCat& cat, int total_rows,

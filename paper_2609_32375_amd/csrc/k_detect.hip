@@ -1165,16 +1165,22 @@ __global__ __launch_bounds__(256) void k_seg_finalize(DetWork wk, int f) {
 // reads it), then F, R and nu over the tile plus sep, in LDS.  A peak's
 // record goes to a slot taken with an atomic counter (its content does not
 // depend on the slot); the rank bitmap then numbers the peaks in raster order.
+// Spline x-pieces a region row of rmw <= 92 columns can touch: at most two
+// knots fall inside when meshes are at least 64 pixels wide (knots 64 apart,
+// the last at least 32 from its neighbour), so three pieces; otherwise the
+// bound for meshes of 16 pixels.
+__host__ __device__ inline int peak_nix(int rmw, int mesh_w) { return mesh_w >= 64 ? 3 : (rmw - 1) / 16 + 3; }
+
 struct PeakLayout {
     int hmx, hmy, rmw, rmh, rf, nix;
     int o_ms, o_nu, o_tab, o_colp, o_cols, o_cand, bytes;
-    __host__ __device__ PeakLayout(int sep, int cwin, int rx, int ry, int real_bytes, int row_bytes) {
+    __host__ __device__ PeakLayout(int sep, int cwin, int rx, int ry, int real_bytes, int row_bytes, int mesh_w) {
         hmx = max(sep + rx, cwin);
         hmy = max(sep + ry, cwin);
         rmw = kTile + 2 * hmx;
         rmh = kTile + 2 * hmy;
         rf = kTile + 2 * sep;
-        nix = (rmw - 1) / 16 + 3;   // spline x-pieces rmw columns can touch (mesh >= 16)
+        nix = peak_nix(rmw, mesh_w);
         int o = 0;
         auto take = [&](int n) {
             o = (o + 15) / 16 * 16;
@@ -1183,11 +1189,12 @@ struct PeakLayout {
             return r;
         };
         o_ms = take(rmw * rmh * real_bytes);
-        // nu, or before it the horizontal pass of a rank-one filter over the
-        // rows the vertical pass reads
-        o_nu = take(max(rf * rf, (rf + 2 * ry) * rf) * real_bytes);
-        // row cubics, later the row maxima of nu (rf rows of the tile's columns)
-        o_tab = take(max(rmh * nix * row_bytes, rf * kTile * real_bytes));
+        // nu and after it the taps of a dense filter, or before nu the
+        // horizontal pass of a rank-one filter over the rows the vertical
+        // pass reads
+        o_nu = take(max(rf * rf + kMaxK * kMaxK, (rf + 2 * ry) * rf) * real_bytes);
+        // row cubics
+        o_tab = take(rmh * nix * row_bytes);
         o_colp = take(rmw * 4);
         o_cols = take(rmw * real_bytes);
         o_cand = take(kTile * 2 * 4);
@@ -1214,7 +1221,7 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
     const int tw = min(kTile, d.W - x0), th = min(kTile, d.H - y0);
     const int kw = pa->kw, kh = pa->kh, rx = kw >> 1, ry = kh >> 1;
     const int sep = pk.sep, cw = pk.cwin;
-    const PeakLayout L(sep, cw, rx, ry, (int)sizeof(Real), (int)sizeof(RowT<Real>));
+    const PeakLayout L(sep, cw, rx, ry, (int)sizeof(Real), (int)sizeof(RowT<Real>), pk.mesh_w);
     Real* ms = reinterpret_cast<Real*>(pk_dyn + L.o_ms);
     Real* nus = reinterpret_cast<Real*>(pk_dyn + L.o_nu);
     RowT<Real>* tab = reinterpret_cast<RowT<Real>*>(pk_dyn + L.o_tab);
@@ -1237,8 +1244,11 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
         }
     }
     if (tid < kTile * 2) cand[tid] = 0u;
-    __shared__ Real taps[kMaxK * kMaxK];
-    if (!VARY)
+    // a dense filter's taps, after nu (the rank-one passes do not use them
+    // and write over that space)
+    const bool sepk = !VARY && pa->separable != 0;
+    Real* taps = nus + L.rf * L.rf;
+    if (!VARY && !sepk)
         for (int i = tid; i < kw * kh; i += 256) taps[i] = kDbl ? (Real)pa->kdd[i] : (Real)pa->kd[i];
     // 1. raw pixels of the M region (reflected at the frame), row cubics and
     //    column pieces
@@ -1318,7 +1328,6 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
     //    filter below skips those positions); candidates F > t R inside the tile
     const Real ts = (Real)pa->thresh;
     const int fw = tw + 2 * sep, fh = th + 2 * sep;
-    const bool sepk = !VARY && pa->separable != 0;
     if (VARY) {
         // S = sum_m c_m (M corr e_m) (c_0 = 1) over the tile plus sep, into
         // nus.  A work item is kVaryRows output rows of one column and keeps
@@ -1442,28 +1451,33 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
         }
     }
     __syncthreads();
-    // 4. maximum of nu over each row's (2 sep + 1) window, for the tile's
-    //    columns (into the row-cubic buffer), then per candidate the maximum
-    //    over its window; a candidate equal to it is a peak unless an earlier
-    //    pixel of the window (raster order) holds the same value
-    Real* rmx = reinterpret_cast<Real*>(pk_dyn + L.o_tab);
-    for (int e = tid; e < fh * tw; e += 256) {
-        const int j = e / tw, c = e - j * tw;
-        const Real* row = &nus[j * L.rf + c];
-        Real m = row[0];
-        for (int b = 1; b <= 2 * sep; ++b) m = fmax(m, row[b]);
-        rmx[j * kTile + c] = m;
-    }
-    __syncthreads();
+    // 4. per tile row (one wavefront per row at a time): the maximum of nu
+    //    over the (2 sep + 1)^2 window of each column, as the maximum down
+    //    the window's rows at every column (one column per lane, the 2 sep
+    //    columns past the 64th by the first lanes) and then across 2 sep + 1
+    //    neighbouring columns by lane shuffles; a candidate equal to it is a
+    //    peak unless an earlier pixel of the window (raster order) holds the
+    //    same value
     const int lane = tid & 63, wv = tid >> 6;
     const float sat = pa->sat;
     for (int k = 0; k < 16; ++k) {
         const int ly = 16 * wv + k, lx = lane;
-        if (ly >= th || lx >= tw || !((cand[ly * 2 + (lx >> 5)] >> (lx & 31)) & 1u)) continue;
+        const bool isc = ly < th && lx < tw && ((cand[ly * 2 + (lx >> 5)] >> (lx & 31)) & 1u);
+        if (__ballot(isc) == 0ull) continue;   // (ly is the same for the whole wavefront)
+        Real vm = (Real)-INFINITY, vm2 = (Real)-INFINITY;
+        for (int a = 0; a <= 2 * sep; ++a) {
+            const Real* row = &nus[(ly + a) * L.rf];
+            if (lane < fw) vm = fmax(vm, row[lane]);
+            if (lane < 2 * sep && kTile + lane < fw) vm2 = fmax(vm2, row[kTile + lane]);
+        }
+        Real wmax = vm;
+        for (int dd = 1; dd <= 2 * sep; ++dd) {
+            const Real o1 = __shfl(vm, (lane + dd) & 63), o2 = __shfl(vm2, (lane + dd) & 63);
+            wmax = fmax(wmax, lane + dd < kTile ? o1 : o2);
+        }
+        if (!isc) continue;
         const int gx = x0 + lx, gy = y0 + ly;
         const Real v = nus[(ly + sep) * L.rf + lx + sep];
-        Real wmax = rmx[ly * kTile + lx];
-        for (int a = 1; a <= 2 * sep; ++a) wmax = fmax(wmax, rmx[(ly + a) * kTile + lx]);
         if (v < wmax) continue;
         // v is the window's maximum: a tie with an earlier pixel loses
         bool is_max = true;
@@ -1603,41 +1617,47 @@ __global__ __launch_bounds__(256) void k_write_peaks(DetWork wk, CatOut cat, int
     }
 }
 
+// xcd_cus: CUs per XCD; the L2 warm-up looks ahead by one round of resident
+// workgroups, those CUs times the workgroups the layout leaves room for
 template <typename Real, int NM>
 static void launch_peak_tiles(const DetWork& wk, const DetArgs* args, const PeakArgs& pk, int kw, int kh,
-                              hipStream_t s) {
-    const PeakLayout L(pk.sep, pk.cwin, kw / 2, kh / 2, (int)sizeof(Real), (int)sizeof(RowT<Real>));
+                              int mesh_w, int xcd_cus, hipStream_t s) {
+    const PeakLayout L(pk.sep, pk.cwin, kw / 2, kh / 2, (int)sizeof(Real), (int)sizeof(RowT<Real>), mesh_w);
     const int g = kXcds * ((wk.total_tiles + kXcds - 1) / kXcds);
-    (void)hipFuncSetAttribute((const void*)k_peaks_tiles<Real, NM>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              L.bytes);
-    k_peaks_tiles<Real, NM><<<g, 256, L.bytes, s>>>(wk, args, pk);
+    const void* k = (const void*)k_peaks_tiles<Real, NM>;
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, L.bytes);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, L.bytes) != hipSuccess || per_cu < 1) per_cu = 2;
+    DetWork w = wk;
+    w.ahead = xcd_cus * per_cu;
+    k_peaks_tiles<Real, NM><<<g, 256, L.bytes, s>>>(w, args, pk);
 }
 
 template <typename Real>
 static void launch_peak_tiles_t(const DetWork& wk, const DetArgs* args, const PeakArgs& pk, int kw, int kh,
-                                int nmodes, hipStream_t s) {
-    if (!pk.psf) launch_peak_tiles<Real, 0>(wk, args, pk, kw, kh, s);
-    else if (nmodes < 2) launch_peak_tiles<Real, 2>(wk, args, pk, kw, kh, s);
-    else if (nmodes < 4) launch_peak_tiles<Real, 4>(wk, args, pk, kw, kh, s);
-    else if (nmodes < 6) launch_peak_tiles<Real, 6>(wk, args, pk, kw, kh, s);
-    else launch_peak_tiles<Real, kMaxModes + 1>(wk, args, pk, kw, kh, s);
+                                int nmodes, int mesh_w, int xcd_cus, hipStream_t s) {
+    if (!pk.psf) launch_peak_tiles<Real, 0>(wk, args, pk, kw, kh, mesh_w, xcd_cus, s);
+    else if (nmodes < 2) launch_peak_tiles<Real, 2>(wk, args, pk, kw, kh, mesh_w, xcd_cus, s);
+    else if (nmodes < 4) launch_peak_tiles<Real, 4>(wk, args, pk, kw, kh, mesh_w, xcd_cus, s);
+    else if (nmodes < 6) launch_peak_tiles<Real, 6>(wk, args, pk, kw, kh, mesh_w, xcd_cus, s);
+    else launch_peak_tiles<Real, kMaxModes + 1>(wk, args, pk, kw, kh, mesh_w, xcd_cus, s);
 }
 
 void launch_peaks(const DetWork& wk, const DetArgs* args, const CatOut& cat, int32_t* comp_status, bool f64, int sep,
                   int cwin, int kw, int kh, int persist_blocks, const PsfArgs* psf, const PsfFrame* pf,
-                  int nmodes, hipStream_t s) {
-    const PeakArgs pk{sep, cwin, psf, pf};
-    if (f64) launch_peak_tiles_t<double>(wk, args, pk, kw, kh, nmodes, s);
-    else launch_peak_tiles_t<float>(wk, args, pk, kw, kh, nmodes, s);
+                  int nmodes, int mesh_w, int xcd_cus, hipStream_t s) {
+    const PeakArgs pk{sep, cwin, psf, pf, mesh_w};
+    if (f64) launch_peak_tiles_t<double>(wk, args, pk, kw, kh, nmodes, mesh_w, xcd_cus, s);
+    else launch_peak_tiles_t<float>(wk, args, pk, kw, kh, nmodes, mesh_w, xcd_cus, s);
     k_peak_bits<<<persist_blocks, 256, 0, s>>>(wk);
     const int nb = wk.total_blocks;
     k_popc_scan<<<(nb + kScanChunk - 1) / kScanChunk, 256, 0, s>>>(wk.bitmap, wk.blockcnt, wk.chunksum, nb);
     k_write_peaks<<<persist_blocks, 256, 0, s>>>(wk, cat, comp_status);
 }
 
-size_t peak_lds_bytes(int sep, int cwin, int kw, int kh, bool f64) {
-    return f64 ? PeakLayout(sep, cwin, kw / 2, kh / 2, 8, (int)sizeof(RowT<double>)).bytes
-               : PeakLayout(sep, cwin, kw / 2, kh / 2, 4, (int)sizeof(RowT<float>)).bytes;
+size_t peak_lds_bytes(int sep, int cwin, int kw, int kh, bool f64, int mesh_w) {
+    return f64 ? PeakLayout(sep, cwin, kw / 2, kh / 2, 8, (int)sizeof(RowT<double>), mesh_w).bytes
+               : PeakLayout(sep, cwin, kw / 2, kh / 2, 4, (int)sizeof(RowT<float>), mesh_w).bytes;
 }
 
 // ---------------------------------------------------------------------------

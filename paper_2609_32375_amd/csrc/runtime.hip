@@ -904,8 +904,7 @@ static gp_status peaks_run(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
     if (ceil_div(P.total_blocks, kScanChunk) > kMaxScanChunks)
         return fail(GP_ERR_UNSUPPORTED, "a detection batch holds at most 2^31 pixels (1024-pixel blocks per frame)");
     const bool f64 = dp->precision == GP_PREC_F64;
-    const size_t taps_lds = (size_t)kMaxK * kMaxK * (f64 ? 8 : 4);
-    if (peak_lds_bytes(pp->sep, pp->cwin, kw, kh, f64) + taps_lds > 160 * 1024)
+    if (peak_lds_bytes(pp->sep, pp->cwin, kw, kh, f64, bp->mesh_w) > 160 * 1024)
         return fail(GP_ERR_UNSUPPORTED, "peak windows and filter too large for one tile's LDS");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(ctx->device));
@@ -983,7 +982,7 @@ static gp_status peaks_run(gp_ctx* ctx, const gp_frame* frames, int32_t nframes,
     {
         ProfScope ps(ctx, s, psf ? "peaks_psf" : "peaks");
         launch_peaks(wk, dargs, co, comp_status, f64, pp->sep, pp->cwin, kw, kh, ctx->cus * 4, pargs, pframes,
-                     psf ? psf->nmodes : 0, s);
+                     psf ? psf->nmodes : 0, bp->mesh_w, std::max(0, ctx->cus / kXcds), s);
     }
     HIP_TRY(hipGetLastError());
     return GP_OK;
