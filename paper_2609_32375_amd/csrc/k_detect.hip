@@ -1173,8 +1173,9 @@ __host__ __device__ inline int peak_nix(int rmw, int mesh_w) { return mesh_w >= 
 
 struct PeakLayout {
     int hmx, hmy, rmw, rmh, rf, nix;
-    int o_ms, o_nu, o_tab, o_colp, o_cols, o_cand, bytes;
-    __host__ __device__ PeakLayout(int sep, int cwin, int rx, int ry, int real_bytes, int row_bytes, int mesh_w) {
+    int o_ms, o_nu, o_tab, o_rn, o_colp, o_cols, o_cand, bytes;
+    __host__ __device__ PeakLayout(int sep, int cwin, int rx, int ry, int real_bytes, int row_bytes, int mesh_w,
+                                   bool vary = false) {
         hmx = max(sep + rx, cwin);
         hmy = max(sep + ry, cwin);
         rmw = kTile + 2 * hmx;
@@ -1189,12 +1190,22 @@ struct PeakLayout {
             return r;
         };
         o_ms = take(rmw * rmh * real_bytes);
-        // nu and after it the taps of a dense filter, or before nu the
-        // horizontal pass of a rank-one filter over the rows the vertical
-        // pass reads
-        o_nu = take(max(rf * rf + kMaxK * kMaxK, (rf + 2 * ry) * rf) * real_bytes);
-        // row cubics
-        o_tab = take(rmh * nix * row_bytes);
+        if (vary) {
+            // the varying filter: nu only, with the row cubics in the same
+            // space (read no more once M is formed, before nu is written)
+            // and the noise cubics, which R needs with nu, after it
+            o_nu = take(max(rf * rf * real_bytes, rmh * nix * row_bytes));
+            o_tab = o_nu;
+            o_rn = take(rmh * nix * 4 * real_bytes);
+        } else {
+            // nu and after it the taps of a dense filter, or before nu the
+            // horizontal pass of a rank-one filter over the rows the
+            // vertical pass reads
+            o_nu = take(max(rf * rf + kMaxK * kMaxK, (rf + 2 * ry) * rf) * real_bytes);
+            // row cubics
+            o_tab = take(rmh * nix * row_bytes);
+            o_rn = o_tab;
+        }
         o_colp = take(rmw * 4);
         o_cols = take(rmw * real_bytes);
         o_cand = take(kTile * 2 * 4);
@@ -1221,10 +1232,11 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
     const int tw = min(kTile, d.W - x0), th = min(kTile, d.H - y0);
     const int kw = pa->kw, kh = pa->kh, rx = kw >> 1, ry = kh >> 1;
     const int sep = pk.sep, cw = pk.cwin;
-    const PeakLayout L(sep, cw, rx, ry, (int)sizeof(Real), (int)sizeof(RowT<Real>), pk.mesh_w);
+    const PeakLayout L(sep, cw, rx, ry, (int)sizeof(Real), (int)sizeof(RowT<Real>), pk.mesh_w, VARY);
     Real* ms = reinterpret_cast<Real*>(pk_dyn + L.o_ms);
     Real* nus = reinterpret_cast<Real*>(pk_dyn + L.o_nu);
     RowT<Real>* tab = reinterpret_cast<RowT<Real>*>(pk_dyn + L.o_tab);
+    Real* rn = reinterpret_cast<Real*>(pk_dyn + L.o_rn);   // noise cubics (varying filter)
     int32_t* colp = reinterpret_cast<int32_t*>(pk_dyn + L.o_colp);
     Real* colsx = reinterpret_cast<Real*>(pk_dyn + L.o_cols);
     uint32_t* cand = reinterpret_cast<uint32_t*>(pk_dyn + L.o_cand);
@@ -1307,7 +1319,15 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
         const int ys = reflect_idx(gy0 + r, d.H);
         const int jy = piece_of(ys, d.H, d.mh);
         const double u = (double)ys - piece_ref(jy, d.H, d.mh);
-        tab[r * L.nix + pi] = make_row<Real>(d.coef, d.nx, d.ny, ixlo + pi, jy, u);
+        const RowT<Real> rt = make_row<Real>(d.coef, d.nx, d.ny, ixlo + pi, jy, u);
+        tab[r * L.nix + pi] = rt;
+        if (VARY) {
+            Real* q = &rn[(r * L.nix + pi) * 4];
+            q[0] = rt.r0;
+            q[1] = rt.r1;
+            q[2] = rt.r2;
+            q[3] = rt.r3;
+        }
     }
     for (int c = tid; c < mw; c += 256) {
         const int xs = reflect_idx(gx0 + c, d.W);
@@ -1332,31 +1352,24 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
         // S = sum_m c_m (M corr e_m) (c_0 = 1) over the tile plus sep, into
         // nus.  A work item is kVaryRows output rows of one column and keeps
         // (K + 1) x kVaryRows accumulators; the taps come through the scalar
-        // cache (uniform addresses, [column][row][mode] layout)
+        // cache (uniform addresses, [column][row][mode] layout).  Ten rows:
+        // the 70 x 70 outputs of sep 3 make 490 items, two rounds of the 256
+        // threads, and each tap feeds ten FMAs
         typedef __attribute__((address_space(4))) const Real ctap_t;
         const ctap_t* tp = (const ctap_t*)(kDbl ? (const void*)pk.psf->tapsd : (const void*)pk.psf->taps);
         const int nmodes = pk.psf->nmodes;
-        constexpr int kVaryRows = 8;
+        constexpr int kVaryRows = 10;
         const int nrb = (fh + kVaryRows - 1) / kVaryRows;
         for (int it = tid; it < fw * nrb; it += 256) {
             const int i = it % fw, j0 = (it / fw) * kVaryRows;
             const int mc = i - sep + L.hmx - rx;           // first M column read
             const int mr0 = j0 - sep + L.hmy - ry;         // first M row read
             constexpr int NA = VARY ? NM : 1;
-            // this item's coefficients, loaded first so that they arrive
-            // during the correlations (positions clamped into the frame; the
-            // values of outside positions are not used)
+            // (the item's coefficients are loaded after the correlations:
+            // held during them they would cost (NA - 1) x kVaryRows registers)
             const PsfFrame pfr = pk.pf[f];
             const int bin = pk.psf->bin;
             const int gx = x0 - sep + i;
-            float cf[NA > 1 ? NA - 1 : 1][kVaryRows];
-#pragma unroll
-            for (int r = 0; r < kVaryRows; ++r) {
-                const int gxc = min(max(gx, 0), d.W - 1), gyc = min(max(y0 - sep + j0 + r, 0), d.H - 1);
-                const float* cp = pfr.data + (int64_t)(gyc / bin) * pfr.pitch + gxc / bin;
-#pragma unroll
-                for (int m = 1; m < NA; ++m) cf[m - 1][r] = (m <= nmodes) ? cp[(int64_t)(m - 1) * pfr.plane] : 0.0f;
-            }
             Real acc[NA][kVaryRows];
 #pragma unroll
             for (int m = 0; m < NA; ++m)
@@ -1384,6 +1397,16 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
                             for (int r = 0; r < kVaryRows; ++r) acc[m][r] = fma(t[m], col[a + r], acc[m][r]);
                     }
                 }
+            }
+            // this item's coefficients (positions clamped into the frame;
+            // the values of outside positions are not used)
+            float cf[NA > 1 ? NA - 1 : 1][kVaryRows];
+#pragma unroll
+            for (int r = 0; r < kVaryRows; ++r) {
+                const int gxc = min(max(gx, 0), d.W - 1), gyc = min(max(y0 - sep + j0 + r, 0), d.H - 1);
+                const float* cp = pfr.data + (int64_t)(gyc / bin) * pfr.pitch + gxc / bin;
+#pragma unroll
+                for (int m = 1; m < NA; ++m) cf[m - 1][r] = (m <= nmodes) ? cp[(int64_t)(m - 1) * pfr.plane] : 0.0f;
             }
 #pragma unroll
             for (int r = 0; r < kVaryRows; ++r) {
@@ -1434,7 +1457,18 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
                     for (int b = 0; b < kw; ++b) acc = fma(krow[b], mrow[b], acc);
                 }
             }
-            const Real R = eval_R(tab[mr * L.nix + colp[mc]], colsx[mc]);
+            Real R;
+            if (VARY) {
+                const Real* q = &rn[(mr * L.nix + colp[mc]) * 4];
+                RowT<Real> rt;
+                rt.r0 = q[0];
+                rt.r1 = q[1];
+                rt.r2 = q[2];
+                rt.r3 = q[3];
+                R = eval_R(rt, colsx[mc]);
+            } else {
+                R = eval_R(tab[mr * L.nix + colp[mc]], colsx[mc]);
+            }
             nv[q] = in ? ((R > (Real)0) ? acc / R : acc) : (Real)-INFINITY;
             const int lx = i - sep, ly = j - sep;
             if (lx >= 0 && lx < tw && ly >= 0 && ly < th && acc > ts * R)
@@ -1622,7 +1656,7 @@ __global__ __launch_bounds__(256) void k_write_peaks(DetWork wk, CatOut cat, int
 template <typename Real, int NM>
 static void launch_peak_tiles(const DetWork& wk, const DetArgs* args, const PeakArgs& pk, int kw, int kh,
                               int mesh_w, int xcd_cus, hipStream_t s) {
-    const PeakLayout L(pk.sep, pk.cwin, kw / 2, kh / 2, (int)sizeof(Real), (int)sizeof(RowT<Real>), mesh_w);
+    const PeakLayout L(pk.sep, pk.cwin, kw / 2, kh / 2, (int)sizeof(Real), (int)sizeof(RowT<Real>), mesh_w, NM > 0);
     const int g = kXcds * ((wk.total_tiles + kXcds - 1) / kXcds);
     const void* k = (const void*)k_peaks_tiles<Real, NM>;
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, L.bytes);
