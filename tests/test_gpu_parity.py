@@ -499,27 +499,33 @@ def _cmp_peak_catalogues(r, o, M, F, R, thresh, sep):
 
 PSF_CASES = [
     # W, H, dtype, seed, thresh, sep, cwin, nmodes, kernel side, coefficient-map bin
+    # [, mesh size (64 if absent)]
     (333, 257, "f32", 91, 3.0, 3, 3, 5, 9, 1),
     (300, 211, "u16", 92, 5.0, 3, 3, 5, 9, 16),
     (257, 190, "f32", 93, 2.0, 2, 4, 8, 15, 7),
     (200, 150, "f32", 94, 2.0, 4, 2, 0, 7, 1),
     (190, 130, "f32", 95, 2.5, 3, 3, 3, (7, 5), 1),   # a non-square kernel
     (400, 300, "f32", 96, 1.0, 2, 2, 5, 13, 1),       # low threshold: hundreds of noise peaks
+    # 16-px meshes: the tile's row-cubic table (8 pieces a row) is larger
+    # than nu, which it shares in the varying filter's LDS layout
+    (300, 220, "f32", 98, 3.0, 3, 3, 5, 13, 1, 16),
 ]
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "fp64"])
-@pytest.mark.parametrize("case", PSF_CASES, ids=lambda c: f"{c[0]}x{c[1]}-{c[2]}-K{c[7]}-k{c[8]}-bin{c[9]}")
+@pytest.mark.parametrize("case", PSF_CASES,
+                         ids=lambda c: f"{c[0]}x{c[1]}-{c[2]}-K{c[7]}-k{c[8]}-bin{c[9]}" + (f"-mesh{c[10]}" if len(c) > 10 else ""))
 def test_peaks_psf_stage_isolated(P, case, prec):
     """gp_peaks_psf against the oracle's varying filter and peaks on the
     oracle's background grids, with synthetic eigen-PSF models and smooth
     coefficient maps (full-frame and binned)."""
     from synth import coef_maps, psf_model
-    W, H, dt, seed, t, sep, cw, K, side, b = case
+    W, H, dt, seed, t, sep, cw, K, side, b = case[:10]
+    mesh = case[10] if len(case) > 10 else 64
     _say("psf peak case", case, prec)
     fr = make_frame("c1", seed=seed, W=W, H=H, dtype=dt, nstars=max(8, W * H // 2500))
     p = f32_params(fr.params)
-    p.mesh_w = p.mesh_h = 64
+    p.mesh_w = p.mesh_h = mesh
     p.thresh = t
     p.sat_level = 60000.0
     if isinstance(side, tuple):
