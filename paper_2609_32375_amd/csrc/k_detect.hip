@@ -1377,7 +1377,8 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
                 for (int r = 0; r < kVaryRows; ++r) acc[m][r] = 0;
             // per tap column b: the M column strip the item's rows read for
             // every tap row (kh + kVaryRows - 1 values) in registers, then
-            // all tap rows (unrolled; taps of one column contiguous)
+            // all tap rows (unrolled; taps of one column contiguous), two at
+            // a time so that one wait on the scalar loads serves both
             constexpr int NC = kMaxK + kVaryRows - 1;
             for (int b = 0; b < kw; ++b) {
                 Real col[NC];
@@ -1385,16 +1386,23 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
                 for (int t = 0; t < NC; ++t)
                     col[t] = (t < kh + kVaryRows - 1) ? ms[min(mr0 + t, L.rmh - 1) * L.rmw + mc + b] : (Real)0;
                 const ctap_t* tb = tp + b * kh * (kMaxModes + 1);
+                constexpr int kTapRows = 2;
 #pragma unroll
-                for (int a = 0; a < kMaxK; ++a) {
-                    if (a < kh) {
-                        Real t[NA];
+                for (int a0 = 0; a0 < kMaxK; a0 += kTapRows) {
+                    if (a0 < kh) {
+                        Real t[kTapRows][NA];
 #pragma unroll
-                        for (int m = 0; m < NA; ++m) t[m] = tb[a * (kMaxModes + 1) + m];
+                        for (int c = 0; c < kTapRows; ++c)
 #pragma unroll
-                        for (int m = 0; m < NA; ++m)
+                            for (int m = 0; m < NA; ++m) t[c][m] = tb[min(a0 + c, kh - 1) * (kMaxModes + 1) + m];
 #pragma unroll
-                            for (int r = 0; r < kVaryRows; ++r) acc[m][r] = fma(t[m], col[a + r], acc[m][r]);
+                        for (int c = 0; c < kTapRows; ++c)
+                            if (a0 + c < kh && a0 + c < kMaxK)
+#pragma unroll
+                                for (int m = 0; m < NA; ++m)
+#pragma unroll
+                                    for (int r = 0; r < kVaryRows; ++r)
+                                        acc[m][r] = fma(t[c][m], col[min(a0 + c, kMaxK - 1) + r], acc[m][r]);
                     }
                 }
             }
@@ -1494,10 +1502,19 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
     //    same value
     const int lane = tid & 63, wv = tid >> 6;
     const float sat = pa->sat;
-    for (int k = 0; k < 16; ++k) {
+    // (the wavefront's tile rows that hold a candidate, from one read of
+    // their 32 candidate words; rows past th have none)
+    uint32_t rows = 0u;
+    {
+        const uint64_t nz = __ballot(lane < 32 && cand[32 * wv + lane] != 0u);
+        for (int k = 0; k < 16; ++k)
+            if ((nz >> (2 * k)) & 3ull) rows |= 1u << k;
+    }
+    while (rows != 0u) {
+        const int k = __builtin_ctz(rows);
+        rows &= rows - 1u;
         const int ly = 16 * wv + k, lx = lane;
         const bool isc = ly < th && lx < tw && ((cand[ly * 2 + (lx >> 5)] >> (lx & 31)) & 1u);
-        if (__ballot(isc) == 0ull) continue;   // (ly is the same for the whole wavefront)
         Real vm = (Real)-INFINITY, vm2 = (Real)-INFINITY;
         for (int a = 0; a <= 2 * sep; ++a) {
             const Real* row = &nus[(ly + a) * L.rf];
@@ -1513,18 +1530,22 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
         const int gx = x0 + lx, gy = y0 + ly;
         const Real v = nus[(ly + sep) * L.rf + lx + sep];
         if (v < wmax) continue;
-        // v is the window's maximum: a tie with an earlier pixel loses
-        bool is_max = true;
-        for (int dy = -sep; dy <= 0 && is_max; ++dy) {
-            for (int dx = -sep; dx <= sep; ++dx) {
-                if (dy == 0 && dx >= 0) break;
-                if (nus[(ly + sep + dy) * L.rf + lx + sep + dx] == v) {
-                    is_max = false;
-                    break;
-                }
-            }
+        // v is the window's maximum: a tie with an earlier pixel loses (the
+        // rows above and the pixels to the left, all read with no early exit)
+        bool tie = false;
+        for (int dy = -sep; dy <= 0; ++dy) {
+            const Real* rp = &nus[(ly + sep + dy) * L.rf + lx + sep];
+            const int dxe = dy == 0 ? -1 : sep;
+            for (int dx = -sep; dx <= dxe; ++dx) tie |= rp[dx] == v;
         }
-        if (!is_max) continue;
+        if (tie) continue;
+        // the record slot first, so that the atomic's round trip overlaps the
+        // centroid sums
+        const uint32_t slot = atomicAdd(&wk.counters[0], 1u);
+        if ((int64_t)slot >= (int64_t)wk.rec_cap) {
+            atomicOr(&wk.counters[1], 1u);
+            continue;
+        }
         // centroid window, inside the frame; FP64 sums in a fixed order
         const int wx0 = max(gx - cw, 0), wx1 = min(gx + cw, d.W - 1);
         const int wy0 = max(gy - cw, 0), wy1 = min(gy + cw, d.H - 1);
@@ -1555,11 +1576,6 @@ __global__ __launch_bounds__(256) void k_peaks_tiles(DetWork wk, const DetArgs* 
             fl |= kFlagNonpos;
         }
         const uint32_t pm = (uint32_t)((int64_t)gy * d.W + gx);
-        const uint32_t slot = atomicAdd(&wk.counters[0], 1u);
-        if ((int64_t)slot >= (int64_t)wk.rec_cap) {
-            atomicOr(&wk.counters[1], 1u);
-            continue;
-        }
         CompRec& R = wk.recs[slot];
         R.acc[0] = flux;
         R.acc[1] = (double)gx + mx;
